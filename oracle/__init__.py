@@ -1,0 +1,142 @@
+"""TEST INFRASTRUCTURE ONLY: FP64 CPU oracle for the FFT-based Poisson solve.
+
+The oracle is a plain C implementation (``poisson_oracle.c``) of the solve in
+FluTAS (arXiv 2204.08834), Section 3.3.1: textbook DFTs along x and y, Gauss
+elimination (Thomas) along z for walls or a DFT along z when periodic, the
+inverse transforms, and a zero-mean gauge.  It shares no code with the GPU
+library.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline
+leg of ``bench.py`` may use it.
+
+Arrays are numpy float64 of shape (nz, ny, nx), x fastest.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "poisson_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+PERIODIC = 0
+NEUMANN = 1
+
+# Planted mistakes (mirrors the MUT_* constants in poisson_oracle.c).
+MUTATIONS = {
+    "fwd_sign_x": 1,
+    "wall_row": 2,
+    "half_angle": 3,
+    "swap_dxdy": 4,
+    "no_norm_y": 5,
+    "no_gauge": 6,
+    "drop_z": 7,
+    "offdiag": 8,
+    "idx_y": 9,
+}
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
+               "-Wall", "-o", tmp, SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        build(force=True)
+    lib = ctypes.CDLL(LIB)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_solve_ex.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
+        ctypes.c_int, dp, dp, dp, dp, ctypes.c_int]
+    lib.oracle_solve_ex.restype = ctypes.c_int
+    lib.oracle_laplacian.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
+        ctypes.c_int, dp, dp]
+    lib.oracle_laplacian.restype = ctypes.c_int
+    lib.oracle_residual.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
+        ctypes.c_int, dp, dp, dp, dp, dp]
+    lib.oracle_residual.restype = ctypes.c_int
+    lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check(f):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    if f.ndim != 3:
+        raise ValueError("expected a (nz, ny, nx) array")
+    return f
+
+
+def solve(f, dx, dy, dz, bc_z, mutation: int | str = 0, return_info: bool = False):
+    """Zero-mean p with L p = f - mean(f).  bc_z: PERIODIC (0) or NEUMANN (1)."""
+    lib = _load()
+    f = _check(f)
+    nz, ny, nx = f.shape
+    p = np.empty_like(f)
+    mean = ctypes.c_double(0.0)
+    mim = ctypes.c_double(0.0)
+    if isinstance(mutation, str):
+        mutation = MUTATIONS[mutation]
+    rc = lib.oracle_solve_ex(nx, ny, nz, dx, dy, dz, int(bc_z), _ptr(f), _ptr(p),
+                             ctypes.byref(mean), ctypes.byref(mim), int(mutation))
+    if rc != 0:
+        raise RuntimeError(f"oracle_solve failed ({rc})")
+    if return_info:
+        return p, {"rhs_mean": mean.value, "max_imag_ratio": mim.value}
+    return p
+
+
+def laplacian(p, dx, dy, dz, bc_z):
+    lib = _load()
+    p = _check(p)
+    nz, ny, nx = p.shape
+    out = np.empty_like(p)
+    rc = lib.oracle_laplacian(nx, ny, nz, dx, dy, dz, int(bc_z), _ptr(p), _ptr(out))
+    if rc != 0:
+        raise RuntimeError("oracle_laplacian failed")
+    return out
+
+
+def residual(f, p, dx, dy, dz, bc_z, return_field: bool = False):
+    """Relative residual ||(f - mean f) - L p||_2 / ||f - mean f||_2 (and Linf)."""
+    lib = _load()
+    f = _check(f)
+    p = _check(p)
+    nz, ny, nx = f.shape
+    r = np.empty_like(f) if return_field else None
+    l2 = ctypes.c_double()
+    li = ctypes.c_double()
+    rc = lib.oracle_residual(nx, ny, nz, dx, dy, dz, int(bc_z), _ptr(f), _ptr(p),
+                             _ptr(r) if r is not None else None,
+                             ctypes.byref(l2), ctypes.byref(li))
+    if rc != 0:
+        raise RuntimeError("oracle_residual failed")
+    if return_field:
+        return l2.value, li.value, r
+    return l2.value, li.value
+
+
+def num_threads() -> int:
+    return _load().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    _load().oracle_set_num_threads(int(n))

@@ -1,0 +1,391 @@
+/*
+ * poisson_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 CPU reference for the pressure Poisson solve of the
+ * two-fluid projection method (FluTAS, arXiv 2204.08834).  It exists to check
+ * the GPU path; nothing in the product library links, calls or includes it.
+ * Only the tests, the package's smoke check and the CPU-baseline leg of the
+ * benchmark may load it.
+ *
+ * What it computes (Section 3.3 "Pressure correction algorithm", equation
+ * eqn:poisson, and Section 3.3.1 "Poisson solver"):
+ *
+ *   the unique zero-mean p with  L p = f - mean(f),
+ *
+ * where L is the second-order finite-difference Laplacian on the uniform
+ * marker-and-cell grid of Section 3 (pressure at cell centres; seven
+ * non-zero diagonals, Section 3.3.1), periodic along x and y, and along z
+ * either periodic or bounded by walls on the cell faces with zero normal
+ * pressure gradient (the wall condition stated after eqn:corr).  At a wall
+ * the ghost value mirrors the first interior cell.
+ *
+ * How (the eigen-expansion of Section 3.3.1, taken in its steps):
+ *   1. remove the mean of f;
+ *   2. forward discrete Fourier transform along x, then along y
+ *      (textbook O(n^2) sums, full complex spectrum, no symmetry shortcuts);
+ *   3. per wavenumber pair (mx,my): walls -> tridiagonal system along z solved
+ *      by Gauss elimination without pivoting (Thomas); periodic -> DFT along
+ *      z and division by the eigenvalue of the 3-D operator;
+ *   4. inverse transforms along y then x, keep the real part;
+ *   5. remove the mean of p (the gauge; the paper leaves it open).
+ *
+ * Eigenvalues of the periodic 3-point operator (not printed in the paper;
+ * they follow from applying the stencil to exp(2 pi i m n / N)):
+ *   lambda(m) = -(4/h^2) sin^2(pi m / N).
+ *
+ * Parity pins: see the tests (closed-form discrete eigenmodes, dense LU on
+ * small grids, zero mean, residual at machine precision, projection
+ * invariant, symmetries, 1-D reductions to DCT-II).
+ *
+ * A "mutation" argument plants one known mistake at a time so the tests can
+ * show that the pins catch it.  mutation = 0 is the oracle.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PERIODIC 0
+#define ORC_NEUMANN 1
+
+/* mutations (test-only planted mistakes) */
+#define MUT_NONE 0
+#define MUT_FWD_SIGN_X 1      /* forward x DFT uses exp(+i..), inverse unchanged */
+#define MUT_WALL_ROW 2        /* wall rows use the interior diagonal */
+#define MUT_HALF_ANGLE 3      /* eigenvalue with sin^2(pi m/(2N)) */
+#define MUT_SWAP_DXDY 4       /* dx and dy exchanged in the eigenvalues */
+#define MUT_NO_NORM_Y 5       /* inverse y DFT without 1/ny */
+#define MUT_NO_GAUGE 6        /* final mean removal skipped, zero mode pinned at k=nz-1 */
+#define MUT_DROP_Z 7          /* the z part of the operator dropped (walls) */
+#define MUT_OFFDIAG 8         /* off-diagonal of the z system uses 1/dx^2 */
+#define MUT_IDX_Y 9           /* y DFT exponent uses (m*j+1) */
+
+static const double ORC_PI = 3.14159265358979323846264338327950288;
+
+/* lambda(m) = -(4/h^2) sin^2(pi m/N): eigenvalue of the periodic
+ * three-point second difference on N points of spacing h. */
+static double eig_periodic(int m, int n, double h, int mutation)
+{
+    double ang = (mutation == MUT_HALF_ANGLE) ? ORC_PI * m / (2.0 * n) : ORC_PI * m / n;
+    double s = sin(ang);
+    return -4.0 / (h * h) * s * s;
+}
+
+/* pairwise (cascade) sum for the mean */
+static double pairwise_sum(const double *v, long n)
+{
+    if (n <= 32) {
+        double s = 0.0;
+        for (long i = 0; i < n; ++i) s += v[i];
+        return s;
+    }
+    long h = n / 2;
+    return pairwise_sum(v, h) + pairwise_sum(v + h, n - h);
+}
+
+/* w[t] = exp(sign * 2 pi i t / n), t = 0..n-1 */
+static void twiddles(int n, int sign, double complex *w)
+{
+    for (int t = 0; t < n; ++t) {
+        double a = sign * 2.0 * ORC_PI * (double)t / (double)n;
+        w[t] = cos(a) + I * sin(a);
+    }
+}
+
+/* Textbook DFT of one strided line: out[m] = sum_i in[i] * w[(m*i) mod n]. */
+static void dft_line(int n, const double complex *w, const double complex *in,
+                     long stride, double complex *out, int idx_mut)
+{
+    for (int m = 0; m < n; ++m) {
+        double complex acc = 0.0;
+        for (int i = 0; i < n; ++i) {
+            long t = ((long)m * i + (idx_mut ? 1 : 0)) % n;
+            acc += in[(long)i * stride] * w[t];
+        }
+        out[m] = acc;
+    }
+}
+
+/* Apply a DFT (sign -1 forward, +1 inverse, scale applied to the output)
+ * along axis 0 (x), 1 (y) or 2 (z) of a complex (nz,ny,nx) array. */
+static void dft_axis(double complex *a, int nx, int ny, int nz, int axis, int sign,
+                     double scale, int mutation)
+{
+    int n = axis == 0 ? nx : (axis == 1 ? ny : nz);
+    long stride = axis == 0 ? 1 : (axis == 1 ? nx : (long)nx * ny);
+    long nlines = (long)nx * ny * nz / n;
+    int sgn = sign;
+    if (axis == 0 && sign < 0 && mutation == MUT_FWD_SIGN_X) sgn = +1;
+    int idx_mut = (axis == 1 && sign < 0 && mutation == MUT_IDX_Y);
+    double complex *w = malloc(sizeof(double complex) * n);
+    twiddles(n, sgn, w);
+#pragma omp parallel
+    {
+        double complex *in = malloc(sizeof(double complex) * n);
+        double complex *out = malloc(sizeof(double complex) * n);
+#pragma omp for schedule(static)
+        for (long l = 0; l < nlines; ++l) {
+            long base;
+            if (axis == 0) {
+                base = l * nx;
+            } else if (axis == 1) {
+                long k = l / nx, i = l % nx;
+                base = k * (long)nx * ny + i;
+            } else {
+                base = l; /* l = j*nx + i */
+            }
+            for (int t = 0; t < n; ++t) in[t] = a[base + (long)t * stride];
+            dft_line(n, w, in, 1, out, idx_mut);
+            for (int t = 0; t < n; ++t) a[base + (long)t * stride] = out[t] * scale;
+        }
+        free(in);
+        free(out);
+    }
+    free(w);
+}
+
+/* Thomas algorithm (Gauss elimination without pivoting) for
+ *   lo[k] x[k-1] + di[k] x[k] + up[k] x[k+1] = d[k],  k = 0..n-1,
+ * real coefficients, complex right-hand side, solved in place. */
+static void thomas(int n, const double *lo, const double *di, const double *up,
+                   double complex *d, double *cp)
+{
+    if (n <= 0) return;
+    cp[0] = up[0] / di[0];
+    d[0] = d[0] / di[0];
+    for (int k = 1; k < n; ++k) {
+        double piv = di[k] - lo[k] * cp[k - 1];
+        cp[k] = up[k] / piv;
+        d[k] = (d[k] - lo[k] * d[k - 1]) / piv;
+    }
+    for (int k = n - 2; k >= 0; --k) d[k] -= cp[k] * d[k + 1];
+}
+
+/* z solve for wall-bounded boxes, one (mx,my) column of the x-y spectrum.
+ * Rows (units 1/dz^2): a p[k-1] + (lam - 2a) p[k] + a p[k+1] = g[k] with the
+ * mirrored ghost at both walls, which turns the wall rows into
+ * (lam - a) p[0] + a p[1] and a p[nz-2] + (lam - a) p[nz-1].
+ * For the singular (0,0) column the value at k=0 is pinned to zero, the
+ * redundant first row is dropped, and the column mean is removed afterwards. */
+static void zsolve_walls(int nz, double dz, double lam, int singular, double complex *g,
+                         double *lo, double *di, double *up, double *cp, int mutation,
+                         double dx)
+{
+    double a = 1.0 / (dz * dz);
+    if (mutation == MUT_OFFDIAG) a = 1.0 / (dx * dx);
+    double two_a = 2.0 / (dz * dz);
+    if (mutation == MUT_DROP_Z) { a = 0.0; two_a = 0.0; }
+    for (int k = 0; k < nz; ++k) {
+        lo[k] = (k > 0) ? a : 0.0;
+        up[k] = (k < nz - 1) ? a : 0.0;
+        double nb = 0.0; /* number of real (non-ghost) neighbours times a */
+        if (k > 0) nb += a;
+        if (k < nz - 1) nb += a;
+        di[k] = lam - nb;
+        if (mutation == MUT_WALL_ROW) di[k] = lam - two_a;
+        if (mutation == MUT_DROP_Z) di[k] = lam;
+    }
+    if (!singular) {
+        thomas(nz, lo, di, up, g, cp);
+        return;
+    }
+    int pin = (mutation == MUT_NO_GAUGE) ? nz - 1 : 0;
+    if (nz == 1) { g[0] = 0.0; return; }
+    if (pin == 0) {
+        /* unknowns p[1..nz-1], p[0] = 0 */
+        thomas(nz - 1, lo + 1, di + 1, up + 1, g + 1, cp);
+        g[0] = 0.0;
+    } else {
+        /* unknowns p[0..nz-2], p[nz-1] = 0 */
+        thomas(nz - 1, lo, di, up, g, cp);
+        g[nz - 1] = 0.0;
+    }
+    if (mutation != MUT_NO_GAUGE) {
+        double complex s = 0.0;
+        for (int k = 0; k < nz; ++k) s += g[k];
+        s /= nz;
+        for (int k = 0; k < nz; ++k) g[k] -= s;
+    }
+}
+
+/*
+ * oracle_solve_ex: the full solve with an optional planted mistake.
+ *   f, p: (nz,ny,nx) C-order (x fastest) double arrays, p written.
+ *   bc_z: 0 periodic, 1 walls (homogeneous Neumann on the cell faces).
+ *   rhs_mean (nullable): receives mean(f).
+ *   max_imag (nullable): receives max|Im| / max|Re| before the real part is taken.
+ * Returns 0 on success, -1 on bad arguments or allocation failure.
+ */
+int oracle_solve_ex(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
+                    const double *f, double *p, double *rhs_mean, double *max_imag,
+                    int mutation)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !(dx > 0) || !(dy > 0) || !(dz > 0) || !f || !p)
+        return -1;
+    if (bc_z != ORC_PERIODIC && bc_z != ORC_NEUMANN) return -1;
+    long n = (long)nx * ny * nz;
+    double complex *a = malloc(sizeof(double complex) * n);
+    if (!a) return -1;
+
+    /* 1. remove the mean */
+    double mean = pairwise_sum(f, n) / (double)n;
+    if (rhs_mean) *rhs_mean = mean;
+    for (long t = 0; t < n; ++t) a[t] = f[t] - mean;
+
+    /* 2. forward DFTs along x and y */
+    dft_axis(a, nx, ny, nz, 0, -1, 1.0, mutation);
+    dft_axis(a, nx, ny, nz, 1, -1, 1.0, mutation);
+
+    double hx = dx, hy = dy;
+    if (mutation == MUT_SWAP_DXDY) { hx = dy; hy = dx; }
+
+    /* 3. z-solve per (mx,my) */
+    if (bc_z == ORC_NEUMANN) {
+#pragma omp parallel
+        {
+            double complex *g = malloc(sizeof(double complex) * nz);
+            double *lo = malloc(sizeof(double) * nz), *di = malloc(sizeof(double) * nz);
+            double *up = malloc(sizeof(double) * nz), *cp = malloc(sizeof(double) * nz);
+#pragma omp for schedule(static)
+            for (long q = 0; q < (long)nx * ny; ++q) {
+                int mx = (int)(q % nx), my = (int)(q / nx);
+                double lam = eig_periodic(mx, nx, hx, mutation) + eig_periodic(my, ny, hy, mutation);
+                for (int k = 0; k < nz; ++k) g[k] = a[(long)k * nx * ny + q];
+                zsolve_walls(nz, dz, lam, mx == 0 && my == 0, g, lo, di, up, cp, mutation, dx);
+                for (int k = 0; k < nz; ++k) a[(long)k * nx * ny + q] = g[k];
+            }
+            free(g); free(lo); free(di); free(up); free(cp);
+        }
+    } else {
+        dft_axis(a, nx, ny, nz, 2, -1, 1.0, mutation);
+#pragma omp parallel for schedule(static)
+        for (long t = 0; t < n; ++t) {
+            int mx = (int)(t % nx);
+            int my = (int)((t / nx) % ny);
+            int mz = (int)(t / ((long)nx * ny));
+            double lam = eig_periodic(mx, nx, hx, mutation) + eig_periodic(my, ny, hy, mutation);
+            double lz = eig_periodic(mz, nz, dz, mutation);
+            if (mutation == MUT_DROP_Z) lz = 0.0;
+            lam += lz;
+            if (mx == 0 && my == 0 && mz == 0)
+                a[t] = 0.0;
+            else if (lam == 0.0)
+                a[t] = 0.0; /* only reachable with a planted mistake */
+            else
+                a[t] /= lam;
+        }
+        dft_axis(a, nx, ny, nz, 2, +1, 1.0 / nz, mutation);
+    }
+
+    /* 4. inverse DFTs along y then x */
+    dft_axis(a, nx, ny, nz, 1, +1, mutation == MUT_NO_NORM_Y ? 1.0 : 1.0 / ny, mutation);
+    dft_axis(a, nx, ny, nz, 0, +1, 1.0 / nx, mutation);
+
+    double mre = 0.0, mim = 0.0;
+    for (long t = 0; t < n; ++t) {
+        p[t] = creal(a[t]);
+        double re = fabs(creal(a[t])), im = fabs(cimag(a[t]));
+        if (re > mre) mre = re;
+        if (im > mim) mim = im;
+    }
+    if (max_imag) *max_imag = (mre > 0) ? mim / mre : mim;
+    free(a);
+
+    /* 5. gauge: zero mean */
+    if (mutation != MUT_NO_GAUGE) {
+        double pm = pairwise_sum(p, n) / (double)n;
+        for (long t = 0; t < n; ++t) p[t] -= pm;
+    }
+    return 0;
+}
+
+int oracle_solve(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
+                 const double *f, double *p, double *rhs_mean, double *max_imag)
+{
+    return oracle_solve_ex(nx, ny, nz, dx, dy, dz, bc_z, f, p, rhs_mean, max_imag, MUT_NONE);
+}
+
+/*
+ * oracle_laplacian: out = L p, the 7-point operator of Section 3 on the MAC
+ * grid (periodic x,y; z periodic or mirrored ghost at the walls).
+ */
+int oracle_laplacian(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
+                     const double *p, double *out)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !p || !out) return -1;
+    double ax = 1.0 / (dx * dx), ay = 1.0 / (dy * dy), az = 1.0 / (dz * dz);
+#pragma omp parallel for schedule(static)
+    for (long kk = 0; kk < (long)nz * ny; ++kk) {
+        int k = (int)(kk / ny), j = (int)(kk % ny);
+        int jm = (j + ny - 1) % ny, jp = (j + 1) % ny;
+        int km, kp;
+        if (bc_z == ORC_PERIODIC) {
+            km = (k + nz - 1) % nz;
+            kp = (k + 1) % nz;
+        } else {
+            km = (k > 0) ? k - 1 : 0;          /* mirrored ghost at the bottom wall */
+            kp = (k < nz - 1) ? k + 1 : nz - 1; /* and at the top wall */
+        }
+        for (int i = 0; i < nx; ++i) {
+            int im = (i + nx - 1) % nx, ip = (i + 1) % nx;
+#define P(K, J, I) p[((long)(K) * ny + (J)) * nx + (I)]
+            double c = P(k, j, i);
+            double v = ax * (P(k, j, ip) - 2.0 * c + P(k, j, im)) +
+                       ay * (P(k, jp, i) - 2.0 * c + P(k, jm, i)) +
+                       az * (P(kp, j, i) - 2.0 * c + P(km, j, i));
+#undef P
+            out[((long)k * ny + j) * nx + i] = v;
+        }
+    }
+    return 0;
+}
+
+/*
+ * oracle_residual: r = (f - mean(f)) - L p, plus the relative L2 and Linf
+ * norms ||r|| / ||f - mean(f)||.  r may be NULL.
+ */
+int oracle_residual(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
+                    const double *f, const double *p, double *r, double *rel_l2,
+                    double *rel_linf)
+{
+    long n = (long)nx * ny * nz;
+    double *lp = malloc(sizeof(double) * n);
+    if (!lp) return -1;
+    if (oracle_laplacian(nx, ny, nz, dx, dy, dz, bc_z, p, lp)) { free(lp); return -1; }
+    double mean = pairwise_sum(f, n) / (double)n;
+    double s2r = 0, s2f = 0, mr = 0, mf = 0;
+    for (long t = 0; t < n; ++t) {
+        double fb = f[t] - mean;
+        double rv = fb - lp[t];
+        if (r) r[t] = rv;
+        s2r += rv * rv;
+        s2f += fb * fb;
+        if (fabs(rv) > mr) mr = fabs(rv);
+        if (fabs(fb) > mf) mf = fabs(fb);
+    }
+    free(lp);
+    if (rel_l2) *rel_l2 = (s2f > 0) ? sqrt(s2r / s2f) : sqrt(s2r);
+    if (rel_linf) *rel_linf = (mf > 0) ? mr / mf : mr;
+    return 0;
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
