@@ -1,0 +1,169 @@
+/*
+ * poisson.h -- C ABI of the MI355X (gfx950) FFT-based pressure Poisson solver.
+ *
+ * The operation (FluTAS, arXiv 2204.08834):
+ *   Section 3.3, eqn:poisson -- the constant-coefficient Poisson equation of
+ *   the pressure-correction step, lap(psi) = (rho_0/dt) div(u*); the caller
+ *   passes the right-hand side f = (rho_0/dt) div(u*) already evaluated.
+ *   Section 3 -- uniform Cartesian marker-and-cell grid with spacings
+ *   dx, dy, dz; psi at the cell centres; second-order 7-point Laplacian.
+ *   Section 3.3.1 -- the solve: Fourier expansions along x and y reduce the
+ *   7-diagonal operator to one tridiagonal system along z per wavenumber pair,
+ *   solved by Gauss elimination; the steps are forward transforms along x
+ *   then y, the z solve, and backward transforms along y then x.  With
+ *   periodic z the z solve becomes a third transform and a division by the
+ *   eigenvalue.  Walls (homogeneous Neumann, the boundary condition stated
+ *   after eqn:corr) sit on the cell faces; the ghost cell mirrors the first
+ *   interior cell.
+ *
+ * Problem solved: the unique zero-mean p with  L p = f - mean(f).
+ * The mean of f (which makes the periodic/Neumann problem incompatible when
+ * non-zero) is removed and reported in poisson_stats_t.rhs_mean; it is not an
+ * error.
+ *
+ * Memory: all field arrays are float64 device pointers (hipMalloc'd, or torch
+ * CUDA tensors), contiguous, shape (nz, ny, nx) in C order (x fastest).  The
+ * caller owns rhs and sol; rhs is never written; rhs and sol must not
+ * overlap.  The plan owns its workspace, twiddle and eigenvalue tables.
+ *
+ * Streams: `stream` is a hipStream_t (passed as void*; NULL = default
+ * stream).  All work of a plan is enqueued on its stream.  POISSON_FP64 and
+ * POISSON_FP32 solves are asynchronous unless stats is non-NULL (then the
+ * call synchronises once to read the removed mean).  POISSON_FP32_REFINE
+ * synchronises once per refinement iteration to read the residual norm.
+ * One plan must be used by one host thread / stream at a time.
+ *
+ * Errors: every function returns POISSON_OK (0) or a negative code below.
+ * Descriptors are fully validated before any HIP call.
+ */
+#ifndef POISSON_H
+#define POISSON_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define POISSON_OK 0
+#define POISSON_ERR_INVALID_ARG (-1)   /* NULL pointer, bad size/spacing, aliasing */
+#define POISSON_ERR_UNSUPPORTED (-2)   /* BC combination or length outside 2^a 3^b */
+#define POISSON_ERR_OUT_OF_MEMORY (-3) /* device allocation failed */
+#define POISSON_ERR_HIP (-4)           /* a HIP runtime call failed */
+#define POISSON_ERR_NOT_CONVERGED (-5) /* refinement stalled or hit max_refine; last iterate kept */
+#define POISSON_ERR_NONFINITE (-6)     /* non-finite residual (NaN/Inf in rhs or solution) */
+
+typedef enum {
+    POISSON_BC_PERIODIC = 0,
+    POISSON_BC_NEUMANN = 1 /* wall on the cell face, zero normal gradient */
+} poisson_bc_t;
+
+typedef enum {
+    POISSON_FP64 = 0,        /* every pass in FP64 */
+    POISSON_FP32_REFINE = 1, /* FP32 transforms + FP64 residual iterative refinement */
+    POISSON_FP32 = 2         /* one FP32 solve (FP64 zero mode), no refinement */
+} poisson_precision_t;
+
+/*
+ * Problem descriptor.
+ *   nx      : even, nx/2 of the form 2^a or 3*2^a, 2 <= nx <= 2048.
+ *   ny      : 2^a or 3*2^a, 1 <= ny <= 2048.
+ *   nz      : walls: 1..4096 (any value); periodic: 2^a or 3*2^a up to 2048.
+ *   nx*ny*nz <= 2^31.
+ *   dx,dy,dz: positive, finite cell sizes.
+ *   bc_x, bc_y: POISSON_BC_PERIODIC (the only supported value).
+ *   bc_z    : POISSON_BC_PERIODIC or POISSON_BC_NEUMANN.
+ *   precision: poisson_precision_t.
+ *   rtol    : FP32_REFINE target for ||f - mean f - L p||_2 / ||f - mean f||_2
+ *             (default 1e-10; must be > 0).
+ *   max_refine: maximum number of refinement corrections (default 8, >= 1).
+ */
+typedef struct {
+    int nx, ny, nz;
+    double dx, dy, dz;
+    int bc_x, bc_y, bc_z;
+    int precision;
+    double rtol;
+    int max_refine;
+} poisson_desc_t;
+
+/*
+ * Per-solve statistics (written when the pointer is non-NULL).
+ *   iterations  : refinement corrections applied (0 for FP64 / FP32).
+ *   rel_residual: final relative L2 residual (FP32_REFINE); -1 when not computed.
+ *   rhs_mean    : mean(f) removed from the right-hand side.
+ *   status      : same value as the return code of the solve.
+ */
+typedef struct {
+    int iterations;
+    double rel_residual;
+    double rhs_mean;
+    int status;
+} poisson_stats_t;
+
+typedef struct poisson_plan_s *poisson_plan;
+
+/* Fill a descriptor with defaults (periodic x,y,z, FP64, rtol 1e-10,
+ * max_refine 8, unit spacing, sizes 0).  Host only. */
+int poisson_desc_init(poisson_desc_t *d);
+
+/* Check a descriptor without touching the GPU.  Host only. */
+int poisson_desc_validate(const poisson_desc_t *d);
+
+/* Device workspace bytes a plan for this descriptor allocates (tables
+ * excluded).  Host only; 0 on an invalid descriptor. */
+size_t poisson_workspace_bytes(const poisson_desc_t *d);
+
+/* Create a plan: validates d, builds FP64 twiddle and eigenvalue tables on
+ * the host (FP32 copies rounded once), allocates the workspace on the current
+ * device.  *out is set only on success. */
+int poisson_plan_create(const poisson_desc_t *d, void *stream, poisson_plan *out);
+
+/* Solve L sol = rhs - mean(rhs) with zero-mean sol (see the file comment).
+ * rhs_dev, sol_dev: device float64, nx*ny*nz elements each, non-overlapping.
+ * stats may be NULL. */
+int poisson_solve(poisson_plan plan, const double *rhs_dev, double *sol_dev,
+                  poisson_stats_t *stats);
+
+/* Release a plan and everything it owns.  NULL is accepted. */
+int poisson_destroy(poisson_plan plan);
+
+/* Batched plan: `count` independent problems (descs[i], possibly different
+ * sizes and boundaries, one shared precision/rtol/max_refine taken from
+ * descs[0]) solved together on one stream.  Problems of equal shape share
+ * kernel launches. */
+int poisson_batch_plan_create(const poisson_desc_t *descs, int count, void *stream,
+                              poisson_plan *out);
+
+/* rhs[i], sol[i]: host arrays of `count` device pointers (problem i's fields).
+ * stats: NULL or an array of `count` entries.  Returns the first non-OK
+ * per-problem status, else POISSON_OK. */
+int poisson_batch_solve(poisson_plan plan, const double *const *rhs, double *const *sol,
+                        poisson_stats_t *stats);
+
+/* Static English description of an error code. */
+const char *poisson_error_string(int code);
+
+/*
+ * Per-pass timing (tracing).  When enabled, every kernel launch of a solve is
+ * bracketed by hipEvents on the plan's stream; the accumulated time and the
+ * algorithmic HBM bytes of each pass are read back with
+ * poisson_plan_get_timing (which synchronises the stream).
+ */
+typedef struct {
+    char name[40];           /* pass name, e.g. "x_r2c_f32" */
+    int launches;            /* launches since the last reset */
+    double total_ms;         /* summed kernel time */
+    double bytes_per_launch; /* algorithmic HBM bytes moved by one launch */
+} poisson_pass_stat_t;
+
+int poisson_plan_set_timing(poisson_plan plan, int enable);
+int poisson_plan_reset_timing(poisson_plan plan);
+int poisson_plan_get_timing(poisson_plan plan, poisson_pass_stat_t *out, int capacity,
+                            int *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POISSON_H */

@@ -1,0 +1,88 @@
+// common.hpp -- types and launcher declarations shared by the host plan code
+// and the HIP kernels of the FFT-based Poisson solver (FluTAS, Section 3.3.1).
+//
+// Data layout in HBM
+//   real fields  f, p : double, (nz, ny, nx), x fastest.
+//   spectrum S        : complex<R>, (nz, ny, M) with M = nx/2, x-wavenumber
+//                       fastest.  Column m = 0 packs the two real x-modes:
+//                       S[.,.,0] = X(0) + i X(M) (DC and Nyquist of the real
+//                       transform along x).  In FP64 mode S aliases the
+//                       solution array (same byte size); in FP32 modes it is a
+//                       separate workspace of 4 bytes per grid point.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace pk {
+
+template <typename R>
+struct Cx {
+    R re, im;
+};
+
+enum Prec { P_F64 = 0, P_F32 = 1 };
+
+// Arguments of the forward real-to-complex pass along x (optionally with the
+// FP64 residual r = (f - mu) - L p evaluated on the fly as its input).
+struct XFwdArgs {
+    const double *f;        // (nz, ny, nx)
+    const double *p;        // residual mode only: current solution
+    void *S;                // complex<R> spectrum, row pitch M
+    const void *tw;         // complex<R> table exp(-2 pi i t/nx), t in [0, nx)
+    double *partials;       // per-workgroup FP64 sums (nullable)
+    int nx, ny, nz;
+    int bc_z;               // 0 periodic, 1 walls
+    double ax, ay, az;      // 1/dx^2, 1/dy^2, 1/dz^2
+    const double *sum_f;    // residual mode: device sum of f (mean = sum_f * inv_n)
+    double inv_n;           // 1/(nx ny nz)
+    int residual;           // 1: input is the residual
+};
+
+// Inverse complex-to-real pass along x: p = result (store) or p += result.
+struct XInvArgs {
+    const void *S;
+    double *p;
+    const void *tw;
+    int nx, ny, nz;
+    int accumulate;
+};
+
+// Strided complex pass along y, in place on S.
+struct YArgs {
+    void *S;
+    const void *tw;         // exp(-2 pi i t/ny), t in [0, ny)
+    int M, ny, nz;
+    int inverse;
+};
+
+// z solve, walls (tridiagonal per (m, ky)) or periodic (transform along z).
+struct ZArgs {
+    void *S;
+    const void *tw;         // periodic: exp(-2 pi i t/nz)
+    const double *lamx;     // lambda_x(m), m in [0, M]
+    const double *lamy;     // lambda_y(ky), ky in [0, ny)
+    const double *lamz;     // periodic: lambda_z(kz), kz in [0, nz)
+    double *zero_mean_out;  // receives mean(f) from the zero-wavenumber column
+    int M, ny, nz;
+    int nx;
+    double dz2;             // dz^2
+    double inv_nxny;        // 1/(nx ny)
+    double inv_ntot;        // 1/(nx ny nz)
+};
+
+// Launchers (return 0 on success, a hipError_t value otherwise).
+int launch_x_fwd(int prec, const XFwdArgs &a, int *nblocks_out, hipStream_t s);
+int launch_x_inv(int prec, const XInvArgs &a, hipStream_t s);
+int launch_y(int prec, const YArgs &a, hipStream_t s);
+int launch_z_walls(int prec, const ZArgs &a, hipStream_t s);
+int launch_z_periodic(int prec, const ZArgs &a, hipStream_t s);
+// number of workgroups the forward x pass uses (size of its partials array)
+int x_fwd_blocks(int prec, int nx, int ny, int nz);
+// Deterministic FP64 sum of `n` entries of `in` with stride `stride`
+// (nsums interleaved sums), result written to out[0..nsums).
+int launch_sum_partials(const double *in, int n, int nsums, double *out, hipStream_t s);
+
+// lengths supported by the transform kernels
+bool fft_length_supported(int n);
+
+}  // namespace pk

@@ -1,0 +1,239 @@
+// k_xpass.hip -- transforms along x (steps 1 and 9 of the solve sequence in
+// FluTAS Section 3.3.1), one workgroup per block of NB grid rows.
+//
+// Forward: a row of nx reals x[i] is read as M = nx/2 complex values
+// z[n] = x[2n] + i x[2n+1]; an M-point FFT gives Z; the half spectrum of the
+// real row follows from
+//     X[m] = (Z[m] + conj Z[M-m])/2 - i w^m (Z[m] - conj Z[M-m])/2,
+//     w = exp(-2 pi i/nx),  m = 1..M-1,
+// and X[0] = Re Z[0] + Im Z[0], X[M] = Re Z[0] - Im Z[0] (both real), which
+// are packed as S[0] = X[0] + i X[M].
+// Optionally the input is the FP64 residual r = (f - mu) - L p of the
+// iterative refinement, evaluated from f and p as the row is loaded (its L2
+// norm and that of f - mu accumulate in FP64 per workgroup), so r never
+// touches HBM.
+//
+// Inverse: Z'[m] = (X[m] + conj X[M-m]) + i w^-m (X[m] - conj X[M-m]) with
+// Z'[0] = (X[0] + X[M]) + i (X[0] - X[M]); an inverse M-point FFT of Z'
+// returns nx (x[2n] + i x[2n+1]) (unnormalised, like the forward pass), which
+// is stored to p or added to it in FP64.
+//
+// Compiled once per precision with PK_REAL = float or double.
+#include "fft_core.hpp"
+#include "lengths.hpp"
+
+#ifndef PK_REAL
+#error "PK_REAL must be defined"
+#endif
+
+namespace pk {
+
+using R = PK_REAL;
+
+template <int M> struct XCfg {
+    static constexpr int ELEMS = sizeof(R) == 4 ? 4096 : 2048;
+    static constexpr int NB0 = ELEMS / M;
+    static constexpr int NB = NB0 < 1 ? 1 : (NB0 > 64 ? 64 : NB0);
+    static constexpr int NT = pick_nt(NB * M, sizeof(R) == 4 ? 16 : 8);
+    static constexpr int PAD = 0;
+};
+
+// sum two doubles over the workgroup; thread 0 gets the totals
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *sh)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { sh[2 * wid] = a; sh[2 * wid + 1] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        a = 0.0;
+        b = 0.0;
+        for (int w = 0; w < nw; ++w) { a += sh[2 * w]; b += sh[2 * w + 1]; }
+    }
+}
+
+template <int M, bool RES>
+__global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a)
+{
+    using C = XCfg<M>;
+    constexpr int NB = C::NB, NT = C::NT, NX = 2 * M;
+    using Tile = LdsTile<R, M, NB, false, C::PAD>;
+    __shared__ Cx<R> s_tile[Tile::elems];
+    __shared__ Cx<R> s_tw[NX];
+    __shared__ double s_red[2 * (NT / 64)];
+
+    const int nrows = a.ny * a.nz;
+    const int row0 = blockIdx.x * NB;
+    load_table(s_tw, (const Cx<R> *)a.tw, NX);
+    __syncthreads();
+
+    const double mu = (RES && a.sum_f) ? (*a.sum_f) * a.inv_n : 0.0;
+    double acc0 = 0.0, acc1 = 0.0;
+    auto gload = [&](int b, int n) -> Cx<R> {
+        const int row = row0 + b;
+        if (row >= nrows) return {R(0), R(0)};
+        const size_t roff = (size_t)row * NX;
+        const double2 fv = *(const double2 *)(a.f + roff + 2 * n);
+        if constexpr (!RES) {
+            acc0 += fv.x + fv.y;
+            return {R(fv.x), R(fv.y)};
+        }
+        const int j = row % a.ny, k = row / a.ny;
+        const double *pr = a.p + roff;
+        const double2 pc = *(const double2 *)(pr + 2 * n);
+        const double pl = pr[(2 * n + NX - 1) % NX];
+        const double pq = pr[(2 * n + 2) % NX];
+        const int jm = (j == 0) ? a.ny - 1 : j - 1;
+        const int jp = (j == a.ny - 1) ? 0 : j + 1;
+        int km, kp;
+        if (a.bc_z == 0) {
+            km = (k == 0) ? a.nz - 1 : k - 1;
+            kp = (k == a.nz - 1) ? 0 : k + 1;
+        } else {  // mirrored ghost at the walls
+            km = (k == 0) ? 0 : k - 1;
+            kp = (k == a.nz - 1) ? k : k + 1;
+        }
+        const size_t plane = (size_t)a.ny * NX;
+        const double2 ps = *(const double2 *)(a.p + (size_t)k * plane + (size_t)jm * NX + 2 * n);
+        const double2 pn = *(const double2 *)(a.p + (size_t)k * plane + (size_t)jp * NX + 2 * n);
+        const double2 pd = *(const double2 *)(a.p + (size_t)km * plane + (size_t)j * NX + 2 * n);
+        const double2 pu = *(const double2 *)(a.p + (size_t)kp * plane + (size_t)j * NX + 2 * n);
+        const double l0 = a.ax * (pc.y - 2.0 * pc.x + pl) + a.ay * (pn.x - 2.0 * pc.x + ps.x) +
+                          a.az * (pu.x - 2.0 * pc.x + pd.x);
+        const double l1 = a.ax * (pq - 2.0 * pc.y + pc.x) + a.ay * (pn.y - 2.0 * pc.y + ps.y) +
+                          a.az * (pu.y - 2.0 * pc.y + pd.y);
+        const double f0 = fv.x - mu, f1 = fv.y - mu;
+        const double r0 = f0 - l0, r1 = f1 - l1;
+        acc0 += r0 * r0 + r1 * r1;
+        acc1 += f0 * f0 + f1 * f1;
+        return {R(r0), R(r1)};
+    };
+    Tile tile{s_tile};
+    auto lstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
+    fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, lstore, tile);
+    __syncthreads();
+
+    // split the M-point spectrum into the half spectrum of the real rows
+    Cx<R> *S = (Cx<R> *)a.S;
+    for (int u = threadIdx.x; u < NB * M; u += NT) {
+        const int b = u / M, m = u % M;
+        const int row = row0 + b;
+        if (row >= nrows) continue;
+        const Cx<R> zm = tile.at(b, m);
+        Cx<R> x;
+        if (m == 0) {
+            x = {zm.re + zm.im, zm.re - zm.im};
+        } else {
+            const Cx<R> zc = cconj(tile.at(b, M - m));
+            const Cx<R> e = cscale(cadd(zm, zc), R(0.5));
+            const Cx<R> o = cscale(cmul_mi(csub(zm, zc)), R(0.5));
+            x = cadd(e, cmul(s_tw[m], o));
+        }
+        S[(size_t)row * M + m] = x;
+    }
+
+    if (a.partials) {
+        block_sum2(acc0, acc1, s_red);
+        if (threadIdx.x == 0) {
+            a.partials[2 * blockIdx.x] = acc0;
+            a.partials[2 * blockIdx.x + 1] = acc1;
+        }
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a)
+{
+    using C = XCfg<M>;
+    constexpr int NB = C::NB, NT = C::NT, NX = 2 * M;
+    using Tile = LdsTile<R, M, NB, false, C::PAD>;
+    __shared__ Cx<R> s_tile[Tile::elems];
+    __shared__ Cx<R> s_tw[NX];
+
+    const int nrows = a.ny * a.nz;
+    const int row0 = blockIdx.x * NB;
+    load_table(s_tw, (const Cx<R> *)a.tw, NX);
+    __syncthreads();
+
+    const Cx<R> *S = (const Cx<R> *)a.S;
+    auto gload = [&](int b, int n) -> Cx<R> {
+        const int row = row0 + b;
+        if (row >= nrows) return {R(0), R(0)};
+        const Cx<R> *sr = S + (size_t)row * M;
+        Cx<R> zp;
+        if (n == 0) {
+            const Cx<R> s0 = sr[0];
+            zp = {s0.re + s0.im, s0.re - s0.im};
+        } else {
+            const Cx<R> xm = sr[n];
+            const Cx<R> xc = cconj(sr[M - n]);
+            const Cx<R> t = cmul(cconj(s_tw[n]), csub(xm, xc));
+            zp = cadd(cadd(xm, xc), cmul_pi(t));
+        }
+        return cconj(zp);  // inverse transform as conj(FFT(conj))
+    };
+    auto gstore = [&](int b, int n, Cx<R> v) {
+        const int row = row0 + b;
+        if (row >= nrows) return;
+        double2 *dst = (double2 *)(a.p + (size_t)row * NX + 2 * n);
+        double2 o = {double(v.re), -double(v.im)};
+        if (a.accumulate) {
+            const double2 old = *dst;
+            o.x += old.x;
+            o.y += old.y;
+        }
+        *dst = o;
+    };
+    Tile tile{s_tile};
+    fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, gstore, tile);
+}
+
+template <int M> static int run_x_fwd(const XFwdArgs &a, hipStream_t s)
+{
+    const int nrows = a.ny * a.nz;
+    const int nb = (nrows + XCfg<M>::NB - 1) / XCfg<M>::NB;
+    if (a.residual)
+        hipLaunchKernelGGL((k_x_fwd<M, true>), dim3(nb), dim3(XCfg<M>::NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_x_fwd<M, false>), dim3(nb), dim3(XCfg<M>::NT), 0, s, a);
+    return (int)hipGetLastError();
+}
+
+template <int M> static int run_x_inv(const XInvArgs &a, hipStream_t s)
+{
+    const int nrows = a.ny * a.nz;
+    const int nb = (nrows + XCfg<M>::NB - 1) / XCfg<M>::NB;
+    hipLaunchKernelGGL(k_x_inv<M>, dim3(nb), dim3(XCfg<M>::NT), 0, s, a);
+    return (int)hipGetLastError();
+}
+
+template <int M> static int blocks_x(int ny, int nz)
+{
+    return (ny * nz + XCfg<M>::NB - 1) / XCfg<M>::NB;
+}
+
+#define PK_CASE_FWD(N) case N: return run_x_fwd<N>(a, s);
+#define PK_CASE_INV(N) case N: return run_x_inv<N>(a, s);
+#define PK_CASE_BLK(N) case N: return blocks_x<N>(ny, nz);
+
+int PK_SUFFIX(launch_x_fwd)(const XFwdArgs &a, hipStream_t s)
+{
+    switch (a.nx / 2) { PK_X_LENGTHS(PK_CASE_FWD) default: return -1; }
+}
+
+int PK_SUFFIX(launch_x_inv)(const XInvArgs &a, hipStream_t s)
+{
+    switch (a.nx / 2) { PK_X_LENGTHS(PK_CASE_INV) default: return -1; }
+}
+
+int PK_SUFFIX(x_fwd_blocks)(int nx, int ny, int nz)
+{
+    switch (nx / 2) { PK_X_LENGTHS(PK_CASE_BLK) default: return -1; }
+}
+
+}  // namespace pk

@@ -1,0 +1,78 @@
+// k_ypass.hip -- transforms along y (steps 3 and 7 of the solve sequence in
+// FluTAS Section 3.3.1), in place on the packed half spectrum S.
+//
+// On one GPU the whole grid is resident, so the x-to-y re-orientation of the
+// paper's distributed code (its transposes 2 and 8) is replaced by a strided
+// pass: a workgroup owns NB consecutive x-wavenumbers m of one z-plane k and
+// transforms its NB columns S[k, :, m0:m0+NB] along y.  A wavefront's loads
+// and stores are runs of NB contiguous complex values per y-row (128 B at the
+// default tile), so the pass streams HBM once in and once out.
+// The inverse is conj(FFT(conj)).
+#include "fft_core.hpp"
+#include "lengths.hpp"
+
+#ifndef PK_REAL
+#error "PK_REAL must be defined"
+#endif
+
+namespace pk {
+
+using R = PK_REAL;
+
+template <int N> struct YCfg {
+    // 128-byte row segments: 16 complex floats or 8 complex doubles; the
+    // tile (up to 128 KB at N = 1024) stays in one workgroup's LDS
+    static constexpr int NB0 = sizeof(R) == 4 ? 16 : 8;
+    static constexpr int MAXE = sizeof(R) == 4 ? 16384 : 8192;
+    static constexpr int NB = (NB0 * N <= MAXE) ? NB0 : ((MAXE / N) < 1 ? 1 : MAXE / N);
+    static constexpr int NT = pick_nt(NB * N, sizeof(R) == 4 ? 16 : 8);
+    static constexpr int PAD = (NB >= 8) ? 1 : 0;
+};
+
+template <int N>
+__global__ __launch_bounds__(YCfg<N>::NT) void k_y(YArgs a)
+{
+    using C = YCfg<N>;
+    constexpr int NB = C::NB, NT = C::NT;
+    using Tile = LdsTile<R, N, NB, true, C::PAD>;
+    __shared__ Cx<R> s_tile[Tile::elems];
+    __shared__ Cx<R> s_tw[N];
+
+    const int ntile = (a.M + NB - 1) / NB;
+    const int tile_i = blockIdx.x % ntile;
+    const int k = blockIdx.x / ntile;
+    const int m0 = tile_i * NB;
+    load_table(s_tw, (const Cx<R> *)a.tw, N);
+    __syncthreads();
+
+    Cx<R> *base = (Cx<R> *)a.S + (size_t)k * N * a.M + m0;
+    const int M = a.M;
+    const bool inv = a.inverse != 0;
+    auto gload = [&](int b, int n) -> Cx<R> {
+        if (m0 + b >= M) return {R(0), R(0)};
+        Cx<R> v = base[(size_t)n * M + b];
+        return inv ? cconj(v) : v;
+    };
+    auto gstore = [&](int b, int n, Cx<R> v) {
+        if (m0 + b >= M) return;
+        base[(size_t)n * M + b] = inv ? cconj(v) : v;
+    };
+    Tile tile{s_tile};
+    fft_tile<R, N, NB, NT, true, C::PAD, false>(s_tw, 1, gload, gstore, tile);
+}
+
+template <int N> static int run_y(const YArgs &a, hipStream_t s)
+{
+    const int ntile = (a.M + YCfg<N>::NB - 1) / YCfg<N>::NB;
+    hipLaunchKernelGGL(k_y<N>, dim3(ntile * a.nz), dim3(YCfg<N>::NT), 0, s, a);
+    return (int)hipGetLastError();
+}
+
+#define PK_CASE_Y(N) case N: return run_y<N>(a, s);
+
+int PK_SUFFIX(launch_y)(const YArgs &a, hipStream_t s)
+{
+    switch (a.ny) { PK_LENGTHS(PK_CASE_Y) default: return -1; }
+}
+
+}  // namespace pk

@@ -1,0 +1,167 @@
+// k_zperiodic.hip -- z solve for triply periodic boxes: the eigen-expansion
+// of FluTAS Section 3.3.1 applied along z as well.  For each column (m, ky)
+// of the spectrum one workgroup-resident pass does
+//     forward FFT along z -> multiply by 1/((lam_x + lam_y + lam_z) nx ny nz)
+//     (the (0,0,0) mode, the mean, is set to zero) -> inverse FFT along z,
+// reading and writing HBM once.  lam(j) = -(4/h^2) sin^2(pi j/n).
+//
+// Column m = 0 packs the DC and Nyquist x-modes as A + iB (see k_xpass.hip);
+// after the y and z transforms they separate through the Hermitian symmetry
+// of each real mode in (ky, kz):
+//     A(ky,kz) = (Z(ky,kz) + conj Z(-ky,-kz))/2,
+//     B(ky,kz) = (Z(ky,kz) - conj Z(-ky,-kz))/(2i).
+// The first `nspecial` workgroups take the column pairs (ky, -ky) of m = 0,
+// scale A and B with their own eigenvalues and recombine.
+#include "fft_core.hpp"
+#include "lengths.hpp"
+
+#ifndef PK_REAL
+#error "PK_REAL must be defined"
+#endif
+
+namespace pk {
+
+using R = PK_REAL;
+
+template <int N> struct ZPCfg {
+    static constexpr int NB0 = sizeof(R) == 4 ? 16 : 8;
+    static constexpr int MAXE = sizeof(R) == 4 ? 16384 : 8192;
+    static constexpr int NB1 = (NB0 * N <= MAXE) ? NB0 : ((MAXE / N) < 2 ? 2 : MAXE / N);
+    static constexpr int NB = NB1 & ~1;  // even: the m = 0 role works on column pairs
+    static constexpr int NT = pick_nt(NB * N, sizeof(R) == 4 ? 16 : 8);
+    static constexpr int PAD = (NB >= 8) ? 1 : 0;
+};
+
+template <int N>
+__global__ __launch_bounds__(ZPCfg<N>::NT) void k_z_per(ZArgs a, int nspecial)
+{
+    using Cf = ZPCfg<N>;
+    constexpr int NB = Cf::NB, NT = Cf::NT;
+    using Tile = LdsTile<R, N, NB, true, Cf::PAD>;
+    __shared__ Cx<R> s_tile[Tile::elems];
+    __shared__ Cx<R> s_tw[N];
+    load_table(s_tw, (const Cx<R> *)a.tw, N);
+    __syncthreads();
+
+    const int M = a.M, ny = a.ny;
+    const int ncol = ny * M;
+    const size_t plane = (size_t)ncol;
+    Cx<R> *S = (Cx<R> *)a.S;
+    Tile tile{s_tile};
+    auto lstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
+
+    if ((int)blockIdx.x >= nspecial) {
+        const int q0 = ((int)blockIdx.x - nspecial) * NB;
+        auto gload = [&](int b, int n) -> Cx<R> {
+            const int q = q0 + b;
+            if (q >= ncol) return {R(0), R(0)};
+            return S[(size_t)n * plane + q];
+        };
+        fft_tile<R, N, NB, NT, true, Cf::PAD, false>(s_tw, 1, gload, lstore, tile);
+        __syncthreads();
+        auto gload2 = [&](int b, int n) -> Cx<R> {
+            const int q = q0 + b;
+            const int m = q % M, ky = q / M;
+            if (q >= ncol || m == 0) return {R(0), R(0)};
+            const double lam = a.lamx[m] + a.lamy[ky] + a.lamz[n];
+            const R sc = R(a.inv_ntot / lam);
+            return cconj(cscale(tile.at(b, n), sc));
+        };
+        auto gstore2 = [&](int b, int n, Cx<R> v) {
+            const int q = q0 + b;
+            if (q >= ncol || (q % M) == 0) return;
+            S[(size_t)n * plane + q] = cconj(v);
+        };
+        fft_tile<R, N, NB, NT, true, Cf::PAD, true>(s_tw, 1, gload2, gstore2, tile);
+        return;
+    }
+
+    // ---- m = 0 column pairs ------------------------------------------------
+    constexpr int NP = NB / 2;
+    const int pair0 = (int)blockIdx.x * NP;
+    auto col_of = [&](int b, bool &valid, bool &dup) -> int {
+        const int ky = pair0 + b / 2;
+        valid = ky <= ny / 2;
+        const int kyv = valid ? ky : 0;
+        const int kyn = (ny - kyv) % ny;
+        dup = (b & 1) && (kyn == kyv);
+        return (b & 1) ? kyn : kyv;
+    };
+    auto gload = [&](int b, int n) -> Cx<R> {
+        bool valid, dup;
+        const int col = col_of(b, valid, dup);
+        if (!valid) return {R(0), R(0)};
+        return S[(size_t)n * plane + (size_t)col * M];
+    };
+    fft_tile<R, N, NB, NT, true, Cf::PAD, false>(s_tw, 1, gload, lstore, tile);
+    __syncthreads();
+
+    constexpr int NE = NP * N;
+    constexpr int PER = (NE + NT - 1) / NT;
+    Cx<R> o1[PER], o2[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int u = threadIdx.x + e * NT;
+        if (u >= NE) continue;
+        const int i = u % NP, kz = u / NP;
+        const int kzn = (N - kz) % N;
+        const int ky = pair0 + i;
+        if (ky > ny / 2) {
+            o1[e] = o2[e] = {R(0), R(0)};
+            continue;
+        }
+        const double lz = a.lamz[kz], ly = a.lamy[ky];
+        const double lamA = a.lamx[0] + ly + lz, lamB = a.lamx[M] + ly + lz;
+        const R sA = (ky == 0 && kz == 0) ? R(0) : R(a.inv_ntot / lamA);
+        const R sB = R(a.inv_ntot / lamB);
+        // (ky, kz)
+        const Cx<R> z1 = tile.at(2 * i, kz), z2 = cconj(tile.at(2 * i + 1, kzn));
+        if (ky == 0 && kz == 0 && a.zero_mean_out)
+            *a.zero_mean_out = double(z1.re) * a.inv_ntot;  // sum of f over the grid
+        const Cx<R> A = cscale(cadd(z1, z2), R(0.5) * sA);
+        const Cx<R> B = cscale(cmul_mi(csub(z1, z2)), R(0.5) * sB);
+        o1[e] = cadd(A, cmul_pi(B));
+        // (ky, -kz), recombined into column -ky at kz
+        const Cx<R> w1 = tile.at(2 * i, kzn), w2 = cconj(tile.at(2 * i + 1, kz));
+        const Cx<R> Am = cscale(cadd(w1, w2), R(0.5) * sA);
+        const Cx<R> Bm = cscale(cmul_mi(csub(w1, w2)), R(0.5) * sB);
+        o2[e] = cadd(cconj(Am), cmul_pi(cconj(Bm)));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int u = threadIdx.x + e * NT;
+        if (u >= NE) continue;
+        const int i = u % NP, kz = u / NP;
+        tile.at(2 * i, kz) = o1[e];
+        tile.at(2 * i + 1, kz) = o2[e];
+    }
+    __syncthreads();
+    auto gload3 = [&](int b, int n) -> Cx<R> { return cconj(tile.at(b, n)); };
+    auto gstore3 = [&](int b, int n, Cx<R> v) {
+        bool valid, dup;
+        const int col = col_of(b, valid, dup);
+        if (!valid || dup) return;
+        S[(size_t)n * plane + (size_t)col * M] = cconj(v);
+    };
+    fft_tile<R, N, NB, NT, true, Cf::PAD, true>(s_tw, 1, gload3, gstore3, tile);
+}
+
+template <int N> static int run_zp(const ZArgs &a, hipStream_t s)
+{
+    using Cf = ZPCfg<N>;
+    const int npairs = a.ny / 2 + 1;
+    const int nspecial = (npairs + Cf::NB / 2 - 1) / (Cf::NB / 2);
+    const int nmain = (a.ny * a.M + Cf::NB - 1) / Cf::NB;
+    hipLaunchKernelGGL(k_z_per<N>, dim3(nspecial + nmain), dim3(Cf::NT), 0, s, a, nspecial);
+    return (int)hipGetLastError();
+}
+
+#define PK_CASE_ZP(N) case N: return run_zp<N>(a, s);
+
+int PK_SUFFIX(launch_z_periodic)(const ZArgs &a, hipStream_t s)
+{
+    switch (a.nz) { PK_LENGTHS(PK_CASE_ZP) default: return -1; }
+}
+
+}  // namespace pk

@@ -1,0 +1,316 @@
+// k_zwalls.hip -- z solve for wall-bounded boxes (steps 4-6 of the solve
+// sequence in FluTAS Section 3.3.1: the tridiagonal system along z of each
+// wavenumber pair, solved by Gauss elimination).
+//
+// For wavenumbers (m, ky) the transformed equation along z is, per row k,
+//     a p[k-1] + (lam - 2a) p[k] + a p[k+1] = fhat[k] / (nx ny),  a = 1/dz^2,
+// lam = lam_x(m) + lam_y(ky), lam(j) = -(4/h^2) sin^2(pi j/n); the mirrored
+// ghost at the walls turns the end rows into (lam - a) on the diagonal.
+// Divided by a: p[k-1] + beta_k p[k] + p[k+1] = d[k], beta_k = sigma - 2
+// (sigma = lam dz^2), sigma - 1 on the end rows (sigma alone when nz = 1).
+//
+// Gauss elimination without pivoting (Thomas) is done in a partitioned form
+// so that a column is spread over C threads, each holding a chunk of L rows in
+// registers; HBM is read and written once.  With c'_k the elimination
+// multipliers and d'_k the eliminated right-hand side,
+//     c'_k = 1/(beta_k - c'_{k-1}),  d'_k = (d_k - d'_{k-1}) c'_k,
+//     p_k  = d'_k - c'_k p_{k+1},
+// every recurrence is composed per chunk and then across chunks through LDS:
+//   1. c' is a Moebius map of c'_{k-1}: each chunk forms the product of its
+//      2x2 matrices [[0,1],[-1,beta]] (scaled by 1/beta); the product of the
+//      preceding chunks gives c' entering the chunk.
+//   2. d' is affine in the value entering the chunk: d'_k = D_k + G_k d'_{s-1}.
+//   3. p is affine in the value leaving the chunk: p_k = X_k + H_k p_{e+1}.
+// Each composition is a short sequential scan over the C chunks.
+//
+// Column m = 0 of the packed spectrum holds two real x-modes (DC and
+// Nyquist) combined as A + iB; after the y transform they separate as
+//     A(ky) = (Z(ky) + conj Z(-ky))/2,  B(ky) = (Z(ky) - conj Z(-ky))/(2i).
+// The first `nspecial` workgroups take these virtual columns (pairs ky,
+// -ky) and recombine the results with a lane exchange.  The singular column
+// (m, ky) = (0, 0) -- the zero wavenumber -- is solved in FP64 whatever the
+// precision: its right-hand side mean is removed (this removes mean(f), which
+// is reported), p is pinned by the zero-mean gauge, and the Neumann problem
+// p[k-1] - 2p[k] + p[k+1] = g[k] is integrated twice (face fluxes are the
+// running sums of g, p the running sums of the fluxes), then made zero-mean.
+#include "fft_core.hpp"
+#include "lengths.hpp"
+
+#ifndef PK_REAL
+#error "PK_REAL must be defined"
+#endif
+
+namespace pk {
+
+using R = PK_REAL;
+
+template <int L, int W, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a, int C, int nspecial)
+{
+    extern __shared__ double smem_d[];
+    R *buf = (R *)smem_d;                                       // C*W slots of 4 reals
+    double *zbuf = smem_d + ((C * W * 4 * sizeof(R) + 7) / 8);  // 3*C doubles
+
+    const int t = threadIdx.x;
+    const int w = t % W, c = t / W;
+    const int nz = a.nz, M = a.M, ny = a.ny;
+    const size_t plane = (size_t)ny * M;
+    Cx<R> *S = (Cx<R> *)a.S;
+    const int s = c * L;
+    const int e = (s + L < nz) ? s + L : nz;  // chunk rows [s, e)
+    const bool special = (int)blockIdx.x < nspecial;
+    const double scale = a.dz2 * a.inv_nxny;
+
+    Cx<R> d[L];
+    bool active;
+    bool zero_lane = false;
+    int q = 0, ky = 0, kyn = 0, part = 0;
+    double sigma_d;
+    if (!special) {
+        q = ((int)blockIdx.x - nspecial) * W + w;
+        const int m = q % M;
+        ky = q / M;
+        active = (q < ny * M) && (m != 0);
+        sigma_d = active ? (a.lamx[m] + a.lamy[ky]) * a.dz2 : -1.0;
+        const Cx<R> *col = S + (size_t)s * plane + (active ? q : 0);
+#pragma unroll
+        for (int i = 0; i < L; ++i)
+            d[i] = (active && s + i < nz) ? col[(size_t)i * plane] : Cx<R>{R(0), R(0)};
+    } else {
+        const int vc = (int)blockIdx.x * W + w;
+        const int pair = vc >> 1;
+        part = vc & 1;
+        active = pair <= ny / 2;
+        ky = active ? pair : 0;
+        kyn = (ny - ky) % ny;
+        zero_lane = active && pair == 0 && part == 0;
+        const double lx = part ? a.lamx[M] : a.lamx[0];
+        sigma_d = (active && !zero_lane) ? (lx + a.lamy[ky]) * a.dz2 : -1.0;
+        const Cx<R> *c1 = S + (size_t)s * plane + (size_t)ky * M;
+        const Cx<R> *c2 = S + (size_t)s * plane + (size_t)kyn * M;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const int k = s + i;
+            Cx<R> v = {R(0), R(0)};
+            if (active && k < nz) {
+                const Cx<R> z1 = c1[(size_t)i * plane];
+                const Cx<R> z2 = cconj(c2[(size_t)i * plane]);
+                v = part ? cscale(cmul_mi(csub(z1, z2)), R(0.5)) : cscale(cadd(z1, z2), R(0.5));
+            }
+            d[i] = v;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i) d[i] = cscale(d[i], R(scale));
+
+    // zero wavenumber: raw A(0,k) = Re S[k,0,0] is re-read (L1-resident)
+    // whenever needed, so the FP64 path keeps only scalars across barriers
+    auto zraw = [&](int k) -> double { return double(S[(size_t)k * plane].re); };
+
+    const R sig = R(sigma_d);
+    const R ib_int = R(1) / (sig - R(2));
+    const R ib_end = R(1) / (sig - R(1));
+    const R ib_one = R(1) / sig;
+
+    // ---- phase 1: Moebius product of the chunk (c' recurrence) ----------
+    // Rows past nz (only in the last chunk) are padding: zero right-hand
+    // side and the interior diagonal; c' = 0 on row nz-1 decouples them from
+    // the real rows, and nothing reads the last chunk's forward products.
+    R p00 = R(1), p01 = R(0), p10 = R(0), p11 = R(1);
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const int k = s + i;
+        const R ib = (nz == 1) ? ib_one : ((k == 0 || k == nz - 1) ? ib_end : ib_int);
+        const R n00 = ib * p10, n01 = ib * p11;
+        const R n10 = p10 - ib * p00, n11 = p11 - ib * p01;
+        p00 = n00; p01 = n01; p10 = n10; p11 = n11;
+    }
+    R *slot = buf + (size_t)(c * W + w) * 4;
+    slot[0] = p00; slot[1] = p01; slot[2] = p10; slot[3] = p11;
+    if (zero_lane) {
+        double zsum = 0.0;
+        for (int k = s; k < e; ++k) zsum += zraw(k);
+        zbuf[c] = zsum;
+    }
+    __syncthreads();  // S1
+
+    R vn = R(0), vd = R(1);
+    for (int cc = 0; cc < c; ++cc) {
+        const R *o = buf + (size_t)(cc * W + w) * 4;
+        const R nn = o[0] * vn + o[1] * vd;
+        const R nd = o[2] * vn + o[3] * vd;
+        const R mx = fmax(fabs(nn), fabs(nd));
+        const R inv = mx > R(0) ? R(1) / mx : R(1);
+        vn = nn * inv;
+        vd = nd * inv;
+    }
+    const R cprev0 = (c == 0) ? R(0) : vn / vd;
+
+    // zero wavenumber, FP64: g = (raw - mean raw) * scale; face fluxes
+    // F_k = sum_{j<=k} g_j; positions p_k = sum_{j<k} F_j (p_0 = 0)
+    double zmu = 0.0, zF0 = 0.0, zsF = 0.0;
+    if (zero_lane) {
+        double tot = 0.0, pre = 0.0;
+        for (int cc = 0; cc < C; ++cc) {
+            if (cc == c) pre = tot;
+            tot += zbuf[cc];
+        }
+        zmu = tot / nz;
+        if (c == 0 && a.zero_mean_out) *a.zero_mean_out = tot * a.inv_ntot;
+        zF0 = (pre - s * zmu) * scale;  // flux entering the chunk, F_{s-1}
+        double run = zF0;
+        for (int k = s; k < e; ++k) {
+            run += (zraw(k) - zmu) * scale;
+            zsF += run;
+        }
+    }
+    __syncthreads();  // S2: Moebius slots consumed
+
+    // ---- phase 2: local forward elimination ------------------------------
+    R cp[L], G[L];
+    {
+        Cx<R> Dp = {R(0), R(0)};
+        R Gp = R(1), cpv = cprev0;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const int k = s + i;
+            const R beta = (nz == 1) ? sig : ((k == 0 || k == nz - 1) ? sig - R(1) : sig - R(2));
+            const R wv = R(1) / (beta - cpv);
+            Dp = cscale(csub(d[i], Dp), wv);
+            Gp = -wv * Gp;
+            cpv = wv;
+            cp[i] = (k == nz - 1) ? R(0) : wv;
+            G[i] = Gp;
+            d[i] = Dp;
+        }
+        slot[0] = Dp.re; slot[1] = Dp.im; slot[2] = Gp;
+    }
+    if (zero_lane) zbuf[C + c] = zsF;
+    __syncthreads();  // S3
+
+    {
+        Cx<R> dprev = {R(0), R(0)};
+        for (int cc = 0; cc < c; ++cc) {
+            const R *o = buf + (size_t)(cc * W + w) * 4;
+            dprev = {o[0] + o[2] * dprev.re, o[1] + o[2] * dprev.im};
+        }
+#pragma unroll
+        for (int i = 0; i < L; ++i) d[i] = {d[i].re + G[i] * dprev.re, d[i].im + G[i] * dprev.im};
+    }
+    // ---- phase 3: local back substitution --------------------------------
+    Cx<R> Xn = {R(0), R(0)};
+    R Hn = R(1);
+#pragma unroll
+    for (int i = L - 1; i >= 0; --i) {
+        const Cx<R> X = {d[i].re - cp[i] * Xn.re, d[i].im - cp[i] * Xn.im};
+        const R H = -cp[i] * Hn;
+        d[i] = X;
+        G[i] = H;
+        Xn = X;
+        Hn = H;
+    }
+    double zP0 = 0.0, zsx = 0.0;
+    if (zero_lane) {
+        for (int cc = 0; cc < c; ++cc) zP0 += zbuf[C + cc];  // p_s
+        double run = zF0, xk = zP0;
+        for (int k = s; k < e; ++k) {
+            zsx += xk;
+            run += (zraw(k) - zmu) * scale;
+            xk += run;
+        }
+    }
+    __syncthreads();  // S4: slots consumed
+    slot[0] = Xn.re; slot[1] = Xn.im; slot[2] = Hn;
+    if (zero_lane) zbuf[2 * C + c] = zsx;
+    __syncthreads();  // S5
+
+    {
+        Cx<R> y = {R(0), R(0)};
+        for (int cc = C - 1; cc > c; --cc) {
+            const R *o = buf + (size_t)(cc * W + w) * 4;
+            y = {o[0] + o[2] * y.re, o[1] + o[2] * y.im};
+        }
+#pragma unroll
+        for (int i = 0; i < L; ++i) d[i] = {d[i].re + G[i] * y.re, d[i].im + G[i] * y.im};
+    }
+    if (zero_lane) {
+        double tot = 0.0;
+        for (int cc = 0; cc < C; ++cc) tot += zbuf[2 * C + cc];
+        const double mean = tot / nz;
+        double run = zF0, xk = zP0;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const int k = s + i;
+            if (k < nz) {
+                d[i] = {R(xk - mean), R(0)};
+                run += (zraw(k) - zmu) * scale;
+                xk += run;
+            }
+        }
+    }
+    __syncthreads();  // S6: every zero-lane re-read of column (0,0) is done
+
+    // ---- store ------------------------------------------------------------
+    if (!special) {
+        if (active) {
+            Cx<R> *col = S + (size_t)s * plane + q;
+#pragma unroll
+            for (int i = 0; i < L; ++i)
+                if (s + i < nz) col[(size_t)i * plane] = d[i];
+        }
+    } else {
+        // lane pairs (A, B) of one ky are adjacent: exchange and recombine
+        Cx<R> *col = S + (size_t)s * plane + (size_t)(part == 0 ? ky : kyn) * M;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const R ore = __shfl_xor(d[i].re, 1, 64);
+            const R oim = __shfl_xor(d[i].im, 1, 64);
+            const int k = s + i;
+            if (active && k < nz) {
+                if (part == 0) {
+                    // column ky: A + iB
+                    col[(size_t)i * plane] = {d[i].re - oim, d[i].im + ore};
+                } else if (kyn != ky) {
+                    // column -ky: conj(A) + i conj(B)
+                    col[(size_t)i * plane] = {ore + d[i].im, -oim + d[i].re};
+                }
+            }
+        }
+    }
+}
+
+template <int L, int W, int MAXT>
+static int run_zw(const ZArgs &a, hipStream_t s)
+{
+    const int C = (a.nz + L - 1) / L;
+    if (C * W > MAXT) return -1;
+    const int npairs = a.ny / 2 + 1;
+    const int nspecial = (2 * npairs + W - 1) / W;
+    const int nmain = (a.ny * a.M + W - 1) / W;
+    const size_t shm = ((C * W * 4 * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double);
+    hipLaunchKernelGGL((k_z_walls<L, W, MAXT>), dim3(nspecial + nmain), dim3(W * C), shm, s, a,
+                       C, nspecial);
+    return (int)hipGetLastError();
+}
+
+int PK_SUFFIX(launch_z_walls)(const ZArgs &a, hipStream_t s)
+{
+    // chunk length L (registers), W columns per workgroup, W*ceil(nz/L) threads
+    const int nz = a.nz;
+    constexpr bool F32 = sizeof(R) == 4;
+    if (nz <= 64) return run_zw<8, 32, 256>(a, s);
+    if constexpr (F32) {
+        if (nz <= 256) return run_zw<16, 16, 256>(a, s);
+        if (nz <= 512) return run_zw<16, 16, 512>(a, s);
+        if (nz <= 1024) return run_zw<16, 16, 1024>(a, s);
+        if (nz <= 4096) return run_zw<16, 2, 1024>(a, s);
+    } else {
+        if (nz <= 256) return run_zw<8, 16, 512>(a, s);
+        if (nz <= 512) return run_zw<8, 16, 1024>(a, s);
+        if (nz <= 1024) return run_zw<8, 8, 1024>(a, s);
+        if (nz <= 4096) return run_zw<8, 2, 1024>(a, s);
+    }
+    return -1;
+}
+
+}  // namespace pk

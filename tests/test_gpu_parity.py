@@ -1,0 +1,235 @@
+"""GPU parity: the HIP solve (through the C ABI) against the FP64 CPU oracle.
+
+Small grids (spanning several tiles, ragged tails, radix-3 lengths, length-1
+axes) are compared element by element with the oracle.  Full-size workloads
+are checked through properties that hold at any size: the relative residual
+of the discrete equation (evaluated by the oracle's FP64 stencil on the CPU),
+the zero-mean gauge, and exact discrete eigenmodes.
+
+Tolerances (relative L2 unless stated):
+  FP64          error vs oracle <= 1e-12
+  FP32_REFINE   residual <= 1e-10 (the stopping rule); error vs oracle <= 1e-9
+  FP32          error vs oracle <= 2e-5 (single FP32 solve, no refinement)
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2204_08834_amd import inputs  # noqa: E402
+
+NEU, PER = 1, 0
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_08834_amd import poisson
+    poisson.lib()  # raises if the HIP library is missing: no fallback
+    return poisson
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def gpu_solve(f, dx, dy, dz, bc, precision="fp64", rtol=1e-10, max_refine=8):
+    P = _gpu()
+    nz, ny, nx = f.shape
+    print(f"[gpu_solve] {nx}x{ny}x{nz} bc={bc} {precision}", flush=True)
+    rhs = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    with P.Plan(nx, ny, nz, dx, dy, dz, bc, precision, rtol, max_refine) as plan:
+        out, st = plan.solve(rhs)
+        torch.cuda.synchronize()
+    return out.cpu().numpy(), st
+
+
+SMALL = [
+    # nx, ny, nz, Lx, Ly, Lz, bc
+    (32, 32, 32, 1.0, 1.0, 1.0, NEU),      # the 32^3 workload's shape
+    (16, 8, 12, 2.0, 1.0, 0.7, NEU),
+    (64, 48, 20, 2.0, 2.0, 1.0, NEU),      # radix 3 in y, ragged z chunks
+    (96, 96, 48, 2.0, 2.0, 1.0, NEU),      # radix 3 in x and y
+    (24, 12, 33, 1.0, 1.0, 1.0, NEU),      # odd nz, last chunk ragged
+    (8, 4, 300, 1.0, 1.0, 3.0, NEU),       # long z: many chunks
+    (2, 1, 5, 1.0, 1.0, 1.0, NEU),         # nx=2, ny=1
+    (4, 2, 1, 1.0, 1.0, 1.0, NEU),         # nz=1
+    (32, 32, 32, 2 * math.pi, 2 * math.pi, 2 * math.pi, PER),
+    (12, 6, 24, 1.0, 2.0, 3.0, PER),
+    (64, 64, 64, 2 * math.pi, 2 * math.pi, 2 * math.pi, PER),
+    (6, 3, 12, 1.0, 1.0, 1.0, PER),        # odd ny: unpaired ky columns
+    (2, 1, 1, 1.0, 1.0, 1.0, PER),         # the smallest grid
+    (128, 16, 8, 2.0, 1.0, 1.0, PER),
+]
+
+
+def _small_case(case, seed=5):
+    nx, ny, nz, Lx, Ly, Lz, bc = case
+    f = inputs.uniform_velocity_rhs(nx, ny, nz, Lx, Ly, Lz, bc, seed)
+    return f, (Lx / nx, Ly / ny, Lz / nz), bc
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[f"{c[0]}x{c[1]}x{c[2]}_{'w' if c[6] else 'p'}"
+                                             for c in SMALL])
+def test_fp64_matches_oracle(orc, case):
+    f, sp, bc = _small_case(case)
+    p_ref = orc.solve(f, *sp, bc)
+    p, st = gpu_solve(f, *sp, bc, "fp64")
+    assert rel(p, p_ref) <= 1e-12, rel(p, p_ref)
+    assert abs(p.mean()) <= 1e-13 * max(np.abs(p).max(), 1e-300)
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[f"{c[0]}x{c[1]}x{c[2]}_{'w' if c[6] else 'p'}"
+                                             for c in SMALL])
+def test_fp32_refine_matches_oracle(orc, case):
+    f, sp, bc = _small_case(case, seed=6)
+    p_ref = orc.solve(f, *sp, bc)
+    p, st = gpu_solve(f, *sp, bc, "fp32_refine", rtol=1e-10)
+    res, _ = orc.residual(f, p, *sp, bc)
+    assert st["status"] == 0
+    assert st["rel_residual"] <= 1e-10
+    assert res <= 1e-10, res
+    assert abs(res - st["rel_residual"]) <= 1e-12 + 0.05 * res
+    assert rel(p, p_ref) <= 1e-9, rel(p, p_ref)
+
+
+@pytest.mark.parametrize("case", SMALL[:4] + SMALL[8:11])
+def test_fp32_single_solve(orc, case):
+    f, sp, bc = _small_case(case, seed=7)
+    p_ref = orc.solve(f, *sp, bc)
+    p, st = gpu_solve(f, *sp, bc, "fp32")
+    assert rel(p, p_ref) <= 2e-5, rel(p, p_ref)
+
+
+@pytest.mark.parametrize("bc", [NEU, PER])
+def test_mean_removed_and_reported(orc, bc):
+    f, sp, _ = _small_case((16, 8, 12, 1.0, 1.0, 1.0, bc))
+    for prec, tol in (("fp64", 1e-12), ("fp32_refine", 1e-9), ("fp32", 2e-5)):
+        p0, _ = gpu_solve(f, *sp, bc, prec)
+        p1, st = gpu_solve(f + 3.25, *sp, bc, prec)
+        assert abs(st["rhs_mean"] - 3.25) <= 1e-9 * 3.25, (prec, st)
+        assert rel(p1, p0) <= tol * 10, prec
+
+
+def test_walls32_workload(orc):
+    """The 32^3 walls workload: FP64 solve against the oracle at 1e-12."""
+    prob = inputs.workload("walls32")
+    p_ref = orc.solve(prob.f, *prob.spacings(), prob.bc_z)
+    p, st = gpu_solve(prob.f, *prob.spacings(), prob.bc_z, "fp64")
+    assert rel(p, p_ref) <= 1e-12
+    res, _ = orc.residual(prob.f, p, *prob.spacings(), prob.bc_z)
+    assert res <= 1e-13
+
+
+def _eigen(nx, ny, nz, Lx, Ly, Lz, bc, a, b, c):
+    dx, dy, dz = Lx / nx, Ly / ny, Lz / nz
+    i = (np.arange(nx) + 0.5)[None, None, :]
+    j = (np.arange(ny) + 0.5)[None, :, None]
+    k = (np.arange(nz) + 0.5)[:, None, None]
+    fx = np.cos(2 * np.pi * a * i / nx + 0.3)
+    fy = np.cos(2 * np.pi * b * j / ny + 0.1)
+    if bc == PER:
+        fz = np.cos(2 * np.pi * c * k / nz + 0.2)
+        lz = -4 / dz ** 2 * math.sin(math.pi * c / nz) ** 2
+    else:
+        fz = np.cos(np.pi * c * k / nz)
+        lz = -4 / dz ** 2 * math.sin(math.pi * c / (2 * nz)) ** 2
+    lam = -4 / dx ** 2 * math.sin(math.pi * a / nx) ** 2 - 4 / dy ** 2 * math.sin(
+        math.pi * b / ny) ** 2 + lz
+    return fx * fy * fz, lam, (dx, dy, dz)
+
+
+@pytest.mark.parametrize("modes", [(1, 0, 0), (0, 0, 1), (3, 5, 7), (256, 256, 255), (0, 1, 0)])
+def test_eigenmode_full_size_walls(modes):
+    """512x512x256 walls: exact discrete eigenmodes (closed form) at full size."""
+    a, b, c = modes
+    f, lam, sp = _eigen(512, 512, 256, 2.0, 2.0, 1.0, NEU, a, b, c)
+    for prec, tol in (("fp64", 1e-12), ("fp32_refine", 1e-9)):
+        p, st = gpu_solve(f, *sp, NEU, prec)
+        assert rel(p, f / lam) <= tol, (prec, rel(p, f / lam))
+
+
+@pytest.mark.parametrize("modes", [(1, 0, 0), (0, 0, 1), (5, 9, 128), (128, 128, 128)])
+def test_eigenmode_full_size_periodic(modes):
+    a, b, c = modes
+    f, lam, sp = _eigen(256, 256, 256, 2 * math.pi, 2 * math.pi, 2 * math.pi, PER, a, b, c)
+    for prec, tol in (("fp64", 1e-12), ("fp32_refine", 1e-9)):
+        p, st = gpu_solve(f, *sp, PER, prec)
+        assert rel(p, f / lam) <= tol, (prec, rel(p, f / lam))
+
+
+@pytest.mark.parametrize("name", ["rb512", "hit256"])
+def test_full_size_workload_properties(orc, name):
+    """Full-size workloads: FP64 residual <= 1e-12, FP32+refinement <= 1e-10,
+    zero mean, and FP32+refinement within 1e-9 of the FP64 solution."""
+    prob = inputs.workload(name)
+    sp = prob.spacings()
+    p64, st64 = gpu_solve(prob.f, *sp, prob.bc_z, "fp64")
+    r64, _ = orc.residual(prob.f, p64, *sp, prob.bc_z)
+    print(f"{name}: fp64 residual {r64:.3e}", flush=True)
+    assert r64 <= 1e-12
+    assert abs(p64.mean()) <= 1e-13 * np.abs(p64).max()
+    p32, st32 = gpu_solve(prob.f, *sp, prob.bc_z, "fp32_refine")
+    r32, _ = orc.residual(prob.f, p32, *sp, prob.bc_z)
+    print(f"{name}: fp32+refine residual {r32:.3e} after {st32['iterations']} corrections, "
+          f"error vs fp64 {rel(p32, p64):.3e}", flush=True)
+    assert st32["status"] == 0 and r32 <= 1e-10
+    assert rel(p32, p64) <= 1e-9
+
+
+def test_repeat_is_bitwise_deterministic():
+    prob = inputs.scaled("rb512", 64, 64, 32)
+    p1, _ = gpu_solve(prob.f, *prob.spacings(), prob.bc_z, "fp32_refine")
+    p2, _ = gpu_solve(prob.f, *prob.spacings(), prob.bc_z, "fp32_refine")
+    assert np.array_equal(p1, p2)
+
+
+def test_nonfinite_rhs_reports_error():
+    P = _gpu()
+    f = inputs.random_rhs(16, 16, 16, 1)
+    f[3, 4, 5] = np.nan
+    rhs = torch.from_numpy(f).cuda()
+    with P.Plan(16, 16, 16, 0.1, 0.1, 0.1, NEU, "fp32_refine") as plan:
+        _, st = plan.solve(rhs, check=False)
+    assert st["status"] == P.ERR_NONFINITE
+
+
+def test_not_converged_reports_error():
+    P = _gpu()
+    prob = inputs.scaled("rb512", 32, 32, 16)
+    rhs = torch.from_numpy(prob.f).cuda()
+    with P.Plan(32, 32, 16, *prob.spacings(), NEU, "fp32_refine", rtol=1e-20,
+                max_refine=1) as plan:
+        out, st = plan.solve(rhs, check=False)
+    assert st["status"] == P.ERR_NOT_CONVERGED
+    assert st["iterations"] == 1
+    assert np.isfinite(out.cpu().numpy()).all()
+
+
+def test_stream_argument_and_aliasing_rejected():
+    P = _gpu()
+    f = torch.from_numpy(inputs.random_rhs(8, 8, 8, 2)).cuda()
+    s = torch.cuda.Stream()
+    with P.Plan(8, 8, 8, 1.0, 1.0, 1.0, NEU, "fp64", stream=s) as plan:
+        with torch.cuda.stream(s):
+            out, _ = plan.solve(f)
+        s.synchronize()
+        with pytest.raises(P.PoissonError):
+            plan.solve(f, out=f)  # rhs and sol alias
+
+
+def test_timing_reports_passes():
+    P = _gpu()
+    f = torch.from_numpy(inputs.random_rhs(64, 64, 32, 3)).cuda()
+    with P.Plan(64, 64, 32, 1.0, 1.0, 1.0, NEU, "fp64") as plan:
+        plan.set_timing(True)
+        plan.solve(f)
+        t = plan.timing()
+    assert {"x_r2c_f64", "y_fwd_f64", "z_walls_f64", "y_inv_f64", "x_c2r_f64"} <= set(t)
+    assert all(v["launches"] == 1 and v["total_ms"] > 0 for v in t.values())
