@@ -27,6 +27,7 @@
 #endif
 
 namespace pk {
+namespace PK_NS {
 
 using R = PK_REAL;
 
@@ -216,6 +217,9 @@ template <int M> static int blocks_x(int ny, int nz)
 {
     return (ny * nz + XCfg<M>::NB - 1) / XCfg<M>::NB;
 }
+
+}  // namespace PK_NS
+using namespace PK_NS;
 
 #define PK_CASE_FWD(N) case N: return run_x_fwd<N>(a, s);
 #define PK_CASE_INV(N) case N: return run_x_inv<N>(a, s);

@@ -16,6 +16,7 @@
 #endif
 
 namespace pk {
+namespace PK_NS {
 
 using R = PK_REAL;
 
@@ -67,6 +68,9 @@ template <int N> static int run_y(const YArgs &a, hipStream_t s)
     hipLaunchKernelGGL(k_y<N>, dim3(ntile * a.nz), dim3(YCfg<N>::NT), 0, s, a);
     return (int)hipGetLastError();
 }
+
+}  // namespace PK_NS
+using namespace PK_NS;
 
 #define PK_CASE_Y(N) case N: return run_y<N>(a, s);
 

@@ -20,6 +20,7 @@
 #endif
 
 namespace pk {
+namespace PK_NS {
 
 using R = PK_REAL;
 
@@ -156,6 +157,9 @@ template <int N> static int run_zp(const ZArgs &a, hipStream_t s)
     hipLaunchKernelGGL(k_z_per<N>, dim3(nspecial + nmain), dim3(Cf::NT), 0, s, a, nspecial);
     return (int)hipGetLastError();
 }
+
+}  // namespace PK_NS
+using namespace PK_NS;
 
 #define PK_CASE_ZP(N) case N: return run_zp<N>(a, s);
 

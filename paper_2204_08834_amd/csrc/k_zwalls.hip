@@ -9,16 +9,27 @@
 // Divided by a: p[k-1] + beta_k p[k] + p[k+1] = d[k], beta_k = sigma - 2
 // (sigma = lam dz^2), sigma - 1 on the end rows (sigma alone when nz = 1).
 //
-// Gauss elimination without pivoting (Thomas) is done in a partitioned form
-// so that a column is spread over C threads, each holding a chunk of L rows in
-// registers; HBM is read and written once.  With c'_k the elimination
-// multipliers and d'_k the eliminated right-hand side,
+// Gauss elimination without pivoting (Thomas):
 //     c'_k = 1/(beta_k - c'_{k-1}),  d'_k = (d_k - d'_{k-1}) c'_k,
-//     p_k  = d'_k - c'_k p_{k+1},
-// every recurrence is composed per chunk and then across chunks through LDS:
-//   1. c' is a Moebius map of c'_{k-1}: each chunk forms the product of its
-//      2x2 matrices [[0,1],[-1,beta]] (scaled by 1/beta); the product of the
-//      preceding chunks gives c' entering the chunk.
+//     p_k  = d'_k - c'_k p_{k+1}.
+// Deficit form.  For the lowest wavenumbers sigma is tiny (about -1.5e-4 for
+// (m, ky) = (1, 0) on 512x512x256), and forming beta = sigma - 2 rounds away
+// most of sigma (a 1e-12 relative error in FP64, 3e-3 in FP32).  With
+// s = -sigma >= 0, u_k = -c'_k and v_k = 1 - u_k, every pivot is a sum of
+// non-negative terms:
+//     |pivot_0| = 1 + s,  |pivot_k| = 1 + s + v_{k-1},  |pivot_{nz-1}| = s + v_{nz-2},
+//     u_k = 1/|pivot_k|,  v_k = (|pivot_k| - 1) u_k,
+//     d'_k = (d'_{k-1} - d_k) u_k,  p_k = d'_k + p_{k+1} - v_k p_{k+1},
+// so s keeps its full relative precision and the near-singular last pivot is
+// formed without cancellation.
+//
+// Partitioned form: a column is spread over C threads, each holding a chunk of
+// L rows in registers; HBM is read and written once.  Every recurrence is
+// composed per chunk and then across chunks through LDS:
+//   1. v is a Moebius map of v_{k-1}: v -> (s + v)/(1 + s + v), matrix
+//      [[1, s], [1, 1+s]]/(1+s) (all entries >= 0, so products do not cancel;
+//      row 0 maps anything to s/(1+s)).  The product of the preceding chunks
+//      gives v entering the chunk.
 //   2. d' is affine in the value entering the chunk: d'_k = D_k + G_k d'_{s-1}.
 //   3. p is affine in the value leaving the chunk: p_k = X_k + H_k p_{e+1}.
 // Each composition is a short sequential scan over the C chunks.
@@ -41,6 +52,7 @@
 #endif
 
 namespace pk {
+namespace PK_NS {
 
 using R = PK_REAL;
 
@@ -65,13 +77,13 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a, int C, int nspecial)
     bool active;
     bool zero_lane = false;
     int q = 0, ky = 0, kyn = 0, part = 0;
-    double sigma_d;
+    double s_d;  // s = -(lam_x + lam_y) dz^2 >= 0
     if (!special) {
         q = ((int)blockIdx.x - nspecial) * W + w;
         const int m = q % M;
         ky = q / M;
         active = (q < ny * M) && (m != 0);
-        sigma_d = active ? (a.lamx[m] + a.lamy[ky]) * a.dz2 : -1.0;
+        s_d = active ? -(a.lamx[m] + a.lamy[ky]) * a.dz2 : 1.0;
         const Cx<R> *col = S + (size_t)s * plane + (active ? q : 0);
 #pragma unroll
         for (int i = 0; i < L; ++i)
@@ -85,7 +97,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a, int C, int nspecial)
         kyn = (ny - ky) % ny;
         zero_lane = active && pair == 0 && part == 0;
         const double lx = part ? a.lamx[M] : a.lamx[0];
-        sigma_d = (active && !zero_lane) ? (lx + a.lamy[ky]) * a.dz2 : -1.0;
+        s_d = (active && !zero_lane) ? -(lx + a.lamy[ky]) * a.dz2 : 1.0;
         const Cx<R> *c1 = S + (size_t)s * plane + (size_t)ky * M;
         const Cx<R> *c2 = S + (size_t)s * plane + (size_t)kyn * M;
 #pragma unroll
@@ -107,22 +119,21 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a, int C, int nspecial)
     // whenever needed, so the FP64 path keeps only scalars across barriers
     auto zraw = [&](int k) -> double { return double(S[(size_t)k * plane].re); };
 
-    const R sig = R(sigma_d);
-    const R ib_int = R(1) / (sig - R(2));
-    const R ib_end = R(1) / (sig - R(1));
-    const R ib_one = R(1) / sig;
+    const R sv = R(s_d);
+    const R mw = R(1) / (R(1) + sv);  // Moebius matrix [[1, s], [1, 1+s]] / (1+s)
+    const R mws = sv * mw;
 
-    // ---- phase 1: Moebius product of the chunk (c' recurrence) ----------
+    // ---- phase 1: Moebius product of the chunk (v recurrence) -----------
     // Rows past nz (only in the last chunk) are padding: zero right-hand
-    // side and the interior diagonal; c' = 0 on row nz-1 decouples them from
-    // the real rows, and nothing reads the last chunk's forward products.
+    // side; v = 1 (u = 0) on row nz-1 decouples them from the real rows in
+    // the back substitution, and nothing reads the last chunk's products.
     R p00 = R(1), p01 = R(0), p10 = R(0), p11 = R(1);
 #pragma unroll
     for (int i = 0; i < L; ++i) {
         const int k = s + i;
-        const R ib = (nz == 1) ? ib_one : ((k == 0 || k == nz - 1) ? ib_end : ib_int);
-        const R n00 = ib * p10, n01 = ib * p11;
-        const R n10 = p10 - ib * p00, n11 = p11 - ib * p01;
+        const R a0 = (k == 0) ? R(0) : mw;  // row 0 ignores the entering v
+        const R n00 = a0 * p00 + mws * p10, n01 = a0 * p01 + mws * p11;
+        const R n10 = a0 * p00 + p10, n11 = a0 * p01 + p11;
         p00 = n00; p01 = n01; p10 = n10; p11 = n11;
     }
     R *slot = buf + (size_t)(c * W + w) * 4;
@@ -144,7 +155,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a, int C, int nspecial)
         vn = nn * inv;
         vd = nd * inv;
     }
-    const R cprev0 = (c == 0) ? R(0) : vn / vd;
+    const R vprev0 = (c == 0) ? R(0) : vn / vd;
 
     // zero wavenumber, FP64: g = (raw - mean raw) * scale; face fluxes
     // F_k = sum_{j<=k} g_j; positions p_k = sum_{j<k} F_j (p_0 = 0)
@@ -167,21 +178,25 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a, int C, int nspecial)
     __syncthreads();  // S2: Moebius slots consumed
 
     // ---- phase 2: local forward elimination ------------------------------
-    R cp[L], G[L];
+    R vk[L], G[L];
     {
         Cx<R> Dp = {R(0), R(0)};
-        R Gp = R(1), cpv = cprev0;
+        R Gp = R(1), vprev = vprev0;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             const int k = s + i;
-            const R beta = (nz == 1) ? sig : ((k == 0 || k == nz - 1) ? sig - R(1) : sig - R(2));
-            const R wv = R(1) / (beta - cpv);
-            Dp = cscale(csub(d[i], Dp), wv);
-            Gp = -wv * Gp;
-            cpv = wv;
-            cp[i] = (k == nz - 1) ? R(0) : wv;
+            // |pivot| = (excess over 1) + 1, except the last row (and nz = 1)
+            const R ex = (k == 0) ? sv : sv + vprev;
+            const bool last = k >= nz - 1;
+            const R piv = (nz == 1) ? sv : (k == nz - 1 ? ex : R(1) + ex);
+            const R u = R(1) / piv;
+            const R vnew = last ? R(1) : ex * u;
+            Dp = cscale(csub(Dp, d[i]), u);
+            Gp = u * Gp;
+            vk[i] = vnew;
             G[i] = Gp;
             d[i] = Dp;
+            vprev = vnew;
         }
         slot[0] = Dp.re; slot[1] = Dp.im; slot[2] = Gp;
     }
@@ -202,8 +217,9 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a, int C, int nspecial)
     R Hn = R(1);
 #pragma unroll
     for (int i = L - 1; i >= 0; --i) {
-        const Cx<R> X = {d[i].re - cp[i] * Xn.re, d[i].im - cp[i] * Xn.im};
-        const R H = -cp[i] * Hn;
+        // p_k = d'_k + u_k p_{k+1} written as d'_k + (p_{k+1} - v_k p_{k+1})
+        const Cx<R> X = {d[i].re + (Xn.re - vk[i] * Xn.re), d[i].im + (Xn.im - vk[i] * Xn.im)};
+        const R H = (R(1) - vk[i]) * Hn;
         d[i] = X;
         G[i] = H;
         Xn = X;
@@ -292,6 +308,9 @@ static int run_zw(const ZArgs &a, hipStream_t s)
                        C, nspecial);
     return (int)hipGetLastError();
 }
+
+}  // namespace PK_NS
+using namespace PK_NS;
 
 int PK_SUFFIX(launch_z_walls)(const ZArgs &a, hipStream_t s)
 {

@@ -11,4 +11,9 @@
 #define PK_CAT(a, b) PK_CAT2(a, b)
 #ifdef PK_TAG
 #define PK_SUFFIX(name) PK_CAT(name, PK_TAG)
+// Kernels of a precision-templated source live in their own namespace: the
+// source is compiled once per precision and the kernel templates are not
+// parameterised on the real type, so without it the FP32 and FP64 objects
+// would define identically-named kernels and the link would keep only one.
+#define PK_NS PK_CAT(prec, PK_TAG)
 #endif
