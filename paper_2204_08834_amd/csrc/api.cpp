@@ -1,8 +1,9 @@
 // api.cpp -- C ABI of the FFT-based Poisson solver (declared in
 // include/poisson.h): descriptor validation, plan construction (FP64
 // twiddle and eigenvalue tables, workspace), the pass sequence of FluTAS
-// Section 3.3.1 (forward x, forward y, z solve, backward y, backward x) and
-// the FP32 + FP64-residual iterative refinement loop.
+// Section 3.3.1 (forward x, forward y, z solve, backward y, backward x), the
+// FP32 + FP64-residual iterative refinement loop, and batched solves in which
+// problems of one shape share every launch.
 #include "../../include/poisson.h"
 
 #include <hip/hip_runtime.h>
@@ -15,7 +16,6 @@
 #include <map>
 #include <memory>
 #include <string>
-#include <tuple>
 #include <vector>
 
 #include "common.hpp"
@@ -33,8 +33,8 @@ void cis_2pi(long t, long n, double &c, double &s)
 {
     t %= n;
     if (t < 0) t += n;
-    const long q = (4 * t) / n;          // quadrant
-    const long r = 4 * t - q * n;        // angle within quadrant = (r/n) pi/2
+    const long q = (4 * t) / n;    // quadrant
+    const long r = 4 * t - q * n;  // angle within the quadrant = (r/n) pi/2
     long double cc, ss;
     const long double halfpi = 1.5707963267948966192313216916397514L;
     if (2 * r <= n) {
@@ -46,7 +46,7 @@ void cis_2pi(long t, long n, double &c, double &s)
         cc = sinl(phi);
         ss = cosl(phi);
     }
-    double c0 = (double)cc, s0 = (double)ss;
+    const double c0 = (double)cc, s0 = (double)ss;
     switch (q) {
     case 0: c = c0; s = s0; break;
     case 1: c = -s0; s = c0; break;
@@ -55,7 +55,7 @@ void cis_2pi(long t, long n, double &c, double &s)
     }
 }
 
-// exp(-2 pi i t/n), t in [0, n)
+// exp(-2 pi i t/n), t in [0, n), interleaved (re, im)
 std::vector<double> twiddle_table(int n)
 {
     std::vector<double> tw(2 * (size_t)n);
@@ -82,7 +82,7 @@ std::vector<double> eig_table(int n, double h, int count)
 }
 
 // ---------------------------------------------------------------------------
-// plan
+// device buffers
 // ---------------------------------------------------------------------------
 struct DevBuf {
     void *p = nullptr;
@@ -92,32 +92,12 @@ struct DevBuf {
     }
 };
 
-struct Tables {
-    // complex twiddle tables per precision (index 0 = f64, 1 = f32)
-    std::shared_ptr<DevBuf> twx[2], twy[2], twz[2];
-    std::shared_ptr<DevBuf> lamx, lamy, lamz;
-};
-
-struct Timed {
-    std::string name;
-    double bytes;
-    hipEvent_t e0, e1;
-};
-
-struct PassStat {
-    int launches = 0;
-    double total_ms = 0.0;
-    double bytes = 0.0;
-};
-
-struct Sub {
-    poisson_desc_t d;
-    int M = 0;
-    long long N = 0;
-    Tables tab;
-    std::shared_ptr<DevBuf> S32;  // FP32 spectrum (FP32 modes)
-    std::shared_ptr<DevBuf> partials;
-    int npart = 0;
+struct PinnedBuf {
+    void *p = nullptr;
+    ~PinnedBuf()
+    {
+        if (p) (void)hipHostFree(p);
+    }
 };
 
 bool fail_alloc_hook()
@@ -137,6 +117,19 @@ int dev_alloc(std::shared_ptr<DevBuf> &out, size_t bytes)
         return POISSON_ERR_OUT_OF_MEMORY;
     }
     out = b;
+    return POISSON_OK;
+}
+
+int pinned_alloc(std::unique_ptr<PinnedBuf> &out, size_t bytes)
+{
+    if (fail_alloc_hook()) return POISSON_ERR_OUT_OF_MEMORY;
+    out.reset(new PinnedBuf());
+    if (hipHostMalloc(&out->p, bytes, 0) != hipSuccess) {
+        out->p = nullptr;
+        (void)hipGetLastError();
+        return POISSON_ERR_OUT_OF_MEMORY;
+    }
+    memset(out->p, 0, bytes);
     return POISSON_OK;
 }
 
@@ -161,6 +154,40 @@ int upload_complex(std::shared_ptr<DevBuf> out[2], const std::vector<double> &tw
     return POISSON_OK;
 }
 
+// ---------------------------------------------------------------------------
+// plan structures
+// ---------------------------------------------------------------------------
+struct Tables {
+    std::shared_ptr<DevBuf> twx[2], twy[2], twz[2];  // [0] FP64, [1] FP32 complex tables
+    std::shared_ptr<DevBuf> lamx, lamy, lamz;
+};
+
+// problems with identical descriptors: one set of tables, one launch per pass
+struct Group {
+    poisson_desc_t d;
+    int M = 0;
+    long long N = 0;
+    Tables tab;
+    std::vector<int> members;          // problem indices in the plan
+    std::shared_ptr<DevBuf> S32;       // FP32 spectra, one per member
+    std::shared_ptr<DevBuf> partials;  // x-pass partial sums, npart*2 per member
+    int npart = 0;
+    std::shared_ptr<DevBuf> ptrs;      // device ProbPtrs[members]
+    int host_off = 0;                  // offset of this group's staging entries
+};
+
+struct Timed {
+    std::string name;
+    double bytes;
+    hipEvent_t e0, e1;
+};
+
+struct PassStat {
+    int launches = 0;
+    double total_ms = 0.0;
+    double bytes = 0.0;
+};
+
 }  // namespace
 
 struct poisson_plan_s {
@@ -169,9 +196,14 @@ struct poisson_plan_s {
     int precision = 0;
     double rtol = 1e-10;
     int max_refine = 8;
-    std::vector<Sub> subs;
-    std::shared_ptr<DevBuf> scalars;   // device FP64 scalars, 4 per sub
-    double *host_scalars = nullptr;    // pinned mirror
+    bool batched = false;
+    int count = 0;
+    std::vector<Group> groups;
+    std::vector<std::pair<int, int>> where;  // problem -> (group, member slot)
+    std::shared_ptr<DevBuf> scalars;         // 4 FP64 scalars per problem
+    std::unique_ptr<PinnedBuf> host_scalars;
+    std::unique_ptr<PinnedBuf> host_ptrs;    // ProbPtrs staging for batched launches
+    hipEvent_t ptrs_done = nullptr;          // last staging upload has been consumed
     bool timing = false;
     std::vector<Timed> pending;
     std::vector<hipEvent_t> event_pool;
@@ -184,7 +216,7 @@ struct poisson_plan_s {
             event_pool.push_back(t.e1);
         }
         for (auto e : event_pool) (void)hipEventDestroy(e);
-        if (host_scalars) (void)hipHostFree(host_scalars);
+        if (ptrs_done) (void)hipEventDestroy(ptrs_done);
     }
 };
 
@@ -223,49 +255,47 @@ int validate(const poisson_desc_t *d)
     return POISSON_OK;
 }
 
+int internal_prec(int precision) { return precision == POISSON_FP64 ? P_F64 : P_F32; }
+
 size_t workspace_bytes(const poisson_desc_t *d)
 {
     const size_t n = (size_t)d->nx * d->ny * d->nz;
     size_t b = 0;
     if (d->precision != POISSON_FP64) b += n * 4;  // FP32 half spectrum: N/2 complex floats
-    const int nb = x_fwd_blocks(d->precision == POISSON_FP64 ? P_F64 : P_F32, d->nx, d->ny, d->nz);
+    const int nb = x_fwd_blocks(internal_prec(d->precision), d->nx, d->ny, d->nz);
     b += (size_t)(nb > 0 ? nb : 1) * 2 * sizeof(double);
     return b;
 }
 
-int build_sub(Sub &s, const poisson_desc_t &d, std::map<std::string, Tables> &cache)
+bool same_problem(const poisson_desc_t &a, const poisson_desc_t &b)
 {
-    s.d = d;
-    s.M = d.nx / 2;
-    s.N = (long long)d.nx * d.ny * d.nz;
-    const bool f32 = d.precision != POISSON_FP64;
-    const bool f64 = d.precision == POISSON_FP64;
-    char key[256];
-    snprintf(key, sizeof key, "%d %d %d %.17g %.17g %.17g %d %d", d.nx, d.ny, d.nz, d.dx, d.dy,
-             d.dz, d.bc_z, d.precision);
-    auto it = cache.find(key);
+    return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.dx == b.dx && a.dy == b.dy &&
+           a.dz == b.dz && a.bc_z == b.bc_z;
+}
+
+int build_group(Group &g)
+{
+    const poisson_desc_t &d = g.d;
+    g.M = d.nx / 2;
+    g.N = (long long)d.nx * d.ny * d.nz;
+    const bool f32 = d.precision != POISSON_FP64, f64 = !f32;
     int rc;
-    if (it != cache.end()) {
-        s.tab = it->second;
-    } else {
-        Tables t;
-        if ((rc = upload_complex(t.twx, twiddle_table(d.nx), f32, f64))) return rc;
-        if ((rc = upload_complex(t.twy, twiddle_table(d.ny), f32, f64))) return rc;
-        if (d.bc_z == POISSON_BC_PERIODIC &&
-            (rc = upload_complex(t.twz, twiddle_table(d.nz), f32, f64)))
-            return rc;
-        auto lx = eig_table(d.nx, d.dx, s.M + 1);
-        auto ly = eig_table(d.ny, d.dy, d.ny);
-        auto lz = eig_table(d.nz, d.dz, d.nz);
-        if ((rc = upload(t.lamx, lx.data(), lx.size() * 8))) return rc;
-        if ((rc = upload(t.lamy, ly.data(), ly.size() * 8))) return rc;
-        if ((rc = upload(t.lamz, lz.data(), lz.size() * 8))) return rc;
-        cache[key] = t;
-        s.tab = t;
-    }
-    if (f32 && (rc = dev_alloc(s.S32, (size_t)s.N * 4))) return rc;
-    s.npart = x_fwd_blocks(f32 ? P_F32 : P_F64, d.nx, d.ny, d.nz);
-    if ((rc = dev_alloc(s.partials, (size_t)s.npart * 2 * sizeof(double)))) return rc;
+    Tables &t = g.tab;
+    if ((rc = upload_complex(t.twx, twiddle_table(d.nx), f32, f64))) return rc;
+    if ((rc = upload_complex(t.twy, twiddle_table(d.ny), f32, f64))) return rc;
+    if (d.bc_z == POISSON_BC_PERIODIC && (rc = upload_complex(t.twz, twiddle_table(d.nz), f32, f64)))
+        return rc;
+    auto lx = eig_table(d.nx, d.dx, g.M + 1);
+    auto ly = eig_table(d.ny, d.dy, d.ny);
+    auto lz = eig_table(d.nz, d.dz, d.nz);
+    if ((rc = upload(t.lamx, lx.data(), lx.size() * 8))) return rc;
+    if ((rc = upload(t.lamy, ly.data(), ly.size() * 8))) return rc;
+    if ((rc = upload(t.lamz, lz.data(), lz.size() * 8))) return rc;
+    const size_t n = g.members.size();
+    if (f32 && (rc = dev_alloc(g.S32, (size_t)g.N * 4 * n))) return rc;
+    g.npart = x_fwd_blocks(internal_prec(d.precision), d.nx, d.ny, d.nz);
+    if ((rc = dev_alloc(g.partials, (size_t)g.npart * 2 * sizeof(double) * n))) return rc;
+    if ((rc = dev_alloc(g.ptrs, sizeof(ProbPtrs) * n))) return rc;
     return POISSON_OK;
 }
 
@@ -323,177 +353,138 @@ void collect_timing(poisson_plan p)
 const char *tag(int prec) { return prec == P_F32 ? "f32" : "f64"; }
 
 // ---------------------------------------------------------------------------
-// the pass sequence of one solve
+// one pass over a set of problems of one group
 // ---------------------------------------------------------------------------
-struct SolveCtx {
+// `dev` null: a single problem with the pointers in `one`; otherwise `n`
+// problems whose ProbPtrs are in device memory at `dev`.
+struct LSet {
     poisson_plan p;
-    Sub *s;
-    double *scal;  // device scalars of this sub: [0] mean (z pass), [1] sum f, [2] sum r^2, [3] sum fbar^2
+    Group *g;
+    int prec;
+    const ProbPtrs *dev;
+    int n;
+    ProbPtrs one;
 };
 
-// forward x (plain or residual input) -> spectrum S
-int pass_x_fwd(SolveCtx &c, int prec, const double *f, const double *p, void *S, bool residual,
-               bool want_partials)
+int pass_x_fwd(LSet &L, bool residual, bool want_partials)
 {
-    Sub &s = *c.s;
-    const double sb = prec == P_F32 ? 4.0 : 8.0;
+    Group &g = *L.g;
+    const double sb = L.prec == P_F32 ? 4.0 : 8.0;
     XFwdArgs a{};
-    a.f = f;
-    a.p = p;
-    a.S = S;
-    a.tw = s.tab.twx[prec == P_F32 ? 1 : 0]->p;
-    a.partials = want_partials ? (double *)s.partials->p : nullptr;
-    a.nx = s.d.nx;
-    a.ny = s.d.ny;
-    a.nz = s.d.nz;
-    a.bc_z = s.d.bc_z;
-    a.ax = 1.0 / (s.d.dx * s.d.dx);
-    a.ay = 1.0 / (s.d.dy * s.d.dy);
-    a.az = 1.0 / (s.d.dz * s.d.dz);
-    a.sum_f = c.scal + 1;
-    a.inv_n = 1.0 / (double)s.N;
+    a.batch = L.dev;
+    a.nbatch = L.n;
+    a.f = L.one.f;
+    a.p = L.one.p;
+    a.S = L.one.S;
+    a.tw = g.tab.twx[L.prec == P_F32 ? 1 : 0]->p;
+    a.partials = want_partials ? (L.dev ? (double *)g.partials->p : L.one.partials) : nullptr;
+    a.nx = g.d.nx;
+    a.ny = g.d.ny;
+    a.nz = g.d.nz;
+    a.bc_z = g.d.bc_z;
+    a.ax = 1.0 / (g.d.dx * g.d.dx);
+    a.ay = 1.0 / (g.d.dy * g.d.dy);
+    a.az = 1.0 / (g.d.dz * g.d.dz);
+    a.sum_f = L.one.scal ? L.one.scal + 1 : nullptr;
+    a.inv_n = 1.0 / (double)g.N;
     a.residual = residual ? 1 : 0;
     char name[40];
-    snprintf(name, sizeof name, residual ? "x_r2c_residual_%s" : "x_r2c_%s", tag(prec));
-    const double bytes = (double)s.N * ((residual ? 16.0 : 8.0) + sb);
-    int rc = timed(c.p, name, bytes, [&] { return launch_x_fwd(prec, a, nullptr, c.p->stream); });
-    if (rc) return rc;
-    if (want_partials) {
-        // partials hold two interleaved sums per workgroup: plain input ->
-        // (sum f, 0) into scal[1..2]; residual -> (sum r^2, sum fbar^2) into scal[2..3]
-        double *dst = residual ? c.scal + 2 : c.scal + 1;
-        rc = timed(c.p, "sum_partials", (double)s.npart * 16.0, [&] {
-            return launch_sum_partials((const double *)s.partials->p, s.npart, 2, dst,
-                                       c.p->stream);
-        });
-    }
-    return rc;
+    snprintf(name, sizeof name, residual ? "x_r2c_residual_%s" : "x_r2c_%s", tag(L.prec));
+    const double bytes = (double)g.N * ((residual ? 16.0 : 8.0) + sb) * L.n;
+    int rc = timed(L.p, name, bytes,
+                   [&] { return launch_x_fwd(L.prec, a, nullptr, L.p->stream); });
+    if (rc || !want_partials) return rc;
+    // two interleaved sums per workgroup: plain input -> (sum f, 0) into
+    // scal[1..2]; residual -> (sum r^2, sum fbar^2) into scal[2..3]
+    const int off = residual ? 2 : 1;
+    return timed(L.p, "sum_partials", (double)g.npart * 16.0 * L.n, [&] {
+        return launch_sum_partials(L.one.partials, g.npart, L.one.scal ? L.one.scal + off : nullptr,
+                                   L.dev, L.n, off, L.p->stream);
+    });
 }
 
-int pass_y(SolveCtx &c, int prec, void *S, bool inverse)
+int pass_y(LSet &L, bool inverse)
 {
-    Sub &s = *c.s;
-    if (s.d.ny == 1) return POISSON_OK;  // a length-1 transform is the identity
-    YArgs a{S, s.tab.twy[prec == P_F32 ? 1 : 0]->p, s.M, s.d.ny, s.d.nz, inverse ? 1 : 0};
+    Group &g = *L.g;
+    if (g.d.ny == 1) return POISSON_OK;  // a length-1 transform is the identity
+    YArgs a{L.dev, L.n, L.one.S, g.tab.twy[L.prec == P_F32 ? 1 : 0]->p, g.M, g.d.ny, g.d.nz,
+            inverse ? 1 : 0};
     char name[40];
-    snprintf(name, sizeof name, inverse ? "y_inv_%s" : "y_fwd_%s", tag(prec));
-    const double bytes = (double)s.N * 2.0 * (prec == P_F32 ? 4.0 : 8.0);
-    return timed(c.p, name, bytes, [&] { return launch_y(prec, a, c.p->stream); });
+    snprintf(name, sizeof name, inverse ? "y_inv_%s" : "y_fwd_%s", tag(L.prec));
+    const double bytes = (double)g.N * 2.0 * (L.prec == P_F32 ? 4.0 : 8.0) * L.n;
+    return timed(L.p, name, bytes, [&] { return launch_y(L.prec, a, L.p->stream); });
 }
 
-int pass_z(SolveCtx &c, int prec, void *S)
+int pass_z(LSet &L)
 {
-    Sub &s = *c.s;
+    Group &g = *L.g;
     ZArgs a{};
-    a.S = S;
-    a.tw = s.d.bc_z == POISSON_BC_PERIODIC ? s.tab.twz[prec == P_F32 ? 1 : 0]->p : nullptr;
-    a.lamx = (const double *)s.tab.lamx->p;
-    a.lamy = (const double *)s.tab.lamy->p;
-    a.lamz = (const double *)s.tab.lamz->p;
-    a.zero_mean_out = c.scal + 0;
-    a.M = s.M;
-    a.ny = s.d.ny;
-    a.nz = s.d.nz;
-    a.nx = s.d.nx;
-    a.dz2 = s.d.dz * s.d.dz;
-    a.inv_nxny = 1.0 / ((double)s.d.nx * s.d.ny);
-    a.inv_ntot = 1.0 / (double)s.N;
-    const double bytes = (double)s.N * 2.0 * (prec == P_F32 ? 4.0 : 8.0);
+    a.batch = L.dev;
+    a.nbatch = L.n;
+    a.S = L.one.S;
+    a.tw = g.d.bc_z == POISSON_BC_PERIODIC ? g.tab.twz[L.prec == P_F32 ? 1 : 0]->p : nullptr;
+    a.lamx = (const double *)g.tab.lamx->p;
+    a.lamy = (const double *)g.tab.lamy->p;
+    a.lamz = (const double *)g.tab.lamz->p;
+    // non-null requests the mean; batched launches redirect it per problem
+    a.zero_mean_out = L.dev ? (double *)g.partials->p : L.one.scal;
+    a.M = g.M;
+    a.ny = g.d.ny;
+    a.nz = g.d.nz;
+    a.nx = g.d.nx;
+    a.dz2 = g.d.dz * g.d.dz;
+    a.inv_nxny = 1.0 / ((double)g.d.nx * g.d.ny);
+    a.inv_ntot = 1.0 / (double)g.N;
+    const double bytes = (double)g.N * 2.0 * (L.prec == P_F32 ? 4.0 : 8.0) * L.n;
     char name[40];
-    if (s.d.bc_z == POISSON_BC_NEUMANN) {
-        snprintf(name, sizeof name, "z_walls_%s", tag(prec));
-        return timed(c.p, name, bytes, [&] { return launch_z_walls(prec, a, c.p->stream); });
+    if (g.d.bc_z == POISSON_BC_NEUMANN) {
+        snprintf(name, sizeof name, "z_walls_%s", tag(L.prec));
+        return timed(L.p, name, bytes, [&] { return launch_z_walls(L.prec, a, L.p->stream); });
     }
-    snprintf(name, sizeof name, "z_periodic_%s", tag(prec));
-    return timed(c.p, name, bytes, [&] { return launch_z_periodic(prec, a, c.p->stream); });
+    snprintf(name, sizeof name, "z_periodic_%s", tag(L.prec));
+    return timed(L.p, name, bytes, [&] { return launch_z_periodic(L.prec, a, L.p->stream); });
 }
 
-int pass_x_inv(SolveCtx &c, int prec, const void *S, double *p, bool accumulate)
+int pass_x_inv(LSet &L, bool accumulate)
 {
-    Sub &s = *c.s;
-    XInvArgs a{S, p, s.tab.twx[prec == P_F32 ? 1 : 0]->p, s.d.nx, s.d.ny, s.d.nz,
-               accumulate ? 1 : 0};
+    Group &g = *L.g;
+    XInvArgs a{L.dev, L.n, L.one.S, L.one.p, g.tab.twx[L.prec == P_F32 ? 1 : 0]->p, g.d.nx,
+               g.d.ny, g.d.nz, accumulate ? 1 : 0};
     char name[40];
-    snprintf(name, sizeof name, accumulate ? "x_c2r_accumulate_%s" : "x_c2r_%s", tag(prec));
-    const double sb = prec == P_F32 ? 4.0 : 8.0;
-    const double bytes = (double)s.N * (sb + (accumulate ? 16.0 : 8.0));
-    return timed(c.p, name, bytes, [&] { return launch_x_inv(prec, a, c.p->stream); });
+    snprintf(name, sizeof name, accumulate ? "x_c2r_accumulate_%s" : "x_c2r_%s", tag(L.prec));
+    const double sb = L.prec == P_F32 ? 4.0 : 8.0;
+    const double bytes = (double)g.N * (sb + (accumulate ? 16.0 : 8.0)) * L.n;
+    return timed(L.p, name, bytes, [&] { return launch_x_inv(L.prec, a, L.p->stream); });
 }
 
-// the five passes: S <- transform(f or residual); z solve; p <- (or +=) inverse
-int solve_passes(SolveCtx &c, int prec, const double *f, double *p, void *S, bool residual,
-                 bool accumulate, bool want_partials)
+// transform of the right-hand side (or residual), z solve, inverse transform
+int solve_passes(LSet &L, bool accumulate_into_p, bool want_partials)
 {
     int rc;
-    if ((rc = pass_x_fwd(c, prec, f, p, S, residual, want_partials))) return rc;
-    if ((rc = pass_y(c, prec, S, false))) return rc;
-    if ((rc = pass_z(c, prec, S))) return rc;
-    if ((rc = pass_y(c, prec, S, true))) return rc;
-    if ((rc = pass_x_inv(c, prec, S, p, accumulate))) return rc;
-    return POISSON_OK;
+    if ((rc = pass_x_fwd(L, false, want_partials))) return rc;
+    if ((rc = pass_y(L, false))) return rc;
+    if ((rc = pass_z(L))) return rc;
+    if ((rc = pass_y(L, true))) return rc;
+    return pass_x_inv(L, accumulate_into_p);
 }
 
-int read_scalars(poisson_plan p, const double *dev, int n, double *host)
+int correction_passes(LSet &L)
 {
-    hipError_t e = hipMemcpyAsync(host, dev, n * sizeof(double), hipMemcpyDeviceToHost,
-                                  p->stream);
+    int rc;
+    if ((rc = pass_y(L, false))) return rc;
+    if ((rc = pass_z(L))) return rc;
+    if ((rc = pass_y(L, true))) return rc;
+    return pass_x_inv(L, true);
+}
+
+int read_scalars(poisson_plan p, int count)
+{
+    hipError_t e = hipMemcpyAsync(p->host_scalars->p, p->scalars->p, 4 * sizeof(double) * count,
+                                  hipMemcpyDeviceToHost, p->stream);
     if (e != hipSuccess) return hip_fail("scalar read-back", (int)e);
     e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return hip_fail("stream synchronize", (int)e);
     return POISSON_OK;
-}
-
-int solve_one(poisson_plan p, int idx, const double *rhs, double *sol, poisson_stats_t *st)
-{
-    Sub &s = p->subs[idx];
-    double *scal = (double *)p->scalars->p + 4 * idx;
-    double *hs = p->host_scalars + 4 * idx;
-    SolveCtx c{p, &s, scal};
-    poisson_stats_t out{0, -1.0, 0.0, POISSON_OK};
-    int rc = POISSON_OK;
-    const int prec = p->precision;
-    if (prec == POISSON_FP64) {
-        // the spectrum lives in the solution array (same byte size)
-        rc = solve_passes(c, P_F64, rhs, sol, sol, false, false, false);
-        if (!rc && st) {
-            rc = read_scalars(p, scal, 1, hs);
-            out.rhs_mean = hs[0];
-        }
-    } else if (prec == POISSON_FP32) {
-        rc = solve_passes(c, P_F32, rhs, sol, s.S32->p, false, false, true);
-        if (!rc && st) {
-            rc = read_scalars(p, scal, 2, hs);
-            out.rhs_mean = hs[1] / (double)s.N;
-        }
-    } else {
-        // FP32 solve, then r = (f - mean f) - L p in FP64 and p += FP32 solve(r)
-        rc = solve_passes(c, P_F32, rhs, sol, s.S32->p, false, false, true);
-        double rho_prev = -1.0;
-        int corrections = 0;
-        for (int it = 0; !rc; ++it) {
-            if ((rc = pass_x_fwd(c, P_F32, rhs, sol, s.S32->p, true, true))) break;
-            if ((rc = read_scalars(p, scal, 4, hs))) break;
-            const double rho = hs[3] > 0 ? std::sqrt(hs[2] / hs[3]) : std::sqrt(hs[2]);
-            out.rel_residual = rho;
-            out.rhs_mean = hs[1] / (double)s.N;
-            if (!std::isfinite(rho)) { rc = POISSON_ERR_NONFINITE; break; }
-            if (rho <= p->rtol) break;
-            if (corrections >= p->max_refine || (rho_prev >= 0 && rho > 0.5 * rho_prev)) {
-                rc = POISSON_ERR_NOT_CONVERGED;
-                break;
-            }
-            rho_prev = rho;
-            if ((rc = pass_y(c, P_F32, s.S32->p, false))) break;
-            if ((rc = pass_z(c, P_F32, s.S32->p))) break;
-            if ((rc = pass_y(c, P_F32, s.S32->p, true))) break;
-            if ((rc = pass_x_inv(c, P_F32, s.S32->p, sol, true))) break;
-            ++corrections;
-        }
-        out.iterations = corrections;
-    }
-    out.status = rc;
-    if (st) *st = out;
-    return rc;
 }
 
 bool overlaps(const double *a, const double *b, long long n)
@@ -502,7 +493,143 @@ bool overlaps(const double *a, const double *b, long long n)
     return x < y + len && y < x + len;
 }
 
-int create_plan(const poisson_desc_t *descs, int count, void *stream, poisson_plan *out)
+// pointers of problem i (member slot `slot` of group g)
+ProbPtrs problem_ptrs(poisson_plan p, const Group &g, int slot, const double *rhs, double *sol)
+{
+    const int i = g.members[slot];
+    ProbPtrs q;
+    q.f = rhs;
+    q.p = sol;
+    q.S = p->precision == POISSON_FP64
+              ? (void *)sol
+              : (void *)((char *)g.S32->p + (size_t)g.N * 4 * slot);
+    q.partials = (double *)g.partials->p + (size_t)g.npart * 2 * slot;
+    q.scal = (double *)p->scalars->p + 4 * i;
+    return q;
+}
+
+enum { RUNNING = 1, DONE = 0 };
+
+// Solve every problem of the plan.  Single-problem plans launch with direct
+// pointers; batched plans upload one ProbPtrs array per group and launch
+// each pass once per group.  FP32 + refinement synchronises once per
+// iteration for the whole plan.
+int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, poisson_stats_t *st)
+{
+    const int prec = internal_prec(p->precision);
+    const int count = p->count;
+    std::vector<LSet> sets(p->groups.size());
+    std::vector<std::vector<int>> active(p->groups.size());
+    ProbPtrs *staging = p->batched ? (ProbPtrs *)p->host_ptrs->p : nullptr;
+
+    // (re)write the device pointer arrays for the listed member slots
+    auto stage = [&](int gi) -> int {
+        Group &g = p->groups[gi];
+        LSet &L = sets[gi];
+        L.n = (int)active[gi].size();
+        if (!p->batched) {
+            L.dev = nullptr;
+            L.one = problem_ptrs(p, g, 0, rhs[0], sol[0]);
+            return POISSON_OK;
+        }
+        ProbPtrs *h = staging + g.host_off;
+        for (int k = 0; k < L.n; ++k) {
+            const int slot = active[gi][k];
+            const int i = g.members[slot];
+            h[k] = problem_ptrs(p, g, slot, rhs[i], sol[i]);
+        }
+        L.dev = (const ProbPtrs *)g.ptrs->p;
+        L.one = ProbPtrs{nullptr, nullptr, nullptr, nullptr, nullptr};
+        if (L.n == 0) return POISSON_OK;
+        hipError_t e = hipMemcpyAsync(g.ptrs->p, h, sizeof(ProbPtrs) * L.n,
+                                      hipMemcpyHostToDevice, p->stream);
+        return e == hipSuccess ? POISSON_OK : hip_fail("pointer upload", (int)e);
+    };
+
+    if (p->batched && p->ptrs_done) {
+        // the staging area may still feed the previous call's copies
+        if (hipEventSynchronize(p->ptrs_done) != hipSuccess) return POISSON_ERR_HIP;
+    }
+    int rc = POISSON_OK;
+    for (size_t gi = 0; gi < p->groups.size() && !rc; ++gi) {
+        sets[gi] = LSet{p, &p->groups[gi], prec, nullptr, 0, {}};
+        active[gi].resize(p->groups[gi].members.size());
+        for (size_t k = 0; k < active[gi].size(); ++k) active[gi][k] = (int)k;
+        rc = stage((int)gi);
+    }
+
+    std::vector<poisson_stats_t> out(count, poisson_stats_t{0, -1.0, 0.0, POISSON_OK});
+    const bool refine = p->precision == POISSON_FP32_REFINE;
+    const bool want_partials = prec == P_F32;  // FP64 mean comes from the z pass
+    for (size_t gi = 0; gi < p->groups.size() && !rc; ++gi)
+        rc = solve_passes(sets[gi], false, want_partials);
+
+    if (!rc && refine) {
+        std::vector<double> rho_prev(count, -1.0);
+        std::vector<int> corrections(count, 0), state(count, RUNNING);
+        double *hs = (double *)p->host_scalars->p;
+        for (int it = 0; !rc; ++it) {
+            // residual + its transform for every running problem
+            for (size_t gi = 0; gi < p->groups.size() && !rc; ++gi)
+                if (sets[gi].n) rc = pass_x_fwd(sets[gi], true, true);
+            if (rc || (rc = read_scalars(p, count))) break;
+            bool any = false;
+            for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+                std::vector<int> next;
+                for (int slot : active[gi]) {
+                    const int i = p->groups[gi].members[slot];
+                    const double *s = hs + 4 * i;
+                    const double rho = s[3] > 0 ? std::sqrt(s[2] / s[3]) : std::sqrt(s[2]);
+                    out[i].rel_residual = rho;
+                    out[i].rhs_mean = s[1] / (double)p->groups[gi].N;
+                    out[i].iterations = corrections[i];
+                    int status = -1;
+                    if (!std::isfinite(rho))
+                        status = POISSON_ERR_NONFINITE;
+                    else if (rho <= p->rtol)
+                        status = POISSON_OK;
+                    else if (corrections[i] >= p->max_refine ||
+                             (rho_prev[i] >= 0 && rho > 0.5 * rho_prev[i]))
+                        status = POISSON_ERR_NOT_CONVERGED;
+                    if (status != -1) {
+                        out[i].status = status;
+                        state[i] = DONE;
+                    } else {
+                        rho_prev[i] = rho;
+                        corrections[i] += 1;
+                        next.push_back(slot);
+                    }
+                }
+                if (next.size() != active[gi].size()) {
+                    active[gi] = next;
+                    if ((rc = stage((int)gi))) break;
+                }
+                any = any || !next.empty();
+            }
+            if (rc || !any) break;
+            for (size_t gi = 0; gi < p->groups.size() && !rc; ++gi)
+                if (sets[gi].n) rc = correction_passes(sets[gi]);
+        }
+    } else if (!rc && st) {
+        rc = read_scalars(p, count);
+        const double *hs = (const double *)p->host_scalars->p;
+        for (auto &g : p->groups)
+            for (int i : g.members)
+                out[i].rhs_mean = prec == P_F64 ? hs[4 * i] : hs[4 * i + 1] / (double)g.N;
+    }
+    if (p->batched && p->ptrs_done) (void)hipEventRecord(p->ptrs_done, p->stream);
+
+    int first = rc;
+    for (int i = 0; i < count; ++i) {
+        if (rc) out[i].status = rc;
+        if (!first && out[i].status) first = out[i].status;
+        if (st) st[i] = out[i];
+    }
+    return first;
+}
+
+int create_plan(const poisson_desc_t *descs, int count, void *stream, bool batched,
+                poisson_plan *out)
 {
     if (!descs || !out || count < 1) return POISSON_ERR_INVALID_ARG;
     for (int i = 0; i < count; ++i) {
@@ -514,28 +641,62 @@ int create_plan(const poisson_desc_t *descs, int count, void *stream, poisson_pl
     p->precision = descs[0].precision;
     p->rtol = descs[0].rtol;
     p->max_refine = descs[0].max_refine;
+    p->batched = batched;
+    p->count = count;
     if (hipGetDevice(&p->device) != hipSuccess) return POISSON_ERR_HIP;
-    std::map<std::string, Tables> cache;
-    p->subs.resize(count);
+    p->where.resize(count);
     for (int i = 0; i < count; ++i) {
         poisson_desc_t d = descs[i];
         d.precision = p->precision;
         d.rtol = p->rtol;
         d.max_refine = p->max_refine;
-        int rc = build_sub(p->subs[i], d, cache);
+        int gi = -1;
+        for (size_t k = 0; k < p->groups.size(); ++k)
+            if (same_problem(p->groups[k].d, d)) gi = (int)k;
+        if (gi < 0) {
+            p->groups.emplace_back();
+            p->groups.back().d = d;
+            gi = (int)p->groups.size() - 1;
+        }
+        p->where[i] = {gi, (int)p->groups[gi].members.size()};
+        p->groups[gi].members.push_back(i);
+    }
+    int off = 0;
+    for (auto &g : p->groups) {
+        int rc = build_group(g);
         if (rc) return rc;
+        g.host_off = off;
+        off += (int)g.members.size();
     }
     int rc = dev_alloc(p->scalars, 4 * sizeof(double) * count);
     if (rc) return rc;
     if (hipMemset(p->scalars->p, 0, 4 * sizeof(double) * count) != hipSuccess)
         return POISSON_ERR_HIP;
-    if (hipHostMalloc((void **)&p->host_scalars, 4 * sizeof(double) * count, 0) != hipSuccess) {
-        p->host_scalars = nullptr;
-        return POISSON_ERR_OUT_OF_MEMORY;
+    if ((rc = pinned_alloc(p->host_scalars, 4 * sizeof(double) * count))) return rc;
+    if (batched) {
+        if ((rc = pinned_alloc(p->host_ptrs, sizeof(ProbPtrs) * count))) return rc;
+        if (hipEventCreateWithFlags(&p->ptrs_done, hipEventDisableTiming) != hipSuccess)
+            return POISSON_ERR_HIP;
     }
     *out = p.release();
     return POISSON_OK;
 }
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+            (void)hipSetDevice(dev);
+        } else {
+            prev = -1;
+        }
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
 
 }  // namespace
 
@@ -563,43 +724,38 @@ size_t poisson_workspace_bytes(const poisson_desc_t *d)
 
 int poisson_plan_create(const poisson_desc_t *d, void *stream, poisson_plan *out)
 {
-    return create_plan(d, 1, stream, out);
+    return create_plan(d, 1, stream, false, out);
 }
 
 int poisson_batch_plan_create(const poisson_desc_t *descs, int count, void *stream,
                               poisson_plan *out)
 {
-    return create_plan(descs, count, stream, out);
+    return create_plan(descs, count, stream, true, out);
 }
 
 int poisson_solve(poisson_plan plan, const double *rhs, double *sol, poisson_stats_t *stats)
 {
-    if (!plan || !rhs || !sol) return POISSON_ERR_INVALID_ARG;
-    if (plan->subs.size() != 1) return POISSON_ERR_INVALID_ARG;
-    if (overlaps(rhs, sol, plan->subs[0].N)) return POISSON_ERR_INVALID_ARG;
-    int cur = -1;
-    if (hipGetDevice(&cur) == hipSuccess && cur != plan->device) (void)hipSetDevice(plan->device);
-    int rc = solve_one(plan, 0, rhs, sol, stats);
-    if (cur >= 0 && cur != plan->device) (void)hipSetDevice(cur);
-    return rc;
+    if (!plan || !rhs || !sol || plan->batched) return POISSON_ERR_INVALID_ARG;
+    if (overlaps(rhs, sol, plan->groups[0].N)) return POISSON_ERR_INVALID_ARG;
+    DeviceGuard guard(plan->device);
+    return solve_all(plan, &rhs, &sol, stats);
 }
 
 int poisson_batch_solve(poisson_plan plan, const double *const *rhs, double *const *sol,
                         poisson_stats_t *stats)
 {
-    if (!plan || !rhs || !sol) return POISSON_ERR_INVALID_ARG;
-    const int n = (int)plan->subs.size();
-    for (int i = 0; i < n; ++i) {
+    if (!plan || !rhs || !sol || !plan->batched) return POISSON_ERR_INVALID_ARG;
+    for (int i = 0; i < plan->count; ++i) {
+        const long long n = plan->groups[plan->where[i].first].N;
         if (!rhs[i] || !sol[i]) return POISSON_ERR_INVALID_ARG;
-        if (overlaps(rhs[i], sol[i], plan->subs[i].N)) return POISSON_ERR_INVALID_ARG;
+        if (overlaps(rhs[i], sol[i], n)) return POISSON_ERR_INVALID_ARG;
+        for (int j = 0; j < i; ++j) {  // solutions must not overlap each other
+            const long long nj = plan->groups[plan->where[j].first].N;
+            if (overlaps(sol[i], sol[j], n < nj ? n : nj)) return POISSON_ERR_INVALID_ARG;
+        }
     }
-    int first = POISSON_OK;
-    for (int i = 0; i < n; ++i) {
-        int rc = solve_one(plan, i, rhs[i], sol[i], stats ? &stats[i] : nullptr);
-        if (rc && !first) first = rc;
-        if (rc == POISSON_ERR_HIP) break;
-    }
-    return first;
+    DeviceGuard guard(plan->device);
+    return solve_all(plan, rhs, sol, stats);
 }
 
 int poisson_destroy(poisson_plan plan)

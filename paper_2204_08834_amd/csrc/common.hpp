@@ -22,9 +22,23 @@ struct Cx {
 
 enum Prec { P_F64 = 0, P_F32 = 1 };
 
+// Per-problem pointers of a batched launch: problems of one shape share a
+// launch and blockIdx.y selects the entry.  A null `batch` pointer in the
+// argument structs below means a single-problem launch using their own
+// pointers.
+struct ProbPtrs {
+    const double *f;   // right-hand side
+    double *p;         // solution
+    void *S;           // spectrum
+    double *partials;  // per-workgroup partial sums of the x pass
+    double *scal;      // 4 FP64 scalars: mean (z pass), sum f, sum r^2, sum (f - mean)^2
+};
+
 // Arguments of the forward real-to-complex pass along x (optionally with the
 // FP64 residual r = (f - mu) - L p evaluated on the fly as its input).
 struct XFwdArgs {
+    const ProbPtrs *batch;  // batched launch (or null)
+    int nbatch;             // gridDim.y
     const double *f;        // (nz, ny, nx)
     const double *p;        // residual mode only: current solution
     void *S;                // complex<R> spectrum, row pitch M
@@ -40,6 +54,8 @@ struct XFwdArgs {
 
 // Inverse complex-to-real pass along x: p = result (store) or p += result.
 struct XInvArgs {
+    const ProbPtrs *batch;
+    int nbatch;
     const void *S;
     double *p;
     const void *tw;
@@ -49,6 +65,8 @@ struct XInvArgs {
 
 // Strided complex pass along y, in place on S.
 struct YArgs {
+    const ProbPtrs *batch;
+    int nbatch;
     void *S;
     const void *tw;         // exp(-2 pi i t/ny), t in [0, ny)
     int M, ny, nz;
@@ -57,6 +75,8 @@ struct YArgs {
 
 // z solve, walls (tridiagonal per (m, ky)) or periodic (transform along z).
 struct ZArgs {
+    const ProbPtrs *batch;
+    int nbatch;
     void *S;
     const void *tw;         // periodic: exp(-2 pi i t/nz)
     const double *lamx;     // lambda_x(m), m in [0, M]
@@ -78,9 +98,11 @@ int launch_z_walls(int prec, const ZArgs &a, hipStream_t s);
 int launch_z_periodic(int prec, const ZArgs &a, hipStream_t s);
 // number of workgroups the forward x pass uses (size of its partials array)
 int x_fwd_blocks(int prec, int nx, int ny, int nz);
-// Deterministic FP64 sum of `n` entries of `in` with stride `stride`
-// (nsums interleaved sums), result written to out[0..nsums).
-int launch_sum_partials(const double *in, int n, int nsums, double *out, hipStream_t s);
+// Deterministic FP64 sums of the x pass's partials: `n` workgroups with two
+// interleaved sums each, written to out[0..2).  Batched: one workgroup per
+// problem, partials and scal taken from batch[i], written to scal + out_off.
+int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *batch,
+                        int nbatch, int out_off, hipStream_t s);
 
 // lengths supported by the transform kernels
 bool fft_length_supported(int n);

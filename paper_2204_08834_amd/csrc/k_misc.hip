@@ -51,13 +51,18 @@ bool fft_length_supported(int n)
     switch (n) { PK_LENGTHS(PK_IS) default: return false; }
 }
 
-// One workgroup; thread t sums entries t, t+256, ... of each interleaved
-// stream in a fixed order, then a fixed-shape tree finishes: bitwise
-// reproducible for a given n.
-__global__ __launch_bounds__(256) void k_sum_partials(const double *in, int n, int nsums,
-                                                      double *out)
+// One workgroup per problem; thread t sums entries t, t+256, ... of each of
+// the two interleaved streams in a fixed order, then a fixed-shape tree
+// finishes: bitwise reproducible for a given n.
+__global__ __launch_bounds__(256) void k_sum_partials(const double *in, int n, double *out,
+                                                      const ProbPtrs *batch, int out_off)
 {
     __shared__ double sh[256];
+    if (batch) {
+        in = batch[blockIdx.x].partials;
+        out = batch[blockIdx.x].scal + out_off;
+    }
+    constexpr int nsums = 2;
     for (int s = 0; s < nsums; ++s) {
         double acc = 0.0;
         for (int i = threadIdx.x; i < n; i += 256) acc += in[(size_t)i * nsums + s];
@@ -72,9 +77,11 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *in, int n, i
     }
 }
 
-int launch_sum_partials(const double *in, int n, int nsums, double *out, hipStream_t s)
+int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *batch,
+                        int nbatch, int out_off, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, in, n, nsums, out);
+    hipLaunchKernelGGL(k_sum_partials, dim3(batch ? nbatch : 1), dim3(256), 0, s, in, n, out,
+                       batch, out_off);
     return (int)hipGetLastError();
 }
 

@@ -59,8 +59,17 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *sh)
 }
 
 template <int M, bool RES>
-__global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a)
+__global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
 {
+    XFwdArgs a = a0;
+    if (a.batch) {
+        const ProbPtrs &q = a.batch[blockIdx.y];
+        a.f = q.f;
+        a.p = q.p;
+        a.S = q.S;
+        if (a.partials) a.partials = q.partials;
+        a.sum_f = q.scal + 1;
+    }
     using C = XCfg<M>;
     constexpr int NB = C::NB, NT = C::NT, NX = 2 * M;
     using Tile = LdsTile<R, M, NB, false, C::PAD>;
@@ -148,8 +157,14 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a)
 }
 
 template <int M>
-__global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a)
+__global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
 {
+    XInvArgs a = a0;
+    if (a.batch) {
+        const ProbPtrs &q = a.batch[blockIdx.y];
+        a.S = q.S;
+        a.p = q.p;
+    }
     using C = XCfg<M>;
     constexpr int NB = C::NB, NT = C::NT, NX = 2 * M;
     using Tile = LdsTile<R, M, NB, false, C::PAD>;
@@ -198,10 +213,11 @@ template <int M> static int run_x_fwd(const XFwdArgs &a, hipStream_t s)
 {
     const int nrows = a.ny * a.nz;
     const int nb = (nrows + XCfg<M>::NB - 1) / XCfg<M>::NB;
+    const dim3 grid(nb, a.batch ? a.nbatch : 1);
     if (a.residual)
-        hipLaunchKernelGGL((k_x_fwd<M, true>), dim3(nb), dim3(XCfg<M>::NT), 0, s, a);
+        hipLaunchKernelGGL((k_x_fwd<M, true>), grid, dim3(XCfg<M>::NT), 0, s, a);
     else
-        hipLaunchKernelGGL((k_x_fwd<M, false>), dim3(nb), dim3(XCfg<M>::NT), 0, s, a);
+        hipLaunchKernelGGL((k_x_fwd<M, false>), grid, dim3(XCfg<M>::NT), 0, s, a);
     return (int)hipGetLastError();
 }
 
@@ -209,7 +225,7 @@ template <int M> static int run_x_inv(const XInvArgs &a, hipStream_t s)
 {
     const int nrows = a.ny * a.nz;
     const int nb = (nrows + XCfg<M>::NB - 1) / XCfg<M>::NB;
-    hipLaunchKernelGGL(k_x_inv<M>, dim3(nb), dim3(XCfg<M>::NT), 0, s, a);
+    hipLaunchKernelGGL(k_x_inv<M>, dim3(nb, a.batch ? a.nbatch : 1), dim3(XCfg<M>::NT), 0, s, a);
     return (int)hipGetLastError();
 }
 

@@ -31,8 +31,10 @@ template <int N> struct YCfg {
 };
 
 template <int N>
-__global__ __launch_bounds__(YCfg<N>::NT) void k_y(YArgs a)
+__global__ __launch_bounds__(YCfg<N>::NT) void k_y(YArgs a0)
 {
+    YArgs a = a0;
+    if (a.batch) a.S = a.batch[blockIdx.y].S;
     using C = YCfg<N>;
     constexpr int NB = C::NB, NT = C::NT;
     using Tile = LdsTile<R, N, NB, true, C::PAD>;
@@ -65,7 +67,8 @@ __global__ __launch_bounds__(YCfg<N>::NT) void k_y(YArgs a)
 template <int N> static int run_y(const YArgs &a, hipStream_t s)
 {
     const int ntile = (a.M + YCfg<N>::NB - 1) / YCfg<N>::NB;
-    hipLaunchKernelGGL(k_y<N>, dim3(ntile * a.nz), dim3(YCfg<N>::NT), 0, s, a);
+    hipLaunchKernelGGL(k_y<N>, dim3(ntile * a.nz, a.batch ? a.nbatch : 1), dim3(YCfg<N>::NT), 0,
+                       s, a);
     return (int)hipGetLastError();
 }
 

@@ -34,8 +34,14 @@ template <int N> struct ZPCfg {
 };
 
 template <int N>
-__global__ __launch_bounds__(ZPCfg<N>::NT) void k_z_per(ZArgs a, int nspecial)
+__global__ __launch_bounds__(ZPCfg<N>::NT) void k_z_per(ZArgs a0, int nspecial)
 {
+    ZArgs a = a0;
+    if (a.batch) {
+        const ProbPtrs &pq = a.batch[blockIdx.y];
+        a.S = pq.S;
+        if (a.zero_mean_out) a.zero_mean_out = pq.scal;
+    }
     using Cf = ZPCfg<N>;
     constexpr int NB = Cf::NB, NT = Cf::NT;
     using Tile = LdsTile<R, N, NB, true, Cf::PAD>;
@@ -154,7 +160,8 @@ template <int N> static int run_zp(const ZArgs &a, hipStream_t s)
     const int npairs = a.ny / 2 + 1;
     const int nspecial = (npairs + Cf::NB / 2 - 1) / (Cf::NB / 2);
     const int nmain = (a.ny * a.M + Cf::NB - 1) / Cf::NB;
-    hipLaunchKernelGGL(k_z_per<N>, dim3(nspecial + nmain), dim3(Cf::NT), 0, s, a, nspecial);
+    hipLaunchKernelGGL(k_z_per<N>, dim3(nspecial + nmain, a.batch ? a.nbatch : 1), dim3(Cf::NT),
+                       0, s, a, nspecial);
     return (int)hipGetLastError();
 }
 

@@ -57,8 +57,14 @@ namespace PK_NS {
 using R = PK_REAL;
 
 template <int L, int W, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a, int C, int nspecial)
+__global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
 {
+    ZArgs a = a0;
+    if (a.batch) {
+        const ProbPtrs &pq = a.batch[blockIdx.y];
+        a.S = pq.S;
+        if (a.zero_mean_out) a.zero_mean_out = pq.scal;
+    }
     extern __shared__ double smem_d[];
     R *buf = (R *)smem_d;                                       // C*W slots of 4 reals
     double *zbuf = smem_d + ((C * W * 4 * sizeof(R) + 7) / 8);  // 3*C doubles
@@ -304,8 +310,8 @@ static int run_zw(const ZArgs &a, hipStream_t s)
     const int nspecial = (2 * npairs + W - 1) / W;
     const int nmain = (a.ny * a.M + W - 1) / W;
     const size_t shm = ((C * W * 4 * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double);
-    hipLaunchKernelGGL((k_z_walls<L, W, MAXT>), dim3(nspecial + nmain), dim3(W * C), shm, s, a,
-                       C, nspecial);
+    hipLaunchKernelGGL((k_z_walls<L, W, MAXT>), dim3(nspecial + nmain, a.batch ? a.nbatch : 1),
+                       dim3(W * C), shm, s, a, C, nspecial);
     return (int)hipGetLastError();
 }
 

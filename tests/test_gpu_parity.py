@@ -276,3 +276,73 @@ def test_timing_reports_passes():
         t = plan.timing()
     assert {"x_r2c_f64", "y_fwd_f64", "z_walls_f64", "y_inv_f64", "x_c2r_f64"} <= set(t)
     assert all(v["launches"] == 1 and v["total_ms"] > 0 for v in t.values())
+
+
+# ---------------------------------------------------------------------------
+# batched solves
+# ---------------------------------------------------------------------------
+def _batch_problems(probs, precision, rtol=1e-10):
+    P = _gpu()
+    specs = [dict(nx=p.nx, ny=p.ny, nz=p.nz, dx=p.dx, dy=p.dy, dz=p.dz, bc_z=p.bc_z)
+             for p in probs]
+    rhs = [torch.from_numpy(p.f).cuda() for p in probs]
+    outs = [torch.empty_like(r) for r in rhs]
+    bp = P.BatchPlan(specs, precision, rtol=rtol)
+    rc, stats = bp.solve(rhs, outs)
+    torch.cuda.synchronize()
+    bp.close()
+    return rc, stats, [o.cpu().numpy() for o in outs]
+
+
+def _mixed_small():
+    probs = [inputs.scaled("hit256", 32, 32, 32, seed=11), inputs.scaled("rb512", 48, 48, 24, seed=12),
+             inputs.scaled("hit256", 32, 32, 32, seed=13), inputs.scaled("rb512", 64, 32, 20, seed=14),
+             inputs.scaled("rb512", 48, 48, 24, seed=15)]
+    return probs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine", "fp32"])
+def test_batch_equals_single_solves(precision):
+    """A mixed-shape batch gives bitwise the same fields as one plan per problem."""
+    probs = _mixed_small()
+    rc, stats, outs = _batch_problems(probs, precision)
+    assert rc == 0, stats
+    for prob, st, p in zip(probs, stats, outs):
+        q, st1 = gpu_solve(prob.f, *prob.spacings(), prob.bc_z, precision)
+        assert np.array_equal(p, q), (prob.name, rel(p, q))
+        assert st["iterations"] == st1["iterations"]
+        assert abs(st["rhs_mean"] - st1["rhs_mean"]) <= 1e-15
+
+
+def test_batch_mixed64_workload(orc):
+    """The 64-problem mixed batch (24 x 64^3 periodic, 24 x 96x96x48 walls,
+    16 x 128x128x64 walls), FP32 + refinement to 1e-10: every problem converges;
+    one problem of each shape is compared with the oracle."""
+    probs = inputs.batch_mixed64()
+    for p in probs:
+        inputs.make_rhs(p)
+    rc, stats, outs = _batch_problems(probs, "fp32_refine")
+    assert rc == 0
+    assert all(s["status"] == 0 and 0 <= s["rel_residual"] <= 1e-10 for s in stats)
+    for idx in (0, 24, 48):
+        prob = probs[idx]
+        sp = prob.spacings()
+        p_ref = orc.solve(prob.f, *sp, prob.bc_z)
+        res, _ = orc.residual(prob.f, outs[idx], *sp, prob.bc_z)
+        err = rel(outs[idx], p_ref)
+        k = kappa(prob.nx, prob.ny, prob.nz, *sp, prob.bc_z)
+        print(f"batch problem {idx} ({prob.name}): residual {res:.2e} error {err:.2e}", flush=True)
+        assert res <= 1e-10 and err <= k * res * 1.01 + 1e-15
+
+
+def test_batch_partial_convergence_and_errors():
+    """Problems that stop early (converged or failing) leave the others running."""
+    P = _gpu()
+    probs = _mixed_small()
+    probs[1].f = probs[1].f.copy()
+    probs[1].f[0, 0, 0] = np.nan
+    rc, stats, outs = _batch_problems(probs, "fp32_refine")
+    assert rc == P.ERR_NONFINITE
+    assert stats[1]["status"] == P.ERR_NONFINITE
+    for i in (0, 2, 3, 4):
+        assert stats[i]["status"] == 0 and stats[i]["rel_residual"] <= 1e-10
