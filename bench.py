@@ -113,6 +113,10 @@ def main():
     ap.add_argument("--cpu-planes", type=int, default=16)
     ap.add_argument("--only", choices=["fp32_refine", "fp64"], default=None,
                     help="time one precision only (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="time a plain device-to-device copy of 1 GiB instead (the HBM "
+                         "bandwidth a streaming kernel attains, and the reference for "
+                         "scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -128,6 +132,25 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     poisson.lib()  # fail loudly if the HIP library is missing
+
+    if args.copy_calibration:
+        n = (1 << 30) // 8
+        src = torch.empty(n, dtype=torch.float64, device="cuda").uniform_()
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
+                          "ms_per_copy": ms, "gbs": 2 * n * 8 / (ms * 1e-3) / 1e9,
+                          "frac_of_peak": 2 * n * 8 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}))
+        return
 
     prob = inputs.workload(args.workload)
     npts = prob.npoints

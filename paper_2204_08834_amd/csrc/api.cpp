@@ -24,6 +24,10 @@ using namespace pk;
 
 namespace {
 
+// device scalars per problem: [0] mean of f from the zero-wavenumber column,
+// [1] sum f, [2] sum r^2, [3] sum (f - mean f)^2, [4] sum p
+constexpr int NSCAL = 8;
+
 // ---------------------------------------------------------------------------
 // host tables
 // ---------------------------------------------------------------------------
@@ -170,7 +174,7 @@ struct Group {
     Tables tab;
     std::vector<int> members;          // problem indices in the plan
     std::shared_ptr<DevBuf> S32;       // FP32 spectra, one per member
-    std::shared_ptr<DevBuf> partials;  // x-pass partial sums, npart*2 per member
+    std::shared_ptr<DevBuf> partials;  // x-pass partial sums, npart*4 per member
     int npart = 0;
     std::shared_ptr<DevBuf> ptrs;      // device ProbPtrs[members]
     int host_off = 0;                  // offset of this group's staging entries
@@ -200,7 +204,7 @@ struct poisson_plan_s {
     int count = 0;
     std::vector<Group> groups;
     std::vector<std::pair<int, int>> where;  // problem -> (group, member slot)
-    std::shared_ptr<DevBuf> scalars;         // 4 FP64 scalars per problem
+    std::shared_ptr<DevBuf> scalars;         // NSCAL FP64 scalars per problem
     std::unique_ptr<PinnedBuf> host_scalars;
     std::unique_ptr<PinnedBuf> host_ptrs;    // ProbPtrs staging for batched launches
     hipEvent_t ptrs_done = nullptr;          // last staging upload has been consumed
@@ -263,7 +267,7 @@ size_t workspace_bytes(const poisson_desc_t *d)
     size_t b = 0;
     if (d->precision != POISSON_FP64) b += n * 4;  // FP32 half spectrum: N/2 complex floats
     const int nb = x_fwd_blocks(internal_prec(d->precision), d->nx, d->ny, d->nz);
-    b += (size_t)(nb > 0 ? nb : 1) * 2 * sizeof(double);
+    b += (size_t)(nb > 0 ? nb : 1) * 4 * sizeof(double);
     return b;
 }
 
@@ -294,7 +298,7 @@ int build_group(Group &g)
     const size_t n = g.members.size();
     if (f32 && (rc = dev_alloc(g.S32, (size_t)g.N * 4 * n))) return rc;
     g.npart = x_fwd_blocks(internal_prec(d.precision), d.nx, d.ny, d.nz);
-    if ((rc = dev_alloc(g.partials, (size_t)g.npart * 2 * sizeof(double) * n))) return rc;
+    if ((rc = dev_alloc(g.partials, (size_t)g.npart * 4 * sizeof(double) * n))) return rc;
     if ((rc = dev_alloc(g.ptrs, sizeof(ProbPtrs) * n))) return rc;
     return POISSON_OK;
 }
@@ -394,8 +398,8 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials)
     int rc = timed(L.p, name, bytes,
                    [&] { return launch_x_fwd(L.prec, a, nullptr, L.p->stream); });
     if (rc || !want_partials) return rc;
-    // two interleaved sums per workgroup: plain input -> (sum f, 0) into
-    // scal[1..2]; residual -> (sum r^2, sum fbar^2) into scal[2..3]
+    // three sums per workgroup: plain input -> (sum f, 0, 0) into scal[1..3];
+    // residual -> (sum r^2, sum fbar^2, sum p) into scal[2..4]
     const int off = residual ? 2 : 1;
     return timed(L.p, "sum_partials", (double)g.npart * 16.0 * L.n, [&] {
         return launch_sum_partials(L.one.partials, g.npart, L.one.scal ? L.one.scal + off : nullptr,
@@ -449,7 +453,9 @@ int pass_x_inv(LSet &L, bool accumulate)
 {
     Group &g = *L.g;
     XInvArgs a{L.dev, L.n, L.one.S, L.one.p, g.tab.twx[L.prec == P_F32 ? 1 : 0]->p, g.d.nx,
-               g.d.ny, g.d.nz, accumulate ? 1 : 0};
+               g.d.ny, g.d.nz, accumulate ? 1 : 0, nullptr, 1.0 / (double)g.N};
+    // the mean of p from the residual pass (batched launches redirect it)
+    if (accumulate) a.sum_p = L.dev ? (const double *)g.partials->p : L.one.scal + 4;
     char name[40];
     snprintf(name, sizeof name, accumulate ? "x_c2r_accumulate_%s" : "x_c2r_%s", tag(L.prec));
     const double sb = L.prec == P_F32 ? 4.0 : 8.0;
@@ -479,7 +485,7 @@ int correction_passes(LSet &L)
 
 int read_scalars(poisson_plan p, int count)
 {
-    hipError_t e = hipMemcpyAsync(p->host_scalars->p, p->scalars->p, 4 * sizeof(double) * count,
+    hipError_t e = hipMemcpyAsync(p->host_scalars->p, p->scalars->p, NSCAL * sizeof(double) * count,
                                   hipMemcpyDeviceToHost, p->stream);
     if (e != hipSuccess) return hip_fail("scalar read-back", (int)e);
     e = hipStreamSynchronize(p->stream);
@@ -503,8 +509,8 @@ ProbPtrs problem_ptrs(poisson_plan p, const Group &g, int slot, const double *rh
     q.S = p->precision == POISSON_FP64
               ? (void *)sol
               : (void *)((char *)g.S32->p + (size_t)g.N * 4 * slot);
-    q.partials = (double *)g.partials->p + (size_t)g.npart * 2 * slot;
-    q.scal = (double *)p->scalars->p + 4 * i;
+    q.partials = (double *)g.partials->p + (size_t)g.npart * 4 * slot;
+    q.scal = (double *)p->scalars->p + NSCAL * i;
     return q;
 }
 
@@ -578,7 +584,7 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
                 std::vector<int> next;
                 for (int slot : active[gi]) {
                     const int i = p->groups[gi].members[slot];
-                    const double *s = hs + 4 * i;
+                    const double *s = hs + NSCAL * i;
                     const double rho = s[3] > 0 ? std::sqrt(s[2] / s[3]) : std::sqrt(s[2]);
                     out[i].rel_residual = rho;
                     out[i].rhs_mean = s[1] / (double)p->groups[gi].N;
@@ -615,7 +621,8 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
         const double *hs = (const double *)p->host_scalars->p;
         for (auto &g : p->groups)
             for (int i : g.members)
-                out[i].rhs_mean = prec == P_F64 ? hs[4 * i] : hs[4 * i + 1] / (double)g.N;
+                out[i].rhs_mean =
+                    prec == P_F64 ? hs[NSCAL * i] : hs[NSCAL * i + 1] / (double)g.N;
     }
     if (p->batched && p->ptrs_done) (void)hipEventRecord(p->ptrs_done, p->stream);
 
@@ -668,11 +675,11 @@ int create_plan(const poisson_desc_t *descs, int count, void *stream, bool batch
         g.host_off = off;
         off += (int)g.members.size();
     }
-    int rc = dev_alloc(p->scalars, 4 * sizeof(double) * count);
+    int rc = dev_alloc(p->scalars, NSCAL * sizeof(double) * count);
     if (rc) return rc;
-    if (hipMemset(p->scalars->p, 0, 4 * sizeof(double) * count) != hipSuccess)
+    if (hipMemset(p->scalars->p, 0, NSCAL * sizeof(double) * count) != hipSuccess)
         return POISSON_ERR_HIP;
-    if ((rc = pinned_alloc(p->host_scalars, 4 * sizeof(double) * count))) return rc;
+    if ((rc = pinned_alloc(p->host_scalars, NSCAL * sizeof(double) * count))) return rc;
     if (batched) {
         if ((rc = pinned_alloc(p->host_ptrs, sizeof(ProbPtrs) * count))) return rc;
         if (hipEventCreateWithFlags(&p->ptrs_done, hipEventDisableTiming) != hipSuccess)

@@ -31,7 +31,8 @@ struct ProbPtrs {
     double *p;         // solution
     void *S;           // spectrum
     double *partials;  // per-workgroup partial sums of the x pass
-    double *scal;      // 4 FP64 scalars: mean (z pass), sum f, sum r^2, sum (f - mean)^2
+    double *scal;      // 8 FP64 scalars: [0] mean (z pass), [1] sum f, [2] sum r^2,
+                       // [3] sum (f - mean)^2, [4] sum p
 };
 
 // Arguments of the forward real-to-complex pass along x (optionally with the
@@ -61,6 +62,8 @@ struct XInvArgs {
     const void *tw;
     int nx, ny, nz;
     int accumulate;
+    const double *sum_p;    // accumulate mode: device sum of p (its mean is removed)
+    double inv_n;           // 1/(nx ny nz)
 };
 
 // Strided complex pass along y, in place on S.
@@ -98,8 +101,8 @@ int launch_z_walls(int prec, const ZArgs &a, hipStream_t s);
 int launch_z_periodic(int prec, const ZArgs &a, hipStream_t s);
 // number of workgroups the forward x pass uses (size of its partials array)
 int x_fwd_blocks(int prec, int nx, int ny, int nz);
-// Deterministic FP64 sums of the x pass's partials: `n` workgroups with two
-// interleaved sums each, written to out[0..2).  Batched: one workgroup per
+// Deterministic FP64 sums of the x pass's partials: `n` workgroups with three
+// sums each (stride 4), written to out[0..3).  Batched: one workgroup per
 // problem, partials and scal taken from batch[i], written to scal + out_off.
 int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *batch,
                         int nbatch, int out_off, hipStream_t s);

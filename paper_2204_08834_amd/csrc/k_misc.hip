@@ -52,8 +52,8 @@ bool fft_length_supported(int n)
 }
 
 // One workgroup per problem; thread t sums entries t, t+256, ... of each of
-// the two interleaved streams in a fixed order, then a fixed-shape tree
-// finishes: bitwise reproducible for a given n.
+// the three interleaved streams (stride 4) in a fixed order, then a
+// fixed-shape tree finishes: bitwise reproducible for a given n.
 __global__ __launch_bounds__(256) void k_sum_partials(const double *in, int n, double *out,
                                                       const ProbPtrs *batch, int out_off)
 {
@@ -62,10 +62,10 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *in, int n, d
         in = batch[blockIdx.x].partials;
         out = batch[blockIdx.x].scal + out_off;
     }
-    constexpr int nsums = 2;
+    constexpr int nsums = 3, stride = 4;
     for (int s = 0; s < nsums; ++s) {
         double acc = 0.0;
-        for (int i = threadIdx.x; i < n; i += 256) acc += in[(size_t)i * nsums + s];
+        for (int i = threadIdx.x; i < n; i += 256) acc += in[(size_t)i * stride + s];
         sh[threadIdx.x] = acc;
         __syncthreads();
         for (int h = 128; h > 0; h >>= 1) {

@@ -39,22 +39,24 @@ template <int M> struct XCfg {
     static constexpr int PAD = 0;
 };
 
-// sum two doubles over the workgroup; thread 0 gets the totals
-__device__ __forceinline__ void block_sum2(double &a, double &b, double *sh)
+// sum three doubles over the workgroup; thread 0 gets the totals
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *sh)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_down(a, off, 64);
         b += __shfl_down(b, off, 64);
+        c += __shfl_down(c, off, 64);
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) { sh[2 * wid] = a; sh[2 * wid + 1] = b; }
+    if (lane == 0) { sh[3 * wid] = a; sh[3 * wid + 1] = b; sh[3 * wid + 2] = c; }
     __syncthreads();
     if (threadIdx.x == 0) {
         const int nw = (blockDim.x + 63) >> 6;
         a = 0.0;
         b = 0.0;
-        for (int w = 0; w < nw; ++w) { a += sh[2 * w]; b += sh[2 * w + 1]; }
+        c = 0.0;
+        for (int w = 0; w < nw; ++w) { a += sh[3 * w]; b += sh[3 * w + 1]; c += sh[3 * w + 2]; }
     }
 }
 
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
     using Tile = LdsTile<R, M, NB, false, C::PAD>;
     __shared__ Cx<R> s_tile[Tile::elems];
     __shared__ Cx<R> s_tw[NX];
-    __shared__ double s_red[2 * (NT / 64)];
+    __shared__ double s_red[3 * (NT / 64)];
 
     const int nrows = a.ny * a.nz;
     const int row0 = blockIdx.x * NB;
@@ -83,7 +85,8 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
     __syncthreads();
 
     const double mu = (RES && a.sum_f) ? (*a.sum_f) * a.inv_n : 0.0;
-    double acc0 = 0.0, acc1 = 0.0;
+    // plain input: acc0 = sum f; residual: sum r^2, sum (f - mu)^2, sum p
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
     auto gload = [&](int b, int n) -> Cx<R> {
         const int row = row0 + b;
         if (row >= nrows) return {R(0), R(0)};
@@ -121,6 +124,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
         const double r0 = f0 - l0, r1 = f1 - l1;
         acc0 += r0 * r0 + r1 * r1;
         acc1 += f0 * f0 + f1 * f1;
+        acc2 += pc.x + pc.y;
         return {R(r0), R(r1)};
     };
     Tile tile{s_tile};
@@ -148,10 +152,11 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
     }
 
     if (a.partials) {
-        block_sum2(acc0, acc1, s_red);
+        block_sum3(acc0, acc1, acc2, s_red);
         if (threadIdx.x == 0) {
-            a.partials[2 * blockIdx.x] = acc0;
-            a.partials[2 * blockIdx.x + 1] = acc1;
+            a.partials[4 * blockIdx.x] = acc0;
+            a.partials[4 * blockIdx.x + 1] = acc1;
+            a.partials[4 * blockIdx.x + 2] = acc2;
         }
     }
 }
@@ -164,7 +169,11 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
         const ProbPtrs &q = a.batch[blockIdx.y];
         a.S = q.S;
         a.p = q.p;
+        if (a.sum_p) a.sum_p = q.scal + 4;
     }
+    // accumulate mode also removes the mean of the previous iterate (the
+    // residual cannot see the constant mode, so the gauge is kept here)
+    const double pmean = (a.accumulate && a.sum_p) ? (*a.sum_p) * a.inv_n : 0.0;
     using C = XCfg<M>;
     constexpr int NB = C::NB, NT = C::NT, NX = 2 * M;
     using Tile = LdsTile<R, M, NB, false, C::PAD>;
@@ -200,8 +209,8 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
         double2 o = {double(v.re), -double(v.im)};
         if (a.accumulate) {
             const double2 old = *dst;
-            o.x += old.x;
-            o.y += old.y;
+            o.x += old.x - pmean;
+            o.y += old.y - pmean;
         }
         *dst = o;
     };

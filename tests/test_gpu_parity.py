@@ -8,7 +8,8 @@ the zero-mean gauge, and exact discrete eigenmodes.
 
 Tolerances (relative L2 unless stated):
   FP64          error vs oracle <= 1e-12
-  FP32_REFINE   residual <= 1e-10 (the stopping rule); error vs oracle <= 1e-9
+  FP32_REFINE   residual <= 1e-10 (the stopping rule) and error <= kappa(L) *
+                residual; error <= 1e-10 when the residual is driven to 1e-12
   FP32          error vs oracle <= 2e-5 (single FP32 solve, no refinement)
 """
 import math
@@ -124,11 +125,11 @@ def test_fp32_refine_matches_oracle(orc, case):
 @pytest.mark.parametrize("case", SMALL, ids=[f"{c[0]}x{c[1]}x{c[2]}_{'w' if c[6] else 'p'}"
                                              for c in SMALL])
 def test_fp32_refine_error_1e10(orc, case):
-    """With the residual driven to 1e-13 the refined solution matches the
+    """With the residual driven to 1e-12 the refined solution matches the
     FP64 oracle to 1e-10 relative error."""
     f, sp, bc = _small_case(case, seed=8)
     p_ref = orc.solve(f, *sp, bc)
-    p, st = gpu_solve(f, *sp, bc, "fp32_refine", rtol=1e-13)
+    p, st = gpu_solve(f, *sp, bc, "fp32_refine", rtol=1e-12)
     err = rel(p, p_ref)
     assert st["status"] == 0, st
     assert err <= 1e-10, err
@@ -288,7 +289,7 @@ def _batch_problems(probs, precision, rtol=1e-10):
     rhs = [torch.from_numpy(p.f).cuda() for p in probs]
     outs = [torch.empty_like(r) for r in rhs]
     bp = P.BatchPlan(specs, precision, rtol=rtol)
-    rc, stats = bp.solve(rhs, outs)
+    rc, stats = bp.solve(rhs, outs, check=False)
     torch.cuda.synchronize()
     bp.close()
     return rc, stats, [o.cpu().numpy() for o in outs]
