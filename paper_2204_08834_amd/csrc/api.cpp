@@ -174,8 +174,11 @@ struct Group {
     Tables tab;
     std::vector<int> members;          // problem indices in the plan
     std::shared_ptr<DevBuf> S32;       // FP32 spectra, one per member
-    std::shared_ptr<DevBuf> partials;  // x-pass partial sums, npart*4 per member
-    int npart = 0;
+    std::shared_ptr<DevBuf> partials;  // per-workgroup partial sums, part_stride per member
+    int npart = 0;                     // workgroups of the forward x pass
+    int ncheck = 0;                    // workgroups of the residual-check pass
+    int part_stride = 0;               // doubles of partials per member
+    int zwalls_variant = 0;            // tile variant of the wall-bounded z solve
     std::shared_ptr<DevBuf> ptrs;      // device ProbPtrs[members]
     int host_off = 0;                  // offset of this group's staging entries
 };
@@ -267,7 +270,8 @@ size_t workspace_bytes(const poisson_desc_t *d)
     size_t b = 0;
     if (d->precision != POISSON_FP64) b += n * 4;  // FP32 half spectrum: N/2 complex floats
     const int nb = x_fwd_blocks(internal_prec(d->precision), d->nx, d->ny, d->nz);
-    b += (size_t)(nb > 0 ? nb : 1) * 4 * sizeof(double);
+    const int nc = d->precision == POISSON_FP32_REFINE ? residual_check_blocks(d->ny, d->nz) : 0;
+    b += (size_t)(nb > nc ? nb : nc) * 4 * sizeof(double);
     return b;
 }
 
@@ -298,8 +302,12 @@ int build_group(Group &g)
     const size_t n = g.members.size();
     if (f32 && (rc = dev_alloc(g.S32, (size_t)g.N * 4 * n))) return rc;
     g.npart = x_fwd_blocks(internal_prec(d.precision), d.nx, d.ny, d.nz);
-    if ((rc = dev_alloc(g.partials, (size_t)g.npart * 4 * sizeof(double) * n))) return rc;
+    g.ncheck = d.precision == POISSON_FP32_REFINE ? residual_check_blocks(d.ny, d.nz) : 0;
+    g.part_stride = (g.npart > g.ncheck ? g.npart : g.ncheck) * 4;
+    if ((rc = dev_alloc(g.partials, (size_t)g.part_stride * sizeof(double) * n))) return rc;
     if ((rc = dev_alloc(g.ptrs, sizeof(ProbPtrs) * n))) return rc;
+    if (const char *e = getenv("POISSON_ZWALLS_CHUNK"))  // 8 or 16 rows per chunk
+        g.zwalls_variant = atoi(e) == 8 ? 1 : (atoi(e) == 16 ? 2 : 0);
     return POISSON_OK;
 }
 
@@ -356,6 +364,18 @@ void collect_timing(poisson_plan p)
 
 const char *tag(int prec) { return prec == P_F32 ? "f32" : "f64"; }
 
+// Passes that consume what the previous pass just wrote walk their blocks in
+// reverse (see block_order in common.hpp).  POISSON_BLOCK_ORDER=forward turns
+// this off (for measurements).
+bool reversed_orders()
+{
+    static const bool on = [] {
+        const char *e = getenv("POISSON_BLOCK_ORDER");
+        return !(e && strcmp(e, "forward") == 0);
+    }();
+    return on;
+}
+
 // ---------------------------------------------------------------------------
 // one pass over a set of problems of one group
 // ---------------------------------------------------------------------------
@@ -401,9 +421,39 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials)
     // three sums per workgroup: plain input -> (sum f, 0, 0) into scal[1..3];
     // residual -> (sum r^2, sum fbar^2, sum p) into scal[2..4]
     const int off = residual ? 2 : 1;
-    return timed(L.p, "sum_partials", (double)g.npart * 16.0 * L.n, [&] {
+    return timed(L.p, "sum_partials", (double)g.npart * 32.0 * L.n, [&] {
         return launch_sum_partials(L.one.partials, g.npart, L.one.scal ? L.one.scal + off : nullptr,
                                    L.dev, L.n, off, L.p->stream);
+    });
+}
+
+// residual and its norms without the transform (a convergence check that
+// does not write the spectrum): sums into scal[2..4] like the residual x pass
+int pass_residual_check(LSet &L)
+{
+    Group &g = *L.g;
+    XFwdArgs a{};
+    a.batch = L.dev;
+    a.nbatch = L.n;
+    a.f = L.one.f;
+    a.p = L.one.p;
+    a.partials = L.one.partials;
+    a.nx = g.d.nx;
+    a.ny = g.d.ny;
+    a.nz = g.d.nz;
+    a.bc_z = g.d.bc_z;
+    a.ax = 1.0 / (g.d.dx * g.d.dx);
+    a.ay = 1.0 / (g.d.dy * g.d.dy);
+    a.az = 1.0 / (g.d.dz * g.d.dz);
+    a.sum_f = L.one.scal ? L.one.scal + 1 : nullptr;
+    a.inv_n = 1.0 / (double)g.N;
+    a.residual = 1;
+    int rc = timed(L.p, "residual_check_f64", (double)g.N * 16.0 * L.n,
+                   [&] { return launch_residual_check(a, nullptr, L.p->stream); });
+    if (rc) return rc;
+    return timed(L.p, "sum_partials", (double)g.ncheck * 32.0 * L.n, [&] {
+        return launch_sum_partials(L.one.partials, g.ncheck, L.one.scal ? L.one.scal + 2 : nullptr,
+                                   L.dev, L.n, 2, L.p->stream);
     });
 }
 
@@ -411,8 +461,9 @@ int pass_y(LSet &L, bool inverse)
 {
     Group &g = *L.g;
     if (g.d.ny == 1) return POISSON_OK;  // a length-1 transform is the identity
+    // the forward y pass follows the x pass, which wrote the planes in order
     YArgs a{L.dev, L.n, L.one.S, g.tab.twy[L.prec == P_F32 ? 1 : 0]->p, g.M, g.d.ny, g.d.nz,
-            inverse ? 1 : 0};
+            inverse ? 1 : 0, (!inverse && reversed_orders()) ? 1 : 0};
     char name[40];
     snprintf(name, sizeof name, inverse ? "y_inv_%s" : "y_fwd_%s", tag(L.prec));
     const double bytes = (double)g.N * 2.0 * (L.prec == P_F32 ? 4.0 : 8.0) * L.n;
@@ -439,6 +490,7 @@ int pass_z(LSet &L)
     a.dz2 = g.d.dz * g.d.dz;
     a.inv_nxny = 1.0 / ((double)g.d.nx * g.d.ny);
     a.inv_ntot = 1.0 / (double)g.N;
+    a.variant = g.zwalls_variant;
     const double bytes = (double)g.N * 2.0 * (L.prec == P_F32 ? 4.0 : 8.0) * L.n;
     char name[40];
     if (g.d.bc_z == POISSON_BC_NEUMANN) {
@@ -452,8 +504,10 @@ int pass_z(LSet &L)
 int pass_x_inv(LSet &L, bool accumulate)
 {
     Group &g = *L.g;
+    // the inverse x pass follows the inverse y pass, which wrote the planes in order
     XInvArgs a{L.dev, L.n, L.one.S, L.one.p, g.tab.twx[L.prec == P_F32 ? 1 : 0]->p, g.d.nx,
-               g.d.ny, g.d.nz, accumulate ? 1 : 0, nullptr, 1.0 / (double)g.N};
+               g.d.ny, g.d.nz, accumulate ? 1 : 0, reversed_orders() ? 1 : 0, nullptr,
+               1.0 / (double)g.N};
     // the mean of p from the residual pass (batched launches redirect it)
     if (accumulate) a.sum_p = L.dev ? (const double *)g.partials->p : L.one.scal + 4;
     char name[40];
@@ -509,7 +563,7 @@ ProbPtrs problem_ptrs(poisson_plan p, const Group &g, int slot, const double *rh
     q.S = p->precision == POISSON_FP64
               ? (void *)sol
               : (void *)((char *)g.S32->p + (size_t)g.N * 4 * slot);
-    q.partials = (double *)g.partials->p + (size_t)g.npart * 4 * slot;
+    q.partials = (double *)g.partials->p + (size_t)g.part_stride * slot;
     q.scal = (double *)p->scalars->p + NSCAL * i;
     return q;
 }
@@ -571,13 +625,29 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
         rc = solve_passes(sets[gi], false, want_partials);
 
     if (!rc && refine) {
-        std::vector<double> rho_prev(count, -1.0);
+        std::vector<double> rho_prev(count, -1.0), rho_first(count, -1.0);
         std::vector<int> corrections(count, 0), state(count, RUNNING);
+        std::vector<char> checked(p->groups.size(), 0);
         double *hs = (double *)p->host_scalars->p;
         for (int it = 0; !rc; ++it) {
-            // residual + its transform for every running problem
-            for (size_t gi = 0; gi < p->groups.size() && !rc; ++gi)
-                if (sets[gi].n) rc = pass_x_fwd(sets[gi], true, true);
+            // Residual of every running problem.  Each correction multiplies
+            // the residual by about the relative accuracy of the FP32 solve,
+            // i.e. by the first residual rho_first; when rho_prev * rho_first
+            // is two decades below rtol for every running problem of a group,
+            // its residual is only checked (no transform, no spectrum write).
+            // If the check fails, the full residual pass follows.
+            for (size_t gi = 0; gi < p->groups.size() && !rc; ++gi) {
+                checked[gi] = 0;
+                if (!sets[gi].n) continue;
+                bool predict = true;
+                for (int slot : active[gi]) {
+                    const int i = p->groups[gi].members[slot];
+                    predict = predict && rho_first[i] > 0 && rho_prev[i] > 0 &&
+                              rho_prev[i] * rho_first[i] * 100.0 <= p->rtol;
+                }
+                checked[gi] = predict;
+                rc = predict ? pass_residual_check(sets[gi]) : pass_x_fwd(sets[gi], true, true);
+            }
             if (rc || (rc = read_scalars(p, count))) break;
             bool any = false;
             for (size_t gi = 0; gi < p->groups.size(); ++gi) {
@@ -597,6 +667,7 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
                     else if (corrections[i] >= p->max_refine ||
                              (rho_prev[i] >= 0 && rho > 0.5 * rho_prev[i]))
                         status = POISSON_ERR_NOT_CONVERGED;
+                    if (rho_first[i] < 0) rho_first[i] = rho;
                     if (status != -1) {
                         out[i].status = status;
                         state[i] = DONE;
@@ -610,6 +681,10 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
                     active[gi] = next;
                     if ((rc = stage((int)gi))) break;
                 }
+                // a check-only pass wrote no spectrum: transform the residual
+                // of the problems that go on
+                if (checked[gi] && !next.empty() && (rc = pass_x_fwd(sets[gi], true, true)))
+                    break;
                 any = any || !next.empty();
             }
             if (rc || !any) break;

@@ -22,6 +22,16 @@ struct Cx {
 
 enum Prec { P_F64 = 0, P_F32 = 1 };
 
+// Block order.  A pass whose input was just written by the previous pass
+// starts on the data that pass wrote last when `reverse` is set: the most
+// recently written lines are the ones still held by the 256 MB last-level
+// (Infinity) cache, so reading them first turns part of the pass's HBM reads
+// into cache hits instead of evicting them before use.
+__device__ __forceinline__ int block_order(int bid, int nblocks, int reverse)
+{
+    return reverse ? nblocks - 1 - bid : bid;
+}
+
 // Per-problem pointers of a batched launch: problems of one shape share a
 // launch and blockIdx.y selects the entry.  A null `batch` pointer in the
 // argument structs below means a single-problem launch using their own
@@ -51,6 +61,7 @@ struct XFwdArgs {
     const double *sum_f;    // residual mode: device sum of f (mean = sum_f * inv_n)
     double inv_n;           // 1/(nx ny nz)
     int residual;           // 1: input is the residual
+    int reverse;            // walk the row blocks from the end (see below)
 };
 
 // Inverse complex-to-real pass along x: p = result (store) or p += result.
@@ -62,6 +73,7 @@ struct XInvArgs {
     const void *tw;
     int nx, ny, nz;
     int accumulate;
+    int reverse;
     const double *sum_p;    // accumulate mode: device sum of p (its mean is removed)
     double inv_n;           // 1/(nx ny nz)
 };
@@ -74,6 +86,7 @@ struct YArgs {
     const void *tw;         // exp(-2 pi i t/ny), t in [0, ny)
     int M, ny, nz;
     int inverse;
+    int reverse;
 };
 
 // z solve, walls (tridiagonal per (m, ky)) or periodic (transform along z).
@@ -91,6 +104,8 @@ struct ZArgs {
     double dz2;             // dz^2
     double inv_nxny;        // 1/(nx ny)
     double inv_ntot;        // 1/(nx ny nz)
+    int reverse;
+    int variant;            // tile variant (0 = default; see the launchers)
 };
 
 // Launchers (return 0 on success, a hipError_t value otherwise).
@@ -106,6 +121,11 @@ int x_fwd_blocks(int prec, int nx, int ny, int nz);
 // problem, partials and scal taken from batch[i], written to scal + out_off.
 int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *batch,
                         int nbatch, int out_off, hipStream_t s);
+// FP64 residual r = (f - mean f) - L p alone (no transform, no spectrum
+// write): per-workgroup sums of r^2, (f - mean f)^2 and p into `partials`
+// (same layout as the forward x pass), for a convergence check.
+int launch_residual_check(const XFwdArgs &a, int *nblocks_out, hipStream_t s);
+int residual_check_blocks(int ny, int nz);
 
 // lengths supported by the transform kernels
 bool fft_length_supported(int n);

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
     __shared__ double s_red[3 * (NT / 64)];
 
     const int nrows = a.ny * a.nz;
-    const int row0 = blockIdx.x * NB;
+    const int row0 = block_order(blockIdx.x, gridDim.x, a.reverse) * NB;
     load_table(s_tw, (const Cx<R> *)a.tw, NX);
     __syncthreads();
 
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
     __shared__ Cx<R> s_tw[NX];
 
     const int nrows = a.ny * a.nz;
-    const int row0 = blockIdx.x * NB;
+    const int row0 = block_order(blockIdx.x, gridDim.x, a.reverse) * NB;
     load_table(s_tw, (const Cx<R> *)a.tw, NX);
     __syncthreads();
 

@@ -42,8 +42,9 @@ __global__ __launch_bounds__(YCfg<N>::NT) void k_y(YArgs a0)
     __shared__ Cx<R> s_tw[N];
 
     const int ntile = (a.M + NB - 1) / NB;
-    const int tile_i = blockIdx.x % ntile;
-    const int k = blockIdx.x / ntile;
+    const int bid = block_order(blockIdx.x, gridDim.x, a.reverse);
+    const int tile_i = bid % ntile;
+    const int k = bid / ntile;
     const int m0 = tile_i * NB;
     load_table(s_tw, (const Cx<R> *)a.tw, N);
     __syncthreads();

@@ -58,7 +58,8 @@ __global__ __launch_bounds__(ZPCfg<N>::NT) void k_z_per(ZArgs a0, int nspecial)
     auto lstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
 
     if ((int)blockIdx.x >= nspecial) {
-        const int q0 = ((int)blockIdx.x - nspecial) * NB;
+        const int q0 =
+            block_order((int)blockIdx.x - nspecial, (int)gridDim.x - nspecial, a.reverse) * NB;
         auto gload = [&](int b, int n) -> Cx<R> {
             const int q = q0 + b;
             if (q >= ncol) return {R(0), R(0)};

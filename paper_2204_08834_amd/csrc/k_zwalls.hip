@@ -56,6 +56,21 @@ namespace PK_NS {
 
 using R = PK_REAL;
 
+// 1/x from the hardware reciprocal refined by Newton steps r += r (1 - x r)
+// (one for FP32, two for FP64): within an ulp, far shorter than the IEEE
+// division sequence on the dependent elimination chain.  x > 0 and normal.
+__device__ __forceinline__ float rcp_nr(float x)
+{
+    float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(fmaf(-x, r, 1.0f), r, r);
+}
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return fma(fma(-x, r, 1.0), r, r);
+}
+
 template <int L, int W, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
 {
@@ -85,7 +100,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
     int q = 0, ky = 0, kyn = 0, part = 0;
     double s_d;  // s = -(lam_x + lam_y) dz^2 >= 0
     if (!special) {
-        q = ((int)blockIdx.x - nspecial) * W + w;
+        q = block_order((int)blockIdx.x - nspecial, (int)gridDim.x - nspecial, a.reverse) * W + w;
         const int m = q % M;
         ky = q / M;
         active = (q < ny * M) && (m != 0);
@@ -126,7 +141,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
     auto zraw = [&](int k) -> double { return double(S[(size_t)k * plane].re); };
 
     const R sv = R(s_d);
-    const R mw = R(1) / (R(1) + sv);  // Moebius matrix [[1, s], [1, 1+s]] / (1+s)
+    const R mw = rcp_nr(R(1) + sv);  // Moebius matrix [[1, s], [1, 1+s]] / (1+s)
     const R mws = sv * mw;
 
     // ---- phase 1: Moebius product of the chunk (v recurrence) -----------
@@ -151,17 +166,27 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
     }
     __syncthreads();  // S1
 
-    R vn = R(0), vd = R(1);
-    for (int cc = 0; cc < c; ++cc) {
-        const R *o = buf + (size_t)(cc * W + w) * 4;
-        const R nn = o[0] * vn + o[1] * vd;
-        const R nd = o[2] * vn + o[3] * vd;
-        const R mx = fmax(fabs(nn), fabs(nd));
-        const R inv = mx > R(0) ? R(1) / mx : R(1);
-        vn = nn * inv;
-        vd = nd * inv;
+    // v entering the chunk: apply the preceding chunks' maps to v (all
+    // entries are >= 0 and the denominator is >= the numerator, so
+    // normalising by it each step is safe and keeps the scan bounded)
+    R vprev0 = R(0);
+    {
+        int cc = 0;
+        for (; cc + 4 <= c; cc += 4) {
+            R o[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) o[u][e] = buf[(size_t)((cc + u) * W + w) * 4 + e];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                vprev0 = (o[u][0] * vprev0 + o[u][1]) * rcp_nr(o[u][2] * vprev0 + o[u][3]);
+        }
+        for (; cc < c; ++cc) {
+            const R *o = buf + (size_t)(cc * W + w) * 4;
+            vprev0 = (o[0] * vprev0 + o[1]) * rcp_nr(o[2] * vprev0 + o[3]);
+        }
     }
-    const R vprev0 = (c == 0) ? R(0) : vn / vd;
 
     // zero wavenumber, FP64: g = (raw - mean raw) * scale; face fluxes
     // F_k = sum_{j<=k} g_j; positions p_k = sum_{j<k} F_j (p_0 = 0)
@@ -184,7 +209,12 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
     __syncthreads();  // S2: Moebius slots consumed
 
     // ---- phase 2: local forward elimination ------------------------------
-    R vk[L], G[L];
+    // Only v is kept per row: the products of u = 1 - v that carry the
+    // boundary values into the chunk (G_k = u_s..u_k forward, H_k = u_k..u_e
+    // backward) are rebuilt from it when needed.  Row nz-1 stores v = 1 (it
+    // does not couple to the row below) and its true u separately.
+    R vk[L];
+    R ulast = R(0);
     {
         Cx<R> Dp = {R(0), R(0)};
         R Gp = R(1), vprev = vprev0;
@@ -195,12 +225,12 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
             const R ex = (k == 0) ? sv : sv + vprev;
             const bool last = k >= nz - 1;
             const R piv = (nz == 1) ? sv : (k == nz - 1 ? ex : R(1) + ex);
-            const R u = R(1) / piv;
+            const R u = rcp_nr(piv);
             const R vnew = last ? R(1) : ex * u;
             Dp = cscale(csub(Dp, d[i]), u);
             Gp = u * Gp;
+            if (k == nz - 1) ulast = u;
             vk[i] = vnew;
-            G[i] = Gp;
             d[i] = Dp;
             vprev = vnew;
         }
@@ -211,12 +241,27 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
 
     {
         Cx<R> dprev = {R(0), R(0)};
-        for (int cc = 0; cc < c; ++cc) {
+        int cc = 0;
+        for (; cc + 4 <= c; cc += 4) {
+            R o[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int e = 0; e < 3; ++e) o[u][e] = buf[(size_t)((cc + u) * W + w) * 4 + e];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                dprev = {o[u][0] + o[u][2] * dprev.re, o[u][1] + o[u][2] * dprev.im};
+        }
+        for (; cc < c; ++cc) {
             const R *o = buf + (size_t)(cc * W + w) * 4;
             dprev = {o[0] + o[2] * dprev.re, o[1] + o[2] * dprev.im};
         }
+        R Gr = R(1);
 #pragma unroll
-        for (int i = 0; i < L; ++i) d[i] = {d[i].re + G[i] * dprev.re, d[i].im + G[i] * dprev.im};
+        for (int i = 0; i < L; ++i) {
+            Gr *= (s + i == nz - 1) ? ulast : R(1) - vk[i];
+            d[i] = {d[i].re + Gr * dprev.re, d[i].im + Gr * dprev.im};
+        }
     }
     // ---- phase 3: local back substitution --------------------------------
     Cx<R> Xn = {R(0), R(0)};
@@ -225,11 +270,9 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
     for (int i = L - 1; i >= 0; --i) {
         // p_k = d'_k + u_k p_{k+1} written as d'_k + (p_{k+1} - v_k p_{k+1})
         const Cx<R> X = {d[i].re + (Xn.re - vk[i] * Xn.re), d[i].im + (Xn.im - vk[i] * Xn.im)};
-        const R H = (R(1) - vk[i]) * Hn;
         d[i] = X;
-        G[i] = H;
         Xn = X;
-        Hn = H;
+        Hn *= R(1) - vk[i];
     }
     double zP0 = 0.0, zsx = 0.0;
     if (zero_lane) {
@@ -248,12 +291,26 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
 
     {
         Cx<R> y = {R(0), R(0)};
-        for (int cc = C - 1; cc > c; --cc) {
+        int cc = C - 1;
+        for (; cc - 4 >= c; cc -= 4) {
+            R o[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int e = 0; e < 3; ++e) o[u][e] = buf[(size_t)((cc - u) * W + w) * 4 + e];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) y = {o[u][0] + o[u][2] * y.re, o[u][1] + o[u][2] * y.im};
+        }
+        for (; cc > c; --cc) {
             const R *o = buf + (size_t)(cc * W + w) * 4;
             y = {o[0] + o[2] * y.re, o[1] + o[2] * y.im};
         }
+        R Hr = R(1);
 #pragma unroll
-        for (int i = 0; i < L; ++i) d[i] = {d[i].re + G[i] * y.re, d[i].im + G[i] * y.im};
+        for (int i = L - 1; i >= 0; --i) {
+            Hr *= R(1) - vk[i];
+            d[i] = {d[i].re + Hr * y.re, d[i].im + Hr * y.im};
+        }
     }
     if (zero_lane) {
         double tot = 0.0;
@@ -320,21 +377,25 @@ using namespace PK_NS;
 
 int PK_SUFFIX(launch_z_walls)(const ZArgs &a, hipStream_t s)
 {
-    // chunk length L (registers), W columns per workgroup, W*ceil(nz/L) threads
+    // chunk length L (registers), W columns per workgroup, W*ceil(nz/L)
+    // threads.  a.variant: 0 or 2 = chunks of 16 rows (default: shorter
+    // cross-chunk scans), 1 = chunks of 8 (fewer registers).
     const int nz = a.nz;
     constexpr bool F32 = sizeof(R) == 4;
+    const int chunk = a.variant == 1 ? 8 : 16;
     if (nz <= 64) return run_zw<8, 32, 256>(a, s);
-    if constexpr (F32) {
+    if (chunk == 16) {
         if (nz <= 256) return run_zw<16, 16, 256>(a, s);
         if (nz <= 512) return run_zw<16, 16, 512>(a, s);
-        if (nz <= 1024) return run_zw<16, 16, 1024>(a, s);
-        if (nz <= 4096) return run_zw<16, 2, 1024>(a, s);
-    } else {
-        if (nz <= 256) return run_zw<8, 16, 512>(a, s);
-        if (nz <= 512) return run_zw<8, 16, 1024>(a, s);
-        if (nz <= 1024) return run_zw<8, 8, 1024>(a, s);
-        if (nz <= 4096) return run_zw<8, 2, 1024>(a, s);
+        if constexpr (F32) {
+            if (nz <= 1024) return run_zw<16, 16, 1024>(a, s);
+            if (nz <= 4096) return run_zw<16, 2, 1024>(a, s);
+        }
     }
+    if (nz <= 256) return run_zw<8, 16, 512>(a, s);
+    if (nz <= 512) return run_zw<8, 16, 1024>(a, s);
+    if (nz <= 1024) return run_zw<8, 8, 1024>(a, s);
+    if (nz <= 4096) return run_zw<8, 2, 1024>(a, s);
     return -1;
 }
 

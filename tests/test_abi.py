@@ -113,4 +113,4 @@ def test_workspace_bytes():
     n = 512 * 512 * 256
     # FP64 works in place in the solution array; FP32 needs a 4 B/point spectrum
     assert P.workspace_bytes(d64) < 1 << 20
-    assert n * 4 <= P.workspace_bytes(d32) < n * 4 + (1 << 20)
+    assert n * 4 <= P.workspace_bytes(d32) < n * 4.1
