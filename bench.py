@@ -27,9 +27,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mpoints/s Poisson solve, FP32+refine vs FP64 @1e-10 resid; HBM GB/s %peak"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published figure
+COPY_BYTES = 1 << 30
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_rb512.txt")
-KERNEL_SOURCES = ["fft_core.hpp", "common.hpp", "k_xpass.hip", "k_ypass.hip", "k_zwalls.hip",
-                  "k_zperiodic.hip"]
+KERNEL_SOURCES = ["api.cpp", "common.hpp", "fft_core.hpp", "lengths.hpp", "k_misc.hip",
+                  "k_xpass.hip", "k_ypass.hip", "k_zperiodic.hip", "k_zwalls.hip"]
 
 DESCRIPTIONS = {
     "rb512": "512x512x256 walls-in-z, box 2x2x1, RHS = div(u/rho_face) with a two-layer "
@@ -50,22 +51,23 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel_name: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when it is absent, for another kernel, or the kernels changed since."""
+def read_traffic(pass_name: str):
+    """HBM bytes per launch of one pass from the committed rocprofv3 counter
+    summary, or None when it is absent, lacks the pass, or the kernel sources
+    changed since it was taken."""
     if not os.path.exists(PROFILE_TRAFFIC):
         return None
     kv = {}
     with open(PROFILE_TRAFFIC) as fh:
         for line in fh:
-            line = line.strip()
-            if "=" in line and not line.startswith("#"):
+            line = line.split("#", 1)[0].strip()
+            if "=" in line:
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("source_hash") != kernel_hash() or kv.get("kernel_pass") != kernel_name:
+    if kv.get("source_hash") != kernel_hash():
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[f"hbm_bytes[{pass_name}]"])
     except (KeyError, ValueError):
         return None
 
@@ -103,6 +105,137 @@ def cpu_baseline(prob, nplanes):
                       f"({prob.nx}x{prob.ny}x{nplanes}), one FP64 oracle solve, {dt:.2f} s"}
 
 
+def copy_calibration(steps, warmup):
+    """Plain streaming kernels of known size: a device-to-device copy (the
+    runtime's blit kernel) and an elementwise negation, 1 GiB read and 1 GiB
+    written each.  The bandwidth they reach, and what the rocprofv3
+    FETCH_SIZE / WRITE_SIZE counters read for them, calibrate the solver's
+    counters."""
+    import torch
+    n = COPY_BYTES // 8
+    src = torch.empty(n, dtype=torch.float64, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    out = {"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES}
+    for label, fn in (("blit_copy", lambda: dst.copy_(src)),
+                      ("elementwise_neg", lambda: torch.neg(src, out=dst))):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(steps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        gbs = 2 * COPY_BYTES / (ms * 1e-3) / 1e9
+        out[label] = {"ms": ms, "gbs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+    return out
+
+
+# kernel-name patterns of the solver's passes (rocprofv3 reports demangled names)
+PASS_PATTERNS = [
+    ("x_r2c_residual_{p}", r"prec_{p}::k_x_fwd<\d+, true>"),
+    ("x_r2c_{p}", r"prec_{p}::k_x_fwd<\d+, false>"),
+    ("x_c2r_accumulate_{p}", r"prec_{p}::k_x_inv<\d+, true>"),
+    ("x_c2r_{p}", r"prec_{p}::k_x_inv<\d+, false>"),
+    ("y_fwd_{p}", r"prec_{p}::k_y<\d+, false>"),
+    ("y_inv_{p}", r"prec_{p}::k_y<\d+, true>"),
+    ("z_walls_{p}", r"prec_{p}::k_z_walls<"),
+    ("z_periodic_{p}", r"prec_{p}::k_z_per<"),
+]
+
+
+def pass_of_kernel(name):
+    import re
+    for p in ("f32", "f64"):
+        for label, pat in PASS_PATTERNS:
+            if re.search(pat.format(p=p), name):
+                return label.format(p=p)
+    if "k_residual_check" in name:
+        return "residual_check_f64"
+    if "k_sum_partials" in name:
+        return "sum_partials"
+    return None
+
+
+def read_counter_csv(path):
+    """{(kernel name, counter): [value per dispatch]} from a rocprofv3
+    counter_collection.csv."""
+    import csv
+    vals = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            key = (r["Kernel_Name"], r["Counter_Name"])
+            vals.setdefault(key, []).append(float(r["Counter_Value"]))
+    return vals
+
+
+def summarize_counters(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, out_path, commands):
+    """Write the HBM traffic summary read by this script's roofline entry:
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per pass, each scaled by
+    what the same counter reads for the 1 GiB elementwise calibration
+    kernel."""
+    import statistics
+    fetch, write = read_counter_csv(fetch_csv), read_counter_csv(write_csv)
+    cfetch, cwrite = read_counter_csv(cal_fetch_csv), read_counter_csv(cal_write_csv)
+
+    def cal(vals, counter):
+        xs = [v for (k, c), vs in vals.items() if c == counter and "neg" in k for v in vs]
+        return statistics.median(xs) * 1024.0
+    f_scale = COPY_BYTES / cal(cfetch, "FETCH_SIZE")
+    w_scale = COPY_BYTES / cal(cwrite, "WRITE_SIZE")
+    per_pass = {}
+    for (k, c), vs in fetch.items():
+        ps = pass_of_kernel(k)
+        if ps and c == "FETCH_SIZE":
+            per_pass.setdefault(ps, {})["fetch"] = statistics.median(vs) * 1024.0
+    for (k, c), vs in write.items():
+        ps = pass_of_kernel(k)
+        if ps and c == "WRITE_SIZE":
+            per_pass.setdefault(ps, {})["write"] = statistics.median(vs) * 1024.0
+    lines = ["# HBM traffic per dispatch, rocprofv3 counters, 512x512x256 walls-in-z (rb512)",
+             "# commands (from the repository root; rocprofv3 runs after "
+             "`cd /tmp && export TMPDIR=/tmp`):"]
+    lines += ["#   " + c for c in commands]
+    lines += [f"# calibration: 1 GiB elementwise kernel reads FETCH_SIZE x {f_scale:.4f}, "
+              f"WRITE_SIZE x {w_scale:.4f} of its true bytes",
+              "# bytes below = counter KiB x 1024 x scale, median over dispatches",
+              f"source_hash = {kernel_hash()}",
+              f"fetch_scale = {f_scale:.6f}", f"write_scale = {w_scale:.6f}"]
+    for ps in sorted(per_pass):
+        fb = per_pass[ps].get("fetch", 0.0) * f_scale
+        wb = per_pass[ps].get("write", 0.0) * w_scale
+        lines.append(f"hbm_bytes[{ps}] = {fb + wb:.0f}   # read {fb:.0f} write {wb:.0f}")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_kernels(stats_csv, out_path, commands):
+    """Write the per-kernel duration summary from a rocprofv3 --stats
+    kernel_stats.csv, with each kernel's pass name."""
+    import csv
+    with open(stats_csv) as fh:
+        rows = list(csv.DictReader(fh))
+    lines = ["# rocprofv3 kernel statistics, 512x512x256 walls-in-z (rb512): every dispatch of "
+             "the run (warmup, timed steps, per-pass timing, FP32+refine and FP64 plans)",
+             "# commands (from the repository root; rocprofv3 runs after "
+             "`cd /tmp && export TMPDIR=/tmp`):"]
+    lines += ["#   " + c for c in commands]
+    lines.append(f"# source_hash = {kernel_hash()}")
+    lines.append(f"{'pass':22s} {'calls':>5s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} "
+                 f"{'pct':>6s}  kernel")
+    for r in rows:
+        name = r["Name"]
+        lines.append(f"{pass_of_kernel(name) or '-':22s} {int(r['Calls']):5d} "
+                     f"{float(r['AverageNs']) / 1e3:9.2f} {float(r['MinNs']) / 1e3:9.2f} "
+                     f"{float(r['MaxNs']) / 1e3:9.2f} {float(r['Percentage']):6.2f}  {name[:70]}")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,10 +247,26 @@ def main():
     ap.add_argument("--only", choices=["fp32_refine", "fp64"], default=None,
                     help="time one precision only (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="time a plain device-to-device copy of 1 GiB instead (the HBM "
-                         "bandwidth a streaming kernel attains, and the reference for "
-                         "scaling FETCH_SIZE / WRITE_SIZE counters)")
+                    help="time plain 1 GiB copy kernels instead (the HBM bandwidth a "
+                         "streaming kernel attains, and the reference for scaling "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--summarize-counters", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV",
+                    "CAL_FETCH_CSV", "CAL_WRITE_CSV", "OUT"),
+                    help="write the HBM traffic summary from rocprofv3 --pmc FETCH_SIZE / "
+                         "WRITE_SIZE counter_collection.csv files of a solve run and of a "
+                         "--copy-calibration run")
+    ap.add_argument("--summarize-kernels", nargs=2, metavar=("STATS_CSV", "OUT"),
+                    help="write the per-kernel duration summary from a rocprofv3 --stats "
+                         "kernel_stats.csv")
+    ap.add_argument("--command", action="append", default=[],
+                    help="with --summarize-*: a command to record in the summary")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, commands=args.command)
+        return
+    if args.summarize_kernels:
+        summarize_kernels(*args.summarize_kernels, commands=args.command)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -134,22 +283,7 @@ def main():
     poisson.lib()  # fail loudly if the HIP library is missing
 
     if args.copy_calibration:
-        n = (1 << 30) // 8
-        src = torch.empty(n, dtype=torch.float64, device="cuda").uniform_()
-        dst = torch.empty_like(src)
-        for _ in range(args.warmup):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(args.steps):
-            dst.copy_(src)
-        ev1.record()
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / args.steps
-        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
-                          "ms_per_copy": ms, "gbs": 2 * n * 8 / (ms * 1e-3) / 1e9,
-                          "frac_of_peak": 2 * n * 8 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}))
+        print(json.dumps(copy_calibration(args.steps, args.warmup)), flush=True)
         return
 
     prob = inputs.workload(args.workload)

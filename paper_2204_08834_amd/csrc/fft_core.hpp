@@ -83,6 +83,21 @@ constexpr RPlan make_rplan(int n)
     return p;
 }
 
+// plan variant: 0 = the order above, 1 = the same radices in reverse order
+// (small radix first)
+constexpr RPlan get_rplan(int n, int variant)
+{
+    RPlan p = make_rplan(n);
+    if (variant == 1) {
+        for (int i = 0; i < p.count / 2; ++i) {
+            const int t = p.r[i];
+            p.r[i] = p.r[p.count - 1 - i];
+            p.r[p.count - 1 - i] = t;
+        }
+    }
+    return p;
+}
+
 constexpr int rplan_ns(RPlan p, int pass)
 {
     int ns = 1;
@@ -232,16 +247,18 @@ __device__ __forceinline__ void stockham_pass(const Cx<R> *__restrict__ tw, int 
 // On return all threads have finished their stores (no trailing barrier).
 // N == 1 is the identity.
 // ---------------------------------------------------------------------------
-template <typename R, int N, int NB, int NT, bool LF, int PAD, bool GL_LDS, int PASS, class GL,
-          class GS>
+template <typename R, int N, int NB, int NT, bool LF, int PAD, bool GL_LDS, int PASS, int END,
+          int PV, class GL, class GS>
 __device__ __forceinline__ void fft_passes(const Cx<R> *__restrict__ tw, int tws, GL &gload,
                                            GS &gstore, LdsTile<R, N, NB, LF, PAD> tile)
 {
-    constexpr RPlan pl = make_rplan(N);
+    // passes PASS .. END-1 of plan variant PV; pass 0 reads through gload,
+    // pass END-1 writes through gstore, the others exchange through the LDS tile
+    constexpr RPlan pl = get_rplan(N, PV);
     constexpr int RAD = pl.r[PASS];
     constexpr int NS = rplan_ns(pl, PASS);
     constexpr bool FIRST = PASS == 0;
-    constexpr bool LAST = PASS == pl.count - 1;
+    constexpr bool LAST = PASS == END - 1;
     auto lload = [&](int b, int n) { return tile.at(b, n); };
     auto lstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
     if constexpr (FIRST && LAST) {
@@ -256,7 +273,8 @@ __device__ __forceinline__ void fft_passes(const Cx<R> *__restrict__ tw, int tws
         __syncthreads();
     }
     if constexpr (!LAST)
-        fft_passes<R, N, NB, NT, LF, PAD, GL_LDS, PASS + 1>(tw, tws, gload, gstore, tile);
+        fft_passes<R, N, NB, NT, LF, PAD, GL_LDS, PASS + 1, END, PV>(tw, tws, gload, gstore,
+                                                                    tile);
 }
 
 // GL_LDS: gload reads the LDS tile itself (pass 0 then needs a barrier between
@@ -276,7 +294,8 @@ __device__ __forceinline__ void fft_tile(const Cx<R> *__restrict__ tw, int tws, 
             if (b < NB) gstore(b, 0, v);
         }
     } else {
-        fft_passes<R, N, NB, NT, LF, PAD, GL_LDS, 0>(tw, tws, gload, gstore, tile);
+        fft_passes<R, N, NB, NT, LF, PAD, GL_LDS, 0, make_rplan(N).count, 0>(tw, tws, gload,
+                                                                             gstore, tile);
     }
 }
 

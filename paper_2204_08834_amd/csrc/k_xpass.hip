@@ -60,6 +60,48 @@ __device__ __forceinline__ void block_sum3(double &a, double &b, double &c, doub
     }
 }
 
+// The split of the M-point spectrum (forward) and its merge (inverse) couple
+// the values at m and M - m.  In the last Stockham pass (forward) and the
+// first one (inverse) the butterfly j handles indices j + r NJ, r < RAD,
+// NJ = M/RAD, and the partner of j + r NJ is (NJ - j) + (RAD-1-r) NJ for
+// j > 0, while butterflies 0 and NJ/2 are their own partners (r <-> RAD-r and
+// r <-> RAD-1-r).  A thread therefore takes the butterfly pair (p, NJ - p)
+// for p in [1, NJ/2), or (0, NJ/2) for p = 0, and both values of every
+// coupled pair meet in its registers: no extra LDS round trip in the forward
+// pass, and every spectrum element is read once in the inverse pass.
+template <int NJ>
+__device__ __forceinline__ void pair_of(int p, int &j1, int &j2)
+{
+    j1 = p;
+    j2 = (p == 0) ? NJ / 2 : NJ - p;
+}
+
+// forward split of one coupled pair: zm = Z[m], zc = Z[M-m], w = exp(-2 pi i m/nx)
+//   X[m] = A + w B,  X[M-m] = conj(A - w B),
+//   A = (zm + conj zc)/2,  B = -i (zm - conj zc)/2
+template <typename T>
+__device__ __forceinline__ void split_pair(Cx<T> zm, Cx<T> zc, Cx<T> w, Cx<T> &xm, Cx<T> &xc)
+{
+    const Cx<T> A = cscale(cadd(zm, cconj(zc)), T(0.5));
+    const Cx<T> B = cscale(cmul_mi(csub(zm, cconj(zc))), T(0.5));
+    const Cx<T> wB = cmul(w, B);
+    xm = cadd(A, wB);
+    xc = cconj(csub(A, wB));
+}
+
+// inverse merge of one coupled pair: xm = X[m], xc = X[M-m], w = exp(-2 pi i m/nx)
+//   Z'[m] = A + T,  Z'[M-m] = conj(A - T),
+//   A = xm + conj xc,  T = i conj(w) (xm - conj xc);
+// returned conjugated (the inverse runs as conj(FFT(conj))).
+template <typename T>
+__device__ __forceinline__ void merge_pair(Cx<T> xm, Cx<T> xc, Cx<T> w, Cx<T> &zm, Cx<T> &zc)
+{
+    const Cx<T> A = cadd(xm, cconj(xc));
+    const Cx<T> Tt = cmul_pi(cmul(cconj(w), csub(xm, cconj(xc))));
+    zm = cconj(cadd(A, Tt));
+    zc = csub(A, Tt);
+}
+
 template <int M, bool RES>
 __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
 {
@@ -77,7 +119,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
     using Tile = LdsTile<R, M, NB, false, C::PAD>;
     __shared__ Cx<R> s_tile[Tile::elems];
     __shared__ Cx<R> s_tw[NX];
-    __shared__ double s_red[3 * (NT / 64)];
+    static_assert(sizeof(Cx<R>) * Tile::elems >= 3 * (NT / 64) * sizeof(double), "");
 
     const int nrows = a.ny * a.nz;
     const int row0 = block_order(blockIdx.x, gridDim.x, a.reverse) * NB;
@@ -129,29 +171,85 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
     };
     Tile tile{s_tile};
     auto lstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
-    fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, lstore, tile);
-    __syncthreads();
-
-    // split the M-point spectrum into the half spectrum of the real rows
     Cx<R> *S = (Cx<R> *)a.S;
-    for (int u = threadIdx.x; u < NB * M; u += NT) {
-        const int b = u / M, m = u % M;
-        const int row = row0 + b;
-        if (row >= nrows) continue;
-        const Cx<R> zm = tile.at(b, m);
-        Cx<R> x;
-        if (m == 0) {
-            x = {zm.re + zm.im, zm.re - zm.im};
-        } else {
-            const Cx<R> zc = cconj(tile.at(b, M - m));
-            const Cx<R> e = cscale(cadd(zm, zc), R(0.5));
-            const Cx<R> o = cscale(cmul_mi(csub(zm, zc)), R(0.5));
-            x = cadd(e, cmul(s_tw[m], o));
+    constexpr RPlan pl = make_rplan(M);
+    if constexpr (pl.count >= 2) {
+        // all passes but the last, then the last pass with the split fused
+        fft_passes<R, M, NB, NT, false, C::PAD, false, 0, pl.count - 1, 0>(s_tw, 2, gload, lstore,
+                                                                           tile);
+        __syncthreads();
+        constexpr int RAD = pl.r[pl.count - 1];
+        constexpr int NJ = M / RAD;
+        static_assert(NJ == rplan_ns(pl, pl.count - 1) && NJ % 2 == 0, "pairing needs even NJ");
+        constexpr int U = NJ / 2, NU = NB * U;
+        constexpr int PER = (NU + NT - 1) / NT;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int u = threadIdx.x + q * NT;
+            if (NU % NT != 0 && u >= NU) break;
+            const int b = u / U, pp = u % U;
+            int j1, j2;
+            pair_of<NJ>(pp, j1, j2);
+            Cx<R> v1[RAD], v2[RAD];
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) {
+                v1[r] = tile.at(b, j1 + r * NJ);
+                v2[r] = tile.at(b, j2 + r * NJ);
+            }
+#pragma unroll
+            for (int r = 1; r < RAD; ++r) {
+                v1[r] = cmul(v1[r], s_tw[2 * r * j1]);
+                v2[r] = cmul(v2[r], s_tw[2 * r * j2]);
+            }
+            Bfly<R, RAD>::run(v1);
+            Bfly<R, RAD>::run(v2);
+            const int row = row0 + b;
+            if (row >= nrows) continue;
+            Cx<R> *Sr = S + (size_t)row * M;
+            auto emit = [&](int m, Cx<R> zm, Cx<R> zc) {
+                Cx<R> xm, xc;
+                split_pair(zm, zc, s_tw[m], xm, xc);
+                Sr[m] = xm;
+                if (2 * m != M) Sr[M - m] = xc;
+            };
+            if (pp == 0) {
+                // butterfly 0: m = r NJ; m = 0 packs X(0) + i X(M)
+                Sr[0] = {v1[0].re + v1[0].im, v1[0].re - v1[0].im};
+#pragma unroll
+                for (int r = 1; r < RAD; ++r)
+                    if (r <= RAD - r) emit(r * NJ, v1[r], v1[RAD - r]);
+                // butterfly NJ/2: m = NJ/2 + r NJ, partner r <-> RAD-1-r
+#pragma unroll
+                for (int r = 0; r < RAD; ++r)
+                    if (r <= RAD - 1 - r) emit(NJ / 2 + r * NJ, v2[r], v2[RAD - 1 - r]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < RAD; ++r) emit(j1 + r * NJ, v1[r], v2[RAD - 1 - r]);
+            }
         }
-        S[(size_t)row * M + m] = x;
+    } else {
+        fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, lstore, tile);
+        __syncthreads();
+        // split the M-point spectrum into the half spectrum of the real rows
+        for (int u = threadIdx.x; u < NB * M; u += NT) {
+            const int b = u / M, m = u % M;
+            const int row = row0 + b;
+            if (row >= nrows) continue;
+            const Cx<R> zm = tile.at(b, m);
+            if (m == 0) {
+                S[(size_t)row * M] = {zm.re + zm.im, zm.re - zm.im};
+            } else {
+                Cx<R> xm, xc;
+                split_pair(zm, tile.at(b, M - m), s_tw[m], xm, xc);
+                S[(size_t)row * M + m] = xm;
+            }
+        }
     }
 
     if (a.partials) {
+        // the reduction scratch reuses the tile once every wave is done with it
+        double *s_red = (double *)s_tile;
+        __syncthreads();
         block_sum3(acc0, acc1, acc2, s_red);
         if (threadIdx.x == 0) {
             a.partials[4 * blockIdx.x] = acc0;
@@ -161,7 +259,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
     }
 }
 
-template <int M>
+template <int M, bool ACC>
 __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
 {
     XInvArgs a = a0;
@@ -169,11 +267,11 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
         const ProbPtrs &q = a.batch[blockIdx.y];
         a.S = q.S;
         a.p = q.p;
-        if (a.sum_p) a.sum_p = q.scal + 4;
+        if (ACC && a.sum_p) a.sum_p = q.scal + 4;
     }
     // accumulate mode also removes the mean of the previous iterate (the
     // residual cannot see the constant mode, so the gauge is kept here)
-    const double pmean = (a.accumulate && a.sum_p) ? (*a.sum_p) * a.inv_n : 0.0;
+    const double pmean = (ACC && a.sum_p) ? (*a.sum_p) * a.inv_n : 0.0;
     using C = XCfg<M>;
     constexpr int NB = C::NB, NT = C::NT, NX = 2 * M;
     using Tile = LdsTile<R, M, NB, false, C::PAD>;
@@ -186,28 +284,12 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
     __syncthreads();
 
     const Cx<R> *S = (const Cx<R> *)a.S;
-    auto gload = [&](int b, int n) -> Cx<R> {
-        const int row = row0 + b;
-        if (row >= nrows) return {R(0), R(0)};
-        const Cx<R> *sr = S + (size_t)row * M;
-        Cx<R> zp;
-        if (n == 0) {
-            const Cx<R> s0 = sr[0];
-            zp = {s0.re + s0.im, s0.re - s0.im};
-        } else {
-            const Cx<R> xm = sr[n];
-            const Cx<R> xc = cconj(sr[M - n]);
-            const Cx<R> t = cmul(cconj(s_tw[n]), csub(xm, xc));
-            zp = cadd(cadd(xm, xc), cmul_pi(t));
-        }
-        return cconj(zp);  // inverse transform as conj(FFT(conj))
-    };
     auto gstore = [&](int b, int n, Cx<R> v) {
         const int row = row0 + b;
         if (row >= nrows) return;
         double2 *dst = (double2 *)(a.p + (size_t)row * NX + 2 * n);
         double2 o = {double(v.re), -double(v.im)};
-        if (a.accumulate) {
+        if constexpr (ACC) {
             const double2 old = *dst;
             o.x += old.x - pmean;
             o.y += old.y - pmean;
@@ -215,7 +297,81 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
         *dst = o;
     };
     Tile tile{s_tile};
-    fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, gstore, tile);
+    // reversed radix order: the small radix first gives more butterfly pairs
+    // per row for the fused first pass
+    constexpr RPlan pl = get_rplan(M, 1);
+    if constexpr (pl.count >= 2 && (M / pl.r[0]) % 2 == 0) {
+        // first pass with the merge fused (no twiddles in a first pass),
+        // outputs of butterfly j to the LDS tile at j RAD + r
+        constexpr int RAD = pl.r[0];
+        constexpr int NJ = M / RAD;
+        static_assert(NJ % 2 == 0, "pairing needs even NJ");
+        constexpr int U = NJ / 2, NU = NB * U;
+        constexpr int PER = (NU + NT - 1) / NT;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int u = threadIdx.x + q * NT;
+            if (NU % NT != 0 && u >= NU) break;
+            const int b = u / U, pp = u % U;
+            int j1, j2;
+            pair_of<NJ>(pp, j1, j2);
+            const int row = row0 + b;
+            Cx<R> v1[RAD], v2[RAD];
+            if (row < nrows) {
+                const Cx<R> *sr = S + (size_t)row * M;
+#pragma unroll
+                for (int r = 0; r < RAD; ++r) {
+                    v1[r] = sr[j1 + r * NJ];
+                    v2[r] = sr[j2 + r * NJ];
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < RAD; ++r) v1[r] = v2[r] = {R(0), R(0)};
+            }
+            Cx<R> z1[RAD], z2[RAD];
+            if (pp == 0) {
+                // m = 0 unpacks X(0) + i X(M); butterfly 0 pairs r <-> RAD-r
+                z1[0] = {v1[0].re + v1[0].im, -(v1[0].re - v1[0].im)};
+#pragma unroll
+                for (int r = 1; r < RAD; ++r)
+                    if (r <= RAD - r) merge_pair(v1[r], v1[RAD - r], s_tw[r * NJ], z1[r], z1[RAD - r]);
+#pragma unroll
+                for (int r = 0; r < RAD; ++r)
+                    if (r <= RAD - 1 - r)
+                        merge_pair(v2[r], v2[RAD - 1 - r], s_tw[NJ / 2 + r * NJ], z2[r],
+                                   z2[RAD - 1 - r]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < RAD; ++r)
+                    merge_pair(v1[r], v2[RAD - 1 - r], s_tw[j1 + r * NJ], z1[r], z2[RAD - 1 - r]);
+            }
+            Bfly<R, RAD>::run(z1);
+            Bfly<R, RAD>::run(z2);
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) {
+                tile.at(b, j1 * RAD + r) = z1[r];
+                tile.at(b, j2 * RAD + r) = z2[r];
+            }
+        }
+        __syncthreads();
+        auto gnone = [&](int, int) -> Cx<R> { return {R(0), R(0)}; };
+        fft_passes<R, M, NB, NT, false, C::PAD, false, 1, pl.count, 1>(s_tw, 2, gnone, gstore,
+                                                                       tile);
+    } else {
+        auto gload = [&](int b, int n) -> Cx<R> {
+            const int row = row0 + b;
+            if (row >= nrows) return {R(0), R(0)};
+            const Cx<R> *sr = S + (size_t)row * M;
+            if (n == 0) {
+                const Cx<R> s0 = sr[0];
+                return {s0.re + s0.im, -(s0.re - s0.im)};
+            }
+            Cx<R> zm, zc;
+            merge_pair(sr[n], sr[M - n], s_tw[n], zm, zc);
+            return zm;
+        };
+        fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, gstore, tile);
+    }
 }
 
 template <int M> static int run_x_fwd(const XFwdArgs &a, hipStream_t s)
@@ -234,7 +390,11 @@ template <int M> static int run_x_inv(const XInvArgs &a, hipStream_t s)
 {
     const int nrows = a.ny * a.nz;
     const int nb = (nrows + XCfg<M>::NB - 1) / XCfg<M>::NB;
-    hipLaunchKernelGGL(k_x_inv<M>, dim3(nb, a.batch ? a.nbatch : 1), dim3(XCfg<M>::NT), 0, s, a);
+    const dim3 grid(nb, a.batch ? a.nbatch : 1);
+    if (a.accumulate)
+        hipLaunchKernelGGL((k_x_inv<M, true>), grid, dim3(XCfg<M>::NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_x_inv<M, false>), grid, dim3(XCfg<M>::NT), 0, s, a);
     return (int)hipGetLastError();
 }
 

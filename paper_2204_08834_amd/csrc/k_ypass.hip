@@ -30,7 +30,7 @@ template <int N> struct YCfg {
     static constexpr int PAD = (NB >= 8) ? 1 : 0;
 };
 
-template <int N>
+template <int N, bool INV>
 __global__ __launch_bounds__(YCfg<N>::NT) void k_y(YArgs a0)
 {
     YArgs a = a0;
@@ -51,15 +51,14 @@ __global__ __launch_bounds__(YCfg<N>::NT) void k_y(YArgs a0)
 
     Cx<R> *base = (Cx<R> *)a.S + (size_t)k * N * a.M + m0;
     const int M = a.M;
-    const bool inv = a.inverse != 0;
     auto gload = [&](int b, int n) -> Cx<R> {
         if (m0 + b >= M) return {R(0), R(0)};
         Cx<R> v = base[(size_t)n * M + b];
-        return inv ? cconj(v) : v;
+        return INV ? cconj(v) : v;
     };
     auto gstore = [&](int b, int n, Cx<R> v) {
         if (m0 + b >= M) return;
-        base[(size_t)n * M + b] = inv ? cconj(v) : v;
+        base[(size_t)n * M + b] = INV ? cconj(v) : v;
     };
     Tile tile{s_tile};
     fft_tile<R, N, NB, NT, true, C::PAD, false>(s_tw, 1, gload, gstore, tile);
@@ -68,8 +67,11 @@ __global__ __launch_bounds__(YCfg<N>::NT) void k_y(YArgs a0)
 template <int N> static int run_y(const YArgs &a, hipStream_t s)
 {
     const int ntile = (a.M + YCfg<N>::NB - 1) / YCfg<N>::NB;
-    hipLaunchKernelGGL(k_y<N>, dim3(ntile * a.nz, a.batch ? a.nbatch : 1), dim3(YCfg<N>::NT), 0,
-                       s, a);
+    const dim3 grid(ntile * a.nz, a.batch ? a.nbatch : 1);
+    if (a.inverse)
+        hipLaunchKernelGGL((k_y<N, true>), grid, dim3(YCfg<N>::NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_y<N, false>), grid, dim3(YCfg<N>::NT), 0, s, a);
     return (int)hipGetLastError();
 }
 
