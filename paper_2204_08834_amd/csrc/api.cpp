@@ -176,6 +176,7 @@ struct Group {
     std::shared_ptr<DevBuf> S32;       // FP32 spectra, one per member
     std::shared_ptr<DevBuf> partials;  // per-workgroup partial sums, part_stride per member
     int npart = 0;                     // workgroups of the forward x pass
+    int nres = 0;                      // workgroups of the residual x pass
     int ncheck = 0;                    // workgroups of the residual-check pass
     int part_stride = 0;               // doubles of partials per member
     int zwalls_variant = 0;            // tile variant of the wall-bounded z solve
@@ -264,14 +265,26 @@ int validate(const poisson_desc_t *d)
 
 int internal_prec(int precision) { return precision == POISSON_FP64 ? P_F64 : P_F32; }
 
+// per-workgroup partial-sum records (4 doubles each) a problem needs: the
+// largest grid of the passes that write them
+int partial_slots(const poisson_desc_t &d)
+{
+    int n = x_fwd_blocks(internal_prec(d.precision), d.nx, d.ny, d.nz, 0);
+    if (d.precision == POISSON_FP32_REFINE) {
+        const int r = x_fwd_blocks(P_F32, d.nx, d.ny, d.nz, 1);
+        const int c = residual_check_blocks(d.nx, d.ny, d.nz);
+        n = n > r ? n : r;
+        n = n > c ? n : c;
+    }
+    return n;
+}
+
 size_t workspace_bytes(const poisson_desc_t *d)
 {
     const size_t n = (size_t)d->nx * d->ny * d->nz;
     size_t b = 0;
     if (d->precision != POISSON_FP64) b += n * 4;  // FP32 half spectrum: N/2 complex floats
-    const int nb = x_fwd_blocks(internal_prec(d->precision), d->nx, d->ny, d->nz);
-    const int nc = d->precision == POISSON_FP32_REFINE ? residual_check_blocks(d->ny, d->nz) : 0;
-    b += (size_t)(nb > nc ? nb : nc) * 4 * sizeof(double);
+    b += (size_t)partial_slots(*d) * 4 * sizeof(double);
     return b;
 }
 
@@ -301,9 +314,11 @@ int build_group(Group &g)
     if ((rc = upload(t.lamz, lz.data(), lz.size() * 8))) return rc;
     const size_t n = g.members.size();
     if (f32 && (rc = dev_alloc(g.S32, (size_t)g.N * 4 * n))) return rc;
-    g.npart = x_fwd_blocks(internal_prec(d.precision), d.nx, d.ny, d.nz);
-    g.ncheck = d.precision == POISSON_FP32_REFINE ? residual_check_blocks(d.ny, d.nz) : 0;
-    g.part_stride = (g.npart > g.ncheck ? g.npart : g.ncheck) * 4;
+    const bool refine = d.precision == POISSON_FP32_REFINE;
+    g.npart = x_fwd_blocks(internal_prec(d.precision), d.nx, d.ny, d.nz, 0);
+    g.nres = refine ? x_fwd_blocks(P_F32, d.nx, d.ny, d.nz, 1) : 0;
+    g.ncheck = refine ? residual_check_blocks(d.nx, d.ny, d.nz) : 0;
+    g.part_stride = partial_slots(d) * 4;
     if ((rc = dev_alloc(g.partials, (size_t)g.part_stride * sizeof(double) * n))) return rc;
     if ((rc = dev_alloc(g.ptrs, sizeof(ProbPtrs) * n))) return rc;
     if (const char *e = getenv("POISSON_ZWALLS_CHUNK"))  // 8 or 16 rows per chunk
@@ -421,8 +436,9 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials)
     // three sums per workgroup: plain input -> (sum f, 0, 0) into scal[1..3];
     // residual -> (sum r^2, sum fbar^2, sum p) into scal[2..4]
     const int off = residual ? 2 : 1;
-    return timed(L.p, "sum_partials", (double)g.npart * 32.0 * L.n, [&] {
-        return launch_sum_partials(L.one.partials, g.npart, L.one.scal ? L.one.scal + off : nullptr,
+    const int np = residual ? g.nres : g.npart;
+    return timed(L.p, "sum_partials", (double)np * 32.0 * L.n, [&] {
+        return launch_sum_partials(L.one.partials, np, L.one.scal ? L.one.scal + off : nullptr,
                                    L.dev, L.n, off, L.p->stream);
     });
 }

@@ -61,7 +61,7 @@ struct XFwdArgs {
     const double *sum_f;    // residual mode: device sum of f (mean = sum_f * inv_n)
     double inv_n;           // 1/(nx ny nz)
     int residual;           // 1: input is the residual
-    int reverse;            // walk the row blocks from the end (see below)
+    int reverse;            // walk the row blocks from the end (see block_order)
 };
 
 // Inverse complex-to-real pass along x: p = result (store) or p += result.
@@ -114,8 +114,9 @@ int launch_x_inv(int prec, const XInvArgs &a, hipStream_t s);
 int launch_y(int prec, const YArgs &a, hipStream_t s);
 int launch_z_walls(int prec, const ZArgs &a, hipStream_t s);
 int launch_z_periodic(int prec, const ZArgs &a, hipStream_t s);
-// number of workgroups the forward x pass uses (size of its partials array)
-int x_fwd_blocks(int prec, int nx, int ny, int nz);
+// number of workgroups the forward x pass uses (size of its partials array);
+// `residual` selects the residual pass of the refinement
+int x_fwd_blocks(int prec, int nx, int ny, int nz, int residual);
 // Deterministic FP64 sums of the x pass's partials: `n` workgroups with three
 // sums each (stride 4), written to out[0..3).  Batched: one workgroup per
 // problem, partials and scal taken from batch[i], written to scal + out_off.
@@ -125,7 +126,7 @@ int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *ba
 // write): per-workgroup sums of r^2, (f - mean f)^2 and p into `partials`
 // (same layout as the forward x pass), for a convergence check.
 int launch_residual_check(const XFwdArgs &a, int *nblocks_out, hipStream_t s);
-int residual_check_blocks(int ny, int nz);
+int residual_check_blocks(int nx, int ny, int nz);
 
 // lengths supported by the transform kernels
 bool fft_length_supported(int n);

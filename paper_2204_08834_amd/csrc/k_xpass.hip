@@ -9,9 +9,9 @@
 // and X[0] = Re Z[0] + Im Z[0], X[M] = Re Z[0] - Im Z[0] (both real), which
 // are packed as S[0] = X[0] + i X[M].
 // Optionally the input is the FP64 residual r = (f - mu) - L p of the
-// iterative refinement, evaluated from f and p as the row is loaded (its L2
-// norm and that of f - mu accumulate in FP64 per workgroup), so r never
-// touches HBM.
+// iterative refinement, evaluated from f and p row by row into the LDS tile
+// (its L2 norm and that of f - mu accumulate in FP64 per workgroup), so r
+// never touches HBM.
 //
 // Inverse: Z'[m] = (X[m] + conj X[M-m]) + i w^-m (X[m] - conj X[M-m]) with
 // Z'[0] = (X[0] + X[M]) + i (X[0] - X[M]); an inverse M-point FFT of Z'
@@ -21,6 +21,7 @@
 // Compiled once per precision with PK_REAL = float or double.
 #include "fft_core.hpp"
 #include "lengths.hpp"
+#include "stencil.hpp"
 
 #ifndef PK_REAL
 #error "PK_REAL must be defined"
@@ -38,27 +39,6 @@ template <int M> struct XCfg {
     static constexpr int NT = pick_nt(NB * M, sizeof(R) == 4 ? 16 : 8);
     static constexpr int PAD = 0;
 };
-
-// sum three doubles over the workgroup; thread 0 gets the totals
-__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *sh)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_down(a, off, 64);
-        b += __shfl_down(b, off, 64);
-        c += __shfl_down(c, off, 64);
-    }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) { sh[3 * wid] = a; sh[3 * wid + 1] = b; sh[3 * wid + 2] = c; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nw = (blockDim.x + 63) >> 6;
-        a = 0.0;
-        b = 0.0;
-        c = 0.0;
-        for (int w = 0; w < nw; ++w) { a += sh[3 * w]; b += sh[3 * w + 1]; c += sh[3 * w + 2]; }
-    }
-}
 
 // The split of the M-point spectrum (forward) and its merge (inverse) couple
 // the values at m and M - m.  In the last Stockham pass (forward) and the
@@ -102,81 +82,20 @@ __device__ __forceinline__ void merge_pair(Cx<T> xm, Cx<T> xc, Cx<T> w, Cx<T> &z
     zc = csub(A, Tt);
 }
 
-template <int M, bool RES>
-__global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
+// Forward transform of the NB lines of M points held by a workgroup: pass 0
+// reads through gload (from global memory, or from the tile itself when
+// GL_LDS), and the last pass writes the half spectra of the real rows through
+// out(b) (row pointer into S, null to skip the row).  LDS tile `tile` and the
+// nx-entry twiddle table `tw` are the caller's; no trailing barrier.
+template <int M, int NB, int NT, bool GL_LDS, class GL, class OUT>
+__device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R, M, NB, false, 0> tile,
+                                          OUT &out)
 {
-    XFwdArgs a = a0;
-    if (a.batch) {
-        const ProbPtrs &q = a.batch[blockIdx.y];
-        a.f = q.f;
-        a.p = q.p;
-        a.S = q.S;
-        if (a.partials) a.partials = q.partials;
-        a.sum_f = q.scal + 1;
-    }
-    using C = XCfg<M>;
-    constexpr int NB = C::NB, NT = C::NT, NX = 2 * M;
-    using Tile = LdsTile<R, M, NB, false, C::PAD>;
-    __shared__ Cx<R> s_tile[Tile::elems];
-    __shared__ Cx<R> s_tw[NX];
-    static_assert(sizeof(Cx<R>) * Tile::elems >= 3 * (NT / 64) * sizeof(double), "");
-
-    const int nrows = a.ny * a.nz;
-    const int row0 = block_order(blockIdx.x, gridDim.x, a.reverse) * NB;
-    load_table(s_tw, (const Cx<R> *)a.tw, NX);
-    __syncthreads();
-
-    const double mu = (RES && a.sum_f) ? (*a.sum_f) * a.inv_n : 0.0;
-    // plain input: acc0 = sum f; residual: sum r^2, sum (f - mu)^2, sum p
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-    auto gload = [&](int b, int n) -> Cx<R> {
-        const int row = row0 + b;
-        if (row >= nrows) return {R(0), R(0)};
-        const size_t roff = (size_t)row * NX;
-        const double2 fv = *(const double2 *)(a.f + roff + 2 * n);
-        if constexpr (!RES) {
-            acc0 += fv.x + fv.y;
-            return {R(fv.x), R(fv.y)};
-        }
-        const int j = row % a.ny, k = row / a.ny;
-        const double *pr = a.p + roff;
-        const double2 pc = *(const double2 *)(pr + 2 * n);
-        const double pl = pr[(2 * n + NX - 1) % NX];
-        const double pq = pr[(2 * n + 2) % NX];
-        const int jm = (j == 0) ? a.ny - 1 : j - 1;
-        const int jp = (j == a.ny - 1) ? 0 : j + 1;
-        int km, kp;
-        if (a.bc_z == 0) {
-            km = (k == 0) ? a.nz - 1 : k - 1;
-            kp = (k == a.nz - 1) ? 0 : k + 1;
-        } else {  // mirrored ghost at the walls
-            km = (k == 0) ? 0 : k - 1;
-            kp = (k == a.nz - 1) ? k : k + 1;
-        }
-        const size_t plane = (size_t)a.ny * NX;
-        const double2 ps = *(const double2 *)(a.p + (size_t)k * plane + (size_t)jm * NX + 2 * n);
-        const double2 pn = *(const double2 *)(a.p + (size_t)k * plane + (size_t)jp * NX + 2 * n);
-        const double2 pd = *(const double2 *)(a.p + (size_t)km * plane + (size_t)j * NX + 2 * n);
-        const double2 pu = *(const double2 *)(a.p + (size_t)kp * plane + (size_t)j * NX + 2 * n);
-        const double l0 = a.ax * (pc.y - 2.0 * pc.x + pl) + a.ay * (pn.x - 2.0 * pc.x + ps.x) +
-                          a.az * (pu.x - 2.0 * pc.x + pd.x);
-        const double l1 = a.ax * (pq - 2.0 * pc.y + pc.x) + a.ay * (pn.y - 2.0 * pc.y + ps.y) +
-                          a.az * (pu.y - 2.0 * pc.y + pd.y);
-        const double f0 = fv.x - mu, f1 = fv.y - mu;
-        const double r0 = f0 - l0, r1 = f1 - l1;
-        acc0 += r0 * r0 + r1 * r1;
-        acc1 += f0 * f0 + f1 * f1;
-        acc2 += pc.x + pc.y;
-        return {R(r0), R(r1)};
-    };
-    Tile tile{s_tile};
     auto lstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
-    Cx<R> *S = (Cx<R> *)a.S;
     constexpr RPlan pl = make_rplan(M);
     if constexpr (pl.count >= 2) {
         // all passes but the last, then the last pass with the split fused
-        fft_passes<R, M, NB, NT, false, C::PAD, false, 0, pl.count - 1, 0>(s_tw, 2, gload, lstore,
-                                                                           tile);
+        fft_passes<R, M, NB, NT, false, 0, GL_LDS, 0, pl.count - 1, 0>(tw, 2, gload, lstore, tile);
         __syncthreads();
         constexpr int RAD = pl.r[pl.count - 1];
         constexpr int NJ = M / RAD;
@@ -198,17 +117,16 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
             }
 #pragma unroll
             for (int r = 1; r < RAD; ++r) {
-                v1[r] = cmul(v1[r], s_tw[2 * r * j1]);
-                v2[r] = cmul(v2[r], s_tw[2 * r * j2]);
+                v1[r] = cmul(v1[r], tw[2 * r * j1]);
+                v2[r] = cmul(v2[r], tw[2 * r * j2]);
             }
             Bfly<R, RAD>::run(v1);
             Bfly<R, RAD>::run(v2);
-            const int row = row0 + b;
-            if (row >= nrows) continue;
-            Cx<R> *Sr = S + (size_t)row * M;
+            Cx<R> *Sr = out(b);
+            if (!Sr) continue;
             auto emit = [&](int m, Cx<R> zm, Cx<R> zc) {
                 Cx<R> xm, xc;
-                split_pair(zm, zc, s_tw[m], xm, xc);
+                split_pair(zm, zc, tw[m], xm, xc);
                 Sr[m] = xm;
                 if (2 * m != M) Sr[M - m] = xc;
             };
@@ -228,34 +146,158 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
             }
         }
     } else {
-        fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, lstore, tile);
+        fft_tile<R, M, NB, NT, false, 0, GL_LDS>(tw, 2, gload, lstore, tile);
         __syncthreads();
         // split the M-point spectrum into the half spectrum of the real rows
         for (int u = threadIdx.x; u < NB * M; u += NT) {
             const int b = u / M, m = u % M;
-            const int row = row0 + b;
-            if (row >= nrows) continue;
+            Cx<R> *Sr = out(b);
+            if (!Sr) continue;
             const Cx<R> zm = tile.at(b, m);
             if (m == 0) {
-                S[(size_t)row * M] = {zm.re + zm.im, zm.re - zm.im};
+                Sr[0] = {zm.re + zm.im, zm.re - zm.im};
             } else {
                 Cx<R> xm, xc;
-                split_pair(zm, tile.at(b, M - m), s_tw[m], xm, xc);
-                S[(size_t)row * M + m] = xm;
+                split_pair(zm, tile.at(b, M - m), tw[m], xm, xc);
+                Sr[m] = xm;
             }
         }
     }
+}
+
+// Plain forward pass: x rows of f; optional per-workgroup sum of f.
+template <int M>
+__global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
+{
+    XFwdArgs a = a0;
+    if (a.batch) {
+        const ProbPtrs &q = a.batch[blockIdx.y];
+        a.f = q.f;
+        a.S = q.S;
+        if (a.partials) a.partials = q.partials;
+    }
+    using C = XCfg<M>;
+    constexpr int NB = C::NB, NT = C::NT, NX = 2 * M;
+    using Tile = LdsTile<R, M, NB, false, 0>;
+    __shared__ Cx<R> s_tile[Tile::elems];
+    __shared__ Cx<R> s_tw[NX];
+    static_assert(sizeof(Cx<R>) * Tile::elems >= 3 * (NT / 64) * sizeof(double), "");
+
+    const int nrows = a.ny * a.nz;
+    const int row0 = block_order(blockIdx.x, gridDim.x, a.reverse) * NB;
+    load_table(s_tw, (const Cx<R> *)a.tw, NX);
+    __syncthreads();
+
+    double acc0 = 0.0;
+    Tile tile{s_tile};
+    auto gload = [&](int b, int n) -> Cx<R> {
+        const int row = row0 + b;
+        if (row >= nrows) return {R(0), R(0)};
+        const double2 fv = *(const double2 *)(a.f + (size_t)row * NX + 2 * n);
+        acc0 += fv.x + fv.y;
+        return {R(fv.x), R(fv.y)};
+    };
+    Cx<R> *S = (Cx<R> *)a.S;
+    auto out = [&](int b) -> Cx<R> * {
+        const int row = row0 + b;
+        return row < nrows ? S + (size_t)row * M : nullptr;
+    };
+    x_forward<M, NB, NT, false>(s_tw, gload, tile, out);
 
     if (a.partials) {
         // the reduction scratch reuses the tile once every wave is done with it
         double *s_red = (double *)s_tile;
+        double z1 = 0.0, z2 = 0.0;
         __syncthreads();
-        block_sum3(acc0, acc1, acc2, s_red);
+        block_sum3(acc0, z1, z2, s_red);
         if (threadIdx.x == 0) {
             a.partials[4 * blockIdx.x] = acc0;
-            a.partials[4 * blockIdx.x + 1] = acc1;
-            a.partials[4 * blockIdx.x + 2] = acc2;
+            a.partials[4 * blockIdx.x + 1] = 0.0;
+            a.partials[4 * blockIdx.x + 2] = 0.0;
         }
+    }
+}
+
+// Residual forward pass of the iterative refinement: the FP64 residual
+// r = (f - mu) - L p of TJ y-rows is evaluated plane by plane with the 2.5-D
+// march of stencil.hpp, rounded once to the transform precision, packed as
+// z[h] = r[2h] + i r[2h+1] into the LDS tile (which aliases the march's plane
+// tile) and transformed in place; per-workgroup FP64 sums of r^2,
+// (f - mu)^2 and p go to `partials`.  r never touches HBM.
+constexpr int XR_NT = 256;
+
+template <int M>
+__global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
+{
+    XFwdArgs a = a0;
+    if (a.batch) {
+        const ProbPtrs &q = a.batch[blockIdx.y];
+        a.f = q.f;
+        a.p = q.p;
+        a.S = q.S;
+        a.partials = q.partials;
+        a.sum_f = q.scal + 1;
+    }
+    constexpr int TJ = march_rows(M), NT = XR_NT, NX = 2 * M;
+    using Mar = PlaneMarch<M, TJ, NT>;
+    using Tile = LdsTile<R, M, TJ, false, 0>;
+    constexpr size_t PLANE_B = sizeof(double2) * (TJ + 2) * M;
+    constexpr size_t FFT_B = sizeof(Cx<R>) * Tile::elems;
+    __shared__ __align__(16) char s_buf[PLANE_B > FFT_B ? PLANE_B : FFT_B];
+    __shared__ Cx<R> s_tw[NX];
+    __shared__ double s_red[3 * (NT / 64)];
+
+    const int njb = march_jblocks(a.ny, TJ);
+    const int bid = block_order(blockIdx.x, gridDim.x, a.reverse);
+    const int jb = bid % njb, kb = bid / njb;
+    const int k0 = kb * MARCH_PLANES;
+    const int k1 = k0 + MARCH_PLANES < a.nz ? k0 + MARCH_PLANES : a.nz;
+
+    Mar m;
+    m.f = a.f;
+    m.p = a.p;
+    m.ax = a.ax;
+    m.ay = a.ay;
+    m.az = a.az;
+    m.mu = a.sum_f ? (*a.sum_f) * a.inv_n : 0.0;
+    m.tile = (double2(*)[M])s_buf;
+    m.setup(jb, a.ny, a.nz, a.bc_z);
+    load_table(s_tw, (const Cx<R> *)a.tw, NX);
+    m.start(k0);
+
+    Tile tile{(Cx<R> *)s_buf};
+    Cx<R> *S = (Cx<R> *)a.S;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        __syncthreads();  // the previous plane's transform is done with the tile
+        Cx<R> rr[Mar::PER];
+        auto sink = [&](int q, int, int, double r0, double r1, double f0, double f1, double2 c) {
+            acc0 += r0 * r0 + r1 * r1;
+            acc1 += f0 * f0 + f1 * f1;
+            acc2 += c.x + c.y;
+            rr[q] = {R(r0), R(r1)};
+        };
+        m.step(k, sink);
+        __syncthreads();  // the march is done reading the plane tile
+#pragma unroll
+        for (int q = 0; q < Mar::PER; ++q) {
+            if (m.valid(q)) {
+                const int e = m.elem(q), t = e / M, h = e - t * M;
+                tile.at(t, h) = rr[q];
+            }
+        }
+        __syncthreads();
+        auto gload = [&](int b, int n) -> Cx<R> { return tile.at(b, n); };
+        const size_t rowk = (size_t)k * a.ny + m.j0;
+        const int V = m.V;
+        auto out = [&](int b) -> Cx<R> * { return b < V ? S + (rowk + b) * M : nullptr; };
+        x_forward<M, TJ, NT, true>(s_tw, gload, tile, out);
+    }
+    block_sum3(acc0, acc1, acc2, s_red);
+    if (threadIdx.x == 0) {
+        a.partials[4 * blockIdx.x] = acc0;
+        a.partials[4 * blockIdx.x + 1] = acc1;
+        a.partials[4 * blockIdx.x + 2] = acc2;
     }
 }
 
@@ -374,15 +416,25 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
     }
 }
 
+template <int M> static int blocks_x(int ny, int nz, int residual)
+{
+    if (residual) return march_jblocks(ny, march_rows(M)) * march_kblocks(nz);
+    return (ny * nz + XCfg<M>::NB - 1) / XCfg<M>::NB;
+}
+
 template <int M> static int run_x_fwd(const XFwdArgs &a, hipStream_t s)
 {
-    const int nrows = a.ny * a.nz;
-    const int nb = (nrows + XCfg<M>::NB - 1) / XCfg<M>::NB;
+    const int nb = blocks_x<M>(a.ny, a.nz, a.residual);
     const dim3 grid(nb, a.batch ? a.nbatch : 1);
-    if (a.residual)
-        hipLaunchKernelGGL((k_x_fwd<M, true>), grid, dim3(XCfg<M>::NT), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_x_fwd<M, false>), grid, dim3(XCfg<M>::NT), 0, s, a);
+    if (a.residual) {
+        // the refinement transforms its residual in FP32 only
+        if constexpr (sizeof(R) == 4)
+            hipLaunchKernelGGL(k_x_res<M>, grid, dim3(XR_NT), 0, s, a);
+        else
+            return -1;
+    } else {
+        hipLaunchKernelGGL(k_x_fwd<M>, grid, dim3(XCfg<M>::NT), 0, s, a);
+    }
     return (int)hipGetLastError();
 }
 
@@ -398,17 +450,13 @@ template <int M> static int run_x_inv(const XInvArgs &a, hipStream_t s)
     return (int)hipGetLastError();
 }
 
-template <int M> static int blocks_x(int ny, int nz)
-{
-    return (ny * nz + XCfg<M>::NB - 1) / XCfg<M>::NB;
-}
 
 }  // namespace PK_NS
 using namespace PK_NS;
 
 #define PK_CASE_FWD(N) case N: return run_x_fwd<N>(a, s);
 #define PK_CASE_INV(N) case N: return run_x_inv<N>(a, s);
-#define PK_CASE_BLK(N) case N: return blocks_x<N>(ny, nz);
+#define PK_CASE_BLK(N) case N: return blocks_x<N>(ny, nz, residual);
 
 int PK_SUFFIX(launch_x_fwd)(const XFwdArgs &a, hipStream_t s)
 {
@@ -420,7 +468,7 @@ int PK_SUFFIX(launch_x_inv)(const XInvArgs &a, hipStream_t s)
     switch (a.nx / 2) { PK_X_LENGTHS(PK_CASE_INV) default: return -1; }
 }
 
-int PK_SUFFIX(x_fwd_blocks)(int nx, int ny, int nz)
+int PK_SUFFIX(x_fwd_blocks)(int nx, int ny, int nz, int residual)
 {
     switch (nx / 2) { PK_X_LENGTHS(PK_CASE_BLK) default: return -1; }
 }

@@ -1,0 +1,178 @@
+// stencil.hpp -- FP64 residual of the discrete Poisson equation on the
+// marker-and-cell grid, r = (f - mean f) - L p, with L the 7-point operator
+// of FluTAS Section 3.3.1: periodic in x and y; in z periodic, or with the
+// mirrored ghost value at the walls (zero normal gradient on the wall face).
+//
+// 2.5-D blocking.  A workgroup owns TJ consecutive y-rows (all of x) and
+// marches up a range of z-planes.  Each thread keeps p at planes k-1, k, k+1
+// of its points in registers, so every p value is read from memory once per
+// plane range; the plane-k tile plus one halo row on each side in y is staged
+// in LDS, from which the x and y neighbours are taken.  Reads per output row:
+// f, p(k+1) and 2/TJ halo rows, against seven row-reads for a plain stencil.
+// Points are handled in pairs (2h, 2h+1) as double2.
+#pragma once
+#include "common.hpp"
+
+namespace pk {
+
+// rows per workgroup for rows of M pairs: about 2048 pairs per plane tile
+constexpr int march_rows(int M)
+{
+    const int t = 2048 / M;
+    return t < 1 ? 1 : (t > 16 ? 16 : t);
+}
+constexpr int MARCH_PLANES = 8;  // z-planes per workgroup
+
+// workgroups of one problem: (y-row blocks) x (z-plane ranges), plane-major
+__host__ __device__ constexpr int march_jblocks(int ny, int tj) { return (ny + tj - 1) / tj; }
+__host__ __device__ constexpr int march_kblocks(int nz) { return (nz + MARCH_PLANES - 1) / MARCH_PLANES; }
+
+template <int M, int TJ, int NT>
+struct PlaneMarch {
+    static constexpr int NX = 2 * M;
+    static constexpr int E = TJ * M;  // pairs per plane tile
+    static constexpr int PER = (E + NT - 1) / NT;
+    static constexpr bool EXACT = (E % NT) == 0;
+
+    const double *f, *p;
+    int ny, nz, bc_z;
+    double ax, ay, az, mu;
+    int j0, V;     // first y-row and number of valid rows of this block
+    int jm, jn;    // halo rows: (j0 - 1) mod ny and (j0 + V) mod ny
+    size_t plane;  // ny * NX
+    double2 (*tile)[M];  // LDS, TJ + 2 rows
+    double2 pd[PER], pc[PER];
+
+    __device__ __forceinline__ int elem(int q) const { return threadIdx.x + q * NT; }
+    __device__ __forceinline__ bool valid(int q) const
+    {
+        const int e = elem(q);
+        return (EXACT || e < E) && e / M < V;
+    }
+    // offset of element q within a plane
+    __device__ __forceinline__ int roff(int q) const
+    {
+        const int e = elem(q), t = e / M, h = e - t * M;
+        return (j0 + t) * NX + 2 * h;
+    }
+    __device__ __forceinline__ int kdown(int k) const
+    {
+        return k > 0 ? k - 1 : (bc_z == 0 ? nz - 1 : 0);
+    }
+    __device__ __forceinline__ int kup(int k) const
+    {
+        return k < nz - 1 ? k + 1 : (bc_z == 0 ? 0 : k);
+    }
+
+    __device__ __forceinline__ void setup(int jb, int ny_, int nz_, int bc_z_)
+    {
+        ny = ny_;
+        nz = nz_;
+        bc_z = bc_z_;
+        j0 = jb * TJ;
+        V = ny - j0 < TJ ? ny - j0 : TJ;
+        jm = j0 == 0 ? ny - 1 : j0 - 1;
+        jn = j0 + V == ny ? 0 : j0 + V;
+        plane = (size_t)ny * NX;
+    }
+
+    // p at planes k0-1 and k0 into registers.  Elements past the last row
+    // of the grid load from the start of the plane (in bounds, never used):
+    // branch-free loads.
+    __device__ __forceinline__ void start(int k0)
+    {
+        const double *pdn = p + (size_t)kdown(k0) * plane;
+        const double *pcn = p + (size_t)k0 * plane;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const bool ok = valid(q);
+            const int o = ok ? roff(q) : 0;
+            pd[q] = *(const double2 *)(pdn + o);
+            pc[q] = *(const double2 *)(pcn + o);
+        }
+    }
+
+    // Residual at plane k: sink(q, t, h, r0, r1, f0, f1, pc) for every valid
+    // element (row j0 + t, pair h).  The caller syncs before the next step
+    // (the LDS tile is rewritten).
+    template <class Sink>
+    __device__ __forceinline__ void step(int k, Sink &sink)
+    {
+        const double *pup = p + (size_t)kup(k) * plane;
+        const double *fk = f + (size_t)k * plane;
+        const double *pk_ = p + (size_t)k * plane;
+        double2 pu[PER], fv[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const bool ok = valid(q);
+            const int o = ok ? roff(q) : 0;
+            pu[q] = *(const double2 *)(pup + o);
+            fv[q] = *(const double2 *)(fk + o);
+        }
+        for (int h = threadIdx.x; h < M; h += NT) {
+            tile[0][h] = *(const double2 *)(pk_ + (size_t)jm * NX + 2 * h);
+            tile[V + 1][h] = *(const double2 *)(pk_ + (size_t)jn * NX + 2 * h);
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (valid(q)) {
+                const int e = elem(q), t = e / M, h = e - t * M;
+                tile[t + 1][h] = pc[q];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (valid(q)) {
+                const int e = elem(q), t = e / M, h = e - t * M;
+                const double2 ps = tile[t][h], pn = tile[t + 2][h];
+                const double pl = tile[t + 1][h == 0 ? M - 1 : h - 1].y;
+                const double pq = tile[t + 1][h == M - 1 ? 0 : h + 1].x;
+                const double2 c = pc[q], d = pd[q], u = pu[q];
+                const double l0 = ax * (c.y - 2.0 * c.x + pl) + ay * (pn.x - 2.0 * c.x + ps.x) +
+                                  az * (u.x - 2.0 * c.x + d.x);
+                const double l1 = ax * (pq - 2.0 * c.y + c.x) + ay * (pn.y - 2.0 * c.y + ps.y) +
+                                  az * (u.y - 2.0 * c.y + d.y);
+                const double f0 = fv[q].x - mu, f1 = fv[q].y - mu;
+                sink(q, t, h, f0 - l0, f1 - l1, f0, f1, c);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            pd[q] = pc[q];
+            pc[q] = pu[q];
+        }
+    }
+};
+
+// sum three doubles over the workgroup; thread 0 gets the totals (the
+// caller's `sh` holds 3 doubles per wavefront; the call syncs)
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *sh)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+        c += __shfl_down(c, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[3 * wid] = a;
+        sh[3 * wid + 1] = b;
+        sh[3 * wid + 2] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        a = 0.0;
+        b = 0.0;
+        c = 0.0;
+        for (int w = 0; w < nw; ++w) {
+            a += sh[3 * w];
+            b += sh[3 * w + 1];
+            c += sh[3 * w + 2];
+        }
+    }
+}
+
+}  // namespace pk
