@@ -430,13 +430,13 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials)
     char name[40];
     snprintf(name, sizeof name, residual ? "x_r2c_residual_%s" : "x_r2c_%s", tag(L.prec));
     const double bytes = (double)g.N * ((residual ? 16.0 : 8.0) + sb) * L.n;
+    int np = 0;
     int rc = timed(L.p, name, bytes,
-                   [&] { return launch_x_fwd(L.prec, a, nullptr, L.p->stream); });
+                   [&] { return launch_x_fwd(L.prec, a, &np, L.p->stream); });
     if (rc || !want_partials) return rc;
     // three sums per workgroup: plain input -> (sum f, 0, 0) into scal[1..3];
     // residual -> (sum r^2, sum fbar^2, sum p) into scal[2..4]
     const int off = residual ? 2 : 1;
-    const int np = residual ? g.nres : g.npart;
     return timed(L.p, "sum_partials", (double)np * 32.0 * L.n, [&] {
         return launch_sum_partials(L.one.partials, np, L.one.scal ? L.one.scal + off : nullptr,
                                    L.dev, L.n, off, L.p->stream);

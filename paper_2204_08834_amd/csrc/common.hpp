@@ -108,7 +108,8 @@ struct ZArgs {
     int variant;            // tile variant (0 = default; see the launchers)
 };
 
-// Launchers (return 0 on success, a hipError_t value otherwise).
+// Launchers (return 0 on success, a hipError_t value otherwise).  The forward
+// x pass reports the workgroups it launched (the partial sums it wrote).
 int launch_x_fwd(int prec, const XFwdArgs &a, int *nblocks_out, hipStream_t s);
 int launch_x_inv(int prec, const XInvArgs &a, hipStream_t s);
 int launch_y(int prec, const YArgs &a, hipStream_t s);

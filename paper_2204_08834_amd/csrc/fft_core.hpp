@@ -277,6 +277,49 @@ __device__ __forceinline__ void fft_passes(const Cx<R> *__restrict__ tw, int tws
                                                                     tile);
 }
 
+// Inputs of pass 0 held in registers, so that a workgroup can load the next
+// tile's inputs (prefetch) while it transforms the current one:
+//   load(gload)  : v <- inputs of this thread's pass-0 butterflies
+//   store(tile)  : pass-0 butterflies (no twiddles) -> LDS tile
+// after which fft_passes continues from pass 1.
+template <typename R, int N, int NB, int NT, bool LF, int PAD, int PV>
+struct Pass0Regs {
+    static constexpr RPlan pl = get_rplan(N, PV);
+    static constexpr int RAD = pl.r[0], NJ = N / RAD, NBF = NB * NJ;
+    static constexpr int PER = (NBF + NT - 1) / NT;
+    static constexpr bool EXACT = (NBF % NT) == 0;
+    Cx<R> v[PER][RAD];
+
+    template <class GL>
+    __device__ __forceinline__ void load(GL &gload)
+    {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int u = threadIdx.x + q * NT;
+            if (EXACT || u < NBF) {
+                const int b = LF ? (u % NB) : (u / NJ);
+                const int j = LF ? (u / NB) : (u % NJ);
+#pragma unroll
+                for (int r = 0; r < RAD; ++r) v[q][r] = gload(b, j + r * NJ);
+            }
+        }
+    }
+    __device__ __forceinline__ void store(LdsTile<R, N, NB, LF, PAD> tile)
+    {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int u = threadIdx.x + q * NT;
+            if (EXACT || u < NBF) {
+                const int b = LF ? (u % NB) : (u / NJ);
+                const int j = LF ? (u / NB) : (u % NJ);
+                Bfly<R, RAD>::run(v[q]);
+#pragma unroll
+                for (int r = 0; r < RAD; ++r) tile.at(b, j * RAD + r) = v[q][r];
+            }
+        }
+    }
+};
+
 // GL_LDS: gload reads the LDS tile itself (pass 0 then needs a barrier between
 // its loads and its stores).
 template <typename R, int N, int NB, int NT, bool LF, int PAD, bool GL_LDS, class GL, class GS>

@@ -7,8 +7,8 @@
 
 namespace pk {
 
-int launch_x_fwd_f32(const XFwdArgs &, hipStream_t);
-int launch_x_fwd_f64(const XFwdArgs &, hipStream_t);
+int launch_x_fwd_f32(const XFwdArgs &, hipStream_t, int *);
+int launch_x_fwd_f64(const XFwdArgs &, hipStream_t, int *);
 int launch_x_inv_f32(const XInvArgs &, hipStream_t);
 int launch_x_inv_f64(const XInvArgs &, hipStream_t);
 int launch_y_f32(const YArgs &, hipStream_t);
@@ -22,8 +22,7 @@ int x_fwd_blocks_f64(int, int, int, int);
 
 int launch_x_fwd(int prec, const XFwdArgs &a, int *nblocks_out, hipStream_t s)
 {
-    if (nblocks_out) *nblocks_out = x_fwd_blocks(prec, a.nx, a.ny, a.nz, a.residual);
-    return prec == P_F32 ? launch_x_fwd_f32(a, s) : launch_x_fwd_f64(a, s);
+    return prec == P_F32 ? launch_x_fwd_f32(a, s, nblocks_out) : launch_x_fwd_f64(a, s, nblocks_out);
 }
 int launch_x_inv(int prec, const XInvArgs &a, hipStream_t s)
 {

@@ -87,16 +87,22 @@ __device__ __forceinline__ void merge_pair(Cx<T> xm, Cx<T> xc, Cx<T> w, Cx<T> &z
 // GL_LDS), and the last pass writes the half spectra of the real rows through
 // out(b) (row pointer into S, null to skip the row).  LDS tile `tile` and the
 // nx-entry twiddle table `tw` are the caller's; no trailing barrier.
-template <int M, int NB, int NT, bool GL_LDS, class GL, class OUT>
+// P0 = 1: the tile already holds the output of pass 0 (Pass0Regs), the
+// transform continues from pass 1 (needs at least two passes).
+template <int M, int NB, int NT, bool GL_LDS, int P0 = 0, class GL, class OUT>
 __device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R, M, NB, false, 0> tile,
                                           OUT &out)
 {
     auto lstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
     constexpr RPlan pl = make_rplan(M);
+    static_assert(P0 == 0 || pl.count >= 2, "");
     if constexpr (pl.count >= 2) {
         // all passes but the last, then the last pass with the split fused
-        fft_passes<R, M, NB, NT, false, 0, GL_LDS, 0, pl.count - 1, 0>(tw, 2, gload, lstore, tile);
-        __syncthreads();
+        if constexpr (pl.count - 1 > P0) {
+            fft_passes<R, M, NB, NT, false, 0, GL_LDS, P0, pl.count - 1, 0>(tw, 2, gload, lstore,
+                                                                            tile);
+            __syncthreads();
+        }
         constexpr int RAD = pl.r[pl.count - 1];
         constexpr int NJ = M / RAD;
         static_assert(NJ == rplan_ns(pl, pl.count - 1) && NJ % 2 == 0, "pairing needs even NJ");
@@ -166,6 +172,10 @@ __device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R,
 }
 
 // Plain forward pass: x rows of f; optional per-workgroup sum of f.
+// Persistent: workgroup w transforms the row blocks w, w + G, w + 2G, ...
+// (G = gridDim.x) and loads the next block's pass-0 inputs into registers
+// right after it has stored the current block's pass 0, so the HBM reads of
+// block i+1 overlap the LDS passes and spectrum writes of block i.
 template <int M>
 __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
 {
@@ -184,25 +194,59 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
     static_assert(sizeof(Cx<R>) * Tile::elems >= 3 * (NT / 64) * sizeof(double), "");
 
     const int nrows = a.ny * a.nz;
-    const int row0 = block_order(blockIdx.x, gridDim.x, a.reverse) * NB;
+    const int nblk = (nrows + NB - 1) / NB;
     load_table(s_tw, (const Cx<R> *)a.tw, NX);
-    __syncthreads();
 
     double acc0 = 0.0;
     Tile tile{s_tile};
-    auto gload = [&](int b, int n) -> Cx<R> {
-        const int row = row0 + b;
-        if (row >= nrows) return {R(0), R(0)};
-        const double2 fv = *(const double2 *)(a.f + (size_t)row * NX + 2 * n);
-        acc0 += fv.x + fv.y;
-        return {R(fv.x), R(fv.y)};
-    };
     Cx<R> *S = (Cx<R> *)a.S;
-    auto out = [&](int b) -> Cx<R> * {
-        const int row = row0 + b;
-        return row < nrows ? S + (size_t)row * M : nullptr;
+    auto loader = [&](int row0) {
+        return [&, row0](int b, int n) -> Cx<R> {
+            const int row = row0 + b;
+            if (row >= nrows) return {R(0), R(0)};
+            const double2 fv = *(const double2 *)(a.f + (size_t)row * NX + 2 * n);
+            acc0 += fv.x + fv.y;
+            return {R(fv.x), R(fv.y)};
+        };
     };
-    x_forward<M, NB, NT, false>(s_tw, gload, tile, out);
+    constexpr RPlan pl = make_rplan(M);
+    if constexpr (pl.count >= 2) {
+        Pass0Regs<R, M, NB, NT, false, 0, 0> in;
+        int blk = blockIdx.x;
+        if (blk < nblk) {
+            auto gl = loader(block_order(blk, nblk, a.reverse) * NB);
+            in.load(gl);
+        }
+        for (; blk < nblk; blk += gridDim.x) {
+            const int row0 = block_order(blk, nblk, a.reverse) * NB;
+            __syncthreads();  // tw table loaded / previous block done with the tile
+            in.store(tile);
+            const int nxt = blk + gridDim.x;
+            if (nxt < nblk) {
+                auto gl = loader(block_order(nxt, nblk, a.reverse) * NB);
+                in.load(gl);
+            }
+            __syncthreads();
+            auto out = [&](int b) -> Cx<R> * {
+                const int row = row0 + b;
+                return row < nrows ? S + (size_t)row * M : nullptr;
+            };
+            auto gnone = [&](int, int) -> Cx<R> { return {R(0), R(0)}; };
+            x_forward<M, NB, NT, false, 1>(s_tw, gnone, tile, out);
+        }
+    } else {
+        __syncthreads();
+        for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+            const int row0 = block_order(blk, nblk, a.reverse) * NB;
+            auto gl = loader(row0);
+            auto out = [&](int b) -> Cx<R> * {
+                const int row = row0 + b;
+                return row < nrows ? S + (size_t)row * M : nullptr;
+            };
+            x_forward<M, NB, NT, false>(s_tw, gl, tile, out);
+            __syncthreads();
+        }
+    }
 
     if (a.partials) {
         // the reduction scratch reuses the tile once every wave is done with it
@@ -416,15 +460,44 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
     }
 }
 
+// row blocks of the plain pass (an upper bound of its workgroup count), or
+// the workgroups of the residual pass
 template <int M> static int blocks_x(int ny, int nz, int residual)
 {
     if (residual) return march_jblocks(ny, march_rows(M)) * march_kblocks(nz);
     return (ny * nz + XCfg<M>::NB - 1) / XCfg<M>::NB;
 }
 
-template <int M> static int run_x_fwd(const XFwdArgs &a, hipStream_t s)
+// workgroups of the persistent plain pass: as many as are resident on the
+// device at once (shared among the problems of a batched launch)
+template <int M> static int grid_x_fwd(int nblk, int nbatch)
 {
-    const int nb = blocks_x<M>(a.ny, a.nz, a.residual);
+    static int resident[64] = {0};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int &r = resident[dev & 63];
+    if (r == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_x_fwd<M>, XCfg<M>::NT, 0) !=
+                hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            per_cu < 1 || cus < 1) {
+            (void)hipGetLastError();
+            per_cu = 1;
+            cus = 256;
+        }
+        r = per_cu * cus;
+    }
+    int g = r / (nbatch > 0 ? nbatch : 1);
+    g = g < 1 ? 1 : g;
+    return g < nblk ? g : nblk;
+}
+
+template <int M> static int run_x_fwd(const XFwdArgs &a, hipStream_t s, int *nblocks_out)
+{
+    int nb = blocks_x<M>(a.ny, a.nz, a.residual);
+    if (!a.residual) nb = grid_x_fwd<M>(nb, a.batch ? a.nbatch : 1);
+    if (nblocks_out) *nblocks_out = nb;
     const dim3 grid(nb, a.batch ? a.nbatch : 1);
     if (a.residual) {
         // the refinement transforms its residual in FP32 only
@@ -454,11 +527,11 @@ template <int M> static int run_x_inv(const XInvArgs &a, hipStream_t s)
 }  // namespace PK_NS
 using namespace PK_NS;
 
-#define PK_CASE_FWD(N) case N: return run_x_fwd<N>(a, s);
+#define PK_CASE_FWD(N) case N: return run_x_fwd<N>(a, s, nblocks_out);
 #define PK_CASE_INV(N) case N: return run_x_inv<N>(a, s);
 #define PK_CASE_BLK(N) case N: return blocks_x<N>(ny, nz, residual);
 
-int PK_SUFFIX(launch_x_fwd)(const XFwdArgs &a, hipStream_t s)
+int PK_SUFFIX(launch_x_fwd)(const XFwdArgs &a, hipStream_t s, int *nblocks_out)
 {
     switch (a.nx / 2) { PK_X_LENGTHS(PK_CASE_FWD) default: return -1; }
 }
