@@ -145,6 +145,28 @@ int poisson_batch_solve(poisson_plan plan, const double *const *rhs, double *con
 const char *poisson_error_string(int code);
 
 /*
+ * Where the refinement loop is driven (the batched schedule and the
+ * refinement control of FluTAS Section 3.3.1 as built here):
+ *   0 (default) host-driven: after each residual the host reads the norms
+ *     back (one synchronisation per iteration) and launches only the passes
+ *     the running problems need;
+ *   1 captured graph: the first solve and a fixed number of loop segments
+ *     (residual evaluation, device-side convergence decision, correction)
+ *     are captured once into a hipGraph and replayed; every pass of a
+ *     segment is gated per problem by a device control record, so problems
+ *     that converge early skip the rest.  Further segment-only graphs are
+ *     launched while a problem still runs (at most max_refine corrections).
+ *     One synchronisation per graph launch;
+ *   2 the launch sequence of mode 1 issued eagerly (no capture), for testing.
+ * Modes 1 and 2 run on a stream owned by the plan, ordered after the plan's
+ * stream on entry and before it on return with events.  Same results as mode 0
+ * up to the order of the per-problem convergence decisions (identical for a
+ * single problem).  Per-pass timing (below) disables the capture of mode 1.
+ * Returns POISSON_ERR_INVALID_ARG for a null plan or another mode.
+ */
+int poisson_plan_set_graph(poisson_plan plan, int mode);
+
+/*
  * Per-pass timing (tracing).  When enabled, every kernel launch of a solve is
  * bracketed by hipEvents on the plan's stream; the accumulated time and the
  * algorithmic HBM bytes of each pass are read back with

@@ -212,6 +212,16 @@ struct poisson_plan_s {
     std::unique_ptr<PinnedBuf> host_scalars;
     std::unique_ptr<PinnedBuf> host_ptrs;    // ProbPtrs staging for batched launches
     hipEvent_t ptrs_done = nullptr;          // last staging upload has been consumed
+    hipStream_t ls = nullptr;                // stream the passes of the current solve use
+    // device-side refinement loop (poisson_plan_set_graph): 0 host-driven loop,
+    // 1 captured graphs, 2 the same launch sequence issued eagerly
+    int graph_mode = 0;
+    std::shared_ptr<DevBuf> ctrl;            // NCTRL ints per problem
+    std::unique_ptr<PinnedBuf> host_ctrl;
+    hipStream_t gstream = nullptr;           // plan-owned stream of the device loop
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};  // [0] solve + loop segments, [1] segments
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
     bool timing = false;
     std::vector<Timed> pending;
     std::vector<hipEvent_t> event_pool;
@@ -225,6 +235,19 @@ struct poisson_plan_s {
         }
         for (auto e : event_pool) (void)hipEventDestroy(e);
         if (ptrs_done) (void)hipEventDestroy(ptrs_done);
+        drop_graphs();
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (gstream) (void)hipStreamDestroy(gstream);
+    }
+    void drop_graphs()
+    {
+        for (int i = 0; i < 2; ++i) {
+            if (gexec[i]) (void)hipGraphExecDestroy(gexec[i]);
+            if (graph[i]) (void)hipGraphDestroy(graph[i]);
+            gexec[i] = nullptr;
+            graph[i] = nullptr;
+        }
     }
 };
 
@@ -353,9 +376,9 @@ int timed(poisson_plan p, const char *name, double bytes, F &&launch)
             return POISSON_ERR_HIP;
         }
     }
-    (void)hipEventRecord(t.e0, p->stream);
+    (void)hipEventRecord(t.e0, p->ls);
     int e = launch();
-    (void)hipEventRecord(t.e1, p->stream);
+    (void)hipEventRecord(t.e1, p->ls);
     p->pending.push_back(t);
     return e ? hip_fail(name, e) : POISSON_OK;
 }
@@ -363,7 +386,7 @@ int timed(poisson_plan p, const char *name, double bytes, F &&launch)
 void collect_timing(poisson_plan p)
 {
     if (p->pending.empty()) return;
-    (void)hipStreamSynchronize(p->stream);
+    (void)hipEventSynchronize(p->pending.back().e1);
     for (auto &t : p->pending) {
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, t.e0, t.e1);
@@ -403,9 +426,10 @@ struct LSet {
     const ProbPtrs *dev;
     int n;
     ProbPtrs one;
+    int gate = 0;  // control slot gating the passes (device-side loop)
 };
 
-int pass_x_fwd(LSet &L, bool residual, bool want_partials)
+int pass_x_fwd(LSet &L, bool residual, bool want_partials, bool sum = true)
 {
     Group &g = *L.g;
     const double sb = L.prec == P_F32 ? 4.0 : 8.0;
@@ -427,25 +451,26 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials)
     a.sum_f = L.one.scal ? L.one.scal + 1 : nullptr;
     a.inv_n = 1.0 / (double)g.N;
     a.residual = residual ? 1 : 0;
+    a.gate = L.gate;
     char name[40];
     snprintf(name, sizeof name, residual ? "x_r2c_residual_%s" : "x_r2c_%s", tag(L.prec));
     const double bytes = (double)g.N * ((residual ? 16.0 : 8.0) + sb) * L.n;
     int np = 0;
     int rc = timed(L.p, name, bytes,
-                   [&] { return launch_x_fwd(L.prec, a, &np, L.p->stream); });
-    if (rc || !want_partials) return rc;
+                   [&] { return launch_x_fwd(L.prec, a, &np, L.p->ls); });
+    if (rc || !want_partials || !sum) return rc;
     // three sums per workgroup: plain input -> (sum f, 0, 0) into scal[1..3];
     // residual -> (sum r^2, sum fbar^2, sum p) into scal[2..4]
     const int off = residual ? 2 : 1;
     return timed(L.p, "sum_partials", (double)np * 32.0 * L.n, [&] {
         return launch_sum_partials(L.one.partials, np, L.one.scal ? L.one.scal + off : nullptr,
-                                   L.dev, L.n, off, L.p->stream);
+                                   L.dev, L.n, off, L.p->ls);
     });
 }
 
 // residual and its norms without the transform (a convergence check that
 // does not write the spectrum): sums into scal[2..4] like the residual x pass
-int pass_residual_check(LSet &L)
+int pass_residual_check(LSet &L, bool sum = true)
 {
     Group &g = *L.g;
     XFwdArgs a{};
@@ -464,12 +489,13 @@ int pass_residual_check(LSet &L)
     a.sum_f = L.one.scal ? L.one.scal + 1 : nullptr;
     a.inv_n = 1.0 / (double)g.N;
     a.residual = 1;
+    a.gate = L.gate;
     int rc = timed(L.p, "residual_check_f64", (double)g.N * 16.0 * L.n,
-                   [&] { return launch_residual_check(a, nullptr, L.p->stream); });
-    if (rc) return rc;
+                   [&] { return launch_residual_check(a, nullptr, L.p->ls); });
+    if (rc || !sum) return rc;
     return timed(L.p, "sum_partials", (double)g.ncheck * 32.0 * L.n, [&] {
         return launch_sum_partials(L.one.partials, g.ncheck, L.one.scal ? L.one.scal + 2 : nullptr,
-                                   L.dev, L.n, 2, L.p->stream);
+                                   L.dev, L.n, 2, L.p->ls);
     });
 }
 
@@ -479,11 +505,11 @@ int pass_y(LSet &L, bool inverse)
     if (g.d.ny == 1) return POISSON_OK;  // a length-1 transform is the identity
     // the forward y pass follows the x pass, which wrote the planes in order
     YArgs a{L.dev, L.n, L.one.S, g.tab.twy[L.prec == P_F32 ? 1 : 0]->p, g.M, g.d.ny, g.d.nz,
-            inverse ? 1 : 0, (!inverse && reversed_orders()) ? 1 : 0};
+            inverse ? 1 : 0, (!inverse && reversed_orders()) ? 1 : 0, L.gate};
     char name[40];
     snprintf(name, sizeof name, inverse ? "y_inv_%s" : "y_fwd_%s", tag(L.prec));
     const double bytes = (double)g.N * 2.0 * (L.prec == P_F32 ? 4.0 : 8.0) * L.n;
-    return timed(L.p, name, bytes, [&] { return launch_y(L.prec, a, L.p->stream); });
+    return timed(L.p, name, bytes, [&] { return launch_y(L.prec, a, L.p->ls); });
 }
 
 int pass_z(LSet &L)
@@ -507,14 +533,15 @@ int pass_z(LSet &L)
     a.inv_nxny = 1.0 / ((double)g.d.nx * g.d.ny);
     a.inv_ntot = 1.0 / (double)g.N;
     a.variant = g.zwalls_variant;
+    a.gate = L.gate;
     const double bytes = (double)g.N * 2.0 * (L.prec == P_F32 ? 4.0 : 8.0) * L.n;
     char name[40];
     if (g.d.bc_z == POISSON_BC_NEUMANN) {
         snprintf(name, sizeof name, "z_walls_%s", tag(L.prec));
-        return timed(L.p, name, bytes, [&] { return launch_z_walls(L.prec, a, L.p->stream); });
+        return timed(L.p, name, bytes, [&] { return launch_z_walls(L.prec, a, L.p->ls); });
     }
     snprintf(name, sizeof name, "z_periodic_%s", tag(L.prec));
-    return timed(L.p, name, bytes, [&] { return launch_z_periodic(L.prec, a, L.p->stream); });
+    return timed(L.p, name, bytes, [&] { return launch_z_periodic(L.prec, a, L.p->ls); });
 }
 
 int pass_x_inv(LSet &L, bool accumulate)
@@ -523,14 +550,14 @@ int pass_x_inv(LSet &L, bool accumulate)
     // the inverse x pass follows the inverse y pass, which wrote the planes in order
     XInvArgs a{L.dev, L.n, L.one.S, L.one.p, g.tab.twx[L.prec == P_F32 ? 1 : 0]->p, g.d.nx,
                g.d.ny, g.d.nz, accumulate ? 1 : 0, reversed_orders() ? 1 : 0, nullptr,
-               1.0 / (double)g.N};
+               1.0 / (double)g.N, L.gate};
     // the mean of p from the residual pass (batched launches redirect it)
     if (accumulate) a.sum_p = L.dev ? (const double *)g.partials->p : L.one.scal + 4;
     char name[40];
     snprintf(name, sizeof name, accumulate ? "x_c2r_accumulate_%s" : "x_c2r_%s", tag(L.prec));
     const double sb = L.prec == P_F32 ? 4.0 : 8.0;
     const double bytes = (double)g.N * (sb + (accumulate ? 16.0 : 8.0)) * L.n;
-    return timed(L.p, name, bytes, [&] { return launch_x_inv(L.prec, a, L.p->stream); });
+    return timed(L.p, name, bytes, [&] { return launch_x_inv(L.prec, a, L.p->ls); });
 }
 
 // transform of the right-hand side (or residual), z solve, inverse transform
@@ -556,9 +583,9 @@ int correction_passes(LSet &L)
 int read_scalars(poisson_plan p, int count)
 {
     hipError_t e = hipMemcpyAsync(p->host_scalars->p, p->scalars->p, NSCAL * sizeof(double) * count,
-                                  hipMemcpyDeviceToHost, p->stream);
+                                  hipMemcpyDeviceToHost, p->ls);
     if (e != hipSuccess) return hip_fail("scalar read-back", (int)e);
-    e = hipStreamSynchronize(p->stream);
+    e = hipStreamSynchronize(p->ls);
     if (e != hipSuccess) return hip_fail("stream synchronize", (int)e);
     return POISSON_OK;
 }
@@ -581,6 +608,7 @@ ProbPtrs problem_ptrs(poisson_plan p, const Group &g, int slot, const double *rh
               : (void *)((char *)g.S32->p + (size_t)g.N * 4 * slot);
     q.partials = (double *)g.partials->p + (size_t)g.part_stride * slot;
     q.scal = (double *)p->scalars->p + NSCAL * i;
+    q.ctrl = (int *)p->ctrl->p + NCTRL * i;
     return q;
 }
 
@@ -597,6 +625,7 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
     std::vector<LSet> sets(p->groups.size());
     std::vector<std::vector<int>> active(p->groups.size());
     ProbPtrs *staging = p->batched ? (ProbPtrs *)p->host_ptrs->p : nullptr;
+    p->ls = p->stream;
 
     // (re)write the device pointer arrays for the listed member slots
     auto stage = [&](int gi) -> int {
@@ -618,7 +647,7 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
         L.one = ProbPtrs{nullptr, nullptr, nullptr, nullptr, nullptr};
         if (L.n == 0) return POISSON_OK;
         hipError_t e = hipMemcpyAsync(g.ptrs->p, h, sizeof(ProbPtrs) * L.n,
-                                      hipMemcpyHostToDevice, p->stream);
+                                      hipMemcpyHostToDevice, p->ls);
         return e == hipSuccess ? POISSON_OK : hip_fail("pointer upload", (int)e);
     };
 
@@ -715,13 +744,191 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
                 out[i].rhs_mean =
                     prec == P_F64 ? hs[NSCAL * i] : hs[NSCAL * i + 1] / (double)g.N;
     }
-    if (p->batched && p->ptrs_done) (void)hipEventRecord(p->ptrs_done, p->stream);
+    if (p->batched && p->ptrs_done) (void)hipEventRecord(p->ptrs_done, p->ls);
 
     int first = rc;
     for (int i = 0; i < count; ++i) {
         if (rc) out[i].status = rc;
         if (!first && out[i].status) first = out[i].status;
         if (st) st[i] = out[i];
+    }
+    return first;
+}
+
+// ---------------------------------------------------------------------------
+// device-side refinement loop (poisson_plan_set_graph)
+// ---------------------------------------------------------------------------
+// Loop segments per graph: a residual evaluation and, when the control kernel
+// says so, one correction.  A problem that needs more corrections gets
+// further launches of the segment-only graph.
+constexpr int GRAPH_SEGMENTS = 2;
+
+// The launch sequence of the device-side loop.  head: control init and the
+// first solve; then GRAPH_SEGMENTS segments of
+//   full residual pass [C_FULL] | residual check [C_CHECK] | sums [C_EVAL]
+//   | control | full residual pass after a failed check [C_FIX]
+//   | y, z, y, accumulating x [C_CORRECT]
+int enqueue_device_sequence(poisson_plan p, std::vector<LSet> &sets, bool head)
+{
+    const bool refine = p->precision == POISSON_FP32_REFINE;
+    const int prec = internal_prec(p->precision);
+    int rc = POISSON_OK;
+    if (head) {
+        for (auto &L : sets) {
+            L.gate = 0;
+            if (refine && (rc = launch_ctrl_init(L.dev, L.n, p->ls)))
+                return hip_fail("control init", rc);
+            if ((rc = solve_passes(L, false, prec == P_F32))) return rc;
+        }
+    }
+    if (!refine) return POISSON_OK;
+    for (int seg = 0; seg < GRAPH_SEGMENTS; ++seg) {
+        for (auto &L : sets) {
+            Group &g = *L.g;
+            L.gate = C_FULL;
+            if ((rc = pass_x_fwd(L, true, true, false))) return rc;
+            L.gate = C_CHECK;
+            if ((rc = pass_residual_check(L, false))) return rc;
+            // both residual kernels run the same 2.5-D march grid (nres == ncheck)
+            rc = timed(p, "sum_partials", (double)g.ncheck * 32.0 * L.n, [&] {
+                return launch_sum_partials(nullptr, g.ncheck, nullptr, L.dev, L.n, 2, p->ls,
+                                           C_EVAL);
+            });
+            if (rc) return rc;
+            if ((rc = launch_refine_control(L.dev, L.n, p->rtol, p->max_refine, p->ls)))
+                return hip_fail("refinement control", rc);
+            L.gate = C_FIX;
+            if ((rc = pass_x_fwd(L, true, true, false))) return rc;
+            L.gate = C_CORRECT;
+            if ((rc = correction_passes(L))) return rc;
+            L.gate = 0;
+        }
+    }
+    return POISSON_OK;
+}
+
+int ensure_device_loop_objects(poisson_plan p)
+{
+    if (p->gstream) return POISSON_OK;
+    if (hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking) != hipSuccess) {
+        p->gstream = nullptr;
+        return POISSON_ERR_HIP;
+    }
+    if (hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming) != hipSuccess)
+        return POISSON_ERR_HIP;
+    return POISSON_OK;
+}
+
+// capture the sequence into graph k (0: head + segments, 1: segments)
+int build_graph(poisson_plan p, std::vector<LSet> &sets, int k)
+{
+    hipError_t e = hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail("graph capture", (int)e);
+    const int rc = enqueue_device_sequence(p, sets, k == 0);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->gstream, &g);
+    if (rc || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return rc ? rc : hip_fail("graph capture", (int)e);
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail("graph instantiate", (int)e);
+    }
+    p->graph[k] = g;
+    p->gexec[k] = x;
+    return POISSON_OK;
+}
+
+// Solve with the device-side loop on the plan's own stream (ordered after
+// the caller's stream by events): per round one graph launch (or the same
+// launches issued eagerly) and one read-back of the scalars and control
+// records.
+int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
+                 poisson_stats_t *st)
+{
+    int rc = ensure_device_loop_objects(p);
+    if (rc) return rc;
+    const int prec = internal_prec(p->precision);
+    const bool refine = p->precision == POISSON_FP32_REFINE;
+    const bool capture = p->graph_mode == 1 && !p->timing;
+    const int count = p->count;
+    p->ls = p->gstream;
+    if (hipEventRecord(p->ev_in, p->stream) != hipSuccess ||
+        hipStreamWaitEvent(p->gstream, p->ev_in, 0) != hipSuccess)
+        return hip_fail("stream ordering", (int)hipGetLastError());
+    if (p->ptrs_done && hipEventSynchronize(p->ptrs_done) != hipSuccess) return POISSON_ERR_HIP;
+
+    std::vector<LSet> sets(p->groups.size());
+    ProbPtrs *staging = (ProbPtrs *)p->host_ptrs->p;
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        Group &g = p->groups[gi];
+        const int n = (int)g.members.size();
+        ProbPtrs *h = staging + g.host_off;
+        for (int k = 0; k < n; ++k) {
+            const int i = g.members[k];
+            h[k] = problem_ptrs(p, g, k, rhs[i], sol[i]);
+        }
+        if (hipMemcpyAsync(g.ptrs->p, h, sizeof(ProbPtrs) * n, hipMemcpyHostToDevice,
+                           p->gstream) != hipSuccess)
+            return hip_fail("pointer upload", (int)hipGetLastError());
+        sets[gi] = LSet{p, &g, prec, (const ProbPtrs *)g.ptrs->p, n, {}};
+    }
+    const double *hs = (const double *)p->host_scalars->p;
+    const int *hc = (const int *)p->host_ctrl->p;
+    const int max_rounds = p->max_refine / GRAPH_SEGMENTS + 2;
+    for (int round = 0; !rc; ++round) {
+        const int k = round == 0 ? 0 : 1;
+        if (capture) {
+            if (!p->gexec[k] && (rc = build_graph(p, sets, k))) break;
+            const hipError_t e = hipGraphLaunch(p->gexec[k], p->gstream);
+            if (e != hipSuccess) {
+                rc = hip_fail("graph launch", (int)e);
+                break;
+            }
+        } else if ((rc = enqueue_device_sequence(p, sets, round == 0))) {
+            break;
+        }
+        if (!refine && !st) break;
+        if (hipMemcpyAsync(p->host_scalars->p, p->scalars->p, NSCAL * sizeof(double) * count,
+                           hipMemcpyDeviceToHost, p->gstream) != hipSuccess ||
+            hipMemcpyAsync(p->host_ctrl->p, p->ctrl->p, NCTRL * sizeof(int) * count,
+                           hipMemcpyDeviceToHost, p->gstream) != hipSuccess ||
+            hipStreamSynchronize(p->gstream) != hipSuccess) {
+            rc = hip_fail("scalar read-back", (int)hipGetLastError());
+            break;
+        }
+        if (!refine) break;
+        bool running = false;
+        for (int i = 0; i < count; ++i) running = running || hc[NCTRL * i + C_STATE] != 0;
+        if (!running || round + 1 >= max_rounds) break;
+    }
+    if (p->ptrs_done) (void)hipEventRecord(p->ptrs_done, p->gstream);
+    (void)hipEventRecord(p->ev_out, p->gstream);
+    (void)hipStreamWaitEvent(p->stream, p->ev_out, 0);
+
+    int first = rc;
+    for (auto &g : p->groups) {
+        for (int i : g.members) {
+            poisson_stats_t o{0, -1.0, 0.0, POISSON_OK};
+            if (!rc && (refine || st)) {
+                const double *sc = hs + NSCAL * i;
+                const int *c = hc + NCTRL * i;
+                o.rhs_mean = prec == P_F64 ? sc[0] : sc[1] / (double)g.N;
+                if (refine) {
+                    o.rel_residual = sc[5];
+                    o.iterations = c[C_CORR];
+                    o.status = c[C_STATE] ? POISSON_ERR_NOT_CONVERGED : c[C_STATUS];
+                }
+            }
+            if (rc) o.status = rc;
+            if (!first && o.status) first = o.status;
+            if (st) st[i] = o;
+        }
     }
     return first;
 }
@@ -771,11 +978,14 @@ int create_plan(const poisson_desc_t *descs, int count, void *stream, bool batch
     if (hipMemset(p->scalars->p, 0, NSCAL * sizeof(double) * count) != hipSuccess)
         return POISSON_ERR_HIP;
     if ((rc = pinned_alloc(p->host_scalars, NSCAL * sizeof(double) * count))) return rc;
-    if (batched) {
-        if ((rc = pinned_alloc(p->host_ptrs, sizeof(ProbPtrs) * count))) return rc;
-        if (hipEventCreateWithFlags(&p->ptrs_done, hipEventDisableTiming) != hipSuccess)
-            return POISSON_ERR_HIP;
-    }
+    if ((rc = dev_alloc(p->ctrl, NCTRL * sizeof(int) * count))) return rc;
+    if (hipMemset(p->ctrl->p, 0, NCTRL * sizeof(int) * count) != hipSuccess)
+        return POISSON_ERR_HIP;
+    if ((rc = pinned_alloc(p->host_ctrl, NCTRL * sizeof(int) * count))) return rc;
+    // pointer staging serves batched launches and the device-side loop
+    if ((rc = pinned_alloc(p->host_ptrs, sizeof(ProbPtrs) * count))) return rc;
+    if (hipEventCreateWithFlags(&p->ptrs_done, hipEventDisableTiming) != hipSuccess)
+        return POISSON_ERR_HIP;
     *out = p.release();
     return POISSON_OK;
 }
@@ -836,7 +1046,8 @@ int poisson_solve(poisson_plan plan, const double *rhs, double *sol, poisson_sta
     if (!plan || !rhs || !sol || plan->batched) return POISSON_ERR_INVALID_ARG;
     if (overlaps(rhs, sol, plan->groups[0].N)) return POISSON_ERR_INVALID_ARG;
     DeviceGuard guard(plan->device);
-    return solve_all(plan, &rhs, &sol, stats);
+    return plan->graph_mode ? solve_device(plan, &rhs, &sol, stats)
+                            : solve_all(plan, &rhs, &sol, stats);
 }
 
 int poisson_batch_solve(poisson_plan plan, const double *const *rhs, double *const *sol,
@@ -853,13 +1064,28 @@ int poisson_batch_solve(poisson_plan plan, const double *const *rhs, double *con
         }
     }
     DeviceGuard guard(plan->device);
-    return solve_all(plan, rhs, sol, stats);
+    return plan->graph_mode ? solve_device(plan, rhs, sol, stats) : solve_all(plan, rhs, sol, stats);
+}
+
+int poisson_plan_set_graph(poisson_plan plan, int mode)
+{
+    if (!plan || mode < 0 || mode > 2) return POISSON_ERR_INVALID_ARG;
+    DeviceGuard guard(plan->device);
+    if (mode != plan->graph_mode) {
+        // graphs capture the plan's buffers, not the solve's arguments, so they
+        // stay valid across solves; a mode change rebuilds them when needed
+        (void)hipStreamSynchronize(plan->gstream ? plan->gstream : plan->stream);
+        plan->drop_graphs();
+    }
+    plan->graph_mode = mode;
+    return POISSON_OK;
 }
 
 int poisson_destroy(poisson_plan plan)
 {
     if (!plan) return POISSON_OK;
     (void)hipStreamSynchronize(plan->stream);
+    if (plan->gstream) (void)hipStreamSynchronize(plan->gstream);
     delete plan;
     return POISSON_OK;
 }

@@ -42,8 +42,32 @@ struct ProbPtrs {
     void *S;           // spectrum
     double *partials;  // per-workgroup partial sums of the x pass
     double *scal;      // 8 FP64 scalars: [0] mean (z pass), [1] sum f, [2] sum r^2,
-                       // [3] sum (f - mean)^2, [4] sum p
+                       // [3] sum (f - mean)^2, [4] sum p, [5] relative residual,
+                       // [6] previous relative residual, [7] first relative residual
+    int *ctrl;         // refinement control record (device-side loop), CtrlSlot
 };
+
+// Device-side control of the refinement loop: one record of NCTRL ints per
+// problem.  Passes of the loop carry a `gate` slot (0: none) and a workgroup
+// of problem i returns at once when ctrl[gate] of problem i is zero, so a
+// fixed launch sequence (a captured graph) serves problems that converge
+// after different numbers of corrections.
+enum CtrlSlot {
+    C_STATE = 0,    // 1 while the problem is running
+    C_FULL = 1,     // next residual: full residual pass (with transform)
+    C_CHECK = 2,    // next residual: check only
+    C_EVAL = 3,     // a residual is evaluated in this segment (C_FULL or C_CHECK)
+    C_FIX = 4,      // a check failed: transform the residual before correcting
+    C_CORRECT = 5,  // run the correction passes
+    C_CORR = 6,     // corrections applied so far
+    C_STATUS = 7,   // final status (poisson error code)
+    NCTRL = 8
+};
+
+__device__ __forceinline__ bool gated_off(const ProbPtrs *batch, int gate, int i)
+{
+    return gate != 0 && batch != nullptr && batch[i].ctrl[gate] == 0;
+}
 
 // Arguments of the forward real-to-complex pass along x (optionally with the
 // FP64 residual r = (f - mu) - L p evaluated on the fly as its input).
@@ -62,6 +86,7 @@ struct XFwdArgs {
     double inv_n;           // 1/(nx ny nz)
     int residual;           // 1: input is the residual
     int reverse;            // walk the row blocks from the end (see block_order)
+    int gate;               // control slot gating this launch (0: none)
 };
 
 // Inverse complex-to-real pass along x: p = result (store) or p += result.
@@ -76,6 +101,7 @@ struct XInvArgs {
     int reverse;
     const double *sum_p;    // accumulate mode: device sum of p (its mean is removed)
     double inv_n;           // 1/(nx ny nz)
+    int gate;
 };
 
 // Strided complex pass along y, in place on S.
@@ -87,6 +113,7 @@ struct YArgs {
     int M, ny, nz;
     int inverse;
     int reverse;
+    int gate;
 };
 
 // z solve, walls (tridiagonal per (m, ky)) or periodic (transform along z).
@@ -106,6 +133,7 @@ struct ZArgs {
     double inv_ntot;        // 1/(nx ny nz)
     int reverse;
     int variant;            // tile variant (0 = default; see the launchers)
+    int gate;
 };
 
 // Launchers (return 0 on success, a hipError_t value otherwise).  The forward
@@ -122,7 +150,11 @@ int x_fwd_blocks(int prec, int nx, int ny, int nz, int residual);
 // sums each (stride 4), written to out[0..3).  Batched: one workgroup per
 // problem, partials and scal taken from batch[i], written to scal + out_off.
 int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *batch,
-                        int nbatch, int out_off, hipStream_t s);
+                        int nbatch, int out_off, hipStream_t s, int gate = 0);
+// device-side refinement control over the n problems of `batch` (CtrlSlot)
+int launch_ctrl_init(const ProbPtrs *batch, int n, hipStream_t s);
+int launch_refine_control(const ProbPtrs *batch, int n, double rtol, int max_refine,
+                          hipStream_t s);
 // FP64 residual r = (f - mean f) - L p alone (no transform, no spectrum
 // write): per-workgroup sums of r^2, (f - mean f)^2 and p into `partials`
 // (same layout as the forward x pass), for a convergence check.

@@ -1,6 +1,7 @@
 // k_misc.hip -- precision dispatch of the pass launchers and the
 // deterministic FP64 reduction of per-workgroup partial sums (residual and
 // right-hand-side norms of the iterative refinement).
+#include "../../include/poisson.h"
 #include "common.hpp"
 #include "lengths.hpp"
 #include "stencil.hpp"
@@ -56,9 +57,11 @@ bool fft_length_supported(int n)
 // t+1024, ... in a fixed order, then a fixed-shape tree finishes: bitwise
 // reproducible for a given n.
 __global__ __launch_bounds__(1024) void k_sum_partials(const double *in, int n, double *out,
-                                                       const ProbPtrs *batch, int out_off)
+                                                       const ProbPtrs *batch, int out_off,
+                                                       int gate)
 {
     __shared__ double sh[3][1024];
+    if (gated_off(batch, gate, blockIdx.x)) return;
     if (batch) {
         in = batch[blockIdx.x].partials;
         out = batch[blockIdx.x].scal + out_off;
@@ -87,10 +90,85 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double *in, int n, 
 }
 
 int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *batch,
-                        int nbatch, int out_off, hipStream_t s)
+                        int nbatch, int out_off, hipStream_t s, int gate)
 {
     hipLaunchKernelGGL(k_sum_partials, dim3(batch ? nbatch : 1), dim3(1024), 0, s, in, n, out,
-                       batch, out_off);
+                       batch, out_off, gate);
+    return (int)hipGetLastError();
+}
+
+// Device-side refinement control (one thread per problem of a batched
+// launch).  k_ctrl_init opens the loop: full residual pass next, no
+// correction yet.  k_refine_control takes the decision after a residual
+// evaluation, with the same rules as the host-driven loop:
+//   rho = ||r|| / ||f - mean f||;  rho <= rtol -> converged;  non-finite ->
+//   error;  max_refine corrections done, or rho > rho_prev / 2 (stall) ->
+//   not converged; otherwise correct, and when rho_prev * rho_first is two
+//   decades below rtol the next residual is evaluated without transform.
+__global__ void k_ctrl_init(const ProbPtrs *batch, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int *c = batch[i].ctrl;
+    double *sc = batch[i].scal;
+    c[C_STATE] = 1;
+    c[C_FULL] = 1;
+    c[C_CHECK] = 0;
+    c[C_EVAL] = 1;
+    c[C_FIX] = 0;
+    c[C_CORRECT] = 0;
+    c[C_CORR] = 0;
+    c[C_STATUS] = POISSON_OK;
+    sc[5] = -1.0;
+    sc[6] = -1.0;
+    sc[7] = -1.0;
+}
+
+__global__ void k_refine_control(const ProbPtrs *batch, int n, double rtol, int max_refine)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int *c = batch[i].ctrl;
+    double *sc = batch[i].scal;
+    if (c[C_EVAL] == 0) return;
+    const bool was_check = c[C_CHECK] != 0;
+    const double rho = sc[3] > 0.0 ? sqrt(sc[2] / sc[3]) : sqrt(sc[2]);
+    sc[5] = rho;
+    if (sc[7] < 0.0) sc[7] = rho;
+    int status = 1;  // 1: go on
+    if (!isfinite(rho))
+        status = POISSON_ERR_NONFINITE;
+    else if (rho <= rtol)
+        status = POISSON_OK;
+    else if (c[C_CORR] >= max_refine || (sc[6] >= 0.0 && rho > 0.5 * sc[6]))
+        status = POISSON_ERR_NOT_CONVERGED;
+    if (status != 1) {
+        c[C_STATUS] = status;
+        c[C_STATE] = 0;
+        c[C_FULL] = c[C_CHECK] = c[C_EVAL] = c[C_FIX] = c[C_CORRECT] = 0;
+        return;
+    }
+    sc[6] = rho;
+    c[C_CORR] += 1;
+    c[C_FIX] = was_check ? 1 : 0;
+    c[C_CORRECT] = 1;
+    const bool predict = sc[7] > 0.0 && sc[6] > 0.0 && sc[6] * sc[7] * 100.0 <= rtol;
+    c[C_FULL] = predict ? 0 : 1;
+    c[C_CHECK] = predict ? 1 : 0;
+    c[C_EVAL] = 1;
+}
+
+int launch_ctrl_init(const ProbPtrs *batch, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctrl_init, dim3((n + 63) / 64), dim3(64), 0, s, batch, n);
+    return (int)hipGetLastError();
+}
+
+int launch_refine_control(const ProbPtrs *batch, int n, double rtol, int max_refine,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_refine_control, dim3((n + 63) / 64), dim3(64), 0, s, batch, n, rtol,
+                       max_refine);
     return (int)hipGetLastError();
 }
 
@@ -103,6 +181,7 @@ constexpr int RC_NT = 256;
 template <int M>
 __global__ __launch_bounds__(RC_NT) void k_residual_check(XFwdArgs a0)
 {
+    if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
     constexpr int TJ = march_rows(M);
     using Mar = PlaneMarch<M, TJ, RC_NT>;
     __shared__ double2 s_tile[TJ + 2][M];

@@ -179,6 +179,7 @@ __device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R,
 template <int M>
 __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
 {
+    if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
     XFwdArgs a = a0;
     if (a.batch) {
         const ProbPtrs &q = a.batch[blockIdx.y];
@@ -273,6 +274,7 @@ constexpr int XR_NT = 256;
 template <int M>
 __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
 {
+    if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
     XFwdArgs a = a0;
     if (a.batch) {
         const ProbPtrs &q = a.batch[blockIdx.y];
@@ -348,6 +350,7 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
 template <int M, bool ACC>
 __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
 {
+    if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
     XInvArgs a = a0;
     if (a.batch) {
         const ProbPtrs &q = a.batch[blockIdx.y];

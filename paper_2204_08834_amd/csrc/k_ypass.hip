@@ -33,6 +33,7 @@ template <int N> struct YCfg {
 template <int N, bool INV>
 __global__ __launch_bounds__(YCfg<N>::NT) void k_y(YArgs a0)
 {
+    if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
     YArgs a = a0;
     if (a.batch) a.S = a.batch[blockIdx.y].S;
     using C = YCfg<N>;

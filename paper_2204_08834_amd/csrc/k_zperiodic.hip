@@ -36,6 +36,7 @@ template <int N> struct ZPCfg {
 template <int N>
 __global__ __launch_bounds__(ZPCfg<N>::NT) void k_z_per(ZArgs a0, int nspecial)
 {
+    if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
     ZArgs a = a0;
     if (a.batch) {
         const ProbPtrs &pq = a.batch[blockIdx.y];

@@ -74,6 +74,7 @@ __device__ __forceinline__ double rcp_nr(double x)
 template <int L, int W, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
 {
+    if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
     ZArgs a = a0;
     if (a.batch) {
         const ProbPtrs &pq = a.batch[blockIdx.y];

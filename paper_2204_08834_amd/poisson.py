@@ -64,7 +64,11 @@ _lib = None
 SYMBOLS = ["poisson_desc_init", "poisson_desc_validate", "poisson_workspace_bytes",
            "poisson_plan_create", "poisson_solve", "poisson_destroy",
            "poisson_batch_plan_create", "poisson_batch_solve", "poisson_error_string",
-           "poisson_plan_set_timing", "poisson_plan_reset_timing", "poisson_plan_get_timing"]
+           "poisson_plan_set_timing", "poisson_plan_reset_timing", "poisson_plan_get_timing",
+           "poisson_plan_set_graph"]
+
+# refinement-loop drivers of poisson_plan_set_graph
+GRAPH_MODES = {"host": 0, "graph": 1, "device": 2}
 
 
 def lib():
@@ -94,6 +98,7 @@ def lib():
     L.poisson_plan_reset_timing.argtypes = [P]
     L.poisson_plan_get_timing.argtypes = [P, ctypes.POINTER(PassStat), ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_int)]
+    L.poisson_plan_set_graph.argtypes = [P, ctypes.c_int]
     for name in SYMBOLS:
         if name != "poisson_workspace_bytes" and name != "poisson_error_string":
             getattr(L, name).restype = ctypes.c_int
@@ -195,6 +200,9 @@ class Plan:
     def timing(self):
         return _get_timing(self._h)
 
+    def set_graph(self, mode="graph"):
+        _set_graph(self._h, mode)
+
     def close(self):
         if getattr(self, "_h", None):
             lib().poisson_destroy(self._h)
@@ -211,6 +219,13 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def _set_graph(h, mode):
+    m = GRAPH_MODES[mode] if isinstance(mode, str) else int(mode)
+    rc = lib().poisson_plan_set_graph(h, m)
+    if rc != OK:
+        raise PoissonError(rc, "poisson_plan_set_graph")
 
 
 def _get_timing(h):
@@ -258,8 +273,14 @@ class BatchPlan:
     def set_timing(self, enable=True):
         lib().poisson_plan_set_timing(self._h, 1 if enable else 0)
 
+    def reset_timing(self):
+        lib().poisson_plan_reset_timing(self._h)
+
     def timing(self):
         return _get_timing(self._h)
+
+    def set_graph(self, mode="graph"):
+        _set_graph(self._h, mode)
 
     def close(self):
         if getattr(self, "_h", None):

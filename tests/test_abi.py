@@ -114,3 +114,9 @@ def test_workspace_bytes():
     # FP64 works in place in the solution array; FP32 needs a 4 B/point spectrum
     assert P.workspace_bytes(d64) < 1 << 20
     assert n * 4 <= P.workspace_bytes(d32) < n * 4.1
+
+
+def test_set_graph_rejects_null_plan():
+    L = P.lib()
+    assert L.poisson_plan_set_graph(None, 1) == P.ERR_INVALID_ARG
+    assert P.GRAPH_MODES == {"host": 0, "graph": 1, "device": 2}
