@@ -86,11 +86,45 @@ def time_solves(plan, rhs, out, steps, sync_each):
     return (time.perf_counter() - t0) / steps * 1e3, last
 
 
+def bench_batch(steps, warmup):
+    """The 64-problem mixed batch (24 x 64^3 periodic, 24 x 96x96x48 walls,
+    16 x 128x128x64 walls; U(-1,1) velocity divergences, seeds 1000+b),
+    FP32 + refinement to 1e-10, through one batched plan: host-driven loop
+    against the captured-graph loop."""
+    import torch
+    from paper_2204_08834_amd import inputs, poisson
+    probs = inputs.batch_mixed64()
+    for p in probs:
+        inputs.make_rhs(p)
+    specs = [dict(nx=p.nx, ny=p.ny, nz=p.nz, dx=p.dx, dy=p.dy, dz=p.dz, bc_z=p.bc_z)
+             for p in probs]
+    rhs = [torch.from_numpy(p.f).cuda() for p in probs]
+    outs = [torch.empty_like(r) for r in rhs]
+    npts = sum(p.npoints for p in probs)
+    res = {"problems": len(probs), "points": npts}
+    for mode in ("host", "graph", "device"):
+        bp = poisson.BatchPlan(specs, "fp32_refine", rtol=1e-10, max_refine=8)
+        bp.set_graph(mode)
+        for _ in range(warmup):
+            bp.solve(rhs, outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, st = bp.solve(rhs, outs)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        bp.close()
+        res[mode] = {"ms_per_batch": ms, "mpoints_s": npts / (ms * 1e-3) / 1e6,
+                     "max_rel_residual": max(x["rel_residual"] for x in st),
+                     "max_iterations": max(x["iterations"] for x in st)}
+    return res
+
+
 def cpu_baseline(prob, nplanes):
-    """The FP64 oracle timed on the host on a slab of the same workload: the
-    first `nplanes` z-planes (x and y lines have their full length, so the
-    per-point cost of the oracle's O(n) per-point DFTs is that of the full
-    grid)."""
+    """The FP64 oracle timed on the host on the workload, or on a slab of it:
+    the first `nplanes` z-planes (x and y lines keep their full length, so
+    the per-point cost of the oracle's O(n) per-point DFTs is that of the
+    full grid).  The default is the whole grid (about 13 s on 16 cores)."""
     import numpy as np
     import oracle
     f = np.ascontiguousarray(prob.f[:nplanes])
@@ -101,8 +135,10 @@ def cpu_baseline(prob, nplanes):
     pts = f.size
     return {"value": pts / dt / 1e6, "unit": "Mpoints/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"first {nplanes} of {prob.nz} z-planes of the workload "
-                      f"({prob.nx}x{prob.ny}x{nplanes}), one FP64 oracle solve, {dt:.2f} s"}
+            "sample": (f"the whole {prob.nx}x{prob.ny}x{prob.nz} workload" if nplanes == prob.nz
+                       else f"first {nplanes} of {prob.nz} z-planes of the workload "
+                            f"({prob.nx}x{prob.ny}x{nplanes})")
+                      + f", one FP64 oracle solve, {dt:.2f} s"}
 
 
 def copy_calibration(steps, warmup):
@@ -243,7 +279,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rb512", choices=sorted(DESCRIPTIONS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-planes", type=int, default=16)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched workload (profiling runs)")
+    ap.add_argument("--cpu-planes", type=int, default=0,
+                    help="z-planes of the workload in the CPU oracle sample (0: all)")
     ap.add_argument("--only", choices=["fp32_refine", "fp64"], default=None,
                     help="time one precision only (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -286,6 +326,10 @@ def main():
         print(json.dumps(copy_calibration(args.steps, args.warmup)), flush=True)
         return
 
+    if args.batch_only:
+        print(json.dumps({"batch_mixed64": bench_batch(args.steps, args.warmup)}), flush=True)
+        return
+
     prob = inputs.workload(args.workload)
     npts = prob.npoints
     dx, dy, dz = prob.spacings()
@@ -319,6 +363,13 @@ def main():
             plan.solve(rhs, out)
         passes = plan.timing()
         plan.set_timing(False)
+        # the same solves through the captured-graph loop
+        plan.set_graph("graph")
+        for _ in range(args.warmup):
+            plan.solve(rhs, out)
+        msg, stg = time_solves(plan, rhs, out, args.steps, sync_each=True)
+        result["fp32refine_graph_loop"] = {"ms_per_step": msg, "mpoints_s": npts / (msg * 1e-3) / 1e6,
+                                           "rel_residual": stg["rel_residual"]}
         plan.close()
         result["value"] = npts / (ms32 * 1e-3) / 1e6
         result["ms_per_step"] = ms32
@@ -375,9 +426,14 @@ def main():
         else:
             result["fp32refine_over_fp64_speed"] = ms64 / result["ms_per_step"]
 
+    if not args.no_batch:
+        print("[bench] batched mixed-64 workload", file=sys.stderr, flush=True)
+        result["batch_mixed64"] = bench_batch(max(3, args.steps // 4), 2)
+
     if not args.no_cpu:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(prob, min(args.cpu_planes, prob.nz))
+        planes = prob.nz if args.cpu_planes <= 0 else min(args.cpu_planes, prob.nz)
+        result["cpu_baseline"] = cpu_baseline(prob, planes)
     print(json.dumps(result), flush=True)
 
 

@@ -180,7 +180,6 @@ struct Group {
     int ncheck = 0;                    // workgroups of the residual-check pass
     int part_stride = 0;               // doubles of partials per member
     int zwalls_variant = 0;            // tile variant of the wall-bounded z solve
-    std::shared_ptr<DevBuf> ptrs;      // device ProbPtrs[members]
     int host_off = 0;                  // offset of this group's staging entries
 };
 
@@ -216,10 +215,15 @@ struct poisson_plan_s {
     // device-side refinement loop (poisson_plan_set_graph): 0 host-driven loop,
     // 1 captured graphs, 2 the same launch sequence issued eagerly
     int graph_mode = 0;
-    std::shared_ptr<DevBuf> ctrl;            // NCTRL ints per problem
-    std::unique_ptr<PinnedBuf> host_ctrl;
+    int *ctrl = nullptr;                     // NCTRL ints per problem (after the scalars)
+    int *host_ctrl = nullptr;                // host copy (after the host scalars)
+    std::shared_ptr<DevBuf> dptrs;           // ProbPtrs of every problem, by group
+    std::vector<ProbPtrs> dptrs_copy;        // what dptrs holds (device-side loop)
+    bool dptrs_valid = false;
     hipStream_t gstream = nullptr;           // plan-owned stream of the device loop
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<hipStream_t> side;           // one more stream per further group
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
     hipGraph_t graph[2] = {nullptr, nullptr};  // [0] solve + loop segments, [1] segments
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     bool timing = false;
@@ -238,6 +242,9 @@ struct poisson_plan_s {
         drop_graphs();
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        for (auto e : ev_join) (void)hipEventDestroy(e);
+        for (auto st : side) (void)hipStreamDestroy(st);
         if (gstream) (void)hipStreamDestroy(gstream);
     }
     void drop_graphs()
@@ -287,6 +294,9 @@ int validate(const poisson_desc_t *d)
 }
 
 int internal_prec(int precision) { return precision == POISSON_FP64 ? P_F64 : P_F32; }
+
+// bytes of the per-problem state: NSCAL doubles, then NCTRL ints, per problem
+size_t state_bytes(int count) { return (NSCAL * sizeof(double) + NCTRL * sizeof(int)) * count; }
 
 // per-workgroup partial-sum records (4 doubles each) a problem needs: the
 // largest grid of the passes that write them
@@ -343,7 +353,6 @@ int build_group(Group &g)
     g.ncheck = refine ? residual_check_blocks(d.nx, d.ny, d.nz) : 0;
     g.part_stride = partial_slots(d) * 4;
     if ((rc = dev_alloc(g.partials, (size_t)g.part_stride * sizeof(double) * n))) return rc;
-    if ((rc = dev_alloc(g.ptrs, sizeof(ProbPtrs) * n))) return rc;
     if (const char *e = getenv("POISSON_ZWALLS_CHUNK"))  // 8 or 16 rows per chunk
         g.zwalls_variant = atoi(e) == 8 ? 1 : (atoi(e) == 16 ? 2 : 0);
     return POISSON_OK;
@@ -426,7 +435,8 @@ struct LSet {
     const ProbPtrs *dev;
     int n;
     ProbPtrs one;
-    int gate = 0;  // control slot gating the passes (device-side loop)
+    int gate = 0;      // control slot gating the passes (device-side loop)
+    int sum_mode = 0;  // control step taken by the sum of the forward x pass
 };
 
 int pass_x_fwd(LSet &L, bool residual, bool want_partials, bool sum = true)
@@ -464,7 +474,8 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials, bool sum = true)
     const int off = residual ? 2 : 1;
     return timed(L.p, "sum_partials", (double)np * 32.0 * L.n, [&] {
         return launch_sum_partials(L.one.partials, np, L.one.scal ? L.one.scal + off : nullptr,
-                                   L.dev, L.n, off, L.p->ls);
+                                   L.dev, L.n, off, L.p->ls, 0, L.sum_mode, L.p->rtol,
+                                   L.p->max_refine);
     });
 }
 
@@ -608,7 +619,7 @@ ProbPtrs problem_ptrs(poisson_plan p, const Group &g, int slot, const double *rh
               : (void *)((char *)g.S32->p + (size_t)g.N * 4 * slot);
     q.partials = (double *)g.partials->p + (size_t)g.part_stride * slot;
     q.scal = (double *)p->scalars->p + NSCAL * i;
-    q.ctrl = (int *)p->ctrl->p + NCTRL * i;
+    q.ctrl = p->ctrl + NCTRL * i;
     return q;
 }
 
@@ -643,11 +654,12 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
             const int i = g.members[slot];
             h[k] = problem_ptrs(p, g, slot, rhs[i], sol[i]);
         }
-        L.dev = (const ProbPtrs *)g.ptrs->p;
-        L.one = ProbPtrs{nullptr, nullptr, nullptr, nullptr, nullptr};
+        L.dev = (const ProbPtrs *)p->dptrs->p + g.host_off;
+        L.one = ProbPtrs{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+        p->dptrs_valid = false;
         if (L.n == 0) return POISSON_OK;
-        hipError_t e = hipMemcpyAsync(g.ptrs->p, h, sizeof(ProbPtrs) * L.n,
-                                      hipMemcpyHostToDevice, p->ls);
+        hipError_t e = hipMemcpyAsync((ProbPtrs *)p->dptrs->p + g.host_off, h,
+                                      sizeof(ProbPtrs) * L.n, hipMemcpyHostToDevice, p->ls);
         return e == hipSuccess ? POISSON_OK : hip_fail("pointer upload", (int)e);
     };
 
@@ -763,60 +775,94 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
 // further launches of the segment-only graph.
 constexpr int GRAPH_SEGMENTS = 2;
 
-// The launch sequence of the device-side loop.  head: control init and the
-// first solve; then GRAPH_SEGMENTS segments of
-//   full residual pass [C_FULL] | residual check [C_CHECK] | sums [C_EVAL]
-//   | control | full residual pass after a failed check [C_FIX]
+// The launch sequence of the device-side loop for one group, on the stream
+// p->ls.  head: the first solve, whose sum of f also opens the control
+// records; then GRAPH_SEGMENTS segments of
+//   full residual pass [C_FULL] | residual check [C_CHECK]
+//   | sums + control decision [C_EVAL]
+//   | full residual pass after a failed check [C_FIX]
 //   | y, z, y, accumulating x [C_CORRECT]
-int enqueue_device_sequence(poisson_plan p, std::vector<LSet> &sets, bool head)
+int enqueue_group_sequence(poisson_plan p, LSet &L, bool head)
 {
     const bool refine = p->precision == POISSON_FP32_REFINE;
     const int prec = internal_prec(p->precision);
+    Group &g = *L.g;
     int rc = POISSON_OK;
     if (head) {
-        for (auto &L : sets) {
-            L.gate = 0;
-            if (refine && (rc = launch_ctrl_init(L.dev, L.n, p->ls)))
-                return hip_fail("control init", rc);
-            if ((rc = solve_passes(L, false, prec == P_F32))) return rc;
-        }
+        L.gate = 0;
+        L.sum_mode = refine ? 1 : 0;
+        rc = solve_passes(L, false, prec == P_F32);
+        L.sum_mode = 0;
+        if (rc) return rc;
     }
     if (!refine) return POISSON_OK;
     for (int seg = 0; seg < GRAPH_SEGMENTS; ++seg) {
-        for (auto &L : sets) {
-            Group &g = *L.g;
-            L.gate = C_FULL;
-            if ((rc = pass_x_fwd(L, true, true, false))) return rc;
-            L.gate = C_CHECK;
-            if ((rc = pass_residual_check(L, false))) return rc;
-            // both residual kernels run the same 2.5-D march grid (nres == ncheck)
-            rc = timed(p, "sum_partials", (double)g.ncheck * 32.0 * L.n, [&] {
-                return launch_sum_partials(nullptr, g.ncheck, nullptr, L.dev, L.n, 2, p->ls,
-                                           C_EVAL);
-            });
-            if (rc) return rc;
-            if ((rc = launch_refine_control(L.dev, L.n, p->rtol, p->max_refine, p->ls)))
-                return hip_fail("refinement control", rc);
-            L.gate = C_FIX;
-            if ((rc = pass_x_fwd(L, true, true, false))) return rc;
-            L.gate = C_CORRECT;
-            if ((rc = correction_passes(L))) return rc;
-            L.gate = 0;
-        }
+        L.gate = C_FULL;
+        if ((rc = pass_x_fwd(L, true, true, false))) return rc;
+        L.gate = C_CHECK;
+        if ((rc = pass_residual_check(L, false))) return rc;
+        // both residual kernels run the same 2.5-D march grid (nres == ncheck)
+        rc = timed(p, "sum_partials", (double)g.ncheck * 32.0 * L.n, [&] {
+            return launch_sum_partials(nullptr, g.ncheck, nullptr, L.dev, L.n, 2, p->ls, C_EVAL,
+                                       2, p->rtol, p->max_refine);
+        });
+        if (rc) return rc;
+        L.gate = C_FIX;
+        if ((rc = pass_x_fwd(L, true, true, false))) return rc;
+        L.gate = C_CORRECT;
+        if ((rc = correction_passes(L))) return rc;
+        L.gate = 0;
     }
     return POISSON_OK;
+}
+
+// All groups, each on a stream of its own forked from the plan's loop
+// stream and joined back (in a captured graph: independent branches), so
+// that the launches of problems of different shapes overlap.
+int enqueue_device_sequence(poisson_plan p, std::vector<LSet> &sets, bool head)
+{
+    const size_t ng = sets.size();
+    int rc = POISSON_OK;
+    if (ng > 1 && hipEventRecord(p->ev_fork, p->gstream) != hipSuccess)
+        return hip_fail("stream fork", (int)hipGetLastError());
+    for (size_t gi = 0; gi < ng && !rc; ++gi) {
+        p->ls = gi == 0 ? p->gstream : p->side[gi - 1];
+        if (gi > 0 && hipStreamWaitEvent(p->ls, p->ev_fork, 0) != hipSuccess) {
+            rc = hip_fail("stream fork", (int)hipGetLastError());
+            break;
+        }
+        rc = enqueue_group_sequence(p, sets[gi], head);
+        if (gi > 0 && hipEventRecord(p->ev_join[gi - 1], p->ls) != hipSuccess && !rc)
+            rc = hip_fail("stream join", (int)hipGetLastError());
+    }
+    p->ls = p->gstream;
+    for (size_t gi = 1; gi < ng; ++gi)
+        if (hipStreamWaitEvent(p->gstream, p->ev_join[gi - 1], 0) != hipSuccess && !rc)
+            rc = hip_fail("stream join", (int)hipGetLastError());
+    return rc;
 }
 
 int ensure_device_loop_objects(poisson_plan p)
 {
     if (p->gstream) return POISSON_OK;
+    // streams of default priority (non-blocking: ordered by events only)
     if (hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking) != hipSuccess) {
         p->gstream = nullptr;
         return POISSON_ERR_HIP;
     }
-    if (hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming) != hipSuccess)
-        return POISSON_ERR_HIP;
+    auto ev = [](hipEvent_t *e) {
+        return hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+    };
+    if (!ev(&p->ev_in) || !ev(&p->ev_out) || !ev(&p->ev_fork)) return POISSON_ERR_HIP;
+    for (size_t gi = 1; gi < p->groups.size(); ++gi) {
+        hipStream_t st = nullptr;
+        hipEvent_t e = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+            return POISSON_ERR_HIP;
+        p->side.push_back(st);
+        if (!ev(&e)) return POISSON_ERR_HIP;
+        p->ev_join.push_back(e);
+    }
     return POISSON_OK;
 }
 
@@ -863,23 +909,28 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
         return hip_fail("stream ordering", (int)hipGetLastError());
     if (p->ptrs_done && hipEventSynchronize(p->ptrs_done) != hipSuccess) return POISSON_ERR_HIP;
 
+    // pointers of every problem, uploaded in one copy when they changed
     std::vector<LSet> sets(p->groups.size());
     ProbPtrs *staging = (ProbPtrs *)p->host_ptrs->p;
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
         Group &g = p->groups[gi];
         const int n = (int)g.members.size();
-        ProbPtrs *h = staging + g.host_off;
         for (int k = 0; k < n; ++k) {
             const int i = g.members[k];
-            h[k] = problem_ptrs(p, g, k, rhs[i], sol[i]);
+            staging[g.host_off + k] = problem_ptrs(p, g, k, rhs[i], sol[i]);
         }
-        if (hipMemcpyAsync(g.ptrs->p, h, sizeof(ProbPtrs) * n, hipMemcpyHostToDevice,
+        sets[gi] = LSet{p, &g, prec, (const ProbPtrs *)p->dptrs->p + g.host_off, n, {}};
+    }
+    if (!p->dptrs_valid ||
+        memcmp(p->dptrs_copy.data(), staging, sizeof(ProbPtrs) * count) != 0) {
+        if (hipMemcpyAsync(p->dptrs->p, staging, sizeof(ProbPtrs) * count, hipMemcpyHostToDevice,
                            p->gstream) != hipSuccess)
             return hip_fail("pointer upload", (int)hipGetLastError());
-        sets[gi] = LSet{p, &g, prec, (const ProbPtrs *)g.ptrs->p, n, {}};
+        memcpy(p->dptrs_copy.data(), staging, sizeof(ProbPtrs) * count);
+        p->dptrs_valid = true;
     }
     const double *hs = (const double *)p->host_scalars->p;
-    const int *hc = (const int *)p->host_ctrl->p;
+    const int *hc = p->host_ctrl;
     const int max_rounds = p->max_refine / GRAPH_SEGMENTS + 2;
     for (int round = 0; !rc; ++round) {
         const int k = round == 0 ? 0 : 1;
@@ -894,9 +945,8 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
             break;
         }
         if (!refine && !st) break;
-        if (hipMemcpyAsync(p->host_scalars->p, p->scalars->p, NSCAL * sizeof(double) * count,
-                           hipMemcpyDeviceToHost, p->gstream) != hipSuccess ||
-            hipMemcpyAsync(p->host_ctrl->p, p->ctrl->p, NCTRL * sizeof(int) * count,
+        // scalars and control records are one allocation: one read-back
+        if (hipMemcpyAsync(p->host_scalars->p, p->scalars->p, state_bytes(count),
                            hipMemcpyDeviceToHost, p->gstream) != hipSuccess ||
             hipStreamSynchronize(p->gstream) != hipSuccess) {
             rc = hip_fail("scalar read-back", (int)hipGetLastError());
@@ -973,16 +1023,16 @@ int create_plan(const poisson_desc_t *descs, int count, void *stream, bool batch
         g.host_off = off;
         off += (int)g.members.size();
     }
-    int rc = dev_alloc(p->scalars, NSCAL * sizeof(double) * count);
+    // scalars, then the control records, in one allocation (and one pinned copy)
+    int rc = dev_alloc(p->scalars, state_bytes(count));
     if (rc) return rc;
-    if (hipMemset(p->scalars->p, 0, NSCAL * sizeof(double) * count) != hipSuccess)
-        return POISSON_ERR_HIP;
-    if ((rc = pinned_alloc(p->host_scalars, NSCAL * sizeof(double) * count))) return rc;
-    if ((rc = dev_alloc(p->ctrl, NCTRL * sizeof(int) * count))) return rc;
-    if (hipMemset(p->ctrl->p, 0, NCTRL * sizeof(int) * count) != hipSuccess)
-        return POISSON_ERR_HIP;
-    if ((rc = pinned_alloc(p->host_ctrl, NCTRL * sizeof(int) * count))) return rc;
-    // pointer staging serves batched launches and the device-side loop
+    if (hipMemset(p->scalars->p, 0, state_bytes(count)) != hipSuccess) return POISSON_ERR_HIP;
+    if ((rc = pinned_alloc(p->host_scalars, state_bytes(count)))) return rc;
+    p->ctrl = (int *)((double *)p->scalars->p + NSCAL * count);
+    p->host_ctrl = (int *)((double *)p->host_scalars->p + NSCAL * count);
+    // pointer arrays of batched launches and of the device-side loop
+    if ((rc = dev_alloc(p->dptrs, sizeof(ProbPtrs) * count))) return rc;
+    p->dptrs_copy.resize(count);
     if ((rc = pinned_alloc(p->host_ptrs, sizeof(ProbPtrs) * count))) return rc;
     if (hipEventCreateWithFlags(&p->ptrs_done, hipEventDisableTiming) != hipSuccess)
         return POISSON_ERR_HIP;

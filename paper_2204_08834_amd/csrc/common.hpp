@@ -149,12 +149,12 @@ int x_fwd_blocks(int prec, int nx, int ny, int nz, int residual);
 // Deterministic FP64 sums of the x pass's partials: `n` workgroups with three
 // sums each (stride 4), written to out[0..3).  Batched: one workgroup per
 // problem, partials and scal taken from batch[i], written to scal + out_off.
+// Batched launches of the device-side loop also take the control step of
+// each problem (CtrlSlot records): mode 1 opens the record, mode 2 decides
+// after a residual evaluation (rtol, max_refine).
 int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *batch,
-                        int nbatch, int out_off, hipStream_t s, int gate = 0);
-// device-side refinement control over the n problems of `batch` (CtrlSlot)
-int launch_ctrl_init(const ProbPtrs *batch, int n, hipStream_t s);
-int launch_refine_control(const ProbPtrs *batch, int n, double rtol, int max_refine,
-                          hipStream_t s);
+                        int nbatch, int out_off, hipStream_t s, int gate = 0, int mode = 0,
+                        double rtol = 0.0, int max_refine = 0);
 // FP64 residual r = (f - mean f) - L p alone (no transform, no spectrum
 // write): per-workgroup sums of r^2, (f - mean f)^2 and p into `partials`
 // (same layout as the forward x pass), for a convergence check.

@@ -53,19 +53,12 @@ bool fft_length_supported(int n)
     switch (n) { PK_LENGTHS(PK_IS) default: return false; }
 }
 
-// One workgroup per problem; thread t sums the 4-wide partial records t,
-// t+1024, ... in a fixed order, then a fixed-shape tree finishes: bitwise
-// reproducible for a given n.
-__global__ __launch_bounds__(1024) void k_sum_partials(const double *in, int n, double *out,
-                                                       const ProbPtrs *batch, int out_off,
-                                                       int gate)
+// Sum of the three sums of n partial records (stride 4 doubles): thread t
+// adds records t, t+1024, ... in a fixed order, then a fixed-shape tree
+// finishes; bitwise reproducible for a given n.  Every thread gets the totals.
+__device__ __forceinline__ void sum_records(const double *in, int n, double (*sh)[1024],
+                                            double &s0, double &s1, double &s2)
 {
-    __shared__ double sh[3][1024];
-    if (gated_off(batch, gate, blockIdx.x)) return;
-    if (batch) {
-        in = batch[blockIdx.x].partials;
-        out = batch[blockIdx.x].scal + out_off;
-    }
     const int t = threadIdx.x;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     for (int i = t; i < n; i += 1024) {
@@ -86,31 +79,19 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double *in, int n, 
         }
         __syncthreads();
     }
-    if (t < 3) out[t] = sh[t][0];
+    s0 = sh[0][0];
+    s1 = sh[1][0];
+    s2 = sh[2][0];
 }
 
-int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *batch,
-                        int nbatch, int out_off, hipStream_t s, int gate)
-{
-    hipLaunchKernelGGL(k_sum_partials, dim3(batch ? nbatch : 1), dim3(1024), 0, s, in, n, out,
-                       batch, out_off, gate);
-    return (int)hipGetLastError();
-}
-
-// Device-side refinement control (one thread per problem of a batched
-// launch).  k_ctrl_init opens the loop: full residual pass next, no
-// correction yet.  k_refine_control takes the decision after a residual
-// evaluation, with the same rules as the host-driven loop:
+// Refinement control (device-side loop): opening a loop, and the decision
+// after a residual evaluation with the host-driven loop's rules:
 //   rho = ||r|| / ||f - mean f||;  rho <= rtol -> converged;  non-finite ->
 //   error;  max_refine corrections done, or rho > rho_prev / 2 (stall) ->
 //   not converged; otherwise correct, and when rho_prev * rho_first is two
 //   decades below rtol the next residual is evaluated without transform.
-__global__ void k_ctrl_init(const ProbPtrs *batch, int n)
+__device__ __forceinline__ void ctrl_open(int *c, double *sc)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int *c = batch[i].ctrl;
-    double *sc = batch[i].scal;
     c[C_STATE] = 1;
     c[C_FULL] = 1;
     c[C_CHECK] = 0;
@@ -124,13 +105,8 @@ __global__ void k_ctrl_init(const ProbPtrs *batch, int n)
     sc[7] = -1.0;
 }
 
-__global__ void k_refine_control(const ProbPtrs *batch, int n, double rtol, int max_refine)
+__device__ __forceinline__ void ctrl_decide(int *c, double *sc, double rtol, int max_refine)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int *c = batch[i].ctrl;
-    double *sc = batch[i].scal;
-    if (c[C_EVAL] == 0) return;
     const bool was_check = c[C_CHECK] != 0;
     const double rho = sc[3] > 0.0 ? sqrt(sc[2] / sc[3]) : sqrt(sc[2]);
     sc[5] = rho;
@@ -158,17 +134,38 @@ __global__ void k_refine_control(const ProbPtrs *batch, int n, double rtol, int 
     c[C_EVAL] = 1;
 }
 
-int launch_ctrl_init(const ProbPtrs *batch, int n, hipStream_t s)
+// One workgroup per problem: the sums of the partial records into
+// out[0..3) (batched: scal + out_off of problem blockIdx.x), then, by mode,
+// nothing (0), opening the control record (1) or the control decision (2).
+__global__ __launch_bounds__(1024) void k_sum_partials(const double *in, int n, double *out,
+                                                       const ProbPtrs *batch, int out_off,
+                                                       int gate, int mode, double rtol,
+                                                       int max_refine)
 {
-    hipLaunchKernelGGL(k_ctrl_init, dim3((n + 63) / 64), dim3(64), 0, s, batch, n);
-    return (int)hipGetLastError();
+    __shared__ double sh[3][1024];
+    if (gated_off(batch, gate, blockIdx.x)) return;
+    if (batch) {
+        in = batch[blockIdx.x].partials;
+        out = batch[blockIdx.x].scal + out_off;
+    }
+    double s0, s1, s2;
+    sum_records(in, n, sh, s0, s1, s2);
+    if (threadIdx.x == 0) {
+        out[0] = s0;
+        out[1] = s1;
+        out[2] = s2;
+        if (mode == 1) ctrl_open(batch[blockIdx.x].ctrl, batch[blockIdx.x].scal);
+        if (mode == 2) ctrl_decide(batch[blockIdx.x].ctrl, batch[blockIdx.x].scal, rtol, max_refine);
+    }
 }
 
-int launch_refine_control(const ProbPtrs *batch, int n, double rtol, int max_refine,
-                          hipStream_t s)
+int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *batch,
+                        int nbatch, int out_off, hipStream_t s, int gate, int mode, double rtol,
+                        int max_refine)
 {
-    hipLaunchKernelGGL(k_refine_control, dim3((n + 63) / 64), dim3(64), 0, s, batch, n, rtol,
-                       max_refine);
+    if (mode != 0 && !batch) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sum_partials, dim3(batch ? nbatch : 1), dim3(1024), 0, s, in, n, out,
+                       batch, out_off, gate, mode, rtol, max_refine);
     return (int)hipGetLastError();
 }
 
@@ -197,8 +194,9 @@ __global__ __launch_bounds__(RC_NT) void k_residual_check(XFwdArgs a0)
     const int njb = march_jblocks(a.ny, TJ);
     const int bid = block_order(blockIdx.x, gridDim.x, a.reverse);
     const int jb = bid % njb, kb = bid / njb;
-    const int k0 = kb * MARCH_PLANES;
-    const int k1 = k0 + MARCH_PLANES < a.nz ? k0 + MARCH_PLANES : a.nz;
+    const int kr = march_planes(a.ny, a.nz, TJ);
+    const int k0 = kb * kr;
+    const int k1 = k0 + kr < a.nz ? k0 + kr : a.nz;
     Mar m;
     m.f = a.f;
     m.p = a.p;
@@ -229,7 +227,7 @@ __global__ __launch_bounds__(RC_NT) void k_residual_check(XFwdArgs a0)
 
 template <int M> static int rc_blocks(int ny, int nz)
 {
-    return march_jblocks(ny, march_rows(M)) * march_kblocks(nz);
+    return march_jblocks(ny, march_rows(M)) * march_kblocks(ny, nz, march_rows(M));
 }
 
 template <int M> static int run_rc(const XFwdArgs &a, hipStream_t s)

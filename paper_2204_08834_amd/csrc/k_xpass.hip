@@ -296,8 +296,9 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
     const int njb = march_jblocks(a.ny, TJ);
     const int bid = block_order(blockIdx.x, gridDim.x, a.reverse);
     const int jb = bid % njb, kb = bid / njb;
-    const int k0 = kb * MARCH_PLANES;
-    const int k1 = k0 + MARCH_PLANES < a.nz ? k0 + MARCH_PLANES : a.nz;
+    const int kr = march_planes(a.ny, a.nz, TJ);
+    const int k0 = kb * kr;
+    const int k1 = k0 + kr < a.nz ? k0 + kr : a.nz;
 
     Mar m;
     m.f = a.f;
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
 // the workgroups of the residual pass
 template <int M> static int blocks_x(int ny, int nz, int residual)
 {
-    if (residual) return march_jblocks(ny, march_rows(M)) * march_kblocks(nz);
+    if (residual) return march_jblocks(ny, march_rows(M)) * march_kblocks(ny, nz, march_rows(M));
     return (ny * nz + XCfg<M>::NB - 1) / XCfg<M>::NB;
 }
 

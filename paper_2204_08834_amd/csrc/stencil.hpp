@@ -21,11 +21,22 @@ constexpr int march_rows(int M)
     const int t = 2048 / M;
     return t < 1 ? 1 : (t > 16 ? 16 : t);
 }
-constexpr int MARCH_PLANES = 8;  // z-planes per workgroup
-
 // workgroups of one problem: (y-row blocks) x (z-plane ranges), plane-major
 __host__ __device__ constexpr int march_jblocks(int ny, int tj) { return (ny + tj - 1) / tj; }
-__host__ __device__ constexpr int march_kblocks(int nz) { return (nz + MARCH_PLANES - 1) / MARCH_PLANES; }
+
+// z-planes per workgroup: 8, halved (down to 1) while a problem would get
+// fewer than 256 workgroups, so that small grids still fill the device
+__host__ __device__ constexpr int march_planes(int ny, int nz, int tj)
+{
+    int kr = 8;
+    while (kr > 1 && march_jblocks(ny, tj) * ((nz + kr - 1) / kr) < 256) kr /= 2;
+    return kr;
+}
+__host__ __device__ constexpr int march_kblocks(int ny, int nz, int tj)
+{
+    const int kr = march_planes(ny, nz, tj);
+    return (nz + kr - 1) / kr;
+}
 
 template <int M, int TJ, int NT>
 struct PlaneMarch {
