@@ -104,6 +104,8 @@ def bench_batch(steps, warmup):
     res = {"problems": len(probs), "points": npts}
     for mode in ("host", "graph", "device"):
         bp = poisson.BatchPlan(specs, "fp32_refine", rtol=1e-10, max_refine=8)
+        bp.autotune()
+        res["schedule"] = bp.describe().strip()
         bp.set_graph(mode)
         for _ in range(warmup):
             bp.solve(rhs, outs)
@@ -280,6 +282,8 @@ def main():
     ap.add_argument("--workload", default="rb512", choices=sorted(DESCRIPTIONS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the default launch variants (no plan-time autotuning)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched workload (profiling runs)")
     ap.add_argument("--cpu-planes", type=int, default=0,
@@ -351,6 +355,9 @@ def main():
     if args.only in (None, "fp32_refine"):
         plan = poisson.Plan(prob.nx, prob.ny, prob.nz, dx, dy, dz, prob.bc_z, "fp32_refine",
                             rtol=1e-10, max_refine=8)
+        if not args.no_tune:
+            plan.autotune()
+        result["schedule_fp32_refine"] = plan.describe().strip()
         for _ in range(args.warmup):
             plan.solve(rhs, out)
         ms32, st = time_solves(plan, rhs, out, args.steps, sync_each=True)
@@ -400,6 +407,9 @@ def main():
     # ---- plain FP64 -----------------------------------------------------
     if args.only in (None, "fp64"):
         plan = poisson.Plan(prob.nx, prob.ny, prob.nz, dx, dy, dz, prob.bc_z, "fp64")
+        if not args.no_tune:
+            plan.autotune()
+        result["schedule_fp64"] = plan.describe().strip()
         for _ in range(args.warmup):
             plan.solve(rhs, out)
         ms64, _ = time_solves(plan, rhs, out, args.steps, sync_each=False)

@@ -167,6 +167,32 @@ const char *poisson_error_string(int code);
 int poisson_plan_set_graph(poisson_plan plan, int mode);
 
 /*
+ * Autotuner (the per-shape schedule choice of the batched solves).  For each
+ * distinct problem shape of the plan, times the launch variants of the
+ * passes on scratch fields of that shape -- the tile of the wall-bounded z
+ * solve, the tile width and radix order of the y transforms, and the block
+ * order of the passes (which decides how much of each pass's input is still
+ * in the last-level cache) -- on the plan's stream, and keeps the fastest.
+ * Choices are cached for the process per (precision, grid, z boundary,
+ * device) and used by later plans of that shape at creation; with the
+ * environment variable POISSON_TUNE_CACHE naming a file they persist across
+ * processes.  POISSON_AUTOTUNE=1 tunes every plan at creation.  Synchronises
+ * the plan's stream; allocates two scratch fields of one problem for the
+ * duration of the call.  flags: 0, or POISSON_TUNE_FORCE to ignore cached
+ * choices.  Errors: INVALID_ARG, OUT_OF_MEMORY, HIP.
+ */
+#define POISSON_TUNE_FORCE 1
+int poisson_plan_autotune(poisson_plan plan, int flags);
+
+/*
+ * Text description of the plan: one line per shape group with its grid,
+ * boundary, precision, number of problems and chosen launch variants.
+ * Writes at most len bytes (NUL-terminated) to buf; returns INVALID_ARG if
+ * the text was truncated or an argument is null.
+ */
+int poisson_plan_describe(poisson_plan plan, char *buf, int len);
+
+/*
  * Per-pass timing (tracing).  When enabled, every kernel launch of a solve is
  * bracketed by hipEvents on the plan's stream; the accumulated time and the
  * algorithmic HBM bytes of each pass are read back with

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -159,6 +160,111 @@ int upload_complex(std::shared_ptr<DevBuf> out[2], const std::vector<double> &tw
 }
 
 // ---------------------------------------------------------------------------
+// launch variants (autotuned per shape)
+// ---------------------------------------------------------------------------
+// zv: tile of the wall-bounded z solve (launch_z_walls), yv: tile / radix
+// order of the y passes (YCfg), rev: reversed block order of the passes that
+// read what the previous pass just wrote (block_order).
+struct Tune {
+    int zv = 0, yv = 0, rev = 1;
+    bool tuned = false;  // chosen by timing (else the defaults below)
+};
+
+// Defaults from measurements on MI355X (512x512x256 and 1024x1024x512):
+// wide z tiles for FP64 up to 256 planes, narrow beyond; the reverse for FP32.
+// POISSON_ZWALLS_VARIANT / POISSON_Y_VARIANT / POISSON_BLOCK_ORDER=forward
+// force a choice (measurements).
+Tune heuristic_tune(const poisson_desc_t &d)
+{
+    Tune t;
+    const bool f64 = d.precision == POISSON_FP64;
+    t.zv = f64 ? (d.nz <= 256 ? 2 : 0) : (d.nz <= 256 ? 0 : 2);
+    t.yv = 0;
+    t.rev = 1;
+    return t;
+}
+
+void apply_env_overrides(Tune &t)
+{
+    if (const char *e = getenv("POISSON_ZWALLS_VARIANT")) t.zv = atoi(e) & 3;
+    if (const char *e = getenv("POISSON_Y_VARIANT")) t.yv = atoi(e) & 3;
+    if (const char *e = getenv("POISSON_BLOCK_ORDER")) t.rev = strcmp(e, "forward") == 0 ? 0 : 1;
+}
+
+// process-wide cache of tuned variants: key "precision nx ny nz bc device"
+std::mutex tune_mu;
+std::map<std::string, Tune> tune_cache;
+bool tune_file_loaded = false;
+
+std::string tune_key(const poisson_desc_t &d)
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s %d %d %d %d %s", d.precision == POISSON_FP64 ? "f64" : "f32",
+             d.nx, d.ny, d.nz, d.bc_z, arch.c_str());
+    for (char *c = buf; *c; ++c)
+        if (*c == ':') *c = '_';
+    return buf;
+}
+
+// optional persistence: POISSON_TUNE_CACHE names a text file of lines
+// "<key> : zv yv rev"
+void load_tune_file()
+{
+    if (tune_file_loaded) return;
+    tune_file_loaded = true;
+    const char *path = getenv("POISSON_TUNE_CACHE");
+    if (!path) return;
+    FILE *fp = fopen(path, "r");
+    if (!fp) return;
+    char line[256];
+    while (fgets(line, sizeof line, fp)) {
+        char *colon = strchr(line, ':');
+        if (!colon) continue;
+        *colon = 0;
+        std::string key(line);
+        while (!key.empty() && key.back() == ' ') key.pop_back();
+        Tune t;
+        if (sscanf(colon + 1, "%d %d %d", &t.zv, &t.yv, &t.rev) == 3) {
+            t.zv &= 3;
+            t.yv &= 3;
+            t.rev = t.rev ? 1 : 0;
+            t.tuned = true;
+            tune_cache[key] = t;
+        }
+    }
+    fclose(fp);
+}
+
+void save_tune_file()
+{
+    const char *path = getenv("POISSON_TUNE_CACHE");
+    if (!path) return;
+    FILE *fp = fopen(path, "w");
+    if (!fp) return;
+    for (auto &kv : tune_cache)
+        fprintf(fp, "%s : %d %d %d\n", kv.first.c_str(), kv.second.zv, kv.second.yv, kv.second.rev);
+    fclose(fp);
+}
+
+Tune initial_tune(const poisson_desc_t &d)
+{
+    Tune t = heuristic_tune(d);
+    {
+        std::lock_guard<std::mutex> lk(tune_mu);
+        load_tune_file();
+        auto it = tune_cache.find(tune_key(d));
+        if (it != tune_cache.end()) t = it->second;
+    }
+    apply_env_overrides(t);
+    return t;
+}
+
+// ---------------------------------------------------------------------------
 // plan structures
 // ---------------------------------------------------------------------------
 struct Tables {
@@ -179,7 +285,7 @@ struct Group {
     int nres = 0;                      // workgroups of the residual x pass
     int ncheck = 0;                    // workgroups of the residual-check pass
     int part_stride = 0;               // doubles of partials per member
-    int zwalls_variant = 0;            // tile variant of the wall-bounded z solve
+    Tune tune;                         // launch variants of this shape (autotuned)
     int host_off = 0;                  // offset of this group's staging entries
 };
 
@@ -353,8 +459,7 @@ int build_group(Group &g)
     g.ncheck = refine ? residual_check_blocks(d.nx, d.ny, d.nz) : 0;
     g.part_stride = partial_slots(d) * 4;
     if ((rc = dev_alloc(g.partials, (size_t)g.part_stride * sizeof(double) * n))) return rc;
-    if (const char *e = getenv("POISSON_ZWALLS_CHUNK"))  // 8 or 16 rows per chunk
-        g.zwalls_variant = atoi(e) == 8 ? 1 : (atoi(e) == 16 ? 2 : 0);
+    g.tune = initial_tune(g.d);
     return POISSON_OK;
 }
 
@@ -411,17 +516,6 @@ void collect_timing(poisson_plan p)
 
 const char *tag(int prec) { return prec == P_F32 ? "f32" : "f64"; }
 
-// Passes that consume what the previous pass just wrote walk their blocks in
-// reverse (see block_order in common.hpp).  POISSON_BLOCK_ORDER=forward turns
-// this off (for measurements).
-bool reversed_orders()
-{
-    static const bool on = [] {
-        const char *e = getenv("POISSON_BLOCK_ORDER");
-        return !(e && strcmp(e, "forward") == 0);
-    }();
-    return on;
-}
 
 // ---------------------------------------------------------------------------
 // one pass over a set of problems of one group
@@ -516,7 +610,7 @@ int pass_y(LSet &L, bool inverse)
     if (g.d.ny == 1) return POISSON_OK;  // a length-1 transform is the identity
     // the forward y pass follows the x pass, which wrote the planes in order
     YArgs a{L.dev, L.n, L.one.S, g.tab.twy[L.prec == P_F32 ? 1 : 0]->p, g.M, g.d.ny, g.d.nz,
-            inverse ? 1 : 0, (!inverse && reversed_orders()) ? 1 : 0, L.gate};
+            inverse ? 1 : 0, (!inverse && g.tune.rev) ? 1 : 0, L.gate, g.tune.yv};
     char name[40];
     snprintf(name, sizeof name, inverse ? "y_inv_%s" : "y_fwd_%s", tag(L.prec));
     const double bytes = (double)g.N * 2.0 * (L.prec == P_F32 ? 4.0 : 8.0) * L.n;
@@ -543,7 +637,7 @@ int pass_z(LSet &L)
     a.dz2 = g.d.dz * g.d.dz;
     a.inv_nxny = 1.0 / ((double)g.d.nx * g.d.ny);
     a.inv_ntot = 1.0 / (double)g.N;
-    a.variant = g.zwalls_variant;
+    a.variant = g.tune.zv;
     a.gate = L.gate;
     const double bytes = (double)g.N * 2.0 * (L.prec == P_F32 ? 4.0 : 8.0) * L.n;
     char name[40];
@@ -560,7 +654,7 @@ int pass_x_inv(LSet &L, bool accumulate)
     Group &g = *L.g;
     // the inverse x pass follows the inverse y pass, which wrote the planes in order
     XInvArgs a{L.dev, L.n, L.one.S, L.one.p, g.tab.twx[L.prec == P_F32 ? 1 : 0]->p, g.d.nx,
-               g.d.ny, g.d.nz, accumulate ? 1 : 0, reversed_orders() ? 1 : 0, nullptr,
+               g.d.ny, g.d.nz, accumulate ? 1 : 0, g.tune.rev, nullptr,
                1.0 / (double)g.N, L.gate};
     // the mean of p from the residual pass (batched launches redirect it)
     if (accumulate) a.sum_p = L.dev ? (const double *)g.partials->p : L.one.scal + 4;
@@ -983,6 +1077,107 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
     return first;
 }
 
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+// Times the launch variants of one shape group on scratch fields of that
+// shape (one problem, zero data: the passes are bandwidth-bound and take no
+// data-dependent paths) and keeps the fastest: the z-solve tile, then the y
+// tile and radix order, then the block order over the whole pass sequence
+// (which decides how much of each pass's input is still in the last-level
+// cache).  Each candidate: one warm-up launch, then the mean of three.
+int autotune_group(poisson_plan p, Group &g)
+{
+    const int prec = internal_prec(p->precision);
+    std::shared_ptr<DevBuf> f, sol, scal;
+    int rc;
+    if ((rc = dev_alloc(f, (size_t)g.N * 8)) || (rc = dev_alloc(sol, (size_t)g.N * 8)) ||
+        (rc = dev_alloc(scal, NSCAL * 8)))
+        return rc;
+    if (hipMemsetAsync(f->p, 0, (size_t)g.N * 8, p->stream) != hipSuccess ||
+        hipMemsetAsync(sol->p, 0, (size_t)g.N * 8, p->stream) != hipSuccess ||
+        hipMemsetAsync(scal->p, 0, NSCAL * 8, p->stream) != hipSuccess ||
+        (g.S32 && hipMemsetAsync(g.S32->p, 0, (size_t)g.N * 4, p->stream) != hipSuccess))
+        return hip_fail("autotune scratch", (int)hipGetLastError());
+    void *S = prec == P_F64 ? sol->p : g.S32->p;
+    ProbPtrs one{(const double *)f->p, (double *)sol->p, S, (double *)g.partials->p,
+                 (double *)scal->p, nullptr};
+    LSet L{p, &g, prec, nullptr, 1, one};
+    p->ls = p->stream;
+    const bool timing = p->timing;
+    p->timing = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        p->timing = timing;
+        return POISSON_ERR_HIP;
+    }
+    auto measure = [&](auto &&fn) -> double {
+        if (fn()) return -1.0;
+        (void)hipEventRecord(e0, p->stream);
+        for (int i = 0; i < 3; ++i)
+            if (fn()) return -1.0;
+        (void)hipEventRecord(e1, p->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) return -1.0;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return ms / 3.0;
+    };
+    auto pick = [&](int &knob, int n, auto &&fn) {
+        int best = knob;
+        double bt = 1e300;
+        for (int v = 0; v < n; ++v) {
+            knob = v;
+            const double t = measure(fn);
+            if (t >= 0.0 && t < bt) {
+                bt = t;
+                best = v;
+            }
+        }
+        knob = best;
+    };
+    if (g.d.bc_z == POISSON_BC_NEUMANN) pick(g.tune.zv, 4, [&] { return pass_z(L); });
+    if (g.d.ny >= 64) {
+        pick(g.tune.yv, 4, [&] {
+            const int r = pass_y(L, false);
+            return r ? r : pass_y(L, true);
+        });
+    }
+    pick(g.tune.rev, 2, [&] { return solve_passes(L, false, false); });
+    g.tune.tuned = true;
+    (void)hipStreamSynchronize(p->stream);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->timing = timing;
+    return POISSON_OK;
+}
+
+int autotune_plan(poisson_plan p, int flags)
+{
+    int rc = POISSON_OK;
+    for (auto &g : p->groups) {
+        const std::string key = tune_key(g.d);
+        bool cached = false;
+        if (!(flags & POISSON_TUNE_FORCE)) {
+            std::lock_guard<std::mutex> lk(tune_mu);
+            load_tune_file();
+            auto it = tune_cache.find(key);
+            if (it != tune_cache.end() && it->second.tuned) {
+                g.tune = it->second;
+                cached = true;
+            }
+        }
+        if (!cached) {
+            if ((rc = autotune_group(p, g))) return rc;
+            std::lock_guard<std::mutex> lk(tune_mu);
+            tune_cache[key] = g.tune;
+            save_tune_file();
+        }
+        apply_env_overrides(g.tune);
+    }
+    p->drop_graphs();  // launch shapes may have changed
+    return rc;
+}
+
 int create_plan(const poisson_desc_t *descs, int count, void *stream, bool batched,
                 poisson_plan *out)
 {
@@ -1036,6 +1231,9 @@ int create_plan(const poisson_desc_t *descs, int count, void *stream, bool batch
     if ((rc = pinned_alloc(p->host_ptrs, sizeof(ProbPtrs) * count))) return rc;
     if (hipEventCreateWithFlags(&p->ptrs_done, hipEventDisableTiming) != hipSuccess)
         return POISSON_ERR_HIP;
+    if (const char *e = getenv("POISSON_AUTOTUNE")) {
+        if (*e && strcmp(e, "0") != 0 && (rc = autotune_plan(p.get(), 0))) return rc;
+    }
     *out = p.release();
     return POISSON_OK;
 }
@@ -1115,6 +1313,35 @@ int poisson_batch_solve(poisson_plan plan, const double *const *rhs, double *con
     }
     DeviceGuard guard(plan->device);
     return plan->graph_mode ? solve_device(plan, rhs, sol, stats) : solve_all(plan, rhs, sol, stats);
+}
+
+int poisson_plan_autotune(poisson_plan plan, int flags)
+{
+    if (!plan || (flags & ~POISSON_TUNE_FORCE)) return POISSON_ERR_INVALID_ARG;
+    DeviceGuard guard(plan->device);
+    (void)hipStreamSynchronize(plan->gstream ? plan->gstream : plan->stream);
+    return autotune_plan(plan, flags);
+}
+
+int poisson_plan_describe(poisson_plan plan, char *buf, int len)
+{
+    if (!plan || !buf || len < 1) return POISSON_ERR_INVALID_ARG;
+    std::string out;
+    char line[256];
+    for (size_t gi = 0; gi < plan->groups.size(); ++gi) {
+        const Group &g = plan->groups[gi];
+        snprintf(line, sizeof line,
+                 "group %zu: %dx%dx%d %s %s problems=%zu z_tile=%d y_tile=%d reverse=%d %s\n", gi,
+                 g.d.nx, g.d.ny, g.d.nz, g.d.bc_z == POISSON_BC_NEUMANN ? "walls" : "periodic",
+                 plan->precision == POISSON_FP64 ? "fp64"
+                                                 : (plan->precision == POISSON_FP32 ? "fp32"
+                                                                                     : "fp32_refine"),
+                 g.members.size(), g.tune.zv, g.tune.yv, g.tune.rev,
+                 g.tune.tuned ? "tuned" : "default");
+        out += line;
+    }
+    snprintf(buf, (size_t)len, "%s", out.c_str());
+    return (int)out.size() < len ? POISSON_OK : POISSON_ERR_INVALID_ARG;
 }
 
 int poisson_plan_set_graph(poisson_plan plan, int mode)

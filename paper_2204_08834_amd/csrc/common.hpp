@@ -114,6 +114,7 @@ struct YArgs {
     int inverse;
     int reverse;
     int gate;
+    int variant;            // tile variant (see YCfg)
 };
 
 // z solve, walls (tridiagonal per (m, ky)) or periodic (transform along z).

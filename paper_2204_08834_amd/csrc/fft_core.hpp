@@ -322,7 +322,8 @@ struct Pass0Regs {
 
 // GL_LDS: gload reads the LDS tile itself (pass 0 then needs a barrier between
 // its loads and its stores).
-template <typename R, int N, int NB, int NT, bool LF, int PAD, bool GL_LDS, class GL, class GS>
+template <typename R, int N, int NB, int NT, bool LF, int PAD, bool GL_LDS, int PV = 0, class GL,
+          class GS>
 __device__ __forceinline__ void fft_tile(const Cx<R> *__restrict__ tw, int tws, GL &gload,
                                          GS &gstore, LdsTile<R, N, NB, LF, PAD> tile)
 {
@@ -337,8 +338,8 @@ __device__ __forceinline__ void fft_tile(const Cx<R> *__restrict__ tw, int tws, 
             if (b < NB) gstore(b, 0, v);
         }
     } else {
-        fft_passes<R, N, NB, NT, LF, PAD, GL_LDS, 0, make_rplan(N).count, 0>(tw, tws, gload,
-                                                                             gstore, tile);
+        fft_passes<R, N, NB, NT, LF, PAD, GL_LDS, 0, make_rplan(N).count, PV>(tw, tws, gload,
+                                                                              gstore, tile);
     }
 }
 

@@ -20,23 +20,27 @@ namespace PK_NS {
 
 using R = PK_REAL;
 
-template <int N> struct YCfg {
+// Tile variants V (chosen per shape by the plan's autotuner):
+//   bit 0: 256-byte row segments (twice the x-wavenumbers per workgroup)
+//   bit 1: radix passes in reverse order (small radix first)
+template <int N, int V> struct YCfg {
     // 128-byte row segments: 16 complex floats or 8 complex doubles; the
     // tile (up to 128 KB at N = 1024) stays in one workgroup's LDS
-    static constexpr int NB0 = sizeof(R) == 4 ? 16 : 8;
+    static constexpr int NB0 = (sizeof(R) == 4 ? 16 : 8) * ((V & 1) ? 2 : 1);
     static constexpr int MAXE = sizeof(R) == 4 ? 16384 : 8192;
     static constexpr int NB = (NB0 * N <= MAXE) ? NB0 : ((MAXE / N) < 1 ? 1 : MAXE / N);
     static constexpr int NT = pick_nt(NB * N, sizeof(R) == 4 ? 16 : 8);
     static constexpr int PAD = (NB >= 8) ? 1 : 0;
+    static constexpr int PV = (V & 2) ? 1 : 0;
 };
 
-template <int N, bool INV>
-__global__ __launch_bounds__(YCfg<N>::NT) void k_y(YArgs a0)
+template <int N, bool INV, int V>
+__global__ __launch_bounds__((YCfg<N, V>::NT)) void k_y(YArgs a0)
 {
     if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
     YArgs a = a0;
     if (a.batch) a.S = a.batch[blockIdx.y].S;
-    using C = YCfg<N>;
+    using C = YCfg<N, V>;
     constexpr int NB = C::NB, NT = C::NT;
     using Tile = LdsTile<R, N, NB, true, C::PAD>;
     __shared__ Cx<R> s_tile[Tile::elems];
@@ -62,18 +66,34 @@ __global__ __launch_bounds__(YCfg<N>::NT) void k_y(YArgs a0)
         base[(size_t)n * M + b] = INV ? cconj(v) : v;
     };
     Tile tile{s_tile};
-    fft_tile<R, N, NB, NT, true, C::PAD, false>(s_tw, 1, gload, gstore, tile);
+    fft_tile<R, N, NB, NT, true, C::PAD, false, C::PV>(s_tw, 1, gload, gstore, tile);
 }
 
-template <int N> static int run_y(const YArgs &a, hipStream_t s)
+template <int N, int V> static int run_yv(const YArgs &a, hipStream_t s)
 {
-    const int ntile = (a.M + YCfg<N>::NB - 1) / YCfg<N>::NB;
+    using C = YCfg<N, V>;
+    const int ntile = (a.M + C::NB - 1) / C::NB;
     const dim3 grid(ntile * a.nz, a.batch ? a.nbatch : 1);
     if (a.inverse)
-        hipLaunchKernelGGL((k_y<N, true>), grid, dim3(YCfg<N>::NT), 0, s, a);
+        hipLaunchKernelGGL((k_y<N, true, V>), grid, dim3(C::NT), 0, s, a);
     else
-        hipLaunchKernelGGL((k_y<N, false>), grid, dim3(YCfg<N>::NT), 0, s, a);
+        hipLaunchKernelGGL((k_y<N, false, V>), grid, dim3(C::NT), 0, s, a);
     return (int)hipGetLastError();
+}
+
+// short transforms have a single tile shape worth having
+template <int N> static int run_y(const YArgs &a, hipStream_t s)
+{
+    if constexpr (N < 64) {
+        return run_yv<N, 0>(a, s);
+    } else {
+        switch (a.variant & 3) {
+        case 1: return run_yv<N, 1>(a, s);
+        case 2: return run_yv<N, 2>(a, s);
+        case 3: return run_yv<N, 3>(a, s);
+        default: return run_yv<N, 0>(a, s);
+        }
+    }
 }
 
 }  // namespace PK_NS

@@ -378,23 +378,47 @@ using namespace PK_NS;
 
 int PK_SUFFIX(launch_z_walls)(const ZArgs &a, hipStream_t s)
 {
-    // chunk length L (registers), W columns per workgroup, W*ceil(nz/L)
-    // threads.  a.variant: 0 or 2 = chunks of 16 rows (default: shorter
-    // cross-chunk scans), 1 = chunks of 8 (fewer registers).
+    // Chunk length L (registers per thread), W columns per workgroup,
+    // W*ceil(nz/L) threads.  a.variant selects the tile (autotuned per shape):
+    //   0: 16-row chunks, 128-byte row runs (W = 16 FP32 / 8 FP64)
+    //   1: 8-row chunks (fewer registers, longer cross-chunk scans)
+    //   2: 16-row chunks, 256-byte row runs (W = 32 FP32 / 16 FP64)
+    //   3: 8-row chunks, 256-byte row runs
     const int nz = a.nz;
     constexpr bool F32 = sizeof(R) == 4;
-    const int chunk = a.variant == 1 ? 8 : 16;
+    const bool c8 = a.variant == 1 || a.variant == 3;
+    const bool wide = a.variant >= 2;
     if (nz <= 64) return run_zw<8, 32, 256>(a, s);
-    if (chunk == 16) {
-        if (nz <= 256) return run_zw<16, 16, 256>(a, s);
-        if (nz <= 512) return run_zw<16, 16, 512>(a, s);
+    if (!c8) {
         if constexpr (F32) {
-            if (nz <= 1024) return run_zw<16, 16, 1024>(a, s);
+            if (wide) {
+                if (nz <= 128) return run_zw<16, 32, 256>(a, s);
+                if (nz <= 256) return run_zw<16, 32, 512>(a, s);
+                if (nz <= 512) return run_zw<16, 32, 1024>(a, s);
+            } else {
+                if (nz <= 256) return run_zw<16, 16, 256>(a, s);
+                if (nz <= 512) return run_zw<16, 16, 512>(a, s);
+                if (nz <= 1024) return run_zw<16, 16, 1024>(a, s);
+            }
             if (nz <= 4096) return run_zw<16, 2, 1024>(a, s);
+        } else {
+            if (wide) {
+                if (nz <= 256) return run_zw<16, 16, 256>(a, s);
+                if (nz <= 512) return run_zw<16, 16, 512>(a, s);
+            } else {
+                if (nz <= 512) return run_zw<16, 8, 256>(a, s);
+                if (nz <= 1024) return run_zw<16, 8, 512>(a, s);
+            }
         }
     }
-    if (nz <= 256) return run_zw<8, 16, 512>(a, s);
-    if (nz <= 512) return run_zw<8, 16, 1024>(a, s);
+    if (wide && !F32) {
+        if (nz <= 256) return run_zw<8, 16, 512>(a, s);
+        if (nz <= 512) return run_zw<8, 16, 1024>(a, s);
+    }
+    if (wide && F32) {
+        if (nz <= 256) return run_zw<8, 32, 1024>(a, s);
+    }
+    if (nz <= 512) return run_zw<8, 8, 512>(a, s);
     if (nz <= 1024) return run_zw<8, 8, 1024>(a, s);
     if (nz <= 4096) return run_zw<8, 2, 1024>(a, s);
     return -1;

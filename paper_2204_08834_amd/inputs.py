@@ -141,6 +141,15 @@ def spectral_velocity_rhs(nx, ny, nz, Lx, Ly, Lz, bc_z, seed, smax, slope=-5.0 /
     seeded (seed, plane).  With walls, w on the top wall is set to zero.
     """
     import scipy.fft as sfft
+    import sys
+
+    # large grids take minutes: report progress on stderr as the synthesis goes
+    verbose = nx * ny * nz >= (1 << 28)
+
+    def note(msg):
+        if verbose:
+            print(f"[inputs] spectral synthesis {nx}x{ny}x{nz}: {msg}", file=sys.stderr,
+                  flush=True)
 
     nxh = nx // 2 + 1
     k0 = 2.0 * math.pi / Lx
@@ -189,6 +198,8 @@ def spectral_velocity_rhs(nx, ny, nz, Lx, Ly, Lz, bc_z, seed, smax, slope=-5.0 /
             sx, sy, sz = shifts[comp]
             phase = np.exp(1j * (kk[0] * sx + kk[1] * sy + kk[2] * sz))
             spec[comp][c] = vec[comp] * phase
+        if (c + 1) % 64 == 0:
+            note(f"modes of {c + 1}/{nz} kz planes")
 
     norm = nx * ny * nz
     vel = []
@@ -196,6 +207,7 @@ def spectral_velocity_rhs(nx, ny, nz, Lx, Ly, Lz, bc_z, seed, smax, slope=-5.0 /
         field_c = sfft.irfftn(spec[comp], s=(nz, ny, nx), axes=(0, 1, 2), workers=-1) * norm
         spec[comp] = None
         vel.append(field_c)
+        note(f"velocity component {comp + 1}/3 transformed")
     u, v, w = vel
     rms = math.sqrt(float((u * u).mean() + (v * v).mean() + (w * w).mean()) / 3.0)
     if rms > 0:

@@ -65,7 +65,7 @@ SYMBOLS = ["poisson_desc_init", "poisson_desc_validate", "poisson_workspace_byte
            "poisson_plan_create", "poisson_solve", "poisson_destroy",
            "poisson_batch_plan_create", "poisson_batch_solve", "poisson_error_string",
            "poisson_plan_set_timing", "poisson_plan_reset_timing", "poisson_plan_get_timing",
-           "poisson_plan_set_graph"]
+           "poisson_plan_set_graph", "poisson_plan_autotune", "poisson_plan_describe"]
 
 # refinement-loop drivers of poisson_plan_set_graph
 GRAPH_MODES = {"host": 0, "graph": 1, "device": 2}
@@ -99,6 +99,8 @@ def lib():
     L.poisson_plan_get_timing.argtypes = [P, ctypes.POINTER(PassStat), ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_int)]
     L.poisson_plan_set_graph.argtypes = [P, ctypes.c_int]
+    L.poisson_plan_autotune.argtypes = [P, ctypes.c_int]
+    L.poisson_plan_describe.argtypes = [P, ctypes.c_char_p, ctypes.c_int]
     for name in SYMBOLS:
         if name != "poisson_workspace_bytes" and name != "poisson_error_string":
             getattr(L, name).restype = ctypes.c_int
@@ -203,6 +205,12 @@ class Plan:
     def set_graph(self, mode="graph"):
         _set_graph(self._h, mode)
 
+    def autotune(self, force=False):
+        _autotune(self._h, force)
+
+    def describe(self):
+        return _describe(self._h)
+
     def close(self):
         if getattr(self, "_h", None):
             lib().poisson_destroy(self._h)
@@ -219,6 +227,23 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+TUNE_FORCE = 1
+
+
+def _autotune(h, force=False):
+    rc = lib().poisson_plan_autotune(h, TUNE_FORCE if force else 0)
+    if rc != OK:
+        raise PoissonError(rc, "poisson_plan_autotune")
+
+
+def _describe(h):
+    buf = ctypes.create_string_buffer(1 << 16)
+    rc = lib().poisson_plan_describe(h, buf, len(buf))
+    if rc != OK:
+        raise PoissonError(rc, "poisson_plan_describe")
+    return buf.value.decode()
 
 
 def _set_graph(h, mode):
@@ -281,6 +306,12 @@ class BatchPlan:
 
     def set_graph(self, mode="graph"):
         _set_graph(self._h, mode)
+
+    def autotune(self, force=False):
+        _autotune(self._h, force)
+
+    def describe(self):
+        return _describe(self._h)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -120,3 +120,10 @@ def test_set_graph_rejects_null_plan():
     L = P.lib()
     assert L.poisson_plan_set_graph(None, 1) == P.ERR_INVALID_ARG
     assert P.GRAPH_MODES == {"host": 0, "graph": 1, "device": 2}
+
+
+def test_autotune_and_describe_reject_null_plan():
+    L = P.lib()
+    assert L.poisson_plan_autotune(None, 0) == P.ERR_INVALID_ARG
+    buf = ctypes.create_string_buffer(64)
+    assert L.poisson_plan_describe(None, buf, 64) == P.ERR_INVALID_ARG

@@ -1,0 +1,88 @@
+"""GPU parity at the largest single-GPU size, 1024x1024x512 walls-in-z (box
+2x2x1), in the launch configuration bench.py times for that workload.
+
+At this size the oracle's O(n^2) DFTs are out of reach, so the checks are
+properties that hold at any size:
+  * exact discrete eigenmodes (closed form; built on the GPU): the solution
+    is f / lambda, FP64 to 1e-12, FP32 + refinement to 1e-9;
+  * a seeded U(-1,1) right-hand side: the oracle's FP64 7-point residual of
+    the returned field (on the host) is <= 1e-12 in FP64 and <= 1e-10 after
+    refinement, and the solution has zero mean.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2204_08834_amd import inputs  # noqa: E402
+
+NX, NY, NZ = 1024, 1024, 512
+LX, LY, LZ = 2.0, 2.0, 1.0
+NEU = 1
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_08834_amd import poisson
+    poisson.lib()  # raises if the HIP library is missing: no fallback
+    return poisson
+
+
+def _eigen_gpu(a, b, c):
+    """cos(2 pi a (i+1/2)/nx + 0.3) cos(2 pi b (j+1/2)/ny + 0.1) cos(pi c (k+1/2)/nz)
+    and its eigenvalue for the walls-in-z operator."""
+    dx, dy, dz = LX / NX, LY / NY, LZ / NZ
+    dev = "cuda"
+    i = torch.arange(NX, dtype=torch.float64, device=dev) + 0.5
+    j = torch.arange(NY, dtype=torch.float64, device=dev) + 0.5
+    k = torch.arange(NZ, dtype=torch.float64, device=dev) + 0.5
+    fx = torch.cos(2 * math.pi * a * i / NX + 0.3)
+    fy = torch.cos(2 * math.pi * b * j / NY + 0.1)
+    fz = torch.cos(math.pi * c * k / NZ)
+    f = fz[:, None, None] * fy[None, :, None] * fx[None, None, :]
+    lam = (-4 / dx ** 2 * math.sin(math.pi * a / NX) ** 2
+           - 4 / dy ** 2 * math.sin(math.pi * b / NY) ** 2
+           - 4 / dz ** 2 * math.sin(math.pi * c / (2 * NZ)) ** 2)
+    return f.contiguous(), lam, (dx, dy, dz)
+
+
+@pytest.mark.parametrize("modes", [(1, 0, 0), (0, 0, 1), (3, 5, 7), (512, 512, 511)])
+def test_eigenmode_1024(modes):
+    P = _gpu()
+    f, lam, sp = _eigen_gpu(*modes)
+    ref = f / lam
+    for prec, tol in (("fp64", 1e-12), ("fp32_refine", 1e-9)):
+        print(f"[1024] eigenmode {modes} {prec}", flush=True)
+        with P.Plan(NX, NY, NZ, *sp, NEU, prec) as plan:
+            p, st = plan.solve(f)
+            err = (torch.linalg.vector_norm(p - ref) / torch.linalg.vector_norm(ref)).item()
+        print(f"[1024] eigenmode {modes} {prec}: error {err:.2e} stats {st}", flush=True)
+        assert err <= tol, (prec, err)
+        del p
+    torch.cuda.empty_cache()
+
+
+def test_residual_1024(orc):
+    P = _gpu()
+    print("[1024] generating the right-hand side", flush=True)
+    f = inputs.random_rhs(NX, NY, NZ, seed=77, zero_mean=False)
+    dx, dy, dz = LX / NX, LY / NY, LZ / NZ
+    rhs = torch.from_numpy(f).cuda()
+    for prec, tol in (("fp64", 1e-12), ("fp32_refine", 1e-10)):
+        with P.Plan(NX, NY, NZ, dx, dy, dz, NEU, prec) as plan:
+            out, st = plan.solve(rhs)
+            torch.cuda.synchronize()
+        p = out.cpu().numpy()
+        del out
+        res, _ = orc.residual(f, p, dx, dy, dz, NEU)
+        print(f"[1024] {prec}: oracle residual {res:.3e}, stats {st}", flush=True)
+        assert res <= tol
+        assert abs(p.mean()) <= 1e-13 * np.abs(p).max()
+        assert abs(st["rhs_mean"] - f.mean()) <= 1e-12
+    del rhs
+    torch.cuda.empty_cache()

@@ -347,3 +347,23 @@ def test_batch_partial_convergence_and_errors():
     assert stats[1]["status"] == P.ERR_NONFINITE
     for i in (0, 2, 3, 4):
         assert stats[i]["status"] == 0 and stats[i]["rel_residual"] <= 1e-10
+
+
+ZCASES = [(64, 48, 20), (24, 12, 33), (8, 4, 300), (32, 32, 130), (16, 8, 520)]
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_zwalls_tile_variants(orc, variant, monkeypatch):
+    """Every tile variant of the wall-bounded z solve (the autotuner's
+    choices) matches the oracle: FP64 to 1e-12, FP32 + refinement to a
+    1e-10 residual."""
+    monkeypatch.setenv("POISSON_ZWALLS_VARIANT", str(variant))
+    for nx, ny, nz in ZCASES:
+        f = inputs.uniform_velocity_rhs(nx, ny, nz, 2.0, 2.0, 1.0, NEU, 7)
+        sp = (2.0 / nx, 2.0 / ny, 1.0 / nz)
+        p_ref = orc.solve(f, *sp, NEU)
+        p, _ = gpu_solve(f, *sp, NEU, "fp64")
+        assert rel(p, p_ref) <= 1e-12, (variant, nx, ny, nz)
+        q, st = gpu_solve(f, *sp, NEU, "fp32_refine")
+        res, _ = orc.residual(f, q, *sp, NEU)
+        assert st["status"] == 0 and res <= 1e-10, (variant, nx, ny, nz, res)
