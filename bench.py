@@ -177,8 +177,8 @@ PASS_PATTERNS = [
     ("x_r2c_{p}", r"prec_{p}::k_x_fwd<\d+, false>"),
     ("x_c2r_accumulate_{p}", r"prec_{p}::k_x_inv<\d+, true>"),
     ("x_c2r_{p}", r"prec_{p}::k_x_inv<\d+, false>"),
-    ("y_fwd_{p}", r"prec_{p}::k_y<\d+, false>"),
-    ("y_inv_{p}", r"prec_{p}::k_y<\d+, true>"),
+    ("y_fwd_{p}", r"prec_{p}::k_y<\d+, false[,>]"),
+    ("y_inv_{p}", r"prec_{p}::k_y<\d+, true[,>]"),
     ("z_walls_{p}", r"prec_{p}::k_z_walls<"),
     ("z_periodic_{p}", r"prec_{p}::k_z_per<"),
 ]

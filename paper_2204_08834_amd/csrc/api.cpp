@@ -1082,10 +1082,9 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
 // ---------------------------------------------------------------------------
 // Times the launch variants of one shape group on scratch fields of that
 // shape (one problem, zero data: the passes are bandwidth-bound and take no
-// data-dependent paths) and keeps the fastest: the z-solve tile, then the y
-// tile and radix order, then the block order over the whole pass sequence
-// (which decides how much of each pass's input is still in the last-level
-// cache).  Each candidate: one warm-up launch, then the mean of three.
+// data-dependent paths) and keeps the fastest, one knob after the other: the
+// z-solve tile, the y tile and radix order, the block order.  Each candidate
+// is scored on the whole pass sequence (one warm-up, then the mean of three).
 int autotune_group(poisson_plan p, Group &g)
 {
     const int prec = internal_prec(p->precision);
@@ -1135,14 +1134,13 @@ int autotune_group(poisson_plan p, Group &g)
         }
         knob = best;
     };
-    if (g.d.bc_z == POISSON_BC_NEUMANN) pick(g.tune.zv, 4, [&] { return pass_z(L); });
-    if (g.d.ny >= 64) {
-        pick(g.tune.yv, 4, [&] {
-            const int r = pass_y(L, false);
-            return r ? r : pass_y(L, true);
-        });
-    }
-    pick(g.tune.rev, 2, [&] { return solve_passes(L, false, false); });
+    // every candidate is scored on the whole pass sequence: how fast a pass
+    // runs depends on how much of its input the previous pass left in the
+    // last-level cache
+    auto whole = [&] { return solve_passes(L, false, false); };
+    if (g.d.bc_z == POISSON_BC_NEUMANN) pick(g.tune.zv, 4, whole);
+    if (g.d.ny >= 64) pick(g.tune.yv, 4, whole);
+    pick(g.tune.rev, 2, whole);
     g.tune.tuned = true;
     (void)hipStreamSynchronize(p->stream);
     (void)hipEventDestroy(e0);

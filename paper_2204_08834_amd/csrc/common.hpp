@@ -20,6 +20,42 @@ struct Cx {
     R re, im;
 };
 
+// Loads and stores of device fields through the global address space.
+// Pointers that reach a kernel through memory (the per-problem pointer table
+// of batched launches) or through structs are generic to the compiler, which
+// then emits flat instructions; flat loads also count against the LDS wait
+// counter, so every LDS wait of an FFT or stencil tile would also wait for
+// the outstanding HBM loads.  All fields live in device memory.
+// The cast has to be applied to the base pointer, before any offset
+// arithmetic (a cast of a derived generic pointer is folded back into a
+// flat access), hence gbl() at the point where a kernel obtains a pointer.
+// (device compilation pass only; the host pass parses the same templates
+// with plain pointers)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define PK_GLOBAL __attribute__((address_space(1)))
+#else
+#define PK_GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ PK_GLOBAL T *gbl(T *p)
+{
+    return (PK_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ const PK_GLOBAL T *gbl(const T *p)
+{
+    return (const PK_GLOBAL T *)p;
+}
+// store of a complex value through a global pointer (member-wise: the
+// implicit assignment operator does not take an address-space-qualified
+// object; the two stores are merged into one vector store)
+template <typename R>
+__device__ __forceinline__ void put(PK_GLOBAL Cx<R> *p, Cx<R> v)
+{
+    p->re = v.re;
+    p->im = v.im;
+}
+
 enum Prec { P_F64 = 0, P_F32 = 1 };
 
 // Block order.  A pass whose input was just written by the previous pass

@@ -56,13 +56,14 @@ bool fft_length_supported(int n)
 // Sum of the three sums of n partial records (stride 4 doubles): thread t
 // adds records t, t+1024, ... in a fixed order, then a fixed-shape tree
 // finishes; bitwise reproducible for a given n.  Every thread gets the totals.
-__device__ __forceinline__ void sum_records(const double *in, int n, double (*sh)[1024],
+__device__ __forceinline__ void sum_records(const double *in_, int n, double (*sh)[1024],
                                             double &s0, double &s1, double &s2)
 {
     const int t = threadIdx.x;
+    const PK_GLOBAL double *in = gbl(in_);
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     for (int i = t; i < n; i += 1024) {
-        const double4 v = *(const double4 *)(in + 4 * (size_t)i);
+        const double4 v = *(const PK_GLOBAL double4 *)(in + 4 * (size_t)i);
         a0 += v.x;
         a1 += v.y;
         a2 += v.z;
@@ -198,8 +199,8 @@ __global__ __launch_bounds__(RC_NT) void k_residual_check(XFwdArgs a0)
     const int k0 = kb * kr;
     const int k1 = k0 + kr < a.nz ? k0 + kr : a.nz;
     Mar m;
-    m.f = a.f;
-    m.p = a.p;
+    m.f = gbl(a.f);
+    m.p = gbl(a.p);
     m.ax = a.ax;
     m.ay = a.ay;
     m.az = a.az;

@@ -128,17 +128,17 @@ __device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R,
             }
             Bfly<R, RAD>::run(v1);
             Bfly<R, RAD>::run(v2);
-            Cx<R> *Sr = out(b);
+            PK_GLOBAL Cx<R> *Sr = out(b);
             if (!Sr) continue;
             auto emit = [&](int m, Cx<R> zm, Cx<R> zc) {
                 Cx<R> xm, xc;
                 split_pair(zm, zc, tw[m], xm, xc);
-                Sr[m] = xm;
-                if (2 * m != M) Sr[M - m] = xc;
+                put(Sr + m, xm);
+                if (2 * m != M) put(Sr + (M - m), xc);
             };
             if (pp == 0) {
                 // butterfly 0: m = r NJ; m = 0 packs X(0) + i X(M)
-                Sr[0] = {v1[0].re + v1[0].im, v1[0].re - v1[0].im};
+                put(Sr, Cx<R>{v1[0].re + v1[0].im, v1[0].re - v1[0].im});
 #pragma unroll
                 for (int r = 1; r < RAD; ++r)
                     if (r <= RAD - r) emit(r * NJ, v1[r], v1[RAD - r]);
@@ -157,15 +157,15 @@ __device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R,
         // split the M-point spectrum into the half spectrum of the real rows
         for (int u = threadIdx.x; u < NB * M; u += NT) {
             const int b = u / M, m = u % M;
-            Cx<R> *Sr = out(b);
+            PK_GLOBAL Cx<R> *Sr = out(b);
             if (!Sr) continue;
             const Cx<R> zm = tile.at(b, m);
             if (m == 0) {
-                Sr[0] = {zm.re + zm.im, zm.re - zm.im};
+                put(Sr, Cx<R>{zm.re + zm.im, zm.re - zm.im});
             } else {
                 Cx<R> xm, xc;
                 split_pair(zm, tile.at(b, M - m), tw[m], xm, xc);
-                Sr[m] = xm;
+                put(Sr + m, xm);
             }
         }
     }
@@ -200,12 +200,13 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
 
     double acc0 = 0.0;
     Tile tile{s_tile};
-    Cx<R> *S = (Cx<R> *)a.S;
+    PK_GLOBAL Cx<R> *S = gbl((Cx<R> *)a.S);
+    const PK_GLOBAL double *gf = gbl(a.f);
     auto loader = [&](int row0) {
         return [&, row0](int b, int n) -> Cx<R> {
             const int row = row0 + b;
             if (row >= nrows) return {R(0), R(0)};
-            const double2 fv = *(const double2 *)(a.f + (size_t)row * NX + 2 * n);
+            const double2 fv = *(const PK_GLOBAL double2 *)(gf + (size_t)row * NX + 2 * n);
             acc0 += fv.x + fv.y;
             return {R(fv.x), R(fv.y)};
         };
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
                 in.load(gl);
             }
             __syncthreads();
-            auto out = [&](int b) -> Cx<R> * {
+            auto out = [&](int b) -> PK_GLOBAL Cx<R> * {
                 const int row = row0 + b;
                 return row < nrows ? S + (size_t)row * M : nullptr;
             };
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
         for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
             const int row0 = block_order(blk, nblk, a.reverse) * NB;
             auto gl = loader(row0);
-            auto out = [&](int b) -> Cx<R> * {
+            auto out = [&](int b) -> PK_GLOBAL Cx<R> * {
                 const int row = row0 + b;
                 return row < nrows ? S + (size_t)row * M : nullptr;
             };
@@ -301,8 +302,8 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
     const int k1 = k0 + kr < a.nz ? k0 + kr : a.nz;
 
     Mar m;
-    m.f = a.f;
-    m.p = a.p;
+    m.f = gbl(a.f);
+    m.p = gbl(a.p);
     m.ax = a.ax;
     m.ay = a.ay;
     m.az = a.az;
@@ -313,7 +314,7 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
     m.start(k0);
 
     Tile tile{(Cx<R> *)s_buf};
-    Cx<R> *S = (Cx<R> *)a.S;
+    PK_GLOBAL Cx<R> *S = gbl((Cx<R> *)a.S);
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
     for (int k = k0; k < k1; ++k) {
         __syncthreads();  // the previous plane's transform is done with the tile
@@ -327,17 +328,13 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
         m.step(k, sink);
         __syncthreads();  // the march is done reading the plane tile
 #pragma unroll
-        for (int q = 0; q < Mar::PER; ++q) {
-            if (m.valid(q)) {
-                const int e = m.elem(q), t = e / M, h = e - t * M;
-                tile.at(t, h) = rr[q];
-            }
-        }
+        for (int q = 0; q < Mar::PER; ++q)
+            if (m.valid(q)) tile.at(m.row_of(q), m.pair_of(q)) = rr[q];
         __syncthreads();
         auto gload = [&](int b, int n) -> Cx<R> { return tile.at(b, n); };
         const size_t rowk = (size_t)k * a.ny + m.j0;
         const int V = m.V;
-        auto out = [&](int b) -> Cx<R> * { return b < V ? S + (rowk + b) * M : nullptr; };
+        auto out = [&](int b) -> PK_GLOBAL Cx<R> * { return b < V ? S + (rowk + b) * M : nullptr; };
         x_forward<M, TJ, NT, true>(s_tw, gload, tile, out);
     }
     block_sum3(acc0, acc1, acc2, s_red);
@@ -373,11 +370,12 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
     load_table(s_tw, (const Cx<R> *)a.tw, NX);
     __syncthreads();
 
-    const Cx<R> *S = (const Cx<R> *)a.S;
+    const PK_GLOBAL Cx<R> *S = gbl((const Cx<R> *)a.S);
+    PK_GLOBAL double *gp = gbl(a.p);
     auto gstore = [&](int b, int n, Cx<R> v) {
         const int row = row0 + b;
         if (row >= nrows) return;
-        double2 *dst = (double2 *)(a.p + (size_t)row * NX + 2 * n);
+        PK_GLOBAL double2 *dst = (PK_GLOBAL double2 *)(gp + (size_t)row * NX + 2 * n);
         double2 o = {double(v.re), -double(v.im)};
         if constexpr (ACC) {
             const double2 old = *dst;
@@ -408,7 +406,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
             const int row = row0 + b;
             Cx<R> v1[RAD], v2[RAD];
             if (row < nrows) {
-                const Cx<R> *sr = S + (size_t)row * M;
+                const PK_GLOBAL Cx<R> *sr = S + (size_t)row * M;
 #pragma unroll
                 for (int r = 0; r < RAD; ++r) {
                     v1[r] = sr[j1 + r * NJ];
@@ -451,7 +449,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
         auto gload = [&](int b, int n) -> Cx<R> {
             const int row = row0 + b;
             if (row >= nrows) return {R(0), R(0)};
-            const Cx<R> *sr = S + (size_t)row * M;
+            const PK_GLOBAL Cx<R> *sr = S + (size_t)row * M;
             if (n == 0) {
                 const Cx<R> s0 = sr[0];
                 return {s0.re + s0.im, -(s0.re - s0.im)};

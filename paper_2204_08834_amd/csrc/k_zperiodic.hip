@@ -54,7 +54,7 @@ __global__ __launch_bounds__(ZPCfg<N>::NT) void k_z_per(ZArgs a0, int nspecial)
     const int M = a.M, ny = a.ny;
     const int ncol = ny * M;
     const size_t plane = (size_t)ncol;
-    Cx<R> *S = (Cx<R> *)a.S;
+    PK_GLOBAL Cx<R> *S = gbl((Cx<R> *)a.S);
     Tile tile{s_tile};
     auto lstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
 

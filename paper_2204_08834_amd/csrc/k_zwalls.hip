@@ -89,7 +89,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
     const int w = t % W, c = t / W;
     const int nz = a.nz, M = a.M, ny = a.ny;
     const size_t plane = (size_t)ny * M;
-    Cx<R> *S = (Cx<R> *)a.S;
+    PK_GLOBAL Cx<R> *S = gbl((Cx<R> *)a.S);
     const int s = c * L;
     const int e = (s + L < nz) ? s + L : nz;  // chunk rows [s, e)
     const bool special = (int)blockIdx.x < nspecial;
@@ -106,10 +106,15 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
         ky = q / M;
         active = (q < ny * M) && (m != 0);
         s_d = active ? -(a.lamx[m] + a.lamy[ky]) * a.dz2 : 1.0;
-        const Cx<R> *col = S + (size_t)s * plane + (active ? q : 0);
+        const PK_GLOBAL Cx<R> *col = S + (size_t)s * plane + (active ? q : 0);
 #pragma unroll
         for (int i = 0; i < L; ++i)
-            d[i] = (active && s + i < nz) ? col[(size_t)i * plane] : Cx<R>{R(0), R(0)};
+            if (active && s + i < nz) {
+                const PK_GLOBAL Cx<R> &v = col[(size_t)i * plane];
+                d[i] = Cx<R>{v.re, v.im};
+            } else {
+                d[i] = Cx<R>{R(0), R(0)};
+            }
     } else {
         const int vc = (int)blockIdx.x * W + w;
         const int pair = vc >> 1;
@@ -120,8 +125,8 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
         zero_lane = active && pair == 0 && part == 0;
         const double lx = part ? a.lamx[M] : a.lamx[0];
         s_d = (active && !zero_lane) ? -(lx + a.lamy[ky]) * a.dz2 : 1.0;
-        const Cx<R> *c1 = S + (size_t)s * plane + (size_t)ky * M;
-        const Cx<R> *c2 = S + (size_t)s * plane + (size_t)kyn * M;
+        const PK_GLOBAL Cx<R> *c1 = S + (size_t)s * plane + (size_t)ky * M;
+        const PK_GLOBAL Cx<R> *c2 = S + (size_t)s * plane + (size_t)kyn * M;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             const int k = s + i;
@@ -333,14 +338,14 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
     // ---- store ------------------------------------------------------------
     if (!special) {
         if (active) {
-            Cx<R> *col = S + (size_t)s * plane + q;
+            PK_GLOBAL Cx<R> *col = S + (size_t)s * plane + q;
 #pragma unroll
             for (int i = 0; i < L; ++i)
                 if (s + i < nz) col[(size_t)i * plane] = d[i];
         }
     } else {
         // lane pairs (A, B) of one ky are adjacent: exchange and recombine
-        Cx<R> *col = S + (size_t)s * plane + (size_t)(part == 0 ? ky : kyn) * M;
+        PK_GLOBAL Cx<R> *col = S + (size_t)s * plane + (size_t)(part == 0 ? ky : kyn) * M;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             const R ore = __shfl_xor(d[i].re, 1, 64);

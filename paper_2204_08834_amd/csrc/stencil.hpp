@@ -45,7 +45,7 @@ struct PlaneMarch {
     static constexpr int PER = (E + NT - 1) / NT;
     static constexpr bool EXACT = (E % NT) == 0;
 
-    const double *f, *p;
+    const PK_GLOBAL double *f, *p;  // set through gbl()
     int ny, nz, bc_z;
     double ax, ay, az, mu;
     int j0, V;     // first y-row and number of valid rows of this block
@@ -54,17 +54,38 @@ struct PlaneMarch {
     double2 (*tile)[M];  // LDS, TJ + 2 rows
     double2 pd[PER], pc[PER];
 
+    // Element q of a thread is (row t, pair h) with e = threadIdx.x + q NT,
+    // t = e / M, h = e % M.  When NT divides M (ROWSPLIT) the row of element q
+    // is the same for the whole workgroup (t = q / (M/NT)), so the row offset
+    // is a uniform value and only the pair offset varies per lane.
+    static constexpr bool ROWSPLIT = (M % NT) == 0;
+    static constexpr int SPR = ROWSPLIT ? M / NT : 1;  // elements per row and thread
+
     __device__ __forceinline__ int elem(int q) const { return threadIdx.x + q * NT; }
+    __device__ __forceinline__ int row_of(int q) const
+    {
+        return ROWSPLIT ? q / SPR : elem(q) / M;
+    }
+    __device__ __forceinline__ int pair_of(int q) const
+    {
+        return ROWSPLIT ? (int)threadIdx.x + (q % SPR) * NT : elem(q) - (elem(q) / M) * M;
+    }
     __device__ __forceinline__ bool valid(int q) const
     {
+        if constexpr (ROWSPLIT) return q / SPR < V;
         const int e = elem(q);
         return (EXACT || e < E) && e / M < V;
     }
-    // offset of element q within a plane
+    // offset of element q within a plane; rows past the grid are clamped to
+    // the first row of the block (loaded, never used): branch-free loads
     __device__ __forceinline__ int roff(int q) const
     {
+        if constexpr (ROWSPLIT) {
+            const int t = q / SPR < V ? q / SPR : 0;
+            return (j0 + t) * NX + 2 * pair_of(q);
+        }
         const int e = elem(q), t = e / M, h = e - t * M;
-        return (j0 + t) * NX + 2 * h;
+        return valid(q) ? (j0 + t) * NX + 2 * h : 0;
     }
     __device__ __forceinline__ int kdown(int k) const
     {
@@ -92,14 +113,13 @@ struct PlaneMarch {
     // branch-free loads.
     __device__ __forceinline__ void start(int k0)
     {
-        const double *pdn = p + (size_t)kdown(k0) * plane;
-        const double *pcn = p + (size_t)k0 * plane;
+        const PK_GLOBAL double *pdn = p + (size_t)kdown(k0) * plane;
+        const PK_GLOBAL double *pcn = p + (size_t)k0 * plane;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const bool ok = valid(q);
-            const int o = ok ? roff(q) : 0;
-            pd[q] = *(const double2 *)(pdn + o);
-            pc[q] = *(const double2 *)(pcn + o);
+            const int o = roff(q);
+            pd[q] = *(const PK_GLOBAL double2 *)(pdn + o);
+            pc[q] = *(const PK_GLOBAL double2 *)(pcn + o);
         }
     }
 
@@ -109,33 +129,28 @@ struct PlaneMarch {
     template <class Sink>
     __device__ __forceinline__ void step(int k, Sink &sink)
     {
-        const double *pup = p + (size_t)kup(k) * plane;
-        const double *fk = f + (size_t)k * plane;
-        const double *pk_ = p + (size_t)k * plane;
+        const PK_GLOBAL double *pup = p + (size_t)kup(k) * plane;
+        const PK_GLOBAL double *fk = f + (size_t)k * plane;
+        const PK_GLOBAL double *pk_ = p + (size_t)k * plane;
         double2 pu[PER], fv[PER];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const bool ok = valid(q);
-            const int o = ok ? roff(q) : 0;
-            pu[q] = *(const double2 *)(pup + o);
-            fv[q] = *(const double2 *)(fk + o);
+            const int o = roff(q);
+            pu[q] = *(const PK_GLOBAL double2 *)(pup + o);
+            fv[q] = *(const PK_GLOBAL double2 *)(fk + o);
         }
         for (int h = threadIdx.x; h < M; h += NT) {
-            tile[0][h] = *(const double2 *)(pk_ + (size_t)jm * NX + 2 * h);
-            tile[V + 1][h] = *(const double2 *)(pk_ + (size_t)jn * NX + 2 * h);
+            tile[0][h] = *(const PK_GLOBAL double2 *)(pk_ + (size_t)jm * NX + 2 * h);
+            tile[V + 1][h] = *(const PK_GLOBAL double2 *)(pk_ + (size_t)jn * NX + 2 * h);
         }
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            if (valid(q)) {
-                const int e = elem(q), t = e / M, h = e - t * M;
-                tile[t + 1][h] = pc[q];
-            }
-        }
+        for (int q = 0; q < PER; ++q)
+            if (valid(q)) tile[row_of(q) + 1][pair_of(q)] = pc[q];
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             if (valid(q)) {
-                const int e = elem(q), t = e / M, h = e - t * M;
+                const int t = row_of(q), h = pair_of(q);
                 const double2 ps = tile[t][h], pn = tile[t + 2][h];
                 const double pl = tile[t + 1][h == 0 ? M - 1 : h - 1].y;
                 const double pq = tile[t + 1][h == M - 1 ? 0 : h + 1].x;
