@@ -173,8 +173,8 @@ def copy_calibration(steps, warmup):
 
 # kernel-name patterns of the solver's passes (rocprofv3 reports demangled names)
 PASS_PATTERNS = [
-    ("x_r2c_residual_{p}", r"prec_{p}::k_x_fwd<\d+, true>"),
-    ("x_r2c_{p}", r"prec_{p}::k_x_fwd<\d+, false>"),
+    ("x_r2c_residual_{p}", r"prec_{p}::k_x_res<"),
+    ("x_r2c_{p}", r"prec_{p}::k_x_fwd<"),
     ("x_c2r_accumulate_{p}", r"prec_{p}::k_x_inv<\d+, true>"),
     ("x_c2r_{p}", r"prec_{p}::k_x_inv<\d+, false>"),
     ("y_fwd_{p}", r"prec_{p}::k_y<\d+, false[,>]"),
@@ -223,22 +223,29 @@ def summarize_counters(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, out_p
         return statistics.median(xs) * 1024.0
     f_scale = COPY_BYTES / cal(cfetch, "FETCH_SIZE")
     w_scale = COPY_BYTES / cal(cwrite, "WRITE_SIZE")
+    def working(vs):
+        # dispatches that did the pass's work: gated-off launches of the
+        # device-side loop exit at once and read almost nothing
+        top = max(vs)
+        return [v for v in vs if v >= 0.1 * top]
+
     per_pass = {}
     for (k, c), vs in fetch.items():
         ps = pass_of_kernel(k)
         if ps and c == "FETCH_SIZE":
-            per_pass.setdefault(ps, {})["fetch"] = statistics.median(vs) * 1024.0
+            per_pass.setdefault(ps, {})["fetch"] = statistics.median(working(vs)) * 1024.0
     for (k, c), vs in write.items():
         ps = pass_of_kernel(k)
         if ps and c == "WRITE_SIZE":
-            per_pass.setdefault(ps, {})["write"] = statistics.median(vs) * 1024.0
+            per_pass.setdefault(ps, {})["write"] = statistics.median(working(vs)) * 1024.0
     lines = ["# HBM traffic per dispatch, rocprofv3 counters, 512x512x256 walls-in-z (rb512)",
              "# commands (from the repository root; rocprofv3 runs after "
              "`cd /tmp && export TMPDIR=/tmp`):"]
     lines += ["#   " + c for c in commands]
     lines += [f"# calibration: 1 GiB elementwise kernel reads FETCH_SIZE x {f_scale:.4f}, "
               f"WRITE_SIZE x {w_scale:.4f} of its true bytes",
-              "# bytes below = counter KiB x 1024 x scale, median over dispatches",
+              "# bytes below = counter KiB x 1024 x scale, median over the dispatches that did "
+              "the pass's work (gated-off launches of the device-side loop excluded)",
               f"source_hash = {kernel_hash()}",
               f"fetch_scale = {f_scale:.6f}", f"write_scale = {w_scale:.6f}"]
     for ps in sorted(per_pass):
@@ -250,25 +257,38 @@ def summarize_counters(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, out_p
     print("\n".join(lines))
 
 
-def summarize_kernels(stats_csv, out_path, commands):
-    """Write the per-kernel duration summary from a rocprofv3 --stats
-    kernel_stats.csv, with each kernel's pass name."""
+def summarize_kernels(trace_csv, out_path, commands):
+    """Write the per-kernel duration summary from a rocprofv3 kernel_trace.csv:
+    dispatches, average / min / max duration of the dispatches that did the
+    pass's work (gated-off launches of the device-side loop, which exit at
+    once, are counted apart), share of the total, and the pass name."""
     import csv
-    with open(stats_csv) as fh:
-        rows = list(csv.DictReader(fh))
-    lines = ["# rocprofv3 kernel statistics, 512x512x256 walls-in-z (rb512): every dispatch of "
-             "the run (warmup, timed steps, per-pass timing, FP32+refine and FP64 plans)",
+    per = {}
+    with open(trace_csv) as fh:
+        for r in csv.DictReader(fh):
+            d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            per.setdefault(r["Kernel_Name"], []).append(d)
+    total = sum(sum(v) for v in per.values())
+    rows = []
+    for name, ds in per.items():
+        top = max(ds)
+        work = [d for d in ds if d >= 0.1 * top]
+        rows.append((sum(ds), name, len(ds), len(ds) - len(work), sum(work) / len(work), min(work),
+                     max(work)))
+    rows.sort(reverse=True)
+    lines = ["# rocprofv3 kernel trace, 512x512x256 walls-in-z (rb512): every dispatch of the "
+             "run (warmup, timed steps, per-pass timing, FP32+refine and FP64 plans)",
              "# commands (from the repository root; rocprofv3 runs after "
              "`cd /tmp && export TMPDIR=/tmp`):"]
     lines += ["#   " + c for c in commands]
     lines.append(f"# source_hash = {kernel_hash()}")
-    lines.append(f"{'pass':22s} {'calls':>5s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} "
-                 f"{'pct':>6s}  kernel")
-    for r in rows:
-        name = r["Name"]
-        lines.append(f"{pass_of_kernel(name) or '-':22s} {int(r['Calls']):5d} "
-                     f"{float(r['AverageNs']) / 1e3:9.2f} {float(r['MinNs']) / 1e3:9.2f} "
-                     f"{float(r['MaxNs']) / 1e3:9.2f} {float(r['Percentage']):6.2f}  {name[:70]}")
+    lines.append("# avg/min/max over the dispatches that did the pass's work; 'gated' counts "
+                 "launches of the device-side loop that exited at once")
+    lines.append(f"{'pass':22s} {'calls':>5s} {'gated':>5s} {'avg_us':>9s} {'min_us':>9s} "
+                 f"{'max_us':>9s} {'pct':>6s}  kernel")
+    for tot, name, n, ng, avg, mn, mx in rows:
+        lines.append(f"{pass_of_kernel(name) or '-':22s} {n:5d} {ng:5d} {avg:9.2f} {mn:9.2f} "
+                     f"{mx:9.2f} {100.0 * tot / total:6.2f}  {name[:70]}")
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -282,6 +302,9 @@ def main():
     ap.add_argument("--workload", default="rb512", choices=sorted(DESCRIPTIONS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the captured-graph loop timing (profiling runs: its gated-off "
+                         "launches would mix into the per-kernel statistics)")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the default launch variants (no plan-time autotuning)")
     ap.add_argument("--batch-only", action="store_true",
@@ -299,9 +322,9 @@ def main():
                     help="write the HBM traffic summary from rocprofv3 --pmc FETCH_SIZE / "
                          "WRITE_SIZE counter_collection.csv files of a solve run and of a "
                          "--copy-calibration run")
-    ap.add_argument("--summarize-kernels", nargs=2, metavar=("STATS_CSV", "OUT"),
-                    help="write the per-kernel duration summary from a rocprofv3 --stats "
-                         "kernel_stats.csv")
+    ap.add_argument("--summarize-kernels", nargs=2, metavar=("TRACE_CSV", "OUT"),
+                    help="write the per-kernel duration summary from a rocprofv3 "
+                         "kernel_trace.csv")
     ap.add_argument("--command", action="append", default=[],
                     help="with --summarize-*: a command to record in the summary")
     args = ap.parse_args()
@@ -371,12 +394,14 @@ def main():
         passes = plan.timing()
         plan.set_timing(False)
         # the same solves through the captured-graph loop
-        plan.set_graph("graph")
-        for _ in range(args.warmup):
-            plan.solve(rhs, out)
-        msg, stg = time_solves(plan, rhs, out, args.steps, sync_each=True)
-        result["fp32refine_graph_loop"] = {"ms_per_step": msg, "mpoints_s": npts / (msg * 1e-3) / 1e6,
-                                           "rel_residual": stg["rel_residual"]}
+        if not args.no_graph:
+            plan.set_graph("graph")
+            for _ in range(args.warmup):
+                plan.solve(rhs, out)
+            msg, stg = time_solves(plan, rhs, out, args.steps, sync_each=True)
+            result["fp32refine_graph_loop"] = {"ms_per_step": msg,
+                                               "mpoints_s": npts / (msg * 1e-3) / 1e6,
+                                               "rel_residual": stg["rel_residual"]}
         plan.close()
         result["value"] = npts / (ms32 * 1e-3) / 1e6
         result["ms_per_step"] = ms32
