@@ -167,6 +167,7 @@ int upload_complex(std::shared_ptr<DevBuf> out[2], const std::vector<double> &tw
 // read what the previous pass just wrote (block_order).
 struct Tune {
     int zv = 0, yv = 0, rev = 1;
+    int kr = 8;          // z-planes per workgroup of the residual passes (plane march)
     bool tuned = false;  // chosen by timing (else the defaults below)
 };
 
@@ -189,6 +190,10 @@ void apply_env_overrides(Tune &t)
     if (const char *e = getenv("POISSON_ZWALLS_VARIANT")) t.zv = atoi(e) & 3;
     if (const char *e = getenv("POISSON_Y_VARIANT")) t.yv = atoi(e) & 3;
     if (const char *e = getenv("POISSON_BLOCK_ORDER")) t.rev = strcmp(e, "forward") == 0 ? 0 : 1;
+    if (const char *e = getenv("POISSON_MARCH_PLANES")) {
+        const int k = atoi(e);
+        if (k == 4 || k == 8 || k == 16) t.kr = k;
+    }
 }
 
 // process-wide cache of tuned variants: key "precision nx ny nz bc device"
@@ -212,7 +217,7 @@ std::string tune_key(const poisson_desc_t &d)
 }
 
 // optional persistence: POISSON_TUNE_CACHE names a text file of lines
-// "<key> : zv yv rev"
+// "<key> : zv yv rev kr"
 void load_tune_file()
 {
     if (tune_file_loaded) return;
@@ -229,10 +234,12 @@ void load_tune_file()
         std::string key(line);
         while (!key.empty() && key.back() == ' ') key.pop_back();
         Tune t;
-        if (sscanf(colon + 1, "%d %d %d", &t.zv, &t.yv, &t.rev) == 3) {
+        const int got = sscanf(colon + 1, "%d %d %d %d", &t.zv, &t.yv, &t.rev, &t.kr);
+        if (got >= 3) {
             t.zv &= 3;
             t.yv &= 3;
             t.rev = t.rev ? 1 : 0;
+            if (got < 4 || !(t.kr == 4 || t.kr == 8 || t.kr == 16)) t.kr = 8;
             t.tuned = true;
             tune_cache[key] = t;
         }
@@ -247,7 +254,8 @@ void save_tune_file()
     FILE *fp = fopen(path, "w");
     if (!fp) return;
     for (auto &kv : tune_cache)
-        fprintf(fp, "%s : %d %d %d\n", kv.first.c_str(), kv.second.zv, kv.second.yv, kv.second.rev);
+        fprintf(fp, "%s : %d %d %d %d\n", kv.first.c_str(), kv.second.zv, kv.second.yv,
+                kv.second.rev, kv.second.kr);
     fclose(fp);
 }
 
@@ -281,9 +289,7 @@ struct Group {
     std::vector<int> members;          // problem indices in the plan
     std::shared_ptr<DevBuf> S32;       // FP32 spectra, one per member
     std::shared_ptr<DevBuf> partials;  // per-workgroup partial sums, part_stride per member
-    int npart = 0;                     // workgroups of the forward x pass
-    int nres = 0;                      // workgroups of the residual x pass
-    int ncheck = 0;                    // workgroups of the residual-check pass
+    int npart = 0;                     // workgroups of the forward x pass (upper bound)
     int part_stride = 0;               // doubles of partials per member
     Tune tune;                         // launch variants of this shape (autotuned)
     int host_off = 0;                  // offset of this group's staging entries
@@ -408,10 +414,11 @@ size_t state_bytes(int count) { return (NSCAL * sizeof(double) + NCTRL * sizeof(
 // largest grid of the passes that write them
 int partial_slots(const poisson_desc_t &d)
 {
-    int n = x_fwd_blocks(internal_prec(d.precision), d.nx, d.ny, d.nz, 0);
+    int n = x_fwd_blocks(internal_prec(d.precision), d.nx, d.ny, d.nz, 0, 0);
     if (d.precision == POISSON_FP32_REFINE) {
-        const int r = x_fwd_blocks(P_F32, d.nx, d.ny, d.nz, 1);
-        const int c = residual_check_blocks(d.nx, d.ny, d.nz);
+        // residual passes: the most workgroups any plane-range depth gives
+        const int r = x_fwd_blocks(P_F32, d.nx, d.ny, d.nz, 1, 1);
+        const int c = residual_check_blocks(d.nx, d.ny, d.nz, 1);
         n = n > r ? n : r;
         n = n > c ? n : c;
     }
@@ -454,9 +461,8 @@ int build_group(Group &g)
     const size_t n = g.members.size();
     if (f32 && (rc = dev_alloc(g.S32, (size_t)g.N * 4 * n))) return rc;
     const bool refine = d.precision == POISSON_FP32_REFINE;
-    g.npart = x_fwd_blocks(internal_prec(d.precision), d.nx, d.ny, d.nz, 0);
-    g.nres = refine ? x_fwd_blocks(P_F32, d.nx, d.ny, d.nz, 1) : 0;
-    g.ncheck = refine ? residual_check_blocks(d.nx, d.ny, d.nz) : 0;
+    (void)refine;
+    g.npart = x_fwd_blocks(internal_prec(d.precision), d.nx, d.ny, d.nz, 0, 0);
     g.part_stride = partial_slots(d) * 4;
     if ((rc = dev_alloc(g.partials, (size_t)g.part_stride * sizeof(double) * n))) return rc;
     g.tune = initial_tune(g.d);
@@ -556,6 +562,7 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials, bool sum = true)
     a.inv_n = 1.0 / (double)g.N;
     a.residual = residual ? 1 : 0;
     a.gate = L.gate;
+    a.kr_max = g.tune.kr;
     char name[40];
     snprintf(name, sizeof name, residual ? "x_r2c_residual_%s" : "x_r2c_%s", tag(L.prec));
     const double bytes = (double)g.N * ((residual ? 16.0 : 8.0) + sb) * L.n;
@@ -595,11 +602,13 @@ int pass_residual_check(LSet &L, bool sum = true)
     a.inv_n = 1.0 / (double)g.N;
     a.residual = 1;
     a.gate = L.gate;
+    a.kr_max = g.tune.kr;
+    int nc = 0;
     int rc = timed(L.p, "residual_check_f64", (double)g.N * 16.0 * L.n,
-                   [&] { return launch_residual_check(a, nullptr, L.p->ls); });
+                   [&] { return launch_residual_check(a, &nc, L.p->ls); });
     if (rc || !sum) return rc;
-    return timed(L.p, "sum_partials", (double)g.ncheck * 32.0 * L.n, [&] {
-        return launch_sum_partials(L.one.partials, g.ncheck, L.one.scal ? L.one.scal + 2 : nullptr,
+    return timed(L.p, "sum_partials", (double)nc * 32.0 * L.n, [&] {
+        return launch_sum_partials(L.one.partials, nc, L.one.scal ? L.one.scal + 2 : nullptr,
                                    L.dev, L.n, 2, L.p->ls);
     });
 }
@@ -895,9 +904,10 @@ int enqueue_group_sequence(poisson_plan p, LSet &L, bool head)
         if ((rc = pass_x_fwd(L, true, true, false))) return rc;
         L.gate = C_CHECK;
         if ((rc = pass_residual_check(L, false))) return rc;
-        // both residual kernels run the same 2.5-D march grid (nres == ncheck)
-        rc = timed(p, "sum_partials", (double)g.ncheck * 32.0 * L.n, [&] {
-            return launch_sum_partials(nullptr, g.ncheck, nullptr, L.dev, L.n, 2, p->ls, C_EVAL,
+        // both residual kernels run the same 2.5-D march grid
+        const int nc = residual_check_blocks(g.d.nx, g.d.ny, g.d.nz, g.tune.kr);
+        rc = timed(p, "sum_partials", (double)nc * 32.0 * L.n, [&] {
+            return launch_sum_partials(nullptr, nc, nullptr, L.dev, L.n, 2, p->ls, C_EVAL,
                                        2, p->rtol, p->max_refine);
         });
         if (rc) return rc;
@@ -1141,6 +1151,18 @@ int autotune_group(poisson_plan p, Group &g)
     if (g.d.bc_z == POISSON_BC_NEUMANN) pick(g.tune.zv, 4, whole);
     if (g.d.ny >= 64) pick(g.tune.yv, 4, whole);
     pick(g.tune.rev, 2, whole);
+    if (p->precision == POISSON_FP32_REFINE) {
+        // plane-range depth of the residual passes: scored on the residual
+        // pass with transform followed by the residual check
+        static const int depths[3] = {4, 8, 16};
+        int idx = 1;
+        pick(idx, 3, [&] {
+            g.tune.kr = depths[idx];
+            const int r = pass_x_fwd(L, true, true);
+            return r ? r : pass_residual_check(L);
+        });
+        g.tune.kr = depths[idx];
+    }
     g.tune.tuned = true;
     (void)hipStreamSynchronize(p->stream);
     (void)hipEventDestroy(e0);
@@ -1329,12 +1351,14 @@ int poisson_plan_describe(poisson_plan plan, char *buf, int len)
     for (size_t gi = 0; gi < plan->groups.size(); ++gi) {
         const Group &g = plan->groups[gi];
         snprintf(line, sizeof line,
-                 "group %zu: %dx%dx%d %s %s problems=%zu z_tile=%d y_tile=%d reverse=%d %s\n", gi,
+                 "group %zu: %dx%dx%d %s %s problems=%zu z_tile=%d y_tile=%d reverse=%d "
+                 "march_planes=%d %s\n",
+                 gi,
                  g.d.nx, g.d.ny, g.d.nz, g.d.bc_z == POISSON_BC_NEUMANN ? "walls" : "periodic",
                  plan->precision == POISSON_FP64 ? "fp64"
                                                  : (plan->precision == POISSON_FP32 ? "fp32"
                                                                                      : "fp32_refine"),
-                 g.members.size(), g.tune.zv, g.tune.yv, g.tune.rev,
+                 g.members.size(), g.tune.zv, g.tune.yv, g.tune.rev, g.tune.kr,
                  g.tune.tuned ? "tuned" : "default");
         out += line;
     }

@@ -123,6 +123,7 @@ struct XFwdArgs {
     int residual;           // 1: input is the residual
     int reverse;            // walk the row blocks from the end (see block_order)
     int gate;               // control slot gating this launch (0: none)
+    int kr_max;             // residual passes: z-planes per workgroup (0: default)
 };
 
 // Inverse complex-to-real pass along x: p = result (store) or p += result.
@@ -182,7 +183,7 @@ int launch_z_walls(int prec, const ZArgs &a, hipStream_t s);
 int launch_z_periodic(int prec, const ZArgs &a, hipStream_t s);
 // number of workgroups the forward x pass uses (size of its partials array);
 // `residual` selects the residual pass of the refinement
-int x_fwd_blocks(int prec, int nx, int ny, int nz, int residual);
+int x_fwd_blocks(int prec, int nx, int ny, int nz, int residual, int kr_max);
 // Deterministic FP64 sums of the x pass's partials: `n` workgroups with three
 // sums each (stride 4), written to out[0..3).  Batched: one workgroup per
 // problem, partials and scal taken from batch[i], written to scal + out_off.
@@ -196,7 +197,7 @@ int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *ba
 // write): per-workgroup sums of r^2, (f - mean f)^2 and p into `partials`
 // (same layout as the forward x pass), for a convergence check.
 int launch_residual_check(const XFwdArgs &a, int *nblocks_out, hipStream_t s);
-int residual_check_blocks(int nx, int ny, int nz);
+int residual_check_blocks(int nx, int ny, int nz, int kr_max);
 
 // lengths supported by the transform kernels
 bool fft_length_supported(int n);

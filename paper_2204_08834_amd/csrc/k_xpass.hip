@@ -297,7 +297,7 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
     const int njb = march_jblocks(a.ny, TJ);
     const int bid = block_order(blockIdx.x, gridDim.x, a.reverse);
     const int jb = bid % njb, kb = bid / njb;
-    const int kr = march_planes(a.ny, a.nz, TJ);
+    const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max);
     const int k0 = kb * kr;
     const int k1 = k0 + kr < a.nz ? k0 + kr : a.nz;
 
@@ -464,9 +464,10 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
 
 // row blocks of the plain pass (an upper bound of its workgroup count), or
 // the workgroups of the residual pass
-template <int M> static int blocks_x(int ny, int nz, int residual)
+template <int M> static int blocks_x(int ny, int nz, int residual, int kr_max)
 {
-    if (residual) return march_jblocks(ny, march_rows(M)) * march_kblocks(ny, nz, march_rows(M));
+    if (residual)
+        return march_jblocks(ny, march_rows(M)) * march_kblocks(ny, nz, march_rows(M), kr_max);
     return (ny * nz + XCfg<M>::NB - 1) / XCfg<M>::NB;
 }
 
@@ -497,7 +498,7 @@ template <int M> static int grid_x_fwd(int nblk, int nbatch)
 
 template <int M> static int run_x_fwd(const XFwdArgs &a, hipStream_t s, int *nblocks_out)
 {
-    int nb = blocks_x<M>(a.ny, a.nz, a.residual);
+    int nb = blocks_x<M>(a.ny, a.nz, a.residual, a.kr_max);
     if (!a.residual) nb = grid_x_fwd<M>(nb, a.batch ? a.nbatch : 1);
     if (nblocks_out) *nblocks_out = nb;
     const dim3 grid(nb, a.batch ? a.nbatch : 1);
@@ -531,7 +532,7 @@ using namespace PK_NS;
 
 #define PK_CASE_FWD(N) case N: return run_x_fwd<N>(a, s, nblocks_out);
 #define PK_CASE_INV(N) case N: return run_x_inv<N>(a, s);
-#define PK_CASE_BLK(N) case N: return blocks_x<N>(ny, nz, residual);
+#define PK_CASE_BLK(N) case N: return blocks_x<N>(ny, nz, residual, kr_max);
 
 int PK_SUFFIX(launch_x_fwd)(const XFwdArgs &a, hipStream_t s, int *nblocks_out)
 {
@@ -543,7 +544,7 @@ int PK_SUFFIX(launch_x_inv)(const XInvArgs &a, hipStream_t s)
     switch (a.nx / 2) { PK_X_LENGTHS(PK_CASE_INV) default: return -1; }
 }
 
-int PK_SUFFIX(x_fwd_blocks)(int nx, int ny, int nz, int residual)
+int PK_SUFFIX(x_fwd_blocks)(int nx, int ny, int nz, int residual, int kr_max)
 {
     switch (nx / 2) { PK_X_LENGTHS(PK_CASE_BLK) default: return -1; }
 }

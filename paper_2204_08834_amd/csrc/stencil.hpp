@@ -24,17 +24,19 @@ constexpr int march_rows(int M)
 // workgroups of one problem: (y-row blocks) x (z-plane ranges), plane-major
 __host__ __device__ constexpr int march_jblocks(int ny, int tj) { return (ny + tj - 1) / tj; }
 
-// z-planes per workgroup: 8, halved (down to 1) while a problem would get
-// fewer than 256 workgroups, so that small grids still fill the device
-__host__ __device__ constexpr int march_planes(int ny, int nz, int tj)
+// z-planes per workgroup: kr_max (8 by default, a tuning knob; 0 means the
+// default), halved (down to 1) while a problem would get fewer than 1024
+// workgroups, so that small grids still fill the device.  Each range
+// re-reads two planes of p, so deeper ranges read less.
+__host__ __device__ constexpr int march_planes(int ny, int nz, int tj, int kr_max)
 {
-    int kr = 8;
-    while (kr > 1 && march_jblocks(ny, tj) * ((nz + kr - 1) / kr) < 256) kr /= 2;
+    int kr = kr_max > 0 ? kr_max : 8;
+    while (kr > 1 && march_jblocks(ny, tj) * ((nz + kr - 1) / kr) < 1024) kr /= 2;
     return kr;
 }
-__host__ __device__ constexpr int march_kblocks(int ny, int nz, int tj)
+__host__ __device__ constexpr int march_kblocks(int ny, int nz, int tj, int kr_max)
 {
-    const int kr = march_planes(ny, nz, tj);
+    const int kr = march_planes(ny, nz, tj, kr_max);
     return (nz + kr - 1) / kr;
 }
 

@@ -107,3 +107,27 @@ def test_batch_autotune_and_describe():
     rc, stats = bp.solve(rhs, outs)
     assert rc == 0 and all(s["rel_residual"] <= 1e-10 for s in stats)
     bp.close()
+
+
+@pytest.mark.parametrize("planes", [4, 8, 16])
+def test_march_depths(planes, monkeypatch):
+    """Every plane-range depth of the residual passes: converged solves, and
+    the device-side loop (whose sum counts the march grid) equal to the host
+    loop bitwise."""
+    P = _gpu()
+    monkeypatch.setenv("POISSON_MARCH_PLANES", str(planes))
+    for name, shape in (("rb512", (128, 128, 96)), ("hit256", (64, 64, 64)), ("rb512", (96, 48, 36))):
+        prob = inputs.scaled(name, *shape, seed=81)
+        sp = prob.spacings()
+        rhs = torch.from_numpy(prob.f).cuda()
+        res = {}
+        for mode in ("host", "graph"):
+            with P.Plan(prob.nx, prob.ny, prob.nz, *sp, prob.bc_z, "fp32_refine") as plan:
+                plan.set_graph(mode)
+                out, st = plan.solve(rhs)
+                assert f"march_planes={planes}" in plan.describe()
+                torch.cuda.synchronize()
+            res[mode] = (out.cpu().numpy(), st)
+        assert res["host"][1]["status"] == 0 and res["host"][1]["rel_residual"] <= 1e-10
+        assert np.array_equal(res["host"][0], res["graph"][0])
+        assert res["host"][1] == res["graph"][1]
