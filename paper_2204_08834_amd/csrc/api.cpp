@@ -904,11 +904,12 @@ int enqueue_group_sequence(poisson_plan p, LSet &L, bool head)
         if ((rc = pass_x_fwd(L, true, true, false))) return rc;
         L.gate = C_CHECK;
         if ((rc = pass_residual_check(L, false))) return rc;
-        // both residual kernels run the same 2.5-D march grid
+        // partial records of whichever residual pass ran for each problem
+        const int nr = x_fwd_blocks(P_F32, g.d.nx, g.d.ny, g.d.nz, 1, g.tune.kr);
         const int nc = residual_check_blocks(g.d.nx, g.d.ny, g.d.nz, g.tune.kr);
-        rc = timed(p, "sum_partials", (double)nc * 32.0 * L.n, [&] {
-            return launch_sum_partials(nullptr, nc, nullptr, L.dev, L.n, 2, p->ls, C_EVAL,
-                                       2, p->rtol, p->max_refine);
+        rc = timed(p, "sum_partials", (double)(nr > nc ? nr : nc) * 32.0 * L.n, [&] {
+            return launch_sum_partials(nullptr, nr, nullptr, L.dev, L.n, 2, p->ls, C_EVAL,
+                                       2, p->rtol, p->max_refine, nc);
         });
         if (rc) return rc;
         L.gate = C_FIX;

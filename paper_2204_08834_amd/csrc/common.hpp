@@ -189,10 +189,12 @@ int x_fwd_blocks(int prec, int nx, int ny, int nz, int residual, int kr_max);
 // problem, partials and scal taken from batch[i], written to scal + out_off.
 // Batched launches of the device-side loop also take the control step of
 // each problem (CtrlSlot records): mode 1 opens the record, mode 2 decides
-// after a residual evaluation (rtol, max_refine).
+// after a residual evaluation (rtol, max_refine); in mode 2, n counts the
+// records of the residual pass with transform and n_check those of the
+// residual check (the problem's C_CHECK flag tells which one ran).
 int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *batch,
                         int nbatch, int out_off, hipStream_t s, int gate = 0, int mode = 0,
-                        double rtol = 0.0, int max_refine = 0);
+                        double rtol = 0.0, int max_refine = 0, int n_check = 0);
 // FP64 residual r = (f - mean f) - L p alone (no transform, no spectrum
 // write): per-workgroup sums of r^2, (f - mean f)^2 and p into `partials`
 // (same layout as the forward x pass), for a convergence check.

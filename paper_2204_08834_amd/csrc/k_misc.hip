@@ -141,7 +141,7 @@ __device__ __forceinline__ void ctrl_decide(int *c, double *sc, double rtol, int
 __global__ __launch_bounds__(1024) void k_sum_partials(const double *in, int n, double *out,
                                                        const ProbPtrs *batch, int out_off,
                                                        int gate, int mode, double rtol,
-                                                       int max_refine)
+                                                       int max_refine, int n_check)
 {
     __shared__ double sh[3][1024];
     if (gated_off(batch, gate, blockIdx.x)) return;
@@ -149,6 +149,9 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double *in, int n, 
         in = batch[blockIdx.x].partials;
         out = batch[blockIdx.x].scal + out_off;
     }
+    // after a residual evaluation: records of the check pass, or of the
+    // residual pass with transform (their grids differ)
+    if (mode == 2 && batch[blockIdx.x].ctrl[C_CHECK]) n = n_check;
     double s0, s1, s2;
     sum_records(in, n, sh, s0, s1, s2);
     if (threadIdx.x == 0) {
@@ -162,11 +165,11 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double *in, int n, 
 
 int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *batch,
                         int nbatch, int out_off, hipStream_t s, int gate, int mode, double rtol,
-                        int max_refine)
+                        int max_refine, int n_check)
 {
     if (mode != 0 && !batch) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sum_partials, dim3(batch ? nbatch : 1), dim3(1024), 0, s, in, n, out,
-                       batch, out_off, gate, mode, rtol, max_refine);
+                       batch, out_off, gate, mode, rtol, max_refine, n_check);
     return (int)hipGetLastError();
 }
 

@@ -285,7 +285,7 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
         a.partials = q.partials;
         a.sum_f = q.scal + 1;
     }
-    constexpr int TJ = march_rows(M), NT = XR_NT, NX = 2 * M;
+    constexpr int TJ = march_rows_res(M), NT = XR_NT, NX = 2 * M;
     using Mar = PlaneMarch<M, TJ, NT>;
     using Tile = LdsTile<R, M, TJ, false, 0>;
     constexpr size_t PLANE_B = sizeof(double2) * (TJ + 2) * M;
@@ -467,7 +467,8 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
 template <int M> static int blocks_x(int ny, int nz, int residual, int kr_max)
 {
     if (residual)
-        return march_jblocks(ny, march_rows(M)) * march_kblocks(ny, nz, march_rows(M), kr_max);
+        return march_jblocks(ny, march_rows_res(M)) *
+               march_kblocks(ny, nz, march_rows_res(M), kr_max);
     return (ny * nz + XCfg<M>::NB - 1) / XCfg<M>::NB;
 }
 

@@ -15,12 +15,16 @@
 
 namespace pk {
 
-// rows per workgroup for rows of M pairs: about 2048 pairs per plane tile
-constexpr int march_rows(int M)
+// rows per workgroup for rows of M pairs: about `pairs` pairs per plane
+// tile.  The residual check streams best with 2048 pairs; the residual pass
+// with transform, which also holds an FFT tile, with 1024 (more workgroups,
+// fewer registers): measured on MI355X at 512x512x256 and 256^3.
+constexpr int march_rows(int M, int pairs = 2048)
 {
-    const int t = 2048 / M;
+    const int t = pairs / M;
     return t < 1 ? 1 : (t > 16 ? 16 : t);
 }
+constexpr int march_rows_res(int M) { return march_rows(M, 1024); }
 // workgroups of one problem: (y-row blocks) x (z-plane ranges), plane-major
 __host__ __device__ constexpr int march_jblocks(int ny, int tj) { return (ny + tj - 1) / tj; }
 
