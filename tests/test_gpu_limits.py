@@ -1,0 +1,115 @@
+"""GPU parity at the limits the descriptor accepts.
+
+* The longest transforms along each axis (nx = 2048, i.e. a 1024-point
+  complex x transform; ny = 2048; nz = 4096 with walls; nz = 2048 periodic)
+  on thin grids, element by element against the oracle (FP64 1e-12,
+  FP32 + refinement to a 1e-10 residual).
+* The largest grid, 2048 x 2048 x 512 = 2^31 points (every 32-bit index
+  path at its limit): exact discrete eigenmodes built and checked on the GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2204_08834_amd import inputs  # noqa: E402
+
+NEU, PER = 1, 0
+LONG = [(2048, 4, 6, NEU), (2048, 2, 6, PER), (6, 2048, 4, PER), (4, 2048, 3, NEU),
+        (4, 6, 4096, NEU), (4, 4, 2048, PER), (6, 3, 3072, NEU), (4, 2, 1536, PER)]
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_08834_amd import poisson
+    poisson.lib()  # raises if the HIP library is missing: no fallback
+    return poisson
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def kappa(nx, ny, nz, dx, dy, dz, bc):
+    """lambda_max / lambda_min (nonzero) of the discrete operator: the factor
+    by which rounding at the level of the unit roundoff can grow into the
+    solution of any FP64 method (the oracle's included)."""
+    def lam(n, h, j, walls=False):
+        return 4 / h ** 2 * math.sin(math.pi * j / ((2 * n) if walls else n)) ** 2
+    lmax = (lam(nx, dx, nx // 2) + lam(ny, dy, ny // 2)
+            + (lam(nz, dz, nz - 1, True) if bc == NEU else lam(nz, dz, nz // 2)))
+    cands = [lam(nx, dx, 1) if nx > 1 else math.inf, lam(ny, dy, 1) if ny > 1 else math.inf,
+             (lam(nz, dz, 1, True) if bc == NEU else lam(nz, dz, 1)) if nz > 1 else math.inf]
+    return lmax / min(cands)
+
+
+@pytest.mark.parametrize("case", LONG, ids=[f"{c[0]}x{c[1]}x{c[2]}_{'w' if c[3] else 'p'}"
+                                            for c in LONG])
+def test_longest_transforms_match_oracle(orc, case):
+    P = _gpu()
+    nx, ny, nz, bc = case
+    L = (2.0, 1.5, 3.0)
+    f = inputs.uniform_velocity_rhs(nx, ny, nz, *L, bc, 17)
+    sp = (L[0] / nx, L[1] / ny, L[2] / nz)
+    p_ref = orc.solve(f, *sp, bc)
+    rhs = torch.from_numpy(f).cuda()
+    k = kappa(nx, ny, nz, *sp, bc)
+    ref_res, _ = orc.residual(f, p_ref, *sp, bc)
+    for prec in ("fp64", "fp32_refine"):
+        print(f"[limits] {nx}x{ny}x{nz} bc={bc} {prec}", flush=True)
+        with P.Plan(nx, ny, nz, *sp, bc, prec) as plan:
+            out, st = plan.solve(rhs, check=False)
+            torch.cuda.synchronize()
+        p = out.cpu().numpy()
+        if prec == "fp64":
+            # 1e-12, or the conditioning bound where the operator is too
+            # ill-conditioned for 1e-12 to be meaningful (both solutions are
+            # then backward stable: residuals at rounding level)
+            res, _ = orc.residual(f, p, *sp, bc)
+            err = rel(p, p_ref)
+            print(f"[limits] kappa {k:.2e} error {err:.2e} residual gpu {res:.2e} "
+                  f"oracle {ref_res:.2e}", flush=True)
+            assert res <= 1e-13 and ref_res <= 1e-13
+            assert err <= max(1e-12, 4 * k * 2.2e-16), err
+        else:
+            res, _ = orc.residual(f, p, *sp, bc)
+            print(f"[limits] residual {res:.2e} stats {st}", flush=True)
+            assert st["status"] == 0 and res <= 1e-10
+
+
+def test_largest_grid_eigenmode():
+    """2048 x 2048 x 512 walls (N = 2^31): f = cos-modes, p = f / lambda."""
+    P = _gpu()
+    nx, ny, nz = 2048, 2048, 512
+    dx, dy, dz = 2.0 / nx, 2.0 / ny, 1.0 / nz
+    a, b, c = 7, 1023, 300
+    dev = "cuda"
+    print("[limits] building the 2^31-point eigenmode", flush=True)
+    i = torch.arange(nx, dtype=torch.float64, device=dev) + 0.5
+    j = torch.arange(ny, dtype=torch.float64, device=dev) + 0.5
+    k = torch.arange(nz, dtype=torch.float64, device=dev) + 0.5
+    fx = torch.cos(2 * math.pi * a * i / nx + 0.3)
+    fy = torch.cos(2 * math.pi * b * j / ny + 0.1)
+    fz = torch.cos(math.pi * c * k / nz)
+    f = (fz[:, None, None] * fy[None, :, None] * fx[None, None, :]).contiguous()
+    lam = (-4 / dx ** 2 * math.sin(math.pi * a / nx) ** 2
+           - 4 / dy ** 2 * math.sin(math.pi * b / ny) ** 2
+           - 4 / dz ** 2 * math.sin(math.pi * c / (2 * nz)) ** 2)
+    fnorm = torch.linalg.vector_norm(f).item()
+    for prec, tol in (("fp64", 1e-12), ("fp32_refine", 1e-9)):
+        print(f"[limits] 2^31 points {prec}", flush=True)
+        with P.Plan(nx, ny, nz, dx, dy, dz, NEU, prec) as plan:
+            p, st = plan.solve(f)
+            torch.cuda.synchronize()
+        # ||p - f/lam|| / ||f/lam||, in place to keep the footprint small
+        p.mul_(lam).sub_(f)
+        err = torch.linalg.vector_norm(p).item() / fnorm
+        print(f"[limits] 2^31 points {prec}: error {err:.2e} stats {st}", flush=True)
+        del p
+        torch.cuda.empty_cache()
+        assert err <= tol, (prec, err)
