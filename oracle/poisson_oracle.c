@@ -37,6 +37,10 @@
  * small grids, zero mean, residual at machine precision, projection
  * invariant, symmetries, 1-D reductions to DCT-II).
  *
+ * Also the projection around the solve (oracle_divergence, oracle_correct):
+ * the right-hand side alpha D u of the face velocities and the velocity
+ * update u -= beta G psi.
+ *
  * A "mutation" argument plants one known mistake at a time so the tests can
  * show that the pins catch it.  mutation = 0 is the oracle.
  */
@@ -369,6 +373,77 @@ int oracle_residual(int nx, int ny, int nz, double dx, double dy, double dz, int
     free(lp);
     if (rel_l2) *rel_l2 = (s2f > 0) ? sqrt(s2r / s2f) : sqrt(s2r);
     if (rel_linf) *rel_linf = (mf > 0) ? mr / mf : mr;
+    return 0;
+}
+
+/*
+ * The projection step around the solve (Section 3.3, the pressure equation
+ * eqn:poisson and the velocity update eqn:corr; Section 3 for the
+ * staggered layout).  Face velocities: u[k][j][i] sits on the east face of
+ * cell (i,j,k), v on its north face, w on its top face.  Periodic directions
+ * wrap; with walls in z the top face of the last cell is the wall
+ * (w[nz-1] holds no flow) and the bottom wall flux below cell 0 is zero.
+ *
+ * oracle_divergence: f = alpha * D u, the cell divergence
+ *   (u[i] - u[i-1])/dx + (v[j] - v[j-1])/dy + (w[k] - w[k-1])/dz.
+ */
+int oracle_divergence(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
+                      const double *u, const double *v, const double *w, double alpha,
+                      double *f)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !u || !v || !w || !f) return -1;
+#pragma omp parallel for schedule(static)
+    for (long kk = 0; kk < (long)nz * ny; ++kk) {
+        int k = (int)(kk / ny), j = (int)(kk % ny);
+        int jm = (j + ny - 1) % ny;
+        for (int i = 0; i < nx; ++i) {
+            int im = (i + nx - 1) % nx;
+#define A(X, K, J, I) X[((long)(K) * ny + (J)) * nx + (I)]
+            double wd;  /* flux through the bottom face of the cell */
+            if (k > 0)
+                wd = A(w, k - 1, j, i);
+            else
+                wd = (bc_z == ORC_PERIODIC) ? A(w, nz - 1, j, i) : 0.0;
+            double wu = (bc_z == ORC_NEUMANN && k == nz - 1) ? 0.0 : A(w, k, j, i);
+            double d = (A(u, k, j, i) - A(u, k, j, im)) / dx +
+                       (A(v, k, j, i) - A(v, k, jm, i)) / dy + (wu - wd) / dz;
+#undef A
+            f[((long)k * ny + j) * nx + i] = alpha * d;
+        }
+    }
+    return 0;
+}
+
+/*
+ * oracle_correct: u -= beta * G psi on every face, G the face gradient
+ *   (psi[i+1] - psi[i])/dx on east faces, (psi[j+1] - psi[j])/dy on north
+ *   faces, (psi[k+1] - psi[k])/dz on top faces; the wall face carries no
+ *   gradient (zero normal pressure gradient), so w[nz-1] is left as it is.
+ * With alpha * beta = 1 the corrected velocity is discretely divergence-free
+ * whenever L psi = alpha D u, since D G = L (the 7-point operator).
+ */
+int oracle_correct(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
+                   const double *psi, double beta, double *u, double *v, double *w)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !psi || !u || !v || !w) return -1;
+#pragma omp parallel for schedule(static)
+    for (long kk = 0; kk < (long)nz * ny; ++kk) {
+        int k = (int)(kk / ny), j = (int)(kk % ny);
+        int jp = (j + 1) % ny;
+        for (int i = 0; i < nx; ++i) {
+            int ip = (i + 1) % nx;
+            long c = ((long)k * ny + j) * nx + i;
+#define P(K, J, I) psi[((long)(K) * ny + (J)) * nx + (I)]
+            double pc = psi[c];
+            u[c] -= beta * (P(k, j, ip) - pc) / dx;
+            v[c] -= beta * (P(k, jp, i) - pc) / dy;
+            if (k < nz - 1)
+                w[c] -= beta * (P(k + 1, j, i) - pc) / dz;
+            else if (bc_z == ORC_PERIODIC)
+                w[c] -= beta * (P(0, j, i) - pc) / dz;
+#undef P
+        }
+    }
     return 0;
 }
 
