@@ -125,6 +125,37 @@ int poisson_plan_create(const poisson_desc_t *d, void *stream, poisson_plan *out
 int poisson_solve(poisson_plan plan, const double *rhs_dev, double *sol_dev,
                   poisson_stats_t *stats);
 
+/*
+ * The whole projection step around the solve (FluTAS Section 3.3:
+ * eqn:poisson, then eqn:corr and eqn:p_upt) on a single-problem plan:
+ *   f   = alpha D(u, v, w)      (alpha = rho_0/dt), evaluated inside the
+ *                               first transform pass (never stored, except
+ *                               under POISSON_FP32_REFINE, see below);
+ *   psi = the zero-mean solution of L psi = f - mean(f), as poisson_solve;
+ *   u  -= beta Gx psi, v -= beta Gy psi, w -= beta Gz psi  (beta = dt/rho_0);
+ *   p  += psi                   (skipped when p is NULL).
+ * Faces (Section 3): u[k,j,i] on x = (i+1) dx, v[k,j,i] on y = (j+1) dy,
+ * w[k,j,i] on z = (k+1) dz; D is the cell-centred divergence,
+ *   (D u)[k,j,i] = (u[i] - u[i-1])/dx + (v[j] - v[j-1])/dy + (w[k] - w[k-1])/dz,
+ * and G the face gradient, (Gx psi)[i] = (psi[i+1] - psi[i])/dx etc., both
+ * periodic in x and y.  With walls in z no flux crosses the bottom face of
+ * plane 0 or the top face of plane nz-1: those values of w are not read, and
+ * w on the top wall (plane nz-1) is not changed.  D G equals the 7-point L,
+ * so with alpha * beta = 1 the corrected velocity is discretely
+ * divergence-free up to the solve's accuracy.
+ * u, v, w, p, psi: device float64, nx*ny*nz elements each, pairwise
+ * non-overlapping; u, v, w and p are updated in place, psi receives the
+ * solution.  alpha, beta: finite.  stats as poisson_solve.  The velocity and
+ * pressure are updated only when the solve succeeds: on any error (for
+ * instance NOT_CONVERGED or NONFINITE under refinement) they are left as they
+ * were and psi holds the last iterate.  Under POISSON_FP32_REFINE the first
+ * call allocates one more float64 field (nx*ny*nz) that the plan keeps for f.
+ * Errors: INVALID_ARG (null plan or field, batched plan, non-finite scale,
+ * overlapping fields), OUT_OF_MEMORY, HIP, and those of poisson_solve.
+ */
+int poisson_project(poisson_plan plan, double *u, double *v, double *w, double *p, double *psi,
+                    double alpha, double beta, poisson_stats_t *stats);
+
 /* Release a plan and everything it owns.  NULL is accepted. */
 int poisson_destroy(poisson_plan plan);
 

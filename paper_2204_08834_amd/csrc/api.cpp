@@ -338,6 +338,15 @@ struct poisson_plan_s {
     std::vector<hipEvent_t> ev_join;
     hipGraph_t graph[2] = {nullptr, nullptr};  // [0] solve + loop segments, [1] segments
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // projection step in progress (poisson_project): the first pass takes
+    // f = alpha D(u, v, w) instead of reading a right-hand side
+    struct Proj {
+        const double *u = nullptr, *v = nullptr, *w = nullptr;
+        double alpha = 1.0;
+        double *f_out = nullptr;  // where the pass stores f (FP32 + refinement)
+    } proj;
+    bool projecting = false;
+    std::shared_ptr<DevBuf> fdiv;  // FP64 f of projections under FP32 + refinement
     bool timing = false;
     std::vector<Timed> pending;
     std::vector<hipEvent_t> event_pool;
@@ -415,11 +424,14 @@ size_t state_bytes(int count) { return (NSCAL * sizeof(double) + NCTRL * sizeof(
 int partial_slots(const poisson_desc_t &d)
 {
     int n = x_fwd_blocks(internal_prec(d.precision), d.nx, d.ny, d.nz, 0, 0);
-    if (d.precision == POISSON_FP32_REFINE) {
-        // residual passes: the most workgroups any plane-range depth gives
+    if (d.precision != POISSON_FP64) {
+        // residual and divergence passes (plane march): the most workgroups
+        // any plane-range depth gives
         const int r = x_fwd_blocks(P_F32, d.nx, d.ny, d.nz, 1, 1);
-        const int c = residual_check_blocks(d.nx, d.ny, d.nz, 1);
         n = n > r ? n : r;
+    }
+    if (d.precision == POISSON_FP32_REFINE) {
+        const int c = residual_check_blocks(d.nx, d.ny, d.nz, 1);
         n = n > c ? n : c;
     }
     return n;
@@ -565,7 +577,22 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials, bool sum = true)
     a.kr_max = g.tune.kr;
     char name[40];
     snprintf(name, sizeof name, residual ? "x_r2c_residual_%s" : "x_r2c_%s", tag(L.prec));
-    const double bytes = (double)g.N * ((residual ? 16.0 : 8.0) + sb) * L.n;
+    double bytes = (double)g.N * ((residual ? 16.0 : 8.0) + sb) * L.n;
+    const bool div = !residual && L.p->projecting;
+    if (div) {
+        // projection: f = alpha D(u, v, w) evaluated on the fly (one problem)
+        const auto &pj = L.p->proj;
+        a.residual = 2;
+        a.u = pj.u;
+        a.v = pj.v;
+        a.w = pj.w;
+        a.cx = pj.alpha / g.d.dx;
+        a.cy = pj.alpha / g.d.dy;
+        a.cz = pj.alpha / g.d.dz;
+        a.f_out = pj.f_out;
+        snprintf(name, sizeof name, "x_r2c_divergence_%s", tag(L.prec));
+        bytes = (double)g.N * (24.0 + sb + (pj.f_out ? 8.0 : 0.0)) * L.n;
+    }
     int np = 0;
     int rc = timed(L.p, name, bytes,
                    [&] { return launch_x_fwd(L.prec, a, &np, L.p->ls); });
@@ -885,7 +912,7 @@ constexpr int GRAPH_SEGMENTS = 2;
 //   | sums + control decision [C_EVAL]
 //   | full residual pass after a failed check [C_FIX]
 //   | y, z, y, accumulating x [C_CORRECT]
-int enqueue_group_sequence(poisson_plan p, LSet &L, bool head)
+int enqueue_group_sequence(poisson_plan p, LSet &L, bool head, bool segs = true)
 {
     const bool refine = p->precision == POISSON_FP32_REFINE;
     const int prec = internal_prec(p->precision);
@@ -898,7 +925,7 @@ int enqueue_group_sequence(poisson_plan p, LSet &L, bool head)
         L.sum_mode = 0;
         if (rc) return rc;
     }
-    if (!refine) return POISSON_OK;
+    if (!refine || !segs) return POISSON_OK;
     for (int seg = 0; seg < GRAPH_SEGMENTS; ++seg) {
         L.gate = C_FULL;
         if ((rc = pass_x_fwd(L, true, true, false))) return rc;
@@ -924,7 +951,8 @@ int enqueue_group_sequence(poisson_plan p, LSet &L, bool head)
 // All groups, each on a stream of its own forked from the plan's loop
 // stream and joined back (in a captured graph: independent branches), so
 // that the launches of problems of different shapes overlap.
-int enqueue_device_sequence(poisson_plan p, std::vector<LSet> &sets, bool head)
+int enqueue_device_sequence(poisson_plan p, std::vector<LSet> &sets, bool head,
+                            bool segs = true)
 {
     const size_t ng = sets.size();
     int rc = POISSON_OK;
@@ -936,7 +964,7 @@ int enqueue_device_sequence(poisson_plan p, std::vector<LSet> &sets, bool head)
             rc = hip_fail("stream fork", (int)hipGetLastError());
             break;
         }
-        rc = enqueue_group_sequence(p, sets[gi], head);
+        rc = enqueue_group_sequence(p, sets[gi], head, segs);
         if (gi > 0 && hipEventRecord(p->ev_join[gi - 1], p->ls) != hipSuccess && !rc)
             rc = hip_fail("stream join", (int)hipGetLastError());
     }
@@ -1038,8 +1066,18 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
     const int *hc = p->host_ctrl;
     const int max_rounds = p->max_refine / GRAPH_SEGMENTS + 2;
     for (int round = 0; !rc; ++round) {
-        const int k = round == 0 ? 0 : 1;
-        if (capture) {
+        int k = round == 0 ? 0 : 1;
+        bool issued = false;
+        if (capture && round == 0 && p->projecting) {
+            // the first pass of a projection takes the call's velocity
+            // pointers: the solve is issued eagerly, the loop segments come
+            // from the segment graph
+            if ((rc = enqueue_device_sequence(p, sets, true, false))) break;
+            issued = !refine;
+            k = 1;
+        }
+        if (issued) {
+        } else if (capture) {
             if (!p->gexec[k] && (rc = build_graph(p, sets, k))) break;
             const hipError_t e = hipGraphLaunch(p->gexec[k], p->gstream);
             if (e != hipSuccess) {
@@ -1259,6 +1297,38 @@ int create_plan(const poisson_desc_t *descs, int count, void *stream, bool batch
     return POISSON_OK;
 }
 
+// Projection step (poisson_project): the first pass evaluates
+// f = alpha D(u, v, w) on the fly; L psi = f is solved as by poisson_solve;
+// after a successful solve one pass applies u -= beta G psi and p += psi.
+int project(poisson_plan p, double *u, double *v, double *w, double *pr, double *psi,
+            double alpha, double beta, poisson_stats_t *st)
+{
+    Group &g = p->groups[0];
+    const bool refine = p->precision == POISSON_FP32_REFINE;
+    if (refine && !p->fdiv) {
+        // the residuals of the refinement need f: stored by the first pass
+        const int rc = dev_alloc(p->fdiv, (size_t)g.N * sizeof(double));
+        if (rc) return rc;
+    }
+    p->proj.u = u;
+    p->proj.v = v;
+    p->proj.w = w;
+    p->proj.alpha = alpha;
+    p->proj.f_out = refine ? (double *)p->fdiv->p : nullptr;
+    p->projecting = true;
+    // a direct solve reads no right-hand side after its first pass
+    const double *rhs = refine ? (const double *)p->fdiv->p : u;
+    int rc = p->graph_mode ? solve_device(p, &rhs, &psi, st) : solve_all(p, &rhs, &psi, st);
+    p->projecting = false;
+    p->proj = poisson_plan_s::Proj{};
+    if (rc) return rc;
+    CorrArgs a{psi, u, v, w, pr, g.d.nx, g.d.ny, g.d.nz, g.d.bc_z,
+               beta / g.d.dx, beta / g.d.dy, beta / g.d.dz, g.tune.kr};
+    p->ls = p->stream;
+    const double bytes = (double)g.N * (pr ? 72.0 : 56.0);
+    return timed(p, "correct_f64", bytes, [&] { return launch_correct(a, p->stream); });
+}
+
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev)
@@ -1334,6 +1404,20 @@ int poisson_batch_solve(poisson_plan plan, const double *const *rhs, double *con
     }
     DeviceGuard guard(plan->device);
     return plan->graph_mode ? solve_device(plan, rhs, sol, stats) : solve_all(plan, rhs, sol, stats);
+}
+
+int poisson_project(poisson_plan plan, double *u, double *v, double *w, double *p, double *psi,
+                    double alpha, double beta, poisson_stats_t *stats)
+{
+    if (!plan || plan->batched || !u || !v || !w || !psi) return POISSON_ERR_INVALID_ARG;
+    if (!std::isfinite(alpha) || !std::isfinite(beta)) return POISSON_ERR_INVALID_ARG;
+    const long long n = plan->groups[0].N;
+    const double *arr[5] = {u, v, w, psi, p};
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < i; ++j)
+            if (arr[i] && arr[j] && overlaps(arr[i], arr[j], n)) return POISSON_ERR_INVALID_ARG;
+    DeviceGuard guard(plan->device);
+    return project(plan, u, v, w, p, psi, alpha, beta, stats);
 }
 
 int poisson_plan_autotune(poisson_plan plan, int flags)

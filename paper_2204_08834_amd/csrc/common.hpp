@@ -120,10 +120,14 @@ struct XFwdArgs {
     double ax, ay, az;      // 1/dx^2, 1/dy^2, 1/dz^2
     const double *sum_f;    // residual mode: device sum of f (mean = sum_f * inv_n)
     double inv_n;           // 1/(nx ny nz)
-    int residual;           // 1: input is the residual
+    int residual;           // 1: input is the residual; 2: the divergence of (u, v, w)
     int reverse;            // walk the row blocks from the end (see block_order)
     int gate;               // control slot gating this launch (0: none)
     int kr_max;             // residual passes: z-planes per workgroup (0: default)
+    // divergence input (residual == 2; one problem): f = cx Dx u + cy Dy v + cz Dz w
+    const double *u, *v, *w;
+    double cx, cy, cz;      // alpha/dx, alpha/dy, alpha/dz
+    double *f_out;          // receives f in FP64 (nullable)
 };
 
 // Inverse complex-to-real pass along x: p = result (store) or p += result.
@@ -200,6 +204,18 @@ int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *ba
 // (same layout as the forward x pass), for a convergence check.
 int launch_residual_check(const XFwdArgs &a, int *nblocks_out, hipStream_t s);
 int residual_check_blocks(int nx, int ny, int nz, int kr_max);
+
+// Velocity correction and pressure update of the projection step:
+// u -= bx Dx+ psi, v -= by Dy+ psi, w -= bz Dz+ psi (not on a top wall),
+// p += psi when p is not null; one problem, arrays (nz, ny, nx).
+struct CorrArgs {
+    const double *psi;
+    double *u, *v, *w, *p;
+    int nx, ny, nz, bc_z;
+    double bx, by, bz;      // beta/dx, beta/dy, beta/dz
+    int kr_max;             // z-planes per workgroup (0: default)
+};
+int launch_correct(const CorrArgs &a, hipStream_t s);
 
 // lengths supported by the transform kernels
 bool fft_length_supported(int n);

@@ -256,4 +256,57 @@ int launch_residual_check(const XFwdArgs &a, int *nblocks_out, hipStream_t s)
     switch (a.nx / 2) { PK_X_LENGTHS(PK_CASE_RC) default: return -1; }
 }
 
+// Velocity correction and pressure update of the projection step
+// (CorrMarch of stencil.hpp): streams psi once (plus halos) and u, v, w and p
+// once each way.
+constexpr int CO_NT = 256;
+
+// about 1024 pairs per plane tile: each element holds six double2 (psi at
+// k and k+1, u, v, w, p) in registers
+template <int M> constexpr int corr_rows() { return march_rows(M, 1024); }
+
+template <int M>
+__global__ __launch_bounds__(CO_NT) void k_correct(CorrArgs a)
+{
+    constexpr int TJ = corr_rows<M>();
+    using Mar = CorrMarch<M, TJ, CO_NT>;
+    __shared__ double2 s_tile[TJ + 1][M];
+    const int njb = march_jblocks(a.ny, TJ);
+    const int jb = blockIdx.x % njb, kb = blockIdx.x / njb;
+    const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max);
+    const int k0 = kb * kr;
+    const int k1 = k0 + kr < a.nz ? k0 + kr : a.nz;
+    Mar m;
+    m.psi = gbl(a.psi);
+    m.u = gbl(a.u);
+    m.v = gbl(a.v);
+    m.w = gbl(a.w);
+    m.p = a.p ? gbl(a.p) : nullptr;
+    m.bx = a.bx;
+    m.by = a.by;
+    m.bz = a.bz;
+    m.tile = s_tile;
+    m.setup(jb, a.ny, a.nz, a.bc_z);
+    m.start(k0);
+    for (int k = k0; k < k1; ++k) {
+        if (k > k0) __syncthreads();
+        m.step(k);
+    }
+}
+
+template <int M> static int run_correct(const CorrArgs &a, hipStream_t s)
+{
+    constexpr int TJ = corr_rows<M>();
+    const int nb = march_jblocks(a.ny, TJ) * march_kblocks(a.ny, a.nz, TJ, a.kr_max);
+    hipLaunchKernelGGL(k_correct<M>, dim3(nb), dim3(CO_NT), 0, s, a);
+    return (int)hipGetLastError();
+}
+
+#define PK_CASE_CO(N) case N: return run_correct<N>(a, s);
+
+int launch_correct(const CorrArgs &a, hipStream_t s)
+{
+    switch (a.nx / 2) { PK_X_LENGTHS(PK_CASE_CO) default: return -1; }
+}
+
 }  // namespace pk

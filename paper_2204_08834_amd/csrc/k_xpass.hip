@@ -345,6 +345,89 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
     }
 }
 
+// Forward pass of the projection step: the right-hand side
+// f = alpha D(u, v, w) (the divergence of the face velocities) of TJ y-rows
+// is evaluated in FP64 plane by plane with the 2.5-D march of stencil.hpp,
+// optionally stored (the refinement's residual passes read it), rounded once
+// to the transform precision into the LDS tile (which aliases the march's
+// staging arrays) and transformed in place; per-workgroup FP64 sums of f go
+// to `partials` like those of the plain pass.  One problem per launch.
+constexpr int XD_NT = 256;
+
+template <int M>
+__global__ __launch_bounds__(XD_NT) void k_x_div(XFwdArgs a0)
+{
+    XFwdArgs a = a0;
+    if (a.batch) {
+        // the device-side loop passes its pointer records (one problem)
+        const ProbPtrs &q = a.batch[0];
+        a.S = q.S;
+        if (a.partials) a.partials = q.partials;
+    }
+    constexpr int TJ = march_rows_res(M), NT = XD_NT, NX = 2 * M;
+    using Mar = DivMarch<M, TJ, NT>;
+    using Tile = LdsTile<R, M, TJ, false, 0>;
+    constexpr size_t PLANE_B = Mar::lds_bytes();
+    constexpr size_t FFT_B = sizeof(Cx<R>) * Tile::elems;
+    __shared__ __align__(16) char s_buf[PLANE_B > FFT_B ? PLANE_B : FFT_B];
+    __shared__ Cx<R> s_tw[NX];
+    __shared__ double s_red[3 * (NT / 64)];
+
+    const int njb = march_jblocks(a.ny, TJ);
+    const int bid = blockIdx.x;
+    const int jb = bid % njb, kb = bid / njb;
+    const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max);
+    const int k0 = kb * kr;
+    const int k1 = k0 + kr < a.nz ? k0 + kr : a.nz;
+
+    Mar m;
+    m.u = gbl(a.u);
+    m.v = gbl(a.v);
+    m.w = gbl(a.w);
+    m.cx = a.cx;
+    m.cy = a.cy;
+    m.cz = a.cz;
+    m.bind(s_buf);
+    m.setup(jb, a.ny, a.nz, a.bc_z);
+    load_table(s_tw, (const Cx<R> *)a.tw, NX);
+    m.start(k0);
+
+    Tile tile{(Cx<R> *)s_buf};
+    PK_GLOBAL Cx<R> *S = gbl((Cx<R> *)a.S);
+    PK_GLOBAL double *fo = a.f_out ? gbl(a.f_out) : nullptr;
+    double acc0 = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        __syncthreads();  // the previous plane's transform is done with the tile
+        Cx<R> ff[Mar::PER];
+        const size_t kp = (size_t)k * m.plane;
+        auto sink = [&](int q, int, int, double f0, double f1) {
+            acc0 += f0 + f1;
+            ff[q] = {R(f0), R(f1)};
+            if (fo) *(PK_GLOBAL double2 *)(fo + kp + m.roff(q)) = double2{f0, f1};
+        };
+        m.step(k, sink);
+        __syncthreads();  // the march is done reading its staging arrays
+#pragma unroll
+        for (int q = 0; q < Mar::PER; ++q)
+            if (m.valid(q)) tile.at(m.row_of(q), m.pair_of(q)) = ff[q];
+        __syncthreads();
+        auto gload = [&](int b, int n) -> Cx<R> { return tile.at(b, n); };
+        const size_t rowk = (size_t)k * a.ny + m.j0;
+        const int V = m.V;
+        auto out = [&](int b) -> PK_GLOBAL Cx<R> * { return b < V ? S + (rowk + b) * M : nullptr; };
+        x_forward<M, TJ, NT, true>(s_tw, gload, tile, out);
+    }
+    if (a.partials) {
+        double z1 = 0.0, z2 = 0.0;
+        block_sum3(acc0, z1, z2, s_red);
+        if (threadIdx.x == 0) {
+            a.partials[4 * blockIdx.x] = acc0;
+            a.partials[4 * blockIdx.x + 1] = 0.0;
+            a.partials[4 * blockIdx.x + 2] = 0.0;
+        }
+    }
+}
+
 template <int M, bool ACC>
 __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
 {
@@ -466,7 +549,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
 // the workgroups of the residual pass
 template <int M> static int blocks_x(int ny, int nz, int residual, int kr_max)
 {
-    if (residual)
+    if (residual)  // residual and divergence passes: the same plane march
         return march_jblocks(ny, march_rows_res(M)) *
                march_kblocks(ny, nz, march_rows_res(M), kr_max);
     return (ny * nz + XCfg<M>::NB - 1) / XCfg<M>::NB;
@@ -503,7 +586,10 @@ template <int M> static int run_x_fwd(const XFwdArgs &a, hipStream_t s, int *nbl
     if (!a.residual) nb = grid_x_fwd<M>(nb, a.batch ? a.nbatch : 1);
     if (nblocks_out) *nblocks_out = nb;
     const dim3 grid(nb, a.batch ? a.nbatch : 1);
-    if (a.residual) {
+    if (a.residual == 2) {
+        if (a.batch && a.nbatch != 1) return -1;
+        hipLaunchKernelGGL(k_x_div<M>, dim3(nb), dim3(XD_NT), 0, s, a);
+    } else if (a.residual) {
         // the refinement transforms its residual in FP32 only
         if constexpr (sizeof(R) == 4)
             hipLaunchKernelGGL(k_x_res<M>, grid, dim3(XR_NT), 0, s, a);

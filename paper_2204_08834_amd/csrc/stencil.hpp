@@ -1,7 +1,10 @@
-// stencil.hpp -- FP64 residual of the discrete Poisson equation on the
-// marker-and-cell grid, r = (f - mean f) - L p, with L the 7-point operator
-// of FluTAS Section 3.3.1: periodic in x and y; in z periodic, or with the
-// mirrored ghost value at the walls (zero normal gradient on the wall face).
+// stencil.hpp -- the nearest-neighbour stencils of the marker-and-cell grid
+// (FluTAS Sections 3 and 3.3), in FP64: the residual of the discrete Poisson
+// equation, r = (f - mean f) - L p, with L the 7-point operator of Section
+// 3.3.1 (periodic in x and y; in z periodic, or with the mirrored ghost value
+// at the walls: zero normal gradient on the wall face); the divergence of the
+// face velocities (the right-hand side of the projection step); and the
+// velocity correction with the pressure update.
 //
 // 2.5-D blocking.  A workgroup owns TJ consecutive y-rows (all of x) and
 // marches up a range of z-planes.  Each thread keeps p at planes k-1, k, k+1
@@ -44,21 +47,19 @@ __host__ __device__ constexpr int march_kblocks(int ny, int nz, int tj, int kr_m
     return (nz + kr - 1) / kr;
 }
 
+// Indexing of a plane tile: TJ consecutive y-rows (all of x) of one z-plane,
+// M pairs (2h, 2h+1) per row, spread over the NT threads of a workgroup.
 template <int M, int TJ, int NT>
-struct PlaneMarch {
+struct MarchIdx {
     static constexpr int NX = 2 * M;
     static constexpr int E = TJ * M;  // pairs per plane tile
     static constexpr int PER = (E + NT - 1) / NT;
     static constexpr bool EXACT = (E % NT) == 0;
 
-    const PK_GLOBAL double *f, *p;  // set through gbl()
     int ny, nz, bc_z;
-    double ax, ay, az, mu;
     int j0, V;     // first y-row and number of valid rows of this block
     int jm, jn;    // halo rows: (j0 - 1) mod ny and (j0 + V) mod ny
     size_t plane;  // ny * NX
-    double2 (*tile)[M];  // LDS, TJ + 2 rows
-    double2 pd[PER], pc[PER];
 
     // Element q of a thread is (row t, pair h) with e = threadIdx.x + q NT,
     // t = e / M, h = e % M.  When NT divides M (ROWSPLIT) the row of element q
@@ -113,6 +114,28 @@ struct PlaneMarch {
         jn = j0 + V == ny ? 0 : j0 + V;
         plane = (size_t)ny * NX;
     }
+};
+
+template <int M, int TJ, int NT>
+struct PlaneMarch : MarchIdx<M, TJ, NT> {
+    using B = MarchIdx<M, TJ, NT>;
+    using B::PER;
+    using B::NX;
+    using B::plane;
+    using B::roff;
+    using B::valid;
+    using B::row_of;
+    using B::pair_of;
+    using B::kdown;
+    using B::kup;
+    using B::jm;
+    using B::jn;
+    using B::V;
+
+    const PK_GLOBAL double *f, *p;  // set through gbl()
+    double ax, ay, az, mu;
+    double2 (*tile)[M];  // LDS, TJ + 2 rows
+    double2 pd[PER], pc[PER];
 
     // p at planes k0-1 and k0 into registers.  Elements past the last row
     // of the grid load from the start of the plane (in bounds, never used):
@@ -174,6 +197,185 @@ struct PlaneMarch {
             pd[q] = pc[q];
             pc[q] = pu[q];
         }
+    }
+};
+
+// Cell-centred divergence of face velocities on the marker-and-cell grid
+// (FluTAS Section 3, right-hand side of eqn:poisson):
+//   f = cx (u_i - u_{i-1}) + cy (v_j - v_{j-1}) + cz (w_k - w_{k-1}),
+// cx = alpha/dx etc., with u on east faces, v on north faces and w on top
+// faces of the cells; x and y periodic; in z periodic, or walls with no flux
+// through the bottom face of plane 0 and the top face of plane nz-1 (the
+// value stored there is not read).  Same 2.5-D march as the residual: w of
+// plane k-1 is kept in registers, the v rows of plane k with the halo row
+// j0-1 and the odd u value of every pair are staged in LDS for the y and x
+// neighbours.  Reads per output row: u, v, w and 1/TJ halo rows.
+template <int M, int TJ, int NT>
+struct DivMarch : MarchIdx<M, TJ, NT> {
+    using B = MarchIdx<M, TJ, NT>;
+    using B::PER;
+    using B::plane;
+    using B::roff;
+    using B::valid;
+    using B::row_of;
+    using B::pair_of;
+    using B::jm;
+
+    const PK_GLOBAL double *u, *v, *w;  // set through gbl()
+    double cx, cy, cz;
+    double2 (*vt)[M];  // LDS: TJ + 1 rows (row 0: the halo row j0 - 1)
+    double (*ut)[M];   // LDS: TJ rows of u[2h+1]
+    double2 wd[PER];   // w of plane k-1 (the flux through the bottom face)
+
+    // LDS bytes of the two staging arrays
+    static constexpr size_t lds_bytes() { return sizeof(double2) * (TJ + 1) * M + sizeof(double) * TJ * M; }
+    __device__ __forceinline__ void bind(char *lds)
+    {
+        vt = (double2(*)[M])lds;
+        ut = (double(*)[M])(lds + sizeof(double2) * (TJ + 1) * M);
+    }
+
+    __device__ __forceinline__ void start(int k0)
+    {
+        const bool none = k0 == 0 && this->bc_z != 0;  // bottom wall
+        const PK_GLOBAL double *wdn = w + (size_t)B::kdown(k0) * plane;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const double2 x = *(const PK_GLOBAL double2 *)(wdn + roff(q));
+            wd[q] = none ? double2{0.0, 0.0} : x;
+        }
+    }
+
+    // sink(q, t, h, f0, f1) for every valid element (row j0 + t, pair h);
+    // the caller syncs before the next step (the LDS arrays are rewritten)
+    template <class Sink>
+    __device__ __forceinline__ void step(int k, Sink &sink)
+    {
+        const size_t kp = (size_t)k * plane;
+        double2 uu[PER], vv[PER], ww[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int o = roff(q);
+            uu[q] = *(const PK_GLOBAL double2 *)(u + kp + o);
+            vv[q] = *(const PK_GLOBAL double2 *)(v + kp + o);
+            ww[q] = *(const PK_GLOBAL double2 *)(w + kp + o);
+        }
+        for (int h = threadIdx.x; h < M; h += NT)
+            vt[0][h] = *(const PK_GLOBAL double2 *)(v + kp + (size_t)jm * B::NX + 2 * h);
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (valid(q)) {
+                vt[row_of(q) + 1][pair_of(q)] = vv[q];
+                ut[row_of(q)][pair_of(q)] = uu[q].y;
+            }
+        __syncthreads();
+        const bool top = k == this->nz - 1 && this->bc_z != 0;  // top wall
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (valid(q)) {
+                const int t = row_of(q), h = pair_of(q);
+                const double ul = ut[t][h == 0 ? M - 1 : h - 1];
+                const double2 vs = vt[t][h];
+                const double2 wu = top ? double2{0.0, 0.0} : ww[q];
+                const double f0 = cx * (uu[q].x - ul) + cy * (vv[q].x - vs.x) + cz * (wu.x - wd[q].x);
+                const double f1 = cx * (uu[q].y - uu[q].x) + cy * (vv[q].y - vs.y) +
+                                  cz * (wu.y - wd[q].y);
+                sink(q, t, h, f0, f1);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) wd[q] = ww[q];
+    }
+};
+
+// Velocity correction and pressure update of the projection step (FluTAS
+// Section 3.3, eqn:corr and eqn:p_upt) from the solution psi:
+//   u -= bx (psi_{i+1} - psi_i),  v -= by (psi_{j+1} - psi_j),
+//   w -= bz (psi_{k+1} - psi_k),  p += psi,
+// bx = beta/dx etc., on the faces of the divergence above: x and y periodic;
+// in z periodic, or walls, where w on the top face of plane nz-1 (the wall)
+// is left as it is.  psi of plane k+1 is read once per plane into registers
+// and kept as the next plane's centre; the plane-k tile and the halo row
+// j0+V are staged in LDS for the x and y neighbours.
+template <int M, int TJ, int NT>
+struct CorrMarch : MarchIdx<M, TJ, NT> {
+    using B = MarchIdx<M, TJ, NT>;
+    using B::PER;
+    using B::plane;
+    using B::roff;
+    using B::valid;
+    using B::row_of;
+    using B::pair_of;
+    using B::jn;
+    using B::V;
+
+    const PK_GLOBAL double *psi;
+    PK_GLOBAL double *u, *v, *w, *p;  // p may be null
+    double bx, by, bz;
+    double2 (*tile)[M];  // LDS: TJ + 1 rows (row V: the halo row j0 + V)
+    double2 pc[PER];     // psi of plane k
+
+    static constexpr size_t lds_bytes() { return sizeof(double2) * (TJ + 1) * M; }
+
+    __device__ __forceinline__ void start(int k0)
+    {
+        const PK_GLOBAL double *c = psi + (size_t)k0 * plane;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) pc[q] = *(const PK_GLOBAL double2 *)(c + roff(q));
+    }
+
+    // the caller syncs before the next step (the LDS tile is rewritten)
+    __device__ __forceinline__ void step(int k)
+    {
+        const size_t kp = (size_t)k * plane;
+        const PK_GLOBAL double *pup = psi + (size_t)B::kup(k) * plane;
+        const bool top = k == this->nz - 1 && this->bc_z != 0;  // top wall: w stays
+        double2 pu[PER], uu[PER], vv[PER], ww[PER], pp[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int o = roff(q);
+            pu[q] = *(const PK_GLOBAL double2 *)(pup + o);
+            uu[q] = *(const PK_GLOBAL double2 *)(u + kp + o);
+            vv[q] = *(const PK_GLOBAL double2 *)(v + kp + o);
+            ww[q] = *(const PK_GLOBAL double2 *)(w + kp + o);
+            if (p) pp[q] = *(const PK_GLOBAL double2 *)(p + kp + o);
+        }
+        for (int h = threadIdx.x; h < M; h += NT)
+            tile[V][h] = *(const PK_GLOBAL double2 *)(psi + kp + (size_t)jn * B::NX + 2 * h);
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (valid(q)) tile[row_of(q)][pair_of(q)] = pc[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (valid(q)) {
+                const int t = row_of(q), h = pair_of(q), o = roff(q);
+                const double2 c = pc[q];
+                const double pr = tile[t][h == M - 1 ? 0 : h + 1].x;  // psi_{2h+2}
+                const double2 pn = tile[t + 1][h];                     // psi of row j + 1
+                double2 a = uu[q], b = vv[q];
+                a.x -= bx * (c.y - c.x);
+                a.y -= bx * (pr - c.y);
+                b.x -= by * (pn.x - c.x);
+                b.y -= by * (pn.y - c.y);
+                *(PK_GLOBAL double2 *)(u + kp + o) = a;
+                *(PK_GLOBAL double2 *)(v + kp + o) = b;
+                if (!top) {
+                    double2 d = ww[q];
+                    d.x -= bz * (pu[q].x - c.x);
+                    d.y -= bz * (pu[q].y - c.y);
+                    *(PK_GLOBAL double2 *)(w + kp + o) = d;
+                }
+                if (p) {
+                    double2 e = pp[q];
+                    e.x += c.x;
+                    e.y += c.y;
+                    *(PK_GLOBAL double2 *)(p + kp + o) = e;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) pc[q] = pu[q];
     }
 };
 

@@ -89,8 +89,9 @@ def _zero_mean(f):
     return f - f.mean(dtype=np.float64)
 
 
-def uniform_velocity_rhs(nx, ny, nz, Lx, Ly, Lz, bc_z, seed):
-    """u, v, w ~ U(-1,1) drawn in that order; w on the top wall set to 0 for walls."""
+def uniform_velocity(nx, ny, nz, bc_z, seed):
+    """Face velocities u, v, w ~ U(-1,1) drawn in that order; w on the top
+    wall set to 0 for walls."""
     rng = np.random.default_rng(seed)
     shape = (nz, ny, nx)
     u = rng.uniform(-1.0, 1.0, shape)
@@ -98,6 +99,12 @@ def uniform_velocity_rhs(nx, ny, nz, Lx, Ly, Lz, bc_z, seed):
     w = rng.uniform(-1.0, 1.0, shape)
     if bc_z == NEUMANN:
         w[nz - 1] = 0.0
+    return u, v, w
+
+
+def uniform_velocity_rhs(nx, ny, nz, Lx, Ly, Lz, bc_z, seed):
+    """Divergence of uniform_velocity (made zero-mean)."""
+    u, v, w = uniform_velocity(nx, ny, nz, bc_z, seed)
     f = divergence(u, v, w, Lx / nx, Ly / ny, Lz / nz, bc_z)
     return _zero_mean(f)
 

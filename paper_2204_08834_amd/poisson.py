@@ -65,7 +65,8 @@ SYMBOLS = ["poisson_desc_init", "poisson_desc_validate", "poisson_workspace_byte
            "poisson_plan_create", "poisson_solve", "poisson_destroy",
            "poisson_batch_plan_create", "poisson_batch_solve", "poisson_error_string",
            "poisson_plan_set_timing", "poisson_plan_reset_timing", "poisson_plan_get_timing",
-           "poisson_plan_set_graph", "poisson_plan_autotune", "poisson_plan_describe"]
+           "poisson_plan_set_graph", "poisson_plan_autotune", "poisson_plan_describe",
+           "poisson_project"]
 
 # refinement-loop drivers of poisson_plan_set_graph
 GRAPH_MODES = {"host": 0, "graph": 1, "device": 2}
@@ -101,6 +102,8 @@ def lib():
     L.poisson_plan_set_graph.argtypes = [P, ctypes.c_int]
     L.poisson_plan_autotune.argtypes = [P, ctypes.c_int]
     L.poisson_plan_describe.argtypes = [P, ctypes.c_char_p, ctypes.c_int]
+    L.poisson_project.argtypes = [P, P, P, P, P, P, ctypes.c_double, ctypes.c_double,
+                                  ctypes.POINTER(Stats)]
     for name in SYMBOLS:
         if name != "poisson_workspace_bytes" and name != "poisson_error_string":
             getattr(L, name).restype = ctypes.c_int
@@ -192,6 +195,31 @@ class Plan:
         if rc != OK:
             raise PoissonError(rc, "poisson_solve")
         return rc
+
+    def project(self, u, v, w, p=None, psi=None, alpha=1.0, beta=1.0, check=True,
+                stats=True):
+        """Projection step (poisson_project): solve L psi = alpha D(u, v, w),
+        then u -= beta G psi (in place, likewise v and w) and p += psi when p
+        is given.  Returns (psi, stats dict or None)."""
+        import torch
+        for t, name in ((u, "u"), (v, "v"), (w, "w")):
+            _check_field(t, self.shape, name)
+        if p is not None:
+            _check_field(p, self.shape, "p")
+        if psi is None:
+            psi = torch.empty_like(u)
+        _check_field(psi, self.shape, "psi")
+        st = Stats()
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        rc = lib().poisson_project(self._h, ptr(u), ptr(v), ptr(w), ptr(p), ptr(psi),
+                                   float(alpha), float(beta), ctypes.byref(st) if stats else None)
+        if check and rc != OK:
+            raise PoissonError(rc, "poisson_project")
+        if not stats:
+            return psi, None
+        d = st.as_dict()
+        d["status"] = rc
+        return psi, d
 
     def set_timing(self, enable=True):
         lib().poisson_plan_set_timing(self._h, 1 if enable else 0)

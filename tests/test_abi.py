@@ -127,3 +127,11 @@ def test_autotune_and_describe_reject_null_plan():
     assert L.poisson_plan_autotune(None, 0) == P.ERR_INVALID_ARG
     buf = ctypes.create_string_buffer(64)
     assert L.poisson_plan_describe(None, buf, 64) == P.ERR_INVALID_ARG
+
+
+def test_project_rejects_null_plan_and_fields():
+    L = P.lib()
+    st = P.Stats()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.poisson_project(None, fake, fake, fake, None, fake, 1.0, 1.0,
+                             ctypes.byref(st)) == P.ERR_INVALID_ARG
