@@ -7,7 +7,10 @@ and for FP32 + refinement the FP64 residual passes and corrections until the
 relative residual is <= 1e-10.  Inputs are resident in HBM before timing.
 
 Prints one JSON line.  `value` is the FP32+refinement throughput in Mpoints/s;
-the plain FP64 solve of the same workload is timed beside it.  The roofline
+the plain FP64 solve of the same workload is timed beside it, and so is the
+whole projection step on the same grid (divergence of the face velocities
+fused into the first pass, the solve, the velocity correction and pressure
+update), under "projection".  The roofline
 entry is for the kernel with the largest share of the FP32+refinement step,
 timed live with HIP events on the plan's stream.
 
@@ -122,6 +125,65 @@ def bench_batch(steps, warmup):
     return res
 
 
+def bench_project(prob, steps, warmup, tune):
+    """The projection step (poisson_project) on the workload's grid: U(-1,1)
+    face velocities (the workload's seed), alpha = beta = 1, with the pressure
+    update.  Every step projects a fresh copy of the same provisional
+    velocity; the copy is made before the step's timed region."""
+    import torch
+    from paper_2204_08834_amd import inputs, poisson
+    u, v, w = inputs.uniform_velocity(prob.nx, prob.ny, prob.nz, prob.bc_z, prob.seed)
+    src = [torch.from_numpy(x).cuda() for x in (u, v, w)]
+    del u, v, w
+    work = [torch.empty_like(x) for x in src]
+    pres = torch.zeros_like(src[0])
+    psi = torch.empty_like(src[0])
+    npts = prob.npoints
+    dx, dy, dz = prob.spacings()
+    res = {"velocity": "U(-1,1) face velocities, alpha = beta = 1, p += psi"}
+
+    def step(plan):
+        for a, b in zip(work, src):
+            a.copy_(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = plan.project(*work, pres, psi, 1.0, 1.0)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, st
+
+    for prec in ("fp32_refine", "fp64"):
+        plan = poisson.Plan(prob.nx, prob.ny, prob.nz, dx, dy, dz, prob.bc_z, prec,
+                            rtol=1e-10, max_refine=8)
+        if tune:
+            plan.autotune()
+        for _ in range(warmup):
+            step(plan)
+        total, st = 0.0, None
+        for _ in range(steps):
+            t, st = step(plan)
+            total += t
+        ms = total / steps * 1e3
+        plan.set_timing(True)
+        plan.reset_timing()
+        for _ in range(steps):
+            step(plan)
+        passes = plan.timing()
+        plan.close()
+        step_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in passes.values()) / steps
+        res[prec] = {
+            "ms_per_step": ms, "mpoints_s": npts / (ms * 1e-3) / 1e6,
+            "rel_residual": st["rel_residual"], "iterations": st["iterations"],
+            "model_bytes_per_point": step_bytes / npts,
+            "model_hbm_gbs": step_bytes / (ms * 1e-3) / 1e9,
+            "passes": {k: {"avg_ms": v["total_ms"] / v["launches"],
+                           "launches_per_step": v["launches"] / steps,
+                           "gbs": v["bytes_per_launch"] / (v["total_ms"] / v["launches"]
+                                                           * 1e-3) / 1e9}
+                       for k, v in passes.items()}}
+        print(f"[bench] projection {prec} {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    return res
+
+
 def cpu_baseline(prob, nplanes):
     """The FP64 oracle timed on the host on the workload, or on a slab of it:
     the first `nplanes` z-planes (x and y lines keep their full length, so
@@ -174,6 +236,7 @@ def copy_calibration(steps, warmup):
 # kernel-name patterns of the solver's passes (rocprofv3 reports demangled names)
 PASS_PATTERNS = [
     ("x_r2c_residual_{p}", r"prec_{p}::k_x_res<"),
+    ("x_r2c_divergence_{p}", r"prec_{p}::k_x_div<"),
     ("x_r2c_{p}", r"prec_{p}::k_x_fwd<"),
     ("x_c2r_accumulate_{p}", r"prec_{p}::k_x_inv<\d+, true>"),
     ("x_c2r_{p}", r"prec_{p}::k_x_inv<\d+, false>"),
@@ -194,6 +257,8 @@ def pass_of_kernel(name):
         return "residual_check_f64"
     if "k_sum_partials" in name:
         return "sum_partials"
+    if "k_correct<" in name:
+        return "correct_f64"
     return None
 
 
@@ -302,6 +367,8 @@ def main():
     ap.add_argument("--workload", default="rb512", choices=sorted(DESCRIPTIONS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-project", action="store_true",
+                    help="skip the projection step (divergence, solve, correction)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the captured-graph loop timing (profiling runs: its gated-off "
                          "launches would mix into the per-kernel statistics)")
@@ -460,6 +527,13 @@ def main():
             result["dtype"] = "f64"
         else:
             result["fp32refine_over_fp64_speed"] = ms64 / result["ms_per_step"]
+
+    if not args.no_project:
+        print("[bench] projection step", file=sys.stderr, flush=True)
+        del rhs, out
+        torch.cuda.empty_cache()
+        result["projection"] = bench_project(prob, max(3, args.steps // 2), 2,
+                                             not args.no_tune)
 
     if not args.no_batch:
         print("[bench] batched mixed-64 workload", file=sys.stderr, flush=True)

@@ -256,9 +256,9 @@ struct DivMarch : MarchIdx<M, TJ, NT> {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int o = roff(q);
-            uu[q] = *(const PK_GLOBAL double2 *)(u + kp + o);
-            vv[q] = *(const PK_GLOBAL double2 *)(v + kp + o);
-            ww[q] = *(const PK_GLOBAL double2 *)(w + kp + o);
+            uu[q] = ld_stream(u + kp + o);
+            vv[q] = *(const PK_GLOBAL double2 *)(v + kp + o);  // also a halo row
+            ww[q] = *(const PK_GLOBAL double2 *)(w + kp + o);  // also read at k + 1
         }
         for (int h = threadIdx.x; h < M; h += NT)
             vt[0][h] = *(const PK_GLOBAL double2 *)(v + kp + (size_t)jm * B::NX + 2 * h);
@@ -335,10 +335,10 @@ struct CorrMarch : MarchIdx<M, TJ, NT> {
         for (int q = 0; q < PER; ++q) {
             const int o = roff(q);
             pu[q] = *(const PK_GLOBAL double2 *)(pup + o);
-            uu[q] = *(const PK_GLOBAL double2 *)(u + kp + o);
-            vv[q] = *(const PK_GLOBAL double2 *)(v + kp + o);
-            ww[q] = *(const PK_GLOBAL double2 *)(w + kp + o);
-            if (p) pp[q] = *(const PK_GLOBAL double2 *)(p + kp + o);
+            uu[q] = ld_stream(u + kp + o);
+            vv[q] = ld_stream(v + kp + o);
+            ww[q] = ld_stream(w + kp + o);
+            if (p) pp[q] = ld_stream(p + kp + o);
         }
         for (int h = threadIdx.x; h < M; h += NT)
             tile[V][h] = *(const PK_GLOBAL double2 *)(psi + kp + (size_t)jn * B::NX + 2 * h);
@@ -358,19 +358,19 @@ struct CorrMarch : MarchIdx<M, TJ, NT> {
                 a.y -= bx * (pr - c.y);
                 b.x -= by * (pn.x - c.x);
                 b.y -= by * (pn.y - c.y);
-                *(PK_GLOBAL double2 *)(u + kp + o) = a;
-                *(PK_GLOBAL double2 *)(v + kp + o) = b;
+                st_stream(u + kp + o, a);
+                st_stream(v + kp + o, b);
                 if (!top) {
                     double2 d = ww[q];
                     d.x -= bz * (pu[q].x - c.x);
                     d.y -= bz * (pu[q].y - c.y);
-                    *(PK_GLOBAL double2 *)(w + kp + o) = d;
+                    st_stream(w + kp + o, d);
                 }
                 if (p) {
                     double2 e = pp[q];
                     e.x += c.x;
                     e.y += c.y;
-                    *(PK_GLOBAL double2 *)(p + kp + o) = e;
+                    st_stream(p + kp + o, e);
                 }
             }
         }
