@@ -84,6 +84,19 @@ __device__ __forceinline__ int block_order(int bid, int nblocks, int reverse)
     return reverse ? nblocks - 1 - bid : bid;
 }
 
+// Workgroup i of a launch starts on accelerator die (XCD) i % 8, and each
+// die has its own L2.  xcd_order maps the launch index to a logical block
+// index such that every die walks a contiguous run of logical blocks: blocks
+// that share halo rows run on the same die at about the same time and share
+// its L2.  A bijection on [0, nblocks).
+__device__ __forceinline__ int xcd_order(int bid, int nblocks)
+{
+    constexpr int X = 8;
+    const int q = nblocks / X, rem = nblocks % X;
+    const int x = bid % X, slot = bid / X;
+    return x * q + (x < rem ? x : rem) + slot;
+}
+
 // Per-problem pointers of a batched launch: problems of one shape share a
 // launch and blockIdx.y selects the entry.  A null `batch` pointer in the
 // argument structs below means a single-problem launch using their own

@@ -196,7 +196,7 @@ __global__ __launch_bounds__(RC_NT) void k_residual_check(XFwdArgs a0)
         a.sum_f = q.scal + 1;
     }
     const int njb = march_jblocks(a.ny, TJ);
-    const int bid = block_order(blockIdx.x, gridDim.x, a.reverse);
+    const int bid = block_order(xcd_order(blockIdx.x, gridDim.x), gridDim.x, a.reverse);
     const int jb = bid % njb, kb = bid / njb;
     const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max);
     const int k0 = kb * kr;
@@ -272,7 +272,8 @@ __global__ __launch_bounds__(CO_NT) void k_correct(CorrArgs a)
     using Mar = CorrMarch<M, TJ, CO_NT>;
     __shared__ double2 s_tile[TJ + 1][M];
     const int njb = march_jblocks(a.ny, TJ);
-    const int jb = blockIdx.x % njb, kb = blockIdx.x / njb;
+    const int bid = xcd_order(blockIdx.x, gridDim.x);
+    const int jb = bid % njb, kb = bid / njb;
     const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max);
     const int k0 = kb * kr;
     const int k1 = k0 + kr < a.nz ? k0 + kr : a.nz;

@@ -297,7 +297,7 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
     __shared__ double s_red[3 * (NT / 64)];
 
     const int njb = march_jblocks(a.ny, TJ);
-    const int bid = block_order(blockIdx.x, gridDim.x, a.reverse);
+    const int bid = block_order(xcd_order(blockIdx.x, gridDim.x), gridDim.x, a.reverse);
     const int jb = bid % njb, kb = bid / njb;
     const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max);
     const int k0 = kb * kr;
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(XD_NT) void k_x_div(XFwdArgs a0)
     __shared__ double s_red[3 * (NT / 64)];
 
     const int njb = march_jblocks(a.ny, TJ);
-    const int bid = blockIdx.x;
+    const int bid = xcd_order(blockIdx.x, gridDim.x);
     const int jb = bid % njb, kb = bid / njb;
     const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max);
     const int k0 = kb * kr;
