@@ -1,9 +1,11 @@
 """TEST INFRASTRUCTURE ONLY: FP64 CPU oracle for the FFT-based Poisson solve.
 
 The oracle is a plain C implementation (``poisson_oracle.c``) of the solve in
-FluTAS (arXiv 2204.08834), Section 3.3.1: textbook DFTs along x and y, Gauss
-elimination (Thomas) along z for walls or a DFT along z when periodic, the
-inverse transforms, and a zero-mean gauge.  It shares no code with the GPU
+FluTAS (arXiv 2204.08834), Section 3.3.1: textbook expansions along x and y
+(DFTs for periodic axes, cosine / sine sums for Neumann / Dirichlet walls),
+Gauss elimination (Thomas) along z for walls or a DFT along z when periodic,
+the inverse expansions, and a zero-mean gauge when the constant is in the
+operator's null space.  It shares no code with the GPU
 library.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline
 leg of ``bench.py`` may use it.
 
@@ -23,6 +25,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 PERIODIC = 0
 NEUMANN = 1
+DIRICHLET = 2
 
 # Planted mistakes (mirrors the MUT_* constants in poisson_oracle.c).
 MUTATIONS = {
@@ -35,6 +38,9 @@ MUTATIONS = {
     "drop_z": 7,
     "offdiag": 8,
     "idx_y": 9,
+    "dir_row": 10,
+    "cos_shift": 11,
+    "sin_index": 12,
 }
 
 _lib = None
@@ -62,6 +68,15 @@ def _load():
     lib.oracle_solve_ex.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
         ctypes.c_int, dp, dp, dp, dp, ctypes.c_int]
     lib.oracle_solve_ex.restype = ctypes.c_int
+    lib.oracle_solve_bc.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
+        ctypes.c_int] * 3 + [dp, dp, dp, dp, ctypes.c_int]
+    lib.oracle_solve_bc.restype = ctypes.c_int
+    lib.oracle_laplacian_bc.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
+        ctypes.c_int] * 3 + [dp, dp]
+    lib.oracle_laplacian_bc.restype = ctypes.c_int
+    lib.oracle_residual_bc.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
+        ctypes.c_int] * 3 + [dp, dp, dp, dp, dp]
+    lib.oracle_residual_bc.restype = ctypes.c_int
     lib.oracle_laplacian.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
         ctypes.c_int, dp, dp]
     lib.oracle_laplacian.restype = ctypes.c_int
@@ -91,8 +106,10 @@ def _check(f):
     return f
 
 
-def solve(f, dx, dy, dz, bc_z, mutation: int | str = 0, return_info: bool = False):
-    """Zero-mean p with L p = f - mean(f).  bc_z: PERIODIC (0) or NEUMANN (1)."""
+def solve(f, dx, dy, dz, bc_z, mutation: int | str = 0, return_info: bool = False,
+          bc_x: int = PERIODIC, bc_y: int = PERIODIC):
+    """p with L p = f - mean(f), zero-mean, when no axis is Dirichlet; else
+    L p = f.  Boundaries per axis: PERIODIC (0), NEUMANN (1), DIRICHLET (2)."""
     lib = _load()
     f = _check(f)
     nz, ny, nx = f.shape
@@ -101,8 +118,9 @@ def solve(f, dx, dy, dz, bc_z, mutation: int | str = 0, return_info: bool = Fals
     mim = ctypes.c_double(0.0)
     if isinstance(mutation, str):
         mutation = MUTATIONS[mutation]
-    rc = lib.oracle_solve_ex(nx, ny, nz, dx, dy, dz, int(bc_z), _ptr(f), _ptr(p),
-                             ctypes.byref(mean), ctypes.byref(mim), int(mutation))
+    rc = lib.oracle_solve_bc(nx, ny, nz, dx, dy, dz, int(bc_x), int(bc_y), int(bc_z),
+                             _ptr(f), _ptr(p), ctypes.byref(mean), ctypes.byref(mim),
+                             int(mutation))
     if rc != 0:
         raise RuntimeError(f"oracle_solve failed ({rc})")
     if return_info:
@@ -110,19 +128,22 @@ def solve(f, dx, dy, dz, bc_z, mutation: int | str = 0, return_info: bool = Fals
     return p
 
 
-def laplacian(p, dx, dy, dz, bc_z):
+def laplacian(p, dx, dy, dz, bc_z, bc_x: int = PERIODIC, bc_y: int = PERIODIC):
     lib = _load()
     p = _check(p)
     nz, ny, nx = p.shape
     out = np.empty_like(p)
-    rc = lib.oracle_laplacian(nx, ny, nz, dx, dy, dz, int(bc_z), _ptr(p), _ptr(out))
+    rc = lib.oracle_laplacian_bc(nx, ny, nz, dx, dy, dz, int(bc_x), int(bc_y), int(bc_z),
+                                 _ptr(p), _ptr(out))
     if rc != 0:
         raise RuntimeError("oracle_laplacian failed")
     return out
 
 
-def residual(f, p, dx, dy, dz, bc_z, return_field: bool = False):
-    """Relative residual ||(f - mean f) - L p||_2 / ||f - mean f||_2 (and Linf)."""
+def residual(f, p, dx, dy, dz, bc_z, return_field: bool = False, bc_x: int = PERIODIC,
+             bc_y: int = PERIODIC):
+    """Relative residual ||(f - mean f) - L p||_2 / ||f - mean f||_2 (and Linf);
+    the mean is removed only when no axis is Dirichlet."""
     lib = _load()
     f = _check(f)
     p = _check(p)
@@ -130,9 +151,9 @@ def residual(f, p, dx, dy, dz, bc_z, return_field: bool = False):
     r = np.empty_like(f) if return_field else None
     l2 = ctypes.c_double()
     li = ctypes.c_double()
-    rc = lib.oracle_residual(nx, ny, nz, dx, dy, dz, int(bc_z), _ptr(f), _ptr(p),
-                             _ptr(r) if r is not None else None,
-                             ctypes.byref(l2), ctypes.byref(li))
+    rc = lib.oracle_residual_bc(nx, ny, nz, dx, dy, dz, int(bc_x), int(bc_y), int(bc_z),
+                                _ptr(f), _ptr(p), _ptr(r) if r is not None else None,
+                                ctypes.byref(l2), ctypes.byref(li))
     if rc != 0:
         raise RuntimeError("oracle_residual failed")
     if return_field:

@@ -14,19 +14,23 @@
  *
  * where L is the second-order finite-difference Laplacian on the uniform
  * marker-and-cell grid of Section 3 (pressure at cell centres; seven
- * non-zero diagonals, Section 3.3.1), periodic along x and y, and along z
- * either periodic or bounded by walls on the cell faces with zero normal
- * pressure gradient (the wall condition stated after eqn:corr).  At a wall
- * the ghost value mirrors the first interior cell.
+ * non-zero diagonals, Section 3.3.1).  Each axis is periodic or bounded by
+ * walls on the end faces of the cells with a homogeneous condition: zero
+ * normal gradient (the wall condition stated after eqn:corr; the ghost value
+ * mirrors the wall cell) or zero value (the ghost value is the negated wall
+ * cell) -- the homogeneous pressure conditions the solver of Section 3.3.1
+ * covers with its Fourier-based expansions.  With a zero-value wall anywhere
+ * the system is regular: nothing is removed and p is not shifted.
  *
  * How (the eigen-expansion of Section 3.3.1, taken in its steps):
- *   1. remove the mean of f;
- *   2. forward discrete Fourier transform along x, then along y
- *      (textbook O(n^2) sums, full complex spectrum, no symmetry shortcuts);
- *   3. per wavenumber pair (mx,my): walls -> tridiagonal system along z solved
+ *   1. remove the mean of f (when the constant is in the null space);
+ *   2. forward expansion along x, then along y: a discrete Fourier transform
+ *      for a periodic axis, the cosine or sine basis of the wall condition
+ *      otherwise (textbook O(n^2) sums, no symmetry shortcuts);
+ *   3. per mode pair (mx,my): walls in z -> tridiagonal system along z solved
  *      by Gauss elimination without pivoting (Thomas); periodic -> DFT along
  *      z and division by the eigenvalue of the 3-D operator;
- *   4. inverse transforms along y then x, keep the real part;
+ *   4. inverse expansions along y then x, keep the real part;
  *   5. remove the mean of p (the gauge; the paper leaves it open).
  *
  * Eigenvalues of the periodic 3-point operator (not printed in the paper;
@@ -54,6 +58,7 @@
 
 #define ORC_PERIODIC 0
 #define ORC_NEUMANN 1
+#define ORC_DIRICHLET 2
 
 /* mutations (test-only planted mistakes) */
 #define MUT_NONE 0
@@ -66,6 +71,9 @@
 #define MUT_DROP_Z 7          /* the z part of the operator dropped (walls) */
 #define MUT_OFFDIAG 8         /* off-diagonal of the z system uses 1/dx^2 */
 #define MUT_IDX_Y 9           /* y DFT exponent uses (m*j+1) */
+#define MUT_DIR_ROW 10        /* Dirichlet wall rows use the Neumann diagonal */
+#define MUT_COS_SHIFT 11      /* cosine basis without the half-cell shift */
+#define MUT_SIN_INDEX 12      /* sine basis index k instead of k+1 */
 
 static const double ORC_PI = 3.14159265358979323846264338327950288;
 
@@ -151,6 +159,88 @@ static void dft_axis(double complex *a, int nx, int ny, int nz, int axis, int si
     free(w);
 }
 
+/* Basis functions of the cell-centred three-point operator with a wall on
+ * each end face (Section 3: pressure at cell centres; the walls sit on the
+ * faces i = -1/2 and i = n - 1/2):
+ *   Neumann (mirrored ghost):  phi_k(i) = cos(pi k (i + 1/2) / n),
+ *                              lambda_k = -(4/h^2) sin^2(pi k / (2n));
+ *   Dirichlet (negated ghost): phi_k(i) = sin(pi (k+1) (i + 1/2) / n),
+ *                              lambda_k = -(4/h^2) sin^2(pi (k+1) / (2n)),
+ * k = 0..n-1.  Both follow from applying the stencil to phi_k: the ghost
+ * value at a wall is phi_k(-1) = phi_k(0) (cosines) or -phi_k(0) (sines).
+ * The bases are orthogonal with sum_i phi_k(i)^2 = n/2, except n for k = 0
+ * (cosines) and for k = n-1 (sines). */
+static double basis(int type, int k, int i, int n, int mutation)
+{
+    if (type == ORC_NEUMANN) {
+        double x = (mutation == MUT_COS_SHIFT) ? (double)i : i + 0.5;
+        return cos(ORC_PI * k * x / n);
+    }
+    int kk = (mutation == MUT_SIN_INDEX) ? k : k + 1;
+    return sin(ORC_PI * kk * (i + 0.5) / n);
+}
+
+static double basis_norm2(int type, int k, int n)
+{
+    if (type == ORC_NEUMANN) return k == 0 ? (double)n : 0.5 * n;
+    return k == n - 1 ? (double)n : 0.5 * n;
+}
+
+static double eig_wall(int type, int k, int n, double h)
+{
+    double ang = (type == ORC_NEUMANN) ? ORC_PI * k / (2.0 * n) : ORC_PI * (k + 1) / (2.0 * n);
+    double s = sin(ang);
+    return -4.0 / (h * h) * s * s;
+}
+
+/* Expansion in one of the wall bases along axis 0 (x) or 1 (y) of a complex
+ * (nz,ny,nx) array, applied to real and imaginary parts alike (the bases are
+ * real): forward c_k = sum_i a_i phi_k(i); inverse a_i = sum_k c_k phi_k(i) /
+ * ||phi_k||^2.  Textbook O(n^2) sums. */
+static void wall_axis(double complex *a, int nx, int ny, int nz, int axis, int type,
+                      int inverse, int mutation)
+{
+    int n = axis == 0 ? nx : ny;
+    long stride = axis == 0 ? 1 : nx;
+    long nlines = (long)nx * ny * nz / n;
+    double *tab = malloc(sizeof(double) * (size_t)n * n); /* tab[k*n + i] = phi_k(i) */
+    for (int k = 0; k < n; ++k)
+        for (int i = 0; i < n; ++i) tab[(long)k * n + i] = basis(type, k, i, n, mutation);
+#pragma omp parallel
+    {
+        double complex *in = malloc(sizeof(double complex) * n);
+#pragma omp for schedule(static)
+        for (long l = 0; l < nlines; ++l) {
+            long base;
+            if (axis == 0) {
+                base = l * nx;
+            } else {
+                long k = l / nx, i = l % nx;
+                base = k * (long)nx * ny + i;
+            }
+            for (int t = 0; t < n; ++t) in[t] = a[base + (long)t * stride];
+            for (int o = 0; o < n; ++o) {
+                double complex acc = 0.0;
+                if (!inverse) {
+                    for (int i = 0; i < n; ++i) acc += in[i] * tab[(long)o * n + i];
+                } else {
+                    for (int k = 0; k < n; ++k)
+                        acc += in[k] * tab[(long)k * n + o] / basis_norm2(type, k, n);
+                }
+                a[base + (long)o * stride] = acc;
+            }
+        }
+        free(in);
+    }
+    free(tab);
+}
+
+/* eigenvalue of mode m of the three-point operator along one axis */
+static double eig_axis(int bc, int m, int n, double h, int mutation)
+{
+    return bc == ORC_PERIODIC ? eig_periodic(m, n, h, mutation) : eig_wall(bc, m, n, h);
+}
+
 /* Thomas algorithm (Gauss elimination without pivoting) for
  *   lo[k] x[k-1] + di[k] x[k] + up[k] x[k+1] = d[k],  k = 0..n-1,
  * real coefficients, complex right-hand side, solved in place. */
@@ -169,14 +259,16 @@ static void thomas(int n, const double *lo, const double *di, const double *up,
 }
 
 /* z solve for wall-bounded boxes, one (mx,my) column of the x-y spectrum.
- * Rows (units 1/dz^2): a p[k-1] + (lam - 2a) p[k] + a p[k+1] = g[k] with the
- * mirrored ghost at both walls, which turns the wall rows into
- * (lam - a) p[0] + a p[1] and a p[nz-2] + (lam - a) p[nz-1].
- * For the singular (0,0) column the value at k=0 is pinned to zero, the
- * redundant first row is dropped, and the column mean is removed afterwards. */
+ * Rows (units 1/dz^2): a p[k-1] + (lam - 2a) p[k] + a p[k+1] = g[k]; at a
+ * wall the ghost value is p[0] (Neumann, mirrored) or -p[0] (Dirichlet,
+ * negated), which turns the wall rows into (lam - a) p[0] + a p[1] or
+ * (lam - 3a) p[0] + a p[1] (likewise at the top).
+ * For the singular column (Neumann, zero wavenumber) the value at k=0 is
+ * pinned to zero, the redundant first row is dropped, and the column mean is
+ * removed afterwards. */
 static void zsolve_walls(int nz, double dz, double lam, int singular, double complex *g,
                          double *lo, double *di, double *up, double *cp, int mutation,
-                         double dx)
+                         double dx, int bc_z)
 {
     double a = 1.0 / (dz * dz);
     if (mutation == MUT_OFFDIAG) a = 1.0 / (dx * dx);
@@ -189,6 +281,10 @@ static void zsolve_walls(int nz, double dz, double lam, int singular, double com
         if (k > 0) nb += a;
         if (k < nz - 1) nb += a;
         di[k] = lam - nb;
+        if (bc_z == ORC_DIRICHLET && mutation != MUT_DIR_ROW) {
+            if (k == 0) di[k] -= 2.0 * a;       /* ghost -p[0]: -2a - a */
+            if (k == nz - 1) di[k] -= 2.0 * a;  /* ghost -p[nz-1] */
+        }
         if (mutation == MUT_WALL_ROW) di[k] = lam - two_a;
         if (mutation == MUT_DROP_Z) di[k] = lam;
     }
@@ -216,38 +312,52 @@ static void zsolve_walls(int nz, double dz, double lam, int singular, double com
 }
 
 /*
- * oracle_solve_ex: the full solve with an optional planted mistake.
+ * oracle_solve_bc: the full solve with a boundary condition per axis and an
+ * optional planted mistake.
  *   f, p: (nz,ny,nx) C-order (x fastest) double arrays, p written.
- *   bc_z: 0 periodic, 1 walls (homogeneous Neumann on the cell faces).
- *   rhs_mean (nullable): receives mean(f).
- *   max_imag (nullable): receives max|Im| / max|Re| before the real part is taken.
+ *   bc_x, bc_y, bc_z: 0 periodic, 1 walls with homogeneous Neumann (zero
+ *   normal gradient), 2 walls with homogeneous Dirichlet (zero value on the
+ *   wall face); walls sit on the end faces of the cells.
+ *   When no axis is Dirichlet the operator has the constant null vector: the
+ *   mean of f is removed (and reported) and p is made zero-mean.  Otherwise
+ *   the system is regular, nothing is removed and rhs_mean receives 0.
+ *   rhs_mean (nullable), max_imag (nullable): max|Im| / max|Re| before the
+ *   real part is taken.
  * Returns 0 on success, -1 on bad arguments or allocation failure.
  */
-int oracle_solve_ex(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
-                    const double *f, double *p, double *rhs_mean, double *max_imag,
-                    int mutation)
+int oracle_solve_bc(int nx, int ny, int nz, double dx, double dy, double dz, int bc_x,
+                    int bc_y, int bc_z, const double *f, double *p, double *rhs_mean,
+                    double *max_imag, int mutation)
 {
     if (nx < 1 || ny < 1 || nz < 1 || !(dx > 0) || !(dy > 0) || !(dz > 0) || !f || !p)
         return -1;
-    if (bc_z != ORC_PERIODIC && bc_z != ORC_NEUMANN) return -1;
+    if (bc_x < 0 || bc_x > 2 || bc_y < 0 || bc_y > 2 || bc_z < 0 || bc_z > 2) return -1;
+    const int singular_problem =
+        bc_x != ORC_DIRICHLET && bc_y != ORC_DIRICHLET && bc_z != ORC_DIRICHLET;
     long n = (long)nx * ny * nz;
     double complex *a = malloc(sizeof(double complex) * n);
     if (!a) return -1;
 
-    /* 1. remove the mean */
-    double mean = pairwise_sum(f, n) / (double)n;
+    /* 1. remove the mean (only where the constant is in the null space) */
+    double mean = singular_problem ? pairwise_sum(f, n) / (double)n : 0.0;
     if (rhs_mean) *rhs_mean = mean;
     for (long t = 0; t < n; ++t) a[t] = f[t] - mean;
 
-    /* 2. forward DFTs along x and y */
-    dft_axis(a, nx, ny, nz, 0, -1, 1.0, mutation);
-    dft_axis(a, nx, ny, nz, 1, -1, 1.0, mutation);
+    /* 2. forward expansions along x and y */
+    if (bc_x == ORC_PERIODIC)
+        dft_axis(a, nx, ny, nz, 0, -1, 1.0, mutation);
+    else
+        wall_axis(a, nx, ny, nz, 0, bc_x, 0, mutation);
+    if (bc_y == ORC_PERIODIC)
+        dft_axis(a, nx, ny, nz, 1, -1, 1.0, mutation);
+    else
+        wall_axis(a, nx, ny, nz, 1, bc_y, 0, mutation);
 
     double hx = dx, hy = dy;
     if (mutation == MUT_SWAP_DXDY) { hx = dy; hy = dx; }
 
     /* 3. z-solve per (mx,my) */
-    if (bc_z == ORC_NEUMANN) {
+    if (bc_z != ORC_PERIODIC) {
 #pragma omp parallel
         {
             double complex *g = malloc(sizeof(double complex) * nz);
@@ -256,9 +366,11 @@ int oracle_solve_ex(int nx, int ny, int nz, double dx, double dy, double dz, int
 #pragma omp for schedule(static)
             for (long q = 0; q < (long)nx * ny; ++q) {
                 int mx = (int)(q % nx), my = (int)(q / nx);
-                double lam = eig_periodic(mx, nx, hx, mutation) + eig_periodic(my, ny, hy, mutation);
+                double lam = eig_axis(bc_x, mx, nx, hx, mutation) +
+                             eig_axis(bc_y, my, ny, hy, mutation);
+                int singular = singular_problem && mx == 0 && my == 0;
                 for (int k = 0; k < nz; ++k) g[k] = a[(long)k * nx * ny + q];
-                zsolve_walls(nz, dz, lam, mx == 0 && my == 0, g, lo, di, up, cp, mutation, dx);
+                zsolve_walls(nz, dz, lam, singular, g, lo, di, up, cp, mutation, dx, bc_z);
                 for (int k = 0; k < nz; ++k) a[(long)k * nx * ny + q] = g[k];
             }
             free(g); free(lo); free(di); free(up); free(cp);
@@ -270,11 +382,12 @@ int oracle_solve_ex(int nx, int ny, int nz, double dx, double dy, double dz, int
             int mx = (int)(t % nx);
             int my = (int)((t / nx) % ny);
             int mz = (int)(t / ((long)nx * ny));
-            double lam = eig_periodic(mx, nx, hx, mutation) + eig_periodic(my, ny, hy, mutation);
+            double lam = eig_axis(bc_x, mx, nx, hx, mutation) +
+                         eig_axis(bc_y, my, ny, hy, mutation);
             double lz = eig_periodic(mz, nz, dz, mutation);
             if (mutation == MUT_DROP_Z) lz = 0.0;
             lam += lz;
-            if (mx == 0 && my == 0 && mz == 0)
+            if (singular_problem && mx == 0 && my == 0 && mz == 0)
                 a[t] = 0.0;
             else if (lam == 0.0)
                 a[t] = 0.0; /* only reachable with a planted mistake */
@@ -284,9 +397,15 @@ int oracle_solve_ex(int nx, int ny, int nz, double dx, double dy, double dz, int
         dft_axis(a, nx, ny, nz, 2, +1, 1.0 / nz, mutation);
     }
 
-    /* 4. inverse DFTs along y then x */
-    dft_axis(a, nx, ny, nz, 1, +1, mutation == MUT_NO_NORM_Y ? 1.0 : 1.0 / ny, mutation);
-    dft_axis(a, nx, ny, nz, 0, +1, 1.0 / nx, mutation);
+    /* 4. inverse expansions along y then x */
+    if (bc_y == ORC_PERIODIC)
+        dft_axis(a, nx, ny, nz, 1, +1, mutation == MUT_NO_NORM_Y ? 1.0 : 1.0 / ny, mutation);
+    else
+        wall_axis(a, nx, ny, nz, 1, bc_y, 1, mutation);
+    if (bc_x == ORC_PERIODIC)
+        dft_axis(a, nx, ny, nz, 0, +1, 1.0 / nx, mutation);
+    else
+        wall_axis(a, nx, ny, nz, 0, bc_x, 1, mutation);
 
     double mre = 0.0, mim = 0.0;
     for (long t = 0; t < n; ++t) {
@@ -298,12 +417,22 @@ int oracle_solve_ex(int nx, int ny, int nz, double dx, double dy, double dz, int
     if (max_imag) *max_imag = (mre > 0) ? mim / mre : mim;
     free(a);
 
-    /* 5. gauge: zero mean */
-    if (mutation != MUT_NO_GAUGE) {
+    /* 5. gauge: zero mean (singular problems only) */
+    if (singular_problem && mutation != MUT_NO_GAUGE) {
         double pm = pairwise_sum(p, n) / (double)n;
         for (long t = 0; t < n; ++t) p[t] -= pm;
     }
     return 0;
+}
+
+/* the solve with x and y periodic (the original interface) */
+int oracle_solve_ex(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
+                    const double *f, double *p, double *rhs_mean, double *max_imag,
+                    int mutation)
+{
+    if (bc_z != ORC_PERIODIC && bc_z != ORC_NEUMANN) return -1;
+    return oracle_solve_bc(nx, ny, nz, dx, dy, dz, ORC_PERIODIC, ORC_PERIODIC, bc_z, f, p,
+                           rhs_mean, max_imag, mutation);
 }
 
 int oracle_solve(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
@@ -312,34 +441,43 @@ int oracle_solve(int nx, int ny, int nz, double dx, double dy, double dz, int bc
     return oracle_solve_ex(nx, ny, nz, dx, dy, dz, bc_z, f, p, rhs_mean, max_imag, MUT_NONE);
 }
 
+/* neighbour of index i at offset +1 or -1 along an axis of n cells:
+ * returns the index and the factor of the ghost value (1 periodic or
+ * mirrored, -1 negated at a Dirichlet wall) */
+static int nbr(int i, int d, int n, int bc, double *fac)
+{
+    int j = i + d;
+    *fac = 1.0;
+    if (j >= 0 && j < n) return j;
+    if (bc == ORC_PERIODIC) return (j + n) % n;
+    if (bc == ORC_DIRICHLET) *fac = -1.0;
+    return i; /* the ghost mirrors (or negates) the wall cell */
+}
+
 /*
- * oracle_laplacian: out = L p, the 7-point operator of Section 3 on the MAC
- * grid (periodic x,y; z periodic or mirrored ghost at the walls).
+ * oracle_laplacian_bc: out = L p, the 7-point operator of Section 3 on the
+ * MAC grid with per-axis boundaries (0 periodic, 1 Neumann: ghost = wall
+ * cell, 2 Dirichlet: ghost = -wall cell).
  */
-int oracle_laplacian(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
-                     const double *p, double *out)
+int oracle_laplacian_bc(int nx, int ny, int nz, double dx, double dy, double dz, int bc_x,
+                        int bc_y, int bc_z, const double *p, double *out)
 {
     if (nx < 1 || ny < 1 || nz < 1 || !p || !out) return -1;
     double ax = 1.0 / (dx * dx), ay = 1.0 / (dy * dy), az = 1.0 / (dz * dz);
 #pragma omp parallel for schedule(static)
     for (long kk = 0; kk < (long)nz * ny; ++kk) {
         int k = (int)(kk / ny), j = (int)(kk % ny);
-        int jm = (j + ny - 1) % ny, jp = (j + 1) % ny;
-        int km, kp;
-        if (bc_z == ORC_PERIODIC) {
-            km = (k + nz - 1) % nz;
-            kp = (k + 1) % nz;
-        } else {
-            km = (k > 0) ? k - 1 : 0;          /* mirrored ghost at the bottom wall */
-            kp = (k < nz - 1) ? k + 1 : nz - 1; /* and at the top wall */
-        }
+        double fjm, fjp, fkm, fkp;
+        int jm = nbr(j, -1, ny, bc_y, &fjm), jp = nbr(j, +1, ny, bc_y, &fjp);
+        int km = nbr(k, -1, nz, bc_z, &fkm), kp = nbr(k, +1, nz, bc_z, &fkp);
         for (int i = 0; i < nx; ++i) {
-            int im = (i + nx - 1) % nx, ip = (i + 1) % nx;
+            double fim, fip;
+            int im = nbr(i, -1, nx, bc_x, &fim), ip = nbr(i, +1, nx, bc_x, &fip);
 #define P(K, J, I) p[((long)(K) * ny + (J)) * nx + (I)]
             double c = P(k, j, i);
-            double v = ax * (P(k, j, ip) - 2.0 * c + P(k, j, im)) +
-                       ay * (P(k, jp, i) - 2.0 * c + P(k, jm, i)) +
-                       az * (P(kp, j, i) - 2.0 * c + P(km, j, i));
+            double v = ax * (fip * P(k, j, ip) - 2.0 * c + fim * P(k, j, im)) +
+                       ay * (fjp * P(k, jp, i) - 2.0 * c + fjm * P(k, jm, i)) +
+                       az * (fkp * P(kp, j, i) - 2.0 * c + fkm * P(km, j, i));
 #undef P
             out[((long)k * ny + j) * nx + i] = v;
         }
@@ -347,19 +485,32 @@ int oracle_laplacian(int nx, int ny, int nz, double dx, double dy, double dz, in
     return 0;
 }
 
+/* x and y periodic; z periodic or Neumann walls (the original interface) */
+int oracle_laplacian(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
+                     const double *p, double *out)
+{
+    return oracle_laplacian_bc(nx, ny, nz, dx, dy, dz, ORC_PERIODIC, ORC_PERIODIC, bc_z, p, out);
+}
+
 /*
- * oracle_residual: r = (f - mean(f)) - L p, plus the relative L2 and Linf
- * norms ||r|| / ||f - mean(f)||.  r may be NULL.
+ * oracle_residual_bc: r = (f - mean(f)) - L p (the mean is removed only when
+ * no axis is Dirichlet, as in the solve), plus the relative L2 and Linf norms
+ * ||r|| / ||f - mean(f)||.  r may be NULL.
  */
-int oracle_residual(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
-                    const double *f, const double *p, double *r, double *rel_l2,
-                    double *rel_linf)
+int oracle_residual_bc(int nx, int ny, int nz, double dx, double dy, double dz, int bc_x,
+                       int bc_y, int bc_z, const double *f, const double *p, double *r,
+                       double *rel_l2, double *rel_linf)
 {
     long n = (long)nx * ny * nz;
     double *lp = malloc(sizeof(double) * n);
     if (!lp) return -1;
-    if (oracle_laplacian(nx, ny, nz, dx, dy, dz, bc_z, p, lp)) { free(lp); return -1; }
-    double mean = pairwise_sum(f, n) / (double)n;
+    if (oracle_laplacian_bc(nx, ny, nz, dx, dy, dz, bc_x, bc_y, bc_z, p, lp)) {
+        free(lp);
+        return -1;
+    }
+    const int singular_problem =
+        bc_x != ORC_DIRICHLET && bc_y != ORC_DIRICHLET && bc_z != ORC_DIRICHLET;
+    double mean = singular_problem ? pairwise_sum(f, n) / (double)n : 0.0;
     double s2r = 0, s2f = 0, mr = 0, mf = 0;
     for (long t = 0; t < n; ++t) {
         double fb = f[t] - mean;
@@ -374,6 +525,14 @@ int oracle_residual(int nx, int ny, int nz, double dx, double dy, double dz, int
     if (rel_l2) *rel_l2 = (s2f > 0) ? sqrt(s2r / s2f) : sqrt(s2r);
     if (rel_linf) *rel_linf = (mf > 0) ? mr / mf : mr;
     return 0;
+}
+
+int oracle_residual(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
+                    const double *f, const double *p, double *r, double *rel_l2,
+                    double *rel_linf)
+{
+    return oracle_residual_bc(nx, ny, nz, dx, dy, dz, ORC_PERIODIC, ORC_PERIODIC, bc_z, f, p, r,
+                              rel_l2, rel_linf);
 }
 
 /*

@@ -15,6 +15,13 @@ periodic x and y, periodic or wall-bounded z with zero normal gradient):
   library FFT + banded-solver implementation;
 * hand-derived tiny solutions stored under tests/golden/;
 * every planted mistake in the oracle is caught by at least one pin.
+
+Walls along x and y, and zero-value (Dirichlet) walls along any axis (the
+homogeneous pressure conditions of the Fourier-based expansions of Section
+3.3.1): a dense solve of the operator assembled cell by cell from the ghost
+rules for all 27 boundary combinations, closed-form cosine / sine eigenmodes
+verified by a shifted-array stencil, and 1-D reductions to scipy's DCT-II and
+DST-II.
 """
 import math
 import os
@@ -27,7 +34,7 @@ import scipy.linalg as sla
 from paper_2204_08834_amd import inputs
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-P, N = 0, 1  # periodic, walls (Neumann) in z
+P, N, D = 0, 1, 2  # periodic, Neumann walls, Dirichlet walls
 
 
 # --------------------------------------------------------------------------
@@ -67,6 +74,52 @@ def dense_operator(nx, ny, nz, dx, dy, dz, bc):
                     A[r, idx(ii, jj, kk)] += 1.0 / h ** 2
                     A[r, r] -= 1.0 / h ** 2
     return A
+
+
+def dense_operator_bc(nx, ny, nz, dx, dy, dz, bcs):
+    """Assemble L cell by cell with a boundary per axis, bcs = (x, y, z):
+    a neighbour outside a wall is a ghost equal to the wall cell (Neumann)
+    or to minus it (Dirichlet)."""
+    n = nx * ny * nz
+    A = np.zeros((n, n))
+    dims = (nx, ny, nz)
+
+    def idx(c):
+        return (c[2] * ny + c[1]) * nx + c[0]
+
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                c = (i, j, k)
+                r = idx(c)
+                for ax, h in ((0, dx), (1, dy), (2, dz)):
+                    for step in (1, -1):
+                        nb = list(c)
+                        nb[ax] += step
+                        A[r, r] -= 1.0 / h ** 2
+                        if 0 <= nb[ax] < dims[ax]:
+                            A[r, idx(nb)] += 1.0 / h ** 2
+                        elif bcs[ax] == P:
+                            nb[ax] %= dims[ax]
+                            A[r, idx(nb)] += 1.0 / h ** 2
+                        elif bcs[ax] == N:
+                            A[r, r] += 1.0 / h ** 2   # ghost = wall cell
+                        else:
+                            A[r, r] -= 1.0 / h ** 2   # ghost = -wall cell
+    return A
+
+
+def dense_solve_bc(f, dx, dy, dz, bcs):
+    """LAPACK solve; with no Dirichlet axis the operator is singular: the mean
+    of f is removed and row 0 becomes the zero-sum condition."""
+    nz, ny, nx = f.shape
+    A = dense_operator_bc(nx, ny, nz, dx, dy, dz, bcs)
+    if D in bcs:
+        return np.linalg.solve(A, f.ravel()).reshape(f.shape)
+    b = (f - f.mean()).ravel().copy()
+    A[0, :] = 1.0
+    b[0] = 0.0
+    return np.linalg.solve(A, b).reshape(f.shape)
 
 
 def dense_solve(f, dx, dy, dz, bc):
@@ -350,6 +403,13 @@ def _battery(orc, mutation):
             failures.append(("dense", bc))
         if abs(p.mean()) > 1e-12 * np.abs(p).max():
             failures.append(("zero_mean", bc))
+    for bcs in ((N, D, D), (D, N, N), (D, D, P)):
+        nx, ny, nz = 4, 5, 3
+        dx, dy, dz = 0.7, 0.45, 0.3
+        f = inputs.random_rhs(nx, ny, nz, 321, zero_mean=False)
+        p = orc.solve(f, dx, dy, dz, bcs[2], mutation=mutation, bc_x=bcs[0], bc_y=bcs[1])
+        if rel(p, dense_solve_bc(f, dx, dy, dz, bcs)) > 1e-10:
+            failures.append(("dense_walls", bcs))
     return failures
 
 
@@ -357,3 +417,130 @@ def _battery(orc, mutation):
 def test_planted_mistakes_are_caught(orc, mutation):
     assert _battery(orc, 0) == []
     assert _battery(orc, mutation), f"planted mistake {mutation} not caught"
+
+
+# --------------------------------------------------------------------------
+# walls along every axis, Neumann and Dirichlet
+# --------------------------------------------------------------------------
+def lap_bc_np(p, dx, dy, dz, bcs):
+    """7-point Laplacian by array shifts with ghost layers per axis."""
+    out = np.zeros_like(p)
+    for ax, h in ((2, dx), (1, dy), (0, dz)):
+        bc = bcs[2 - ax]
+        if bc == P:
+            lo, hi = np.roll(p, 1, ax), np.roll(p, -1, ax)
+        else:
+            sgn = 1.0 if bc == N else -1.0
+            first = np.take(p, [0], axis=ax) * sgn
+            last = np.take(p, [p.shape[ax] - 1], axis=ax) * sgn
+            ext = np.concatenate([first, p, last], axis=ax)
+            lo = np.take(ext, range(0, p.shape[ax]), axis=ax)
+            hi = np.take(ext, range(2, p.shape[ax] + 2), axis=ax)
+        out += (hi - 2 * p + lo) / h ** 2
+    return out
+
+
+ALL_BCS = [(a, b, c) for a in (P, N, D) for b in (P, N, D) for c in (P, N, D)]
+WALL_SHAPES = [(3, 4, 5), (4, 3, 2), (1, 3, 4), (5, 1, 1), (2, 2, 6)]
+
+
+@pytest.mark.parametrize("bcs", ALL_BCS, ids=["".join("PND"[b] for b in c) for c in ALL_BCS])
+def test_dense_all_boundaries(orc, bcs):
+    dx, dy, dz = 0.7, 0.45, 0.3
+    for shape in WALL_SHAPES:
+        nx, ny, nz = shape
+        f = inputs.random_rhs(nx, ny, nz, seed=7 * nx + 3 * ny + nz, zero_mean=False)
+        p = orc.solve(f, dx, dy, dz, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+        q = dense_solve_bc(f, dx, dy, dz, bcs)
+        assert rel(p, q) < 1e-12, (shape, bcs)
+        A = dense_operator_bc(nx, ny, nz, dx, dy, dz, bcs)
+        # the assembled matrix and the shifted-array stencil agree
+        assert np.allclose(A @ p.ravel(), lap_bc_np(p, dx, dy, dz, bcs).ravel(), atol=1e-12)
+
+
+def wall_mode(n, bc, m):
+    """Cell-centred mode of one axis: cos(pi m (i+1/2)/n) for Neumann,
+    sin(pi (m+1) (i+1/2)/n) for Dirichlet, exp-phase cosine for periodic."""
+    x = np.arange(n) + 0.5
+    if bc == N:
+        return np.cos(np.pi * m * x / n)
+    if bc == D:
+        return np.sin(np.pi * (m + 1) * x / n)
+    return np.cos(2 * np.pi * m * x / n + 0.3)
+
+
+def wall_lambda(n, h, bc, m):
+    if bc == N:
+        return -4 / h ** 2 * math.sin(math.pi * m / (2 * n)) ** 2
+    if bc == D:
+        return -4 / h ** 2 * math.sin(math.pi * (m + 1) / (2 * n)) ** 2
+    return -4 / h ** 2 * math.sin(math.pi * m / n) ** 2
+
+
+WALL_EIG = [
+    # nx, ny, nz, bcs, (a, b, c)
+    (8, 6, 5, (N, D, N), (3, 0, 4)),
+    (8, 6, 5, (D, N, D), (7, 5, 0)),
+    (6, 8, 7, (D, D, D), (0, 7, 6)),
+    (10, 4, 6, (N, N, D), (9, 1, 2)),
+    (12, 6, 4, (P, D, N), (5, 2, 3)),
+    (6, 12, 8, (D, P, P), (4, 3, 2)),
+]
+
+
+@pytest.mark.parametrize("case", WALL_EIG)
+def test_wall_eigenmodes(orc, case):
+    nx, ny, nz, bcs, (a, b, c) = case
+    dx, dy, dz = 0.3, 0.2, 0.25
+    f = (wall_mode(nz, bcs[2], c)[:, None, None] * wall_mode(ny, bcs[1], b)[None, :, None]
+         * wall_mode(nx, bcs[0], a)[None, None, :])
+    lam = wall_lambda(nx, dx, bcs[0], a) + wall_lambda(ny, dy, bcs[1], b) + \
+        wall_lambda(nz, dz, bcs[2], c)
+    # an eigenpair of the stencil, checked without the oracle
+    assert rel(lap_bc_np(f, dx, dy, dz, bcs), lam * f) < 1e-13
+    p = orc.solve(f, dx, dy, dz, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+    assert rel(p, f / lam) < 1e-13
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("bc", [N, D])
+def test_1d_walls_are_dct2_dst2(orc, axis, bc):
+    """One axis of 9 cells, the others of length 1: the solve is the 1-D
+    eigen-expansion, computed here with scipy's DCT-II / DST-II."""
+    n, h = 9, 0.37
+    rng = np.random.default_rng(11 + axis)
+    g = rng.uniform(-1, 1, n)
+    k = np.arange(n)
+    if bc == N:
+        lam = -4 / h ** 2 * np.sin(np.pi * k / (2 * n)) ** 2
+        c = sfft.dct(g - g.mean(), type=2)
+        c[0] = 0.0
+        lam[0] = 1.0
+        ref = sfft.idct(c / lam, type=2)
+        ref -= ref.mean()
+    else:
+        lam = -4 / h ** 2 * np.sin(np.pi * (k + 1) / (2 * n)) ** 2
+        ref = sfft.idst(sfft.dst(g, type=2) / lam, type=2)
+    shape = [1, 1, 1]
+    shape[2 - axis] = n
+    f = g.reshape(shape)
+    bcs = [P, P, P]
+    bcs[axis] = bc
+    sp = [1.0, 1.0, 1.0]
+    sp[axis] = h
+    p = orc.solve(f, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+    assert rel(p.ravel(), ref) < 1e-13
+
+
+def test_dirichlet_keeps_the_mean(orc):
+    """With a zero-value wall the constant is not in the null space: the
+    solve removes nothing, reports 0, and a constant RHS has a solution."""
+    nx, ny, nz = 6, 4, 5
+    sp = (0.2, 0.3, 0.25)
+    f = np.full((nz, ny, nx), 2.0)
+    p, info = orc.solve(f, *sp, D, return_info=True, bc_x=N, bc_y=P)
+    assert info["rhs_mean"] == 0.0
+    assert np.abs(p).max() > 0.01
+    r, _ = orc.residual(f, p, *sp, D, bc_x=N, bc_y=P)
+    assert r < 1e-13
+    assert rel(p, dense_solve_bc(f, *sp, (N, P, D))) < 1e-12
