@@ -12,14 +12,18 @@
  *   solved by Gauss elimination; the steps are forward transforms along x
  *   then y, the z solve, and backward transforms along y then x.  With
  *   periodic z the z solve becomes a third transform and a division by the
- *   eigenvalue.  Walls (homogeneous Neumann, the boundary condition stated
- *   after eqn:corr) sit on the cell faces; the ghost cell mirrors the first
- *   interior cell.
+ *   eigenvalue.  Walls sit on the cell faces with a homogeneous condition:
+ *   Neumann (zero normal gradient, the boundary condition stated after
+ *   eqn:corr; the ghost cell mirrors the first interior cell) or Dirichlet
+ *   (zero value on the face; the ghost cell is the negated interior cell) --
+ *   the homogeneous pressure conditions the Fourier-based expansions of
+ *   Section 3.3.1 cover.
  *
- * Problem solved: the unique zero-mean p with  L p = f - mean(f).
- * The mean of f (which makes the periodic/Neumann problem incompatible when
- * non-zero) is removed and reported in poisson_stats_t.rhs_mean; it is not an
- * error.
+ * Problem solved: the unique zero-mean p with  L p = f - mean(f)  when no wall
+ * is Dirichlet (the constant is then in the null space).  The mean of f (which
+ * makes the periodic/Neumann problem incompatible when non-zero) is removed
+ * and reported in poisson_stats_t.rhs_mean; it is not an error.  With a
+ * Dirichlet wall the operator is regular: L p = f, nothing is removed.
  *
  * Memory: all field arrays are float64 device pointers (hipMalloc'd, or torch
  * CUDA tensors), contiguous, shape (nz, ny, nx) in C order (x fastest).  The
@@ -55,7 +59,8 @@ extern "C" {
 
 typedef enum {
     POISSON_BC_PERIODIC = 0,
-    POISSON_BC_NEUMANN = 1 /* wall on the cell face, zero normal gradient */
+    POISSON_BC_NEUMANN = 1,  /* wall on the cell face, zero normal gradient */
+    POISSON_BC_DIRICHLET = 2 /* wall on the cell face, zero value there (ghost = -wall cell) */
 } poisson_bc_t;
 
 typedef enum {
@@ -72,7 +77,10 @@ typedef enum {
  *   nx*ny*nz <= 2^31.
  *   dx,dy,dz: positive, finite cell sizes.
  *   bc_x, bc_y: POISSON_BC_PERIODIC (the only supported value).
- *   bc_z    : POISSON_BC_PERIODIC or POISSON_BC_NEUMANN.
+ *   bc_z    : POISSON_BC_PERIODIC, POISSON_BC_NEUMANN or POISSON_BC_DIRICHLET
+ *             (the homogeneous pressure conditions of the expansions of
+ *             Section 3.3.1).  With a Dirichlet wall the operator has no null
+ *             space: f keeps its mean, p is not shifted, rhs_mean reports 0.
  *   precision: poisson_precision_t.
  *   rtol    : FP32_REFINE target for ||f - mean f - L p||_2 / ||f - mean f||_2
  *             (default 1e-10; must be > 0).
@@ -151,7 +159,9 @@ int poisson_solve(poisson_plan plan, const double *rhs_dev, double *sol_dev,
  * were and psi holds the last iterate.  Under POISSON_FP32_REFINE the first
  * call allocates one more float64 field (nx*ny*nz) that the plan keeps for f.
  * Errors: INVALID_ARG (null plan or field, batched plan, non-finite scale,
- * overlapping fields), OUT_OF_MEMORY, HIP, and those of poisson_solve.
+ * overlapping fields), UNSUPPORTED (a plan with Dirichlet walls, whose
+ * velocity conventions are not those of no-slip walls), OUT_OF_MEMORY, HIP,
+ * and those of poisson_solve.
  */
 int poisson_project(poisson_plan plan, double *u, double *v, double *w, double *p, double *psi,
                     double alpha, double beta, poisson_stats_t *stats);

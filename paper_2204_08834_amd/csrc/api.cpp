@@ -209,8 +209,8 @@ std::string tune_key(const poisson_desc_t &d)
     std::string arch = "unknown";
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
     char buf[160];
-    snprintf(buf, sizeof buf, "%s %d %d %d %d %s", d.precision == POISSON_FP64 ? "f64" : "f32",
-             d.nx, d.ny, d.nz, d.bc_z, arch.c_str());
+    snprintf(buf, sizeof buf, "%s %d %d %d %d%d%d %s", d.precision == POISSON_FP64 ? "f64" : "f32",
+             d.nx, d.ny, d.nz, d.bc_x, d.bc_y, d.bc_z, arch.c_str());
     for (char *c = buf; *c; ++c)
         if (*c == ':') *c = '_';
     return buf;
@@ -388,14 +388,10 @@ int validate(const poisson_desc_t *d)
     if (!(std::isfinite(d->dx) && d->dx > 0) || !(std::isfinite(d->dy) && d->dy > 0) ||
         !(std::isfinite(d->dz) && d->dz > 0))
         return POISSON_ERR_INVALID_ARG;
-    if (d->bc_x != POISSON_BC_PERIODIC || d->bc_y != POISSON_BC_PERIODIC) {
-        if ((d->bc_x == POISSON_BC_NEUMANN || d->bc_x == POISSON_BC_PERIODIC) &&
-            (d->bc_y == POISSON_BC_NEUMANN || d->bc_y == POISSON_BC_PERIODIC))
-            return POISSON_ERR_UNSUPPORTED;
-        return POISSON_ERR_INVALID_ARG;
-    }
-    if (d->bc_z != POISSON_BC_PERIODIC && d->bc_z != POISSON_BC_NEUMANN)
-        return POISSON_ERR_INVALID_ARG;
+    auto known = [](int bc) { return bc >= POISSON_BC_PERIODIC && bc <= POISSON_BC_DIRICHLET; };
+    if (!known(d->bc_x) || !known(d->bc_y) || !known(d->bc_z)) return POISSON_ERR_INVALID_ARG;
+    if (d->bc_x != POISSON_BC_PERIODIC || d->bc_y != POISSON_BC_PERIODIC)
+        return POISSON_ERR_UNSUPPORTED;
     if (d->precision < POISSON_FP64 || d->precision > POISSON_FP32) return POISSON_ERR_INVALID_ARG;
     if (d->precision == POISSON_FP32_REFINE) {
         if (!(std::isfinite(d->rtol) && d->rtol > 0)) return POISSON_ERR_INVALID_ARG;
@@ -446,10 +442,18 @@ size_t workspace_bytes(const poisson_desc_t *d)
     return b;
 }
 
+// a zero-value wall on some axis: the operator has no null space, so no
+// mean is removed from f or p
+bool regular(const poisson_desc_t &d)
+{
+    return d.bc_x == POISSON_BC_DIRICHLET || d.bc_y == POISSON_BC_DIRICHLET ||
+           d.bc_z == POISSON_BC_DIRICHLET;
+}
+
 bool same_problem(const poisson_desc_t &a, const poisson_desc_t &b)
 {
     return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.dx == b.dx && a.dy == b.dy &&
-           a.dz == b.dz && a.bc_z == b.bc_z;
+           a.dz == b.dz && a.bc_x == b.bc_x && a.bc_y == b.bc_y && a.bc_z == b.bc_z;
 }
 
 int build_group(Group &g)
@@ -575,6 +579,7 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials, bool sum = true)
     a.residual = residual ? 1 : 0;
     a.gate = L.gate;
     a.kr_max = g.tune.kr;
+    a.regular = regular(g.d) ? 1 : 0;
     char name[40];
     snprintf(name, sizeof name, residual ? "x_r2c_residual_%s" : "x_r2c_%s", tag(L.prec));
     double bytes = (double)g.N * ((residual ? 16.0 : 8.0) + sb) * L.n;
@@ -630,6 +635,7 @@ int pass_residual_check(LSet &L, bool sum = true)
     a.residual = 1;
     a.gate = L.gate;
     a.kr_max = g.tune.kr;
+    a.regular = regular(g.d) ? 1 : 0;
     int nc = 0;
     int rc = timed(L.p, "residual_check_f64", (double)g.N * 16.0 * L.n,
                    [&] { return launch_residual_check(a, &nc, L.p->ls); });
@@ -675,9 +681,11 @@ int pass_z(LSet &L)
     a.inv_ntot = 1.0 / (double)g.N;
     a.variant = g.tune.zv;
     a.gate = L.gate;
+    a.dirichlet_z = g.d.bc_z == POISSON_BC_DIRICHLET ? 1 : 0;
+    a.regular = regular(g.d) ? 1 : 0;
     const double bytes = (double)g.N * 2.0 * (L.prec == P_F32 ? 4.0 : 8.0) * L.n;
     char name[40];
-    if (g.d.bc_z == POISSON_BC_NEUMANN) {
+    if (g.d.bc_z != POISSON_BC_PERIODIC) {
         snprintf(name, sizeof name, "z_walls_%s", tag(L.prec));
         return timed(L.p, name, bytes, [&] { return launch_z_walls(L.prec, a, L.p->ls); });
     }
@@ -691,7 +699,7 @@ int pass_x_inv(LSet &L, bool accumulate)
     // the inverse x pass follows the inverse y pass, which wrote the planes in order
     XInvArgs a{L.dev, L.n, L.one.S, L.one.p, g.tab.twx[L.prec == P_F32 ? 1 : 0]->p, g.d.nx,
                g.d.ny, g.d.nz, accumulate ? 1 : 0, g.tune.rev, nullptr,
-               1.0 / (double)g.N, L.gate};
+               1.0 / (double)g.N, L.gate, regular(g.d) ? 1 : 0};
     // the mean of p from the residual pass (batched launches redirect it)
     if (accumulate) a.sum_p = L.dev ? (const double *)g.partials->p : L.one.scal + 4;
     char name[40];
@@ -844,7 +852,8 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
                     const double *s = hs + NSCAL * i;
                     const double rho = s[3] > 0 ? std::sqrt(s[2] / s[3]) : std::sqrt(s[2]);
                     out[i].rel_residual = rho;
-                    out[i].rhs_mean = s[1] / (double)p->groups[gi].N;
+                    out[i].rhs_mean =
+                        regular(p->groups[gi].d) ? 0.0 : s[1] / (double)p->groups[gi].N;
                     out[i].iterations = corrections[i];
                     int status = -1;
                     if (!std::isfinite(rho))
@@ -884,7 +893,8 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
         for (auto &g : p->groups)
             for (int i : g.members)
                 out[i].rhs_mean =
-                    prec == P_F64 ? hs[NSCAL * i] : hs[NSCAL * i + 1] / (double)g.N;
+                    regular(g.d) ? 0.0
+                                 : (prec == P_F64 ? hs[NSCAL * i] : hs[NSCAL * i + 1] / (double)g.N);
     }
     if (p->batched && p->ptrs_done) (void)hipEventRecord(p->ptrs_done, p->ls);
 
@@ -1111,7 +1121,7 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
             if (!rc && (refine || st)) {
                 const double *sc = hs + NSCAL * i;
                 const int *c = hc + NCTRL * i;
-                o.rhs_mean = prec == P_F64 ? sc[0] : sc[1] / (double)g.N;
+                o.rhs_mean = regular(g.d) ? 0.0 : (prec == P_F64 ? sc[0] : sc[1] / (double)g.N);
                 if (refine) {
                     o.rel_residual = sc[5];
                     o.iterations = c[C_CORR];
@@ -1187,7 +1197,7 @@ int autotune_group(poisson_plan p, Group &g)
     // runs depends on how much of its input the previous pass left in the
     // last-level cache
     auto whole = [&] { return solve_passes(L, false, false); };
-    if (g.d.bc_z == POISSON_BC_NEUMANN) pick(g.tune.zv, 4, whole);
+    if (g.d.bc_z != POISSON_BC_PERIODIC) pick(g.tune.zv, 4, whole);
     if (g.d.ny >= 64) pick(g.tune.yv, 4, whole);
     pick(g.tune.rev, 2, whole);
     if (p->precision == POISSON_FP32_REFINE) {
@@ -1411,6 +1421,12 @@ int poisson_project(poisson_plan plan, double *u, double *v, double *w, double *
 {
     if (!plan || plan->batched || !u || !v || !w || !psi) return POISSON_ERR_INVALID_ARG;
     if (!std::isfinite(alpha) || !std::isfinite(beta)) return POISSON_ERR_INVALID_ARG;
+    // the velocity conventions at the walls are those of the no-slip walls
+    // (zero-gradient pressure); zero-value pressure walls are not projected
+    const poisson_desc_t &d0 = plan->groups[0].d;
+    if (d0.bc_x != POISSON_BC_PERIODIC || d0.bc_y != POISSON_BC_PERIODIC ||
+        d0.bc_z == POISSON_BC_DIRICHLET)
+        return POISSON_ERR_UNSUPPORTED;
     const long long n = plan->groups[0].N;
     const double *arr[5] = {u, v, w, psi, p};
     for (int i = 0; i < 5; ++i)
@@ -1439,7 +1455,10 @@ int poisson_plan_describe(poisson_plan plan, char *buf, int len)
                  "group %zu: %dx%dx%d %s %s problems=%zu z_tile=%d y_tile=%d reverse=%d "
                  "march_planes=%d %s\n",
                  gi,
-                 g.d.nx, g.d.ny, g.d.nz, g.d.bc_z == POISSON_BC_NEUMANN ? "walls" : "periodic",
+                 g.d.nx, g.d.ny, g.d.nz,
+                 g.d.bc_z == POISSON_BC_NEUMANN
+                     ? "walls"
+                     : (g.d.bc_z == POISSON_BC_DIRICHLET ? "dirichlet-walls" : "periodic"),
                  plan->precision == POISSON_FP64 ? "fp64"
                                                  : (plan->precision == POISSON_FP32 ? "fp32"
                                                                                      : "fp32_refine"),

@@ -145,7 +145,7 @@ struct XFwdArgs {
     const void *tw;         // complex<R> table exp(-2 pi i t/nx), t in [0, nx)
     double *partials;       // per-workgroup FP64 sums (nullable)
     int nx, ny, nz;
-    int bc_z;               // 0 periodic, 1 walls
+    int bc_z;               // 0 periodic, 1 Neumann walls, 2 Dirichlet walls
     double ax, ay, az;      // 1/dx^2, 1/dy^2, 1/dz^2
     const double *sum_f;    // residual mode: device sum of f (mean = sum_f * inv_n)
     double inv_n;           // 1/(nx ny nz)
@@ -153,6 +153,7 @@ struct XFwdArgs {
     int reverse;            // walk the row blocks from the end (see block_order)
     int gate;               // control slot gating this launch (0: none)
     int kr_max;             // residual passes: z-planes per workgroup (0: default)
+    int regular;            // a Dirichlet wall: no null space, f keeps its mean
     // divergence input (residual == 2; one problem): f = cx Dx u + cy Dy v + cz Dz w
     const double *u, *v, *w;
     double cx, cy, cz;      // alpha/dx, alpha/dy, alpha/dz
@@ -172,6 +173,7 @@ struct XInvArgs {
     const double *sum_p;    // accumulate mode: device sum of p (its mean is removed)
     double inv_n;           // 1/(nx ny nz)
     int gate;
+    int regular;            // a Dirichlet wall: the mean of p is kept
 };
 
 // Strided complex pass along y, in place on S.
@@ -205,6 +207,8 @@ struct ZArgs {
     int reverse;
     int variant;            // tile variant (0 = default; see the launchers)
     int gate;
+    int dirichlet_z;        // walls with zero value (ghost = -wall cell) instead of zero gradient
+    int regular;            // no null space (a Dirichlet wall on some axis): no zero mode
 };
 
 // Launchers (return 0 on success, a hipError_t value otherwise).  The forward

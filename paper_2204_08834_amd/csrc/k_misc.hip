@@ -207,7 +207,7 @@ __global__ __launch_bounds__(RC_NT) void k_residual_check(XFwdArgs a0)
     m.ax = a.ax;
     m.ay = a.ay;
     m.az = a.az;
-    m.mu = a.sum_f ? (*a.sum_f) * a.inv_n : 0.0;
+    m.mu = (a.sum_f && !a.regular) ? (*a.sum_f) * a.inv_n : 0.0;
     m.tile = s_tile;
     m.setup(jb, a.ny, a.nz, a.bc_z);
     m.start(k0);

@@ -309,7 +309,7 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
     m.ax = a.ax;
     m.ay = a.ay;
     m.az = a.az;
-    m.mu = a.sum_f ? (*a.sum_f) * a.inv_n : 0.0;
+    m.mu = (a.sum_f && !a.regular) ? (*a.sum_f) * a.inv_n : 0.0;
     m.tile = (double2(*)[M])s_buf;
     m.setup(jb, a.ny, a.nz, a.bc_z);
     load_table(s_tw, (const Cx<R> *)a.tw, NX);
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
     }
     // accumulate mode also removes the mean of the previous iterate (the
     // residual cannot see the constant mode, so the gauge is kept here)
-    const double pmean = (ACC && a.sum_p) ? (*a.sum_p) * a.inv_n : 0.0;
+    const double pmean = (ACC && a.sum_p && !a.regular) ? (*a.sum_p) * a.inv_n : 0.0;
     using C = XCfg<M>;
     constexpr int NB = C::NB, NT = C::NT, NX = 2 * M;
     using Tile = LdsTile<R, M, NB, false, C::PAD>;

@@ -5,9 +5,12 @@
 // For wavenumbers (m, ky) the transformed equation along z is, per row k,
 //     a p[k-1] + (lam - 2a) p[k] + a p[k+1] = fhat[k] / (nx ny),  a = 1/dz^2,
 // lam = lam_x(m) + lam_y(ky), lam(j) = -(4/h^2) sin^2(pi j/n); the mirrored
-// ghost at the walls turns the end rows into (lam - a) on the diagonal.
+// ghost at the walls turns the end rows into (lam - a) on the diagonal; with
+// zero-value (Dirichlet) walls the ghost is the negated wall cell and the end
+// rows get (lam - 3a).
 // Divided by a: p[k-1] + beta_k p[k] + p[k+1] = d[k], beta_k = sigma - 2
-// (sigma = lam dz^2), sigma - 1 on the end rows (sigma alone when nz = 1).
+// (sigma = lam dz^2), sigma - 1 on the end rows (sigma alone when nz = 1);
+// Dirichlet: sigma - 3 on the end rows (sigma - 4 when nz = 1).
 //
 // Gauss elimination without pivoting (Thomas):
 //     c'_k = 1/(beta_k - c'_{k-1}),  d'_k = (d_k - d'_{k-1}) c'_k,
@@ -21,7 +24,9 @@
 //     u_k = 1/|pivot_k|,  v_k = (|pivot_k| - 1) u_k,
 //     d'_k = (d'_{k-1} - d_k) u_k,  p_k = d'_k + p_{k+1} - v_k p_{k+1},
 // so s keeps its full relative precision and the near-singular last pivot is
-// formed without cancellation.
+// formed without cancellation.  Dirichlet walls add 2 to the first and the
+// last pivot (|pivot_0| = 3 + s, |pivot_{nz-1}| = 2 + s + v_{nz-2}): the
+// system is then regular for every wavenumber, (0, 0) included.
 //
 // Partitioned form: a column is spread over C threads, each holding a chunk of
 // L rows in registers; HBM is read and written once.  Every recurrence is
@@ -122,7 +127,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
         active = pair <= ny / 2;
         ky = active ? pair : 0;
         kyn = (ny - ky) % ny;
-        zero_lane = active && pair == 0 && part == 0;
+        zero_lane = active && pair == 0 && part == 0 && !a.regular;
         const double lx = part ? a.lamx[M] : a.lamx[0];
         s_d = (active && !zero_lane) ? -(lx + a.lamy[ky]) * a.dz2 : 1.0;
         const PK_GLOBAL Cx<R> *c1 = S + (size_t)s * plane + (size_t)ky * M;
@@ -149,6 +154,10 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
     const R sv = R(s_d);
     const R mw = rcp_nr(R(1) + sv);  // Moebius matrix [[1, s], [1, 1+s]] / (1+s)
     const R mws = sv * mw;
+    // Dirichlet walls: 2 more on the first and last pivot; row 0 maps any
+    // entering v to (s + 2)/(s + 3) instead of s/(1 + s)
+    const R dir2 = a.dirichlet_z ? R(2) : R(0);
+    const R mws0 = a.dirichlet_z ? (sv + R(2)) * rcp_nr(sv + R(3)) : mws;
 
     // ---- phase 1: Moebius product of the chunk (v recurrence) -----------
     // Rows past nz (only in the last chunk) are padding: zero right-hand
@@ -159,7 +168,8 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
     for (int i = 0; i < L; ++i) {
         const int k = s + i;
         const R a0 = (k == 0) ? R(0) : mw;  // row 0 ignores the entering v
-        const R n00 = a0 * p00 + mws * p10, n01 = a0 * p01 + mws * p11;
+        const R b0 = (k == 0) ? mws0 : mws;
+        const R n00 = a0 * p00 + b0 * p10, n01 = a0 * p01 + b0 * p11;
         const R n10 = a0 * p00 + p10, n11 = a0 * p01 + p11;
         p00 = n00; p01 = n01; p10 = n10; p11 = n11;
     }
@@ -228,9 +238,9 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
         for (int i = 0; i < L; ++i) {
             const int k = s + i;
             // |pivot| = (excess over 1) + 1, except the last row (and nz = 1)
-            const R ex = (k == 0) ? sv : sv + vprev;
+            const R ex = (k == 0) ? sv + dir2 : sv + vprev;
             const bool last = k >= nz - 1;
-            const R piv = (nz == 1) ? sv : (k == nz - 1 ? ex : R(1) + ex);
+            const R piv = (nz == 1) ? sv + dir2 + dir2 : (k == nz - 1 ? ex + dir2 : R(1) + ex);
             const R u = rcp_nr(piv);
             const R vnew = last ? R(1) : ex * u;
             Dp = cscale(csub(Dp, d[i]), u);

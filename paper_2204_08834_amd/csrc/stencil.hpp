@@ -144,10 +144,13 @@ struct PlaneMarch : MarchIdx<M, TJ, NT> {
     {
         const PK_GLOBAL double *pdn = p + (size_t)kdown(k0) * plane;
         const PK_GLOBAL double *pcn = p + (size_t)k0 * plane;
+        // below a Dirichlet bottom wall the ghost plane is -p(0)
+        const double gs = (k0 == 0 && this->bc_z == 2) ? -1.0 : 1.0;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int o = roff(q);
-            pd[q] = *(const PK_GLOBAL double2 *)(pdn + o);
+            const double2 x = *(const PK_GLOBAL double2 *)(pdn + o);
+            pd[q] = double2{gs * x.x, gs * x.y};
             pc[q] = *(const PK_GLOBAL double2 *)(pcn + o);
         }
     }
@@ -161,11 +164,14 @@ struct PlaneMarch : MarchIdx<M, TJ, NT> {
         const PK_GLOBAL double *pup = p + (size_t)kup(k) * plane;
         const PK_GLOBAL double *fk = f + (size_t)k * plane;
         const PK_GLOBAL double *pk_ = p + (size_t)k * plane;
+        // above a Dirichlet top wall the ghost plane is -p(nz-1)
+        const double gs = (k == this->nz - 1 && this->bc_z == 2) ? -1.0 : 1.0;
         double2 pu[PER], fv[PER];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int o = roff(q);
-            pu[q] = *(const PK_GLOBAL double2 *)(pup + o);
+            const double2 x = *(const PK_GLOBAL double2 *)(pup + o);
+            pu[q] = double2{gs * x.x, gs * x.y};
             fv[q] = *(const PK_GLOBAL double2 *)(fk + o);
         }
         for (int h = threadIdx.x; h < M; h += NT) {

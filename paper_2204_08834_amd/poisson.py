@@ -23,6 +23,7 @@ ERR_NONFINITE = -6
 
 BC_PERIODIC = 0
 BC_NEUMANN = 1
+BC_DIRICHLET = 2
 
 FP64 = 0
 FP32_REFINE = 1
@@ -160,8 +161,9 @@ class Plan:
     """One Poisson problem (grid, spacings, z boundary, precision) on one stream."""
 
     def __init__(self, nx, ny, nz, dx=1.0, dy=1.0, dz=1.0, bc_z=BC_NEUMANN, precision="fp64",
-                 rtol=1e-10, max_refine=8, stream=None):
-        self.desc = make_desc(nx, ny, nz, dx, dy, dz, bc_z, precision, rtol, max_refine)
+                 rtol=1e-10, max_refine=8, stream=None, bc_x=BC_PERIODIC, bc_y=BC_PERIODIC):
+        self.desc = make_desc(nx, ny, nz, dx, dy, dz, bc_z, precision, rtol, max_refine,
+                              bc_x, bc_y)
         self.shape = (nz, ny, nx)
         self._stream = stream
         h = ctypes.c_void_p()
@@ -295,12 +297,14 @@ class BatchPlan:
     """Several independent problems (possibly different shapes) on one stream."""
 
     def __init__(self, problems, precision="fp64", rtol=1e-10, max_refine=8, stream=None):
-        """problems: list of dicts with nx, ny, nz, dx, dy, dz, bc_z."""
+        """problems: list of dicts with nx, ny, nz, dx, dy, dz, bc_z (and
+        optionally bc_x, bc_y)."""
         n = len(problems)
         arr = (Desc * n)()
         for i, p in enumerate(problems):
             arr[i] = make_desc(p["nx"], p["ny"], p["nz"], p["dx"], p["dy"], p["dz"],
-                               p["bc_z"], precision, rtol, max_refine)
+                               p["bc_z"], precision, rtol, max_refine,
+                               p.get("bc_x", BC_PERIODIC), p.get("bc_y", BC_PERIODIC))
         self.shapes = [(p["nz"], p["ny"], p["nx"]) for p in problems]
         h = ctypes.c_void_p()
         rc = lib().poisson_batch_plan_create(arr, n, _stream_handle(stream), ctypes.byref(h))

@@ -45,7 +45,8 @@ def test_desc_init_defaults():
 @pytest.mark.parametrize("shape,bc", [((512, 512, 256), 1), ((256, 256, 256), 0),
                                       ((1024, 1024, 512), 1), ((96, 96, 48), 1),
                                       ((64, 64, 64), 0), ((2, 1, 1), 0), ((32, 32, 33), 1),
-                                      ((2048, 2048, 1), 1), ((6, 3, 12), 0)])
+                                      ((2048, 2048, 1), 1), ((6, 3, 12), 0), ((64, 32, 33), 2),
+                                      ((8, 8, 4096), 2)])
 def test_valid_descriptors(shape, bc):
     d = P.make_desc(*shape, 0.1, 0.2, 0.3, bc, "fp32_refine")
     assert P.validate(d) == P.OK
@@ -66,9 +67,10 @@ def test_valid_descriptors(shape, bc):
     (dict(dy=-1.0), P.ERR_INVALID_ARG),
     (dict(dz=float("nan")), P.ERR_INVALID_ARG),
     (dict(dz=float("inf")), P.ERR_INVALID_ARG),
-    (dict(bc_z=2), P.ERR_INVALID_ARG),
+    (dict(bc_z=3), P.ERR_INVALID_ARG),
     (dict(bc_x=1), P.ERR_UNSUPPORTED),          # walls in x: not in this build
     (dict(bc_y=1), P.ERR_UNSUPPORTED),
+    (dict(bc_x=2), P.ERR_UNSUPPORTED),
     (dict(bc_x=5), P.ERR_INVALID_ARG),
     (dict(precision=3), P.ERR_INVALID_ARG),
     (dict(precision="fp32_refine", rtol=0.0), P.ERR_INVALID_ARG),

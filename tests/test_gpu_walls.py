@@ -1,0 +1,188 @@
+"""GPU parity for zero-value (Dirichlet) pressure walls against the oracle.
+
+With a Dirichlet wall the operator is regular: nothing is removed from f,
+p is not shifted, rhs_mean reports 0.  Checks, element by element against
+the oracle on the same seeded inputs: FP64 to 1e-12 (or the conditioning
+bound kappa * eps), FP32 + refinement to an oracle residual of 1e-10, FP32
+by conditioning; grids cover every tile of the wall-bounded z solve (nz up
+to 4096, nz = 1, ragged chunks); every z-solve tile variant; the device
+loop equal to the host loop bitwise; batches mixing Neumann and Dirichlet
+problems equal to single solves.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2204_08834_amd import inputs  # noqa: E402
+
+PER, NEU, DIR = 0, 1, 2
+BOX = (2.0, 1.5, 1.0)
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_08834_amd import poisson
+    poisson.lib()  # raises if the HIP library is missing: no fallback
+    return poisson
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def lam1(n, h, j, bc):
+    if bc == PER:
+        return 4 / h ** 2 * math.sin(math.pi * j / n) ** 2
+    if bc == NEU:
+        return 4 / h ** 2 * math.sin(math.pi * j / (2 * n)) ** 2
+    return 4 / h ** 2 * math.sin(math.pi * (j + 1) / (2 * n)) ** 2
+
+
+def kappa(nx, ny, nz, sp, bcs):
+    """lambda_max / lambda_min (non-zero) of the operator."""
+    ns = (nx, ny, nz)
+    lmax = sum(max(lam1(n, h, j, bc) for j in range(n)) for n, h, bc in zip(ns, sp, bcs))
+    mins = []
+    for n, h, bc in zip(ns, sp, bcs):
+        vals = [lam1(n, h, j, bc) for j in range(n)]
+        nz_ = [v for v in vals if v > 0]
+        if nz_:
+            mins.append(min(nz_))
+    regular = DIR in bcs
+    lmin = sum(min(lam1(n, h, j, bc) for j in range(n)) for n, h, bc in zip(ns, sp, bcs)) \
+        if regular else min(mins)
+    return lmax / lmin
+
+
+def gpu_solve(P, f, sp, bcs, prec, mode="host", rtol=1e-10):
+    nz, ny, nx = f.shape
+    with P.Plan(nx, ny, nz, *sp, bcs[2], prec, rtol=rtol, bc_x=bcs[0], bc_y=bcs[1]) as plan:
+        plan.set_graph(mode)
+        out, st = plan.solve(torch.from_numpy(f).cuda(), check=False)
+        torch.cuda.synchronize()
+    return out.cpu().numpy(), st
+
+
+CASES = [(16, 12, 10), (64, 48, 20), (6, 3, 5), (2, 1, 1), (32, 32, 33), (8, 4, 1),
+         (512, 6, 70), (4, 6, 300), (4, 2, 1500), (6, 2, 4096)]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}x{c[2]}" for c in CASES])
+def test_dirichlet_z_matches_oracle(orc, case):
+    P = _gpu()
+    nx, ny, nz = case
+    sp = (BOX[0] / nx, BOX[1] / ny, BOX[2] / nz)
+    bcs = (PER, PER, DIR)
+    # a right-hand side with a mean: nothing may be removed
+    f = inputs.random_rhs(nx, ny, nz, seed=nx + 7 * ny + 3 * nz, zero_mean=False) + 0.5
+    p_ref = orc.solve(f, *sp, DIR)
+    k = kappa(nx, ny, nz, sp, bcs)
+    # the refinement is asked for what FP64 can deliver on this operator:
+    # 1e-10, or ten times the oracle's own FP64 residual where that is higher
+    res_ref, _ = orc.residual(f, p_ref, *sp, DIR)
+    rtol = max(1e-10, 10 * res_ref)
+    for prec in ("fp64", "fp32_refine", "fp32"):
+        print(f"[walls] {nx}x{ny}x{nz} dirichlet-z {prec}", flush=True)
+        p, st = gpu_solve(P, f, sp, bcs, prec, rtol=rtol)
+        assert st["status"] == 0, st
+        assert st["rhs_mean"] == 0.0
+        if prec == "fp64":
+            # both solutions backward stable: the GPU's residual is at the
+            # oracle's own level (which grows with the conditioning)
+            res, _ = orc.residual(f, p, *sp, DIR)
+            res_ref, _ = orc.residual(f, p_ref, *sp, DIR)
+            print(f"[walls] kappa {k:.1e} error {rel(p, p_ref):.2e} residual {res:.1e} "
+                  f"oracle {res_ref:.1e}", flush=True)
+            assert res <= max(1e-13, 4 * res_ref), (res, res_ref)
+            assert rel(p, p_ref) <= max(1e-12, 4 * k * 2.2e-16), (rel(p, p_ref), k)
+        elif prec == "fp32_refine":
+            res, _ = orc.residual(f, p, *sp, DIR)
+            assert res <= rtol, (res, rtol, st)
+        else:
+            assert rel(p, p_ref) <= max(2e-5, 8 * k * 6e-8), (rel(p, p_ref), k)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_dirichlet_z_tile_variants(orc, variant, monkeypatch):
+    P = _gpu()
+    monkeypatch.setenv("POISSON_ZWALLS_VARIANT", str(variant))
+    for nx, ny, nz in [(64, 32, 48), (32, 16, 200), (16, 8, 700)]:
+        sp = (2.0 / nx, 2.0 / ny, 1.0 / nz)
+        f = inputs.random_rhs(nx, ny, nz, seed=variant + nz, zero_mean=False)
+        p_ref = orc.solve(f, *sp, DIR)
+        p, _ = gpu_solve(P, f, sp, (PER, PER, DIR), "fp64")
+        tol = max(1e-12, 4 * kappa(nx, ny, nz, sp, (PER, PER, DIR)) * 2.2e-16)
+        assert rel(p, p_ref) <= tol, (variant, nx, ny, nz, rel(p, p_ref))
+        q, st = gpu_solve(P, f, sp, (PER, PER, DIR), "fp32_refine")
+        res, _ = orc.residual(f, q, *sp, DIR)
+        assert st["status"] == 0 and res <= 1e-10, (variant, nx, ny, nz, res)
+
+
+def test_dirichlet_z_eigenmode():
+    """sin-modes along z (closed form), 256 x 128 x 200: p = f / lambda."""
+    P = _gpu()
+    nx, ny, nz = 256, 128, 200
+    sp = (2.0 / nx, 1.0 / ny, 1.0 / nz)
+    a, b, c = 5, 17, 150
+    i = np.arange(nx) + 0.5
+    j = np.arange(ny) + 0.5
+    k = np.arange(nz) + 0.5
+    f = (np.sin(np.pi * (c + 1) * k / nz)[:, None, None] * np.cos(2 * np.pi * b * j / ny)[None, :, None]
+         * np.cos(2 * np.pi * a * i / nx + 0.2)[None, None, :])
+    lam = -(lam1(nx, sp[0], a, PER) + lam1(ny, sp[1], b, PER) + lam1(nz, sp[2], c, DIR))
+    for prec, tol in (("fp64", 1e-12), ("fp32_refine", 1e-9)):
+        p, st = gpu_solve(P, f, sp, (PER, PER, DIR), prec)
+        assert rel(p, f / lam) <= tol, (prec, rel(p, f / lam), st)
+
+
+@pytest.mark.parametrize("mode", ["graph", "device"])
+def test_dirichlet_z_device_loop_matches_host(mode):
+    P = _gpu()
+    nx, ny, nz = 64, 48, 20
+    sp = (2.0 / nx, 2.0 / ny, 1.0 / nz)
+    f = inputs.random_rhs(nx, ny, nz, seed=3, zero_mean=False)
+    a, sa = gpu_solve(P, f, sp, (PER, PER, DIR), "fp32_refine", "host")
+    b, sb = gpu_solve(P, f, sp, (PER, PER, DIR), "fp32_refine", mode)
+    assert sa == sb and np.array_equal(a, b)
+
+
+def test_batch_mixing_neumann_and_dirichlet(orc):
+    """Same grid, different wall conditions: separate shape groups in one
+    batch, each equal to its single solve and to the oracle."""
+    P = _gpu()
+    nx, ny, nz = 32, 24, 16
+    sp = (2.0 / nx, 2.0 / ny, 1.0 / nz)
+    fs, specs = [], []
+    for b, bc in enumerate((NEU, DIR, DIR, NEU, PER)):
+        f = inputs.random_rhs(nx, ny, nz, seed=50 + b, zero_mean=False)
+        fs.append((f, bc))
+        specs.append(dict(nx=nx, ny=ny, nz=nz, dx=sp[0], dy=sp[1], dz=sp[2], bc_z=bc))
+    for prec in ("fp64", "fp32_refine"):
+        rhs = [torch.from_numpy(f).cuda() for f, _ in fs]
+        outs = [torch.empty_like(r) for r in rhs]
+        bp = P.BatchPlan(specs, prec)
+        rc, stats = bp.solve(rhs, outs, check=False)
+        torch.cuda.synchronize()
+        bp.close()
+        assert rc == 0
+        for (f, bc), o, st in zip(fs, outs, stats):
+            single, _ = gpu_solve(P, f, sp, (PER, PER, bc), prec)
+            assert np.array_equal(o.cpu().numpy(), single), (prec, bc)
+            if prec == "fp64":
+                assert rel(single, orc.solve(f, *sp, bc)) <= 1e-12
+            assert (st["rhs_mean"] == 0.0) == (bc == DIR)
+
+
+def test_project_refuses_dirichlet():
+    P = _gpu()
+    with P.Plan(16, 8, 4, 0.1, 0.1, 0.1, DIR, "fp64") as plan:
+        u = torch.zeros((4, 8, 16), dtype=torch.float64, device="cuda")
+        with pytest.raises(P.PoissonError) as e:
+            plan.project(u, torch.zeros_like(u), torch.zeros_like(u))
+        assert e.value.code == P.ERR_UNSUPPORTED
