@@ -86,6 +86,34 @@ std::vector<double> eig_table(int n, double h, int count)
     return l;
 }
 
+// eigenvalues of the 3-point operator on n cells between two walls:
+// Neumann lam(k) = -(4/h^2) sin^2(pi k/(2n)) (cosine modes), Dirichlet
+// lam(k) = -(4/h^2) sin^2(pi (k+1)/(2n)) (sine modes), k in [0, n)
+std::vector<double> eig_table_walls(int n, double h, int bc)
+{
+    std::vector<double> l(n);
+    for (int k = 0; k < n; ++k) {
+        double c, s;
+        cis_2pi(bc == POISSON_BC_DIRICHLET ? k + 1 : k, 4L * n, c, s);
+        l[k] = -4.0 / (h * h) * s * s;
+    }
+    return l;
+}
+
+// exp(-i pi k/(2n)), k in [0, n): the half-sample shift of the cosine and
+// sine expansions
+std::vector<double> quarter_table(int n)
+{
+    std::vector<double> tw(2 * (size_t)n);
+    for (int k = 0; k < n; ++k) {
+        double c, s;
+        cis_2pi(k, 4L * n, c, s);
+        tw[2 * k] = c;
+        tw[2 * k + 1] = -s;
+    }
+    return tw;
+}
+
 // ---------------------------------------------------------------------------
 // device buffers
 // ---------------------------------------------------------------------------
@@ -277,6 +305,7 @@ Tune initial_tune(const poisson_desc_t &d)
 // ---------------------------------------------------------------------------
 struct Tables {
     std::shared_ptr<DevBuf> twx[2], twy[2], twz[2];  // [0] FP64, [1] FP32 complex tables
+    std::shared_ptr<DevBuf> twy4[2];                 // walls along y: exp(-i pi k/(2 ny))
     std::shared_ptr<DevBuf> lamx, lamy, lamz;
 };
 
@@ -390,8 +419,7 @@ int validate(const poisson_desc_t *d)
         return POISSON_ERR_INVALID_ARG;
     auto known = [](int bc) { return bc >= POISSON_BC_PERIODIC && bc <= POISSON_BC_DIRICHLET; };
     if (!known(d->bc_x) || !known(d->bc_y) || !known(d->bc_z)) return POISSON_ERR_INVALID_ARG;
-    if (d->bc_x != POISSON_BC_PERIODIC || d->bc_y != POISSON_BC_PERIODIC)
-        return POISSON_ERR_UNSUPPORTED;
+    if (d->bc_x != POISSON_BC_PERIODIC) return POISSON_ERR_UNSUPPORTED;
     if (d->precision < POISSON_FP64 || d->precision > POISSON_FP32) return POISSON_ERR_INVALID_ARG;
     if (d->precision == POISSON_FP32_REFINE) {
         if (!(std::isfinite(d->rtol) && d->rtol > 0)) return POISSON_ERR_INVALID_ARG;
@@ -469,7 +497,11 @@ int build_group(Group &g)
     if (d.bc_z == POISSON_BC_PERIODIC && (rc = upload_complex(t.twz, twiddle_table(d.nz), f32, f64)))
         return rc;
     auto lx = eig_table(d.nx, d.dx, g.M + 1);
-    auto ly = eig_table(d.ny, d.dy, d.ny);
+    auto ly = d.bc_y == POISSON_BC_PERIODIC ? eig_table(d.ny, d.dy, d.ny)
+                                            : eig_table_walls(d.ny, d.dy, d.bc_y);
+    if (d.bc_y != POISSON_BC_PERIODIC &&
+        (rc = upload_complex(t.twy4, quarter_table(d.ny), f32, f64)))
+        return rc;
     auto lz = eig_table(d.nz, d.dz, d.nz);
     if ((rc = upload(t.lamx, lx.data(), lx.size() * 8))) return rc;
     if ((rc = upload(t.lamy, ly.data(), ly.size() * 8))) return rc;
@@ -571,6 +603,7 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials, bool sum = true)
     a.ny = g.d.ny;
     a.nz = g.d.nz;
     a.bc_z = g.d.bc_z;
+    a.bc_y = g.d.bc_y;
     a.ax = 1.0 / (g.d.dx * g.d.dx);
     a.ay = 1.0 / (g.d.dy * g.d.dy);
     a.az = 1.0 / (g.d.dz * g.d.dz);
@@ -627,6 +660,7 @@ int pass_residual_check(LSet &L, bool sum = true)
     a.ny = g.d.ny;
     a.nz = g.d.nz;
     a.bc_z = g.d.bc_z;
+    a.bc_y = g.d.bc_y;
     a.ax = 1.0 / (g.d.dx * g.d.dx);
     a.ay = 1.0 / (g.d.dy * g.d.dy);
     a.az = 1.0 / (g.d.dz * g.d.dz);
@@ -651,8 +685,11 @@ int pass_y(LSet &L, bool inverse)
     Group &g = *L.g;
     if (g.d.ny == 1) return POISSON_OK;  // a length-1 transform is the identity
     // the forward y pass follows the x pass, which wrote the planes in order
-    YArgs a{L.dev, L.n, L.one.S, g.tab.twy[L.prec == P_F32 ? 1 : 0]->p, g.M, g.d.ny, g.d.nz,
-            inverse ? 1 : 0, (!inverse && g.tune.rev) ? 1 : 0, L.gate, g.tune.yv};
+    const int pi = L.prec == P_F32 ? 1 : 0;
+    const bool wall = g.d.bc_y != POISSON_BC_PERIODIC;
+    YArgs a{L.dev, L.n, L.one.S, g.tab.twy[pi]->p, g.M, g.d.ny, g.d.nz,
+            inverse ? 1 : 0, (!inverse && g.tune.rev) ? 1 : 0, L.gate, g.tune.yv,
+            g.d.bc_y, wall ? g.tab.twy4[pi]->p : nullptr};
     char name[40];
     snprintf(name, sizeof name, inverse ? "y_inv_%s" : "y_fwd_%s", tag(L.prec));
     const double bytes = (double)g.N * 2.0 * (L.prec == P_F32 ? 4.0 : 8.0) * L.n;
@@ -683,6 +720,7 @@ int pass_z(LSet &L)
     a.gate = L.gate;
     a.dirichlet_z = g.d.bc_z == POISSON_BC_DIRICHLET ? 1 : 0;
     a.regular = regular(g.d) ? 1 : 0;
+    a.ywall = g.d.bc_y != POISSON_BC_PERIODIC ? 1 : 0;
     const double bytes = (double)g.N * 2.0 * (L.prec == P_F32 ? 4.0 : 8.0) * L.n;
     char name[40];
     if (g.d.bc_z != POISSON_BC_PERIODIC) {
@@ -1198,7 +1236,7 @@ int autotune_group(poisson_plan p, Group &g)
     // last-level cache
     auto whole = [&] { return solve_passes(L, false, false); };
     if (g.d.bc_z != POISSON_BC_PERIODIC) pick(g.tune.zv, 4, whole);
-    if (g.d.ny >= 64) pick(g.tune.yv, 4, whole);
+    if (g.d.ny >= 64 && g.d.bc_y == POISSON_BC_PERIODIC) pick(g.tune.yv, 4, whole);
     pick(g.tune.rev, 2, whole);
     if (p->precision == POISSON_FP32_REFINE) {
         // plane-range depth of the residual passes: scored on the residual

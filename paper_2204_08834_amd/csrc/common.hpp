@@ -146,6 +146,7 @@ struct XFwdArgs {
     double *partials;       // per-workgroup FP64 sums (nullable)
     int nx, ny, nz;
     int bc_z;               // 0 periodic, 1 Neumann walls, 2 Dirichlet walls
+    int bc_y;               // the same along y (residual marches)
     double ax, ay, az;      // 1/dx^2, 1/dy^2, 1/dz^2
     const double *sum_f;    // residual mode: device sum of f (mean = sum_f * inv_n)
     double inv_n;           // 1/(nx ny nz)
@@ -187,6 +188,8 @@ struct YArgs {
     int reverse;
     int gate;
     int variant;            // tile variant (see YCfg)
+    int bc;                 // 0 periodic (FFT), 1 Neumann walls (cosines), 2 Dirichlet (sines)
+    const void *tw4;        // walls: exp(-i pi k/(2 ny)), k in [0, ny)
 };
 
 // z solve, walls (tridiagonal per (m, ky)) or periodic (transform along z).
@@ -209,6 +212,7 @@ struct ZArgs {
     int gate;
     int dirichlet_z;        // walls with zero value (ghost = -wall cell) instead of zero gradient
     int regular;            // no null space (a Dirichlet wall on some axis): no zero mode
+    int ywall;              // walls along y: the m = 0 column holds A + iB with real y-modes
 };
 
 // Launchers (return 0 on success, a hipError_t value otherwise).  The forward

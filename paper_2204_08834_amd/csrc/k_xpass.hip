@@ -311,7 +311,7 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
     m.az = a.az;
     m.mu = (a.sum_f && !a.regular) ? (*a.sum_f) * a.inv_n : 0.0;
     m.tile = (double2(*)[M])s_buf;
-    m.setup(jb, a.ny, a.nz, a.bc_z);
+    m.setup(jb, a.ny, a.nz, a.bc_z, a.bc_y);
     load_table(s_tw, (const Cx<R> *)a.tw, NX);
     m.start(k0);
 

@@ -69,6 +69,137 @@ __global__ __launch_bounds__((YCfg<N, V>::NT)) void k_y(YArgs a0)
     fft_tile<R, N, NB, NT, true, C::PAD, false, C::PV>(s_tw, 1, gload, gstore, tile);
 }
 
+// ---------------------------------------------------------------------------
+// Walls along y: expansion in the cosine (Neumann) or sine (Dirichlet) basis
+// of the cell-centred operator, phi_k(j) = cos(pi k (j+1/2)/n) or
+// sin(pi (k+1)(j+1/2)/n), computed with one n-point FFT per column
+// (Makhoul's reordering, written for complex columns: every step is linear
+// over the complex numbers, so the real and imaginary parts of a column are
+// expanded independently, as the x-wavenumber columns require):
+//   forward cosine:  v[j] = c[r(j)],  r(j) = 2j (2j < n) or 2n-1-2j,
+//                    V = FFT(v),  C[k] = (w_k V[k] + conj(w_k) V[(n-k) mod n]) / 2,
+//                    w_k = exp(-i pi k / (2n));
+//   forward sine:    the cosine transform of (-1)^j c[j], read out reversed
+//                    (S[k] = C'[n-1-k]);
+//   inverse cosine:  W[k] = conj(w_k) (C[k] - i C[n-k]),  C[n] = 0,
+//                    v = FFT^-1(W) (unnormalised),  c[r(j)] = v[j]  (times n,
+//                    like the periodic pass: 1/ny is applied in the z step);
+//   inverse sine:    the inverse cosine transform of C'[k] = S[n-1-k], times
+//                    (-1)^j.
+// The forward FFT writes into a second LDS tile, from which the pairs
+// (k, n-k) are combined and stored; the inverse forms W in place in LDS by
+// pairs and transforms from there.  Two tiles: half the x-wavenumbers per
+// workgroup of the periodic pass (64-byte row runs at most sizes).
+template <int N> struct YWCfg {
+    static constexpr int NB0 = sizeof(R) == 4 ? 16 : 8;
+    // two NB x N tiles (plus padding) and two N-entry tables within ~150 KB of LDS
+    static constexpr int ELEMS = 150 * 1024 / (int)sizeof(Cx<R>);
+    static constexpr int NBMAX = ELEMS / (2 * N) - 2;  // 2 N (NB + PAD) + 2 N <= ELEMS
+    static constexpr int NB1 = NB0 < NBMAX ? NB0 : NBMAX;
+    static constexpr int NB = NB1 >= 16 ? 16 : (NB1 >= 8 ? 8 : (NB1 >= 4 ? 4 : (NB1 >= 2 ? 2 : 1)));
+    static constexpr int NT = pick_nt(NB * N, sizeof(R) == 4 ? 16 : 8);
+    static constexpr int PAD = (NB >= 8) ? 1 : 0;
+};
+
+__device__ __forceinline__ int wall_reorder(int j, int n) { return 2 * j < n ? 2 * j : 2 * n - 1 - 2 * j; }
+
+template <int N, bool INV>
+__global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
+{
+    if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
+    YArgs a = a0;
+    if (a.batch) a.S = a.batch[blockIdx.y].S;
+    using C = YWCfg<N>;
+    constexpr int NB = C::NB, NT = C::NT;
+    using Tile = LdsTile<R, N, NB, true, C::PAD>;
+    __shared__ Cx<R> s_tile[Tile::elems];
+    __shared__ Cx<R> s_out[INV ? 1 : Tile::elems];
+    __shared__ Cx<R> s_tw[N];
+    __shared__ Cx<R> s_w4[N];  // exp(-i pi k / (2n))
+
+    const bool sine = a.bc == 2;
+    const int ntile = (a.M + NB - 1) / NB;
+    const int bid = block_order(blockIdx.x, gridDim.x, a.reverse);
+    const int tile_i = bid % ntile;
+    const int k = bid / ntile;
+    const int m0 = tile_i * NB;
+    load_table(s_tw, (const Cx<R> *)a.tw, N);
+    load_table(s_w4, (const Cx<R> *)a.tw4, N);
+    __syncthreads();
+
+    const int M = a.M;
+    PK_GLOBAL Cx<R> *base = gbl((Cx<R> *)a.S) + (size_t)k * N * M + m0;
+    Tile tile{s_tile};
+    if constexpr (!INV) {
+        Tile out{s_out};
+        auto gload = [&](int b, int n) -> Cx<R> {
+            if (m0 + b >= M) return {R(0), R(0)};
+            const int r = wall_reorder(n, N);
+            const Cx<R> v = base[(size_t)r * M + b];
+            return (sine && (r & 1)) ? Cx<R>{-v.re, -v.im} : Cx<R>{v.re, v.im};
+        };
+        auto lstore = [&](int b, int n, Cx<R> v) { out.at(b, n) = v; };
+        fft_tile<R, N, NB, NT, true, C::PAD, false>(s_tw, 1, gload, lstore, tile);
+        __syncthreads();
+        for (int e = threadIdx.x; e < NB * N; e += NT) {
+            const int b = e % NB, kk = e / NB;
+            if (m0 + b >= M) continue;
+            const Cx<R> w = s_w4[kk];
+            const Cx<R> v1 = out.at(b, kk), v2 = out.at(b, kk == 0 ? 0 : N - kk);
+            const Cx<R> c = cscale(cadd(cmul(w, v1), cmul(cconj(w), v2)), R(0.5));
+            put(base + (size_t)(sine ? N - 1 - kk : kk) * M + b, c);
+        }
+    } else {
+        // coefficients into LDS (read reversed for the sine basis)
+        for (int e = threadIdx.x; e < NB * N; e += NT) {
+            const int b = e % NB, kk = e / NB;
+            Cx<R> v = {R(0), R(0)};
+            if (m0 + b < M) {
+                const Cx<R> g = base[(size_t)(sine ? N - 1 - kk : kk) * M + b];
+                v = {g.re, g.im};
+            }
+            tile.at(b, kk) = v;
+        }
+        __syncthreads();
+        // W by pairs (k, n-k) in place: W[k] = conj(w_k) (C[k] - i C[n-k])
+        constexpr int NPAIR = N / 2 + 1;
+        for (int e = threadIdx.x; e < NB * NPAIR; e += NT) {
+            const int b = e % NB, kk = e / NB;
+            const int kc = N - kk;  // N for kk = 0: C[N] = 0
+            const Cx<R> c1 = tile.at(b, kk);
+            const Cx<R> c2 = (kk == 0) ? Cx<R>{R(0), R(0)} : tile.at(b, kc == N ? 0 : kc);
+            const Cx<R> w1 = cconj(s_w4[kk]);
+            tile.at(b, kk) = cmul(w1, csub(c1, cmul_pi(c2)));
+            if (kk != 0 && kc != kk) {
+                const Cx<R> w2 = cconj(s_w4[kc]);
+                tile.at(b, kc) = cmul(w2, csub(c2, cmul_pi(c1)));
+            }
+        }
+        __syncthreads();
+        // inverse FFT as conj(FFT(conj)), from LDS; store un-reordered
+        auto gload = [&](int b, int n) -> Cx<R> { return cconj(tile.at(b, n)); };
+        auto gstore = [&](int b, int n, Cx<R> v) {
+            if (m0 + b >= M) return;
+            const int r = wall_reorder(n, N);
+            const R sg = (sine && (r & 1)) ? R(-1) : R(1);
+            put(base + (size_t)r * M + b, Cx<R>{sg * v.re, -sg * v.im});
+        };
+        fft_tile<R, N, NB, NT, true, C::PAD, true>(s_tw, 1, gload, gstore, tile);
+    }
+}
+
+template <int N> static int run_yw(const YArgs &a, hipStream_t s)
+{
+    using C = YWCfg<N>;
+    const int ntile = (a.M + C::NB - 1) / C::NB;
+    const dim3 grid(ntile * a.nz, a.batch ? a.nbatch : 1);
+    if (a.inverse)
+        hipLaunchKernelGGL((k_yw<N, true>), grid, dim3(C::NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_yw<N, false>), grid, dim3(C::NT), 0, s, a);
+    return (int)hipGetLastError();
+}
+
 template <int N, int V> static int run_yv(const YArgs &a, hipStream_t s)
 {
     using C = YCfg<N, V>;
@@ -84,6 +215,7 @@ template <int N, int V> static int run_yv(const YArgs &a, hipStream_t s)
 // short transforms have a single tile shape worth having
 template <int N> static int run_y(const YArgs &a, hipStream_t s)
 {
+    if (a.bc != 0) return run_yw<N>(a, s);
     if constexpr (N < 64) {
         return run_yv<N, 0>(a, s);
     } else {

@@ -85,6 +85,60 @@ __global__ __launch_bounds__(ZPCfg<N>::NT) void k_z_per(ZArgs a0, int nspecial)
         return;
     }
 
+    if (a.ywall) {
+        // ---- m = 0 with walls along y: each column (0, ky) holds A + iB
+        // (real modes along y), which separate through the symmetry kz <-> -kz
+        // of the same column
+        const int ky0 = (int)blockIdx.x * NB;
+        auto gload = [&](int b, int n) -> Cx<R> {
+            const int ky = ky0 + b;
+            if (ky >= ny) return {R(0), R(0)};
+            return S[(size_t)n * plane + (size_t)ky * M];
+        };
+        fft_tile<R, N, NB, NT, true, Cf::PAD, false>(s_tw, 1, gload, lstore, tile);
+        __syncthreads();
+        constexpr int NE = NB * N;
+        constexpr int PER = (NE + NT - 1) / NT;
+        Cx<R> o[PER];
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int u = threadIdx.x + e * NT;
+            if (u >= NE) continue;
+            const int b = u % NB, kz = u / NB;
+            const int ky = ky0 + b;
+            if (ky >= ny) {
+                o[e] = {R(0), R(0)};
+                continue;
+            }
+            const int kzn = (N - kz) % N;
+            const double ly = a.lamy[ky], lz = a.lamz[kz];
+            const double lamA = a.lamx[0] + ly + lz, lamB = a.lamx[M] + ly + lz;
+            const bool zero = ky == 0 && kz == 0 && !a.regular;
+            const R sA = zero ? R(0) : R(a.inv_ntot / lamA);
+            const R sB = R(a.inv_ntot / lamB);
+            const Cx<R> z1 = tile.at(b, kz), z2 = cconj(tile.at(b, kzn));
+            if (zero && a.zero_mean_out) *a.zero_mean_out = double(z1.re) * a.inv_ntot;
+            const Cx<R> A = cscale(cadd(z1, z2), R(0.5) * sA);
+            const Cx<R> B = cscale(cmul_mi(csub(z1, z2)), R(0.5) * sB);
+            o[e] = cadd(A, cmul_pi(B));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int u = threadIdx.x + e * NT;
+            if (u < NE) tile.at(u % NB, u / NB) = o[e];
+        }
+        __syncthreads();
+        auto gload3 = [&](int b, int n) -> Cx<R> { return cconj(tile.at(b, n)); };
+        auto gstore3 = [&](int b, int n, Cx<R> v) {
+            const int ky = ky0 + b;
+            if (ky >= ny) return;
+            S[(size_t)n * plane + (size_t)ky * M] = cconj(v);
+        };
+        fft_tile<R, N, NB, NT, true, Cf::PAD, true>(s_tw, 1, gload3, gstore3, tile);
+        return;
+    }
+
     // ---- m = 0 column pairs ------------------------------------------------
     constexpr int NP = NB / 2;
     const int pair0 = (int)blockIdx.x * NP;
@@ -160,7 +214,8 @@ template <int N> static int run_zp(const ZArgs &a, hipStream_t s)
 {
     using Cf = ZPCfg<N>;
     const int npairs = a.ny / 2 + 1;
-    const int nspecial = (npairs + Cf::NB / 2 - 1) / (Cf::NB / 2);
+    const int nspecial = a.ywall ? (a.ny + Cf::NB - 1) / Cf::NB
+                                 : (npairs + Cf::NB / 2 - 1) / (Cf::NB / 2);
     const int nmain = (a.ny * a.M + Cf::NB - 1) / Cf::NB;
     hipLaunchKernelGGL(k_z_per<N>, dim3(nspecial + nmain, a.batch ? a.nbatch : 1), dim3(Cf::NT),
                        0, s, a, nspecial);

@@ -43,7 +43,9 @@
 // Nyquist) combined as A + iB; after the y transform they separate as
 //     A(ky) = (Z(ky) + conj Z(-ky))/2,  B(ky) = (Z(ky) - conj Z(-ky))/(2i).
 // The first `nspecial` workgroups take these virtual columns (pairs ky,
-// -ky) and recombine the results with a lane exchange.  The singular column
+// -ky) and recombine the results with a lane exchange.  With walls along y
+// the y coefficients are real-linear: column (0, ky) holds A + iB itself, and
+// the lanes of a pair take its real and imaginary parts.  The singular column
 // (m, ky) = (0, 0) -- the zero wavenumber -- is solved in FP64 whatever the
 // precision: its right-hand side mean is removed (this removes mean(f), which
 // is reported), p is pinned by the zero-mean gauge, and the Neumann problem
@@ -124,9 +126,18 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
         const int vc = (int)blockIdx.x * W + w;
         const int pair = vc >> 1;
         part = vc & 1;
-        active = pair <= ny / 2;
-        ky = active ? pair : 0;
-        kyn = (ny - ky) % ny;
+        if (a.ywall) {
+            // walls along y: the coefficients along y are real-linear, so
+            // column (0, ky) holds the two real x-modes as A + iB with no
+            // partner column: part 0 solves Re, part 1 solves Im
+            active = pair < ny;
+            ky = active ? pair : 0;
+            kyn = ky;
+        } else {
+            active = pair <= ny / 2;
+            ky = active ? pair : 0;
+            kyn = (ny - ky) % ny;
+        }
         zero_lane = active && pair == 0 && part == 0 && !a.regular;
         const double lx = part ? a.lamx[M] : a.lamx[0];
         s_d = (active && !zero_lane) ? -(lx + a.lamy[ky]) * a.dz2 : 1.0;
@@ -138,8 +149,13 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
             Cx<R> v = {R(0), R(0)};
             if (active && k < nz) {
                 const Cx<R> z1 = c1[(size_t)i * plane];
-                const Cx<R> z2 = cconj(c2[(size_t)i * plane]);
-                v = part ? cscale(cmul_mi(csub(z1, z2)), R(0.5)) : cscale(cadd(z1, z2), R(0.5));
+                if (a.ywall) {
+                    v = part ? Cx<R>{z1.im, R(0)} : Cx<R>{z1.re, R(0)};
+                } else {
+                    const Cx<R> z2 = cconj(c2[(size_t)i * plane]);
+                    v = part ? cscale(cmul_mi(csub(z1, z2)), R(0.5))
+                             : cscale(cadd(z1, z2), R(0.5));
+                }
             }
             d[i] = v;
         }
@@ -379,7 +395,7 @@ static int run_zw(const ZArgs &a, hipStream_t s)
 {
     const int C = (a.nz + L - 1) / L;
     if (C * W > MAXT) return -1;
-    const int npairs = a.ny / 2 + 1;
+    const int npairs = a.ywall ? a.ny : a.ny / 2 + 1;
     const int nspecial = (2 * npairs + W - 1) / W;
     const int nmain = (a.ny * a.M + W - 1) / W;
     const size_t shm = ((C * W * 4 * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double);

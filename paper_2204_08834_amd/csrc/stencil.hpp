@@ -58,7 +58,8 @@ struct MarchIdx {
 
     int ny, nz, bc_z;
     int j0, V;     // first y-row and number of valid rows of this block
-    int jm, jn;    // halo rows: (j0 - 1) mod ny and (j0 + V) mod ny
+    int jm, jn;    // halo rows: (j0 - 1) mod ny and (j0 + V) mod ny, or the wall row
+    double sm, sn; // factors of the halo rows: -1 for the ghost of a Dirichlet wall
     size_t plane;  // ny * NX
 
     // Element q of a thread is (row t, pair h) with e = threadIdx.x + q NT,
@@ -103,15 +104,20 @@ struct MarchIdx {
         return k < nz - 1 ? k + 1 : (bc_z == 0 ? 0 : k);
     }
 
-    __device__ __forceinline__ void setup(int jb, int ny_, int nz_, int bc_z_)
+    // bc: 0 periodic, 1 Neumann walls (the ghost row mirrors the wall row),
+    // 2 Dirichlet walls (the ghost row is the negated wall row)
+    __device__ __forceinline__ void setup(int jb, int ny_, int nz_, int bc_z_, int bc_y = 0)
     {
         ny = ny_;
         nz = nz_;
         bc_z = bc_z_;
         j0 = jb * TJ;
         V = ny - j0 < TJ ? ny - j0 : TJ;
-        jm = j0 == 0 ? ny - 1 : j0 - 1;
-        jn = j0 + V == ny ? 0 : j0 + V;
+        const bool lo = j0 == 0, hi = j0 + V == ny;
+        jm = lo ? (bc_y == 0 ? ny - 1 : 0) : j0 - 1;
+        jn = hi ? (bc_y == 0 ? 0 : ny - 1) : j0 + V;
+        sm = (lo && bc_y == 2) ? -1.0 : 1.0;
+        sn = (hi && bc_y == 2) ? -1.0 : 1.0;
         plane = (size_t)ny * NX;
     }
 };
@@ -174,9 +180,12 @@ struct PlaneMarch : MarchIdx<M, TJ, NT> {
             pu[q] = double2{gs * x.x, gs * x.y};
             fv[q] = *(const PK_GLOBAL double2 *)(fk + o);
         }
+        const double sm = this->sm, sn = this->sn;
         for (int h = threadIdx.x; h < M; h += NT) {
-            tile[0][h] = *(const PK_GLOBAL double2 *)(pk_ + (size_t)jm * NX + 2 * h);
-            tile[V + 1][h] = *(const PK_GLOBAL double2 *)(pk_ + (size_t)jn * NX + 2 * h);
+            const double2 a = *(const PK_GLOBAL double2 *)(pk_ + (size_t)jm * NX + 2 * h);
+            const double2 b = *(const PK_GLOBAL double2 *)(pk_ + (size_t)jn * NX + 2 * h);
+            tile[0][h] = double2{sm * a.x, sm * a.y};
+            tile[V + 1][h] = double2{sn * b.x, sn * b.y};
         }
 #pragma unroll
         for (int q = 0; q < PER; ++q)

@@ -69,8 +69,8 @@ def test_valid_descriptors(shape, bc):
     (dict(dz=float("inf")), P.ERR_INVALID_ARG),
     (dict(bc_z=3), P.ERR_INVALID_ARG),
     (dict(bc_x=1), P.ERR_UNSUPPORTED),          # walls in x: not in this build
-    (dict(bc_y=1), P.ERR_UNSUPPORTED),
     (dict(bc_x=2), P.ERR_UNSUPPORTED),
+    (dict(bc_y=3), P.ERR_INVALID_ARG),
     (dict(bc_x=5), P.ERR_INVALID_ARG),
     (dict(precision=3), P.ERR_INVALID_ARG),
     (dict(precision="fp32_refine", rtol=0.0), P.ERR_INVALID_ARG),

@@ -186,3 +186,85 @@ def test_project_refuses_dirichlet():
         with pytest.raises(P.PoissonError) as e:
             plan.project(u, torch.zeros_like(u), torch.zeros_like(u))
         assert e.value.code == P.ERR_UNSUPPORTED
+
+
+# --------------------------------------------------------------------------
+# walls along y (cosine / sine expansions), x periodic
+# --------------------------------------------------------------------------
+YCASES = [((16, 12, 10), NEU), ((16, 12, 10), DIR), ((32, 6, 8), PER), ((8, 3, 5), NEU),
+          ((2, 1, 3), DIR), ((64, 48, 20), NEU), ((12, 96, 6), PER), ((4, 512, 3), NEU),
+          ((2, 2048, 2), DIR), ((6, 768, 4), PER)]
+
+
+@pytest.mark.parametrize("bc_y", [NEU, DIR])
+@pytest.mark.parametrize("case", YCASES, ids=[f"{c[0][0]}x{c[0][1]}x{c[0][2]}_z{c[1]}"
+                                              for c in YCASES])
+def test_y_walls_match_oracle(orc, case, bc_y):
+    P = _gpu()
+    (nx, ny, nz), bc_z = case
+    sp = (BOX[0] / nx, BOX[1] / ny, BOX[2] / nz)
+    bcs = (PER, bc_y, bc_z)
+    f = inputs.random_rhs(nx, ny, nz, seed=nx + 5 * ny + 11 * nz + bc_y, zero_mean=False) + 0.25
+    p_ref = orc.solve(f, *sp, bc_z, bc_y=bc_y)
+    res_ref, _ = orc.residual(f, p_ref, *sp, bc_z, bc_y=bc_y)
+    k = kappa(nx, ny, nz, sp, bcs)
+    rtol = max(1e-10, 10 * res_ref)
+    for prec in ("fp64", "fp32_refine", "fp32"):
+        print(f"[walls] {nx}x{ny}x{nz} y{bc_y} z{bc_z} {prec}", flush=True)
+        p, st = gpu_solve(P, f, sp, bcs, prec, rtol=rtol)
+        assert st["status"] == 0, st
+        if DIR in bcs:
+            assert st["rhs_mean"] == 0.0
+        else:
+            assert abs(st["rhs_mean"] - f.mean()) <= 1e-12
+        err = rel(p, p_ref)
+        if prec == "fp64":
+            res, _ = orc.residual(f, p, *sp, bc_z, bc_y=bc_y)
+            print(f"[walls] kappa {k:.1e} error {err:.2e} residual {res:.1e} oracle "
+                  f"{res_ref:.1e}", flush=True)
+            assert res <= max(1e-13, 4 * res_ref), (res, res_ref)
+            assert err <= max(1e-12, 4 * k * 2.2e-16), (err, k)
+        elif prec == "fp32_refine":
+            res, _ = orc.residual(f, p, *sp, bc_z, bc_y=bc_y)
+            assert res <= rtol, (res, rtol, st)
+        else:
+            assert err <= max(2e-5, 8 * k * 6e-8), (err, k)
+
+
+@pytest.mark.parametrize("bcs", [(PER, NEU, NEU), (PER, DIR, NEU), (PER, NEU, PER),
+                                 (PER, DIR, DIR)])
+def test_y_walls_eigenmode(bcs):
+    """Closed-form modes at 256 x 192 x 64: a cosine or sine along y."""
+    P = _gpu()
+    nx, ny, nz = 256, 192, 64
+    sp = (2.0 / nx, 1.5 / ny, 1.0 / nz)
+    a, b, c = 7, 150, 33
+    i = np.arange(nx) + 0.5
+    j = np.arange(ny) + 0.5
+    k = np.arange(nz) + 0.5
+
+    def mode(n, bc, m, x):
+        if bc == NEU:
+            return np.cos(np.pi * m * x / n)
+        if bc == DIR:
+            return np.sin(np.pi * (m + 1) * x / n)
+        return np.cos(2 * np.pi * m * x / n + 0.4)
+
+    f = (mode(nz, bcs[2], c, k)[:, None, None] * mode(ny, bcs[1], b, j)[None, :, None]
+         * mode(nx, bcs[0], a, i)[None, None, :])
+    lam = -(lam1(nx, sp[0], a, bcs[0]) + lam1(ny, sp[1], b, bcs[1]) + lam1(nz, sp[2], c, bcs[2]))
+    for prec, tol in (("fp64", 1e-12), ("fp32_refine", 1e-9)):
+        p, st = gpu_solve(P, f, sp, bcs, prec)
+        assert rel(p, f / lam) <= tol, (prec, bcs, rel(p, f / lam), st)
+
+
+@pytest.mark.parametrize("mode", ["graph", "device"])
+def test_y_walls_device_loop_matches_host(mode):
+    P = _gpu()
+    nx, ny, nz = 64, 48, 24
+    sp = (2.0 / nx, 2.0 / ny, 1.0 / nz)
+    f = inputs.random_rhs(nx, ny, nz, seed=4, zero_mean=False)
+    for bcs in ((PER, NEU, NEU), (PER, DIR, PER)):
+        a, sa = gpu_solve(P, f, sp, bcs, "fp32_refine", "host")
+        b, sb = gpu_solve(P, f, sp, bcs, "fp32_refine", mode)
+        assert sa == sb and np.array_equal(a, b), bcs
