@@ -76,11 +76,13 @@ typedef enum {
  *   nz      : walls: 1..4096 (any value); periodic: 2^a or 3*2^a up to 2048.
  *   nx*ny*nz <= 2^31.
  *   dx,dy,dz: positive, finite cell sizes.
- *   bc_x, bc_y: POISSON_BC_PERIODIC (the only supported value).
- *   bc_z    : POISSON_BC_PERIODIC, POISSON_BC_NEUMANN or POISSON_BC_DIRICHLET
- *             (the homogeneous pressure conditions of the expansions of
- *             Section 3.3.1).  With a Dirichlet wall the operator has no null
- *             space: f keeps its mean, p is not shifted, rhs_mean reports 0.
+ *   bc_x, bc_y, bc_z: POISSON_BC_PERIODIC, POISSON_BC_NEUMANN or
+ *             POISSON_BC_DIRICHLET, any combination (the homogeneous pressure
+ *             conditions of the expansions of Section 3.3.1: Fourier series
+ *             along a periodic axis, cosine / sine series between walls along
+ *             x and y, the tridiagonal solve between walls along z).  With a
+ *             Dirichlet wall the operator has no null space: f keeps its
+ *             mean, p is not shifted, rhs_mean reports 0.
  *   precision: poisson_precision_t.
  *   rtol    : FP32_REFINE target for ||f - mean f - L p||_2 / ||f - mean f||_2
  *             (default 1e-10; must be > 0).
@@ -159,9 +161,9 @@ int poisson_solve(poisson_plan plan, const double *rhs_dev, double *sol_dev,
  * were and psi holds the last iterate.  Under POISSON_FP32_REFINE the first
  * call allocates one more float64 field (nx*ny*nz) that the plan keeps for f.
  * Errors: INVALID_ARG (null plan or field, batched plan, non-finite scale,
- * overlapping fields), UNSUPPORTED (a plan with Dirichlet walls, whose
- * velocity conventions are not those of no-slip walls), OUT_OF_MEMORY, HIP,
- * and those of poisson_solve.
+ * overlapping fields), UNSUPPORTED (a plan with walls along x or y, or with
+ * Dirichlet walls: the face conventions above are those of periodic x, y and
+ * no-slip walls in z), OUT_OF_MEMORY, HIP, and those of poisson_solve.
  */
 int poisson_project(poisson_plan plan, double *u, double *v, double *w, double *p, double *psi,
                     double alpha, double beta, poisson_stats_t *stats);

@@ -306,6 +306,7 @@ Tune initial_tune(const poisson_desc_t &d)
 struct Tables {
     std::shared_ptr<DevBuf> twx[2], twy[2], twz[2];  // [0] FP64, [1] FP32 complex tables
     std::shared_ptr<DevBuf> twy4[2];                 // walls along y: exp(-i pi k/(2 ny))
+    std::shared_ptr<DevBuf> twx4[2];                 // walls along x: exp(-i pi k/(2 nx))
     std::shared_ptr<DevBuf> lamx, lamy, lamz;
 };
 
@@ -419,7 +420,6 @@ int validate(const poisson_desc_t *d)
         return POISSON_ERR_INVALID_ARG;
     auto known = [](int bc) { return bc >= POISSON_BC_PERIODIC && bc <= POISSON_BC_DIRICHLET; };
     if (!known(d->bc_x) || !known(d->bc_y) || !known(d->bc_z)) return POISSON_ERR_INVALID_ARG;
-    if (d->bc_x != POISSON_BC_PERIODIC) return POISSON_ERR_UNSUPPORTED;
     if (d->precision < POISSON_FP64 || d->precision > POISSON_FP32) return POISSON_ERR_INVALID_ARG;
     if (d->precision == POISSON_FP32_REFINE) {
         if (!(std::isfinite(d->rtol) && d->rtol > 0)) return POISSON_ERR_INVALID_ARG;
@@ -496,7 +496,12 @@ int build_group(Group &g)
     if ((rc = upload_complex(t.twy, twiddle_table(d.ny), f32, f64))) return rc;
     if (d.bc_z == POISSON_BC_PERIODIC && (rc = upload_complex(t.twz, twiddle_table(d.nz), f32, f64)))
         return rc;
-    auto lx = eig_table(d.nx, d.dx, g.M + 1);
+    // walls along x: nx cosine / sine modes; periodic: M + 1 wavenumbers
+    auto lx = d.bc_x == POISSON_BC_PERIODIC ? eig_table(d.nx, d.dx, g.M + 1)
+                                            : eig_table_walls(d.nx, d.dx, d.bc_x);
+    if (d.bc_x != POISSON_BC_PERIODIC &&
+        (rc = upload_complex(t.twx4, quarter_table(d.nx), f32, f64)))
+        return rc;
     auto ly = d.bc_y == POISSON_BC_PERIODIC ? eig_table(d.ny, d.dy, d.ny)
                                             : eig_table_walls(d.ny, d.dy, d.bc_y);
     if (d.bc_y != POISSON_BC_PERIODIC &&
@@ -604,6 +609,8 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials, bool sum = true)
     a.nz = g.d.nz;
     a.bc_z = g.d.bc_z;
     a.bc_y = g.d.bc_y;
+    a.bc_x = g.d.bc_x;
+    a.tw4x = g.d.bc_x != POISSON_BC_PERIODIC ? g.tab.twx4[L.prec == P_F32 ? 1 : 0]->p : nullptr;
     a.ax = 1.0 / (g.d.dx * g.d.dx);
     a.ay = 1.0 / (g.d.dy * g.d.dy);
     a.az = 1.0 / (g.d.dz * g.d.dz);
@@ -661,6 +668,7 @@ int pass_residual_check(LSet &L, bool sum = true)
     a.nz = g.d.nz;
     a.bc_z = g.d.bc_z;
     a.bc_y = g.d.bc_y;
+    a.bc_x = g.d.bc_x;
     a.ax = 1.0 / (g.d.dx * g.d.dx);
     a.ay = 1.0 / (g.d.dy * g.d.dy);
     a.az = 1.0 / (g.d.dz * g.d.dz);
@@ -721,6 +729,7 @@ int pass_z(LSet &L)
     a.dirichlet_z = g.d.bc_z == POISSON_BC_DIRICHLET ? 1 : 0;
     a.regular = regular(g.d) ? 1 : 0;
     a.ywall = g.d.bc_y != POISSON_BC_PERIODIC ? 1 : 0;
+    a.xwall = g.d.bc_x != POISSON_BC_PERIODIC ? 1 : 0;
     const double bytes = (double)g.N * 2.0 * (L.prec == P_F32 ? 4.0 : 8.0) * L.n;
     char name[40];
     if (g.d.bc_z != POISSON_BC_PERIODIC) {
@@ -737,7 +746,9 @@ int pass_x_inv(LSet &L, bool accumulate)
     // the inverse x pass follows the inverse y pass, which wrote the planes in order
     XInvArgs a{L.dev, L.n, L.one.S, L.one.p, g.tab.twx[L.prec == P_F32 ? 1 : 0]->p, g.d.nx,
                g.d.ny, g.d.nz, accumulate ? 1 : 0, g.tune.rev, nullptr,
-               1.0 / (double)g.N, L.gate, regular(g.d) ? 1 : 0};
+               1.0 / (double)g.N, L.gate, regular(g.d) ? 1 : 0, g.d.bc_x,
+               g.d.bc_x != POISSON_BC_PERIODIC ? g.tab.twx4[L.prec == P_F32 ? 1 : 0]->p
+                                               : nullptr};
     // the mean of p from the residual pass (batched launches redirect it)
     if (accumulate) a.sum_p = L.dev ? (const double *)g.partials->p : L.one.scal + 4;
     char name[40];

@@ -147,6 +147,8 @@ struct XFwdArgs {
     int nx, ny, nz;
     int bc_z;               // 0 periodic, 1 Neumann walls, 2 Dirichlet walls
     int bc_y;               // the same along y (residual marches)
+    int bc_x;               // the same along x: walls take cosine / sine expansions
+    const void *tw4x;       // walls along x: exp(-i pi k/(2 nx)), k in [0, nx)
     double ax, ay, az;      // 1/dx^2, 1/dy^2, 1/dz^2
     const double *sum_f;    // residual mode: device sum of f (mean = sum_f * inv_n)
     double inv_n;           // 1/(nx ny nz)
@@ -175,6 +177,8 @@ struct XInvArgs {
     double inv_n;           // 1/(nx ny nz)
     int gate;
     int regular;            // a Dirichlet wall: the mean of p is kept
+    int bc_x;               // 0 periodic, 1 Neumann walls (cosines), 2 Dirichlet walls (sines)
+    const void *tw4x;       // walls along x: exp(-i pi k/(2 nx)), k in [0, nx)
 };
 
 // Strided complex pass along y, in place on S.
@@ -213,6 +217,7 @@ struct ZArgs {
     int dirichlet_z;        // walls with zero value (ghost = -wall cell) instead of zero gradient
     int regular;            // no null space (a Dirichlet wall on some axis): no zero mode
     int ywall;              // walls along y: the m = 0 column holds A + iB with real y-modes
+    int xwall;              // walls along x: every column m holds the real x-modes 2m, 2m+1
 };
 
 // Launchers (return 0 on success, a hipError_t value otherwise).  The forward

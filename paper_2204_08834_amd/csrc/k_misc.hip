@@ -210,6 +210,7 @@ __global__ __launch_bounds__(RC_NT) void k_residual_check(XFwdArgs a0)
     m.mu = (a.sum_f && !a.regular) ? (*a.sum_f) * a.inv_n : 0.0;
     m.tile = s_tile;
     m.setup(jb, a.ny, a.nz, a.bc_z, a.bc_y);
+    m.bc_x = a.bc_x;
     m.start(k0);
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
     auto sink = [&](int, int, int, double r0, double r1, double f0, double f1, double2 c) {

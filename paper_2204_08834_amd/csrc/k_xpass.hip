@@ -82,6 +82,50 @@ __device__ __forceinline__ void merge_pair(Cx<T> xm, Cx<T> xc, Cx<T> w, Cx<T> &z
     zc = csub(A, Tt);
 }
 
+// Walls along x (cosine basis for Neumann, sine basis for Dirichlet): a real
+// row x of nx cells is read reordered, v[j] = x[r(j)] with r(j) = 2j (2j < nx)
+// or 2nx-1-2j (and (-1)^r(j) x[r(j)] for sines), so the half spectrum X of v
+// gives the coefficients (Makhoul's method)
+//     C[k] = Re(w_k X[k]),  C[nx-k] = Re(w_{nx-k} conj X[k]),  w_k = exp(-i pi k/(2nx)),
+// each X[k] yielding two; for sines coefficient k sits at nx-1-k.  They are
+// stored in the real view of the row (coefficient k at real offset k), so a
+// spectrum column m holds the real x-modes 2m and 2m+1 as C[2m] + i C[2m+1].
+// The inverse reads W[k] = conj(w_k) (C[k] - i C[nx-k]) (C[nx] = 0; W is
+// Hermitian, so the C2R merge applies), with W[0] + i W[M] = C[0] + i sqrt2
+// C[M] in the packed column, and stores v[j] back to x[r(j)].
+__device__ __forceinline__ int wall_index(int j, int nx) { return 2 * j < nx ? 2 * j : 2 * nx - 1 - 2 * j; }
+
+template <typename T>
+__device__ __forceinline__ void wall_emit(PK_GLOBAL T *row, int nx, int m, Cx<T> X,
+                                          const PK_GLOBAL Cx<T> *w4, bool sine)
+{
+    const Cx<T> wa = w4[m];
+    row[sine ? nx - 1 - m : m] = wa.re * X.re - wa.im * X.im;  // Re(w_m X)
+    if (2 * m != nx) {
+        const Cx<T> wb = w4[nx - m];
+        row[sine ? m - 1 : nx - m] = wb.re * X.re + wb.im * X.im;  // Re(w_{nx-m} conj X)
+    }
+}
+
+// coefficient k of a wall row (real view), reversed for sines; C[nx] = 0
+template <typename T>
+__device__ __forceinline__ T wall_coef(const PK_GLOBAL T *row, int nx, int k, bool sine)
+{
+    if (k >= nx) return T(0);
+    return row[sine ? nx - 1 - k : k];
+}
+
+// X[m] for the inverse pass from the coefficients of a wall row
+template <typename T>
+__device__ __forceinline__ Cx<T> wall_load(const PK_GLOBAL T *row, int nx, int m,
+                                           const PK_GLOBAL Cx<T> *w4, bool sine)
+{
+    if (m == 0) return {wall_coef(row, nx, 0, sine), T(1.4142135623730951) * wall_coef(row, nx, nx / 2, sine)};
+    const T a = wall_coef(row, nx, m, sine), b = wall_coef(row, nx, nx - m, sine);
+    const Cx<T> w = w4[m];
+    return {w.re * a - w.im * b, -(w.re * b + w.im * a)};
+}
+
 // Forward transform of the NB lines of M points held by a workgroup: pass 0
 // reads through gload (from global memory, or from the tile itself when
 // GL_LDS), and the last pass writes the half spectra of the real rows through
@@ -91,8 +135,10 @@ __device__ __forceinline__ void merge_pair(Cx<T> xm, Cx<T> xc, Cx<T> w, Cx<T> &z
 // transform continues from pass 1 (needs at least two passes).
 template <int M, int NB, int NT, bool GL_LDS, int P0 = 0, class GL, class OUT>
 __device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R, M, NB, false, 0> tile,
-                                          OUT &out)
+                                          OUT &out, int xbc = 0,
+                                          const PK_GLOBAL Cx<R> *w4 = nullptr)
 {
+    const bool sine = xbc == 2;
     auto lstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
     constexpr RPlan pl = make_rplan(M);
     static_assert(P0 == 0 || pl.count >= 2, "");
@@ -130,15 +176,27 @@ __device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R,
             Bfly<R, RAD>::run(v2);
             PK_GLOBAL Cx<R> *Sr = out(b);
             if (!Sr) continue;
+            PK_GLOBAL R *Sreal = (PK_GLOBAL R *)Sr;
             auto emit = [&](int m, Cx<R> zm, Cx<R> zc) {
                 Cx<R> xm, xc;
                 split_pair(zm, zc, tw[m], xm, xc);
-                put(Sr + m, xm);
-                if (2 * m != M) put(Sr + (M - m), xc);
+                if (xbc) {
+                    wall_emit(Sreal, 2 * M, m, xm, w4, sine);
+                    if (2 * m != M) wall_emit(Sreal, 2 * M, M - m, xc, w4, sine);
+                } else {
+                    put(Sr + m, xm);
+                    if (2 * m != M) put(Sr + (M - m), xc);
+                }
             };
             if (pp == 0) {
                 // butterfly 0: m = r NJ; m = 0 packs X(0) + i X(M)
-                put(Sr, Cx<R>{v1[0].re + v1[0].im, v1[0].re - v1[0].im});
+                const R X0 = v1[0].re + v1[0].im, XM = v1[0].re - v1[0].im;
+                if (xbc) {
+                    Sreal[sine ? 2 * M - 1 : 0] = X0;
+                    Sreal[sine ? M - 1 : M] = XM * w4[M].re;
+                } else {
+                    put(Sr, Cx<R>{X0, XM});
+                }
 #pragma unroll
                 for (int r = 1; r < RAD; ++r)
                     if (r <= RAD - r) emit(r * NJ, v1[r], v1[RAD - r]);
@@ -159,13 +217,23 @@ __device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R,
             const int b = u / M, m = u % M;
             PK_GLOBAL Cx<R> *Sr = out(b);
             if (!Sr) continue;
+            PK_GLOBAL R *Sreal = (PK_GLOBAL R *)Sr;
             const Cx<R> zm = tile.at(b, m);
             if (m == 0) {
-                put(Sr, Cx<R>{zm.re + zm.im, zm.re - zm.im});
+                const R X0 = zm.re + zm.im, XM = zm.re - zm.im;
+                if (xbc) {
+                    Sreal[sine ? 2 * M - 1 : 0] = X0;
+                    Sreal[sine ? M - 1 : M] = XM * w4[M].re;
+                } else {
+                    put(Sr, Cx<R>{X0, XM});
+                }
             } else {
                 Cx<R> xm, xc;
                 split_pair(zm, tile.at(b, M - m), tw[m], xm, xc);
-                put(Sr + m, xm);
+                if (xbc)
+                    wall_emit(Sreal, 2 * M, m, xm, w4, sine);  // C[m] and C[nx-m]
+                else
+                    put(Sr + m, xm);
             }
         }
     }
@@ -202,10 +270,23 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
     Tile tile{s_tile};
     PK_GLOBAL Cx<R> *S = gbl((Cx<R> *)a.S);
     const PK_GLOBAL double *gf = gbl(a.f);
+    const int xbc = a.bc_x;
+    const PK_GLOBAL Cx<R> *w4 = xbc ? gbl((const Cx<R> *)a.tw4x) : nullptr;
     auto loader = [&](int row0) {
         return [&, row0](int b, int n) -> Cx<R> {
             const int row = row0 + b;
             if (row >= nrows) return {R(0), R(0)};
+            if (xbc) {
+                // walls: the reordered row v[j] = x[r(j)] (sines: signed)
+                const int i0 = wall_index(2 * n, NX), i1 = wall_index(2 * n + 1, NX);
+                double f0 = gf[(size_t)row * NX + i0], f1 = gf[(size_t)row * NX + i1];
+                acc0 += f0 + f1;
+                if (xbc == 2) {
+                    f0 = (i0 & 1) ? -f0 : f0;
+                    f1 = (i1 & 1) ? -f1 : f1;
+                }
+                return {R(f0), R(f1)};
+            }
             // f is read once (streaming loads measured 16 % faster for the
             // FP64 pass; the residual marches, which also read f, lost 1-3 %)
             const double2 fv = ld_stream(gf + (size_t)row * NX + 2 * n);
@@ -236,7 +317,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
                 return row < nrows ? S + (size_t)row * M : nullptr;
             };
             auto gnone = [&](int, int) -> Cx<R> { return {R(0), R(0)}; };
-            x_forward<M, NB, NT, false, 1>(s_tw, gnone, tile, out);
+            x_forward<M, NB, NT, false, 1>(s_tw, gnone, tile, out, xbc, w4);
         }
     } else {
         __syncthreads();
@@ -247,7 +328,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
                 const int row = row0 + b;
                 return row < nrows ? S + (size_t)row * M : nullptr;
             };
-            x_forward<M, NB, NT, false>(s_tw, gl, tile, out);
+            x_forward<M, NB, NT, false>(s_tw, gl, tile, out, xbc, w4);
             __syncthreads();
         }
     }
@@ -312,6 +393,9 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
     m.mu = (a.sum_f && !a.regular) ? (*a.sum_f) * a.inv_n : 0.0;
     m.tile = (double2(*)[M])s_buf;
     m.setup(jb, a.ny, a.nz, a.bc_z, a.bc_y);
+    m.bc_x = a.bc_x;
+    const int xbc = a.bc_x;
+    const PK_GLOBAL Cx<R> *w4 = xbc ? gbl((const Cx<R> *)a.tw4x) : nullptr;
     load_table(s_tw, (const Cx<R> *)a.tw, NX);
     m.start(k0);
 
@@ -330,14 +414,24 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
         m.step(k, sink);
         __syncthreads();  // the march is done reading the plane tile
 #pragma unroll
-        for (int q = 0; q < Mar::PER; ++q)
-            if (m.valid(q)) tile.at(m.row_of(q), m.pair_of(q)) = rr[q];
+        for (int q = 0; q < Mar::PER; ++q) {
+            if (!m.valid(q)) continue;
+            const int t = m.row_of(q), h = m.pair_of(q);
+            if (xbc) {
+                // walls: x[2h] -> v[h], x[2h+1] -> v[nx-1-h] (negated for sines)
+                R *trow = (R *)&tile.at(t, 0);
+                trow[h] = rr[q].re;
+                trow[NX - 1 - h] = xbc == 2 ? -rr[q].im : rr[q].im;
+            } else {
+                tile.at(t, h) = rr[q];
+            }
+        }
         __syncthreads();
         auto gload = [&](int b, int n) -> Cx<R> { return tile.at(b, n); };
         const size_t rowk = (size_t)k * a.ny + m.j0;
         const int V = m.V;
         auto out = [&](int b) -> PK_GLOBAL Cx<R> * { return b < V ? S + (rowk + b) * M : nullptr; };
-        x_forward<M, TJ, NT, true>(s_tw, gload, tile, out);
+        x_forward<M, TJ, NT, true>(s_tw, gload, tile, out, xbc, w4);
     }
     block_sum3(acc0, acc1, acc2, s_red);
     if (threadIdx.x == 0) {
@@ -457,17 +551,42 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
 
     const PK_GLOBAL Cx<R> *S = gbl((const Cx<R> *)a.S);
     PK_GLOBAL double *gp = gbl(a.p);
+    const int xbc = a.bc_x;
+    const bool sine = xbc == 2;
+    const PK_GLOBAL Cx<R> *w4 = xbc ? gbl((const Cx<R> *)a.tw4x) : nullptr;
     auto gstore = [&](int b, int n, Cx<R> v) {
         const int row = row0 + b;
         if (row >= nrows) return;
-        PK_GLOBAL double *dst = gp + (size_t)row * NX + 2 * n;
         double2 o = {double(v.re), -double(v.im)};
+        if (xbc) {
+            // walls: v[j] goes back to x[r(j)] (negated at odd x for sines)
+            const int i0 = wall_index(2 * n, NX), i1 = wall_index(2 * n + 1, NX);
+            if (sine) {
+                o.x = (i0 & 1) ? -o.x : o.x;
+                o.y = (i1 & 1) ? -o.y : o.y;
+            }
+            PK_GLOBAL double *rp = gp + (size_t)row * NX;
+            if constexpr (ACC) {
+                o.x += rp[i0] - pmean;
+                o.y += rp[i1] - pmean;
+            }
+            rp[i0] = o.x;
+            rp[i1] = o.y;
+            return;
+        }
+        PK_GLOBAL double *dst = gp + (size_t)row * NX + 2 * n;
         if constexpr (ACC) {
             const double2 old = ld_stream(dst);
             o.x += old.x - pmean;
             o.y += old.y - pmean;
         }
         st_stream(dst, o);
+    };
+    // spectrum value m of a row: the packed half spectrum, or for walls the
+    // inverse input formed from the cosine / sine coefficients
+    auto xval = [&](const PK_GLOBAL Cx<R> *sr, int m) -> Cx<R> {
+        if (xbc) return wall_load((const PK_GLOBAL R *)sr, NX, m, w4, sine);
+        return sr[m];
     };
     Tile tile{s_tile};
     // reversed radix order: the small radix first gives more butterfly pairs
@@ -494,8 +613,8 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
                 const PK_GLOBAL Cx<R> *sr = S + (size_t)row * M;
 #pragma unroll
                 for (int r = 0; r < RAD; ++r) {
-                    v1[r] = sr[j1 + r * NJ];
-                    v2[r] = sr[j2 + r * NJ];
+                    v1[r] = xval(sr, j1 + r * NJ);
+                    v2[r] = xval(sr, j2 + r * NJ);
                 }
             } else {
 #pragma unroll
@@ -536,11 +655,11 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
             if (row >= nrows) return {R(0), R(0)};
             const PK_GLOBAL Cx<R> *sr = S + (size_t)row * M;
             if (n == 0) {
-                const Cx<R> s0 = sr[0];
+                const Cx<R> s0 = xval(sr, 0);
                 return {s0.re + s0.im, -(s0.re - s0.im)};
             }
             Cx<R> zm, zc;
-            merge_pair(sr[n], sr[M - n], s_tw[n], zm, zc);
+            merge_pair(xval(sr, n), xval(sr, M - n), s_tw[n], zm, zc);
             return zm;
         };
         fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, gstore, tile);

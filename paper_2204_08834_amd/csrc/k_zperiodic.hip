@@ -85,15 +85,26 @@ __global__ __launch_bounds__(ZPCfg<N>::NT) void k_z_per(ZArgs a0, int nspecial)
         return;
     }
 
+    // walls along x: every column m holds the real x-modes (2m, 2m+1) as
+    // A + iB and takes the paths below (workgroups along m, coalesced);
+    // otherwise only m = 0 (DC and Nyquist) does
+    const int mblocks_y = a.xwall ? (M + NB - 1) / NB : 1;
+    auto lamA_of = [&](int m) { return a.xwall ? a.lamx[2 * m] : a.lamx[0]; };
+    auto lamB_of = [&](int m) { return a.xwall ? a.lamx[2 * m + 1] : a.lamx[M]; };
     if (a.ywall) {
-        // ---- m = 0 with walls along y: each column (0, ky) holds A + iB
-        // (real modes along y), which separate through the symmetry kz <-> -kz
-        // of the same column
-        const int ky0 = (int)blockIdx.x * NB;
+        // ---- walls along y: each column (m, ky) holds A + iB (real modes
+        // along y), which separate through the symmetry kz <-> -kz of the
+        // same column.  A workgroup takes NB columns: NB values of ky at m = 0,
+        // or NB consecutive m at one ky (walls along x)
+        const int bx = (int)blockIdx.x;
+        const int kyb = a.xwall ? bx / mblocks_y : bx * NB;
+        const int mb = a.xwall ? (bx % mblocks_y) * NB : 0;
+        auto colm = [&](int b) { return a.xwall ? mb + b : 0; };
+        auto colky = [&](int b) { return a.xwall ? kyb : kyb + b; };
+        auto inside = [&](int b) { return colky(b) < ny && colm(b) < M; };
         auto gload = [&](int b, int n) -> Cx<R> {
-            const int ky = ky0 + b;
-            if (ky >= ny) return {R(0), R(0)};
-            return S[(size_t)n * plane + (size_t)ky * M];
+            if (!inside(b)) return {R(0), R(0)};
+            return S[(size_t)n * plane + (size_t)colky(b) * M + colm(b)];
         };
         fft_tile<R, N, NB, NT, true, Cf::PAD, false>(s_tw, 1, gload, lstore, tile);
         __syncthreads();
@@ -105,15 +116,15 @@ __global__ __launch_bounds__(ZPCfg<N>::NT) void k_z_per(ZArgs a0, int nspecial)
             const int u = threadIdx.x + e * NT;
             if (u >= NE) continue;
             const int b = u % NB, kz = u / NB;
-            const int ky = ky0 + b;
-            if (ky >= ny) {
+            const int ky = colky(b), m = colm(b);
+            if (!inside(b)) {
                 o[e] = {R(0), R(0)};
                 continue;
             }
             const int kzn = (N - kz) % N;
             const double ly = a.lamy[ky], lz = a.lamz[kz];
-            const double lamA = a.lamx[0] + ly + lz, lamB = a.lamx[M] + ly + lz;
-            const bool zero = ky == 0 && kz == 0 && !a.regular;
+            const double lamA = lamA_of(m) + ly + lz, lamB = lamB_of(m) + ly + lz;
+            const bool zero = m == 0 && ky == 0 && kz == 0 && !a.regular;
             const R sA = zero ? R(0) : R(a.inv_ntot / lamA);
             const R sB = R(a.inv_ntot / lamB);
             const Cx<R> z1 = tile.at(b, kz), z2 = cconj(tile.at(b, kzn));
@@ -131,30 +142,37 @@ __global__ __launch_bounds__(ZPCfg<N>::NT) void k_z_per(ZArgs a0, int nspecial)
         __syncthreads();
         auto gload3 = [&](int b, int n) -> Cx<R> { return cconj(tile.at(b, n)); };
         auto gstore3 = [&](int b, int n, Cx<R> v) {
-            const int ky = ky0 + b;
-            if (ky >= ny) return;
-            S[(size_t)n * plane + (size_t)ky * M] = cconj(v);
+            if (!inside(b)) return;
+            S[(size_t)n * plane + (size_t)colky(b) * M + colm(b)] = cconj(v);
         };
         fft_tile<R, N, NB, NT, true, Cf::PAD, true>(s_tw, 1, gload3, gstore3, tile);
         return;
     }
 
     // ---- m = 0 column pairs ------------------------------------------------
+    // A workgroup takes NP column pairs (ky, -ky): NP values of ky at m = 0,
+    // or NP consecutive m at one ky (walls along x)
     constexpr int NP = NB / 2;
-    const int pair0 = (int)blockIdx.x * NP;
-    auto col_of = [&](int b, bool &valid, bool &dup) -> int {
-        const int ky = pair0 + b / 2;
-        valid = ky <= ny / 2;
+    const int mblocks_p = a.xwall ? (M + NP - 1) / NP : 1;
+    const int bx = (int)blockIdx.x;
+    const int kyp = a.xwall ? bx / mblocks_p : bx * NP;
+    const int mp = a.xwall ? (bx % mblocks_p) * NP : 0;
+    auto pm = [&](int i) { return a.xwall ? mp + i : 0; };
+    auto pky = [&](int i) { return a.xwall ? kyp : kyp + i; };
+    auto col_of = [&](int b, bool &valid, bool &dup) -> size_t {
+        const int i = b / 2;
+        const int ky = pky(i);
+        valid = ky <= ny / 2 && pm(i) < M;
         const int kyv = valid ? ky : 0;
         const int kyn = (ny - kyv) % ny;
         dup = (b & 1) && (kyn == kyv);
-        return (b & 1) ? kyn : kyv;
+        return (size_t)((b & 1) ? kyn : kyv) * M + (valid ? pm(i) : 0);
     };
     auto gload = [&](int b, int n) -> Cx<R> {
         bool valid, dup;
-        const int col = col_of(b, valid, dup);
+        const size_t col = col_of(b, valid, dup);
         if (!valid) return {R(0), R(0)};
-        return S[(size_t)n * plane + (size_t)col * M];
+        return S[(size_t)n * plane + col];
     };
     fft_tile<R, N, NB, NT, true, Cf::PAD, false>(s_tw, 1, gload, lstore, tile);
     __syncthreads();
@@ -168,18 +186,19 @@ __global__ __launch_bounds__(ZPCfg<N>::NT) void k_z_per(ZArgs a0, int nspecial)
         if (u >= NE) continue;
         const int i = u % NP, kz = u / NP;
         const int kzn = (N - kz) % N;
-        const int ky = pair0 + i;
-        if (ky > ny / 2) {
+        const int ky = pky(i), m = pm(i);
+        if (ky > ny / 2 || m >= M) {
             o1[e] = o2[e] = {R(0), R(0)};
             continue;
         }
         const double lz = a.lamz[kz], ly = a.lamy[ky];
-        const double lamA = a.lamx[0] + ly + lz, lamB = a.lamx[M] + ly + lz;
-        const R sA = (ky == 0 && kz == 0) ? R(0) : R(a.inv_ntot / lamA);
+        const double lamA = lamA_of(m) + ly + lz, lamB = lamB_of(m) + ly + lz;
+        const bool zero = m == 0 && ky == 0 && kz == 0 && !a.regular;
+        const R sA = zero ? R(0) : R(a.inv_ntot / lamA);
         const R sB = R(a.inv_ntot / lamB);
         // (ky, kz)
         const Cx<R> z1 = tile.at(2 * i, kz), z2 = cconj(tile.at(2 * i + 1, kzn));
-        if (ky == 0 && kz == 0 && a.zero_mean_out)
+        if (zero && a.zero_mean_out)
             *a.zero_mean_out = double(z1.re) * a.inv_ntot;  // sum of f over the grid
         const Cx<R> A = cscale(cadd(z1, z2), R(0.5) * sA);
         const Cx<R> B = cscale(cmul_mi(csub(z1, z2)), R(0.5) * sB);
@@ -203,9 +222,9 @@ __global__ __launch_bounds__(ZPCfg<N>::NT) void k_z_per(ZArgs a0, int nspecial)
     auto gload3 = [&](int b, int n) -> Cx<R> { return cconj(tile.at(b, n)); };
     auto gstore3 = [&](int b, int n, Cx<R> v) {
         bool valid, dup;
-        const int col = col_of(b, valid, dup);
+        const size_t col = col_of(b, valid, dup);
         if (!valid || dup) return;
-        S[(size_t)n * plane + (size_t)col * M] = cconj(v);
+        S[(size_t)n * plane + col] = cconj(v);
     };
     fft_tile<R, N, NB, NT, true, Cf::PAD, true>(s_tw, 1, gload3, gstore3, tile);
 }
@@ -214,9 +233,14 @@ template <int N> static int run_zp(const ZArgs &a, hipStream_t s)
 {
     using Cf = ZPCfg<N>;
     const int npairs = a.ny / 2 + 1;
-    const int nspecial = a.ywall ? (a.ny + Cf::NB - 1) / Cf::NB
-                                 : (npairs + Cf::NB / 2 - 1) / (Cf::NB / 2);
-    const int nmain = (a.ny * a.M + Cf::NB - 1) / Cf::NB;
+    constexpr int NB = Cf::NB, NP = Cf::NB / 2;
+    int nspecial, nmain = (a.ny * a.M + NB - 1) / NB;
+    if (a.xwall) {
+        nspecial = a.ywall ? a.ny * ((a.M + NB - 1) / NB) : npairs * ((a.M + NP - 1) / NP);
+        nmain = 0;
+    } else {
+        nspecial = a.ywall ? (a.ny + NB - 1) / NB : (npairs + NP - 1) / NP;
+    }
     hipLaunchKernelGGL(k_z_per<N>, dim3(nspecial + nmain, a.batch ? a.nbatch : 1), dim3(Cf::NT),
                        0, s, a, nspecial);
     return (int)hipGetLastError();

@@ -45,7 +45,9 @@
 // The first `nspecial` workgroups take these virtual columns (pairs ky,
 // -ky) and recombine the results with a lane exchange.  With walls along y
 // the y coefficients are real-linear: column (0, ky) holds A + iB itself, and
-// the lanes of a pair take its real and imaginary parts.  The singular column
+// the lanes of a pair take its real and imaginary parts.  With walls along x
+// every column m holds two real x-modes (2m, 2m+1) as A + iB, so every column
+// takes this path (eigenvalues lam_x(2m), lam_x(2m+1)).  The singular column
 // (m, ky) = (0, 0) -- the zero wavenumber -- is solved in FP64 whatever the
 // precision: its right-hand side mean is removed (this removes mean(f), which
 // is reported), p is pinned by the zero-mean gauge, and the Neumann problem
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
     Cx<R> d[L];
     bool active;
     bool zero_lane = false;
-    int q = 0, ky = 0, kyn = 0, part = 0;
+    int q = 0, ky = 0, kyn = 0, part = 0, mm = 0;
     double s_d;  // s = -(lam_x + lam_y) dz^2 >= 0
     if (!special) {
         q = block_order((int)blockIdx.x - nspecial, (int)gridDim.x - nspecial, a.reverse) * W + w;
@@ -124,8 +126,11 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
             }
     } else {
         const int vc = (int)blockIdx.x * W + w;
-        const int pair = vc >> 1;
         part = vc & 1;
+        // walls along x: every column m holds the real x-modes 2m and 2m+1;
+        // lanes run along m (coalesced), two lanes per (m, ky pair)
+        const int pair = a.xwall ? (vc >> 1) / M : vc >> 1;
+        mm = a.xwall ? (vc >> 1) % M : 0;
         if (a.ywall) {
             // walls along y: the coefficients along y are real-linear, so
             // column (0, ky) holds the two real x-modes as A + iB with no
@@ -138,11 +143,11 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
             ky = active ? pair : 0;
             kyn = (ny - ky) % ny;
         }
-        zero_lane = active && pair == 0 && part == 0 && !a.regular;
-        const double lx = part ? a.lamx[M] : a.lamx[0];
+        zero_lane = active && mm == 0 && pair == 0 && part == 0 && !a.regular;
+        const double lx = a.xwall ? a.lamx[2 * mm + part] : (part ? a.lamx[M] : a.lamx[0]);
         s_d = (active && !zero_lane) ? -(lx + a.lamy[ky]) * a.dz2 : 1.0;
-        const PK_GLOBAL Cx<R> *c1 = S + (size_t)s * plane + (size_t)ky * M;
-        const PK_GLOBAL Cx<R> *c2 = S + (size_t)s * plane + (size_t)kyn * M;
+        const PK_GLOBAL Cx<R> *c1 = S + (size_t)s * plane + (size_t)ky * M + mm;
+        const PK_GLOBAL Cx<R> *c2 = S + (size_t)s * plane + (size_t)kyn * M + mm;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             const int k = s + i;
@@ -371,7 +376,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
         }
     } else {
         // lane pairs (A, B) of one ky are adjacent: exchange and recombine
-        PK_GLOBAL Cx<R> *col = S + (size_t)s * plane + (size_t)(part == 0 ? ky : kyn) * M;
+        PK_GLOBAL Cx<R> *col = S + (size_t)s * plane + (size_t)(part == 0 ? ky : kyn) * M + mm;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             const R ore = __shfl_xor(d[i].re, 1, 64);
@@ -396,8 +401,8 @@ static int run_zw(const ZArgs &a, hipStream_t s)
     const int C = (a.nz + L - 1) / L;
     if (C * W > MAXT) return -1;
     const int npairs = a.ywall ? a.ny : a.ny / 2 + 1;
-    const int nspecial = (2 * npairs + W - 1) / W;
-    const int nmain = (a.ny * a.M + W - 1) / W;
+    const int nspecial = (2 * npairs * (a.xwall ? a.M : 1) + W - 1) / W;
+    const int nmain = a.xwall ? 0 : (a.ny * a.M + W - 1) / W;
     const size_t shm = ((C * W * 4 * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double);
     hipLaunchKernelGGL((k_z_walls<L, W, MAXT>), dim3(nspecial + nmain, a.batch ? a.nbatch : 1),
                        dim3(W * C), shm, s, a, C, nspecial);

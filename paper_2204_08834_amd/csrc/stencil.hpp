@@ -56,7 +56,7 @@ struct MarchIdx {
     static constexpr int PER = (E + NT - 1) / NT;
     static constexpr bool EXACT = (E % NT) == 0;
 
-    int ny, nz, bc_z;
+    int ny, nz, bc_z, bc_x = 0;
     int j0, V;     // first y-row and number of valid rows of this block
     int jm, jn;    // halo rows: (j0 - 1) mod ny and (j0 + V) mod ny, or the wall row
     double sm, sn; // factors of the halo rows: -1 for the ghost of a Dirichlet wall
@@ -196,9 +196,14 @@ struct PlaneMarch : MarchIdx<M, TJ, NT> {
             if (valid(q)) {
                 const int t = row_of(q), h = pair_of(q);
                 const double2 ps = tile[t][h], pn = tile[t + 2][h];
-                const double pl = tile[t + 1][h == 0 ? M - 1 : h - 1].y;
-                const double pq = tile[t + 1][h == M - 1 ? 0 : h + 1].x;
                 const double2 c = pc[q], d = pd[q], u = pu[q];
+                // x neighbours; at walls along x the ghost is the wall cell
+                // (Neumann) or its negation (Dirichlet)
+                const int bx = this->bc_x;
+                const double pl = h != 0 ? tile[t + 1][h - 1].y
+                                         : (bx == 0 ? tile[t + 1][M - 1].y : (bx == 1 ? c.x : -c.x));
+                const double pq = h != M - 1 ? tile[t + 1][h + 1].x
+                                             : (bx == 0 ? tile[t + 1][0].x : (bx == 1 ? c.y : -c.y));
                 const double l0 = ax * (c.y - 2.0 * c.x + pl) + ay * (pn.x - 2.0 * c.x + ps.x) +
                                   az * (u.x - 2.0 * c.x + d.x);
                 const double l1 = ax * (pq - 2.0 * c.y + c.x) + ay * (pn.y - 2.0 * c.y + ps.y) +

@@ -68,8 +68,7 @@ def test_valid_descriptors(shape, bc):
     (dict(dz=float("nan")), P.ERR_INVALID_ARG),
     (dict(dz=float("inf")), P.ERR_INVALID_ARG),
     (dict(bc_z=3), P.ERR_INVALID_ARG),
-    (dict(bc_x=1), P.ERR_UNSUPPORTED),          # walls in x: not in this build
-    (dict(bc_x=2), P.ERR_UNSUPPORTED),
+    (dict(bc_x=3), P.ERR_INVALID_ARG),
     (dict(bc_y=3), P.ERR_INVALID_ARG),
     (dict(bc_x=5), P.ERR_INVALID_ARG),
     (dict(precision=3), P.ERR_INVALID_ARG),

@@ -268,3 +268,130 @@ def test_y_walls_device_loop_matches_host(mode):
         a, sa = gpu_solve(P, f, sp, bcs, "fp32_refine", "host")
         b, sb = gpu_solve(P, f, sp, bcs, "fp32_refine", mode)
         assert sa == sb and np.array_equal(a, b), bcs
+
+
+# --------------------------------------------------------------------------
+# walls along x (and any y, z): every boundary combination
+# --------------------------------------------------------------------------
+XCASES = [(16, 12, 10), (6, 3, 5), (2, 4, 3), (64, 8, 16), (24, 6, 12)]
+XBCS = [(bx, by, bz) for bx in (NEU, DIR) for by in (PER, NEU, DIR) for bz in (PER, NEU, DIR)]
+
+
+def _fft_len_ok(n):
+    while n % 2 == 0 and n > 1:
+        n //= 2
+    return n in (1, 3)
+
+
+@pytest.mark.parametrize("bcs", XBCS, ids=["".join("PND"[b] for b in c) for c in XBCS])
+def test_x_walls_match_oracle(orc, bcs):
+    P = _gpu()
+    for nx, ny, nz in XCASES:
+        if bcs[2] == PER and not _fft_len_ok(nz):
+            nz = 8
+        sp = (BOX[0] / nx, BOX[1] / ny, BOX[2] / nz)
+        f = inputs.random_rhs(nx, ny, nz, seed=3 * nx + ny + 7 * nz, zero_mean=False) + 0.3
+        p_ref = orc.solve(f, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+        res_ref, _ = orc.residual(f, p_ref, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+        k = kappa(nx, ny, nz, sp, bcs)
+        rtol = max(1e-10, 10 * res_ref)
+        for prec in ("fp64", "fp32_refine", "fp32"):
+            print(f"[walls] {nx}x{ny}x{nz} {bcs} {prec}", flush=True)
+            p, st = gpu_solve(P, f, sp, bcs, prec, rtol=rtol)
+            assert st["status"] == 0, (nx, ny, nz, prec, st)
+            if DIR in bcs:
+                assert st["rhs_mean"] == 0.0
+            else:
+                assert abs(st["rhs_mean"] - f.mean()) <= 1e-12
+            err = rel(p, p_ref)
+            if prec == "fp64":
+                assert err <= max(1e-12, 4 * k * 2.2e-16), (nx, ny, nz, err, k)
+            elif prec == "fp32_refine":
+                res, _ = orc.residual(f, p, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+                assert res <= rtol, (nx, ny, nz, res, rtol, st)
+            else:
+                assert err <= max(2e-5, 8 * k * 6e-8), (nx, ny, nz, err, k)
+
+
+@pytest.mark.parametrize("case", [((2048, 2, 3), (NEU, PER, NEU)), ((1536, 2, 4), (DIR, NEU, PER)),
+                                  ((512, 6, 9), (NEU, DIR, DIR)), ((768, 4, 4), (DIR, PER, DIR))])
+def test_x_walls_long_rows(orc, case):
+    """The longest wall rows (nx = 2048, radix-3 1536 and 768)."""
+    P = _gpu()
+    (nx, ny, nz), bcs = case
+    sp = (BOX[0] / nx, BOX[1] / ny, BOX[2] / nz)
+    f = inputs.random_rhs(nx, ny, nz, seed=nx, zero_mean=False)
+    p_ref = orc.solve(f, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+    res_ref, _ = orc.residual(f, p_ref, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+    k = kappa(nx, ny, nz, sp, bcs)
+    p, _ = gpu_solve(P, f, sp, bcs, "fp64")
+    assert rel(p, p_ref) <= max(1e-12, 4 * k * 2.2e-16), (rel(p, p_ref), k)
+    rtol = max(1e-10, 10 * res_ref)
+    q, st = gpu_solve(P, f, sp, bcs, "fp32_refine", rtol=rtol)
+    res, _ = orc.residual(f, q, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+    assert st["status"] == 0 and res <= rtol, (res, rtol, st)
+
+
+@pytest.mark.parametrize("bcs", [(NEU, NEU, NEU), (DIR, DIR, DIR), (NEU, PER, DIR), (DIR, NEU, PER)])
+def test_x_walls_eigenmode(bcs):
+    """Closed-form modes at 256 x 96 x 64 (a cavity and mixed boxes)."""
+    P = _gpu()
+    nx, ny, nz = 256, 96, 64
+    sp = (1.0 / nx, 0.75 / ny, 0.5 / nz)
+    a, b, c = 201, 40, 17
+    i = np.arange(nx) + 0.5
+    j = np.arange(ny) + 0.5
+    k = np.arange(nz) + 0.5
+
+    def mode(n, bc, m, x):
+        if bc == NEU:
+            return np.cos(np.pi * m * x / n)
+        if bc == DIR:
+            return np.sin(np.pi * (m + 1) * x / n)
+        return np.cos(2 * np.pi * m * x / n + 0.4)
+
+    f = (mode(nz, bcs[2], c, k)[:, None, None] * mode(ny, bcs[1], b, j)[None, :, None]
+         * mode(nx, bcs[0], a, i)[None, None, :])
+    lam = -(lam1(nx, sp[0], a, bcs[0]) + lam1(ny, sp[1], b, bcs[1]) + lam1(nz, sp[2], c, bcs[2]))
+    for prec, tol in (("fp64", 1e-12), ("fp32_refine", 1e-9)):
+        p, st = gpu_solve(P, f, sp, bcs, prec)
+        assert rel(p, f / lam) <= tol, (prec, bcs, rel(p, f / lam), st)
+
+
+@pytest.mark.parametrize("mode", ["graph", "device"])
+def test_x_walls_device_loop_matches_host(mode):
+    P = _gpu()
+    nx, ny, nz = 64, 48, 24
+    sp = (2.0 / nx, 2.0 / ny, 1.0 / nz)
+    f = inputs.random_rhs(nx, ny, nz, seed=6, zero_mean=False)
+    for bcs in ((NEU, NEU, NEU), (DIR, PER, PER), (NEU, DIR, NEU)):
+        a, sa = gpu_solve(P, f, sp, bcs, "fp32_refine", "host")
+        b, sb = gpu_solve(P, f, sp, bcs, "fp32_refine", mode)
+        assert sa == sb and np.array_equal(a, b), bcs
+
+
+def test_batch_of_boxes(orc):
+    """One batch of a periodic box, a channel (walls in y), a cavity (walls
+    everywhere) and a Dirichlet box of the same grid: shape groups per
+    boundary, each equal to its single solve and to the oracle."""
+    P = _gpu()
+    nx, ny, nz = 32, 24, 16
+    sp = (2.0 / nx, 2.0 / ny, 1.0 / nz)
+    kinds = [(PER, PER, PER), (PER, NEU, PER), (NEU, NEU, NEU), (DIR, DIR, DIR), (NEU, NEU, NEU)]
+    fs = [inputs.random_rhs(nx, ny, nz, seed=70 + b, zero_mean=False) for b in range(len(kinds))]
+    specs = [dict(nx=nx, ny=ny, nz=nz, dx=sp[0], dy=sp[1], dz=sp[2], bc_x=c[0], bc_y=c[1],
+                  bc_z=c[2]) for c in kinds]
+    for prec in ("fp64", "fp32_refine"):
+        rhs = [torch.from_numpy(f).cuda() for f in fs]
+        outs = [torch.empty_like(r) for r in rhs]
+        bp = P.BatchPlan(specs, prec)
+        rc, stats = bp.solve(rhs, outs, check=False)
+        torch.cuda.synchronize()
+        bp.close()
+        assert rc == 0
+        for f, c, o in zip(fs, kinds, outs):
+            single, _ = gpu_solve(P, f, sp, c, prec)
+            assert np.array_equal(o.cpu().numpy(), single), (prec, c)
+            if prec == "fp64":
+                ref = orc.solve(f, *sp, c[2], bc_x=c[0], bc_y=c[1])
+                assert rel(single, ref) <= 1e-12, c
