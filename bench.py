@@ -10,7 +10,8 @@ Prints one JSON line.  `value` is the FP32+refinement throughput in Mpoints/s;
 the plain FP64 solve of the same workload is timed beside it, and so is the
 whole projection step on the same grid (divergence of the face velocities
 fused into the first pass, the solve, the velocity correction and pressure
-update), under "projection".  The roofline
+update), under "projection", and wall-bounded boxes of the same grid (a
+cavity and a channel, cosine expansions along x and y), under "walls".  The roofline
 entry is for the kernel with the largest share of the FP32+refinement step,
 timed live with HIP events on the plan's stream.
 
@@ -181,6 +182,49 @@ def bench_project(prob, steps, warmup, tune):
                                                            * 1e-3) / 1e9}
                        for k, v in passes.items()}}
         print(f"[bench] projection {prec} {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    return res
+
+
+def bench_walls(steps, warmup, tune):
+    """Wall-bounded boxes on the rb512 grid (512x512x256, box 2x2x1): a
+    cavity with Neumann walls on every axis and a channel (periodic x, walls
+    in y and z), U(-1,1) right-hand side (seed 3); FP32 + refinement to 1e-10
+    and FP64, per-pass event timing."""
+    import torch
+    from paper_2204_08834_amd import inputs, poisson
+    nx, ny, nz = 512, 512, 256
+    sp = (2.0 / nx, 2.0 / ny, 1.0 / nz)
+    f = torch.from_numpy(inputs.random_rhs(nx, ny, nz, seed=3, zero_mean=False)).cuda()
+    out = torch.empty_like(f)
+    npts = nx * ny * nz
+    res = {}
+    for name, (bx, by, bz) in (("cavity_NNN", (1, 1, 1)), ("channel_PNN", (0, 1, 1))):
+        entry = {}
+        for prec in ("fp32_refine", "fp64"):
+            plan = poisson.Plan(nx, ny, nz, *sp, bz, prec, rtol=1e-10, max_refine=8,
+                                bc_x=bx, bc_y=by)
+            if tune:
+                plan.autotune()
+            for _ in range(warmup):
+                plan.solve(f, out)
+            ms, st = time_solves(plan, f, out, steps, sync_each=True)
+            plan.set_timing(True)
+            plan.reset_timing()
+            for _ in range(steps):
+                plan.solve(f, out)
+            passes = plan.timing()
+            plan.close()
+            step_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in passes.values()) / steps
+            entry[prec] = {
+                "ms_per_step": ms, "mpoints_s": npts / (ms * 1e-3) / 1e6,
+                "rel_residual": st["rel_residual"], "iterations": st["iterations"],
+                "model_hbm_gbs": step_bytes / (ms * 1e-3) / 1e9,
+                "passes": {k: {"avg_ms": v["total_ms"] / v["launches"],
+                               "gbs": v["bytes_per_launch"] / (v["total_ms"] / v["launches"]
+                                                               * 1e-3) / 1e9}
+                           for k, v in passes.items()}}
+            print(f"[bench] walls {name} {prec} {ms:.3f} ms/solve", file=sys.stderr, flush=True)
+        res[name] = entry
     return res
 
 
@@ -369,6 +413,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-project", action="store_true",
                     help="skip the projection step (divergence, solve, correction)")
+    ap.add_argument("--no-walls", action="store_true",
+                    help="skip the wall-bounded boxes (walls along x and y)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the captured-graph loop timing (profiling runs: its gated-off "
                          "launches would mix into the per-kernel statistics)")
@@ -534,6 +580,11 @@ def main():
         torch.cuda.empty_cache()
         result["projection"] = bench_project(prob, max(3, args.steps // 2), 2,
                                              not args.no_tune)
+
+    if not args.no_walls:
+        print("[bench] wall-bounded boxes", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        result["walls"] = bench_walls(max(3, args.steps // 2), 2, not args.no_tune)
 
     if not args.no_batch:
         print("[bench] batched mixed-64 workload", file=sys.stderr, flush=True)

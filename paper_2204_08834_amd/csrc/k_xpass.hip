@@ -133,12 +133,11 @@ __device__ __forceinline__ Cx<T> wall_load(const PK_GLOBAL T *row, int nx, int m
 // nx-entry twiddle table `tw` are the caller's; no trailing barrier.
 // P0 = 1: the tile already holds the output of pass 0 (Pass0Regs), the
 // transform continues from pass 1 (needs at least two passes).
-template <int M, int NB, int NT, bool GL_LDS, int P0 = 0, class GL, class OUT>
+template <int M, int NB, int NT, bool GL_LDS, int P0 = 0, bool XW = false, class GL, class OUT>
 __device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R, M, NB, false, 0> tile,
-                                          OUT &out, int xbc = 0,
+                                          OUT &out, bool sine = false,
                                           const PK_GLOBAL Cx<R> *w4 = nullptr)
 {
-    const bool sine = xbc == 2;
     auto lstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
     constexpr RPlan pl = make_rplan(M);
     static_assert(P0 == 0 || pl.count >= 2, "");
@@ -180,7 +179,7 @@ __device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R,
             auto emit = [&](int m, Cx<R> zm, Cx<R> zc) {
                 Cx<R> xm, xc;
                 split_pair(zm, zc, tw[m], xm, xc);
-                if (xbc) {
+                if constexpr (XW) {
                     wall_emit(Sreal, 2 * M, m, xm, w4, sine);
                     if (2 * m != M) wall_emit(Sreal, 2 * M, M - m, xc, w4, sine);
                 } else {
@@ -191,7 +190,7 @@ __device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R,
             if (pp == 0) {
                 // butterfly 0: m = r NJ; m = 0 packs X(0) + i X(M)
                 const R X0 = v1[0].re + v1[0].im, XM = v1[0].re - v1[0].im;
-                if (xbc) {
+                if constexpr (XW) {
                     Sreal[sine ? 2 * M - 1 : 0] = X0;
                     Sreal[sine ? M - 1 : M] = XM * w4[M].re;
                 } else {
@@ -221,7 +220,7 @@ __device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R,
             const Cx<R> zm = tile.at(b, m);
             if (m == 0) {
                 const R X0 = zm.re + zm.im, XM = zm.re - zm.im;
-                if (xbc) {
+                if constexpr (XW) {
                     Sreal[sine ? 2 * M - 1 : 0] = X0;
                     Sreal[sine ? M - 1 : M] = XM * w4[M].re;
                 } else {
@@ -230,7 +229,7 @@ __device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R,
             } else {
                 Cx<R> xm, xc;
                 split_pair(zm, tile.at(b, M - m), tw[m], xm, xc);
-                if (xbc)
+                if constexpr (XW)
                     wall_emit(Sreal, 2 * M, m, xm, w4, sine);  // C[m] and C[nx-m]
                 else
                     put(Sr + m, xm);
@@ -244,7 +243,7 @@ __device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R,
 // (G = gridDim.x) and loads the next block's pass-0 inputs into registers
 // right after it has stored the current block's pass 0, so the HBM reads of
 // block i+1 overlap the LDS passes and spectrum writes of block i.
-template <int M>
+template <int M, bool XW>
 __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
 {
     if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
@@ -270,32 +269,68 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
     Tile tile{s_tile};
     PK_GLOBAL Cx<R> *S = gbl((Cx<R> *)a.S);
     const PK_GLOBAL double *gf = gbl(a.f);
-    const int xbc = a.bc_x;
-    const PK_GLOBAL Cx<R> *w4 = xbc ? gbl((const Cx<R> *)a.tw4x) : nullptr;
+    const bool sine = a.bc_x == 2;
+    const PK_GLOBAL Cx<R> *w4 = XW ? gbl((const Cx<R> *)a.tw4x) : nullptr;
     auto loader = [&](int row0) {
         return [&, row0](int b, int n) -> Cx<R> {
             const int row = row0 + b;
             if (row >= nrows) return {R(0), R(0)};
-            if (xbc) {
+            if constexpr (XW) {
                 // walls: the reordered row v[j] = x[r(j)] (sines: signed)
                 const int i0 = wall_index(2 * n, NX), i1 = wall_index(2 * n + 1, NX);
                 double f0 = gf[(size_t)row * NX + i0], f1 = gf[(size_t)row * NX + i1];
                 acc0 += f0 + f1;
-                if (xbc == 2) {
+                if (sine) {
                     f0 = (i0 & 1) ? -f0 : f0;
                     f1 = (i1 & 1) ? -f1 : f1;
                 }
                 return {R(f0), R(f1)};
-            }
+            } else {
             // f is read once (streaming loads measured 16 % faster for the
             // FP64 pass; the residual marches, which also read f, lost 1-3 %)
-            const double2 fv = ld_stream(gf + (size_t)row * NX + 2 * n);
-            acc0 += fv.x + fv.y;
-            return {R(fv.x), R(fv.y)};
+                const double2 fv = ld_stream(gf + (size_t)row * NX + 2 * n);
+                acc0 += fv.x + fv.y;
+                return {R(fv.x), R(fv.y)};
+            }
         };
     };
     constexpr RPlan pl = make_rplan(M);
-    if constexpr (pl.count >= 2) {
+    if constexpr (XW) {
+        // walls: contiguous row loads, stored reordered into the LDS tile
+        // (x[2h] -> v[h], x[2h+1] -> v[nx-1-h], negated for sines), then
+        // the transform from LDS
+        for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+            const int row0 = block_order(blk, nblk, a.reverse) * NB;
+            __syncthreads();  // tw table loaded / previous block done with the tile
+            // all loads of the block in flight first, then the LDS stores
+            constexpr int PERW = (NB * M + NT - 1) / NT;
+            double2 fv[PERW];
+#pragma unroll
+            for (int q = 0; q < PERW; ++q) {
+                const int e = threadIdx.x + q * NT;
+                const int row = row0 + e / M;
+                fv[q] = {0.0, 0.0};
+                if (e < NB * M && row < nrows) fv[q] = ld_stream(gf + (size_t)row * NX + 2 * (e % M));
+            }
+#pragma unroll
+            for (int q = 0; q < PERW; ++q) {
+                const int e = threadIdx.x + q * NT;
+                if (e >= NB * M) continue;
+                const int b = e / M, h = e % M;
+                acc0 += fv[q].x + fv[q].y;
+                R *trow = (R *)&tile.at(b, 0);
+                trow[h] = R(fv[q].x);
+                trow[NX - 1 - h] = R(sine ? -fv[q].y : fv[q].y);
+            }
+            __syncthreads();
+            auto gload = [&](int b, int n) -> Cx<R> { return tile.at(b, n); };
+            auto out = [&](int b) -> PK_GLOBAL Cx<R> * {
+                const int row = row0 + b;
+                return row < nrows ? S + (size_t)row * M : nullptr;
+            };
+            x_forward<M, NB, NT, true, 0, true>(s_tw, gload, tile, out, sine, w4);
+        }
+    } else if constexpr (pl.count >= 2) {
         Pass0Regs<R, M, NB, NT, false, 0, 0> in;
         int blk = blockIdx.x;
         if (blk < nblk) {
@@ -317,7 +352,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
                 return row < nrows ? S + (size_t)row * M : nullptr;
             };
             auto gnone = [&](int, int) -> Cx<R> { return {R(0), R(0)}; };
-            x_forward<M, NB, NT, false, 1>(s_tw, gnone, tile, out, xbc, w4);
+            x_forward<M, NB, NT, false, 1, XW>(s_tw, gnone, tile, out, sine, w4);
         }
     } else {
         __syncthreads();
@@ -328,7 +363,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
                 const int row = row0 + b;
                 return row < nrows ? S + (size_t)row * M : nullptr;
             };
-            x_forward<M, NB, NT, false>(s_tw, gl, tile, out, xbc, w4);
+            x_forward<M, NB, NT, false, 0, XW>(s_tw, gl, tile, out, sine, w4);
             __syncthreads();
         }
     }
@@ -355,7 +390,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
 // (f - mu)^2 and p go to `partials`.  r never touches HBM.
 constexpr int XR_NT = 256;
 
-template <int M>
+template <int M, bool XW>
 __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
 {
     if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
@@ -393,9 +428,9 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
     m.mu = (a.sum_f && !a.regular) ? (*a.sum_f) * a.inv_n : 0.0;
     m.tile = (double2(*)[M])s_buf;
     m.setup(jb, a.ny, a.nz, a.bc_z, a.bc_y);
-    m.bc_x = a.bc_x;
-    const int xbc = a.bc_x;
-    const PK_GLOBAL Cx<R> *w4 = xbc ? gbl((const Cx<R> *)a.tw4x) : nullptr;
+    m.bc_x = XW ? a.bc_x : 0;
+    const bool sine = a.bc_x == 2;
+    const PK_GLOBAL Cx<R> *w4 = XW ? gbl((const Cx<R> *)a.tw4x) : nullptr;
     load_table(s_tw, (const Cx<R> *)a.tw, NX);
     m.start(k0);
 
@@ -417,11 +452,11 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
         for (int q = 0; q < Mar::PER; ++q) {
             if (!m.valid(q)) continue;
             const int t = m.row_of(q), h = m.pair_of(q);
-            if (xbc) {
+            if constexpr (XW) {
                 // walls: x[2h] -> v[h], x[2h+1] -> v[nx-1-h] (negated for sines)
                 R *trow = (R *)&tile.at(t, 0);
                 trow[h] = rr[q].re;
-                trow[NX - 1 - h] = xbc == 2 ? -rr[q].im : rr[q].im;
+                trow[NX - 1 - h] = sine ? -rr[q].im : rr[q].im;
             } else {
                 tile.at(t, h) = rr[q];
             }
@@ -431,7 +466,7 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
         const size_t rowk = (size_t)k * a.ny + m.j0;
         const int V = m.V;
         auto out = [&](int b) -> PK_GLOBAL Cx<R> * { return b < V ? S + (rowk + b) * M : nullptr; };
-        x_forward<M, TJ, NT, true>(s_tw, gload, tile, out, xbc, w4);
+        x_forward<M, TJ, NT, true, 0, XW>(s_tw, gload, tile, out, sine, w4);
     }
     block_sum3(acc0, acc1, acc2, s_red);
     if (threadIdx.x == 0) {
@@ -524,7 +559,7 @@ __global__ __launch_bounds__(XD_NT) void k_x_div(XFwdArgs a0)
     }
 }
 
-template <int M, bool ACC>
+template <int M, bool ACC, bool XW>
 __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
 {
     if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
@@ -551,14 +586,13 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
 
     const PK_GLOBAL Cx<R> *S = gbl((const Cx<R> *)a.S);
     PK_GLOBAL double *gp = gbl(a.p);
-    const int xbc = a.bc_x;
-    const bool sine = xbc == 2;
-    const PK_GLOBAL Cx<R> *w4 = xbc ? gbl((const Cx<R> *)a.tw4x) : nullptr;
+    const bool sine = a.bc_x == 2;
+    const PK_GLOBAL Cx<R> *w4 = XW ? gbl((const Cx<R> *)a.tw4x) : nullptr;
     auto gstore = [&](int b, int n, Cx<R> v) {
         const int row = row0 + b;
         if (row >= nrows) return;
         double2 o = {double(v.re), -double(v.im)};
-        if (xbc) {
+        if constexpr (XW) {
             // walls: v[j] goes back to x[r(j)] (negated at odd x for sines)
             const int i0 = wall_index(2 * n, NX), i1 = wall_index(2 * n + 1, NX);
             if (sine) {
@@ -585,10 +619,49 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
     // spectrum value m of a row: the packed half spectrum, or for walls the
     // inverse input formed from the cosine / sine coefficients
     auto xval = [&](const PK_GLOBAL Cx<R> *sr, int m) -> Cx<R> {
-        if (xbc) return wall_load((const PK_GLOBAL R *)sr, NX, m, w4, sine);
-        return sr[m];
+        if constexpr (XW)
+            return wall_load((const PK_GLOBAL R *)sr, NX, m, w4, sine);
+        else
+            return sr[m];
     };
     Tile tile{s_tile};
+    // walls: the tile holds conj(v) of each row in transform order; write
+    // x[2h] = v[h], x[2h+1] = v[nx-1-h] (negated for sines) with contiguous
+    // stores (or accumulate)
+    auto wall_rows_out = [&]() {
+        __syncthreads();
+        constexpr int PERW = (NB * M + NT - 1) / NT;
+        double2 old[PERW];
+        if constexpr (ACC) {
+            // all loads of the previous iterate in flight first
+#pragma unroll
+            for (int q = 0; q < PERW; ++q) {
+                const int e = threadIdx.x + q * NT;
+                const int row = row0 + e / M;
+                old[q] = {0.0, 0.0};
+                if (e < NB * M && row < nrows) old[q] = ld_stream(gp + (size_t)row * NX + 2 * (e % M));
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PERW; ++q) {
+            const int e = threadIdx.x + q * NT;
+            const int b = e / M, h = e % M;
+            const int row = row0 + b;
+            if (e >= NB * M || row >= nrows) continue;
+            const R *trow = (const R *)&tile.at(b, 0);
+            // the tile holds conj(z), z[j] = v[2j] + i v[2j+1]
+            const int j1 = NX - 1 - h;
+            const double v0 = (h & 1) ? -double(trow[h]) : double(trow[h]);
+            double v1 = (j1 & 1) ? -double(trow[j1]) : double(trow[j1]);
+            if (sine) v1 = -v1;
+            double2 o = {v0, v1};
+            if constexpr (ACC) {
+                o.x += old[q].x - pmean;
+                o.y += old[q].y - pmean;
+            }
+            st_stream(gp + (size_t)row * NX + 2 * h, o);
+        }
+    };
     // reversed radix order: the small radix first gives more butterfly pairs
     // per row for the fused first pass
     constexpr RPlan pl = get_rplan(M, 1);
@@ -647,8 +720,17 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
         }
         __syncthreads();
         auto gnone = [&](int, int) -> Cx<R> { return {R(0), R(0)}; };
-        fft_passes<R, M, NB, NT, false, C::PAD, false, 1, pl.count, 1>(s_tw, 2, gnone, gstore,
-                                                                       tile);
+        if constexpr (XW) {
+            // the last pass stores back into the tile (it synchronises between
+            // its reads and writes); rows are then written contiguously
+            auto tstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
+            fft_passes<R, M, NB, NT, false, C::PAD, false, 1, pl.count, 1>(s_tw, 2, gnone,
+                                                                           tstore, tile);
+            wall_rows_out();
+        } else {
+            fft_passes<R, M, NB, NT, false, C::PAD, false, 1, pl.count, 1>(s_tw, 2, gnone,
+                                                                           gstore, tile);
+        }
     } else {
         auto gload = [&](int b, int n) -> Cx<R> {
             const int row = row0 + b;
@@ -662,7 +744,13 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
             merge_pair(xval(sr, n), xval(sr, M - n), s_tw[n], zm, zc);
             return zm;
         };
-        fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, gstore, tile);
+        if constexpr (XW) {
+            auto tstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
+            fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, tstore, tile);
+            wall_rows_out();
+        } else {
+            fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, gstore, tile);
+        }
     }
 }
 
@@ -678,7 +766,7 @@ template <int M> static int blocks_x(int ny, int nz, int residual, int kr_max)
 
 // workgroups of the persistent plain pass: as many as are resident on the
 // device at once (shared among the problems of a batched launch)
-template <int M> static int grid_x_fwd(int nblk, int nbatch)
+template <int M, bool XW> static int grid_x_fwd(int nblk, int nbatch)
 {
     static int resident[64] = {0};
     int dev = 0;
@@ -686,7 +774,7 @@ template <int M> static int grid_x_fwd(int nblk, int nbatch)
     int &r = resident[dev & 63];
     if (r == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_x_fwd<M>, XCfg<M>::NT, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_x_fwd<M, XW>, XCfg<M>::NT, 0) !=
                 hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             per_cu < 1 || cus < 1) {
@@ -703,8 +791,10 @@ template <int M> static int grid_x_fwd(int nblk, int nbatch)
 
 template <int M> static int run_x_fwd(const XFwdArgs &a, hipStream_t s, int *nblocks_out)
 {
+    const bool xw = a.bc_x != 0;
     int nb = blocks_x<M>(a.ny, a.nz, a.residual, a.kr_max);
-    if (!a.residual) nb = grid_x_fwd<M>(nb, a.batch ? a.nbatch : 1);
+    if (!a.residual) nb = xw ? grid_x_fwd<M, true>(nb, a.batch ? a.nbatch : 1)
+                             : grid_x_fwd<M, false>(nb, a.batch ? a.nbatch : 1);
     if (nblocks_out) *nblocks_out = nb;
     const dim3 grid(nb, a.batch ? a.nbatch : 1);
     if (a.residual == 2) {
@@ -712,12 +802,18 @@ template <int M> static int run_x_fwd(const XFwdArgs &a, hipStream_t s, int *nbl
         hipLaunchKernelGGL(k_x_div<M>, dim3(nb), dim3(XD_NT), 0, s, a);
     } else if (a.residual) {
         // the refinement transforms its residual in FP32 only
-        if constexpr (sizeof(R) == 4)
-            hipLaunchKernelGGL(k_x_res<M>, grid, dim3(XR_NT), 0, s, a);
-        else
+        if constexpr (sizeof(R) == 4) {
+            if (xw)
+                hipLaunchKernelGGL((k_x_res<M, true>), grid, dim3(XR_NT), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_x_res<M, false>), grid, dim3(XR_NT), 0, s, a);
+        } else {
             return -1;
+        }
+    } else if (xw) {
+        hipLaunchKernelGGL((k_x_fwd<M, true>), grid, dim3(XCfg<M>::NT), 0, s, a);
     } else {
-        hipLaunchKernelGGL(k_x_fwd<M>, grid, dim3(XCfg<M>::NT), 0, s, a);
+        hipLaunchKernelGGL((k_x_fwd<M, false>), grid, dim3(XCfg<M>::NT), 0, s, a);
     }
     return (int)hipGetLastError();
 }
@@ -727,10 +823,18 @@ template <int M> static int run_x_inv(const XInvArgs &a, hipStream_t s)
     const int nrows = a.ny * a.nz;
     const int nb = (nrows + XCfg<M>::NB - 1) / XCfg<M>::NB;
     const dim3 grid(nb, a.batch ? a.nbatch : 1);
-    if (a.accumulate)
-        hipLaunchKernelGGL((k_x_inv<M, true>), grid, dim3(XCfg<M>::NT), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_x_inv<M, false>), grid, dim3(XCfg<M>::NT), 0, s, a);
+    const bool xw = a.bc_x != 0;
+    if (a.accumulate) {
+        if (xw)
+            hipLaunchKernelGGL((k_x_inv<M, true, true>), grid, dim3(XCfg<M>::NT), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_x_inv<M, true, false>), grid, dim3(XCfg<M>::NT), 0, s, a);
+    } else {
+        if (xw)
+            hipLaunchKernelGGL((k_x_inv<M, false, true>), grid, dim3(XCfg<M>::NT), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_x_inv<M, false, false>), grid, dim3(XCfg<M>::NT), 0, s, a);
+    }
     return (int)hipGetLastError();
 }
 

@@ -81,22 +81,25 @@ __global__ __launch_bounds__((YCfg<N, V>::NT)) void k_y(YArgs a0)
 //                    w_k = exp(-i pi k / (2n));
 //   forward sine:    the cosine transform of (-1)^j c[j], read out reversed
 //                    (S[k] = C'[n-1-k]);
-//   inverse cosine:  W[k] = conj(w_k) (C[k] - i C[n-k]),  C[n] = 0,
+//   inverse cosine:  W[k] = conj(w_k) (C[k] - i C[n-k]),  C[n] = 0 (formed as
+//                    the FFT's first pass loads it),
 //                    v = FFT^-1(W) (unnormalised),  c[r(j)] = v[j]  (times n,
 //                    like the periodic pass: 1/ny is applied in the z step);
 //   inverse sine:    the inverse cosine transform of C'[k] = S[n-1-k], times
 //                    (-1)^j.
-// The forward FFT writes into a second LDS tile, from which the pairs
-// (k, n-k) are combined and stored; the inverse forms W in place in LDS by
-// pairs and transforms from there.  Two tiles: half the x-wavenumbers per
-// workgroup of the periodic pass (64-byte row runs at most sizes).
+// The forward FFT's last pass writes back into its LDS tile (the pass
+// synchronises between its reads and its writes), from which the pairs
+// (k, n-k) are combined and stored.  Row runs of 128 bytes as in the periodic
+// pass, narrower only where the tile and two N-entry tables would not fit.
 template <int N> struct YWCfg {
     static constexpr int NB0 = sizeof(R) == 4 ? 16 : 8;
-    // two NB x N tiles (plus padding) and two N-entry tables within ~150 KB of LDS
+    // one NB x N tile (plus padding) and two N-entry tables within ~150 KB of LDS
     static constexpr int ELEMS = 150 * 1024 / (int)sizeof(Cx<R>);
-    static constexpr int NBMAX = ELEMS / (2 * N) - 2;  // 2 N (NB + PAD) + 2 N <= ELEMS
+    static constexpr int NBMAX = ELEMS / N - 2;  // N (NB + PAD) + 2 N <= ELEMS
     static constexpr int NB1 = NB0 < NBMAX ? NB0 : NBMAX;
-    static constexpr int NB = NB1 >= 16 ? 16 : (NB1 >= 8 ? 8 : (NB1 >= 4 ? 4 : (NB1 >= 2 ? 2 : 1)));
+    static constexpr int NB2 = NB1 >= 16 ? 16 : (NB1 >= 8 ? 8 : (NB1 >= 4 ? 4 : (NB1 >= 2 ? 2 : 1)));
+    // the padding column of tiles with 8 or more lines must fit as well
+    static constexpr int NB = (NB2 >= 8 && N * (NB2 + 3) > ELEMS) ? NB2 / 2 : NB2;
     static constexpr int NT = pick_nt(NB * N, sizeof(R) == 4 ? 16 : 8);
     static constexpr int PAD = (NB >= 8) ? 1 : 0;
 };
@@ -113,7 +116,6 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
     constexpr int NB = C::NB, NT = C::NT;
     using Tile = LdsTile<R, N, NB, true, C::PAD>;
     __shared__ Cx<R> s_tile[Tile::elems];
-    __shared__ Cx<R> s_out[INV ? 1 : Tile::elems];
     __shared__ Cx<R> s_tw[N];
     __shared__ Cx<R> s_w4[N];  // exp(-i pi k / (2n))
 
@@ -131,7 +133,7 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
     PK_GLOBAL Cx<R> *base = gbl((Cx<R> *)a.S) + (size_t)k * N * M + m0;
     Tile tile{s_tile};
     if constexpr (!INV) {
-        Tile out{s_out};
+        Tile out = tile;  // the last pass stores back into the tile
         auto gload = [&](int b, int n) -> Cx<R> {
             if (m0 + b >= M) return {R(0), R(0)};
             const int r = wall_reorder(n, N);
@@ -150,41 +152,26 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
             put(base + (size_t)(sine ? N - 1 - kk : kk) * M + b, c);
         }
     } else {
-        // coefficients into LDS (read reversed for the sine basis)
-        for (int e = threadIdx.x; e < NB * N; e += NT) {
-            const int b = e % NB, kk = e / NB;
-            Cx<R> v = {R(0), R(0)};
-            if (m0 + b < M) {
-                const Cx<R> g = base[(size_t)(sine ? N - 1 - kk : kk) * M + b];
-                v = {g.re, g.im};
-            }
-            tile.at(b, kk) = v;
-        }
-        __syncthreads();
-        // W by pairs (k, n-k) in place: W[k] = conj(w_k) (C[k] - i C[n-k])
-        constexpr int NPAIR = N / 2 + 1;
-        for (int e = threadIdx.x; e < NB * NPAIR; e += NT) {
-            const int b = e % NB, kk = e / NB;
-            const int kc = N - kk;  // N for kk = 0: C[N] = 0
-            const Cx<R> c1 = tile.at(b, kk);
-            const Cx<R> c2 = (kk == 0) ? Cx<R>{R(0), R(0)} : tile.at(b, kc == N ? 0 : kc);
-            const Cx<R> w1 = cconj(s_w4[kk]);
-            tile.at(b, kk) = cmul(w1, csub(c1, cmul_pi(c2)));
-            if (kk != 0 && kc != kk) {
-                const Cx<R> w2 = cconj(s_w4[kc]);
-                tile.at(b, kc) = cmul(w2, csub(c2, cmul_pi(c1)));
-            }
-        }
-        __syncthreads();
-        // inverse FFT as conj(FFT(conj)), from LDS; store un-reordered
-        auto gload = [&](int b, int n) -> Cx<R> { return cconj(tile.at(b, n)); };
+        // W[k] = conj(w_k) (C[k] - i C[n-k]) formed in pass 0's loads from the
+        // coefficient rows k and n-k (C[n] = 0; read reversed for sines); the
+        // inverse FFT as conj(FFT(conj))
+        auto coef = [&](int b, int kk) -> Cx<R> {
+            if (kk >= N) return {R(0), R(0)};
+            const Cx<R> g = base[(size_t)(sine ? N - 1 - kk : kk) * M + b];
+            return {g.re, g.im};
+        };
+        auto gload = [&](int b, int n) -> Cx<R> {
+            if (m0 + b >= M) return {R(0), R(0)};
+            const Cx<R> c1 = coef(b, n), c2 = n == 0 ? Cx<R>{R(0), R(0)} : coef(b, N - n);
+            return cconj(cmul(cconj(s_w4[n]), csub(c1, cmul_pi(c2))));
+        };
         auto gstore = [&](int b, int n, Cx<R> v) {
             if (m0 + b >= M) return;
             const int r = wall_reorder(n, N);
             const R sg = (sine && (r & 1)) ? R(-1) : R(1);
             put(base + (size_t)r * M + b, Cx<R>{sg * v.re, -sg * v.im});
         };
-        fft_tile<R, N, NB, NT, true, C::PAD, true>(s_tw, 1, gload, gstore, tile);
+        fft_tile<R, N, NB, NT, true, C::PAD, false>(s_tw, 1, gload, gstore, tile);
     }
 }
 

@@ -125,44 +125,53 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
                 d[i] = Cx<R>{R(0), R(0)};
             }
     } else {
-        const int vc = (int)blockIdx.x * W + w;
-        part = vc & 1;
-        // walls along x: every column m holds the real x-modes 2m and 2m+1;
-        // lanes run along m (coalesced), two lanes per (m, ky pair)
-        const int pair = a.xwall ? (vc >> 1) / M : vc >> 1;
-        mm = a.xwall ? (vc >> 1) % M : 0;
+        // two-mode columns: lanes [0, W/2) take part A, lanes [W/2, W) part B
+        // of the same (m, ky pair), so each half reads a contiguous run of m
+        // (walls along x) and the halves exchange values with a lane shuffle
+        constexpr int H = W / 2 > 0 ? W / 2 : 1;
+        part = w >= H ? 1 : 0;
+        const int mi = w - part * H;
+        const int sb = (int)blockIdx.x;
+        const int mblk = a.xwall ? (M + H - 1) / H : 1;
+        const int pair = a.xwall ? sb / mblk : sb * H + mi;
+        mm = a.xwall ? (sb % mblk) * H + mi : 0;
         if (a.ywall) {
             // walls along y: the coefficients along y are real-linear, so
-            // column (0, ky) holds the two real x-modes as A + iB with no
-            // partner column: part 0 solves Re, part 1 solves Im
-            active = pair < ny;
+            // column (m, ky) holds the two real x-modes as A + iB with no
+            // partner column: part A solves Re, part B solves Im
+            active = pair < ny && mm < M;
             ky = active ? pair : 0;
             kyn = ky;
         } else {
-            active = pair <= ny / 2;
+            active = pair <= ny / 2 && mm < M;
             ky = active ? pair : 0;
             kyn = (ny - ky) % ny;
         }
         zero_lane = active && mm == 0 && pair == 0 && part == 0 && !a.regular;
-        const double lx = a.xwall ? a.lamx[2 * mm + part] : (part ? a.lamx[M] : a.lamx[0]);
+        const double lx = a.xwall ? a.lamx[2 * (active ? mm : 0) + part]
+                                  : (part ? a.lamx[M] : a.lamx[0]);
         s_d = (active && !zero_lane) ? -(lx + a.lamy[ky]) * a.dz2 : 1.0;
-        const PK_GLOBAL Cx<R> *c1 = S + (size_t)s * plane + (size_t)ky * M + mm;
-        const PK_GLOBAL Cx<R> *c2 = S + (size_t)s * plane + (size_t)kyn * M + mm;
+        // part A reads column ky, part B column -ky (the same with walls along y)
+        const PK_GLOBAL Cx<R> *col =
+            S + (size_t)s * plane + (size_t)(part ? kyn : ky) * M + (active ? mm : 0);
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             const int k = s + i;
-            Cx<R> v = {R(0), R(0)};
+            Cx<R> own = {R(0), R(0)};
             if (active && k < nz) {
-                const Cx<R> z1 = c1[(size_t)i * plane];
-                if (a.ywall) {
-                    v = part ? Cx<R>{z1.im, R(0)} : Cx<R>{z1.re, R(0)};
-                } else {
-                    const Cx<R> z2 = cconj(c2[(size_t)i * plane]);
-                    v = part ? cscale(cmul_mi(csub(z1, z2)), R(0.5))
-                             : cscale(cadd(z1, z2), R(0.5));
-                }
+                const Cx<R> g = col[(size_t)i * plane];
+                own = {g.re, g.im};
             }
-            d[i] = v;
+            Cx<R> v;
+            if (a.ywall) {
+                v = part ? Cx<R>{own.im, R(0)} : Cx<R>{own.re, R(0)};
+            } else {
+                const Cx<R> oth = {__shfl_xor(own.re, H, 64), __shfl_xor(own.im, H, 64)};
+                const Cx<R> z1 = part ? oth : own;           // Z(ky)
+                const Cx<R> z2 = cconj(part ? own : oth);    // conj Z(-ky)
+                v = part ? cscale(cmul_mi(csub(z1, z2)), R(0.5)) : cscale(cadd(z1, z2), R(0.5));
+            }
+            d[i] = (active && k < nz) ? v : Cx<R>{R(0), R(0)};
         }
     }
 #pragma unroll
@@ -375,12 +384,15 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
                 if (s + i < nz) col[(size_t)i * plane] = d[i];
         }
     } else {
-        // lane pairs (A, B) of one ky are adjacent: exchange and recombine
-        PK_GLOBAL Cx<R> *col = S + (size_t)s * plane + (size_t)(part == 0 ? ky : kyn) * M + mm;
+        // the lanes of parts A and B of one (m, ky pair) are W/2 apart:
+        // exchange and recombine
+        constexpr int H = W / 2 > 0 ? W / 2 : 1;
+        PK_GLOBAL Cx<R> *col =
+            S + (size_t)s * plane + (size_t)(part == 0 ? ky : kyn) * M + (active ? mm : 0);
 #pragma unroll
         for (int i = 0; i < L; ++i) {
-            const R ore = __shfl_xor(d[i].re, 1, 64);
-            const R oim = __shfl_xor(d[i].im, 1, 64);
+            const R ore = __shfl_xor(d[i].re, H, 64);
+            const R oim = __shfl_xor(d[i].im, H, 64);
             const int k = s + i;
             if (active && k < nz) {
                 if (part == 0) {
@@ -401,7 +413,8 @@ static int run_zw(const ZArgs &a, hipStream_t s)
     const int C = (a.nz + L - 1) / L;
     if (C * W > MAXT) return -1;
     const int npairs = a.ywall ? a.ny : a.ny / 2 + 1;
-    const int nspecial = (2 * npairs * (a.xwall ? a.M : 1) + W - 1) / W;
+    constexpr int H = W / 2 > 0 ? W / 2 : 1;
+    const int nspecial = a.xwall ? npairs * ((a.M + H - 1) / H) : (npairs + H - 1) / H;
     const int nmain = a.xwall ? 0 : (a.ny * a.M + W - 1) / W;
     const size_t shm = ((C * W * 4 * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double);
     hipLaunchKernelGGL((k_z_walls<L, W, MAXT>), dim3(nspecial + nmain, a.batch ? a.nbatch : 1),
@@ -423,7 +436,10 @@ int PK_SUFFIX(launch_z_walls)(const ZArgs &a, hipStream_t s)
     const int nz = a.nz;
     constexpr bool F32 = sizeof(R) == 4;
     const bool c8 = a.variant == 1 || a.variant == 3;
-    const bool wide = a.variant >= 2;
+    // walls along x: every column is a two-mode column whose lane halves
+    // read W/2 consecutive m each, so only the wide tiles give full
+    // 128-byte runs (narrow ones split cache lines across dies)
+    const bool wide = a.variant >= 2 || a.xwall;
     if (nz <= 64) return run_zw<8, 32, 256>(a, s);
     if (!c8) {
         if constexpr (F32) {

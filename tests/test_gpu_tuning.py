@@ -89,7 +89,7 @@ def test_autotune_choices_solve_and_are_reused(orc, tmp_path, monkeypatch):
         q, st, desc3 = _solve(prob.f, sp, prob.bc_z, "fp32_refine", tune=True)
         assert "tuned" in desc3 and st["rel_residual"] <= 1e-10
     text = (tmp_path / "tune.txt").read_text()
-    assert "f64 96 96 48 1" in text and "f32 64 64 64 0" in text
+    assert "f64 96 96 48 001" in text and "f32 64 64 64 000" in text
 
 
 def test_batch_autotune_and_describe():
