@@ -97,7 +97,7 @@ __device__ __forceinline__ int wall_index(int j, int nx) { return 2 * j < nx ? 2
 
 template <typename T>
 __device__ __forceinline__ void wall_emit(PK_GLOBAL T *row, int nx, int m, Cx<T> X,
-                                          const PK_GLOBAL Cx<T> *w4, bool sine)
+                                          const Cx<T> *w4, bool sine)
 {
     const Cx<T> wa = w4[m];
     row[sine ? nx - 1 - m : m] = wa.re * X.re - wa.im * X.im;  // Re(w_m X)
@@ -135,8 +135,7 @@ __device__ __forceinline__ Cx<T> wall_load(const PK_GLOBAL T *row, int nx, int m
 // transform continues from pass 1 (needs at least two passes).
 template <int M, int NB, int NT, bool GL_LDS, int P0 = 0, bool XW = false, class GL, class OUT>
 __device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R, M, NB, false, 0> tile,
-                                          OUT &out, bool sine = false,
-                                          const PK_GLOBAL Cx<R> *w4 = nullptr)
+                                          OUT &out, bool sine = false, const Cx<R> *w4 = nullptr)
 {
     auto lstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
     constexpr RPlan pl = make_rplan(M);
@@ -270,7 +269,10 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
     PK_GLOBAL Cx<R> *S = gbl((Cx<R> *)a.S);
     const PK_GLOBAL double *gf = gbl(a.f);
     const bool sine = a.bc_x == 2;
-    const PK_GLOBAL Cx<R> *w4 = XW ? gbl((const Cx<R> *)a.tw4x) : nullptr;
+    // walls: exp(-i pi k/(2nx)) in LDS for the cosine / sine read-out
+    __shared__ Cx<R> s_w4[XW ? NX : 1];
+    const Cx<R> *w4 = s_w4;
+    if constexpr (XW) load_table(s_w4, (const Cx<R> *)a.tw4x, NX);
     auto loader = [&](int row0) {
         return [&, row0](int b, int n) -> Cx<R> {
             const int row = row0 + b;
@@ -430,7 +432,9 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
     m.setup(jb, a.ny, a.nz, a.bc_z, a.bc_y);
     m.bc_x = XW ? a.bc_x : 0;
     const bool sine = a.bc_x == 2;
-    const PK_GLOBAL Cx<R> *w4 = XW ? gbl((const Cx<R> *)a.tw4x) : nullptr;
+    __shared__ Cx<R> s_w4[XW ? NX : 1];
+    const Cx<R> *w4 = s_w4;
+    if constexpr (XW) load_table(s_w4, (const Cx<R> *)a.tw4x, NX);
     load_table(s_tw, (const Cx<R> *)a.tw, NX);
     m.start(k0);
 
