@@ -93,15 +93,22 @@ __global__ __launch_bounds__((YCfg<N, V>::NT)) void k_y(YArgs a0)
 // pass, narrower only where the tile and two N-entry tables would not fit.
 template <int N> struct YWCfg {
     static constexpr int NB0 = sizeof(R) == 4 ? 16 : 8;
-    // one NB x N tile (plus padding) and two N-entry tables within ~150 KB of LDS
+    // one NB x N tile (plus padding) and the N-entry twiddle table within
+    // ~150 KB of LDS
     static constexpr int ELEMS = 150 * 1024 / (int)sizeof(Cx<R>);
-    static constexpr int NBMAX = ELEMS / N - 2;  // N (NB + PAD) + 2 N <= ELEMS
+    static constexpr int NBMAX = ELEMS / N - 1;  // N (NB + PAD) + N <= ELEMS
     static constexpr int NB1 = NB0 < NBMAX ? NB0 : NBMAX;
     static constexpr int NB2 = NB1 >= 16 ? 16 : (NB1 >= 8 ? 8 : (NB1 >= 4 ? 4 : (NB1 >= 2 ? 2 : 1)));
     // the padding column of tiles with 8 or more lines must fit as well
-    static constexpr int NB = (NB2 >= 8 && N * (NB2 + 3) > ELEMS) ? NB2 / 2 : NB2;
+    static constexpr int NB = (NB2 >= 8 && N * (NB2 + 2) > ELEMS) ? NB2 / 2 : NB2;
     static constexpr int NT = pick_nt(NB * N, sizeof(R) == 4 ? 16 : 8);
     static constexpr int PAD = (NB >= 8) ? 1 : 0;
+    // the exp(-i pi k/(2n)) table goes to LDS unless it would cost a resident
+    // workgroup per CU (then it is read through the caches)
+    static constexpr int BASE_B = (N * (NB + PAD) + N) * (int)sizeof(Cx<R>);
+    static constexpr int LDS_CU = 160 * 1024;
+    static constexpr bool W4_LDS =
+        LDS_CU / (BASE_B + N * (int)sizeof(Cx<R>)) == LDS_CU / BASE_B;
 };
 
 __device__ __forceinline__ int wall_reorder(int j, int n) { return 2 * j < n ? 2 * j : 2 * n - 1 - 2 * j; }
@@ -117,7 +124,7 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
     using Tile = LdsTile<R, N, NB, true, C::PAD>;
     __shared__ Cx<R> s_tile[Tile::elems];
     __shared__ Cx<R> s_tw[N];
-    __shared__ Cx<R> s_w4[N];  // exp(-i pi k / (2n))
+    __shared__ Cx<R> s_w4l[C::W4_LDS ? N : 1];  // exp(-i pi k / (2n))
 
     const bool sine = a.bc == 2;
     const int ntile = (a.M + NB - 1) / NB;
@@ -126,8 +133,14 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
     const int k = bid / ntile;
     const int m0 = tile_i * NB;
     load_table(s_tw, (const Cx<R> *)a.tw, N);
-    load_table(s_w4, (const Cx<R> *)a.tw4, N);
+    if constexpr (C::W4_LDS) load_table(s_w4l, (const Cx<R> *)a.tw4, N);
     __syncthreads();
+    auto s_w4 = [&]() {
+        if constexpr (C::W4_LDS)
+            return (const Cx<R> *)s_w4l;
+        else
+            return gbl((const Cx<R> *)a.tw4);
+    }();
 
     const int M = a.M;
     PK_GLOBAL Cx<R> *base = gbl((Cx<R> *)a.S) + (size_t)k * N * M + m0;
@@ -141,15 +154,74 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
             return (sine && (r & 1)) ? Cx<R>{-v.re, -v.im} : Cx<R>{v.re, v.im};
         };
         auto lstore = [&](int b, int n, Cx<R> v) { out.at(b, n) = v; };
-        fft_tile<R, N, NB, NT, true, C::PAD, false>(s_tw, 1, gload, lstore, tile);
-        __syncthreads();
-        for (int e = threadIdx.x; e < NB * N; e += NT) {
-            const int b = e % NB, kk = e / NB;
-            if (m0 + b >= M) continue;
-            const Cx<R> w = s_w4[kk];
-            const Cx<R> v1 = out.at(b, kk), v2 = out.at(b, kk == 0 ? 0 : N - kk);
-            const Cx<R> c = cscale(cadd(cmul(w, v1), cmul(cconj(w), v2)), R(0.5));
-            put(base + (size_t)(sine ? N - 1 - kk : kk) * M + b, c);
+        constexpr RPlan pl = make_rplan(N);
+        constexpr int LR = pl.count >= 2 ? pl.r[pl.count - 1] : 1;
+        if constexpr (pl.count >= 2 && (N / LR) % 2 == 0) {
+            // every pass but the last into LDS; the last pass with butterfly
+            // pairs (p, NJ - p) (or (0, NJ/2)), so that V[k] and V[N-k] meet in
+            // one thread and the coefficients are stored from registers:
+            //   C[k] = (w_k V[k] + conj(w_k) V[N-k]) / 2, likewise C[N-k]
+            fft_passes<R, N, NB, NT, true, C::PAD, false, 0, pl.count - 1, 0>(s_tw, 1, gload,
+                                                                              lstore, tile);
+            __syncthreads();
+            constexpr int RAD = LR, NJ = N / LR, U = NJ / 2, NU = NB * U;
+            constexpr int PER = (NU + NT - 1) / NT;
+            auto emit = [&](int b, int kk, Cx<R> vk, Cx<R> vc) {
+                const Cx<R> w = s_w4[kk];
+                put(base + (size_t)(sine ? N - 1 - kk : kk) * M + b,
+                    cscale(cadd(cmul(w, vk), cmul(cconj(w), vc)), R(0.5)));
+                if (kk != 0 && 2 * kk != N) {
+                    const Cx<R> w2 = s_w4[N - kk];
+                    put(base + (size_t)(sine ? kk - 1 : N - kk) * M + b,
+                        cscale(cadd(cmul(w2, vc), cmul(cconj(w2), vk)), R(0.5)));
+                }
+            };
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int u = threadIdx.x + q * NT;
+                if (NU % NT != 0 && u >= NU) break;
+                const int b = u % NB, pp = u / NB;
+                const int j1 = pp, j2 = pp == 0 ? NJ / 2 : NJ - pp;
+                Cx<R> v1[RAD], v2[RAD];
+#pragma unroll
+                for (int r = 0; r < RAD; ++r) {
+                    v1[r] = out.at(b, j1 + r * NJ);
+                    v2[r] = out.at(b, j2 + r * NJ);
+                }
+#pragma unroll
+                for (int r = 1; r < RAD; ++r) {
+                    v1[r] = cmul(v1[r], s_tw[r * j1]);
+                    v2[r] = cmul(v2[r], s_tw[r * j2]);
+                }
+                Bfly<R, RAD>::run(v1);
+                Bfly<R, RAD>::run(v2);
+                if (m0 + b >= M) continue;
+                if (pp == 0) {
+                    // butterfly 0: k = r NJ with partner (RAD - r) NJ; k = 0 alone
+                    emit(b, 0, v1[0], v1[0]);
+#pragma unroll
+                    for (int r = 1; r < RAD; ++r)
+                        if (r <= RAD - r) emit(b, r * NJ, v1[r], v1[RAD - r]);
+                    // butterfly NJ/2: k = NJ/2 + r NJ with partner r <-> RAD-1-r
+#pragma unroll
+                    for (int r = 0; r < RAD; ++r)
+                        if (r <= RAD - 1 - r) emit(b, NJ / 2 + r * NJ, v2[r], v2[RAD - 1 - r]);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < RAD; ++r) emit(b, j1 + r * NJ, v1[r], v2[RAD - 1 - r]);
+                }
+            }
+        } else {
+            fft_tile<R, N, NB, NT, true, C::PAD, false>(s_tw, 1, gload, lstore, tile);
+            __syncthreads();
+            for (int e = threadIdx.x; e < NB * N; e += NT) {
+                const int b = e % NB, kk = e / NB;
+                if (m0 + b >= M) continue;
+                const Cx<R> w = s_w4[kk];
+                const Cx<R> v1 = out.at(b, kk), v2 = out.at(b, kk == 0 ? 0 : N - kk);
+                const Cx<R> c = cscale(cadd(cmul(w, v1), cmul(cconj(w), v2)), R(0.5));
+                put(base + (size_t)(sine ? N - 1 - kk : kk) * M + b, c);
+            }
         }
     } else {
         // W[k] = conj(w_k) (C[k] - i C[n-k]) formed in pass 0's loads from the
