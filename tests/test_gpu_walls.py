@@ -395,3 +395,34 @@ def test_batch_of_boxes(orc):
             if prec == "fp64":
                 ref = orc.solve(f, *sp, c[2], bc_x=c[0], bc_y=c[1])
                 assert rel(single, ref) <= 1e-12, c
+
+
+@pytest.mark.parametrize("bcs", [(NEU, NEU, NEU), (PER, NEU, NEU), (DIR, PER, DIR)],
+                         ids=["cavity", "channel", "dirichlet_x_z"])
+def test_walls_full_size(orc, bcs):
+    """512 x 512 x 256 (box 2x2x1), the benchmark's wall boxes and launch
+    configuration: the oracle's residual of the GPU solution over the whole
+    grid (FP64 1e-12, FP32 + refinement 1e-10), the reported mean, and the
+    zero-mean gauge where the constant is in the null space."""
+    P = _gpu()
+    nx, ny, nz = 512, 512, 256
+    sp = (2.0 / nx, 2.0 / ny, 1.0 / nz)
+    print(f"[walls] full size {bcs}: generating the right-hand side", flush=True)
+    f = inputs.random_rhs(nx, ny, nz, seed=3, zero_mean=False)
+    rhs = torch.from_numpy(f).cuda()
+    for prec, tol in (("fp64", 1e-12), ("fp32_refine", 1e-10)):
+        with P.Plan(nx, ny, nz, *sp, bcs[2], prec, bc_x=bcs[0], bc_y=bcs[1]) as plan:
+            out, st = plan.solve(rhs)
+            torch.cuda.synchronize()
+        p = out.cpu().numpy()
+        del out
+        res, _ = orc.residual(f, p, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+        print(f"[walls] full size {bcs} {prec}: residual {res:.2e} stats {st}", flush=True)
+        assert st["status"] == 0 and res <= tol, (prec, res)
+        if DIR in bcs:
+            assert st["rhs_mean"] == 0.0
+        else:
+            assert abs(st["rhs_mean"] - f.mean()) <= 1e-12
+            assert abs(p.mean()) <= 1e-13 * np.abs(p).max()
+    del rhs
+    torch.cuda.empty_cache()
