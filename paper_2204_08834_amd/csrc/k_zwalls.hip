@@ -407,6 +407,243 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
     }
 }
 
+// Walls along x and y: every column (m, ky) holds two real modes as A + iB
+// (x-modes 2m and 2m+1, real-linear y coefficients), i.e. two real
+// tridiagonal systems with different eigenvalues.  This variant gives each
+// lane one column and runs the recurrences above twice, one set for the real
+// part (s_A) and one for the imaginary part (s_B), instead of spending two
+// lanes on it; everything else (deficit form, chunk scans, the FP64 zero
+// mode for part A of column (0, 0)) is as in k_z_walls.
+template <int L, int W, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_z_walls2(ZArgs a0, int C)
+{
+    if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
+    ZArgs a = a0;
+    if (a.batch) {
+        const ProbPtrs &pq = a.batch[blockIdx.y];
+        a.S = pq.S;
+        if (a.zero_mean_out) a.zero_mean_out = pq.scal;
+    }
+    extern __shared__ double smem_d[];
+    R *buf = (R *)smem_d;                                       // C*W slots of 8 reals
+    double *zbuf = smem_d + ((C * W * 8 * sizeof(R) + 7) / 8);  // 3*C doubles
+
+    const int t = threadIdx.x;
+    const int w = t % W, c = t / W;
+    const int nz = a.nz, M = a.M, ny = a.ny;
+    const size_t plane = (size_t)ny * M;
+    PK_GLOBAL Cx<R> *S = gbl((Cx<R> *)a.S);
+    const int s = c * L;
+    const int e = (s + L < nz) ? s + L : nz;  // chunk rows [s, e)
+    const double scale = a.dz2 * a.inv_nxny;
+
+    const int q = block_order((int)blockIdx.x, (int)gridDim.x, a.reverse) * W + w;
+    const int mm = q % M, ky = q / M;
+    const bool active = q < ny * M;
+    const bool zero_lane = active && q == 0 && !a.regular;  // part A of column (0, 0)
+    const double ly = active ? a.lamy[ky] : 0.0;
+    const double sA_d = (active && !zero_lane) ? -(a.lamx[2 * mm] + ly) * a.dz2 : 1.0;
+    const double sB_d = active ? -(a.lamx[2 * mm + 1] + ly) * a.dz2 : 1.0;
+
+    Cx<R> d[L];
+    {
+        const PK_GLOBAL Cx<R> *col = S + (size_t)s * plane + (active ? q : 0);
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            d[i] = {R(0), R(0)};
+            if (active && s + i < nz) {
+                const Cx<R> g = col[(size_t)i * plane];
+                d[i] = {g.re * R(scale), g.im * R(scale)};
+            }
+        }
+    }
+    auto zraw = [&](int k) -> double { return double(S[(size_t)k * plane].re); };
+
+    const R sA = R(sA_d), sB = R(sB_d);
+    const R mwA = rcp_nr(R(1) + sA), mwB = rcp_nr(R(1) + sB);
+    const R mwsA = sA * mwA, mwsB = sB * mwB;
+    const R dir2 = a.dirichlet_z ? R(2) : R(0);
+    const R mws0A = a.dirichlet_z ? (sA + R(2)) * rcp_nr(sA + R(3)) : mwsA;
+    const R mws0B = a.dirichlet_z ? (sB + R(2)) * rcp_nr(sB + R(3)) : mwsB;
+
+    // ---- phase 1: Moebius products of the chunk, one per part -------------
+    R a00 = R(1), a01 = R(0), a10 = R(0), a11 = R(1);
+    R b00 = R(1), b01 = R(0), b10 = R(0), b11 = R(1);
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const int k = s + i;
+        const R xA = (k == 0) ? R(0) : mwA, yA = (k == 0) ? mws0A : mwsA;
+        const R xB = (k == 0) ? R(0) : mwB, yB = (k == 0) ? mws0B : mwsB;
+        const R n00 = xA * a00 + yA * a10, n01 = xA * a01 + yA * a11;
+        const R n10 = xA * a00 + a10, n11 = xA * a01 + a11;
+        a00 = n00; a01 = n01; a10 = n10; a11 = n11;
+        const R m00 = xB * b00 + yB * b10, m01 = xB * b01 + yB * b11;
+        const R m10 = xB * b00 + b10, m11 = xB * b01 + b11;
+        b00 = m00; b01 = m01; b10 = m10; b11 = m11;
+    }
+    R *slot = buf + (size_t)(c * W + w) * 8;
+    slot[0] = a00; slot[1] = a01; slot[2] = a10; slot[3] = a11;
+    slot[4] = b00; slot[5] = b01; slot[6] = b10; slot[7] = b11;
+    if (zero_lane) {
+        double zsum = 0.0;
+        for (int k = s; k < e; ++k) zsum += zraw(k);
+        zbuf[c] = zsum;
+    }
+    __syncthreads();  // S1
+
+    R vA0 = R(0), vB0 = R(0);
+    for (int cc = 0; cc < c; ++cc) {
+        const R *o = buf + (size_t)(cc * W + w) * 8;
+        vA0 = (o[0] * vA0 + o[1]) * rcp_nr(o[2] * vA0 + o[3]);
+        vB0 = (o[4] * vB0 + o[5]) * rcp_nr(o[6] * vB0 + o[7]);
+    }
+
+    double zmu = 0.0, zF0 = 0.0, zsF = 0.0;
+    if (zero_lane) {
+        double tot = 0.0, pre = 0.0;
+        for (int cc = 0; cc < C; ++cc) {
+            if (cc == c) pre = tot;
+            tot += zbuf[cc];
+        }
+        zmu = tot / nz;
+        if (c == 0 && a.zero_mean_out) *a.zero_mean_out = tot * a.inv_ntot;
+        zF0 = (pre - s * zmu) * scale;
+        double run = zF0;
+        for (int k = s; k < e; ++k) {
+            run += (zraw(k) - zmu) * scale;
+            zsF += run;
+        }
+    }
+    __syncthreads();  // S2
+
+    // ---- phase 2: local forward elimination, both parts -------------------
+    R vkA[L], vkB[L];
+    R ulA = R(0), ulB = R(0);
+    {
+        Cx<R> Dp = {R(0), R(0)};
+        R GpA = R(1), GpB = R(1), vpA = vA0, vpB = vB0;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const int k = s + i;
+            const bool last = k >= nz - 1;
+            const R exA = (k == 0) ? sA + dir2 : sA + vpA;
+            const R exB = (k == 0) ? sB + dir2 : sB + vpB;
+            const R pivA = (nz == 1) ? sA + dir2 + dir2 : (k == nz - 1 ? exA + dir2 : R(1) + exA);
+            const R pivB = (nz == 1) ? sB + dir2 + dir2 : (k == nz - 1 ? exB + dir2 : R(1) + exB);
+            const R uA = rcp_nr(pivA), uB = rcp_nr(pivB);
+            const R nA = last ? R(1) : exA * uA, nB = last ? R(1) : exB * uB;
+            Dp = {(Dp.re - d[i].re) * uA, (Dp.im - d[i].im) * uB};
+            GpA = uA * GpA;
+            GpB = uB * GpB;
+            if (k == nz - 1) {
+                ulA = uA;
+                ulB = uB;
+            }
+            vkA[i] = nA;
+            vkB[i] = nB;
+            d[i] = Dp;
+            vpA = nA;
+            vpB = nB;
+        }
+        slot[0] = Dp.re; slot[1] = Dp.im; slot[2] = GpA; slot[3] = GpB;
+    }
+    if (zero_lane) zbuf[C + c] = zsF;
+    __syncthreads();  // S3
+
+    {
+        Cx<R> dprev = {R(0), R(0)};
+        for (int cc = 0; cc < c; ++cc) {
+            const R *o = buf + (size_t)(cc * W + w) * 8;
+            dprev = {o[0] + o[2] * dprev.re, o[1] + o[3] * dprev.im};
+        }
+        R GrA = R(1), GrB = R(1);
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const bool lr = s + i == nz - 1;
+            GrA *= lr ? ulA : R(1) - vkA[i];
+            GrB *= lr ? ulB : R(1) - vkB[i];
+            d[i] = {d[i].re + GrA * dprev.re, d[i].im + GrB * dprev.im};
+        }
+    }
+    // ---- phase 3: local back substitution ---------------------------------
+    Cx<R> Xn = {R(0), R(0)};
+    R HnA = R(1), HnB = R(1);
+#pragma unroll
+    for (int i = L - 1; i >= 0; --i) {
+        const Cx<R> X = {d[i].re + (Xn.re - vkA[i] * Xn.re), d[i].im + (Xn.im - vkB[i] * Xn.im)};
+        d[i] = X;
+        Xn = X;
+        HnA *= R(1) - vkA[i];
+        HnB *= R(1) - vkB[i];
+    }
+    double zP0 = 0.0, zsx = 0.0;
+    if (zero_lane) {
+        for (int cc = 0; cc < c; ++cc) zP0 += zbuf[C + cc];
+        double run = zF0, xk = zP0;
+        for (int k = s; k < e; ++k) {
+            zsx += xk;
+            run += (zraw(k) - zmu) * scale;
+            xk += run;
+        }
+    }
+    __syncthreads();  // S4
+    slot[0] = Xn.re; slot[1] = Xn.im; slot[2] = HnA; slot[3] = HnB;
+    if (zero_lane) zbuf[2 * C + c] = zsx;
+    __syncthreads();  // S5
+
+    {
+        Cx<R> y = {R(0), R(0)};
+        for (int cc = C - 1; cc > c; --cc) {
+            const R *o = buf + (size_t)(cc * W + w) * 8;
+            y = {o[0] + o[2] * y.re, o[1] + o[3] * y.im};
+        }
+        R HrA = R(1), HrB = R(1);
+#pragma unroll
+        for (int i = L - 1; i >= 0; --i) {
+            HrA *= R(1) - vkA[i];
+            HrB *= R(1) - vkB[i];
+            d[i] = {d[i].re + HrA * y.re, d[i].im + HrB * y.im};
+        }
+    }
+    if (zero_lane) {
+        // part A of column (0, 0): the FP64 zero-mode solution (part B keeps
+        // its own, regular, solve)
+        double tot = 0.0;
+        for (int cc = 0; cc < C; ++cc) tot += zbuf[2 * C + cc];
+        const double mean = tot / nz;
+        double run = zF0, xk = zP0;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const int k = s + i;
+            if (k < nz) {
+                d[i].re = R(xk - mean);
+                run += (zraw(k) - zmu) * scale;
+                xk += run;
+            }
+        }
+    }
+    __syncthreads();  // S6: every zero-lane re-read of column (0,0) is done
+
+    if (active) {
+        PK_GLOBAL Cx<R> *col = S + (size_t)s * plane + q;
+#pragma unroll
+        for (int i = 0; i < L; ++i)
+            if (s + i < nz) col[(size_t)i * plane] = d[i];
+    }
+}
+
+template <int L, int W, int MAXT>
+static int run_zw2(const ZArgs &a, hipStream_t s)
+{
+    const int C = (a.nz + L - 1) / L;
+    if (C * W > MAXT) return -1;
+    const int nb = (a.ny * a.M + W - 1) / W;
+    const size_t shm = ((C * W * 8 * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double);
+    hipLaunchKernelGGL((k_z_walls2<L, W, MAXT>), dim3(nb, a.batch ? a.nbatch : 1), dim3(W * C),
+                       shm, s, a, C);
+    return (int)hipGetLastError();
+}
+
 template <int L, int W, int MAXT>
 static int run_zw(const ZArgs &a, hipStream_t s)
 {
@@ -435,6 +672,25 @@ int PK_SUFFIX(launch_z_walls)(const ZArgs &a, hipStream_t s)
     //   3: 8-row chunks, 256-byte row runs
     const int nz = a.nz;
     constexpr bool F32 = sizeof(R) == 4;
+    if (F32 && a.xwall && a.ywall) {
+        // every column holds two real modes: one lane per column, both solves.
+        // FP32 only: measured at 512x512x256 the cavity's z pass drops from
+        // 219 to 168 us; in FP64 the doubled recurrences need 256 VGPRs with
+        // 16-row chunks (or twice the chunk scans with 8), 740 against 590 us
+        // for two lanes per column.  Variant bit 0 selects 16-row chunks.
+        const bool n16 = (a.variant & 1) != 0;
+        if (nz <= 64) return run_zw2<8, 32, 256>(a, s);
+        if (n16) {
+            if (nz <= 256) return run_zw2<16, 16, 256>(a, s);
+            if (nz <= 512) return run_zw2<16, 16, 512>(a, s);
+            if (nz <= 1024) return run_zw2<16, 16, 1024>(a, s);
+        }
+        if (nz <= 256) return run_zw2<8, 16, 512>(a, s);
+        if (nz <= 512) return run_zw2<8, 16, 1024>(a, s);
+        if (nz <= 1024) return run_zw2<8, 8, 1024>(a, s);
+        if (nz <= 4096) return run_zw2<8, 2, 1024>(a, s);
+        return -1;
+    }
     const bool c8 = a.variant == 1 || a.variant == 3;
     // walls along x: every column is a two-mode column whose lane halves
     // read W/2 consecutive m each, so only the wide tiles give full
