@@ -83,12 +83,12 @@ def _load():
     lib.oracle_residual.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
         ctypes.c_int, dp, dp, dp, dp, dp]
     lib.oracle_residual.restype = ctypes.c_int
-    lib.oracle_divergence.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
-        ctypes.c_int, dp, dp, dp, ctypes.c_double, dp]
-    lib.oracle_divergence.restype = ctypes.c_int
-    lib.oracle_correct.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
-        ctypes.c_int, dp, ctypes.c_double, dp, dp, dp]
-    lib.oracle_correct.restype = ctypes.c_int
+    lib.oracle_divergence_bc.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
+        ctypes.c_int] * 3 + [dp, dp, dp, ctypes.c_double, dp]
+    lib.oracle_divergence_bc.restype = ctypes.c_int
+    lib.oracle_correct_bc.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
+        ctypes.c_int] * 3 + [dp, ctypes.c_double, dp, dp, dp]
+    lib.oracle_correct_bc.restype = ctypes.c_int
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     _lib = lib
@@ -161,39 +161,44 @@ def residual(f, p, dx, dy, dz, bc_z, return_field: bool = False, bc_x: int = PER
     return l2.value, li.value
 
 
-def divergence(u, v, w, dx, dy, dz, bc_z, alpha=1.0):
+def divergence(u, v, w, dx, dy, dz, bc_z, alpha=1.0, bc_x: int = PERIODIC,
+               bc_y: int = PERIODIC):
     """alpha * D u: cell divergence of face velocities (u east, v north, w top
-    faces; walls in z: w[nz-1] is the wall, the bottom wall flux is zero)."""
+    faces).  Per axis PERIODIC or NEUMANN (solid walls: the last face of the
+    axis is the wall and, like the face below the first cell, carries no
+    flux)."""
     lib = _load()
     u, v, w = _check(u), _check(v), _check(w)
     nz, ny, nx = u.shape
     f = np.empty_like(u)
-    rc = lib.oracle_divergence(nx, ny, nz, dx, dy, dz, int(bc_z), _ptr(u), _ptr(v), _ptr(w),
-                               float(alpha), _ptr(f))
+    rc = lib.oracle_divergence_bc(nx, ny, nz, dx, dy, dz, int(bc_x), int(bc_y), int(bc_z),
+                                  _ptr(u), _ptr(v), _ptr(w), float(alpha), _ptr(f))
     if rc != 0:
         raise RuntimeError("oracle_divergence failed")
     return f
 
 
-def correct(u, v, w, psi, dx, dy, dz, bc_z, beta=1.0):
-    """(u, v, w) - beta * G psi on the faces (copies; the wall face unchanged)."""
+def correct(u, v, w, psi, dx, dy, dz, bc_z, beta=1.0, bc_x: int = PERIODIC,
+            bc_y: int = PERIODIC):
+    """(u, v, w) - beta * G psi on the faces (copies; wall faces unchanged)."""
     lib = _load()
     u, v, w = _check(u).copy(), _check(v).copy(), _check(w).copy()
     psi = _check(psi)
     nz, ny, nx = u.shape
-    rc = lib.oracle_correct(nx, ny, nz, dx, dy, dz, int(bc_z), _ptr(psi), float(beta), _ptr(u),
-                            _ptr(v), _ptr(w))
+    rc = lib.oracle_correct_bc(nx, ny, nz, dx, dy, dz, int(bc_x), int(bc_y), int(bc_z),
+                               _ptr(psi), float(beta), _ptr(u), _ptr(v), _ptr(w))
     if rc != 0:
         raise RuntimeError("oracle_correct failed")
     return u, v, w
 
 
-def project(u, v, w, dx, dy, dz, bc_z, alpha=1.0, beta=1.0):
+def project(u, v, w, dx, dy, dz, bc_z, alpha=1.0, beta=1.0, bc_x: int = PERIODIC,
+            bc_y: int = PERIODIC):
     """The projection around the solve: f = alpha D u, psi = the zero-mean
     solution of L psi = f - mean(f), and the corrected velocities."""
-    f = divergence(u, v, w, dx, dy, dz, bc_z, alpha)
-    psi = solve(f, dx, dy, dz, bc_z)
-    return psi, correct(u, v, w, psi, dx, dy, dz, bc_z, beta)
+    f = divergence(u, v, w, dx, dy, dz, bc_z, alpha, bc_x=bc_x, bc_y=bc_y)
+    psi = solve(f, dx, dy, dz, bc_z, bc_x=bc_x, bc_y=bc_y)
+    return psi, correct(u, v, w, psi, dx, dy, dz, bc_z, beta, bc_x=bc_x, bc_y=bc_y)
 
 
 def num_threads() -> int:

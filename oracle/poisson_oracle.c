@@ -540,70 +540,96 @@ int oracle_residual(int nx, int ny, int nz, double dx, double dy, double dz, int
  * eqn:poisson and the velocity update eqn:corr; Section 3 for the
  * staggered layout).  Face velocities: u[k][j][i] sits on the east face of
  * cell (i,j,k), v on its north face, w on its top face.  Periodic directions
- * wrap; with walls in z the top face of the last cell is the wall
- * (w[nz-1] holds no flow) and the bottom wall flux below cell 0 is zero.
+ * wrap; along an axis with walls (solid, no-slip: the pressure has zero
+ * normal gradient there) the last face of the axis is the wall (u[nx-1],
+ * v[ny-1] or w[nz-1] holds no flow and is not read) and no flux enters
+ * through the first face either.
  *
- * oracle_divergence: f = alpha * D u, the cell divergence
- *   (u[i] - u[i-1])/dx + (v[j] - v[j-1])/dy + (w[k] - w[k-1])/dz.
+ * oracle_divergence_bc: f = alpha * D u, the cell divergence
+ *   (u[i] - u[i-1])/dx + (v[j] - v[j-1])/dy + (w[k] - w[k-1])/dz,
+ * boundaries per axis: 0 periodic, 1 walls.
  */
-int oracle_divergence(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
-                      const double *u, const double *v, const double *w, double alpha,
-                      double *f)
+/* flux through the faces below (lo) and above (hi) cell n of an axis of
+ * N cells, faces holding face[n] (upper face of cell n) */
+static void face_pair(const double *lo_face, const double *hi_face, int n, int N, int bc,
+                      double *lo, double *hi)
+{
+    *lo = (n > 0) ? *lo_face : (bc == ORC_PERIODIC ? *lo_face : 0.0);
+    *hi = (bc != ORC_PERIODIC && n == N - 1) ? 0.0 : *hi_face;
+}
+
+int oracle_divergence_bc(int nx, int ny, int nz, double dx, double dy, double dz, int bc_x,
+                         int bc_y, int bc_z, const double *u, const double *v, const double *w,
+                         double alpha, double *f)
 {
     if (nx < 1 || ny < 1 || nz < 1 || !u || !v || !w || !f) return -1;
+    if (bc_x < 0 || bc_x > 1 || bc_y < 0 || bc_y > 1 || bc_z < 0 || bc_z > 1) return -1;
 #pragma omp parallel for schedule(static)
     for (long kk = 0; kk < (long)nz * ny; ++kk) {
         int k = (int)(kk / ny), j = (int)(kk % ny);
-        int jm = (j + ny - 1) % ny;
+        int jm = (j + ny - 1) % ny, km = (k + nz - 1) % nz;
         for (int i = 0; i < nx; ++i) {
             int im = (i + nx - 1) % nx;
 #define A(X, K, J, I) X[((long)(K) * ny + (J)) * nx + (I)]
-            double wd;  /* flux through the bottom face of the cell */
-            if (k > 0)
-                wd = A(w, k - 1, j, i);
-            else
-                wd = (bc_z == ORC_PERIODIC) ? A(w, nz - 1, j, i) : 0.0;
-            double wu = (bc_z == ORC_NEUMANN && k == nz - 1) ? 0.0 : A(w, k, j, i);
-            double d = (A(u, k, j, i) - A(u, k, j, im)) / dx +
-                       (A(v, k, j, i) - A(v, k, jm, i)) / dy + (wu - wd) / dz;
+            double ul, ur, vl, vr, wl, wr;
+            face_pair(&A(u, k, j, im), &A(u, k, j, i), i, nx, bc_x, &ul, &ur);
+            face_pair(&A(v, k, jm, i), &A(v, k, j, i), j, ny, bc_y, &vl, &vr);
+            face_pair(&A(w, km, j, i), &A(w, k, j, i), k, nz, bc_z, &wl, &wr);
 #undef A
-            f[((long)k * ny + j) * nx + i] = alpha * d;
+            f[((long)k * ny + j) * nx + i] =
+                alpha * ((ur - ul) / dx + (vr - vl) / dy + (wr - wl) / dz);
         }
     }
     return 0;
 }
 
+int oracle_divergence(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
+                      const double *u, const double *v, const double *w, double alpha,
+                      double *f)
+{
+    return oracle_divergence_bc(nx, ny, nz, dx, dy, dz, ORC_PERIODIC, ORC_PERIODIC, bc_z, u, v,
+                                w, alpha, f);
+}
+
 /*
- * oracle_correct: u -= beta * G psi on every face, G the face gradient
+ * oracle_correct_bc: u -= beta * G psi on every face, G the face gradient
  *   (psi[i+1] - psi[i])/dx on east faces, (psi[j+1] - psi[j])/dy on north
- *   faces, (psi[k+1] - psi[k])/dz on top faces; the wall face carries no
- *   gradient (zero normal pressure gradient), so w[nz-1] is left as it is.
+ *   faces, (psi[k+1] - psi[k])/dz on top faces; a wall face carries no
+ *   gradient (zero normal pressure gradient), so u[nx-1], v[ny-1] or
+ *   w[nz-1] of an axis with walls is left as it is.
  * With alpha * beta = 1 the corrected velocity is discretely divergence-free
- * whenever L psi = alpha D u, since D G = L (the 7-point operator).
+ * whenever L psi = alpha D u, since D G = L (the 7-point operator with
+ * mirrored ghosts at the walls).
  */
-int oracle_correct(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
-                   const double *psi, double beta, double *u, double *v, double *w)
+int oracle_correct_bc(int nx, int ny, int nz, double dx, double dy, double dz, int bc_x,
+                      int bc_y, int bc_z, const double *psi, double beta, double *u, double *v,
+                      double *w)
 {
     if (nx < 1 || ny < 1 || nz < 1 || !psi || !u || !v || !w) return -1;
+    if (bc_x < 0 || bc_x > 1 || bc_y < 0 || bc_y > 1 || bc_z < 0 || bc_z > 1) return -1;
 #pragma omp parallel for schedule(static)
     for (long kk = 0; kk < (long)nz * ny; ++kk) {
         int k = (int)(kk / ny), j = (int)(kk % ny);
-        int jp = (j + 1) % ny;
+        int jp = (j + 1) % ny, kp = (k + 1) % nz;
         for (int i = 0; i < nx; ++i) {
             int ip = (i + 1) % nx;
             long c = ((long)k * ny + j) * nx + i;
 #define P(K, J, I) psi[((long)(K) * ny + (J)) * nx + (I)]
             double pc = psi[c];
-            u[c] -= beta * (P(k, j, ip) - pc) / dx;
-            v[c] -= beta * (P(k, jp, i) - pc) / dy;
-            if (k < nz - 1)
-                w[c] -= beta * (P(k + 1, j, i) - pc) / dz;
-            else if (bc_z == ORC_PERIODIC)
-                w[c] -= beta * (P(0, j, i) - pc) / dz;
+            if (!(bc_x != ORC_PERIODIC && i == nx - 1)) u[c] -= beta * (P(k, j, ip) - pc) / dx;
+            if (!(bc_y != ORC_PERIODIC && j == ny - 1)) v[c] -= beta * (P(k, jp, i) - pc) / dy;
+            if (!(bc_z != ORC_PERIODIC && k == nz - 1)) w[c] -= beta * (P(kp, j, i) - pc) / dz;
 #undef P
         }
     }
     return 0;
+}
+
+int oracle_correct(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
+                   const double *psi, double beta, double *u, double *v, double *w)
+{
+    return oracle_correct_bc(nx, ny, nz, dx, dy, dz, ORC_PERIODIC, ORC_PERIODIC, bc_z, psi, beta,
+                             u, v, w);
 }
 
 int oracle_num_threads(void)

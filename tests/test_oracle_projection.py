@@ -116,3 +116,64 @@ def test_uniform_psi_leaves_velocity(orc):
     psi = np.full((3, 4, 5), 2.5)
     u2, v2, w2 = orc.correct(u, v, w, psi, 0.1, 0.2, 0.3, NEU, beta=3.0)
     assert np.array_equal(u2, u) and np.array_equal(v2, v) and np.array_equal(w2, w)
+
+
+# --------------------------------------------------------------------------
+# solid walls along x and y as well
+# --------------------------------------------------------------------------
+WALL_SETS = [(NEU, NEU, NEU), (NEU, PER, NEU), (PER, NEU, PER), (NEU, NEU, PER)]
+
+
+@pytest.mark.parametrize("bcs", WALL_SETS)
+def test_walls_divergence_conserves_flux(orc, bcs):
+    u, v, w = _vel((5, 6, 7), 11)
+    f = orc.divergence(u, v, w, 0.1, 0.2, 0.3, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+    assert abs(f.sum()) <= 1e-12 * np.abs(f).sum()
+
+
+def test_walls_unit_face_flux(orc):
+    """With walls along x and y the last faces carry nothing; an interior
+    face moves +1/h to -1/h as before."""
+    nz, ny, nx = 3, 4, 5
+    dx, dy, dz = 0.5, 0.25, 0.125
+    z = np.zeros((nz, ny, nx))
+    for axis, (i, j, k) in (("u", (nx - 1, 2, 1)), ("v", (3, ny - 1, 2))):
+        a = z.copy()
+        a[k, j, i] = 1.0
+        args = (a, z, z) if axis == "u" else (z, a, z)
+        f = orc.divergence(*args, dx, dy, dz, NEU, bc_x=NEU, bc_y=NEU)
+        assert np.array_equal(f, z), axis  # the wall face is not read
+    a = z.copy()
+    a[1, 2, 1] = 1.0
+    f = orc.divergence(a, z, z, dx, dy, dz, NEU, bc_x=NEU, bc_y=NEU)
+    exp = z.copy()
+    exp[1, 2, 1] = 1 / dx
+    exp[1, 2, 2] = -1 / dx
+    assert np.array_equal(f, exp)
+
+
+@pytest.mark.parametrize("bcs", WALL_SETS)
+def test_walls_divergence_of_gradient_is_laplacian(orc, bcs):
+    rng = np.random.default_rng(13)
+    psi = rng.uniform(-1, 1, (6, 7, 8))
+    sp = (0.3, 0.2, 0.1)
+    z = np.zeros_like(psi)
+    gu, gv, gw = orc.correct(z, z, z, psi, *sp, bcs[2], beta=-1.0, bc_x=bcs[0], bc_y=bcs[1])
+    lap = orc.laplacian(psi, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+    dg = orc.divergence(gu, gv, gw, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+    assert np.max(np.abs(dg - lap)) <= 1e-12 * np.max(np.abs(lap))
+
+
+@pytest.mark.parametrize("bcs", WALL_SETS)
+def test_walls_projection_is_divergence_free(orc, bcs):
+    u, v, w = _vel((8, 12, 16), 15)
+    sp = (1 / 16, 1 / 12, 1 / 8)
+    psi, (u2, v2, w2) = orc.project(u, v, w, *sp, bcs[2], alpha=4.0, beta=0.25, bc_x=bcs[0],
+                                    bc_y=bcs[1])
+    d0 = orc.divergence(u, v, w, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+    d1 = orc.divergence(u2, v2, w2, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+    assert np.max(np.abs(d1)) <= 1e-12 * np.max(np.abs(d0))
+    if bcs[0] == NEU:
+        assert np.array_equal(u2[:, :, -1], u[:, :, -1])
+    if bcs[1] == NEU:
+        assert np.array_equal(v2[:, -1, :], v[:, -1, :])
