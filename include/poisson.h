@@ -148,9 +148,9 @@ int poisson_solve(poisson_plan plan, const double *rhs_dev, double *sol_dev,
  * w[k,j,i] on z = (k+1) dz; D is the cell-centred divergence,
  *   (D u)[k,j,i] = (u[i] - u[i-1])/dx + (v[j] - v[j-1])/dy + (w[k] - w[k-1])/dz,
  * and G the face gradient, (Gx psi)[i] = (psi[i+1] - psi[i])/dx etc., both
- * periodic in x and y.  With walls in z no flux crosses the bottom face of
- * plane 0 or the top face of plane nz-1: those values of w are not read, and
- * w on the top wall (plane nz-1) is not changed.  D G equals the 7-point L,
+ * periodic along periodic axes.  Along an axis with (Neumann, solid) walls no
+ * flux crosses the first face or the last face, which is the wall: u[nx-1],
+ * v[ny-1] or w[nz-1] of such an axis is not read and not changed.  D G equals the 7-point L,
  * so with alpha * beta = 1 the corrected velocity is discretely
  * divergence-free up to the solve's accuracy.
  * u, v, w, p, psi: device float64, nx*ny*nz elements each, pairwise
@@ -161,9 +161,9 @@ int poisson_solve(poisson_plan plan, const double *rhs_dev, double *sol_dev,
  * were and psi holds the last iterate.  Under POISSON_FP32_REFINE the first
  * call allocates one more float64 field (nx*ny*nz) that the plan keeps for f.
  * Errors: INVALID_ARG (null plan or field, batched plan, non-finite scale,
- * overlapping fields), UNSUPPORTED (a plan with walls along x or y, or with
- * Dirichlet walls: the face conventions above are those of periodic x, y and
- * no-slip walls in z), OUT_OF_MEMORY, HIP, and those of poisson_solve.
+ * overlapping fields), UNSUPPORTED (a plan with Dirichlet walls: the face
+ * conventions above are those of solid walls), OUT_OF_MEMORY, HIP, and those
+ * of poisson_solve.
  */
 int poisson_project(poisson_plan plan, double *u, double *v, double *w, double *p, double *psi,
                     double alpha, double beta, poisson_stats_t *stats);

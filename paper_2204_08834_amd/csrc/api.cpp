@@ -1382,7 +1382,8 @@ int project(poisson_plan p, double *u, double *v, double *w, double *pr, double 
     p->proj = poisson_plan_s::Proj{};
     if (rc) return rc;
     CorrArgs a{psi, u, v, w, pr, g.d.nx, g.d.ny, g.d.nz, g.d.bc_z,
-               beta / g.d.dx, beta / g.d.dy, beta / g.d.dz, g.tune.kr};
+               beta / g.d.dx, beta / g.d.dy, beta / g.d.dz, g.tune.kr,
+               g.d.bc_x != POISSON_BC_PERIODIC ? 1 : 0, g.d.bc_y != POISSON_BC_PERIODIC ? 1 : 0};
     p->ls = p->stream;
     const double bytes = (double)g.N * (pr ? 72.0 : 56.0);
     return timed(p, "correct_f64", bytes, [&] { return launch_correct(a, p->stream); });
@@ -1473,9 +1474,7 @@ int poisson_project(poisson_plan plan, double *u, double *v, double *w, double *
     // the velocity conventions at the walls are those of the no-slip walls
     // (zero-gradient pressure); zero-value pressure walls are not projected
     const poisson_desc_t &d0 = plan->groups[0].d;
-    if (d0.bc_x != POISSON_BC_PERIODIC || d0.bc_y != POISSON_BC_PERIODIC ||
-        d0.bc_z == POISSON_BC_DIRICHLET)
-        return POISSON_ERR_UNSUPPORTED;
+    if (regular(d0)) return POISSON_ERR_UNSUPPORTED;
     const long long n = plan->groups[0].N;
     const double *arr[5] = {u, v, w, psi, p};
     for (int i = 0; i < 5; ++i)

@@ -256,6 +256,7 @@ struct CorrArgs {
     int nx, ny, nz, bc_z;
     double bx, by, bz;      // beta/dx, beta/dy, beta/dz
     int kr_max;             // z-planes per workgroup (0: default)
+    int xwall, ywall;       // solid walls along x / y (wall faces left as they are)
 };
 int launch_correct(const CorrArgs &a, hipStream_t s);
 

@@ -287,6 +287,8 @@ __global__ __launch_bounds__(CO_NT) void k_correct(CorrArgs a)
     m.bx = a.bx;
     m.by = a.by;
     m.bz = a.bz;
+    m.xwall = a.xwall != 0;
+    m.ywall = a.ywall != 0;
     m.tile = s_tile;
     m.setup(jb, a.ny, a.nz, a.bc_z);
     m.start(k0);

@@ -489,7 +489,7 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
 // to `partials` like those of the plain pass.  One problem per launch.
 constexpr int XD_NT = 256;
 
-template <int M>
+template <int M, bool XW>
 __global__ __launch_bounds__(XD_NT) void k_x_div(XFwdArgs a0)
 {
     XFwdArgs a = a0;
@@ -522,9 +522,15 @@ __global__ __launch_bounds__(XD_NT) void k_x_div(XFwdArgs a0)
     m.cx = a.cx;
     m.cy = a.cy;
     m.cz = a.cz;
+    m.xwall = a.bc_x != 0;
+    m.ywall = a.bc_y != 0;
     m.bind(s_buf);
     m.setup(jb, a.ny, a.nz, a.bc_z);
     load_table(s_tw, (const Cx<R> *)a.tw, NX);
+    // walls along x: cosine expansion of the rows (exp(-i pi k/(2nx)) in LDS)
+    __shared__ Cx<R> s_w4[XW ? NX : 1];
+    if constexpr (XW) load_table(s_w4, (const Cx<R> *)a.tw4x, NX);
+    const bool sine = a.bc_x == 2;
     m.start(k0);
 
     Tile tile{(Cx<R> *)s_buf};
@@ -543,14 +549,24 @@ __global__ __launch_bounds__(XD_NT) void k_x_div(XFwdArgs a0)
         m.step(k, sink);
         __syncthreads();  // the march is done reading its staging arrays
 #pragma unroll
-        for (int q = 0; q < Mar::PER; ++q)
-            if (m.valid(q)) tile.at(m.row_of(q), m.pair_of(q)) = ff[q];
+        for (int q = 0; q < Mar::PER; ++q) {
+            if (!m.valid(q)) continue;
+            const int t = m.row_of(q), h = m.pair_of(q);
+            if constexpr (XW) {
+                // x[2h] -> v[h], x[2h+1] -> v[nx-1-h]
+                R *trow = (R *)&tile.at(t, 0);
+                trow[h] = ff[q].re;
+                trow[NX - 1 - h] = sine ? -ff[q].im : ff[q].im;
+            } else {
+                tile.at(t, h) = ff[q];
+            }
+        }
         __syncthreads();
         auto gload = [&](int b, int n) -> Cx<R> { return tile.at(b, n); };
         const size_t rowk = (size_t)k * a.ny + m.j0;
         const int V = m.V;
         auto out = [&](int b) -> PK_GLOBAL Cx<R> * { return b < V ? S + (rowk + b) * M : nullptr; };
-        x_forward<M, TJ, NT, true>(s_tw, gload, tile, out);
+        x_forward<M, TJ, NT, true, 0, XW>(s_tw, gload, tile, out, sine, s_w4);
     }
     if (a.partials) {
         double z1 = 0.0, z2 = 0.0;
@@ -803,7 +819,10 @@ template <int M> static int run_x_fwd(const XFwdArgs &a, hipStream_t s, int *nbl
     const dim3 grid(nb, a.batch ? a.nbatch : 1);
     if (a.residual == 2) {
         if (a.batch && a.nbatch != 1) return -1;
-        hipLaunchKernelGGL(k_x_div<M>, dim3(nb), dim3(XD_NT), 0, s, a);
+        if (xw)
+            hipLaunchKernelGGL((k_x_div<M, true>), dim3(nb), dim3(XD_NT), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_x_div<M, false>), dim3(nb), dim3(XD_NT), 0, s, a);
     } else if (a.residual) {
         // the refinement transforms its residual in FP32 only
         if constexpr (sizeof(R) == 4) {

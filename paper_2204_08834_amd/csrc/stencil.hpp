@@ -243,6 +243,8 @@ struct DivMarch : MarchIdx<M, TJ, NT> {
 
     const PK_GLOBAL double *u, *v, *w;  // set through gbl()
     double cx, cy, cz;
+    bool xwall = false, ywall = false;  // solid walls along x / y: no flux through
+                                        // the first face or the last (wall) face
     double2 (*vt)[M];  // LDS: TJ + 1 rows (row 0: the halo row j0 - 1)
     double (*ut)[M];   // LDS: TJ rows of u[2h+1]
     double2 wd[PER];   // w of plane k-1 (the flux through the bottom face)
@@ -280,8 +282,11 @@ struct DivMarch : MarchIdx<M, TJ, NT> {
             vv[q] = *(const PK_GLOBAL double2 *)(v + kp + o);  // also a halo row
             ww[q] = *(const PK_GLOBAL double2 *)(w + kp + o);  // also read at k + 1
         }
-        for (int h = threadIdx.x; h < M; h += NT)
-            vt[0][h] = *(const PK_GLOBAL double2 *)(v + kp + (size_t)jm * B::NX + 2 * h);
+        const bool vnone = ywall && this->j0 == 0;  // no flux below row 0
+        for (int h = threadIdx.x; h < M; h += NT) {
+            const double2 x = *(const PK_GLOBAL double2 *)(v + kp + (size_t)jm * B::NX + 2 * h);
+            vt[0][h] = vnone ? double2{0.0, 0.0} : x;
+        }
 #pragma unroll
         for (int q = 0; q < PER; ++q)
             if (valid(q)) {
@@ -294,12 +299,14 @@ struct DivMarch : MarchIdx<M, TJ, NT> {
         for (int q = 0; q < PER; ++q) {
             if (valid(q)) {
                 const int t = row_of(q), h = pair_of(q);
-                const double ul = ut[t][h == 0 ? M - 1 : h - 1];
+                const double ul = (xwall && h == 0) ? 0.0 : ut[t][h == 0 ? M - 1 : h - 1];
+                const double ur = (xwall && h == M - 1) ? 0.0 : uu[q].y;  // the wall face
                 const double2 vs = vt[t][h];
+                const double2 vn = (ywall && this->j0 + t == this->ny - 1) ? double2{0.0, 0.0}
+                                                                           : vv[q];
                 const double2 wu = top ? double2{0.0, 0.0} : ww[q];
-                const double f0 = cx * (uu[q].x - ul) + cy * (vv[q].x - vs.x) + cz * (wu.x - wd[q].x);
-                const double f1 = cx * (uu[q].y - uu[q].x) + cy * (vv[q].y - vs.y) +
-                                  cz * (wu.y - wd[q].y);
+                const double f0 = cx * (uu[q].x - ul) + cy * (vn.x - vs.x) + cz * (wu.x - wd[q].x);
+                const double f1 = cx * (ur - uu[q].x) + cy * (vn.y - vs.y) + cz * (wu.y - wd[q].y);
                 sink(q, t, h, f0, f1);
             }
         }
@@ -332,6 +339,7 @@ struct CorrMarch : MarchIdx<M, TJ, NT> {
     const PK_GLOBAL double *psi;
     PK_GLOBAL double *u, *v, *w, *p;  // p may be null
     double bx, by, bz;
+    bool xwall = false, ywall = false;  // wall faces (u[nx-1], v[ny-1]) stay as they are
     double2 (*tile)[M];  // LDS: TJ + 1 rows (row V: the halo row j0 + V)
     double2 pc[PER];     // psi of plane k
 
@@ -375,9 +383,11 @@ struct CorrMarch : MarchIdx<M, TJ, NT> {
                 const double2 pn = tile[t + 1][h];                     // psi of row j + 1
                 double2 a = uu[q], b = vv[q];
                 a.x -= bx * (c.y - c.x);
-                a.y -= bx * (pr - c.y);
-                b.x -= by * (pn.x - c.x);
-                b.y -= by * (pn.y - c.y);
+                if (!(xwall && h == M - 1)) a.y -= bx * (pr - c.y);
+                if (!(ywall && this->j0 + t == this->ny - 1)) {
+                    b.x -= by * (pn.x - c.x);
+                    b.y -= by * (pn.y - c.y);
+                }
                 st_stream(u + kp + o, a);
                 st_stream(v + kp + o, b);
                 if (!top) {

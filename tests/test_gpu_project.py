@@ -213,3 +213,69 @@ def test_project_rb512_full_size(orc, prec):
     assert np.abs(d1).max() <= (1e-11 if prec == "fp64" else 1e-9) * np.abs(f).max()
     del du, dv, dw
     torch.cuda.empty_cache()
+
+
+# --------------------------------------------------------------------------
+# solid walls along x and y
+# --------------------------------------------------------------------------
+WALL_CASES = [((16, 12, 10), (NEU, NEU, NEU)), ((64, 48, 20), (PER, NEU, NEU)),
+              ((24, 12, 8), (NEU, PER, PER)), ((6, 3, 5), (NEU, NEU, NEU)),
+              ((512, 6, 9), (NEU, NEU, NEU)), ((2, 4, 3), (NEU, NEU, PER))]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+@pytest.mark.parametrize("case", WALL_CASES, ids=[f"{c[0][0]}x{c[0][1]}x{c[0][2]}_"
+                                                  + "".join("PND"[b] for b in c[1])
+                                                  for c in WALL_CASES])
+def test_project_walls_match_oracle(orc, case, prec):
+    P = _gpu()
+    (nx, ny, nz), bcs = case
+    sp = (BOX[0] / nx, BOX[1] / ny, BOX[2] / nz)
+    kw = dict(bc_x=bcs[0], bc_y=bcs[1])
+    u, v, w, p0 = _fields(nx, ny, nz, bcs[2], 21)
+    u[:, :, -1] = 0.5  # wall faces (when there are walls): neither read nor changed
+    v[:, -1, :] = -0.5
+    du, dv, dw, dp = (torch.from_numpy(a.copy()).cuda() for a in (u, v, w, p0))
+    alpha, beta = 2.0, 0.5
+    print(f"[project] walls {nx}x{ny}x{nz} {bcs} {prec}", flush=True)
+    with P.Plan(nx, ny, nz, *sp, bcs[2], prec, **kw) as plan:
+        psi, st = plan.project(du, dv, dw, dp, alpha=alpha, beta=beta)
+        torch.cuda.synchronize()
+    assert st["status"] == 0
+    u1, v1, w1, psi = (t.cpu().numpy() for t in (du, dv, dw, psi))
+    f = orc.divergence(u, v, w, *sp, bcs[2], alpha=alpha, **kw)
+    res, _ = orc.residual(f, psi, *sp, bcs[2], **kw)
+    assert res <= (1e-12 if prec == "fp64" else 1e-10), res
+    ur, vr, wr = orc.correct(u, v, w, psi, *sp, bcs[2], beta=beta, **kw)
+    for a, b, name in ((u1, ur, "u"), (v1, vr, "v"), (w1, wr, "w")):
+        assert np.abs(a - b).max() <= 1e-14 * max(np.abs(b).max(), 1.0), name
+    if bcs[0] == NEU:
+        assert np.array_equal(u1[:, :, -1], u[:, :, -1])
+    if bcs[1] == NEU:
+        assert np.array_equal(v1[:, -1, :], v[:, -1, :])
+    assert np.array_equal(dp.cpu().numpy(), p0 + psi)
+    d1 = orc.divergence(u1, v1, w1, *sp, bcs[2], **kw)
+    d0 = orc.divergence(u, v, w, *sp, bcs[2], **kw)
+    assert np.abs(d1).max() <= (1e-11 if prec == "fp64" else 1e-9) * np.abs(d0).max()
+
+
+def test_project_cavity_full_size(orc):
+    """512 x 512 x 256 cavity (solid walls on every axis): the oracle's
+    residual of psi and the divergence of the corrected field, FP32 +
+    refinement."""
+    P = _gpu()
+    nx, ny, nz = 512, 512, 256
+    sp = (2.0 / nx, 2.0 / ny, 1.0 / nz)
+    kw = dict(bc_x=NEU, bc_y=NEU)
+    u, v, w = inputs.uniform_velocity(nx, ny, nz, NEU, 8)
+    du, dv, dw = (torch.from_numpy(x).cuda() for x in (u, v, w))
+    with P.Plan(nx, ny, nz, *sp, NEU, "fp32_refine", **kw) as plan:
+        psi, st = plan.project(du, dv, dw, None)
+        torch.cuda.synchronize()
+    assert st["status"] == 0
+    f = orc.divergence(u, v, w, *sp, NEU, **kw)
+    res, _ = orc.residual(f, psi.cpu().numpy(), *sp, NEU, **kw)
+    print(f"[project] cavity full size: residual {res:.2e} {st}", flush=True)
+    assert res <= 1e-10
+    d1 = orc.divergence(du.cpu().numpy(), dv.cpu().numpy(), dw.cpu().numpy(), *sp, NEU, **kw)
+    assert np.abs(d1).max() <= 1e-9 * np.abs(f).max()
