@@ -18,6 +18,11 @@
 // returns nx (x[2n] + i x[2n+1]) (unnormalised, like the forward pass), which
 // is stored to p or added to it in FP64.
 //
+// Walls along x (the XW kernel variants): the rows are expanded in the
+// cosine or sine modes of the wall condition through the same half spectrum
+// of the reordered row (see wall_emit / wall_load below).  The projection
+// step's forward pass takes the divergence of the face velocities as input.
+//
 // Compiled once per precision with PK_REAL = float or double.
 #include "fft_core.hpp"
 #include "lengths.hpp"

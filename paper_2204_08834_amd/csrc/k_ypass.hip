@@ -7,7 +7,8 @@
 // transforms its NB columns S[k, :, m0:m0+NB] along y.  A wavefront's loads
 // and stores are runs of NB contiguous complex values per y-row (128 B at the
 // default tile), so the pass streams HBM once in and once out.
-// The inverse is conj(FFT(conj)).
+// The inverse is conj(FFT(conj)).  With walls along y the columns are
+// expanded in cosine or sine modes instead (k_yw below).
 #include "fft_core.hpp"
 #include "lengths.hpp"
 
@@ -87,10 +88,12 @@ __global__ __launch_bounds__((YCfg<N, V>::NT)) void k_y(YArgs a0)
 //                    like the periodic pass: 1/ny is applied in the z step);
 //   inverse sine:    the inverse cosine transform of C'[k] = S[n-1-k], times
 //                    (-1)^j.
-// The forward FFT's last pass writes back into its LDS tile (the pass
-// synchronises between its reads and its writes), from which the pairs
-// (k, n-k) are combined and stored.  Row runs of 128 bytes as in the periodic
-// pass, narrower only where the tile and two N-entry tables would not fit.
+// Forward: the last Stockham pass takes butterfly pairs (p, NJ - p), so V[k]
+// and V[n-k] meet in one thread and the coefficients are stored from
+// registers (lengths whose last pass has an odd number of butterflies store
+// the FFT back into the LDS tile and combine the pairs from there).  Inverse:
+// W is formed as pass 0 loads it.  Row runs of 128 bytes as in the periodic
+// pass, narrower only where the tile and the tables would not fit.
 template <int N> struct YWCfg {
     static constexpr int NB0 = sizeof(R) == 4 ? 16 : 8;
     // one NB x N tile (plus padding) and the N-entry twiddle table within
@@ -135,7 +138,7 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
     load_table(s_tw, (const Cx<R> *)a.tw, N);
     if constexpr (C::W4_LDS) load_table(s_w4l, (const Cx<R> *)a.tw4, N);
     __syncthreads();
-    auto s_w4 = [&]() {
+    auto w4 = [&]() {
         if constexpr (C::W4_LDS)
             return (const Cx<R> *)s_w4l;
         else
@@ -167,11 +170,11 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
             constexpr int RAD = LR, NJ = N / LR, U = NJ / 2, NU = NB * U;
             constexpr int PER = (NU + NT - 1) / NT;
             auto emit = [&](int b, int kk, Cx<R> vk, Cx<R> vc) {
-                const Cx<R> w = s_w4[kk];
+                const Cx<R> w = w4[kk];
                 put(base + (size_t)(sine ? N - 1 - kk : kk) * M + b,
                     cscale(cadd(cmul(w, vk), cmul(cconj(w), vc)), R(0.5)));
                 if (kk != 0 && 2 * kk != N) {
-                    const Cx<R> w2 = s_w4[N - kk];
+                    const Cx<R> w2 = w4[N - kk];
                     put(base + (size_t)(sine ? kk - 1 : N - kk) * M + b,
                         cscale(cadd(cmul(w2, vc), cmul(cconj(w2), vk)), R(0.5)));
                 }
@@ -217,7 +220,7 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
             for (int e = threadIdx.x; e < NB * N; e += NT) {
                 const int b = e % NB, kk = e / NB;
                 if (m0 + b >= M) continue;
-                const Cx<R> w = s_w4[kk];
+                const Cx<R> w = w4[kk];
                 const Cx<R> v1 = out.at(b, kk), v2 = out.at(b, kk == 0 ? 0 : N - kk);
                 const Cx<R> c = cscale(cadd(cmul(w, v1), cmul(cconj(w), v2)), R(0.5));
                 put(base + (size_t)(sine ? N - 1 - kk : kk) * M + b, c);
@@ -235,7 +238,7 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
         auto gload = [&](int b, int n) -> Cx<R> {
             if (m0 + b >= M) return {R(0), R(0)};
             const Cx<R> c1 = coef(b, n), c2 = n == 0 ? Cx<R>{R(0), R(0)} : coef(b, N - n);
-            return cconj(cmul(cconj(s_w4[n]), csub(c1, cmul_pi(c2))));
+            return cconj(cmul(cconj(w4[n]), csub(c1, cmul_pi(c2))));
         };
         auto gstore = [&](int b, int n, Cx<R> v) {
             if (m0 + b >= M) return;
