@@ -105,13 +105,17 @@ template <int N> struct YWCfg {
     // the padding column of tiles with 8 or more lines must fit as well
     static constexpr int NB = (NB2 >= 8 && N * (NB2 + 2) > ELEMS) ? NB2 / 2 : NB2;
     static constexpr int NT = pick_nt(NB * N, sizeof(R) == 4 ? 16 : 8);
-    static constexpr int PAD = (NB >= 8) ? 1 : 0;
-    // the exp(-i pi k/(2n)) table goes to LDS unless it would cost a resident
-    // workgroup per CU (then it is read through the caches)
-    static constexpr int BASE_B = (N * (NB + PAD) + N) * (int)sizeof(Cx<R>);
+    // the exp(-i pi k/(2n)) table goes to LDS; the padding column of the tile
+    // is dropped where that keeps a resident workgroup per CU
     static constexpr int LDS_CU = 160 * 1024;
-    static constexpr bool W4_LDS =
-        LDS_CU / (BASE_B + N * (int)sizeof(Cx<R>)) == LDS_CU / BASE_B;
+    static constexpr int PAD0 = (NB >= 8) ? 1 : 0;
+    static constexpr int B_PAD = (N * (NB + PAD0) + 2 * N) * (int)sizeof(Cx<R>);
+    static constexpr int B_NOPAD = (N * NB + 2 * N) * (int)sizeof(Cx<R>);
+    static constexpr int B_GLB = (N * (NB + PAD0) + N) * (int)sizeof(Cx<R>);
+    static constexpr bool FITS_PAD = LDS_CU / B_PAD == LDS_CU / B_GLB;
+    static constexpr bool FITS_NOPAD = LDS_CU / B_NOPAD == LDS_CU / B_GLB;
+    static constexpr int PAD = FITS_PAD ? PAD0 : (FITS_NOPAD ? 0 : PAD0);
+    static constexpr bool W4_LDS = FITS_PAD || FITS_NOPAD;
 };
 
 __device__ __forceinline__ int wall_reorder(int j, int n) { return 2 * j < n ? 2 * j : 2 * n - 1 - 2 * j; }
