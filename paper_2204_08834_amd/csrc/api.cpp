@@ -959,23 +959,53 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
 // ---------------------------------------------------------------------------
 // device-side refinement loop (poisson_plan_set_graph)
 // ---------------------------------------------------------------------------
-// Loop segments per graph: a residual evaluation and, when the control kernel
-// says so, one correction.  A problem that needs more corrections gets
-// further launches of the segment-only graph.
+// Loop segments per graph: one correction (when the control kernel says so)
+// followed by the residual evaluation that decides on the next.  A problem
+// that needs more corrections gets further launches of the segment-only
+// graph.
 constexpr int GRAPH_SEGMENTS = 2;
+// segments after the head: a problem that converges after one correction
+// (the usual case) ends the first round with no gated-off launch but the
+// unused kind of residual pass
+constexpr int HEAD_SEGMENTS = 1;
+
+// full residual pass [C_FULL] | residual check [C_CHECK, optional]
+// | sums + control decision [C_EVAL]
+int enqueue_residual_decision(poisson_plan p, LSet &L, bool with_check)
+{
+    Group &g = *L.g;
+    int rc;
+    L.gate = C_FULL;
+    if ((rc = pass_x_fwd(L, true, true, false))) return rc;
+    if (with_check) {
+        L.gate = C_CHECK;
+        if ((rc = pass_residual_check(L, false))) return rc;
+    }
+    // partial records of whichever residual pass ran for each problem
+    const int nr = x_fwd_blocks(P_F32, g.d.nx, g.d.ny, g.d.nz, 1, g.tune.kr);
+    const int nc = residual_check_blocks(g.d.nx, g.d.ny, g.d.nz, g.tune.kr);
+    rc = timed(p, "sum_partials", (double)(nr > nc ? nr : nc) * 32.0 * L.n, [&] {
+        return launch_sum_partials(nullptr, nr, nullptr, L.dev, L.n, 2, p->ls, C_EVAL, 2,
+                                   p->rtol, p->max_refine, nc);
+    });
+    L.gate = 0;
+    return rc;
+}
 
 // The launch sequence of the device-side loop for one group, on the stream
 // p->ls.  head: the first solve, whose sum of f also opens the control
-// records; then GRAPH_SEGMENTS segments of
-//   full residual pass [C_FULL] | residual check [C_CHECK]
-//   | sums + control decision [C_EVAL]
-//   | full residual pass after a failed check [C_FIX]
+// records, and the first residual (always the full pass); then segments of
+//   full residual pass after a failed check [C_FIX]
 //   | y, z, y, accumulating x [C_CORRECT]
+//   | full residual pass [C_FULL] | residual check [C_CHECK]
+//   | sums + control decision [C_EVAL]
+// (HEAD_SEGMENTS after the head, GRAPH_SEGMENTS otherwise).  The first
+// segment after the head has no fix: the decision before it followed a
+// full residual pass.
 int enqueue_group_sequence(poisson_plan p, LSet &L, bool head, bool segs = true)
 {
     const bool refine = p->precision == POISSON_FP32_REFINE;
     const int prec = internal_prec(p->precision);
-    Group &g = *L.g;
     int rc = POISSON_OK;
     if (head) {
         L.gate = 0;
@@ -985,25 +1015,18 @@ int enqueue_group_sequence(poisson_plan p, LSet &L, bool head, bool segs = true)
         if (rc) return rc;
     }
     if (!refine || !segs) return POISSON_OK;
-    for (int seg = 0; seg < GRAPH_SEGMENTS; ++seg) {
-        L.gate = C_FULL;
-        if ((rc = pass_x_fwd(L, true, true, false))) return rc;
-        L.gate = C_CHECK;
-        if ((rc = pass_residual_check(L, false))) return rc;
-        // partial records of whichever residual pass ran for each problem
-        const int nr = x_fwd_blocks(P_F32, g.d.nx, g.d.ny, g.d.nz, 1, g.tune.kr);
-        const int nc = residual_check_blocks(g.d.nx, g.d.ny, g.d.nz, g.tune.kr);
-        rc = timed(p, "sum_partials", (double)(nr > nc ? nr : nc) * 32.0 * L.n, [&] {
-            return launch_sum_partials(nullptr, nr, nullptr, L.dev, L.n, 2, p->ls, C_EVAL,
-                                       2, p->rtol, p->max_refine, nc);
-        });
-        if (rc) return rc;
-        L.gate = C_FIX;
-        if ((rc = pass_x_fwd(L, true, true, false))) return rc;
+    if (head && (rc = enqueue_residual_decision(p, L, false))) return rc;
+    const int nseg = head ? HEAD_SEGMENTS : GRAPH_SEGMENTS;
+    for (int seg = 0; seg < nseg; ++seg) {
+        if (!(head && seg == 0)) {
+            L.gate = C_FIX;
+            if ((rc = pass_x_fwd(L, true, true, false))) return rc;
+        }
         L.gate = C_CORRECT;
         if ((rc = correction_passes(L))) return rc;
-        L.gate = 0;
+        if ((rc = enqueue_residual_decision(p, L, true))) return rc;
     }
+    L.gate = 0;
     return POISSON_OK;
 }
 

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpoisson.so")
@@ -312,15 +313,36 @@ class BatchPlan:
             raise PoissonError(rc, "poisson_batch_plan_create")
         self._h = h
         self.count = n
+        self._validated = None
+
+    def _pointers(self, rhs_list, out_list):
+        """Device pointers of the right-hand sides and outputs, after the
+        checks of every tensor (float64, GPU, contiguous, the problem's
+        shape).  A call with the same tensor objects as the previous one,
+        unchanged in place (data pointers, shapes and contiguity), skips the
+        per-tensor checks, which otherwise cost more than the launches of a
+        small batch."""
+        n = self.count
+        if len(rhs_list) != n or len(out_list) != n:
+            raise ValueError("one rhs and one output per problem")
+        ts = [*rhs_list, *out_list]
+        try:
+            sig = [(t.data_ptr(), t.shape, t.is_contiguous()) for t in ts]
+        except (AttributeError, TypeError):
+            sig = None
+        last = self._validated
+        if (sig is None or last is None or sig != last[1]
+                or not all(r() is t for r, t in zip(last[0], ts))):
+            self._validated = None
+            for i, (r, o) in enumerate(zip(rhs_list, out_list)):
+                _check_field(r, self.shapes[i], f"rhs[{i}]")
+                _check_field(o, self.shapes[i], f"out[{i}]")
+            self._validated = ([weakref.ref(t) for t in ts], sig)
+        ptrs = [x[0] for x in sig]
+        return (ctypes.c_void_p * n)(*ptrs[:n]), (ctypes.c_void_p * n)(*ptrs[n:])
 
     def solve(self, rhs_list, out_list, check=True):
-        if len(rhs_list) != self.count or len(out_list) != self.count:
-            raise ValueError("one rhs and one output per problem")
-        for i, (r, o) in enumerate(zip(rhs_list, out_list)):
-            _check_field(r, self.shapes[i], f"rhs[{i}]")
-            _check_field(o, self.shapes[i], f"out[{i}]")
-        R = (ctypes.c_void_p * self.count)(*[r.data_ptr() for r in rhs_list])
-        O = (ctypes.c_void_p * self.count)(*[o.data_ptr() for o in out_list])
+        R, O = self._pointers(rhs_list, out_list)
         st = (Stats * self.count)()
         rc = lib().poisson_batch_solve(self._h, R, O, st)
         if check and rc != OK:

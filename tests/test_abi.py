@@ -136,3 +136,21 @@ def test_project_rejects_null_plan_and_fields():
     fake = ctypes.c_void_p(0x1000)
     assert L.poisson_project(None, fake, fake, fake, None, fake, 1.0, 1.0,
                              ctypes.byref(st)) == P.ERR_INVALID_ARG
+
+
+def test_batch_argument_checks_are_not_cached_on_failure():
+    """The batch binding caches a successful check of its tensors only: a
+    rejected call is rejected again, whatever came before it."""
+    torch = pytest.importorskip("torch")
+    bp = P.BatchPlan.__new__(P.BatchPlan)
+    bp._h, bp.count, bp._validated = None, 2, None
+    bp.shapes = [(4, 4, 4), (2, 4, 6)]
+    cpu = [torch.zeros(s, dtype=torch.float64) for s in bp.shapes]
+    for _ in range(2):
+        with pytest.raises(ValueError, match="GPU"):
+            bp._pointers(cpu, cpu)
+        assert bp._validated is None
+    with pytest.raises(TypeError):
+        bp._pointers(["not a tensor", cpu[1]], cpu)
+    with pytest.raises(ValueError, match="one rhs"):
+        bp._pointers(cpu[:1], cpu)

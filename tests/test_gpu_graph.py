@@ -155,3 +155,40 @@ def test_mode_switch_and_invalid_mode():
             plan.set_graph(3)
         torch.cuda.synchronize()
     assert torch.equal(a, b) and torch.equal(a, c)
+
+
+def test_batch_rechecks_changed_arguments():
+    """Calls with the same tensors as the previous call skip the per-tensor
+    checks; a tensor replaced in the list, or changed in place, is checked
+    again, and the results of the repeated calls agree."""
+    P = _gpu()
+    probs = _mixed()[:2]
+    specs = [dict(nx=p.nx, ny=p.ny, nz=p.nz, dx=p.dx, dy=p.dy, dz=p.dz, bc_z=p.bc_z)
+             for p in probs]
+    rhs = [torch.from_numpy(p.f).cuda() for p in probs]
+    outs = [torch.empty_like(r) for r in rhs]
+    bp = P.BatchPlan(specs, "fp64")
+    try:
+        bp.solve(rhs, outs)
+        first = [o.clone() for o in outs]
+        bp.solve(rhs, outs)
+        assert all(torch.equal(a, b) for a, b in zip(first, outs))
+        good = outs[1]
+        bad = [torch.empty(3, 3, 3, dtype=torch.float64, device="cuda"),  # shape
+               torch.empty_like(good, dtype=torch.float32),  # dtype
+               torch.empty_like(good).transpose(0, 2),  # not contiguous
+               torch.empty_like(good, device="cpu")]  # not on the GPU
+        for t in bad:
+            with pytest.raises((ValueError, TypeError)):
+                bp.solve(rhs, [outs[0], t])
+        # the same tensor object, changed in place
+        keep = good.data
+        good.data = torch.empty(3, 3, 3, dtype=torch.float64, device="cuda")
+        with pytest.raises(ValueError):
+            bp.solve(rhs, outs)
+        good.data = keep
+        bp.solve(rhs, outs)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(first, outs))
+    finally:
+        bp.close()
