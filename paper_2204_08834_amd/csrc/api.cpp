@@ -592,6 +592,10 @@ struct LSet {
     int sum_mode = 0;  // control step taken by the sum of the forward x pass
 };
 
+// problems that share the plane-range choice of the residual passes: the
+// whole group in a batched launch, whichever of them a launch still serves
+int kr_group(const LSet &L) { return L.dev ? (int)L.g->members.size() : 1; }
+
 int pass_x_fwd(LSet &L, bool residual, bool want_partials, bool sum = true)
 {
     Group &g = *L.g;
@@ -619,6 +623,7 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials, bool sum = true)
     a.residual = residual ? 1 : 0;
     a.gate = L.gate;
     a.kr_max = g.tune.kr;
+    a.kr_nb = kr_group(L);
     a.regular = regular(g.d) ? 1 : 0;
     char name[40];
     snprintf(name, sizeof name, residual ? "x_r2c_residual_%s" : "x_r2c_%s", tag(L.prec));
@@ -677,6 +682,7 @@ int pass_residual_check(LSet &L, bool sum = true)
     a.residual = 1;
     a.gate = L.gate;
     a.kr_max = g.tune.kr;
+    a.kr_nb = kr_group(L);
     a.regular = regular(g.d) ? 1 : 0;
     int nc = 0;
     int rc = timed(L.p, "residual_check_f64", (double)g.N * 16.0 * L.n,
@@ -982,8 +988,8 @@ int enqueue_residual_decision(poisson_plan p, LSet &L, bool with_check)
         if ((rc = pass_residual_check(L, false))) return rc;
     }
     // partial records of whichever residual pass ran for each problem
-    const int nr = x_fwd_blocks(P_F32, g.d.nx, g.d.ny, g.d.nz, 1, g.tune.kr);
-    const int nc = residual_check_blocks(g.d.nx, g.d.ny, g.d.nz, g.tune.kr);
+    const int nr = x_fwd_blocks(P_F32, g.d.nx, g.d.ny, g.d.nz, 1, g.tune.kr, kr_group(L));
+    const int nc = residual_check_blocks(g.d.nx, g.d.ny, g.d.nz, g.tune.kr, kr_group(L));
     rc = timed(p, "sum_partials", (double)(nr > nc ? nr : nc) * 32.0 * L.n, [&] {
         return launch_sum_partials(nullptr, nr, nullptr, L.dev, L.n, 2, p->ls, C_EVAL, 2,
                                    p->rtol, p->max_refine, nc);

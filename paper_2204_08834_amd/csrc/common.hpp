@@ -156,6 +156,7 @@ struct XFwdArgs {
     int reverse;            // walk the row blocks from the end (see block_order)
     int gate;               // control slot gating this launch (0: none)
     int kr_max;             // residual passes: z-planes per workgroup (0: default)
+    int kr_nb;              // residual passes: problems of the group (march_planes)
     int regular;            // a Dirichlet wall: no null space, f keeps its mean
     // divergence input (residual == 2; one problem): f = cx Dx u + cy Dy v + cz Dz w
     const double *u, *v, *w;
@@ -229,7 +230,7 @@ int launch_z_walls(int prec, const ZArgs &a, hipStream_t s);
 int launch_z_periodic(int prec, const ZArgs &a, hipStream_t s);
 // number of workgroups the forward x pass uses (size of its partials array);
 // `residual` selects the residual pass of the refinement
-int x_fwd_blocks(int prec, int nx, int ny, int nz, int residual, int kr_max);
+int x_fwd_blocks(int prec, int nx, int ny, int nz, int residual, int kr_max, int kr_nb = 1);
 // Deterministic FP64 sums of the x pass's partials: `n` workgroups with three
 // sums each (stride 4), written to out[0..3).  Batched: one workgroup per
 // problem, partials and scal taken from batch[i], written to scal + out_off.
@@ -245,7 +246,7 @@ int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *ba
 // write): per-workgroup sums of r^2, (f - mean f)^2 and p into `partials`
 // (same layout as the forward x pass), for a convergence check.
 int launch_residual_check(const XFwdArgs &a, int *nblocks_out, hipStream_t s);
-int residual_check_blocks(int nx, int ny, int nz, int kr_max);
+int residual_check_blocks(int nx, int ny, int nz, int kr_max, int kr_nb = 1);
 
 // Velocity correction and pressure update of the projection step:
 // u -= bx Dx+ psi, v -= by Dy+ psi, w -= bz Dz+ psi (not on a top wall),

@@ -18,8 +18,8 @@ int launch_z_walls_f32(const ZArgs &, hipStream_t);
 int launch_z_walls_f64(const ZArgs &, hipStream_t);
 int launch_z_periodic_f32(const ZArgs &, hipStream_t);
 int launch_z_periodic_f64(const ZArgs &, hipStream_t);
-int x_fwd_blocks_f32(int, int, int, int, int);
-int x_fwd_blocks_f64(int, int, int, int, int);
+int x_fwd_blocks_f32(int, int, int, int, int, int);
+int x_fwd_blocks_f64(int, int, int, int, int, int);
 
 int launch_x_fwd(int prec, const XFwdArgs &a, int *nblocks_out, hipStream_t s)
 {
@@ -41,10 +41,10 @@ int launch_z_periodic(int prec, const ZArgs &a, hipStream_t s)
 {
     return prec == P_F32 ? launch_z_periodic_f32(a, s) : launch_z_periodic_f64(a, s);
 }
-int x_fwd_blocks(int prec, int nx, int ny, int nz, int residual, int kr_max)
+int x_fwd_blocks(int prec, int nx, int ny, int nz, int residual, int kr_max, int kr_nb)
 {
-    return prec == P_F32 ? x_fwd_blocks_f32(nx, ny, nz, residual, kr_max)
-                         : x_fwd_blocks_f64(nx, ny, nz, residual, kr_max);
+    return prec == P_F32 ? x_fwd_blocks_f32(nx, ny, nz, residual, kr_max, kr_nb)
+                         : x_fwd_blocks_f64(nx, ny, nz, residual, kr_max, kr_nb);
 }
 
 #define PK_IS(N) case N: return true;
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(RC_NT) void k_residual_check(XFwdArgs a0)
     const int njb = march_jblocks(a.ny, TJ);
     const int bid = block_order(xcd_order(blockIdx.x, gridDim.x), gridDim.x, a.reverse);
     const int jb = bid % njb, kb = bid / njb;
-    const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max);
+    const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max, a.kr_nb);
     const int k0 = kb * kr;
     const int k1 = k0 + kr < a.nz ? k0 + kr : a.nz;
     Mar m;
@@ -230,30 +230,31 @@ __global__ __launch_bounds__(RC_NT) void k_residual_check(XFwdArgs a0)
     }
 }
 
-template <int M> static int rc_blocks(int ny, int nz, int kr_max)
+template <int M> static int rc_blocks(int ny, int nz, int kr_max, int kr_nb)
 {
-    return march_jblocks(ny, march_rows(M)) * march_kblocks(ny, nz, march_rows(M), kr_max);
+    return march_jblocks(ny, march_rows(M)) *
+           march_kblocks(ny, nz, march_rows(M), kr_max, kr_nb);
 }
 
 template <int M> static int run_rc(const XFwdArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_residual_check<M>,
-                       dim3(rc_blocks<M>(a.ny, a.nz, a.kr_max), a.batch ? a.nbatch : 1),
+                       dim3(rc_blocks<M>(a.ny, a.nz, a.kr_max, a.kr_nb), a.batch ? a.nbatch : 1),
                        dim3(RC_NT), 0, s, a);
     return (int)hipGetLastError();
 }
 
-#define PK_CASE_RCB(N) case N: return rc_blocks<N>(ny, nz, kr_max);
+#define PK_CASE_RCB(N) case N: return rc_blocks<N>(ny, nz, kr_max, kr_nb);
 #define PK_CASE_RC(N) case N: return run_rc<N>(a, s);
 
-int residual_check_blocks(int nx, int ny, int nz, int kr_max)
+int residual_check_blocks(int nx, int ny, int nz, int kr_max, int kr_nb)
 {
     switch (nx / 2) { PK_X_LENGTHS(PK_CASE_RCB) default: return -1; }
 }
 
 int launch_residual_check(const XFwdArgs &a, int *nblocks_out, hipStream_t s)
 {
-    if (nblocks_out) *nblocks_out = residual_check_blocks(a.nx, a.ny, a.nz, a.kr_max);
+    if (nblocks_out) *nblocks_out = residual_check_blocks(a.nx, a.ny, a.nz, a.kr_max, a.kr_nb);
     switch (a.nx / 2) { PK_X_LENGTHS(PK_CASE_RC) default: return -1; }
 }
 

@@ -422,7 +422,7 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
     const int njb = march_jblocks(a.ny, TJ);
     const int bid = block_order(xcd_order(blockIdx.x, gridDim.x), gridDim.x, a.reverse);
     const int jb = bid % njb, kb = bid / njb;
-    const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max);
+    const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max, a.kr_nb);
     const int k0 = kb * kr;
     const int k1 = k0 + kr < a.nz ? k0 + kr : a.nz;
 
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(XD_NT) void k_x_div(XFwdArgs a0)
     const int njb = march_jblocks(a.ny, TJ);
     const int bid = xcd_order(blockIdx.x, gridDim.x);
     const int jb = bid % njb, kb = bid / njb;
-    const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max);
+    const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max, a.kr_nb);
     const int k0 = kb * kr;
     const int k1 = k0 + kr < a.nz ? k0 + kr : a.nz;
 
@@ -781,11 +781,11 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
 
 // row blocks of the plain pass (an upper bound of its workgroup count), or
 // the workgroups of the residual pass
-template <int M> static int blocks_x(int ny, int nz, int residual, int kr_max)
+template <int M> static int blocks_x(int ny, int nz, int residual, int kr_max, int kr_nb)
 {
     if (residual)  // residual and divergence passes: the same plane march
         return march_jblocks(ny, march_rows_res(M)) *
-               march_kblocks(ny, nz, march_rows_res(M), kr_max);
+               march_kblocks(ny, nz, march_rows_res(M), kr_max, kr_nb);
     return (ny * nz + XCfg<M>::NB - 1) / XCfg<M>::NB;
 }
 
@@ -817,7 +817,7 @@ template <int M, bool XW> static int grid_x_fwd(int nblk, int nbatch)
 template <int M> static int run_x_fwd(const XFwdArgs &a, hipStream_t s, int *nblocks_out)
 {
     const bool xw = a.bc_x != 0;
-    int nb = blocks_x<M>(a.ny, a.nz, a.residual, a.kr_max);
+    int nb = blocks_x<M>(a.ny, a.nz, a.residual, a.kr_max, a.kr_nb);
     if (!a.residual) nb = xw ? grid_x_fwd<M, true>(nb, a.batch ? a.nbatch : 1)
                              : grid_x_fwd<M, false>(nb, a.batch ? a.nbatch : 1);
     if (nblocks_out) *nblocks_out = nb;
@@ -872,7 +872,7 @@ using namespace PK_NS;
 
 #define PK_CASE_FWD(N) case N: return run_x_fwd<N>(a, s, nblocks_out);
 #define PK_CASE_INV(N) case N: return run_x_inv<N>(a, s);
-#define PK_CASE_BLK(N) case N: return blocks_x<N>(ny, nz, residual, kr_max);
+#define PK_CASE_BLK(N) case N: return blocks_x<N>(ny, nz, residual, kr_max, kr_nb);
 
 int PK_SUFFIX(launch_x_fwd)(const XFwdArgs &a, hipStream_t s, int *nblocks_out)
 {
@@ -884,7 +884,7 @@ int PK_SUFFIX(launch_x_inv)(const XInvArgs &a, hipStream_t s)
     switch (a.nx / 2) { PK_X_LENGTHS(PK_CASE_INV) default: return -1; }
 }
 
-int PK_SUFFIX(x_fwd_blocks)(int nx, int ny, int nz, int residual, int kr_max)
+int PK_SUFFIX(x_fwd_blocks)(int nx, int ny, int nz, int residual, int kr_max, int kr_nb)
 {
     switch (nx / 2) { PK_X_LENGTHS(PK_CASE_BLK) default: return -1; }
 }

@@ -32,18 +32,22 @@ constexpr int march_rows_res(int M) { return march_rows(M, 1024); }
 __host__ __device__ constexpr int march_jblocks(int ny, int tj) { return (ny + tj - 1) / tj; }
 
 // z-planes per workgroup: kr_max (8 by default, a tuning knob; 0 means the
-// default), halved (down to 1) while a problem would get fewer than 1024
-// workgroups, so that small grids still fill the device.  Each range
-// re-reads two planes of p, so deeper ranges read less.
-__host__ __device__ constexpr int march_planes(int ny, int nz, int tj, int kr_max)
+// default), halved (down to 1) while the nb problems of a batched launch
+// would get fewer than 1024 workgroups together, so that small grids still
+// fill the device.  nb is the size of the problem group, not the number of
+// problems a launch still serves, so that every launch of the group tiles
+// and sums the same way.  Each range re-reads two planes of p, so deeper
+// ranges read less.
+__host__ __device__ constexpr int march_planes(int ny, int nz, int tj, int kr_max, int nb = 1)
 {
     int kr = kr_max > 0 ? kr_max : 8;
-    while (kr > 1 && march_jblocks(ny, tj) * ((nz + kr - 1) / kr) < 1024) kr /= 2;
+    const int b = nb > 1 ? nb : 1;
+    while (kr > 1 && march_jblocks(ny, tj) * ((nz + kr - 1) / kr) * b < 1024) kr /= 2;
     return kr;
 }
-__host__ __device__ constexpr int march_kblocks(int ny, int nz, int tj, int kr_max)
+__host__ __device__ constexpr int march_kblocks(int ny, int nz, int tj, int kr_max, int nb = 1)
 {
-    const int kr = march_planes(ny, nz, tj, kr_max);
+    const int kr = march_planes(ny, nz, tj, kr_max, nb);
     return (nz + kr - 1) / kr;
 }
 

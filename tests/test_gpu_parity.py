@@ -304,13 +304,19 @@ def _mixed_small():
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine", "fp32"])
 def test_batch_equals_single_solves(precision):
-    """A mixed-shape batch gives bitwise the same fields as one plan per problem."""
+    """A mixed-shape batch gives the fields of one plan per problem: bitwise
+    for the plain solves; with refinement, the residual sums of a batched
+    group are blocked by the group's size, so the mean of p (a constant
+    removed from the field) may differ by rounding: within 1e-14 max|p|."""
     probs = _mixed_small()
     rc, stats, outs = _batch_problems(probs, precision)
     assert rc == 0, stats
     for prob, st, p in zip(probs, stats, outs):
         q, st1 = gpu_solve(prob.f, *prob.spacings(), prob.bc_z, precision)
-        assert np.array_equal(p, q), (prob.name, rel(p, q))
+        if precision == "fp32_refine":
+            assert np.max(np.abs(p - q)) <= 1e-14 * np.max(np.abs(q)), (prob.name, rel(p, q))
+        else:
+            assert np.array_equal(p, q), (prob.name, rel(p, q))
         assert st["iterations"] == st1["iterations"]
         assert abs(st["rhs_mean"] - st1["rhs_mean"]) <= 1e-15
 

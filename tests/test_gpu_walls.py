@@ -60,6 +60,17 @@ def kappa(nx, ny, nz, sp, bcs):
     return lmax / lmin
 
 
+def same_field(batched, single, prec, case):
+    """A batched problem against its own plan: bitwise for the plain solves;
+    with refinement the residual sums of a batched group are blocked by the
+    group's size, so the mean of p (a constant removed from the field) may
+    differ by rounding."""
+    if prec == "fp32_refine":
+        assert np.max(np.abs(batched - single)) <= 1e-14 * np.max(np.abs(single)), (prec, case)
+    else:
+        assert np.array_equal(batched, single), (prec, case)
+
+
 def gpu_solve(P, f, sp, bcs, prec, mode="host", rtol=1e-10):
     nz, ny, nx = f.shape
     with P.Plan(nx, ny, nz, *sp, bcs[2], prec, rtol=rtol, bc_x=bcs[0], bc_y=bcs[1]) as plan:
@@ -173,7 +184,7 @@ def test_batch_mixing_neumann_and_dirichlet(orc):
         assert rc == 0
         for (f, bc), o, st in zip(fs, outs, stats):
             single, _ = gpu_solve(P, f, sp, (PER, PER, bc), prec)
-            assert np.array_equal(o.cpu().numpy(), single), (prec, bc)
+            same_field(o.cpu().numpy(), single, prec, bc)
             if prec == "fp64":
                 assert rel(single, orc.solve(f, *sp, bc)) <= 1e-12
             assert (st["rhs_mean"] == 0.0) == (bc == DIR)
@@ -391,7 +402,7 @@ def test_batch_of_boxes(orc):
         assert rc == 0
         for f, c, o in zip(fs, kinds, outs):
             single, _ = gpu_solve(P, f, sp, c, prec)
-            assert np.array_equal(o.cpu().numpy(), single), (prec, c)
+            same_field(o.cpu().numpy(), single, prec, c)
             if prec == "fp64":
                 ref = orc.solve(f, *sp, c[2], bc_x=c[0], bc_y=c[1])
                 assert rel(single, ref) <= 1e-12, c
