@@ -279,15 +279,15 @@ def copy_calibration(steps, warmup):
 
 # kernel-name patterns of the solver's passes (rocprofv3 reports demangled names)
 PASS_PATTERNS = [
-    ("x_r2c_residual_{p}", r"prec_{p}::k_x_res<\d+, false>"),
-    ("x_r2c_residual_walls_{p}", r"prec_{p}::k_x_res<\d+, true>"),
+    ("x_r2c_residual_{p}", r"prec_{p}::k_x_res<\d+, false[,>]"),
+    ("x_r2c_residual_walls_{p}", r"prec_{p}::k_x_res<\d+, true[,>]"),
     ("x_r2c_divergence_{p}", r"prec_{p}::k_x_div<"),
     ("x_r2c_{p}", r"prec_{p}::k_x_fwd<\d+, false>"),
     ("x_r2c_walls_{p}", r"prec_{p}::k_x_fwd<\d+, true>"),
-    ("x_c2r_accumulate_{p}", r"prec_{p}::k_x_inv<\d+, true, false>"),
-    ("x_c2r_accumulate_walls_{p}", r"prec_{p}::k_x_inv<\d+, true, true>"),
-    ("x_c2r_{p}", r"prec_{p}::k_x_inv<\d+, false, false>"),
-    ("x_c2r_walls_{p}", r"prec_{p}::k_x_inv<\d+, false, true>"),
+    ("x_c2r_accumulate_{p}", r"prec_{p}::k_x_inv<\d+, true, false[,>]"),
+    ("x_c2r_accumulate_walls_{p}", r"prec_{p}::k_x_inv<\d+, true, true[,>]"),
+    ("x_c2r_{p}", r"prec_{p}::k_x_inv<\d+, false, false[,>]"),
+    ("x_c2r_walls_{p}", r"prec_{p}::k_x_inv<\d+, false, true[,>]"),
     ("y_fwd_{p}", r"prec_{p}::k_y<\d+, false[,>]"),
     ("y_inv_{p}", r"prec_{p}::k_y<\d+, true[,>]"),
     ("y_fwd_walls_{p}", r"prec_{p}::k_yw<\d+, false>"),

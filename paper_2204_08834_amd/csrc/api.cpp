@@ -318,6 +318,7 @@ struct Group {
     Tables tab;
     std::vector<int> members;          // problem indices in the plan
     std::shared_ptr<DevBuf> S32;       // FP32 spectra, one per member
+    std::shared_ptr<DevBuf> P32;       // refinement: FP32 first iterates, one per member
     std::shared_ptr<DevBuf> partials;  // per-workgroup partial sums, part_stride per member
     int npart = 0;                     // workgroups of the forward x pass (upper bound)
     int part_stride = 0;               // doubles of partials per member
@@ -466,6 +467,7 @@ size_t workspace_bytes(const poisson_desc_t *d)
     const size_t n = (size_t)d->nx * d->ny * d->nz;
     size_t b = 0;
     if (d->precision != POISSON_FP64) b += n * 4;  // FP32 half spectrum: N/2 complex floats
+    if (d->precision == POISSON_FP32_REFINE) b += n * 4;  // FP32 first iterate
     b += (size_t)partial_slots(*d) * 4 * sizeof(double);
     return b;
 }
@@ -513,8 +515,10 @@ int build_group(Group &g)
     if ((rc = upload(t.lamz, lz.data(), lz.size() * 8))) return rc;
     const size_t n = g.members.size();
     if (f32 && (rc = dev_alloc(g.S32, (size_t)g.N * 4 * n))) return rc;
+    // the first iterate of the refinement is an FP32 field: kept exactly in
+    // 4 B/point, it is written and read back at half the bytes
     const bool refine = d.precision == POISSON_FP32_REFINE;
-    (void)refine;
+    if (refine && (rc = dev_alloc(g.P32, (size_t)g.N * 4 * n))) return rc;
     g.npart = x_fwd_blocks(internal_prec(d.precision), d.nx, d.ny, d.nz, 0, 0);
     g.part_stride = partial_slots(d) * 4;
     if ((rc = dev_alloc(g.partials, (size_t)g.part_stride * sizeof(double) * n))) return rc;
@@ -590,6 +594,11 @@ struct LSet {
     ProbPtrs one;
     int gate = 0;      // control slot gating the passes (device-side loop)
     int sum_mode = 0;  // control step taken by the sum of the forward x pass
+    // refinement: the first solve writes its iterate to the FP32 copy
+    // (use32); while the current iterate is that copy (cur32) the residual
+    // pass reads it and the next accumulating pass reads it and writes p
+    bool use32 = false;
+    bool cur32 = false;
 };
 
 // problems that share the plane-range choice of the residual passes: the
@@ -625,9 +634,11 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials, bool sum = true)
     a.kr_max = g.tune.kr;
     a.kr_nb = kr_group(L);
     a.regular = regular(g.d) ? 1 : 0;
+    a.p_in32 = residual && L.cur32 ? 1 : 0;
+    a.p32 = L.one.p32;
     char name[40];
     snprintf(name, sizeof name, residual ? "x_r2c_residual_%s" : "x_r2c_%s", tag(L.prec));
-    double bytes = (double)g.N * ((residual ? 16.0 : 8.0) + sb) * L.n;
+    double bytes = (double)g.N * ((residual ? (a.p_in32 ? 12.0 : 16.0) : 8.0) + sb) * L.n;
     const bool div = !residual && L.p->projecting;
     if (div) {
         // projection: f = alpha D(u, v, w) evaluated on the fly (one problem)
@@ -662,6 +673,8 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials, bool sum = true)
 int pass_residual_check(LSet &L, bool sum = true)
 {
     Group &g = *L.g;
+    // a check follows a correction, which left the iterate in p
+    if (L.cur32) return hip_fail("residual check of the FP32 first iterate", -1);
     XFwdArgs a{};
     a.batch = L.dev;
     a.nbatch = L.n;
@@ -754,14 +767,22 @@ int pass_x_inv(LSet &L, bool accumulate)
                g.d.ny, g.d.nz, accumulate ? 1 : 0, g.tune.rev, nullptr,
                1.0 / (double)g.N, L.gate, regular(g.d) ? 1 : 0, g.d.bc_x,
                g.d.bc_x != POISSON_BC_PERIODIC ? g.tab.twx4[L.prec == P_F32 ? 1 : 0]->p
-                                               : nullptr};
+                                               : nullptr,
+               0, L.one.p32};
+    // the plain pass of the first solve writes the FP32 copy; the first
+    // accumulating pass reads it
+    const bool in32 = accumulate ? L.cur32 : L.use32;
+    a.p_in32 = in32 ? 1 : 0;
     // the mean of p from the residual pass (batched launches redirect it)
     if (accumulate) a.sum_p = L.dev ? (const double *)g.partials->p : L.one.scal + 4;
     char name[40];
     snprintf(name, sizeof name, accumulate ? "x_c2r_accumulate_%s" : "x_c2r_%s", tag(L.prec));
     const double sb = L.prec == P_F32 ? 4.0 : 8.0;
-    const double bytes = (double)g.N * (sb + (accumulate ? 16.0 : 8.0)) * L.n;
-    return timed(L.p, name, bytes, [&] { return launch_x_inv(L.prec, a, L.p->ls); });
+    const double pin = in32 ? 4.0 : 8.0;  // bytes of the iterate read or written in FP32 / FP64
+    const double bytes = (double)g.N * (sb + (accumulate ? pin + 8.0 : pin)) * L.n;
+    const int rc = timed(L.p, name, bytes, [&] { return launch_x_inv(L.prec, a, L.p->ls); });
+    if (!rc) L.cur32 = accumulate ? false : in32;
+    return rc;
 }
 
 // transform of the right-hand side (or residual), z solve, inverse transform
@@ -813,6 +834,7 @@ ProbPtrs problem_ptrs(poisson_plan p, const Group &g, int slot, const double *rh
     q.partials = (double *)g.partials->p + (size_t)g.part_stride * slot;
     q.scal = (double *)p->scalars->p + NSCAL * i;
     q.ctrl = p->ctrl + NCTRL * i;
+    q.p32 = g.P32 ? (float *)((char *)g.P32->p + (size_t)g.N * 4 * slot) : nullptr;
     return q;
 }
 
@@ -863,6 +885,7 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
     int rc = POISSON_OK;
     for (size_t gi = 0; gi < p->groups.size() && !rc; ++gi) {
         sets[gi] = LSet{p, &p->groups[gi], prec, nullptr, 0, {}};
+        sets[gi].use32 = p->groups[gi].P32 != nullptr;
         active[gi].resize(p->groups[gi].members.size());
         for (size_t k = 0; k < active[gi].size(); ++k) active[gi][k] = (int)k;
         rc = stage((int)gi);
@@ -922,6 +945,15 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
                     if (status != -1) {
                         out[i].status = status;
                         state[i] = DONE;
+                        // stopped before any correction: the solution is the
+                        // first iterate, still in its FP32 copy
+                        if (sets[gi].cur32 && !rc) {
+                            const ProbPtrs q =
+                                problem_ptrs(p, p->groups[gi], slot, rhs[i], sol[i]);
+                            const int e = launch_widen(q.p32, sol[i],
+                                                       (size_t)p->groups[gi].N, p->ls);
+                            if (e) rc = hip_fail("first iterate widening", e);
+                        }
                     } else {
                         rho_prev[i] = rho;
                         corrections[i] += 1;
@@ -1141,6 +1173,9 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
             staging[g.host_off + k] = problem_ptrs(p, g, k, rhs[i], sol[i]);
         }
         sets[gi] = LSet{p, &g, prec, (const ProbPtrs *)p->dptrs->p + g.host_off, n, {}};
+        // the projection under capture issues its first solve eagerly and
+        // continues with the segment-only graph, which reads the iterate in p
+        sets[gi].use32 = g.P32 != nullptr && !(capture && p->projecting);
     }
     if (!p->dptrs_valid ||
         memcmp(p->dptrs_copy.data(), staging, sizeof(ProbPtrs) * count) != 0) {

@@ -71,6 +71,19 @@ __device__ __forceinline__ void st_stream(PK_GLOBAL double *p, double2 a)
     const pk_d2v v = {a.x, a.y};
     __builtin_nontemporal_store(v, (PK_GLOBAL pk_d2v *)p);
 }
+// the same for a pair held in FP32 (widened / narrowed exactly by callers
+// whose values are FP32 numbers)
+typedef float pk_f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_stream(const PK_GLOBAL float *p)
+{
+    const pk_f2v v = __builtin_nontemporal_load((const PK_GLOBAL pk_f2v *)p);
+    return double2{(double)v.x, (double)v.y};
+}
+__device__ __forceinline__ void st_stream(PK_GLOBAL float *p, double2 a)
+{
+    const pk_f2v v = {(float)a.x, (float)a.y};
+    __builtin_nontemporal_store(v, (PK_GLOBAL pk_f2v *)p);
+}
 
 enum Prec { P_F64 = 0, P_F32 = 1 };
 
@@ -110,6 +123,7 @@ struct ProbPtrs {
                        // [3] sum (f - mean)^2, [4] sum p, [5] relative residual,
                        // [6] previous relative residual, [7] first relative residual
     int *ctrl;         // refinement control record (device-side loop), CtrlSlot
+    float *p32;        // refinement: the first iterate, exactly, in FP32 (or null)
 };
 
 // Device-side control of the refinement loop: one record of NCTRL ints per
@@ -126,7 +140,8 @@ enum CtrlSlot {
     C_CORRECT = 5,  // run the correction passes
     C_CORR = 6,     // corrections applied so far
     C_STATUS = 7,   // final status (poisson error code)
-    NCTRL = 8
+    C_COPY = 8,     // done before any correction: the solution is the first iterate
+    NCTRL = 9
 };
 
 __device__ __forceinline__ bool gated_off(const ProbPtrs *batch, int gate, int i)
@@ -157,6 +172,8 @@ struct XFwdArgs {
     int gate;               // control slot gating this launch (0: none)
     int kr_max;             // residual passes: z-planes per workgroup (0: default)
     int kr_nb;              // residual passes: problems of the group (march_planes)
+    int p_in32;             // residual pass: p is the FP32 first iterate (p32 / batch[i].p32)
+    const float *p32;
     int regular;            // a Dirichlet wall: no null space, f keeps its mean
     // divergence input (residual == 2; one problem): f = cx Dx u + cy Dy v + cz Dz w
     const double *u, *v, *w;
@@ -180,6 +197,11 @@ struct XInvArgs {
     int regular;            // a Dirichlet wall: the mean of p is kept
     int bc_x;               // 0 periodic, 1 Neumann walls (cosines), 2 Dirichlet walls (sines)
     const void *tw4x;       // walls along x: exp(-i pi k/(2 nx)), k in [0, nx)
+    // refinement with the first iterate kept in FP32: the plain pass writes
+    // it to p32; the accumulating pass reads it from p32 and writes p (or,
+    // for a problem whose control record says C_COPY, only widens p32 to p)
+    int p_in32;
+    float *p32;
 };
 
 // Strided complex pass along y, in place on S.
@@ -247,6 +269,8 @@ int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *ba
 // (same layout as the forward x pass), for a convergence check.
 int launch_residual_check(const XFwdArgs &a, int *nblocks_out, hipStream_t s);
 int residual_check_blocks(int nx, int ny, int nz, int kr_max, int kr_nb = 1);
+// dst[i] = (double)src[i], i < n (device arrays)
+int launch_widen(const float *src, double *dst, size_t n, hipStream_t s);
 
 // Velocity correction and pressure update of the projection step:
 // u -= bx Dx+ psi, v -= by Dy+ psi, w -= bz Dz+ psi (not on a top wall),

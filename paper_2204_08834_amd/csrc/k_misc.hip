@@ -101,6 +101,7 @@ __device__ __forceinline__ void ctrl_open(int *c, double *sc)
     c[C_CORRECT] = 0;
     c[C_CORR] = 0;
     c[C_STATUS] = POISSON_OK;
+    c[C_COPY] = 0;
     sc[5] = -1.0;
     sc[6] = -1.0;
     sc[7] = -1.0;
@@ -123,6 +124,7 @@ __device__ __forceinline__ void ctrl_decide(int *c, double *sc, double rtol, int
         c[C_STATUS] = status;
         c[C_STATE] = 0;
         c[C_FULL] = c[C_CHECK] = c[C_EVAL] = c[C_FIX] = c[C_CORRECT] = 0;
+        c[C_COPY] = c[C_CORR] == 0 ? 1 : 0;
         return;
     }
     sc[6] = rho;
@@ -308,6 +310,24 @@ template <int M> static int run_correct(const CorrArgs &a, hipStream_t s)
 }
 
 #define PK_CASE_CO(N) case N: return run_correct<N>(a, s);
+
+// p = p32 widened to FP64 (the refinement's first iterate as the solution of
+// a problem that stopped before any correction), n points
+__global__ __launch_bounds__(256) void k_widen(const float *src, double *dst, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        dst[i] = (double)src[i];
+}
+
+int launch_widen(const float *src, double *dst, size_t n, hipStream_t s)
+{
+    if (!src || !dst || n == 0) return (int)hipErrorInvalidValue;
+    const size_t want = (n + 255) / 256;
+    const int nb = (int)(want < 4096 ? want : 4096);
+    hipLaunchKernelGGL(k_widen, dim3(nb), dim3(256), 0, s, src, dst, n);
+    return (int)hipGetLastError();
+}
 
 int launch_correct(const CorrArgs &a, hipStream_t s)
 {

@@ -24,6 +24,8 @@
 // step's forward pass takes the divergence of the face velocities as input.
 //
 // Compiled once per precision with PK_REAL = float or double.
+#include <type_traits>
+
 #include "fft_core.hpp"
 #include "lengths.hpp"
 #include "stencil.hpp"
@@ -394,10 +396,11 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
 // march of stencil.hpp, rounded once to the transform precision, packed as
 // z[h] = r[2h] + i r[2h+1] into the LDS tile (which aliases the march's plane
 // tile) and transformed in place; per-workgroup FP64 sums of r^2,
-// (f - mu)^2 and p go to `partials`.  r never touches HBM.
+// (f - mu)^2 and p go to `partials`.  r never touches HBM.  P32: p is the
+// refinement's first iterate, read from its exact FP32 copy.
 constexpr int XR_NT = 256;
 
-template <int M, bool XW>
+template <int M, bool XW, bool P32>
 __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
 {
     if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
@@ -406,12 +409,14 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
         const ProbPtrs &q = a.batch[blockIdx.y];
         a.f = q.f;
         a.p = q.p;
+        a.p32 = q.p32;
         a.S = q.S;
         a.partials = q.partials;
         a.sum_f = q.scal + 1;
     }
     constexpr int TJ = march_rows_res(M), NT = XR_NT, NX = 2 * M;
-    using Mar = PlaneMarch<M, TJ, NT>;
+    using PT = typename std::conditional<P32, float, double>::type;
+    using Mar = PlaneMarch<M, TJ, NT, PT>;
     using Tile = LdsTile<R, M, TJ, false, 0>;
     constexpr size_t PLANE_B = sizeof(double2) * (TJ + 2) * M;
     constexpr size_t FFT_B = sizeof(Cx<R>) * Tile::elems;
@@ -428,7 +433,10 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
 
     Mar m;
     m.f = gbl(a.f);
-    m.p = gbl(a.p);
+    if constexpr (P32)
+        m.p = gbl(a.p32);
+    else
+        m.p = gbl(a.p);
     m.ax = a.ax;
     m.ay = a.ay;
     m.az = a.az;
@@ -584,15 +592,31 @@ __global__ __launch_bounds__(XD_NT) void k_x_div(XFwdArgs a0)
     }
 }
 
-template <int M, bool ACC, bool XW>
+template <int M, bool ACC, bool XW, bool P32>
 __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
 {
-    if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
+    // P32: the first iterate lives in FP32 (a.p32); the plain pass writes it
+    // there, the accumulating pass reads it there and writes p.  A problem
+    // of the device-side loop that stopped before any correction (C_COPY)
+    // gets p = p32 widened instead.
+    bool widen_only = false;
+    if constexpr (P32 && ACC) {
+        if (a0.batch && a0.gate) {
+            const int *c = a0.batch[blockIdx.y].ctrl;
+            if (c[C_CORRECT] == 0) {
+                if (c[C_COPY] == 0) return;
+                widen_only = true;
+            }
+        }
+    } else {
+        if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
+    }
     XInvArgs a = a0;
     if (a.batch) {
         const ProbPtrs &q = a.batch[blockIdx.y];
         a.S = q.S;
         a.p = q.p;
+        a.p32 = q.p32;
         if (ACC && a.sum_p) a.sum_p = q.scal + 4;
     }
     // accumulate mode also removes the mean of the previous iterate (the
@@ -606,11 +630,21 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
 
     const int nrows = a.ny * a.nz;
     const int row0 = block_order(blockIdx.x, gridDim.x, a.reverse) * NB;
+    PK_GLOBAL double *gp = gbl(a.p);
+    PK_GLOBAL float *gp32 = gbl(a.p32);
+    if (widen_only) {  // uniform over the workgroup
+        for (int e = threadIdx.x; e < NB * M; e += NT) {
+            const int row = row0 + e / M;
+            if (row >= nrows) break;
+            const size_t o = (size_t)row * NX + 2 * (e % M);
+            st_stream(gp + o, ld_stream(gp32 + o));
+        }
+        return;
+    }
     load_table(s_tw, (const Cx<R> *)a.tw, NX);
     __syncthreads();
 
     const PK_GLOBAL Cx<R> *S = gbl((const Cx<R> *)a.S);
-    PK_GLOBAL double *gp = gbl(a.p);
     const bool sine = a.bc_x == 2;
     const PK_GLOBAL Cx<R> *w4 = XW ? gbl((const Cx<R> *)a.tw4x) : nullptr;
     auto gstore = [&](int b, int n, Cx<R> v) {
@@ -625,21 +659,30 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
                 o.y = (i1 & 1) ? -o.y : o.y;
             }
             PK_GLOBAL double *rp = gp + (size_t)row * NX;
+            PK_GLOBAL float *rp32 = gp32 + (size_t)row * NX;
             if constexpr (ACC) {
-                o.x += rp[i0] - pmean;
-                o.y += rp[i1] - pmean;
+                o.x += (P32 ? (double)rp32[i0] : rp[i0]) - pmean;
+                o.y += (P32 ? (double)rp32[i1] : rp[i1]) - pmean;
             }
-            rp[i0] = o.x;
-            rp[i1] = o.y;
+            if constexpr (P32 && !ACC) {
+                rp32[i0] = (float)o.x;
+                rp32[i1] = (float)o.y;
+            } else {
+                rp[i0] = o.x;
+                rp[i1] = o.y;
+            }
             return;
         }
-        PK_GLOBAL double *dst = gp + (size_t)row * NX + 2 * n;
+        const size_t di = (size_t)row * NX + 2 * n;
         if constexpr (ACC) {
-            const double2 old = ld_stream(dst);
+            const double2 old = P32 ? ld_stream(gp32 + di) : ld_stream(gp + di);
             o.x += old.x - pmean;
             o.y += old.y - pmean;
         }
-        st_stream(dst, o);
+        if constexpr (P32 && !ACC)
+            st_stream(gp32 + di, o);
+        else
+            st_stream(gp + di, o);
     };
     // spectrum value m of a row: the packed half spectrum, or for walls the
     // inverse input formed from the cosine / sine coefficients
@@ -664,7 +707,10 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
                 const int e = threadIdx.x + q * NT;
                 const int row = row0 + e / M;
                 old[q] = {0.0, 0.0};
-                if (e < NB * M && row < nrows) old[q] = ld_stream(gp + (size_t)row * NX + 2 * (e % M));
+                if (e < NB * M && row < nrows) {
+                    const size_t oi = (size_t)row * NX + 2 * (e % M);
+                    old[q] = P32 ? ld_stream(gp32 + oi) : ld_stream(gp + oi);
+                }
             }
         }
 #pragma unroll
@@ -684,7 +730,10 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
                 o.x += old[q].x - pmean;
                 o.y += old[q].y - pmean;
             }
-            st_stream(gp + (size_t)row * NX + 2 * h, o);
+            if constexpr (P32 && !ACC)
+                st_stream(gp32 + (size_t)row * NX + 2 * h, o);
+            else
+                st_stream(gp + (size_t)row * NX + 2 * h, o);
         }
     };
     // reversed radix order: the small radix first gives more butterfly pairs
@@ -831,10 +880,16 @@ template <int M> static int run_x_fwd(const XFwdArgs &a, hipStream_t s, int *nbl
     } else if (a.residual) {
         // the refinement transforms its residual in FP32 only
         if constexpr (sizeof(R) == 4) {
-            if (xw)
-                hipLaunchKernelGGL((k_x_res<M, true>), grid, dim3(XR_NT), 0, s, a);
-            else
-                hipLaunchKernelGGL((k_x_res<M, false>), grid, dim3(XR_NT), 0, s, a);
+            if (a.p_in32) {
+                if (xw)
+                    hipLaunchKernelGGL((k_x_res<M, true, true>), grid, dim3(XR_NT), 0, s, a);
+                else
+                    hipLaunchKernelGGL((k_x_res<M, false, true>), grid, dim3(XR_NT), 0, s, a);
+            } else if (xw) {
+                hipLaunchKernelGGL((k_x_res<M, true, false>), grid, dim3(XR_NT), 0, s, a);
+            } else {
+                hipLaunchKernelGGL((k_x_res<M, false, false>), grid, dim3(XR_NT), 0, s, a);
+            }
         } else {
             return -1;
         }
@@ -852,16 +907,33 @@ template <int M> static int run_x_inv(const XInvArgs &a, hipStream_t s)
     const int nb = (nrows + XCfg<M>::NB - 1) / XCfg<M>::NB;
     const dim3 grid(nb, a.batch ? a.nbatch : 1);
     const bool xw = a.bc_x != 0;
-    if (a.accumulate) {
+    if (a.p_in32) {
+        // the refinement keeps its first iterate in FP32 only
+        if constexpr (sizeof(R) == 4) {
+            if (a.accumulate) {
+                if (xw)
+                    hipLaunchKernelGGL((k_x_inv<M, true, true, true>), grid, dim3(XCfg<M>::NT), 0, s, a);
+                else
+                    hipLaunchKernelGGL((k_x_inv<M, true, false, true>), grid, dim3(XCfg<M>::NT), 0, s, a);
+            } else {
+                if (xw)
+                    hipLaunchKernelGGL((k_x_inv<M, false, true, true>), grid, dim3(XCfg<M>::NT), 0, s, a);
+                else
+                    hipLaunchKernelGGL((k_x_inv<M, false, false, true>), grid, dim3(XCfg<M>::NT), 0, s, a);
+            }
+        } else {
+            return -1;
+        }
+    } else if (a.accumulate) {
         if (xw)
-            hipLaunchKernelGGL((k_x_inv<M, true, true>), grid, dim3(XCfg<M>::NT), 0, s, a);
+            hipLaunchKernelGGL((k_x_inv<M, true, true, false>), grid, dim3(XCfg<M>::NT), 0, s, a);
         else
-            hipLaunchKernelGGL((k_x_inv<M, true, false>), grid, dim3(XCfg<M>::NT), 0, s, a);
+            hipLaunchKernelGGL((k_x_inv<M, true, false, false>), grid, dim3(XCfg<M>::NT), 0, s, a);
     } else {
         if (xw)
-            hipLaunchKernelGGL((k_x_inv<M, false, true>), grid, dim3(XCfg<M>::NT), 0, s, a);
+            hipLaunchKernelGGL((k_x_inv<M, false, true, false>), grid, dim3(XCfg<M>::NT), 0, s, a);
         else
-            hipLaunchKernelGGL((k_x_inv<M, false, false>), grid, dim3(XCfg<M>::NT), 0, s, a);
+            hipLaunchKernelGGL((k_x_inv<M, false, false, false>), grid, dim3(XCfg<M>::NT), 0, s, a);
     }
     return (int)hipGetLastError();
 }

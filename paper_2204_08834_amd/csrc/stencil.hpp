@@ -126,7 +126,19 @@ struct MarchIdx {
     }
 };
 
-template <int M, int TJ, int NT>
+// an element pair of p as FP64: p stored in FP64, or (the refinement's first
+// iterate) in FP32, widened exactly
+__device__ __forceinline__ double2 ld_pair(const PK_GLOBAL double *p)
+{
+    return *(const PK_GLOBAL double2 *)p;
+}
+__device__ __forceinline__ double2 ld_pair(const PK_GLOBAL float *p)
+{
+    const float2 v = *(const PK_GLOBAL float2 *)p;
+    return double2{(double)v.x, (double)v.y};
+}
+
+template <int M, int TJ, int NT, class PT = double>
 struct PlaneMarch : MarchIdx<M, TJ, NT> {
     using B = MarchIdx<M, TJ, NT>;
     using B::PER;
@@ -142,7 +154,8 @@ struct PlaneMarch : MarchIdx<M, TJ, NT> {
     using B::jn;
     using B::V;
 
-    const PK_GLOBAL double *f, *p;  // set through gbl()
+    const PK_GLOBAL double *f;  // set through gbl()
+    const PK_GLOBAL PT *p;
     double ax, ay, az, mu;
     double2 (*tile)[M];  // LDS, TJ + 2 rows
     double2 pd[PER], pc[PER];
@@ -152,16 +165,16 @@ struct PlaneMarch : MarchIdx<M, TJ, NT> {
     // branch-free loads.
     __device__ __forceinline__ void start(int k0)
     {
-        const PK_GLOBAL double *pdn = p + (size_t)kdown(k0) * plane;
-        const PK_GLOBAL double *pcn = p + (size_t)k0 * plane;
+        const PK_GLOBAL PT *pdn = p + (size_t)kdown(k0) * plane;
+        const PK_GLOBAL PT *pcn = p + (size_t)k0 * plane;
         // below a Dirichlet bottom wall the ghost plane is -p(0)
         const double gs = (k0 == 0 && this->bc_z == 2) ? -1.0 : 1.0;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int o = roff(q);
-            const double2 x = *(const PK_GLOBAL double2 *)(pdn + o);
+            const double2 x = ld_pair(pdn + o);
             pd[q] = double2{gs * x.x, gs * x.y};
-            pc[q] = *(const PK_GLOBAL double2 *)(pcn + o);
+            pc[q] = ld_pair(pcn + o);
         }
     }
 
@@ -171,23 +184,23 @@ struct PlaneMarch : MarchIdx<M, TJ, NT> {
     template <class Sink>
     __device__ __forceinline__ void step(int k, Sink &sink)
     {
-        const PK_GLOBAL double *pup = p + (size_t)kup(k) * plane;
+        const PK_GLOBAL PT *pup = p + (size_t)kup(k) * plane;
         const PK_GLOBAL double *fk = f + (size_t)k * plane;
-        const PK_GLOBAL double *pk_ = p + (size_t)k * plane;
+        const PK_GLOBAL PT *pk_ = p + (size_t)k * plane;
         // above a Dirichlet top wall the ghost plane is -p(nz-1)
         const double gs = (k == this->nz - 1 && this->bc_z == 2) ? -1.0 : 1.0;
         double2 pu[PER], fv[PER];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int o = roff(q);
-            const double2 x = *(const PK_GLOBAL double2 *)(pup + o);
+            const double2 x = ld_pair(pup + o);
             pu[q] = double2{gs * x.x, gs * x.y};
             fv[q] = *(const PK_GLOBAL double2 *)(fk + o);
         }
         const double sm = this->sm, sn = this->sn;
         for (int h = threadIdx.x; h < M; h += NT) {
-            const double2 a = *(const PK_GLOBAL double2 *)(pk_ + (size_t)jm * NX + 2 * h);
-            const double2 b = *(const PK_GLOBAL double2 *)(pk_ + (size_t)jn * NX + 2 * h);
+            const double2 a = ld_pair(pk_ + (size_t)jm * NX + 2 * h);
+            const double2 b = ld_pair(pk_ + (size_t)jn * NX + 2 * h);
             tile[0][h] = double2{sm * a.x, sm * a.y};
             tile[V + 1][h] = double2{sn * b.x, sn * b.y};
         }

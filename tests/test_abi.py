@@ -112,9 +112,12 @@ def test_workspace_bytes():
     d64 = P.make_desc(512, 512, 256, precision="fp64")
     d32 = P.make_desc(512, 512, 256, precision="fp32_refine")
     n = 512 * 512 * 256
-    # FP64 works in place in the solution array; FP32 needs a 4 B/point spectrum
+    # FP64 works in place in the solution array; FP32 needs a 4 B/point
+    # spectrum, and the refinement a 4 B/point copy of its first iterate
+    d32p = P.make_desc(512, 512, 256, precision="fp32")
     assert P.workspace_bytes(d64) < 1 << 20
-    assert n * 4 <= P.workspace_bytes(d32) < n * 4.1
+    assert n * 4 <= P.workspace_bytes(d32p) < n * 4.1
+    assert n * 8 <= P.workspace_bytes(d32) < n * 8.1
 
 
 def test_set_graph_rejects_null_plan():

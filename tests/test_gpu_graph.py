@@ -192,3 +192,47 @@ def test_batch_rechecks_changed_arguments():
         assert all(torch.equal(a, b) for a, b in zip(first, outs))
     finally:
         bp.close()
+
+
+@pytest.mark.parametrize("mode", ["host", "device", "graph"])
+@pytest.mark.parametrize("bcs", [(PER, PER, NEU), (NEU, NEU, NEU)])
+def test_stop_before_any_correction_returns_first_iterate(mode, bcs):
+    """The refinement keeps its first iterate in an exact FP32 copy.  A
+    problem whose first residual already meets rtol stops there: the
+    solution is that iterate, widened exactly, i.e. bitwise the plain FP32
+    solve (same kernels, same tuned variants), whatever the output array
+    held before."""
+    P = _gpu()
+    prob = inputs.scaled("rb512", 48, 24, 20, seed=61)
+    sp = prob.spacings()
+    rhs = torch.from_numpy(prob.f).cuda()
+    print(f"[graph] first iterate {mode} {bcs}", flush=True)
+    with P.Plan(48, 24, 20, *sp, bcs[2], "fp32", bc_x=bcs[0], bc_y=bcs[1]) as plan:
+        ref, _ = plan.solve(rhs)
+    with P.Plan(48, 24, 20, *sp, bcs[2], "fp32_refine", rtol=1e-3, bc_x=bcs[0],
+                bc_y=bcs[1]) as plan:
+        plan.set_graph(mode)
+        for _ in range(2):
+            out = torch.full_like(rhs, float("nan"))
+            out, st = plan.solve(rhs, out)
+            torch.cuda.synchronize()
+            assert st["status"] == 0 and st["iterations"] == 0, st
+            assert 0 < st["rel_residual"] <= 1e-3
+            assert torch.equal(out, ref)
+
+
+@pytest.mark.parametrize("mode", ["host", "device", "graph"])
+def test_batch_with_a_zero_problem(mode):
+    """A zero right-hand side converges at its first residual (the zero
+    iterate) while the others of its group go on: its solution is zero and
+    the others equal the host loop's bitwise."""
+    probs = _mixed()
+    probs[1].f = np.zeros_like(probs[1].f)
+    rc_h, st_h, p_h = _batch(probs, "fp32_refine", "host")
+    rc, st, outs = _batch(probs, "fp32_refine", mode)
+    assert rc == rc_h == 0
+    assert st[1]["iterations"] == 0 and st[1]["status"] == 0
+    assert not np.any(outs[1])
+    for a, b, sa, sb in zip(p_h, outs, st_h, st):
+        assert np.array_equal(a, b)
+        assert sa == sb
