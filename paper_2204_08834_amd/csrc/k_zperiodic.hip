@@ -29,7 +29,9 @@ template <int N> struct ZPCfg {
     static constexpr int MAXE = sizeof(R) == 4 ? 16384 : 8192;
     static constexpr int NB1 = (NB0 * N <= MAXE) ? NB0 : ((MAXE / N) < 2 ? 2 : MAXE / N);
     static constexpr int NB = NB1 & ~1;  // even: the m = 0 role works on column pairs
-    static constexpr int NT = pick_nt(NB * N, sizeof(R) == 4 ? 16 : 8);
+    // short columns: one butterfly per thread and pass (more waves in flight
+    // for the small problems of a batch), else up to 16 FP32 elements each
+    static constexpr int NT = pick_nt(NB * N, (sizeof(R) == 4 && N > 64) ? 16 : 8);
     static constexpr int PAD = (NB >= 8) ? 1 : 0;
 };
 
