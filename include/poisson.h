@@ -121,7 +121,11 @@ int poisson_desc_init(poisson_desc_t *d);
 int poisson_desc_validate(const poisson_desc_t *d);
 
 /* Device workspace bytes a plan for this descriptor allocates (tables
- * excluded).  Host only; 0 on an invalid descriptor. */
+ * excluded): none field-sized for FP64 (the transforms run in place in the
+ * solution array); 4 B per point for FP32 (the FP32 spectrum); 8 B per point
+ * for FP32_REFINE (the spectrum and an exact FP32 copy of the first
+ * iterate); plus the per-workgroup partial-sum records.  Host only; 0 on an
+ * invalid descriptor. */
 size_t poisson_workspace_bytes(const poisson_desc_t *d);
 
 /* Create a plan: validates d, builds FP64 twiddle and eigenvalue tables on
