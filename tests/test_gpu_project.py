@@ -279,3 +279,42 @@ def test_project_cavity_full_size(orc):
     assert res <= 1e-10
     d1 = orc.divergence(du.cpu().numpy(), dv.cpu().numpy(), dw.cpu().numpy(), *sp, NEU, **kw)
     assert np.abs(d1).max() <= 1e-9 * np.abs(f).max()
+
+
+@pytest.mark.parametrize("first", ["project", "solve"])
+def test_graph_plan_alternating_project_and_solve(first):
+    """One graph-mode FP32 + refinement plan serves projections and plain
+    solves in either order.  The projection takes its first solve eagerly
+    and the segment-only graph, keeping the first iterate in FP64; a plain
+    solve captures the first-round graph, which keeps it in its FP32 copy.
+    Every call equals the host loop bitwise."""
+    P = _gpu()
+    nx, ny, nz, bc = 32, 24, 16, NEU
+    sp = (BOX[0] / nx, BOX[1] / ny, BOX[2] / nz)
+    u, v, w, _ = _fields(nx, ny, nz, bc, 21)
+    f = torch.from_numpy(inputs.random_rhs(nx, ny, nz, seed=22)).cuda()
+    print(f"[project] alternating, {first} first", flush=True)
+
+    def calls(mode):
+        res = []
+        with P.Plan(nx, ny, nz, *sp, bc, "fp32_refine") as plan:
+            plan.set_graph(mode)
+            order = ["project", "solve"] if first == "project" else ["solve", "project"]
+            for what in order * 2:
+                if what == "project":
+                    du, dv, dw = (torch.from_numpy(x.copy()).cuda() for x in (u, v, w))
+                    psi, st = plan.project(du, dv, dw, None, alpha=2.0, beta=0.5)
+                    out = [t.cpu().numpy() for t in (du, dv, dw, psi)]
+                else:
+                    p, st = plan.solve(f)
+                    out = [p.cpu().numpy()]
+                torch.cuda.synchronize()
+                assert st["status"] == 0 and st["rel_residual"] <= 1e-10, (what, st)
+                res.append((what, out, st))
+        return res
+
+    host, graph = calls("host"), calls("graph")
+    for (w1, o1, s1), (w2, o2, s2) in zip(host, graph):
+        assert w1 == w2 and s1 == s2, (w1, s1, s2)
+        for a, b in zip(o1, o2):
+            assert np.array_equal(a, b), w1
