@@ -673,8 +673,12 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials, bool sum = true)
 int pass_residual_check(LSet &L, bool sum = true)
 {
     Group &g = *L.g;
-    // a check follows a correction, which left the iterate in p
-    if (L.cur32) return hip_fail("residual check of the FP32 first iterate", -1);
+    // a check follows a correction, which left the iterate in p; the loops
+    // never ask for a check of the first iterate
+    if (L.cur32) {
+        fprintf(stderr, "libpoisson: residual check requested for the FP32 first iterate\n");
+        return POISSON_ERR_HIP;
+    }
     XFwdArgs a{};
     a.batch = L.dev;
     a.nbatch = L.n;
