@@ -8,6 +8,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -1074,15 +1075,24 @@ int enqueue_group_sequence(poisson_plan p, LSet &L, bool head, bool segs = true)
 
 // All groups, each on a stream of its own forked from the plan's loop
 // stream and joined back (in a captured graph: independent branches), so
-// that the launches of problems of different shapes overlap.
+// that the launches of problems of different shapes overlap.  The host
+// issues the groups with the most points first: the longest sequence starts
+// while the launches of the others are still being issued.
 int enqueue_device_sequence(poisson_plan p, std::vector<LSet> &sets, bool head,
                             bool segs = true)
 {
     const size_t ng = sets.size();
     int rc = POISSON_OK;
+    std::vector<size_t> order(ng);
+    for (size_t gi = 0; gi < ng; ++gi) order[gi] = gi;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+        const Group &ga = *sets[a].g, &gb = *sets[b].g;
+        return (double)ga.N * ga.members.size() > (double)gb.N * gb.members.size();
+    });
     if (ng > 1 && hipEventRecord(p->ev_fork, p->gstream) != hipSuccess)
         return hip_fail("stream fork", (int)hipGetLastError());
-    for (size_t gi = 0; gi < ng && !rc; ++gi) {
+    for (size_t oi = 0; oi < ng && !rc; ++oi) {
+        const size_t gi = order[oi];
         p->ls = gi == 0 ? p->gstream : p->side[gi - 1];
         if (gi > 0 && hipStreamWaitEvent(p->ls, p->ev_fork, 0) != hipSuccess) {
             rc = hip_fail("stream fork", (int)hipGetLastError());
