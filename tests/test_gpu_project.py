@@ -318,3 +318,31 @@ def test_graph_plan_alternating_project_and_solve(first):
         assert w1 == w2 and s1 == s2, (w1, s1, s2)
         for a, b in zip(o1, o2):
             assert np.array_equal(a, b), w1
+
+
+@pytest.mark.parametrize("mode", ["host", "device", "graph"])
+def test_project_stopping_at_first_iterate(mode):
+    """A projection whose refinement meets rtol at its first residual uses
+    the first (FP32) iterate as psi, widened exactly: every field equals the
+    plain FP32 projection bitwise, in every loop mode (the device loop widens
+    inside its gated accumulating pass; under capture the projection keeps
+    the iterate in FP64)."""
+    P = _gpu()
+    nx, ny, nz, bc = 32, 24, 16, NEU
+    sp = (BOX[0] / nx, BOX[1] / ny, BOX[2] / nz)
+    u, v, w, p0 = _fields(nx, ny, nz, bc, 31)
+    print(f"[project] first iterate {mode}", flush=True)
+
+    def run(prec, m, rtol):
+        du, dv, dw, dp = (torch.from_numpy(x.copy()).cuda() for x in (u, v, w, p0))
+        with P.Plan(nx, ny, nz, *sp, bc, prec, rtol=rtol) as plan:
+            plan.set_graph(m)
+            psi, st = plan.project(du, dv, dw, dp, alpha=2.0, beta=0.5)
+            torch.cuda.synchronize()
+        return [t.cpu().numpy() for t in (du, dv, dw, dp, psi)], st
+
+    ref, _ = run("fp32", "host", 1e-10)
+    out, st = run("fp32_refine", mode, 1e-3)
+    assert st["status"] == 0 and st["iterations"] == 0, st
+    for a, b in zip(ref, out):
+        assert np.array_equal(a, b)
