@@ -456,8 +456,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU; multi-GPU runs are not supported "
-              "(the slab-decomposed design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU; multi-GPU runs are not supported "
+              "(a slab decomposition with all-to-all transposes would be the way to shard it)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
