@@ -178,8 +178,11 @@ int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *ba
 // Residual of the discrete equation, r = (f - mean f) - L p, in FP64 (the
 // 7-point operator of the marker-and-cell grid, 2.5-D march of stencil.hpp):
 // streams f and p once and writes three partial sums per workgroup: sum r^2,
-// sum (f - mean f)^2, sum p.
-constexpr int RC_NT = 256;
+// sum (f - mean f)^2, sum p.  512 threads share a plane tile of about 2048
+// pairs (4 per thread): 118 VGPRs and four waves per SIMD at nx = 512, where
+// 256 threads (8 pairs each) needed 200 and ran two (212 -> 207 us at
+// 512x512x256).
+constexpr int RC_NT = 512;
 
 template <int M>
 __global__ __launch_bounds__(RC_NT) void k_residual_check(XFwdArgs a0)
