@@ -265,8 +265,9 @@ int launch_residual_check(const XFwdArgs &a, int *nblocks_out, hipStream_t s)
 
 // Velocity correction and pressure update of the projection step
 // (CorrMarch of stencil.hpp): streams psi once (plus halos) and u, v, w and p
-// once each way.
-constexpr int CO_NT = 256;
+// once each way.  512 threads per plane tile of about 1024 pairs (two each):
+// at nx = 512 98 VGPRs and four waves per SIMD, against 182 and two with 256.
+constexpr int CO_NT = 512;
 
 // about 1024 pairs per plane tile: each element holds six double2 (psi at
 // k and k+1, u, v, w, p) in registers

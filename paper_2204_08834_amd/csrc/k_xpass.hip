@@ -397,7 +397,10 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
 // z[h] = r[2h] + i r[2h+1] into the LDS tile (which aliases the march's plane
 // tile) and transformed in place; per-workgroup FP64 sums of r^2,
 // (f - mu)^2 and p go to `partials`.  r never touches HBM.  P32: p is the
-// refinement's first iterate, read from its exact FP32 copy.
+// refinement's first iterate, read from its exact FP32 copy.  256 threads:
+// with 512 the transform leaves threads idle and the pass is slower (237
+// against 221 us at 512x512x256) although it runs four waves per SIMD
+// instead of three.
 constexpr int XR_NT = 256;
 
 template <int M, bool XW, bool P32>
@@ -500,10 +503,14 @@ __global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
 // to the transform precision into the LDS tile (which aliases the march's
 // staging arrays) and transformed in place; per-workgroup FP64 sums of f go
 // to `partials` like those of the plain pass.  One problem per launch.
-constexpr int XD_NT = 256;
+// Threads per workgroup: 512 with periodic x (at nx = 512 108 / 128 VGPRs
+// in FP32 / FP64, four waves per SIMD; 441 / 394 against 455 / 402 us with
+// 256 threads); the wall variants stay at 256 (with 512 they need more
+// registers, not fewer).
+template <bool XW> constexpr int xd_nt() { return XW ? 256 : 512; }
 
 template <int M, bool XW>
-__global__ __launch_bounds__(XD_NT) void k_x_div(XFwdArgs a0)
+__global__ __launch_bounds__(xd_nt<XW>()) void k_x_div(XFwdArgs a0)
 {
     XFwdArgs a = a0;
     if (a.batch) {
@@ -512,7 +519,7 @@ __global__ __launch_bounds__(XD_NT) void k_x_div(XFwdArgs a0)
         a.S = q.S;
         if (a.partials) a.partials = q.partials;
     }
-    constexpr int TJ = march_rows_res(M), NT = XD_NT, NX = 2 * M;
+    constexpr int TJ = march_rows_res(M), NT = xd_nt<XW>(), NX = 2 * M;
     using Mar = DivMarch<M, TJ, NT>;
     using Tile = LdsTile<R, M, TJ, false, 0>;
     constexpr size_t PLANE_B = Mar::lds_bytes();
@@ -874,9 +881,9 @@ template <int M> static int run_x_fwd(const XFwdArgs &a, hipStream_t s, int *nbl
     if (a.residual == 2) {
         if (a.batch && a.nbatch != 1) return -1;
         if (xw)
-            hipLaunchKernelGGL((k_x_div<M, true>), dim3(nb), dim3(XD_NT), 0, s, a);
+            hipLaunchKernelGGL((k_x_div<M, true>), dim3(nb), dim3(xd_nt<true>()), 0, s, a);
         else
-            hipLaunchKernelGGL((k_x_div<M, false>), dim3(nb), dim3(XD_NT), 0, s, a);
+            hipLaunchKernelGGL((k_x_div<M, false>), dim3(nb), dim3(xd_nt<false>()), 0, s, a);
     } else if (a.residual) {
         // the refinement transforms its residual in FP32 only
         if constexpr (sizeof(R) == 4) {
@@ -884,7 +891,8 @@ template <int M> static int run_x_fwd(const XFwdArgs &a, hipStream_t s, int *nbl
                 if (xw)
                     hipLaunchKernelGGL((k_x_res<M, true, true>), grid, dim3(XR_NT), 0, s, a);
                 else
-                    hipLaunchKernelGGL((k_x_res<M, false, true>), grid, dim3(XR_NT), 0, s, a);
+                    hipLaunchKernelGGL((k_x_res<M, false, true>), grid, dim3(XR_NT), 0, s,
+                                       a);
             } else if (xw) {
                 hipLaunchKernelGGL((k_x_res<M, true, false>), grid, dim3(XR_NT), 0, s, a);
             } else {
