@@ -319,15 +319,15 @@ class BatchPlan:
         """Device pointers of the right-hand sides and outputs, after the
         checks of every tensor (float64, GPU, contiguous, the problem's
         shape).  A call with the same tensor objects as the previous one,
-        unchanged in place (data pointers, shapes and contiguity), skips the
-        per-tensor checks, which otherwise cost more than the launches of a
-        small batch."""
+        unchanged in place (data pointers, shapes, contiguity, dtypes and
+        devices), skips the per-tensor checks, which otherwise cost more
+        than the launches of a small batch."""
         n = self.count
         if len(rhs_list) != n or len(out_list) != n:
             raise ValueError("one rhs and one output per problem")
         ts = [*rhs_list, *out_list]
         try:
-            sig = [(t.data_ptr(), t.shape, t.is_contiguous()) for t in ts]
+            sig = [(t.data_ptr(), t.shape, t.is_contiguous(), t.dtype, t.is_cuda) for t in ts]
         except (AttributeError, TypeError):
             sig = None
         last = self._validated

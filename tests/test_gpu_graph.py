@@ -181,9 +181,12 @@ def test_batch_rechecks_changed_arguments():
         for t in bad:
             with pytest.raises((ValueError, TypeError)):
                 bp.solve(rhs, [outs[0], t])
-        # the same tensor object, changed in place
+        # the same tensor object, changed in place: shape, then dtype alone
         keep = good.data
         good.data = torch.empty(3, 3, 3, dtype=torch.float64, device="cuda")
+        with pytest.raises(ValueError):
+            bp.solve(rhs, outs)
+        good.data = keep.view(torch.int64)
         with pytest.raises(ValueError):
             bp.solve(rhs, outs)
         good.data = keep
