@@ -41,6 +41,11 @@ MUTATIONS = {
     "dir_row": 10,
     "cos_shift": 11,
     "sin_index": 12,
+    "res_no_sqrt": 13,
+    "lap_dir_x": 14,
+    "lap_dir_y": 15,
+    "res_no_mean": 16,
+    "res_mean_dir": 17,
 }
 
 _lib = None
@@ -74,9 +79,15 @@ def _load():
     lib.oracle_laplacian_bc.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
         ctypes.c_int] * 3 + [dp, dp]
     lib.oracle_laplacian_bc.restype = ctypes.c_int
+    lib.oracle_laplacian_bc_mut.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
+        ctypes.c_int] * 3 + [dp, dp, ctypes.c_int]
+    lib.oracle_laplacian_bc_mut.restype = ctypes.c_int
     lib.oracle_residual_bc.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
         ctypes.c_int] * 3 + [dp, dp, dp, dp, dp]
     lib.oracle_residual_bc.restype = ctypes.c_int
+    lib.oracle_residual_bc_mut.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
+        ctypes.c_int] * 3 + [dp, dp, dp, dp, dp, ctypes.c_int]
+    lib.oracle_residual_bc_mut.restype = ctypes.c_int
     lib.oracle_laplacian.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
         ctypes.c_int, dp, dp]
     lib.oracle_laplacian.restype = ctypes.c_int
@@ -116,8 +127,7 @@ def solve(f, dx, dy, dz, bc_z, mutation: int | str = 0, return_info: bool = Fals
     p = np.empty_like(f)
     mean = ctypes.c_double(0.0)
     mim = ctypes.c_double(0.0)
-    if isinstance(mutation, str):
-        mutation = MUTATIONS[mutation]
+    mutation = _mutation(mutation)
     rc = lib.oracle_solve_bc(nx, ny, nz, dx, dy, dz, int(bc_x), int(bc_y), int(bc_z),
                              _ptr(f), _ptr(p), ctypes.byref(mean), ctypes.byref(mim),
                              int(mutation))
@@ -128,20 +138,26 @@ def solve(f, dx, dy, dz, bc_z, mutation: int | str = 0, return_info: bool = Fals
     return p
 
 
-def laplacian(p, dx, dy, dz, bc_z, bc_x: int = PERIODIC, bc_y: int = PERIODIC):
+def _mutation(m):
+    return MUTATIONS[m] if isinstance(m, str) else int(m)
+
+
+def laplacian(p, dx, dy, dz, bc_z, bc_x: int = PERIODIC, bc_y: int = PERIODIC,
+              mutation: int | str = 0):
+    """L p, the 7-point operator with the ghost rule of each axis."""
     lib = _load()
     p = _check(p)
     nz, ny, nx = p.shape
     out = np.empty_like(p)
-    rc = lib.oracle_laplacian_bc(nx, ny, nz, dx, dy, dz, int(bc_x), int(bc_y), int(bc_z),
-                                 _ptr(p), _ptr(out))
+    rc = lib.oracle_laplacian_bc_mut(nx, ny, nz, dx, dy, dz, int(bc_x), int(bc_y), int(bc_z),
+                                     _ptr(p), _ptr(out), _mutation(mutation))
     if rc != 0:
         raise RuntimeError("oracle_laplacian failed")
     return out
 
 
 def residual(f, p, dx, dy, dz, bc_z, return_field: bool = False, bc_x: int = PERIODIC,
-             bc_y: int = PERIODIC):
+             bc_y: int = PERIODIC, mutation: int | str = 0):
     """Relative residual ||(f - mean f) - L p||_2 / ||f - mean f||_2 (and Linf);
     the mean is removed only when no axis is Dirichlet."""
     lib = _load()
@@ -151,9 +167,9 @@ def residual(f, p, dx, dy, dz, bc_z, return_field: bool = False, bc_x: int = PER
     r = np.empty_like(f) if return_field else None
     l2 = ctypes.c_double()
     li = ctypes.c_double()
-    rc = lib.oracle_residual_bc(nx, ny, nz, dx, dy, dz, int(bc_x), int(bc_y), int(bc_z),
-                                _ptr(f), _ptr(p), _ptr(r) if r is not None else None,
-                                ctypes.byref(l2), ctypes.byref(li))
+    rc = lib.oracle_residual_bc_mut(nx, ny, nz, dx, dy, dz, int(bc_x), int(bc_y), int(bc_z),
+                                    _ptr(f), _ptr(p), _ptr(r) if r is not None else None,
+                                    ctypes.byref(l2), ctypes.byref(li), _mutation(mutation))
     if rc != 0:
         raise RuntimeError("oracle_residual failed")
     if return_field:

@@ -74,6 +74,12 @@
 #define MUT_DIR_ROW 10        /* Dirichlet wall rows use the Neumann diagonal */
 #define MUT_COS_SHIFT 11      /* cosine basis without the half-cell shift */
 #define MUT_SIN_INDEX 12      /* sine basis index k instead of k+1 */
+/* planted mistakes of the operator and residual evaluation */
+#define MUT_RES_NO_SQRT 13    /* relative L2 residual reported without the square root */
+#define MUT_LAP_DIR_X 14      /* Dirichlet x wall takes the mirrored (Neumann) ghost in L */
+#define MUT_LAP_DIR_Y 15      /* Dirichlet y wall takes the mirrored (Neumann) ghost in L */
+#define MUT_RES_NO_MEAN 16    /* residual keeps the mean of f on a singular problem */
+#define MUT_RES_MEAN_DIR 17   /* residual removes the mean of f despite a Dirichlet wall */
 
 static const double ORC_PI = 3.14159265358979323846264338327950288;
 
@@ -459,10 +465,12 @@ static int nbr(int i, int d, int n, int bc, double *fac)
  * MAC grid with per-axis boundaries (0 periodic, 1 Neumann: ghost = wall
  * cell, 2 Dirichlet: ghost = -wall cell).
  */
-int oracle_laplacian_bc(int nx, int ny, int nz, double dx, double dy, double dz, int bc_x,
-                        int bc_y, int bc_z, const double *p, double *out)
+int oracle_laplacian_bc_mut(int nx, int ny, int nz, double dx, double dy, double dz, int bc_x,
+                            int bc_y, int bc_z, const double *p, double *out, int mutation)
 {
     if (nx < 1 || ny < 1 || nz < 1 || !p || !out) return -1;
+    if (mutation == MUT_LAP_DIR_X && bc_x == ORC_DIRICHLET) bc_x = ORC_NEUMANN;
+    if (mutation == MUT_LAP_DIR_Y && bc_y == ORC_DIRICHLET) bc_y = ORC_NEUMANN;
     double ax = 1.0 / (dx * dx), ay = 1.0 / (dy * dy), az = 1.0 / (dz * dz);
 #pragma omp parallel for schedule(static)
     for (long kk = 0; kk < (long)nz * ny; ++kk) {
@@ -485,6 +493,12 @@ int oracle_laplacian_bc(int nx, int ny, int nz, double dx, double dy, double dz,
     return 0;
 }
 
+int oracle_laplacian_bc(int nx, int ny, int nz, double dx, double dy, double dz, int bc_x,
+                        int bc_y, int bc_z, const double *p, double *out)
+{
+    return oracle_laplacian_bc_mut(nx, ny, nz, dx, dy, dz, bc_x, bc_y, bc_z, p, out, MUT_NONE);
+}
+
 /* x and y periodic; z periodic or Neumann walls (the original interface) */
 int oracle_laplacian(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,
                      const double *p, double *out)
@@ -495,21 +509,23 @@ int oracle_laplacian(int nx, int ny, int nz, double dx, double dy, double dz, in
 /*
  * oracle_residual_bc: r = (f - mean(f)) - L p (the mean is removed only when
  * no axis is Dirichlet, as in the solve), plus the relative L2 and Linf norms
- * ||r|| / ||f - mean(f)||.  r may be NULL.
+ * ||r|| / ||f - mean(f)||.  r may be NULL.  (_mut: with a planted mistake.)
  */
-int oracle_residual_bc(int nx, int ny, int nz, double dx, double dy, double dz, int bc_x,
-                       int bc_y, int bc_z, const double *f, const double *p, double *r,
-                       double *rel_l2, double *rel_linf)
+int oracle_residual_bc_mut(int nx, int ny, int nz, double dx, double dy, double dz, int bc_x,
+                           int bc_y, int bc_z, const double *f, const double *p, double *r,
+                           double *rel_l2, double *rel_linf, int mutation)
 {
     long n = (long)nx * ny * nz;
     double *lp = malloc(sizeof(double) * n);
     if (!lp) return -1;
-    if (oracle_laplacian_bc(nx, ny, nz, dx, dy, dz, bc_x, bc_y, bc_z, p, lp)) {
+    if (oracle_laplacian_bc_mut(nx, ny, nz, dx, dy, dz, bc_x, bc_y, bc_z, p, lp, mutation)) {
         free(lp);
         return -1;
     }
-    const int singular_problem =
+    int singular_problem =
         bc_x != ORC_DIRICHLET && bc_y != ORC_DIRICHLET && bc_z != ORC_DIRICHLET;
+    if (mutation == MUT_RES_NO_MEAN) singular_problem = 0;
+    if (mutation == MUT_RES_MEAN_DIR) singular_problem = 1;
     double mean = singular_problem ? pairwise_sum(f, n) / (double)n : 0.0;
     double s2r = 0, s2f = 0, mr = 0, mf = 0;
     for (long t = 0; t < n; ++t) {
@@ -522,9 +538,20 @@ int oracle_residual_bc(int nx, int ny, int nz, double dx, double dy, double dz, 
         if (fabs(fb) > mf) mf = fabs(fb);
     }
     free(lp);
-    if (rel_l2) *rel_l2 = (s2f > 0) ? sqrt(s2r / s2f) : sqrt(s2r);
+    if (rel_l2) {
+        double q = (s2f > 0) ? s2r / s2f : s2r;
+        *rel_l2 = (mutation == MUT_RES_NO_SQRT) ? q : sqrt(q);
+    }
     if (rel_linf) *rel_linf = (mf > 0) ? mr / mf : mr;
     return 0;
+}
+
+int oracle_residual_bc(int nx, int ny, int nz, double dx, double dy, double dz, int bc_x,
+                       int bc_y, int bc_z, const double *f, const double *p, double *r,
+                       double *rel_l2, double *rel_linf)
+{
+    return oracle_residual_bc_mut(nx, ny, nz, dx, dy, dz, bc_x, bc_y, bc_z, f, p, r, rel_l2,
+                                  rel_linf, MUT_NONE);
 }
 
 int oracle_residual(int nx, int ny, int nz, double dx, double dy, double dz, int bc_z,

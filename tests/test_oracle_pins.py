@@ -410,6 +410,12 @@ def _battery(orc, mutation):
         p = orc.solve(f, dx, dy, dz, bcs[2], mutation=mutation, bc_x=bcs[0], bc_y=bcs[1])
         if rel(p, dense_solve_bc(f, dx, dy, dz, bcs)) > 1e-10:
             failures.append(("dense_walls", bcs))
+    # the operator and the residual evaluation on a field that is not a solution
+    for bcs in ((P, P, N), (D, N, P), (N, D, N), (N, N, D)):
+        sp = (0.7, 0.45, 0.3)
+        f, p = _perturbed_solution(orc, (4, 5, 3), bcs, 0.3, 55)
+        if _residual_pin_errors(orc, f, p, sp, bcs, mutation) > 1e-12:
+            failures.append(("residual", bcs))
     return failures
 
 
@@ -544,3 +550,76 @@ def test_dirichlet_keeps_the_mean(orc):
     r, _ = orc.residual(f, p, *sp, D, bc_x=N, bc_y=P)
     assert r < 1e-13
     assert rel(p, dense_solve_bc(f, *sp, (N, P, D))) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# the operator and the residual evaluation, the checker of every refined GPU
+# result: values pinned against the shifted-array stencil and norms written
+# out here, on fields that are not solutions
+# --------------------------------------------------------------------------
+def residual_np(f, p, sp, bcs):
+    """r = fbar - L p, fbar = f - mean(f) when no axis is Dirichlet (else f),
+    and the relative norms ||r||_2/||fbar||_2, max|r|/max|fbar|."""
+    fb = f.copy() if D in bcs else f - f.mean()
+    r = fb - lap_bc_np(p, *sp, bcs)
+    return r, math.sqrt((r * r).sum() / (fb * fb).sum()), np.abs(r).max() / np.abs(fb).max()
+
+
+def _perturbed_solution(orc, shape, bcs, scale, seed):
+    """The oracle's solution of a seeded right-hand side (with a mean) plus a
+    seeded perturbation of relative size `scale`."""
+    nx, ny, nz = shape
+    sp = (0.7, 0.45, 0.3)
+    f = inputs.random_rhs(nx, ny, nz, seed=seed, zero_mean=False) + 0.25
+    p = orc.solve(f, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+    rng = np.random.default_rng(seed + 1)
+    return f, p + scale * max(np.abs(p).max(), 1e-3) * rng.uniform(-1, 1, p.shape)
+
+
+def _residual_pin_errors(orc, f, p, sp, bcs, mutation=0):
+    """Largest relative deviation of the oracle's L p, residual field and
+    residual norms from the independent evaluation."""
+    lap = orc.laplacian(p, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1], mutation=mutation)
+    ref = lap_bc_np(p, *sp, bcs)
+    l2, li, r = orc.residual(f, p, *sp, bcs[2], return_field=True, bc_x=bcs[0], bc_y=bcs[1],
+                             mutation=mutation)
+    rr, l2r, lir = residual_np(f, p, sp, bcs)
+    return max(rel(lap, ref), rel(r, rr), abs(l2 - l2r) / l2r, abs(li - lir) / lir)
+
+
+RES_SHAPES = [(3, 4, 5), (8, 8, 8), (1, 6, 7), (5, 1, 2), (6, 5, 1), (2, 2, 2)]
+
+
+@pytest.mark.parametrize("bcs", ALL_BCS, ids=["".join("PND"[b] for b in c) for c in ALL_BCS])
+def test_residual_and_laplacian_values(orc, bcs):
+    sp = (0.7, 0.45, 0.3)
+    for shape in RES_SHAPES:
+        seed = 17 * shape[0] + 5 * shape[1] + shape[2]
+        # a perturbation of the size of the solution: the residual is O(f)
+        f, p = _perturbed_solution(orc, shape, bcs, 0.3, seed)
+        assert _residual_pin_errors(orc, f, p, sp, bcs) <= 1e-14, (shape, bcs)
+        # a perturbation of 1e-6: the residual norms scale with it (a norm
+        # without its square root would read about 1e-12)
+        f, p = _perturbed_solution(orc, shape, bcs, 1e-6, seed)
+        l2, li = orc.residual(f, p, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+        _, l2r, lir = residual_np(f, p, sp, bcs)
+        assert abs(l2 - l2r) <= 1e-8 * l2r and abs(li - lir) <= 1e-8 * lir, (shape, bcs)
+        assert 1e-8 < l2 < 1e-4, (shape, bcs, l2)
+        # the exact solution: residual at rounding level
+        f, p = _perturbed_solution(orc, shape, bcs, 0.0, seed)
+        assert orc.residual(f, p, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])[0] < 1e-13
+
+
+def test_residual_mean_removal(orc):
+    """The mean of f is removed exactly when the constant is in the null
+    space: adding a constant to f leaves the residual of a singular problem
+    unchanged and changes that of a regular one by the constant."""
+    sp = (0.7, 0.45, 0.3)
+    f, p = _perturbed_solution(orc, (4, 3, 5), (N, P, N), 0.1, 3)
+    a = orc.residual(f, p, *sp, N, return_field=True, bc_x=N, bc_y=P)[2]
+    b = orc.residual(f + 3.0, p, *sp, N, return_field=True, bc_x=N, bc_y=P)[2]
+    assert np.abs(a - b).max() < 1e-13
+    f, p = _perturbed_solution(orc, (4, 3, 5), (N, P, D), 0.1, 3)
+    a = orc.residual(f, p, *sp, D, return_field=True, bc_x=N, bc_y=P)[2]
+    b = orc.residual(f + 3.0, p, *sp, D, return_field=True, bc_x=N, bc_y=P)[2]
+    assert np.abs((b - a) - 3.0).max() < 1e-13
