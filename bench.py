@@ -11,7 +11,11 @@ the plain FP64 solve of the same workload is timed beside it, and so is the
 whole projection step on the same grid (divergence of the face velocities
 fused into the first pass, the solve, the velocity correction and pressure
 update), under "projection", and wall-bounded boxes of the same grid (a
-cavity and a channel, cosine expansions along x and y), under "walls".  The roofline
+cavity and a channel, cosine expansions along x and y), under "walls".  The
+256^3 triply periodic workload (spectral right-hand side) is timed the same
+way under "hit256".  The error of every returned field against the FP64
+oracle is reported under "err_vs_oracle" (the oracle's solve of the whole
+grid is also the CPU baseline).  The roofline
 entry is for the kernel with the largest share of the FP32+refinement step,
 timed live with HIP events on the plan's stream.
 
@@ -228,25 +232,102 @@ def bench_walls(steps, warmup, tune):
     return res
 
 
+def host_cpu():
+    """CPU model name and logical CPU counts of the host (Linux /proc)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
 def cpu_baseline(prob, nplanes):
     """The FP64 oracle timed on the host on the workload, or on a slab of it:
     the first `nplanes` z-planes (x and y lines keep their full length, so
     the per-point cost of the oracle's O(n) per-point DFTs is that of the
-    full grid).  The default is the whole grid (about 13 s on 16 cores)."""
+    full grid).  The default is the whole grid (about 13 s on 16 cores).
+    Returns the record and the oracle's solution (None for a slab, which is
+    a different problem)."""
     import numpy as np
     import oracle
     f = np.ascontiguousarray(prob.f[:nplanes])
     oracle.solve(f[:2], *prob.spacings(), prob.bc_z)  # load the library, warm up
     t0 = time.perf_counter()
-    oracle.solve(f, *prob.spacings(), prob.bc_z)
+    p = oracle.solve(f, *prob.spacings(), prob.bc_z)
     dt = time.perf_counter() - t0
     pts = f.size
-    return {"value": pts / dt / 1e6, "unit": "Mpoints/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": (f"the whole {prob.nx}x{prob.ny}x{prob.nz} workload" if nplanes == prob.nz
-                       else f"first {nplanes} of {prob.nz} z-planes of the workload "
-                            f"({prob.nx}x{prob.ny}x{nplanes})")
-                      + f", one FP64 oracle solve, {dt:.2f} s"}
+    rec = {"value": pts / dt / 1e6, "unit": "Mpoints/s", "cores": oracle.num_threads(),
+           "kind": "oracle",
+           "sample": (f"the whole {prob.nx}x{prob.ny}x{prob.nz} workload" if nplanes == prob.nz
+                      else f"first {nplanes} of {prob.nz} z-planes of the workload "
+                           f"({prob.nx}x{prob.ny}x{nplanes})")
+                     + f", one FP64 oracle solve, {dt:.2f} s"}
+    rec.update(host_cpu())
+    return rec, (p if nplanes == prob.nz else None)
+
+
+def error_vs_oracle(p, ref):
+    """Relative L2 and max-norm error of a solution against the oracle's."""
+    import numpy as np
+    d = p - ref
+    return {"rel_l2": float(np.linalg.norm(d.ravel()) / np.linalg.norm(ref.ravel())),
+            "rel_max": float(np.abs(d).max() / np.abs(ref).max())}
+
+
+def bench_extra_workload(name, steps, warmup, tune, with_oracle):
+    """A second workload of the scope (hit256: 256^3 triply periodic,
+    spectral right-hand side): FP32 + refinement to 1e-10 and plain FP64,
+    each timed like the main workload, with the error of both results
+    against the FP64 oracle."""
+    import torch
+    from paper_2204_08834_amd import inputs, poisson
+    prob = inputs.workload(name)
+    npts = prob.npoints
+    sp = prob.spacings()
+    rhs = torch.from_numpy(prob.f).cuda()
+    out = torch.empty_like(rhs)
+    res = {"workload": f"{name}: {DESCRIPTIONS[name]}", "grid": [prob.nx, prob.ny, prob.nz]}
+    sols = {}
+    for prec in ("fp32_refine", "fp64"):
+        plan = poisson.Plan(prob.nx, prob.ny, prob.nz, *sp, prob.bc_z, prec, rtol=1e-10,
+                            max_refine=8)
+        if tune:
+            plan.autotune()
+        for _ in range(warmup):
+            plan.solve(rhs, out)
+        refine = prec == "fp32_refine"
+        ms, st = time_solves(plan, rhs, out, steps, sync_each=refine)
+        plan.set_timing(True)
+        plan.reset_timing()
+        for _ in range(steps):
+            plan.solve(rhs, out)
+        passes = plan.timing()
+        plan.close()
+        step_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in passes.values()) / steps
+        res[prec] = {"ms_per_step": ms, "mpoints_s": npts / (ms * 1e-3) / 1e6,
+                     "model_hbm_gbs": step_bytes / (ms * 1e-3) / 1e9,
+                     "model_bytes_per_point": step_bytes / npts}
+        if refine:
+            res[prec].update(rel_residual=st["rel_residual"], iterations=st["iterations"])
+        sols[prec] = out.cpu().numpy()
+        print(f"[bench] {name} {prec} {ms:.3f} ms/solve", file=sys.stderr, flush=True)
+    res["fp32refine_over_fp64_speed"] = res["fp64"]["ms_per_step"] / res["fp32_refine"][
+        "ms_per_step"]
+    if with_oracle:
+        import oracle
+        print(f"[bench] {name}: oracle solve for the error check", file=sys.stderr, flush=True)
+        ref = oracle.solve(prob.f, *sp, prob.bc_z)
+        res["err_vs_oracle"] = {k: error_vs_oracle(v, ref) for k, v in sols.items()}
+    return res
 
 
 def copy_calibration(steps, warmup):
@@ -421,6 +502,8 @@ def main():
                     help="skip the projection step (divergence, solve, correction)")
     ap.add_argument("--no-walls", action="store_true",
                     help="skip the wall-bounded boxes (walls along x and y)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the second workload (hit256: 256^3 triply periodic)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the captured-graph loop timing (profiling runs: its gated-off "
                          "launches would mix into the per-kernel statistics)")
@@ -494,6 +577,8 @@ def main():
                          "bc_z": "walls" if prob.bc_z == 1 else "periodic",
                          "rtol": 1e-10, "parallelism": "single GPU"}}
 
+    solutions = {}  # returned fields, for the error against the oracle
+
     # ---- FP32 + FP64-residual refinement --------------------------------
     if args.only in (None, "fp32_refine"):
         plan = poisson.Plan(prob.nx, prob.ny, prob.nz, dx, dy, dz, prob.bc_z, "fp32_refine",
@@ -523,6 +608,7 @@ def main():
                                                "mpoints_s": npts / (msg * 1e-3) / 1e6,
                                                "rel_residual": stg["rel_residual"]}
         plan.close()
+        solutions["fp32_refine"] = out.cpu().numpy()
         result["value"] = npts / (ms32 * 1e-3) / 1e6
         result["ms_per_step"] = ms32
         result["refine_iterations"] = st["iterations"]
@@ -564,6 +650,7 @@ def main():
             plan.solve_async(rhs, out)
         p64 = plan.timing()
         plan.close()
+        solutions["fp64"] = out.cpu().numpy()
         print(f"[bench] fp64 {ms64:.3f} ms/solve", file=sys.stderr, flush=True)
         b64 = sum(v["bytes_per_launch"] * v["launches"] for v in p64.values()) / args.steps
         result["fp64_plain"] = {
@@ -597,10 +684,19 @@ def main():
         print("[bench] batched mixed-64 workload", file=sys.stderr, flush=True)
         result["batch_mixed64"] = bench_batch(max(3, args.steps // 4), 2)
 
+    if not args.no_extra and prob.name != "hit256":
+        print("[bench] hit256 workload", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        result["hit256"] = bench_extra_workload("hit256", args.steps, args.warmup,
+                                                not args.no_tune, not args.no_cpu)
+
     if not args.no_cpu:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         planes = prob.nz if args.cpu_planes <= 0 else min(args.cpu_planes, prob.nz)
-        result["cpu_baseline"] = cpu_baseline(prob, planes)
+        result["cpu_baseline"], ref = cpu_baseline(prob, planes)
+        if ref is not None:
+            # the error of each returned field against the FP64 oracle
+            result["err_vs_oracle"] = {k: error_vs_oracle(v, ref) for k, v in solutions.items()}
     print(json.dumps(result), flush=True)
 
 

@@ -182,7 +182,11 @@ int poisson_destroy(poisson_plan plan);
 int poisson_batch_plan_create(const poisson_desc_t *descs, int count, void *stream,
                               poisson_plan *out);
 
-/* rhs[i], sol[i]: host arrays of `count` device pointers (problem i's fields).
+/* rhs[i], sol[i]: host arrays of `count` device pointers (problem i's fields,
+ * each of that problem's nx*ny*nz doubles).  No sol[i] may share a byte with
+ * another problem's solution or with any right-hand side (the refinement
+ * re-reads every rhs while the solutions are written): INVALID_ARG, checked
+ * before any work is enqueued.  Right-hand sides may overlap each other.
  * stats: NULL or an array of `count` entries.  Returns the first non-OK
  * per-problem status, else POISSON_OK. */
 int poisson_batch_solve(poisson_plan plan, const double *const *rhs, double *const *sol,

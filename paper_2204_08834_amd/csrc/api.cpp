@@ -820,10 +820,11 @@ int read_scalars(poisson_plan p, int count)
     return POISSON_OK;
 }
 
-bool overlaps(const double *a, const double *b, long long n)
+// [a, a + na) and [b, b + nb) (doubles) share a byte
+bool overlaps(const double *a, long long na, const double *b, long long nb)
 {
-    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b, len = (uintptr_t)(n * 8);
-    return x < y + len && y < x + len;
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + (uintptr_t)(nb * 8) && y < x + (uintptr_t)(na * 8);
 }
 
 // pointers of problem i (member slot `slot` of group g)
@@ -1521,7 +1522,8 @@ int poisson_batch_plan_create(const poisson_desc_t *descs, int count, void *stre
 int poisson_solve(poisson_plan plan, const double *rhs, double *sol, poisson_stats_t *stats)
 {
     if (!plan || !rhs || !sol || plan->batched) return POISSON_ERR_INVALID_ARG;
-    if (overlaps(rhs, sol, plan->groups[0].N)) return POISSON_ERR_INVALID_ARG;
+    const long long n = plan->groups[0].N;
+    if (overlaps(rhs, n, sol, n)) return POISSON_ERR_INVALID_ARG;
     DeviceGuard guard(plan->device);
     return plan->graph_mode ? solve_device(plan, &rhs, &sol, stats)
                             : solve_all(plan, &rhs, &sol, stats);
@@ -1531,13 +1533,17 @@ int poisson_batch_solve(poisson_plan plan, const double *const *rhs, double *con
                         poisson_stats_t *stats)
 {
     if (!plan || !rhs || !sol || !plan->batched) return POISSON_ERR_INVALID_ARG;
-    for (int i = 0; i < plan->count; ++i) {
-        const long long n = plan->groups[plan->where[i].first].N;
+    // every solution is written while every right-hand side is still read
+    // (the refinement's residual passes re-read f): no solution may share a
+    // byte with another solution or with any right-hand side
+    for (int i = 0; i < plan->count; ++i)
         if (!rhs[i] || !sol[i]) return POISSON_ERR_INVALID_ARG;
-        if (overlaps(rhs[i], sol[i], n)) return POISSON_ERR_INVALID_ARG;
-        for (int j = 0; j < i; ++j) {  // solutions must not overlap each other
+    for (int i = 0; i < plan->count; ++i) {
+        const long long ni = plan->groups[plan->where[i].first].N;
+        for (int j = 0; j < plan->count; ++j) {
             const long long nj = plan->groups[plan->where[j].first].N;
-            if (overlaps(sol[i], sol[j], n < nj ? n : nj)) return POISSON_ERR_INVALID_ARG;
+            if (overlaps(sol[i], ni, rhs[j], nj)) return POISSON_ERR_INVALID_ARG;
+            if (j < i && overlaps(sol[i], ni, sol[j], nj)) return POISSON_ERR_INVALID_ARG;
         }
     }
     DeviceGuard guard(plan->device);
@@ -1557,7 +1563,7 @@ int poisson_project(poisson_plan plan, double *u, double *v, double *w, double *
     const double *arr[5] = {u, v, w, psi, p};
     for (int i = 0; i < 5; ++i)
         for (int j = 0; j < i; ++j)
-            if (arr[i] && arr[j] && overlaps(arr[i], arr[j], n)) return POISSON_ERR_INVALID_ARG;
+            if (arr[i] && arr[j] && overlaps(arr[i], n, arr[j], n)) return POISSON_ERR_INVALID_ARG;
     DeviceGuard guard(plan->device);
     return project(plan, u, v, w, p, psi, alpha, beta, stats);
 }

@@ -193,6 +193,8 @@ class Plan:
     def solve_async(self, rhs, out):
         """Enqueue a solve without reading statistics (no host synchronisation
         except the once-per-iteration residual read of FP32_REFINE)."""
+        _check_field(rhs, self.shape, "rhs")
+        _check_field(out, self.shape, "out")
         rc = lib().poisson_solve(self._h, ctypes.c_void_p(rhs.data_ptr()),
                                  ctypes.c_void_p(out.data_ptr()), None)
         if rc != OK:

@@ -4,7 +4,7 @@
 At this size the oracle's O(n^2) DFTs are out of reach, so the checks are
 properties that hold at any size:
   * exact discrete eigenmodes (closed form; built on the GPU): the solution
-    is f / lambda, FP64 to 1e-12, FP32 + refinement to 1e-9;
+    is f / lambda, FP64 to 1e-12, FP32 + refinement to 1e-10;
   * a seeded U(-1,1) right-hand side: the oracle's FP64 7-point residual of
     the returned field (on the host) is <= 1e-12 in FP64 and <= 1e-10 after
     refinement, and the solution has zero mean.
@@ -56,7 +56,7 @@ def test_eigenmode_1024(modes):
     P = _gpu()
     f, lam, sp = _eigen_gpu(*modes)
     ref = f / lam
-    for prec, tol in (("fp64", 1e-12), ("fp32_refine", 1e-9)):
+    for prec, tol in (("fp64", 1e-12), ("fp32_refine", 1e-10)):
         print(f"[1024] eigenmode {modes} {prec}", flush=True)
         with P.Plan(NX, NY, NZ, *sp, NEU, prec) as plan:
             p, st = plan.solve(f)

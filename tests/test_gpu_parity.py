@@ -1,10 +1,11 @@
 """GPU parity: the HIP solve (through the C ABI) against the FP64 CPU oracle.
 
 Small grids (spanning several tiles, ragged tails, radix-3 lengths, length-1
-axes) are compared element by element with the oracle.  Full-size workloads
-are checked through properties that hold at any size: the relative residual
-of the discrete equation (evaluated by the oracle's FP64 stencil on the CPU),
-the zero-mean gauge, and exact discrete eigenmodes.
+axes) are compared element by element with the oracle, and so are the
+full-size 512x512x256 and 256^3 workloads (the oracle solves them in seconds
+to tens of seconds); full-size exact discrete eigenmodes, the relative
+residual of the discrete equation (the oracle's FP64 stencil on the CPU) and
+the zero-mean gauge are checked besides.
 
 Tolerances (relative L2 unless stated):
   FP64          error vs oracle <= 1e-12
@@ -187,7 +188,7 @@ def test_eigenmode_full_size_walls(modes):
     """512x512x256 walls: exact discrete eigenmodes (closed form) at full size."""
     a, b, c = modes
     f, lam, sp = _eigen(512, 512, 256, 2.0, 2.0, 1.0, NEU, a, b, c)
-    for prec, tol in (("fp64", 1e-12), ("fp32_refine", 1e-9)):
+    for prec, tol in (("fp64", 1e-12), ("fp32_refine", 1e-10)):
         p, st = gpu_solve(f, *sp, NEU, prec)
         err = rel(p, f / lam)
         print(f"walls eigenmode {modes} {prec}: error {err:.2e} stats {st}", flush=True)
@@ -198,7 +199,7 @@ def test_eigenmode_full_size_walls(modes):
 def test_eigenmode_full_size_periodic(modes):
     a, b, c = modes
     f, lam, sp = _eigen(256, 256, 256, 2 * math.pi, 2 * math.pi, 2 * math.pi, PER, a, b, c)
-    for prec, tol in (("fp64", 1e-12), ("fp32_refine", 1e-9)):
+    for prec, tol in (("fp64", 1e-12), ("fp32_refine", 1e-10)):
         p, st = gpu_solve(f, *sp, PER, prec)
         err = rel(p, f / lam)
         print(f"periodic eigenmode {modes} {prec}: error {err:.2e} stats {st}", flush=True)
@@ -206,25 +207,38 @@ def test_eigenmode_full_size_periodic(modes):
 
 
 @pytest.mark.parametrize("name", ["rb512", "hit256"])
-def test_full_size_workload_properties(orc, name):
-    """Full-size workloads: FP64 residual <= 1e-12, FP32+refinement <= 1e-10,
-    zero mean; the FP32+refinement error (against the FP64 solve) is bounded
-    by kappa(L) times its residual and printed."""
+def test_full_size_workload_matches_oracle(orc, name):
+    """The full-size workloads in the benchmark's configuration (512x512x256
+    walls with the two-layer right-hand side; 256^3 periodic with the
+    spectral one), element by element against the oracle's solve of the
+    whole grid: FP64 to 1e-12 relative L2 error, FP32 + refinement (stopping
+    at a 1e-10 residual) to 1e-10; also the oracle residual of each field,
+    the zero mean, and the largest pointwise error relative to max|p|."""
     prob = inputs.workload(name)
     sp = prob.spacings()
+    print(f"[{name}] oracle solve of the whole grid", flush=True)
+    ref = orc.solve(prob.f, *sp, prob.bc_z)
+    scale = np.abs(ref).max()
     p64, st64 = gpu_solve(prob.f, *sp, prob.bc_z, "fp64")
     r64, _ = orc.residual(prob.f, p64, *sp, prob.bc_z)
-    print(f"{name}: fp64 residual {r64:.3e}", flush=True)
+    e64 = rel(p64, ref)
+    m64 = float(np.abs(p64 - ref).max() / scale)
+    print(f"{name}: fp64 residual {r64:.3e}, error vs oracle {e64:.3e} (max {m64:.3e})",
+          flush=True)
     assert r64 <= 1e-12
+    assert e64 <= 1e-12 and m64 <= 1e-12
     assert abs(p64.mean()) <= 1e-13 * np.abs(p64).max()
+    del p64
     p32, st32 = gpu_solve(prob.f, *sp, prob.bc_z, "fp32_refine")
     r32, _ = orc.residual(prob.f, p32, *sp, prob.bc_z)
-    e32 = rel(p32, p64)
-    k = kappa(prob.nx, prob.ny, prob.nz, *sp, prob.bc_z)
+    e32 = rel(p32, ref)
+    m32 = float(np.abs(p32 - ref).max() / scale)
     print(f"{name}: fp32+refine residual {r32:.3e} after {st32['iterations']} corrections, "
-          f"error vs fp64 {e32:.3e} (kappa {k:.1e})", flush=True)
+          f"error vs oracle {e32:.3e} (max {m32:.3e})", flush=True)
     assert st32["status"] == 0 and r32 <= 1e-10
-    assert e32 <= k * (r32 + r64) * 1.01
+    assert abs(r32 - st32["rel_residual"]) <= 1e-12 + 0.05 * r32
+    assert e32 <= 1e-10 and m32 <= 1e-10
+    assert abs(p32.mean()) <= 1e-13 * np.abs(p32).max()
 
 
 def test_repeat_is_bitwise_deterministic():
@@ -373,3 +387,36 @@ def test_zwalls_tile_variants(orc, variant, monkeypatch):
         q, st = gpu_solve(f, *sp, NEU, "fp32_refine")
         res, _ = orc.residual(f, q, *sp, NEU)
         assert st["status"] == 0 and res <= 1e-10, (variant, nx, ny, nz, res)
+
+
+def test_batch_rejects_overlap_across_problems():
+    """A batch refuses a solution that shares memory with another problem's
+    solution or with any right-hand side, whatever the two problems' sizes:
+    a small problem's output placed in the tail of a large problem's output,
+    or on another problem's right-hand side.  The check runs before any
+    launch; every pointer lies inside one allocation."""
+    P = _gpu()
+    import ctypes
+    big, small = (32, 32, 32), (8, 8, 8)
+    nb, ns = 32 * 32 * 32, 8 * 8 * 8
+    specs = [dict(nx=big[0], ny=big[1], nz=big[2], dx=1.0, dy=1.0, dz=1.0, bc_z=NEU),
+             dict(nx=small[0], ny=small[1], nz=small[2], dx=1.0, dy=1.0, dz=1.0, bc_z=NEU)]
+    arena = torch.zeros(5 * nb, dtype=torch.float64, device="cuda")
+    base, es = arena.data_ptr(), arena.element_size()
+    r0, r1, s0 = base, base + nb * es, base + 2 * nb * es
+    bp = P.BatchPlan(specs, "fp64")
+    L = P.lib()
+    V = ctypes.c_void_p * 2
+
+    def call(rhs, sol):
+        return L.poisson_batch_solve(bp._h, V(*rhs), V(*sol), None)
+
+    tail = s0 + (nb - ns // 2) * es          # small output starts inside the big one's tail
+    assert call([r0, r1], [s0, tail]) == P.ERR_INVALID_ARG
+    s1 = s0 + nb * es                        # big output starts inside the small one
+    assert call([r0, r1], [s1 + (ns // 2) * es, s1]) == P.ERR_INVALID_ARG
+    assert call([r0, r1], [s0, r0 + 16 * es]) == P.ERR_INVALID_ARG   # sol[1] on rhs[0]
+    assert call([r0, r1], [r1, s0]) == P.ERR_INVALID_ARG             # sol[0] on rhs[1]
+    assert call([r0, r0], [s0, s0 + nb * es]) == P.OK                 # shared rhs is fine
+    torch.cuda.synchronize()
+    bp.close()
