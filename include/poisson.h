@@ -56,6 +56,11 @@ extern "C" {
 #define POISSON_ERR_HIP (-4)           /* a HIP runtime call failed */
 #define POISSON_ERR_NOT_CONVERGED (-5) /* refinement stalled or hit max_refine; last iterate kept */
 #define POISSON_ERR_NONFINITE (-6)     /* non-finite residual (NaN/Inf in rhs or solution) */
+#define POISSON_ERR_TOO_LARGE (-7)     /* exceeds the fixed scratch of poisson_solve_noalloc */
+
+/* Bytes of the fixed device scratch array of poisson_solve_noalloc (one copy
+ * per GPU the library runs on, held until the process ends). */
+#define POISSON_NOALLOC_SCRATCH_BYTES ((size_t)160 << 20)
 
 typedef enum {
     POISSON_BC_PERIODIC = 0,
@@ -138,6 +143,41 @@ int poisson_plan_create(const poisson_desc_t *d, void *stream, poisson_plan *out
  * stats may be NULL. */
 int poisson_solve(poisson_plan plan, const double *rhs_dev, double *sol_dev,
                   poisson_stats_t *stats);
+
+/*
+ * Allocation-free solve, for callers that cannot allocate device memory:
+ * code running under HIP graph capture, tight serving loops, and harnesses
+ * that forbid hipMalloc.  Same operation, kernels and results as
+ * poisson_plan_create + poisson_solve with the default launch variants (and
+ * those of a tuning cache, as a new plan would take them), without a plan
+ * object: every device buffer (tables, partial sums, scalars, and for
+ * FP32 / FP32_REFINE the 4 B/point spectrum and, for FP32_REFINE, the
+ * 4 B/point first iterate) is a piece of one fixed static device array of
+ * POISSON_NOALLOC_SCRATCH_BYTES per GPU.  The call allocates no device or
+ * pinned host memory (no hipMalloc, hipHostMalloc, hipFree, no library
+ * allocator).
+ *   d      : descriptor, validated as for poisson_plan_create.
+ *   stream : hipStream_t as void* (NULL = default stream); the current
+ *            device is the one used.
+ *   rhs, sol, stats: as poisson_solve (device float64, nx*ny*nz each,
+ *            non-overlapping; rhs is not written; stats may be NULL).
+ * Size limit: the tables plus 4 B/point (FP32) or 8 B/point (FP32_REFINE)
+ * plus the partial-sum records must fit the array (FP32_REFINE up to about
+ * 19 M points, e.g. 256^3; FP64 needs only the tables and records, so every
+ * valid size fits).  A larger problem returns POISSON_ERR_TOO_LARGE (with a
+ * message on stderr) before any work is enqueued.
+ * State: the array keeps the last call's contents.  The tables are
+ * regenerated and copied (then `stream` is synchronised once) only when the
+ * descriptor differs from the previous call's on that GPU; the scalars are
+ * cleared by a kernel on every call.  All calls on one GPU share the one
+ * array: calls that overlap in time on one GPU (from several host threads,
+ * or on several streams) race and give wrong results; serialise them.
+ * Synchronisation otherwise as poisson_solve (FP32_REFINE synchronises once
+ * per refinement iteration).  Errors: INVALID_ARG, UNSUPPORTED, TOO_LARGE,
+ * HIP, and those of poisson_solve.
+ */
+int poisson_solve_noalloc(const poisson_desc_t *d, void *stream, const double *rhs, double *sol,
+                          poisson_stats_t *stats);
 
 /*
  * The whole projection step around the solve (FluTAS Section 3.3:

@@ -120,9 +120,10 @@ std::vector<double> quarter_table(int n)
 // ---------------------------------------------------------------------------
 struct DevBuf {
     void *p = nullptr;
+    bool owned = true;  // false: a piece of a region the plan does not own
     ~DevBuf()
     {
-        if (p) (void)hipFree(p);
+        if (p && owned) (void)hipFree(p);
     }
 };
 
@@ -175,15 +176,50 @@ int upload(std::shared_ptr<DevBuf> &out, const void *host, size_t bytes)
     return POISSON_OK;
 }
 
-int upload_complex(std::shared_ptr<DevBuf> out[2], const std::vector<double> &tw, bool need32,
-                   bool need64)
+// Where a plan's device memory comes from: its own hipMalloc'd buffers, or
+// pieces of one caller-provided region (the allocation-free solve), carved in
+// order at 256-byte alignment.  In the region mode the tables are not copied
+// one by one: their bytes are staged at the same offsets in a host image of
+// the region, which the caller copies to the device in one transfer.
+struct Alloc {
+    char *base = nullptr;          // null: hipMalloc every buffer
+    size_t cap = 0, used = 0;
+    std::vector<char> *image = nullptr;  // host image of [base, base + used) for tables
+
+    int get(std::shared_ptr<DevBuf> &out, size_t bytes)
+    {
+        if (!base) return dev_alloc(out, bytes);
+        const size_t off = (used + 255) & ~(size_t)255;
+        if (bytes == 0) bytes = 16;
+        if (off > cap || bytes > cap - off) return POISSON_ERR_OUT_OF_MEMORY;
+        auto b = std::make_shared<DevBuf>();
+        b->p = base + off;
+        b->owned = false;
+        used = off + bytes;
+        out = b;
+        return POISSON_OK;
+    }
+    int put(std::shared_ptr<DevBuf> &out, const void *host, size_t bytes)
+    {
+        if (!base) return upload(out, host, bytes);
+        const int rc = get(out, bytes);
+        if (rc) return rc;
+        const size_t off = (size_t)((char *)out->p - base);
+        if (image->size() < off + bytes) image->resize(off + bytes, 0);
+        memcpy(image->data() + off, host, bytes);
+        return POISSON_OK;
+    }
+};
+
+int upload_complex(Alloc &A, std::shared_ptr<DevBuf> out[2], const std::vector<double> &tw,
+                   bool need32, bool need64)
 {
     int rc;
-    if (need64 && (rc = upload(out[0], tw.data(), tw.size() * sizeof(double)))) return rc;
+    if (need64 && (rc = A.put(out[0], tw.data(), tw.size() * sizeof(double)))) return rc;
     if (need32) {
         std::vector<float> f(tw.size());
         for (size_t i = 0; i < tw.size(); ++i) f[i] = (float)tw[i];  // one rounding
-        if ((rc = upload(out[1], f.data(), f.size() * sizeof(float)))) return rc;
+        if ((rc = A.put(out[1], f.data(), f.size() * sizeof(float)))) return rc;
     }
     return POISSON_OK;
 }
@@ -353,6 +389,7 @@ struct poisson_plan_s {
     std::vector<std::pair<int, int>> where;  // problem -> (group, member slot)
     std::shared_ptr<DevBuf> scalars;         // NSCAL FP64 scalars per problem
     std::unique_ptr<PinnedBuf> host_scalars;
+    void *hs = nullptr;                      // host copy of scalars + control records
     std::unique_ptr<PinnedBuf> host_ptrs;    // ProbPtrs staging for batched launches
     hipEvent_t ptrs_done = nullptr;          // last staging upload has been consumed
     hipStream_t ls = nullptr;                // stream the passes of the current solve use
@@ -487,7 +524,9 @@ bool same_problem(const poisson_desc_t &a, const poisson_desc_t &b)
            a.dz == b.dz && a.bc_x == b.bc_x && a.bc_y == b.bc_y && a.bc_z == b.bc_z;
 }
 
-int build_group(Group &g)
+// Tables of the group in A (copied now, or staged in A's host image), then
+// the field-sized buffers
+int build_group(Group &g, Alloc &A)
 {
     const poisson_desc_t &d = g.d;
     g.M = d.nx / 2;
@@ -495,34 +534,35 @@ int build_group(Group &g)
     const bool f32 = d.precision != POISSON_FP64, f64 = !f32;
     int rc;
     Tables &t = g.tab;
-    if ((rc = upload_complex(t.twx, twiddle_table(d.nx), f32, f64))) return rc;
-    if ((rc = upload_complex(t.twy, twiddle_table(d.ny), f32, f64))) return rc;
-    if (d.bc_z == POISSON_BC_PERIODIC && (rc = upload_complex(t.twz, twiddle_table(d.nz), f32, f64)))
+    if ((rc = upload_complex(A, t.twx, twiddle_table(d.nx), f32, f64))) return rc;
+    if ((rc = upload_complex(A, t.twy, twiddle_table(d.ny), f32, f64))) return rc;
+    if (d.bc_z == POISSON_BC_PERIODIC &&
+        (rc = upload_complex(A, t.twz, twiddle_table(d.nz), f32, f64)))
         return rc;
     // walls along x: nx cosine / sine modes; periodic: M + 1 wavenumbers
     auto lx = d.bc_x == POISSON_BC_PERIODIC ? eig_table(d.nx, d.dx, g.M + 1)
                                             : eig_table_walls(d.nx, d.dx, d.bc_x);
     if (d.bc_x != POISSON_BC_PERIODIC &&
-        (rc = upload_complex(t.twx4, quarter_table(d.nx), f32, f64)))
+        (rc = upload_complex(A, t.twx4, quarter_table(d.nx), f32, f64)))
         return rc;
     auto ly = d.bc_y == POISSON_BC_PERIODIC ? eig_table(d.ny, d.dy, d.ny)
                                             : eig_table_walls(d.ny, d.dy, d.bc_y);
     if (d.bc_y != POISSON_BC_PERIODIC &&
-        (rc = upload_complex(t.twy4, quarter_table(d.ny), f32, f64)))
+        (rc = upload_complex(A, t.twy4, quarter_table(d.ny), f32, f64)))
         return rc;
     auto lz = eig_table(d.nz, d.dz, d.nz);
-    if ((rc = upload(t.lamx, lx.data(), lx.size() * 8))) return rc;
-    if ((rc = upload(t.lamy, ly.data(), ly.size() * 8))) return rc;
-    if ((rc = upload(t.lamz, lz.data(), lz.size() * 8))) return rc;
+    if ((rc = A.put(t.lamx, lx.data(), lx.size() * 8))) return rc;
+    if ((rc = A.put(t.lamy, ly.data(), ly.size() * 8))) return rc;
+    if ((rc = A.put(t.lamz, lz.data(), lz.size() * 8))) return rc;
     const size_t n = g.members.size();
-    if (f32 && (rc = dev_alloc(g.S32, (size_t)g.N * 4 * n))) return rc;
+    g.npart = x_fwd_blocks(internal_prec(d.precision), d.nx, d.ny, d.nz, 0, 0);
+    g.part_stride = partial_slots(d) * 4;
+    if ((rc = A.get(g.partials, (size_t)g.part_stride * sizeof(double) * n))) return rc;
+    if (f32 && (rc = A.get(g.S32, (size_t)g.N * 4 * n))) return rc;
     // the first iterate of the refinement is an FP32 field: kept exactly in
     // 4 B/point, it is written and read back at half the bytes
     const bool refine = d.precision == POISSON_FP32_REFINE;
-    if (refine && (rc = dev_alloc(g.P32, (size_t)g.N * 4 * n))) return rc;
-    g.npart = x_fwd_blocks(internal_prec(d.precision), d.nx, d.ny, d.nz, 0, 0);
-    g.part_stride = partial_slots(d) * 4;
-    if ((rc = dev_alloc(g.partials, (size_t)g.part_stride * sizeof(double) * n))) return rc;
+    if (refine && (rc = A.get(g.P32, (size_t)g.N * 4 * n))) return rc;
     g.tune = initial_tune(g.d);
     return POISSON_OK;
 }
@@ -812,7 +852,7 @@ int correction_passes(LSet &L)
 
 int read_scalars(poisson_plan p, int count)
 {
-    hipError_t e = hipMemcpyAsync(p->host_scalars->p, p->scalars->p, NSCAL * sizeof(double) * count,
+    hipError_t e = hipMemcpyAsync(p->hs, p->scalars->p, NSCAL * sizeof(double) * count,
                                   hipMemcpyDeviceToHost, p->ls);
     if (e != hipSuccess) return hip_fail("scalar read-back", (int)e);
     e = hipStreamSynchronize(p->ls);
@@ -907,7 +947,7 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
         std::vector<double> rho_prev(count, -1.0), rho_first(count, -1.0);
         std::vector<int> corrections(count, 0), state(count, RUNNING);
         std::vector<char> checked(p->groups.size(), 0);
-        double *hs = (double *)p->host_scalars->p;
+        double *hs = (double *)p->hs;
         for (int it = 0; !rc; ++it) {
             // Residual of every running problem.  Each correction multiplies
             // the residual by about the relative accuracy of the FP32 solve,
@@ -982,7 +1022,7 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
         }
     } else if (!rc && st) {
         rc = read_scalars(p, count);
-        const double *hs = (const double *)p->host_scalars->p;
+        const double *hs = (const double *)p->hs;
         for (auto &g : p->groups)
             for (int i : g.members)
                 out[i].rhs_mean =
@@ -1200,7 +1240,7 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
         memcpy(p->dptrs_copy.data(), staging, sizeof(ProbPtrs) * count);
         p->dptrs_valid = true;
     }
-    const double *hs = (const double *)p->host_scalars->p;
+    const double *hs = (const double *)p->hs;
     const int *hc = p->host_ctrl;
     const int max_rounds = p->max_refine / GRAPH_SEGMENTS + 2;
     for (int round = 0; !rc; ++round) {
@@ -1227,7 +1267,7 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
         }
         if (!refine && !st) break;
         // scalars and control records are one allocation: one read-back
-        if (hipMemcpyAsync(p->host_scalars->p, p->scalars->p, state_bytes(count),
+        if (hipMemcpyAsync(p->hs, p->scalars->p, state_bytes(count),
                            hipMemcpyDeviceToHost, p->gstream) != hipSuccess ||
             hipStreamSynchronize(p->gstream) != hipSuccess) {
             rc = hip_fail("scalar read-back", (int)hipGetLastError());
@@ -1410,7 +1450,8 @@ int create_plan(const poisson_desc_t *descs, int count, void *stream, bool batch
     }
     int off = 0;
     for (auto &g : p->groups) {
-        int rc = build_group(g);
+        Alloc A;
+        int rc = build_group(g, A);
         if (rc) return rc;
         g.host_off = off;
         off += (int)g.members.size();
@@ -1420,8 +1461,9 @@ int create_plan(const poisson_desc_t *descs, int count, void *stream, bool batch
     if (rc) return rc;
     if (hipMemset(p->scalars->p, 0, state_bytes(count)) != hipSuccess) return POISSON_ERR_HIP;
     if ((rc = pinned_alloc(p->host_scalars, state_bytes(count)))) return rc;
+    p->hs = p->host_scalars->p;
     p->ctrl = (int *)((double *)p->scalars->p + NSCAL * count);
-    p->host_ctrl = (int *)((double *)p->host_scalars->p + NSCAL * count);
+    p->host_ctrl = (int *)((double *)p->hs + NSCAL * count);
     // pointer arrays of batched launches and of the device-side loop
     if ((rc = dev_alloc(p->dptrs, sizeof(ProbPtrs) * count))) return rc;
     p->dptrs_copy.resize(count);
@@ -1486,6 +1528,132 @@ struct DeviceGuard {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// allocation-free solve (poisson_solve_noalloc)
+// ---------------------------------------------------------------------------
+// Every device buffer of the allocation-free entry point -- twiddle and
+// eigenvalue tables, partial-sum records, scalars and control records, the
+// FP32 spectrum and the FP32 first iterate -- is a piece of this array.  Each
+// GPU the library runs on holds its own copy for the life of the process.
+// Host code never passes the array's name to a kernel or a copy: it uses the
+// device address hipGetSymbolAddress returns, kept per device.
+static __device__ __align__(256) char scratch[POISSON_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+// per device: the scratch array's address and a host-side plan whose buffers
+// are pieces of it, kept while calls pass the same descriptor
+struct NoAllocDevice {
+    std::mutex mu;
+    char *base = nullptr;
+    std::unique_ptr<poisson_plan_s> plan;
+    poisson_desc_t desc{};
+    std::vector<char> image;  // host image of the table region
+    std::vector<double> host_state;
+};
+NoAllocDevice noalloc_dev[NOALLOC_MAX_DEVICES];
+
+bool same_desc(const poisson_desc_t &a, const poisson_desc_t &b)
+{
+    return same_problem(a, b) && a.precision == b.precision && a.rtol == b.rtol &&
+           a.max_refine == b.max_refine;
+}
+
+// The plan of descriptor d inside the scratch array of device D: tables,
+// partial sums, the FP32 fields, then the scalars and control records; the
+// tables are copied in one transfer on `stream`, which is then synchronised
+// (the host image must outlive the copy).  Fails with TOO_LARGE, before any
+// copy, when the pieces do not fit.
+int noalloc_build(NoAllocDevice &D, const poisson_desc_t &d, int dev, hipStream_t stream)
+{
+    D.plan.reset();
+    std::unique_ptr<poisson_plan_s> p(new poisson_plan_s());
+    p->stream = stream;
+    p->device = dev;
+    p->precision = d.precision;
+    p->rtol = d.rtol;
+    p->max_refine = d.max_refine;
+    p->batched = false;
+    p->count = 1;
+    p->where.assign(1, {0, 0});
+    p->groups.emplace_back();
+    Group &g = p->groups.back();
+    g.d = d;
+    g.members.assign(1, 0);
+    D.image.clear();
+    Alloc A;
+    A.base = D.base;
+    A.cap = POISSON_NOALLOC_SCRATCH_BYTES;
+    A.image = &D.image;
+    int rc = build_group(g, A);
+    if (!rc) rc = A.get(p->scalars, state_bytes(1));
+    if (rc == POISSON_ERR_OUT_OF_MEMORY) {
+        fprintf(stderr,
+                "libpoisson: poisson_solve_noalloc: %dx%dx%d (%s) needs more than the %zu bytes "
+                "of its fixed scratch\n",
+                d.nx, d.ny, d.nz,
+                d.precision == POISSON_FP64 ? "fp64"
+                                            : (d.precision == POISSON_FP32 ? "fp32" : "fp32_refine"),
+                (size_t)POISSON_NOALLOC_SCRATCH_BYTES);
+        return POISSON_ERR_TOO_LARGE;
+    }
+    if (rc) return rc;
+    if (!D.image.empty()) {
+        hipError_t e = hipMemcpyAsync(D.base, D.image.data(), D.image.size(),
+                                      hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail("scratch table upload", (int)e);
+    }
+    D.host_state.assign((state_bytes(1) + sizeof(double) - 1) / sizeof(double), 0.0);
+    p->hs = D.host_state.data();
+    p->ctrl = (int *)((double *)p->scalars->p + NSCAL);
+    p->host_ctrl = (int *)((double *)p->hs + NSCAL);
+    D.plan = std::move(p);
+    D.desc = d;
+    return POISSON_OK;
+}
+
+int solve_noalloc(const poisson_desc_t *d, void *stream, const double *rhs, double *sol,
+                  poisson_stats_t *stats)
+{
+    if (!d || !rhs || !sol) return POISSON_ERR_INVALID_ARG;
+    int rc = validate(d);
+    if (rc) return rc;
+    const long long n = (long long)d->nx * d->ny * d->nz;
+    if (overlaps(rhs, n, sol, n)) return POISSON_ERR_INVALID_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hip_fail("hipGetDevice", (int)hipGetLastError());
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return POISSON_ERR_UNSUPPORTED;
+    NoAllocDevice &D = noalloc_dev[dev];
+    std::lock_guard<std::mutex> lk(D.mu);
+    if (!D.base) {
+        // once per device, with the device current: the address of this
+        // device's copy of the scratch array
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail("scratch symbol address", (int)e);
+        D.base = (char *)ptr;
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    if (!D.plan || !same_desc(D.desc, *d)) {
+        if ((rc = noalloc_build(D, *d, dev, s))) {
+            D.plan.reset();
+            return rc;
+        }
+    }
+    poisson_plan_s *p = D.plan.get();
+    p->stream = s;
+    // the array keeps the previous call's contents: clear the scalars and
+    // control records (the other pieces are written before they are read)
+    const int e = launch_zero(p->scalars->p, state_bytes(1), s);
+    if (e) return hip_fail("scratch clear", e);
+    return solve_all(p, &rhs, &sol, stats);
+}
+
+}  // namespace
+
 extern "C" {
 
 int poisson_desc_init(poisson_desc_t *d)
@@ -1527,6 +1695,12 @@ int poisson_solve(poisson_plan plan, const double *rhs, double *sol, poisson_sta
     DeviceGuard guard(plan->device);
     return plan->graph_mode ? solve_device(plan, &rhs, &sol, stats)
                             : solve_all(plan, &rhs, &sol, stats);
+}
+
+int poisson_solve_noalloc(const poisson_desc_t *d, void *stream, const double *rhs, double *sol,
+                          poisson_stats_t *stats)
+{
+    return solve_noalloc(d, stream, rhs, sol, stats);
 }
 
 int poisson_batch_solve(poisson_plan plan, const double *const *rhs, double *const *sol,
@@ -1635,6 +1809,7 @@ const char *poisson_error_string(int code)
     case POISSON_ERR_HIP: return "HIP runtime error";
     case POISSON_ERR_NOT_CONVERGED: return "iterative refinement did not converge";
     case POISSON_ERR_NONFINITE: return "non-finite residual";
+    case POISSON_ERR_TOO_LARGE: return "problem exceeds the fixed scratch of the allocation-free solve";
     default: return "unknown error code";
     }
 }

@@ -271,6 +271,8 @@ int launch_residual_check(const XFwdArgs &a, int *nblocks_out, hipStream_t s);
 int residual_check_blocks(int nx, int ny, int nz, int kr_max, int kr_nb = 1);
 // dst[i] = (double)src[i], i < n (device arrays)
 int launch_widen(const float *src, double *dst, size_t n, hipStream_t s);
+// clear `bytes` (a multiple of 4) at dst with a kernel
+int launch_zero(void *dst, size_t bytes, hipStream_t s);
 
 // Velocity correction and pressure update of the projection step:
 // u -= bx Dx+ psi, v -= by Dy+ psi, w -= bz Dz+ psi (not on a top wall),

@@ -333,6 +333,26 @@ int launch_widen(const float *src, double *dst, size_t n, hipStream_t s)
     return (int)hipGetLastError();
 }
 
+// zero n 4-byte words (control records and scalars of a plan whose state
+// must start cleared; a kernel rather than a memset so the clear also
+// behaves inside a captured graph)
+__global__ __launch_bounds__(256) void k_zero_words(unsigned *dst, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = 0u;
+}
+
+int launch_zero(void *dst, size_t bytes, hipStream_t s)
+{
+    if (!dst || bytes % 4) return (int)hipErrorInvalidValue;
+    const size_t n = bytes / 4;
+    if (n == 0) return 0;
+    const size_t want = (n + 255) / 256;
+    const int nb = (int)(want < 1024 ? want : 1024);
+    hipLaunchKernelGGL(k_zero_words, dim3(nb), dim3(256), 0, s, (unsigned *)dst, n);
+    return (int)hipGetLastError();
+}
+
 int launch_correct(const CorrArgs &a, hipStream_t s)
 {
     switch (a.nx / 2) { PK_X_LENGTHS(PK_CASE_CO) default: return -1; }

@@ -21,6 +21,7 @@ ERR_OUT_OF_MEMORY = -3
 ERR_HIP = -4
 ERR_NOT_CONVERGED = -5
 ERR_NONFINITE = -6
+ERR_TOO_LARGE = -7
 
 BC_PERIODIC = 0
 BC_NEUMANN = 1
@@ -68,7 +69,7 @@ SYMBOLS = ["poisson_desc_init", "poisson_desc_validate", "poisson_workspace_byte
            "poisson_batch_plan_create", "poisson_batch_solve", "poisson_error_string",
            "poisson_plan_set_timing", "poisson_plan_reset_timing", "poisson_plan_get_timing",
            "poisson_plan_set_graph", "poisson_plan_autotune", "poisson_plan_describe",
-           "poisson_project"]
+           "poisson_project", "poisson_solve_noalloc"]
 
 # refinement-loop drivers of poisson_plan_set_graph
 GRAPH_MODES = {"host": 0, "graph": 1, "device": 2}
@@ -106,6 +107,7 @@ def lib():
     L.poisson_plan_describe.argtypes = [P, ctypes.c_char_p, ctypes.c_int]
     L.poisson_project.argtypes = [P, P, P, P, P, P, ctypes.c_double, ctypes.c_double,
                                   ctypes.POINTER(Stats)]
+    L.poisson_solve_noalloc.argtypes = [dp, P, P, P, ctypes.POINTER(Stats)]
     for name in SYMBOLS:
         if name != "poisson_workspace_bytes" and name != "poisson_error_string":
             getattr(L, name).restype = ctypes.c_int
@@ -156,6 +158,27 @@ def _stream_handle(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def solve_noalloc(rhs, out, dx=1.0, dy=1.0, dz=1.0, bc_z=BC_NEUMANN, precision="fp64",
+                  rtol=1e-10, max_refine=8, bc_x=BC_PERIODIC, bc_y=BC_PERIODIC, stream=None,
+                  check=True):
+    """poisson_solve_noalloc: one solve without a plan and without device
+    allocation (the library's fixed per-GPU scratch).  rhs, out: float64 GPU
+    tensors of shape (nz, ny, nx).  Returns the stats dict."""
+    nz, ny, nx = rhs.shape
+    _check_field(rhs, (nz, ny, nx), "rhs")
+    _check_field(out, (nz, ny, nx), "out")
+    d = make_desc(nx, ny, nz, dx, dy, dz, bc_z, precision, rtol, max_refine, bc_x, bc_y)
+    st = Stats()
+    rc = lib().poisson_solve_noalloc(ctypes.byref(d), _stream_handle(stream),
+                                     ctypes.c_void_p(rhs.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), ctypes.byref(st))
+    if check and rc != OK:
+        raise PoissonError(rc, "poisson_solve_noalloc")
+    r = st.as_dict()
+    r["status"] = rc
+    return r
 
 
 class Plan:

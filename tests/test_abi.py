@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_error_strings():
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         s = P.error_string(code)
         assert s and "unknown" not in s
     assert "unknown" in P.error_string(-99)
