@@ -373,7 +373,7 @@ PASS_PATTERNS = [
     ("y_inv_{p}", r"prec_{p}::k_y<\d+, true[,>]"),
     ("y_fwd_walls_{p}", r"prec_{p}::k_yw<\d+, false>"),
     ("y_inv_walls_{p}", r"prec_{p}::k_yw<\d+, true>"),
-    ("z_walls_{p}", r"prec_{p}::k_z_walls2?<"),
+    ("z_walls_{p}", r"prec_{p}::k_z_walls(_r)?<"),
     ("z_periodic_{p}", r"prec_{p}::k_z_per<"),
 ]
 

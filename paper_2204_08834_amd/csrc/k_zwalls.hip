@@ -407,15 +407,18 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
     }
 }
 
-// Walls along x and y: every column (m, ky) holds two real modes as A + iB
-// (x-modes 2m and 2m+1, real-linear y coefficients), i.e. two real
-// tridiagonal systems with different eigenvalues.  This variant gives each
-// lane one column and runs the recurrences above twice, one set for the real
-// part (s_A) and one for the imaginary part (s_B), instead of spending two
-// lanes on it; everything else (deficit form, chunk scans, the FP64 zero
-// mode for part A of column (0, 0)) is as in k_z_walls.
+// Walls along x and y, one real system per lane.  Column (m, ky) of the
+// spectrum holds the real coefficients of x-modes 2m and 2m+1 as its real
+// and imaginary parts, and the y-modes are real as well, so viewed as reals
+// the spectrum is an (nz, ny, nx) array whose entry r of row ky is the
+// coefficient of x-mode r: each (r, ky) is one real tridiagonal system with
+// s = -(lam_x(r) + lam_y(ky)) dz^2.  A lane takes one such column (a wavefront
+// reads a contiguous run of reals per plane, no lane exchange) and runs the
+// recurrences of k_z_walls on real values: half the registers of a complex
+// lane whose imaginary half is zero.  Column (0, 0) is the zero mode (FP64,
+// as in k_z_walls).
 template <int L, int W, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_z_walls2(ZArgs a0, int C)
+__global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
 {
     if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
     ZArgs a = a0;
@@ -425,65 +428,53 @@ __global__ __launch_bounds__(MAXT) void k_z_walls2(ZArgs a0, int C)
         if (a.zero_mean_out) a.zero_mean_out = pq.scal;
     }
     extern __shared__ double smem_d[];
-    R *buf = (R *)smem_d;                                       // C*W slots of 8 reals
-    double *zbuf = smem_d + ((C * W * 8 * sizeof(R) + 7) / 8);  // 3*C doubles
+    R *buf = (R *)smem_d;                                       // C*W slots of 4 reals
+    double *zbuf = smem_d + ((C * W * 4 * sizeof(R) + 7) / 8);  // 3*C doubles
 
     const int t = threadIdx.x;
     const int w = t % W, c = t / W;
-    const int nz = a.nz, M = a.M, ny = a.ny;
-    const size_t plane = (size_t)ny * M;
-    PK_GLOBAL Cx<R> *S = gbl((Cx<R> *)a.S);
+    const int nz = a.nz, nx = a.nx, ny = a.ny;
+    const size_t plane = (size_t)ny * nx;  // reals per z-plane
+    PK_GLOBAL R *S = gbl((R *)a.S);
     const int s = c * L;
     const int e = (s + L < nz) ? s + L : nz;  // chunk rows [s, e)
     const double scale = a.dz2 * a.inv_nxny;
 
     const int q = block_order((int)blockIdx.x, (int)gridDim.x, a.reverse) * W + w;
-    const int mm = q % M, ky = q / M;
-    const bool active = q < ny * M;
-    const bool zero_lane = active && q == 0 && !a.regular;  // part A of column (0, 0)
-    const double ly = active ? a.lamy[ky] : 0.0;
-    const double sA_d = (active && !zero_lane) ? -(a.lamx[2 * mm] + ly) * a.dz2 : 1.0;
-    const double sB_d = active ? -(a.lamx[2 * mm + 1] + ly) * a.dz2 : 1.0;
+    const int r = q % nx, ky = q / nx;
+    const bool active = q < ny * nx;
+    const bool zero_lane = active && q == 0 && !a.regular;
+    const double s_d = (active && !zero_lane) ? -(a.lamx[r] + a.lamy[ky]) * a.dz2 : 1.0;
 
-    Cx<R> d[L];
+    R d[L];
     {
-        const PK_GLOBAL Cx<R> *col = S + (size_t)s * plane + (active ? q : 0);
+        const PK_GLOBAL R *col = S + (size_t)s * plane + (active ? q : 0);
 #pragma unroll
-        for (int i = 0; i < L; ++i) {
-            d[i] = {R(0), R(0)};
-            if (active && s + i < nz) {
-                const Cx<R> g = col[(size_t)i * plane];
-                d[i] = {g.re * R(scale), g.im * R(scale)};
-            }
-        }
+        for (int i = 0; i < L; ++i)
+            d[i] = (active && s + i < nz) ? col[(size_t)i * plane] * R(scale) : R(0);
     }
-    auto zraw = [&](int k) -> double { return double(S[(size_t)k * plane].re); };
+    // zero wavenumber: raw values re-read (L1-resident) whenever needed
+    auto zraw = [&](int k) -> double { return double(S[(size_t)k * plane]); };
 
-    const R sA = R(sA_d), sB = R(sB_d);
-    const R mwA = rcp_nr(R(1) + sA), mwB = rcp_nr(R(1) + sB);
-    const R mwsA = sA * mwA, mwsB = sB * mwB;
+    const R sv = R(s_d);
+    const R mw = rcp_nr(R(1) + sv);
+    const R mws = sv * mw;
     const R dir2 = a.dirichlet_z ? R(2) : R(0);
-    const R mws0A = a.dirichlet_z ? (sA + R(2)) * rcp_nr(sA + R(3)) : mwsA;
-    const R mws0B = a.dirichlet_z ? (sB + R(2)) * rcp_nr(sB + R(3)) : mwsB;
+    const R mws0 = a.dirichlet_z ? (sv + R(2)) * rcp_nr(sv + R(3)) : mws;
 
-    // ---- phase 1: Moebius products of the chunk, one per part -------------
-    R a00 = R(1), a01 = R(0), a10 = R(0), a11 = R(1);
-    R b00 = R(1), b01 = R(0), b10 = R(0), b11 = R(1);
+    // ---- phase 1: Moebius product of the chunk (v recurrence) -----------
+    R p00 = R(1), p01 = R(0), p10 = R(0), p11 = R(1);
 #pragma unroll
     for (int i = 0; i < L; ++i) {
         const int k = s + i;
-        const R xA = (k == 0) ? R(0) : mwA, yA = (k == 0) ? mws0A : mwsA;
-        const R xB = (k == 0) ? R(0) : mwB, yB = (k == 0) ? mws0B : mwsB;
-        const R n00 = xA * a00 + yA * a10, n01 = xA * a01 + yA * a11;
-        const R n10 = xA * a00 + a10, n11 = xA * a01 + a11;
-        a00 = n00; a01 = n01; a10 = n10; a11 = n11;
-        const R m00 = xB * b00 + yB * b10, m01 = xB * b01 + yB * b11;
-        const R m10 = xB * b00 + b10, m11 = xB * b01 + b11;
-        b00 = m00; b01 = m01; b10 = m10; b11 = m11;
+        const R x0 = (k == 0) ? R(0) : mw;
+        const R y0 = (k == 0) ? mws0 : mws;
+        const R n00 = x0 * p00 + y0 * p10, n01 = x0 * p01 + y0 * p11;
+        const R n10 = x0 * p00 + p10, n11 = x0 * p01 + p11;
+        p00 = n00; p01 = n01; p10 = n10; p11 = n11;
     }
-    R *slot = buf + (size_t)(c * W + w) * 8;
-    slot[0] = a00; slot[1] = a01; slot[2] = a10; slot[3] = a11;
-    slot[4] = b00; slot[5] = b01; slot[6] = b10; slot[7] = b11;
+    R *slot = buf + (size_t)(c * W + w) * 4;
+    slot[0] = p00; slot[1] = p01; slot[2] = p10; slot[3] = p11;
     if (zero_lane) {
         double zsum = 0.0;
         for (int k = s; k < e; ++k) zsum += zraw(k);
@@ -491,11 +482,23 @@ __global__ __launch_bounds__(MAXT) void k_z_walls2(ZArgs a0, int C)
     }
     __syncthreads();  // S1
 
-    R vA0 = R(0), vB0 = R(0);
-    for (int cc = 0; cc < c; ++cc) {
-        const R *o = buf + (size_t)(cc * W + w) * 8;
-        vA0 = (o[0] * vA0 + o[1]) * rcp_nr(o[2] * vA0 + o[3]);
-        vB0 = (o[4] * vB0 + o[5]) * rcp_nr(o[6] * vB0 + o[7]);
+    R vprev0 = R(0);
+    {
+        int cc = 0;
+        for (; cc + 4 <= c; cc += 4) {
+            R o[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) o[u][j] = buf[(size_t)((cc + u) * W + w) * 4 + j];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                vprev0 = (o[u][0] * vprev0 + o[u][1]) * rcp_nr(o[u][2] * vprev0 + o[u][3]);
+        }
+        for (; cc < c; ++cc) {
+            const R *o = buf + (size_t)(cc * W + w) * 4;
+            vprev0 = (o[0] * vprev0 + o[1]) * rcp_nr(o[2] * vprev0 + o[3]);
+        }
     }
 
     double zmu = 0.0, zF0 = 0.0, zsF = 0.0;
@@ -516,65 +519,62 @@ __global__ __launch_bounds__(MAXT) void k_z_walls2(ZArgs a0, int C)
     }
     __syncthreads();  // S2
 
-    // ---- phase 2: local forward elimination, both parts -------------------
-    R vkA[L], vkB[L];
-    R ulA = R(0), ulB = R(0);
+    // ---- phase 2: local forward elimination ------------------------------
+    R vk[L];
+    R ulast = R(0);
     {
-        Cx<R> Dp = {R(0), R(0)};
-        R GpA = R(1), GpB = R(1), vpA = vA0, vpB = vB0;
+        R Dp = R(0), Gp = R(1), vprev = vprev0;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             const int k = s + i;
+            const R ex = (k == 0) ? sv + dir2 : sv + vprev;
             const bool last = k >= nz - 1;
-            const R exA = (k == 0) ? sA + dir2 : sA + vpA;
-            const R exB = (k == 0) ? sB + dir2 : sB + vpB;
-            const R pivA = (nz == 1) ? sA + dir2 + dir2 : (k == nz - 1 ? exA + dir2 : R(1) + exA);
-            const R pivB = (nz == 1) ? sB + dir2 + dir2 : (k == nz - 1 ? exB + dir2 : R(1) + exB);
-            const R uA = rcp_nr(pivA), uB = rcp_nr(pivB);
-            const R nA = last ? R(1) : exA * uA, nB = last ? R(1) : exB * uB;
-            Dp = {(Dp.re - d[i].re) * uA, (Dp.im - d[i].im) * uB};
-            GpA = uA * GpA;
-            GpB = uB * GpB;
-            if (k == nz - 1) {
-                ulA = uA;
-                ulB = uB;
-            }
-            vkA[i] = nA;
-            vkB[i] = nB;
+            const R piv = (nz == 1) ? sv + dir2 + dir2 : (k == nz - 1 ? ex + dir2 : R(1) + ex);
+            const R u = rcp_nr(piv);
+            const R vnew = last ? R(1) : ex * u;
+            Dp = (Dp - d[i]) * u;
+            Gp = u * Gp;
+            if (k == nz - 1) ulast = u;
+            vk[i] = vnew;
             d[i] = Dp;
-            vpA = nA;
-            vpB = nB;
+            vprev = vnew;
         }
-        slot[0] = Dp.re; slot[1] = Dp.im; slot[2] = GpA; slot[3] = GpB;
+        slot[0] = Dp; slot[1] = Gp;
     }
     if (zero_lane) zbuf[C + c] = zsF;
     __syncthreads();  // S3
 
     {
-        Cx<R> dprev = {R(0), R(0)};
-        for (int cc = 0; cc < c; ++cc) {
-            const R *o = buf + (size_t)(cc * W + w) * 8;
-            dprev = {o[0] + o[2] * dprev.re, o[1] + o[3] * dprev.im};
+        R dprev = R(0);
+        int cc = 0;
+        for (; cc + 4 <= c; cc += 4) {
+            R o[4][2];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) o[u][j] = buf[(size_t)((cc + u) * W + w) * 4 + j];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dprev = o[u][0] + o[u][1] * dprev;
         }
-        R GrA = R(1), GrB = R(1);
+        for (; cc < c; ++cc) {
+            const R *o = buf + (size_t)(cc * W + w) * 4;
+            dprev = o[0] + o[1] * dprev;
+        }
+        R Gr = R(1);
 #pragma unroll
         for (int i = 0; i < L; ++i) {
-            const bool lr = s + i == nz - 1;
-            GrA *= lr ? ulA : R(1) - vkA[i];
-            GrB *= lr ? ulB : R(1) - vkB[i];
-            d[i] = {d[i].re + GrA * dprev.re, d[i].im + GrB * dprev.im};
+            Gr *= (s + i == nz - 1) ? ulast : R(1) - vk[i];
+            d[i] = d[i] + Gr * dprev;
         }
     }
-    // ---- phase 3: local back substitution ---------------------------------
-    Cx<R> Xn = {R(0), R(0)};
-    R HnA = R(1), HnB = R(1);
+    // ---- phase 3: local back substitution --------------------------------
+    R Xn = R(0), Hn = R(1);
 #pragma unroll
     for (int i = L - 1; i >= 0; --i) {
-        const Cx<R> X = {d[i].re + (Xn.re - vkA[i] * Xn.re), d[i].im + (Xn.im - vkB[i] * Xn.im)};
+        const R X = d[i] + (Xn - vk[i] * Xn);
         d[i] = X;
         Xn = X;
-        HnA *= R(1) - vkA[i];
-        HnB *= R(1) - vkB[i];
+        Hn *= R(1) - vk[i];
     }
     double zP0 = 0.0, zsx = 0.0;
     if (zero_lane) {
@@ -587,27 +587,34 @@ __global__ __launch_bounds__(MAXT) void k_z_walls2(ZArgs a0, int C)
         }
     }
     __syncthreads();  // S4
-    slot[0] = Xn.re; slot[1] = Xn.im; slot[2] = HnA; slot[3] = HnB;
+    slot[0] = Xn; slot[1] = Hn;
     if (zero_lane) zbuf[2 * C + c] = zsx;
     __syncthreads();  // S5
 
     {
-        Cx<R> y = {R(0), R(0)};
-        for (int cc = C - 1; cc > c; --cc) {
-            const R *o = buf + (size_t)(cc * W + w) * 8;
-            y = {o[0] + o[2] * y.re, o[1] + o[3] * y.im};
+        R y = R(0);
+        int cc = C - 1;
+        for (; cc - 4 >= c; cc -= 4) {
+            R o[4][2];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) o[u][j] = buf[(size_t)((cc - u) * W + w) * 4 + j];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) y = o[u][0] + o[u][1] * y;
         }
-        R HrA = R(1), HrB = R(1);
+        for (; cc > c; --cc) {
+            const R *o = buf + (size_t)(cc * W + w) * 4;
+            y = o[0] + o[1] * y;
+        }
+        R Hr = R(1);
 #pragma unroll
         for (int i = L - 1; i >= 0; --i) {
-            HrA *= R(1) - vkA[i];
-            HrB *= R(1) - vkB[i];
-            d[i] = {d[i].re + HrA * y.re, d[i].im + HrB * y.im};
+            Hr *= R(1) - vk[i];
+            d[i] = d[i] + Hr * y;
         }
     }
     if (zero_lane) {
-        // part A of column (0, 0): the FP64 zero-mode solution (part B keeps
-        // its own, regular, solve)
         double tot = 0.0;
         for (int cc = 0; cc < C; ++cc) tot += zbuf[2 * C + cc];
         const double mean = tot / nz;
@@ -616,7 +623,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls2(ZArgs a0, int C)
         for (int i = 0; i < L; ++i) {
             const int k = s + i;
             if (k < nz) {
-                d[i].re = R(xk - mean);
+                d[i] = R(xk - mean);
                 run += (zraw(k) - zmu) * scale;
                 xk += run;
             }
@@ -625,7 +632,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls2(ZArgs a0, int C)
     __syncthreads();  // S6: every zero-lane re-read of column (0,0) is done
 
     if (active) {
-        PK_GLOBAL Cx<R> *col = S + (size_t)s * plane + q;
+        PK_GLOBAL R *col = S + (size_t)s * plane + q;
 #pragma unroll
         for (int i = 0; i < L; ++i)
             if (s + i < nz) col[(size_t)i * plane] = d[i];
@@ -633,13 +640,13 @@ __global__ __launch_bounds__(MAXT) void k_z_walls2(ZArgs a0, int C)
 }
 
 template <int L, int W, int MAXT>
-static int run_zw2(const ZArgs &a, hipStream_t s)
+static int run_zwr(const ZArgs &a, hipStream_t s)
 {
     const int C = (a.nz + L - 1) / L;
     if (C * W > MAXT) return -1;
-    const int nb = (a.ny * a.M + W - 1) / W;
-    const size_t shm = ((C * W * 8 * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double);
-    hipLaunchKernelGGL((k_z_walls2<L, W, MAXT>), dim3(nb, a.batch ? a.nbatch : 1), dim3(W * C),
+    const int nb = (a.ny * a.nx + W - 1) / W;
+    const size_t shm = ((C * W * 4 * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double);
+    hipLaunchKernelGGL((k_z_walls_r<L, W, MAXT>), dim3(nb, a.batch ? a.nbatch : 1), dim3(W * C),
                        shm, s, a, C);
     return (int)hipGetLastError();
 }
@@ -672,23 +679,49 @@ int PK_SUFFIX(launch_z_walls)(const ZArgs &a, hipStream_t s)
     //   3: 8-row chunks, 256-byte row runs
     const int nz = a.nz;
     constexpr bool F32 = sizeof(R) == 4;
-    if (F32 && a.xwall && a.ywall) {
-        // every column holds two real modes: one lane per column, both solves.
-        // FP32 only: measured at 512x512x256 the cavity's z pass drops from
-        // 219 to 168 us; in FP64 the doubled recurrences need 256 VGPRs with
-        // 16-row chunks (or twice the chunk scans with 8), 740 against 590 us
-        // for two lanes per column.  Variant bit 0 selects 16-row chunks.
-        const bool n16 = (a.variant & 1) != 0;
-        if (nz <= 64) return run_zw2<8, 32, 256>(a, s);
-        if (n16) {
-            if (nz <= 256) return run_zw2<16, 16, 256>(a, s);
-            if (nz <= 512) return run_zw2<16, 16, 512>(a, s);
-            if (nz <= 1024) return run_zw2<16, 16, 1024>(a, s);
+    if (a.xwall && a.ywall) {
+        // every column holds two real modes: one real system per lane
+        // (k_z_walls_r).  Tiles as below: 16- or 8-row chunks, 128- or
+        // 256-byte row runs.
+        const int v = a.variant & 3;
+        const bool c8 = v == 1 || v == 3, wide = v >= 2;
+        if (nz <= 64) return run_zwr<8, 32, 256>(a, s);
+        if constexpr (F32) {
+            if (!c8 && !wide) {
+                if (nz <= 128) return run_zwr<16, 32, 256>(a, s);
+                if (nz <= 256) return run_zwr<16, 32, 512>(a, s);
+                if (nz <= 512) return run_zwr<16, 32, 1024>(a, s);
+            } else if (!c8) {
+                if (nz <= 128) return run_zwr<16, 64, 512>(a, s);
+                if (nz <= 256) return run_zwr<16, 64, 1024>(a, s);
+            } else if (!wide) {
+                if (nz <= 128) return run_zwr<8, 32, 512>(a, s);
+                if (nz <= 256) return run_zwr<8, 32, 1024>(a, s);
+            } else {
+                if (nz <= 128) return run_zwr<8, 64, 1024>(a, s);
+            }
+        } else {
+            if (!c8 && !wide) {
+                if (nz <= 256) return run_zwr<16, 16, 256>(a, s);
+                if (nz <= 512) return run_zwr<16, 16, 512>(a, s);
+            } else if (!c8) {
+                if (nz <= 128) return run_zwr<16, 32, 256>(a, s);
+                if (nz <= 256) return run_zwr<16, 32, 512>(a, s);
+            } else if (!wide) {
+                if (nz <= 128) return run_zwr<8, 16, 256>(a, s);
+                if (nz <= 256) return run_zwr<8, 16, 512>(a, s);
+                if (nz <= 512) return run_zwr<8, 16, 1024>(a, s);
+            } else {
+                if (nz <= 128) return run_zwr<8, 32, 512>(a, s);
+                if (nz <= 256) return run_zwr<8, 32, 1024>(a, s);
+            }
+            if (nz <= 512) return run_zwr<16, 16, 512>(a, s);
         }
-        if (nz <= 256) return run_zw2<8, 16, 512>(a, s);
-        if (nz <= 512) return run_zw2<8, 16, 1024>(a, s);
-        if (nz <= 1024) return run_zw2<8, 8, 1024>(a, s);
-        if (nz <= 4096) return run_zw2<8, 2, 1024>(a, s);
+        // beyond the variant's reach: narrower tiles of 8-row chunks (a
+        // 1024-thread workgroup of 16-row chunks would spill registers)
+        if (nz <= 1024) return run_zwr<8, 8, 1024>(a, s);
+        if (nz <= 2048) return run_zwr<8, 4, 1024>(a, s);
+        if (nz <= 4096) return run_zwr<8, 2, 1024>(a, s);
         return -1;
     }
     const bool c8 = a.variant == 1 || a.variant == 3;

@@ -23,7 +23,7 @@ KERNELS = {
     "void pk::prec_f64::k_yw<512, false>(pk::YArgs)": "y_fwd_walls_f64",
     "void pk::prec_f32::k_yw<96, true>(pk::YArgs)": "y_inv_walls_f32",
     "void pk::prec_f64::k_z_walls<16, 16, 256>(pk::ZArgs, int, int)": "z_walls_f64",
-    "void pk::prec_f32::k_z_walls2<8, 16, 512>(pk::ZArgs, int)": "z_walls_f32",
+    "void pk::prec_f32::k_z_walls_r<8, 16, 512>(pk::ZArgs, int)": "z_walls_f32",
     "void pk::prec_f32::k_z_per<64>(pk::ZArgs, int)": "z_periodic_f32",
     "void pk::k_residual_check<256>(pk::XFwdArgs)": "residual_check_f64",
     "pk::k_sum_partials(double const*, int, double*, pk::ProbPtrs const*, int, int, int)":
