@@ -38,7 +38,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published figure
 COPY_BYTES = 1 << 30
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_rb512.txt")
 KERNEL_SOURCES = ["api.cpp", "common.hpp", "fft_core.hpp", "lengths.hpp", "k_misc.hip",
-                  "k_xpass.hip", "k_ypass.hip", "k_zperiodic.hip", "k_zwalls.hip"]
+                  "k_xpass.hip", "k_xlist.hip", "k_ypass.hip", "k_zperiodic.hip", "k_zwalls.hip",
+                  "zper_body.hpp", "stencil.hpp"]
 
 DESCRIPTIONS = {
     "rb512": "512x512x256 walls-in-z, box 2x2x1, RHS = div(u/rho_face) with a two-layer "
@@ -97,8 +98,9 @@ def time_solves(plan, rhs, out, steps, sync_each):
 def bench_batch(steps, warmup):
     """The 64-problem mixed batch (24 x 64^3 periodic, 24 x 96x96x48 walls,
     16 x 128x128x64 walls; U(-1,1) velocity divergences, seeds 1000+b),
-    FP32 + refinement to 1e-10, through one batched plan: host-driven loop
-    against the captured-graph loop."""
+    FP32 + refinement to 1e-10, through one batched plan: host-driven loop,
+    captured-graph loop and eager device loop in the work-list schedule, and
+    the two device loops in the per-group schedule for comparison."""
     import torch
     from paper_2204_08834_amd import inputs, poisson
     probs = inputs.batch_mixed64()
@@ -109,11 +111,21 @@ def bench_batch(steps, warmup):
     rhs = [torch.from_numpy(p.f).cuda() for p in probs]
     outs = [torch.empty_like(r) for r in rhs]
     npts = sum(p.npoints for p in probs)
-    res = {"problems": len(probs), "points": npts}
-    for mode in ("host", "graph", "device"):
+    res = {"problems": len(probs), "points": npts,
+           "schedules": "list: one work-list launch per pass for all shapes; groups: one "
+                        "launch per shape group and pass on forked streams; tuned: the "
+                        "autotuner's choice per loop driver (host / graph / device entries)"}
+    runs = [("host", "tuned"), ("graph", "tuned"), ("device", "tuned"),
+            ("host", "list"), ("device", "list"), ("graph", "list"),
+            ("host", "groups"), ("device", "groups"), ("graph", "groups")]
+    for mode, sched in runs:
+        if sched != "tuned":
+            os.environ["POISSON_BATCH_SCHEDULE"] = sched
         bp = poisson.BatchPlan(specs, "fp32_refine", rtol=1e-10, max_refine=8)
+        os.environ.pop("POISSON_BATCH_SCHEDULE", None)
         bp.autotune()
-        res["schedule"] = bp.describe().strip()
+        if sched == "tuned":
+            res["schedule"] = bp.describe().strip()
         bp.set_graph(mode)
         for _ in range(warmup):
             bp.solve(rhs, outs)
@@ -124,9 +136,10 @@ def bench_batch(steps, warmup):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / steps * 1e3
         bp.close()
-        res[mode] = {"ms_per_batch": ms, "mpoints_s": npts / (ms * 1e-3) / 1e6,
-                     "max_rel_residual": max(x["rel_residual"] for x in st),
-                     "max_iterations": max(x["iterations"] for x in st)}
+        key = mode if sched == "tuned" else f"{mode}_{sched}"
+        res[key] = {"ms_per_batch": ms, "mpoints_s": npts / (ms * 1e-3) / 1e6,
+                    "max_rel_residual": max(x["rel_residual"] for x in st),
+                    "max_iterations": max(x["iterations"] for x in st)}
     return res
 
 

@@ -32,7 +32,7 @@ COMMON_FLAGS = [
     f"-I{CSRC}", f"-I{INCLUDE}",
 ]
 
-PRECISION_SOURCES = ["k_xpass.hip", "k_ypass.hip", "k_zwalls.hip", "k_zperiodic.hip"]
+PRECISION_SOURCES = ["k_xpass.hip", "k_xlist.hip", "k_ypass.hip", "k_zwalls.hip", "k_zperiodic.hip"]
 PLAIN_SOURCES = ["k_misc.hip", "api.cpp"]
 
 

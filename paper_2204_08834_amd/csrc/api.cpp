@@ -375,6 +375,21 @@ struct PassStat {
     double bytes = 0.0;
 };
 
+// One pass of one shape group, recorded instead of launched (work-list
+// schedule): the launches of every group at the same position of their
+// sequences are issued together, one work-list launch per pass kind.
+enum RecKind { RK_XF, RK_XR, RK_XI, RK_Y, RK_Z, RK_RC, RK_SUM };
+struct Rec {
+    int kind = RK_XF;
+    std::string name;
+    double bytes = 0.0;
+    XFwdArgs xf{};
+    XInvArgs xi{};
+    YArgs y{};
+    ZArgs z{};
+    SumSeg sum{};
+};
+
 }  // namespace
 
 struct poisson_plan_s {
@@ -416,6 +431,14 @@ struct poisson_plan_s {
     } proj;
     bool projecting = false;
     std::shared_ptr<DevBuf> fdiv;  // FP64 f of projections under FP32 + refinement
+    // work-list schedule of a batched plan: every pass serves all shape
+    // groups in one launch (0: one launch per group, on forked streams)
+    bool list_mode = false;
+    // the schedule of each refinement-loop driver (host loop; device-side
+    // loops), chosen by the autotuner when it runs, and whether an
+    // environment setting forces one
+    bool list_host = false, list_device = false, sched_forced = false;
+    std::vector<Rec> *rec = nullptr;  // non-null: passes are recorded here
     bool timing = false;
     std::vector<Timed> pending;
     std::vector<hipEvent_t> event_pool;
@@ -643,8 +666,14 @@ struct LSet {
 };
 
 // problems that share the plane-range choice of the residual passes: the
-// whole group in a batched launch, whichever of them a launch still serves
-int kr_group(const LSet &L) { return L.dev ? (int)L.g->members.size() : 1; }
+// whole group in a batched launch, whichever of them a launch still serves;
+// in the work-list schedule every problem of the plan (one launch serves
+// them all)
+int kr_group(const LSet &L)
+{
+    if (!L.dev) return 1;
+    return L.p->list_mode ? L.p->count : (int)L.g->members.size();
+}
 
 int pass_x_fwd(LSet &L, bool residual, bool want_partials, bool sum = true)
 {
@@ -696,12 +725,32 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials, bool sum = true)
         bytes = (double)g.N * (24.0 + sb + (pj.f_out ? 8.0 : 0.0)) * L.n;
     }
     int np = 0;
-    int rc = timed(L.p, name, bytes,
-                   [&] { return launch_x_fwd(L.prec, a, &np, L.p->ls); });
+    int rc;
+    if (L.p->rec) {
+        Rec r;
+        r.kind = residual ? RK_XR : RK_XF;
+        r.name = name;
+        r.bytes = bytes;
+        r.xf = a;
+        L.p->rec->push_back(r);
+        np = x_fwd_list_blocks(L.prec, a);
+        rc = np < 0 ? hip_fail(name, -1) : POISSON_OK;
+    } else {
+        rc = timed(L.p, name, bytes, [&] { return launch_x_fwd(L.prec, a, &np, L.p->ls); });
+    }
     if (rc || !want_partials || !sum) return rc;
     // three sums per workgroup: plain input -> (sum f, 0, 0) into scal[1..3];
     // residual -> (sum r^2, sum fbar^2, sum p) into scal[2..4]
     const int off = residual ? 2 : 1;
+    if (L.p->rec) {
+        Rec r;
+        r.kind = RK_SUM;
+        r.name = "sum_partials";
+        r.bytes = (double)np * 32.0 * L.n;
+        r.sum = SumSeg{L.dev, L.n, np, 0, off, 0, L.sum_mode};
+        L.p->rec->push_back(r);
+        return POISSON_OK;
+    }
     return timed(L.p, "sum_partials", (double)np * 32.0 * L.n, [&] {
         return launch_sum_partials(L.one.partials, np, L.one.scal ? L.one.scal + off : nullptr,
                                    L.dev, L.n, off, L.p->ls, 0, L.sum_mode, L.p->rtol,
@@ -743,9 +792,30 @@ int pass_residual_check(LSet &L, bool sum = true)
     a.kr_nb = kr_group(L);
     a.regular = regular(g.d) ? 1 : 0;
     int nc = 0;
-    int rc = timed(L.p, "residual_check_f64", (double)g.N * 16.0 * L.n,
+    int rc;
+    if (L.p->rec) {
+        Rec r;
+        r.kind = RK_RC;
+        r.name = "residual_check_f64";
+        r.bytes = (double)g.N * 16.0 * L.n;
+        r.xf = a;
+        L.p->rec->push_back(r);
+        nc = residual_check_blocks(a.nx, a.ny, a.nz, a.kr_max, a.kr_nb);
+        rc = POISSON_OK;
+    } else {
+        rc = timed(L.p, "residual_check_f64", (double)g.N * 16.0 * L.n,
                    [&] { return launch_residual_check(a, &nc, L.p->ls); });
+    }
     if (rc || !sum) return rc;
+    if (L.p->rec) {
+        Rec r;
+        r.kind = RK_SUM;
+        r.name = "sum_partials";
+        r.bytes = (double)nc * 32.0 * L.n;
+        r.sum = SumSeg{L.dev, L.n, nc, 0, 2, 0, 0};
+        L.p->rec->push_back(r);
+        return POISSON_OK;
+    }
     return timed(L.p, "sum_partials", (double)nc * 32.0 * L.n, [&] {
         return launch_sum_partials(L.one.partials, nc, L.one.scal ? L.one.scal + 2 : nullptr,
                                    L.dev, L.n, 2, L.p->ls);
@@ -755,7 +825,9 @@ int pass_residual_check(LSet &L, bool sum = true)
 int pass_y(LSet &L, bool inverse)
 {
     Group &g = *L.g;
-    if (g.d.ny == 1) return POISSON_OK;  // a length-1 transform is the identity
+    // a length-1 transform is the identity (recorded all the same, so that
+    // every group's sequence has the same passes; the list launcher skips it)
+    if (g.d.ny == 1 && !L.p->rec) return POISSON_OK;
     // the forward y pass follows the x pass, which wrote the planes in order
     const int pi = L.prec == P_F32 ? 1 : 0;
     const bool wall = g.d.bc_y != POISSON_BC_PERIODIC;
@@ -765,6 +837,15 @@ int pass_y(LSet &L, bool inverse)
     char name[40];
     snprintf(name, sizeof name, inverse ? "y_inv_%s" : "y_fwd_%s", tag(L.prec));
     const double bytes = (double)g.N * 2.0 * (L.prec == P_F32 ? 4.0 : 8.0) * L.n;
+    if (L.p->rec) {
+        Rec r;
+        r.kind = RK_Y;
+        r.name = name;
+        r.bytes = g.d.ny == 1 ? 0.0 : bytes;
+        r.y = a;
+        L.p->rec->push_back(r);
+        return POISSON_OK;
+    }
     return timed(L.p, name, bytes, [&] { return launch_y(L.prec, a, L.p->ls); });
 }
 
@@ -794,8 +875,19 @@ int pass_z(LSet &L)
     a.regular = regular(g.d) ? 1 : 0;
     a.ywall = g.d.bc_y != POISSON_BC_PERIODIC ? 1 : 0;
     a.xwall = g.d.bc_x != POISSON_BC_PERIODIC ? 1 : 0;
+    a.periodic_z = g.d.bc_z == POISSON_BC_PERIODIC ? 1 : 0;
     const double bytes = (double)g.N * 2.0 * (L.prec == P_F32 ? 4.0 : 8.0) * L.n;
     char name[40];
+    if (L.p->rec) {
+        Rec r;
+        r.kind = RK_Z;
+        snprintf(name, sizeof name, "z_%s", tag(L.prec));
+        r.name = name;
+        r.bytes = bytes;
+        r.z = a;
+        L.p->rec->push_back(r);
+        return POISSON_OK;
+    }
     if (g.d.bc_z != POISSON_BC_PERIODIC) {
         snprintf(name, sizeof name, "z_walls_%s", tag(L.prec));
         return timed(L.p, name, bytes, [&] { return launch_z_walls(L.prec, a, L.p->ls); });
@@ -825,7 +917,17 @@ int pass_x_inv(LSet &L, bool accumulate)
     const double sb = L.prec == P_F32 ? 4.0 : 8.0;
     const double pin = in32 ? 4.0 : 8.0;  // bytes of the iterate read or written in FP32 / FP64
     const double bytes = (double)g.N * (sb + (accumulate ? pin + 8.0 : pin)) * L.n;
-    const int rc = timed(L.p, name, bytes, [&] { return launch_x_inv(L.prec, a, L.p->ls); });
+    int rc = POISSON_OK;
+    if (L.p->rec) {
+        Rec r;
+        r.kind = RK_XI;
+        r.name = name;
+        r.bytes = bytes;
+        r.xi = a;
+        L.p->rec->push_back(r);
+    } else {
+        rc = timed(L.p, name, bytes, [&] { return launch_x_inv(L.prec, a, L.p->ls); });
+    }
     if (!rc) L.cur32 = accumulate ? false : in32;
     return rc;
 }
@@ -848,6 +950,103 @@ int correction_passes(LSet &L)
     if ((rc = pass_z(L))) return rc;
     if ((rc = pass_y(L, true))) return rc;
     return pass_x_inv(L, true);
+}
+
+// Issue the recorded passes of several groups: position by position (every
+// group records the same sequence of pass kinds, or at one position one of
+// two kinds), one work-list launch per pass kind present at a position.
+int issue_recs(poisson_plan p, std::vector<std::vector<Rec>> &per)
+{
+    size_t len = 0;
+    for (auto &v : per) len = std::max(len, v.size());
+    const int prec = internal_prec(p->precision);
+    for (size_t i = 0; i < len; ++i) {
+        for (int kind = RK_XF; kind <= RK_SUM; ++kind) {
+            std::vector<const Rec *> rs;
+            for (auto &v : per)
+                if (i < v.size() && v[i].kind == kind) rs.push_back(&v[i]);
+            if (rs.empty()) continue;
+            double bytes = 0.0;
+            for (auto *r : rs) bytes += r->bytes;
+            const int n = (int)rs.size();
+            const char *name = rs[0]->name.c_str();
+            int rc = POISSON_OK;
+            switch (kind) {
+            case RK_XF:
+            case RK_XR: {
+                std::vector<XFwdArgs> a(n);
+                for (int k = 0; k < n; ++k) a[k] = rs[k]->xf;
+                rc = timed(p, name, bytes,
+                           [&] { return launch_x_fwd_list(prec, a.data(), n, p->ls); });
+                break;
+            }
+            case RK_XI: {
+                std::vector<XInvArgs> a(n);
+                for (int k = 0; k < n; ++k) a[k] = rs[k]->xi;
+                rc = timed(p, name, bytes,
+                           [&] { return launch_x_inv_list(prec, a.data(), n, p->ls); });
+                break;
+            }
+            case RK_Y: {
+                std::vector<YArgs> a(n);
+                for (int k = 0; k < n; ++k) a[k] = rs[k]->y;
+                rc = timed(p, name, bytes, [&] { return launch_y_list(prec, a.data(), n, p->ls); });
+                break;
+            }
+            case RK_Z: {
+                std::vector<ZArgs> a(n);
+                for (int k = 0; k < n; ++k) a[k] = rs[k]->z;
+                rc = timed(p, name, bytes, [&] { return launch_z_list(prec, a.data(), n, p->ls); });
+                break;
+            }
+            case RK_RC: {
+                std::vector<XFwdArgs> a(n);
+                for (int k = 0; k < n; ++k) a[k] = rs[k]->xf;
+                rc = timed(p, name, bytes,
+                           [&] { return launch_residual_check_list(a.data(), n, p->ls); });
+                break;
+            }
+            default: {
+                std::vector<SumSeg> a(n);
+                for (int k = 0; k < n; ++k) a[k] = rs[k]->sum;
+                rc = timed(p, name, bytes, [&] {
+                    return launch_sum_partials_list(a.data(), n, p->rtol, p->max_refine, p->ls);
+                });
+                break;
+            }
+            }
+            if (rc) return rc;
+        }
+    }
+    return POISSON_OK;
+}
+
+// Run f (the passes of one group) for the listed groups: launched group by
+// group, or, in the work-list schedule, recorded for every group and then
+// issued together.
+template <class F>
+int over_groups(poisson_plan p, std::vector<LSet> &sets, const std::vector<size_t> &which, F &&f)
+{
+    if (!p->list_mode) {
+        for (size_t gi : which) {
+            const int rc = f(sets[gi]);
+            if (rc) return rc;
+        }
+        return POISSON_OK;
+    }
+    // the groups of the largest problems first: their blocks are dispatched
+    // first and the small problems' blocks fill the end of each launch
+    std::vector<size_t> order(which);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return sets[a].g->N > sets[b].g->N; });
+    std::vector<std::vector<Rec>> per(order.size());
+    int rc = POISSON_OK;
+    for (size_t k = 0; k < order.size() && !rc; ++k) {
+        p->rec = &per[k];
+        rc = f(sets[order[k]]);
+    }
+    p->rec = nullptr;
+    return rc ? rc : issue_recs(p, per);
 }
 
 int read_scalars(poisson_plan p, int count)
@@ -892,6 +1091,7 @@ enum { RUNNING = 1, DONE = 0 };
 // iteration for the whole plan.
 int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, poisson_stats_t *st)
 {
+    p->list_mode = p->list_host;
     const int prec = internal_prec(p->precision);
     const int count = p->count;
     std::vector<LSet> sets(p->groups.size());
@@ -940,8 +1140,11 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
     std::vector<poisson_stats_t> out(count, poisson_stats_t{0, -1.0, 0.0, POISSON_OK});
     const bool refine = p->precision == POISSON_FP32_REFINE;
     const bool want_partials = prec == P_F32;  // FP64 mean comes from the z pass
-    for (size_t gi = 0; gi < p->groups.size() && !rc; ++gi)
-        rc = solve_passes(sets[gi], false, want_partials);
+    std::vector<size_t> all(p->groups.size());
+    for (size_t gi = 0; gi < all.size(); ++gi) all[gi] = gi;
+    if (!rc)
+        rc = over_groups(p, sets, all,
+                         [&](LSet &L) { return solve_passes(L, false, want_partials); });
 
     if (!rc && refine) {
         std::vector<double> rho_prev(count, -1.0), rho_first(count, -1.0);
@@ -955,7 +1158,8 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
             // is two decades below rtol for every running problem of a group,
             // its residual is only checked (no transform, no spectrum write).
             // If the check fails, the full residual pass follows.
-            for (size_t gi = 0; gi < p->groups.size() && !rc; ++gi) {
+            std::vector<size_t> running;
+            for (size_t gi = 0; gi < p->groups.size(); ++gi) {
                 checked[gi] = 0;
                 if (!sets[gi].n) continue;
                 bool predict = true;
@@ -965,9 +1169,14 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
                               rho_prev[i] * rho_first[i] * 100.0 <= p->rtol;
                 }
                 checked[gi] = predict;
-                rc = predict ? pass_residual_check(sets[gi]) : pass_x_fwd(sets[gi], true, true);
+                running.push_back(gi);
             }
+            rc = over_groups(p, sets, running, [&](LSet &L) {
+                const size_t gi = (size_t)(L.g - p->groups.data());
+                return checked[gi] ? pass_residual_check(L) : pass_x_fwd(L, true, true);
+            });
             if (rc || (rc = read_scalars(p, count))) break;
+            std::vector<size_t> fix;
             bool any = false;
             for (size_t gi = 0; gi < p->groups.size(); ++gi) {
                 std::vector<int> next;
@@ -1012,13 +1221,16 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
                 }
                 // a check-only pass wrote no spectrum: transform the residual
                 // of the problems that go on
-                if (checked[gi] && !next.empty() && (rc = pass_x_fwd(sets[gi], true, true)))
-                    break;
+                if (checked[gi] && !next.empty()) fix.push_back(gi);
                 any = any || !next.empty();
             }
+            if (!rc && !fix.empty())
+                rc = over_groups(p, sets, fix, [&](LSet &L) { return pass_x_fwd(L, true, true); });
             if (rc || !any) break;
-            for (size_t gi = 0; gi < p->groups.size() && !rc; ++gi)
-                if (sets[gi].n) rc = correction_passes(sets[gi]);
+            std::vector<size_t> go;
+            for (size_t gi = 0; gi < p->groups.size(); ++gi)
+                if (sets[gi].n) go.push_back(gi);
+            rc = over_groups(p, sets, go, [&](LSet &L) { return correction_passes(L); });
         }
     } else if (!rc && st) {
         rc = read_scalars(p, count);
@@ -1068,6 +1280,16 @@ int enqueue_residual_decision(poisson_plan p, LSet &L, bool with_check)
     // partial records of whichever residual pass ran for each problem
     const int nr = x_fwd_blocks(P_F32, g.d.nx, g.d.ny, g.d.nz, 1, g.tune.kr, kr_group(L));
     const int nc = residual_check_blocks(g.d.nx, g.d.ny, g.d.nz, g.tune.kr, kr_group(L));
+    if (p->rec) {
+        Rec r;
+        r.kind = RK_SUM;
+        r.name = "sum_partials";
+        r.bytes = (double)(nr > nc ? nr : nc) * 32.0 * L.n;
+        r.sum = SumSeg{L.dev, L.n, nr, nc, 2, C_EVAL, 2};
+        p->rec->push_back(r);
+        L.gate = 0;
+        return POISSON_OK;
+    }
     rc = timed(p, "sum_partials", (double)(nr > nc ? nr : nc) * 32.0 * L.n, [&] {
         return launch_sum_partials(nullptr, nr, nullptr, L.dev, L.n, 2, p->ls, C_EVAL, 2,
                                    p->rtol, p->max_refine, nc);
@@ -1124,6 +1346,15 @@ int enqueue_device_sequence(poisson_plan p, std::vector<LSet> &sets, bool head,
 {
     const size_t ng = sets.size();
     int rc = POISSON_OK;
+    if (p->list_mode) {
+        // work-list schedule: every group's sequence recorded, then issued
+        // on the loop stream, one launch per pass for all groups
+        p->ls = p->gstream;
+        std::vector<size_t> all(ng);
+        for (size_t gi = 0; gi < ng; ++gi) all[gi] = gi;
+        return over_groups(p, sets, all,
+                           [&](LSet &L) { return enqueue_group_sequence(p, L, head, segs); });
+    }
     std::vector<size_t> order(ng);
     for (size_t gi = 0; gi < ng; ++gi) order[gi] = gi;
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
@@ -1205,6 +1436,8 @@ int build_graph(poisson_plan p, std::vector<LSet> &sets, int k)
 int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
                  poisson_stats_t *st)
 {
+    if (p->list_mode != p->list_device) p->drop_graphs();  // captured with the other schedule
+    p->list_mode = p->list_device;
     int rc = ensure_device_loop_objects(p);
     if (rc) return rc;
     const int prec = internal_prec(p->precision);
@@ -1388,6 +1621,69 @@ int autotune_group(poisson_plan p, Group &g)
     return POISSON_OK;
 }
 
+// Schedule of a batch of several shapes (work list or per-group launches),
+// per loop driver: each candidate times the whole batched solve on zero
+// scratch fields (first solve, residual and the control decision), one
+// warm-up and then the mean of three.
+int autotune_schedule(poisson_plan p)
+{
+    if (!p->batched || p->groups.size() < 2 || p->sched_forced) return POISSON_OK;
+    size_t total = 0;
+    for (auto &g : p->groups) total += (size_t)g.N * g.members.size();
+    std::shared_ptr<DevBuf> fbuf, sbuf;
+    int rc;
+    if ((rc = dev_alloc(fbuf, total * 8)) || (rc = dev_alloc(sbuf, total * 8))) return rc;
+    if ((rc = launch_zero(fbuf->p, total * 8, p->stream)))
+        return hip_fail("autotune scratch", rc);
+    std::vector<const double *> rhs(p->count);
+    std::vector<double *> sol(p->count);
+    size_t off = 0;
+    for (auto &g : p->groups)
+        for (int i : g.members) {
+            rhs[i] = (const double *)fbuf->p + off;
+            sol[i] = (double *)sbuf->p + off;
+            off += (size_t)g.N;
+        }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return POISSON_ERR_HIP;
+    const int mode0 = p->graph_mode;
+    const bool timing = p->timing;
+    p->timing = false;
+    auto run = [&](int mode) {
+        p->graph_mode = mode;
+        return mode ? solve_device(p, rhs.data(), sol.data(), nullptr)
+                    : solve_all(p, rhs.data(), sol.data(), nullptr);
+    };
+    auto measure = [&](int mode) -> double {
+        if (run(mode) < 0) return -1.0;
+        (void)hipStreamSynchronize(p->stream);
+        (void)hipEventRecord(e0, p->stream);
+        for (int i = 0; i < 3; ++i)
+            if (run(mode) < 0) return -1.0;
+        (void)hipEventRecord(e1, p->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) return -1.0;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return ms / 3.0;
+    };
+    for (int mode : {0, 2}) {
+        bool &knob = mode ? p->list_device : p->list_host;
+        knob = false;
+        const double tg = measure(mode);
+        knob = true;
+        const double tl = measure(mode);
+        knob = !(tg >= 0.0 && (tl < 0.0 || tg < tl));
+    }
+    p->graph_mode = mode0;
+    p->timing = timing;
+    p->drop_graphs();
+    (void)hipStreamSynchronize(p->stream);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return POISSON_OK;
+}
+
 int autotune_plan(poisson_plan p, int flags)
 {
     int rc = POISSON_OK;
@@ -1412,7 +1708,7 @@ int autotune_plan(poisson_plan p, int flags)
         apply_env_overrides(g.tune);
     }
     p->drop_graphs();  // launch shapes may have changed
-    return rc;
+    return autotune_schedule(p);
 }
 
 int create_plan(const poisson_desc_t *descs, int count, void *stream, bool batched,
@@ -1470,6 +1766,13 @@ int create_plan(const poisson_desc_t *descs, int count, void *stream, bool batch
     if ((rc = pinned_alloc(p->host_ptrs, sizeof(ProbPtrs) * count))) return rc;
     if (hipEventCreateWithFlags(&p->ptrs_done, hipEventDisableTiming) != hipSuccess)
         return POISSON_ERR_HIP;
+    // batches of several shapes: one work-list launch per pass serves them
+    // all, unless POISSON_BATCH_SCHEDULE=groups asks for one launch per
+    // shape group on forked streams
+    const char *sched = getenv("POISSON_BATCH_SCHEDULE");
+    p->list_mode = batched && p->groups.size() > 1 && !(sched && strcmp(sched, "groups") == 0);
+    p->list_host = p->list_device = p->list_mode;
+    p->sched_forced = sched && *sched;
     if (const char *e = getenv("POISSON_AUTOTUNE")) {
         if (*e && strcmp(e, "0") != 0 && (rc = autotune_plan(p.get(), 0))) return rc;
     }
@@ -1755,6 +2058,14 @@ int poisson_plan_describe(poisson_plan plan, char *buf, int len)
     if (!plan || !buf || len < 1) return POISSON_ERR_INVALID_ARG;
     std::string out;
     char line[256];
+    if (plan->batched) {
+        snprintf(line, sizeof line,
+                 "schedule=%s (host loop: %s, device loops: %s; list = one work-list launch "
+                 "per pass for all shapes, groups = one launch per shape group and pass)\n",
+                 plan->list_host ? "list" : "groups", plan->list_host ? "list" : "groups",
+                 plan->list_device ? "list" : "groups");
+        out += line;
+    }
     for (size_t gi = 0; gi < plan->groups.size(); ++gi) {
         const Group &g = plan->groups[gi];
         snprintf(line, sizeof line,

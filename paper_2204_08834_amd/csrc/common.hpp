@@ -241,7 +241,69 @@ struct ZArgs {
     int regular;            // no null space (a Dirichlet wall on some axis): no zero mode
     int ywall;              // walls along y: the m = 0 column holds A + iB with real y-modes
     int xwall;              // walls along x: every column m holds the real x-modes 2m, 2m+1
+    int periodic_z;         // 1: periodic z (transform), 0: walls (tridiagonal solve)
 };
+
+// ---------------------------------------------------------------------------
+// Work lists: one launch serving problems of different shapes.  The blocks of
+// a list launch are dealt out to segments, one per shape group; segment g
+// covers blocks [start[g], start[g+1]) and serves nbatch problems of one
+// shape with gx blocks each: its relative block b is block (b % gx, b / gx)
+// of that group's own launch.  The body that runs is picked by the segment's
+// class (a transform length and its compile-time variant); it uses the first
+// nt threads of the workgroup (the others leave at once) and carves its LDS
+// from the launch's dynamic LDS.
+// ---------------------------------------------------------------------------
+struct VBlock {
+    int x, y, gx;  // block within the group's launch, problem, blocks per problem
+};
+
+constexpr int LIST_MAX_SEG = 8;
+
+template <class A>
+struct ListArgs {
+    int nseg;
+    int start[LIST_MAX_SEG + 1];
+    int gx[LIST_MAX_SEG];
+    int cls[LIST_MAX_SEG];   // class of the segment's body
+    int nt[LIST_MAX_SEG];    // threads its body uses
+    int aux[LIST_MAX_SEG];   // per-class launch parameters (chunks, special blocks)
+    int aux2[LIST_MAX_SEG];
+    A a[LIST_MAX_SEG];
+};
+
+// The list kernels take one argument, the ListArgs, and read it through the
+// kernel argument segment's address (constant address space: scalar loads
+// at any segment index; an indexed copy of the by-value argument would be
+// placed in scratch memory).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define PK_KARG __attribute__((address_space(4)))
+#else
+#define PK_KARG
+#endif
+template <class A>
+__device__ __forceinline__ const PK_KARG ListArgs<A> *list_args()
+{
+    return (const PK_KARG ListArgs<A> *)__builtin_amdgcn_kernarg_segment_ptr();
+}
+
+// Segment and virtual block of this workgroup; false when the thread is
+// beyond the body's threads (it has nothing to do).  The bodies check their
+// problem's gate themselves.
+template <class A>
+__device__ __forceinline__ bool list_find(const PK_KARG ListArgs<A> *L, int &g, VBlock &vb)
+{
+    const int b = (int)blockIdx.x;
+    int i = 0;
+    while (i + 1 < L->nseg && b >= L->start[i + 1]) ++i;
+    g = i;
+    const int local = b - L->start[i];
+    const int gx = L->gx[i];
+    vb.y = local / gx;
+    vb.x = local - vb.y * gx;
+    vb.gx = gx;
+    return (int)threadIdx.x < L->nt[i];
+}
 
 // Launchers (return 0 on success, a hipError_t value otherwise).  The forward
 // x pass reports the workgroups it launched (the partial sums it wrote).
@@ -273,6 +335,32 @@ int residual_check_blocks(int nx, int ny, int nz, int kr_max, int kr_nb = 1);
 int launch_widen(const float *src, double *dst, size_t n, hipStream_t s);
 // clear `bytes` (a multiple of 4) at dst with a kernel
 int launch_zero(void *dst, size_t bytes, hipStream_t s);
+
+// Work-list launchers: n argument records of one pass kind, one per shape
+// group (batched records), served by as few launches as possible (one per
+// LIST_MAX_SEG groups); a group outside the list kernels' classes gets its
+// own launch of the per-group launcher.  x passes: all records plain
+// (residual = 0, periodic x) or all residual; y: all forward or all inverse;
+// z: walls and periodic records mixed.
+int launch_y_list(int prec, const YArgs *a, int n, hipStream_t s);
+int launch_z_list(int prec, const ZArgs *a, int n, hipStream_t s);
+int launch_x_fwd_list(int prec, const XFwdArgs *a, int n, hipStream_t s);
+int launch_x_inv_list(int prec, const XInvArgs *a, int n, hipStream_t s);
+int launch_residual_check_list(const XFwdArgs *a, int n, hipStream_t s);
+// workgroups of a group's forward x pass in a list launch (its partial
+// records): plain passes take one tile of rows per workgroup
+int x_fwd_list_blocks(int prec, const XFwdArgs &a);
+// sum of the partial records of several groups (batched records), one
+// workgroup per problem: n records per problem of group i, or n_check when
+// the problem's control record says a residual check ran (mode 2)
+struct SumSeg {
+    const ProbPtrs *batch;
+    int nbatch;
+    int n, n_check;
+    int out_off, gate, mode;
+};
+int launch_sum_partials_list(const SumSeg *segs, int nseg, double rtol, int max_refine,
+                             hipStream_t s);
 
 // Velocity correction and pressure update of the projection step:
 // u -= bx Dx+ psi, v -= by Dy+ psi, w -= bz Dz+ psi (not on a top wall),

@@ -343,11 +343,14 @@ __device__ __forceinline__ void fft_tile(const Cx<R> *__restrict__ tw, int tws, 
     }
 }
 
-// copy a global twiddle table (n entries) into LDS; caller syncs
+// copy a global twiddle table (n entries) into LDS with the first nt threads
+// (all of the workgroup by default); caller syncs
 template <typename R>
-__device__ __forceinline__ void load_table(Cx<R> *dst, const Cx<R> *__restrict__ src, int n)
+__device__ __forceinline__ void load_table(Cx<R> *dst, const Cx<R> *__restrict__ src, int n,
+                                           int nt = 0)
 {
-    for (int t = threadIdx.x; t < n; t += blockDim.x) dst[t] = src[t];
+    const int step = nt > 0 ? nt : (int)blockDim.x;
+    for (int t = threadIdx.x; t < n; t += step) dst[t] = src[t];
 }
 
 }  // namespace pk

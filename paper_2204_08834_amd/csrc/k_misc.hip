@@ -20,6 +20,37 @@ int launch_z_periodic_f32(const ZArgs &, hipStream_t);
 int launch_z_periodic_f64(const ZArgs &, hipStream_t);
 int x_fwd_blocks_f32(int, int, int, int, int, int);
 int x_fwd_blocks_f64(int, int, int, int, int, int);
+int launch_y_list_f32(const YArgs *, int, hipStream_t);
+int launch_y_list_f64(const YArgs *, int, hipStream_t);
+int launch_z_list_f32(const ZArgs *, int, hipStream_t);
+int launch_z_list_f64(const ZArgs *, int, hipStream_t);
+int launch_x_fwd_list_f32(const XFwdArgs *, int, hipStream_t);
+int launch_x_fwd_list_f64(const XFwdArgs *, int, hipStream_t);
+int launch_x_inv_list_f32(const XInvArgs *, int, hipStream_t);
+int launch_x_inv_list_f64(const XInvArgs *, int, hipStream_t);
+int x_fwd_list_blocks_f32(const XFwdArgs &);
+int x_fwd_list_blocks_f64(const XFwdArgs &);
+
+int launch_y_list(int prec, const YArgs *a, int n, hipStream_t s)
+{
+    return prec == P_F32 ? launch_y_list_f32(a, n, s) : launch_y_list_f64(a, n, s);
+}
+int launch_z_list(int prec, const ZArgs *a, int n, hipStream_t s)
+{
+    return prec == P_F32 ? launch_z_list_f32(a, n, s) : launch_z_list_f64(a, n, s);
+}
+int launch_x_fwd_list(int prec, const XFwdArgs *a, int n, hipStream_t s)
+{
+    return prec == P_F32 ? launch_x_fwd_list_f32(a, n, s) : launch_x_fwd_list_f64(a, n, s);
+}
+int launch_x_inv_list(int prec, const XInvArgs *a, int n, hipStream_t s)
+{
+    return prec == P_F32 ? launch_x_inv_list_f32(a, n, s) : launch_x_inv_list_f64(a, n, s);
+}
+int x_fwd_list_blocks(int prec, const XFwdArgs &a)
+{
+    return prec == P_F32 ? x_fwd_list_blocks_f32(a) : x_fwd_list_blocks_f64(a);
+}
 
 int launch_x_fwd(int prec, const XFwdArgs &a, int *nblocks_out, hipStream_t s)
 {
@@ -184,55 +215,70 @@ int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *ba
 // 512x512x256).
 constexpr int RC_NT = 512;
 
+// One workgroup's work (plane range and row block vb.x of problem vb.y);
+// LDS carved from `lds` (LDS_BYTES).
+template <int M> struct RCBody {
+    static constexpr int TJ = march_rows(M);
+    using Mar = PlaneMarch<M, TJ, RC_NT>;
+    static constexpr size_t TILE_B = sizeof(double2) * (TJ + 2) * M;
+    static constexpr size_t LDS_BYTES = TILE_B + sizeof(double) * 3 * (RC_NT / 64);
+
+    static __device__ __forceinline__ void run(const XFwdArgs &a0, VBlock vb, char *lds)
+    {
+
+        if (gated_off(a0.batch, a0.gate, vb.y)) return;
+        double2(*s_tile)[M] = (double2(*)[M])lds;
+        double *s_red = (double *)(lds + TILE_B);
+        XFwdArgs a = a0;
+        if (a.batch) {
+            const ProbPtrs &q = a.batch[vb.y];
+            a.f = q.f;
+            a.p = q.p;
+            a.partials = q.partials;
+            a.sum_f = q.scal + 1;
+        }
+        const int njb = march_jblocks(a.ny, TJ);
+        const int bid = block_order(xcd_order(vb.x, vb.gx), vb.gx, a.reverse);
+        const int jb = bid % njb, kb = bid / njb;
+        const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max, a.kr_nb);
+        const int k0 = kb * kr;
+        const int k1 = k0 + kr < a.nz ? k0 + kr : a.nz;
+        Mar m;
+        m.f = gbl(a.f);
+        m.p = gbl(a.p);
+        m.ax = a.ax;
+        m.ay = a.ay;
+        m.az = a.az;
+        m.mu = (a.sum_f && !a.regular) ? (*a.sum_f) * a.inv_n : 0.0;
+        m.tile = s_tile;
+        m.setup(jb, a.ny, a.nz, a.bc_z, a.bc_y);
+        m.bc_x = a.bc_x;
+        m.start(k0);
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+        auto sink = [&](int, int, int, double r0, double r1, double f0, double f1, double2 c) {
+            acc0 += r0 * r0 + r1 * r1;
+            acc1 += f0 * f0 + f1 * f1;
+            acc2 += c.x + c.y;
+        };
+        for (int k = k0; k < k1; ++k) {
+            if (k > k0) __syncthreads();
+            m.step(k, sink);
+        }
+        block_sum3(acc0, acc1, acc2, s_red, RC_NT);
+        if (threadIdx.x == 0) {
+            a.partials[4 * vb.x] = acc0;
+            a.partials[4 * vb.x + 1] = acc1;
+            a.partials[4 * vb.x + 2] = acc2;
+        }
+    }
+};
+
 template <int M>
 __global__ __launch_bounds__(RC_NT) void k_residual_check(XFwdArgs a0)
 {
-    if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
-    constexpr int TJ = march_rows(M);
-    using Mar = PlaneMarch<M, TJ, RC_NT>;
-    __shared__ double2 s_tile[TJ + 2][M];
-    __shared__ double s_red[3 * (RC_NT / 64)];
-    XFwdArgs a = a0;
-    if (a.batch) {
-        const ProbPtrs &q = a.batch[blockIdx.y];
-        a.f = q.f;
-        a.p = q.p;
-        a.partials = q.partials;
-        a.sum_f = q.scal + 1;
-    }
-    const int njb = march_jblocks(a.ny, TJ);
-    const int bid = block_order(xcd_order(blockIdx.x, gridDim.x), gridDim.x, a.reverse);
-    const int jb = bid % njb, kb = bid / njb;
-    const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max, a.kr_nb);
-    const int k0 = kb * kr;
-    const int k1 = k0 + kr < a.nz ? k0 + kr : a.nz;
-    Mar m;
-    m.f = gbl(a.f);
-    m.p = gbl(a.p);
-    m.ax = a.ax;
-    m.ay = a.ay;
-    m.az = a.az;
-    m.mu = (a.sum_f && !a.regular) ? (*a.sum_f) * a.inv_n : 0.0;
-    m.tile = s_tile;
-    m.setup(jb, a.ny, a.nz, a.bc_z, a.bc_y);
-    m.bc_x = a.bc_x;
-    m.start(k0);
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-    auto sink = [&](int, int, int, double r0, double r1, double f0, double f1, double2 c) {
-        acc0 += r0 * r0 + r1 * r1;
-        acc1 += f0 * f0 + f1 * f1;
-        acc2 += c.x + c.y;
-    };
-    for (int k = k0; k < k1; ++k) {
-        if (k > k0) __syncthreads();
-        m.step(k, sink);
-    }
-    block_sum3(acc0, acc1, acc2, s_red);
-    if (threadIdx.x == 0) {
-        a.partials[4 * blockIdx.x] = acc0;
-        a.partials[4 * blockIdx.x + 1] = acc1;
-        a.partials[4 * blockIdx.x + 2] = acc2;
-    }
+    using B = RCBody<M>;
+    __shared__ __align__(16) char s_lds[B::LDS_BYTES];
+    B::run(a0, VBlock{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x}, s_lds);
 }
 
 template <int M> static int rc_blocks(int ny, int nz, int kr_max, int kr_nb)
@@ -261,6 +307,128 @@ int launch_residual_check(const XFwdArgs &a, int *nblocks_out, hipStream_t s)
 {
     if (nblocks_out) *nblocks_out = residual_check_blocks(a.nx, a.ny, a.nz, a.kr_max, a.kr_nb);
     switch (a.nx / 2) { PK_X_LENGTHS(PK_CASE_RC) default: return -1; }
+}
+
+// Work list of residual checks of problems of different shapes (class: the
+// half row length M; periodic and wall boxes alike)
+#define PK_RL_LENGTHS(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128)
+
+__global__ __launch_bounds__(RC_NT) void k_rc_list(ListArgs<XFwdArgs>)
+{
+    extern __shared__ __align__(16) char s_dyn[];
+    const PK_KARG ListArgs<XFwdArgs> *L = list_args<XFwdArgs>();
+    int g;
+    VBlock vb;
+    if (!list_find(L, g, vb)) return;
+    const XFwdArgs arg = L->a[g];
+    switch (L->cls[g]) {
+#define PK_RL_CASE(N) case N: RCBody<N>::run(arg, vb, s_dyn); break;
+        PK_RL_LENGTHS(PK_RL_CASE)
+#undef PK_RL_CASE
+    default: break;
+    }
+}
+
+int launch_residual_check_list(const XFwdArgs *a, int n, hipStream_t s)
+{
+    ListArgs<XFwdArgs> L{};
+    size_t lds = 0;
+    int total = 0;
+    auto flush = [&]() -> int {
+        if (L.nseg == 0) return 0;
+        L.start[L.nseg] = total;
+        hipLaunchKernelGGL(k_rc_list, dim3(total), dim3(RC_NT), lds, s, L);
+        L.nseg = 0;
+        total = 0;
+        lds = 0;
+        return (int)hipGetLastError();
+    };
+    for (int i = 0; i < n; ++i) {
+        size_t b = 0;
+        switch (a[i].nx / 2) {
+#define PK_RL_INFO(N) case N: b = RCBody<N>::LDS_BYTES; break;
+            PK_RL_LENGTHS(PK_RL_INFO)
+#undef PK_RL_INFO
+        default: break;
+        }
+        if (b == 0) {
+            const int e = launch_residual_check(a[i], nullptr, s);
+            if (e) return e;
+            continue;
+        }
+        const int gx = residual_check_blocks(a[i].nx, a[i].ny, a[i].nz, a[i].kr_max, a[i].kr_nb);
+        const int g = L.nseg++;
+        L.start[g] = total;
+        L.gx[g] = gx;
+        L.cls[g] = a[i].nx / 2;
+        L.nt[g] = RC_NT;
+        L.a[g] = a[i];
+        total += gx * (a[i].batch ? a[i].nbatch : 1);
+        lds = lds > b ? lds : b;
+        if (L.nseg == LIST_MAX_SEG) {
+            const int e = flush();
+            if (e) return e;
+        }
+    }
+    return flush();
+}
+
+// Sums of the partial records of several groups: one workgroup per problem
+// of every segment (the problem's records, its scalars and control record
+// from its ProbPtrs entry)
+__global__ __launch_bounds__(1024) void k_sum_list(ListArgs<SumSeg>, double rtol, int max_refine)
+{
+    __shared__ double sh[3][1024];
+    const PK_KARG ListArgs<SumSeg> *L = list_args<SumSeg>();
+    int g;
+    VBlock vb;
+    if (!list_find(L, g, vb)) return;
+    const SumSeg sg = L->a[g];
+    const ProbPtrs *batch = sg.batch;
+    const int i = vb.y;
+    if (gated_off(batch, sg.gate, i)) return;
+    const double *in = batch[i].partials;
+    double *out = batch[i].scal + sg.out_off;
+    int n = sg.n;
+    if (sg.mode == 2 && batch[i].ctrl[C_CHECK]) n = sg.n_check;
+    double s0, s1, s2;
+    sum_records(in, n, sh, s0, s1, s2);
+    if (threadIdx.x == 0) {
+        out[0] = s0;
+        out[1] = s1;
+        out[2] = s2;
+        if (sg.mode == 1) ctrl_open(batch[i].ctrl, batch[i].scal);
+        if (sg.mode == 2) ctrl_decide(batch[i].ctrl, batch[i].scal, rtol, max_refine);
+    }
+}
+
+int launch_sum_partials_list(const SumSeg *segs, int nseg, double rtol, int max_refine,
+                             hipStream_t s)
+{
+    ListArgs<SumSeg> L{};
+    int total = 0;
+    for (int i = 0; i < nseg; ++i) {
+        if (!segs[i].batch || segs[i].nbatch < 1) continue;
+        if (L.nseg == LIST_MAX_SEG) {
+            L.start[L.nseg] = total;
+            hipLaunchKernelGGL(k_sum_list, dim3(total), dim3(1024), 0, s, L, rtol, max_refine);
+            const int e = (int)hipGetLastError();
+            if (e) return e;
+            L.nseg = 0;
+            total = 0;
+        }
+        const int g = L.nseg++;
+        L.start[g] = total;
+        L.gx[g] = 1;
+        L.cls[g] = 0;
+        L.nt[g] = 1024;
+        L.a[g] = segs[i];
+        total += segs[i].nbatch;
+    }
+    if (L.nseg == 0) return 0;
+    L.start[L.nseg] = total;
+    hipLaunchKernelGGL(k_sum_list, dim3(total), dim3(1024), 0, s, L, rtol, max_refine);
+    return (int)hipGetLastError();
 }
 
 // Velocity correction and pressure update of the projection step

@@ -403,97 +403,115 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
 // instead of three.
 constexpr int XR_NT = 256;
 
-template <int M, bool XW, bool P32>
-__global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
-{
-    if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
-    XFwdArgs a = a0;
-    if (a.batch) {
-        const ProbPtrs &q = a.batch[blockIdx.y];
-        a.f = q.f;
-        a.p = q.p;
-        a.p32 = q.p32;
-        a.S = q.S;
-        a.partials = q.partials;
-        a.sum_f = q.scal + 1;
-    }
-    constexpr int TJ = march_rows_res(M), NT = XR_NT, NX = 2 * M;
+// One workgroup's work (plane range and row block vb.x of problem vb.y) of
+// the residual pass; LDS carved from `lds` (LDS_BYTES).
+template <int M, bool XW, bool P32> struct XRBody {
+    static constexpr int TJ = march_rows_res(M), NT = XR_NT;
     using PT = typename std::conditional<P32, float, double>::type;
     using Mar = PlaneMarch<M, TJ, NT, PT>;
     using Tile = LdsTile<R, M, TJ, false, 0>;
-    constexpr size_t PLANE_B = sizeof(double2) * (TJ + 2) * M;
-    constexpr size_t FFT_B = sizeof(Cx<R>) * Tile::elems;
-    __shared__ __align__(16) char s_buf[PLANE_B > FFT_B ? PLANE_B : FFT_B];
-    __shared__ Cx<R> s_tw[NX];
-    __shared__ double s_red[3 * (NT / 64)];
+    static constexpr size_t PLANE_B = sizeof(double2) * (TJ + 2) * M;
+    static constexpr size_t FFT_B = sizeof(Cx<R>) * Tile::elems;
+    static constexpr size_t BUF_B = ((PLANE_B > FFT_B ? PLANE_B : FFT_B) + 15) / 16 * 16;
+    static constexpr size_t TW_B = sizeof(Cx<R>) * 2 * M;
+    static constexpr size_t RED_B = (sizeof(double) * 3 * (NT / 64) + 15) / 16 * 16;
+    static constexpr size_t LDS_BYTES = BUF_B + TW_B + RED_B + (XW ? TW_B : 0);
 
-    const int njb = march_jblocks(a.ny, TJ);
-    const int bid = block_order(xcd_order(blockIdx.x, gridDim.x), gridDim.x, a.reverse);
-    const int jb = bid % njb, kb = bid / njb;
-    const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max, a.kr_nb);
-    const int k0 = kb * kr;
-    const int k1 = k0 + kr < a.nz ? k0 + kr : a.nz;
+    static __device__ __forceinline__ void run(const XFwdArgs &a0, VBlock vb, char *lds)
+    {
 
-    Mar m;
-    m.f = gbl(a.f);
-    if constexpr (P32)
-        m.p = gbl(a.p32);
-    else
-        m.p = gbl(a.p);
-    m.ax = a.ax;
-    m.ay = a.ay;
-    m.az = a.az;
-    m.mu = (a.sum_f && !a.regular) ? (*a.sum_f) * a.inv_n : 0.0;
-    m.tile = (double2(*)[M])s_buf;
-    m.setup(jb, a.ny, a.nz, a.bc_z, a.bc_y);
-    m.bc_x = XW ? a.bc_x : 0;
-    const bool sine = a.bc_x == 2;
-    __shared__ Cx<R> s_w4[XW ? NX : 1];
-    const Cx<R> *w4 = s_w4;
-    if constexpr (XW) load_table(s_w4, (const Cx<R> *)a.tw4x, NX);
-    load_table(s_tw, (const Cx<R> *)a.tw, NX);
-    m.start(k0);
-
-    Tile tile{(Cx<R> *)s_buf};
-    PK_GLOBAL Cx<R> *S = gbl((Cx<R> *)a.S);
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-    for (int k = k0; k < k1; ++k) {
-        __syncthreads();  // the previous plane's transform is done with the tile
-        Cx<R> rr[Mar::PER];
-        auto sink = [&](int q, int, int, double r0, double r1, double f0, double f1, double2 c) {
-            acc0 += r0 * r0 + r1 * r1;
-            acc1 += f0 * f0 + f1 * f1;
-            acc2 += c.x + c.y;
-            rr[q] = {R(r0), R(r1)};
-        };
-        m.step(k, sink);
-        __syncthreads();  // the march is done reading the plane tile
-#pragma unroll
-        for (int q = 0; q < Mar::PER; ++q) {
-            if (!m.valid(q)) continue;
-            const int t = m.row_of(q), h = m.pair_of(q);
-            if constexpr (XW) {
-                // walls: x[2h] -> v[h], x[2h+1] -> v[nx-1-h] (negated for sines)
-                R *trow = (R *)&tile.at(t, 0);
-                trow[h] = rr[q].re;
-                trow[NX - 1 - h] = sine ? -rr[q].im : rr[q].im;
-            } else {
-                tile.at(t, h) = rr[q];
-            }
+        if (gated_off(a0.batch, a0.gate, vb.y)) return;
+        XFwdArgs a = a0;
+        if (a.batch) {
+            const ProbPtrs &q = a.batch[vb.y];
+            a.f = q.f;
+            a.p = q.p;
+            a.p32 = q.p32;
+            a.S = q.S;
+            a.partials = q.partials;
+            a.sum_f = q.scal + 1;
         }
-        __syncthreads();
-        auto gload = [&](int b, int n) -> Cx<R> { return tile.at(b, n); };
-        const size_t rowk = (size_t)k * a.ny + m.j0;
-        const int V = m.V;
-        auto out = [&](int b) -> PK_GLOBAL Cx<R> * { return b < V ? S + (rowk + b) * M : nullptr; };
-        x_forward<M, TJ, NT, true, 0, XW>(s_tw, gload, tile, out, sine, w4);
+        constexpr int NX = 2 * M;
+        char *s_buf = lds;
+        Cx<R> *s_tw = (Cx<R> *)(lds + BUF_B);
+        double *s_red = (double *)(lds + BUF_B + TW_B);
+
+        const int njb = march_jblocks(a.ny, TJ);
+        const int bid = block_order(xcd_order(vb.x, vb.gx), vb.gx, a.reverse);
+        const int jb = bid % njb, kb = bid / njb;
+        const int kr = march_planes(a.ny, a.nz, TJ, a.kr_max, a.kr_nb);
+        const int k0 = kb * kr;
+        const int k1 = k0 + kr < a.nz ? k0 + kr : a.nz;
+
+        Mar m;
+        m.f = gbl(a.f);
+        if constexpr (P32)
+            m.p = gbl(a.p32);
+        else
+            m.p = gbl(a.p);
+        m.ax = a.ax;
+        m.ay = a.ay;
+        m.az = a.az;
+        m.mu = (a.sum_f && !a.regular) ? (*a.sum_f) * a.inv_n : 0.0;
+        m.tile = (double2(*)[M])s_buf;
+        m.setup(jb, a.ny, a.nz, a.bc_z, a.bc_y);
+        m.bc_x = XW ? a.bc_x : 0;
+        const bool sine = a.bc_x == 2;
+        Cx<R> *s_w4 = (Cx<R> *)(lds + BUF_B + TW_B + RED_B);
+        const Cx<R> *w4 = s_w4;
+        if constexpr (XW) load_table(s_w4, (const Cx<R> *)a.tw4x, NX, NT);
+        load_table(s_tw, (const Cx<R> *)a.tw, NX, NT);
+        m.start(k0);
+
+        Tile tile{(Cx<R> *)s_buf};
+        PK_GLOBAL Cx<R> *S = gbl((Cx<R> *)a.S);
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+        for (int k = k0; k < k1; ++k) {
+            __syncthreads();  // the previous plane's transform is done with the tile
+            Cx<R> rr[Mar::PER];
+            auto sink = [&](int q, int, int, double r0, double r1, double f0, double f1, double2 c) {
+                acc0 += r0 * r0 + r1 * r1;
+                acc1 += f0 * f0 + f1 * f1;
+                acc2 += c.x + c.y;
+                rr[q] = {R(r0), R(r1)};
+            };
+            m.step(k, sink);
+            __syncthreads();  // the march is done reading the plane tile
+#pragma unroll
+            for (int q = 0; q < Mar::PER; ++q) {
+                if (!m.valid(q)) continue;
+                const int t = m.row_of(q), h = m.pair_of(q);
+                if constexpr (XW) {
+                    // walls: x[2h] -> v[h], x[2h+1] -> v[nx-1-h] (negated for sines)
+                    R *trow = (R *)&tile.at(t, 0);
+                    trow[h] = rr[q].re;
+                    trow[NX - 1 - h] = sine ? -rr[q].im : rr[q].im;
+                } else {
+                    tile.at(t, h) = rr[q];
+                }
+            }
+            __syncthreads();
+            auto gload = [&](int b, int n) -> Cx<R> { return tile.at(b, n); };
+            const size_t rowk = (size_t)k * a.ny + m.j0;
+            const int V = m.V;
+            auto out = [&](int b) -> PK_GLOBAL Cx<R> * { return b < V ? S + (rowk + b) * M : nullptr; };
+            x_forward<M, TJ, NT, true, 0, XW>(s_tw, gload, tile, out, sine, w4);
+        }
+        block_sum3(acc0, acc1, acc2, s_red, NT);
+        if (threadIdx.x == 0) {
+            a.partials[4 * vb.x] = acc0;
+            a.partials[4 * vb.x + 1] = acc1;
+            a.partials[4 * vb.x + 2] = acc2;
+        }
     }
-    block_sum3(acc0, acc1, acc2, s_red);
-    if (threadIdx.x == 0) {
-        a.partials[4 * blockIdx.x] = acc0;
-        a.partials[4 * blockIdx.x + 1] = acc1;
-        a.partials[4 * blockIdx.x + 2] = acc2;
-    }
+};
+
+template <int M, bool XW, bool P32>
+__global__ __launch_bounds__(XR_NT) void k_x_res(XFwdArgs a0)
+{
+    using B = XRBody<M, XW, P32>;
+    __shared__ __align__(16) char s_lds[B::LDS_BYTES];
+    B::run(a0, VBlock{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x}, s_lds);
 }
 
 // Forward pass of the projection step: the right-hand side
@@ -599,240 +617,255 @@ __global__ __launch_bounds__(xd_nt<XW>()) void k_x_div(XFwdArgs a0)
     }
 }
 
-template <int M, bool ACC, bool XW, bool P32>
-__global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
-{
-    // P32: the first iterate lives in FP32 (a.p32); the plain pass writes it
-    // there, the accumulating pass reads it there and writes p.  A problem
-    // of the device-side loop that stopped before any correction (C_COPY)
-    // gets p = p32 widened instead.
-    bool widen_only = false;
-    if constexpr (P32 && ACC) {
-        if (a0.batch && a0.gate) {
-            const int *c = a0.batch[blockIdx.y].ctrl;
-            if (c[C_CORRECT] == 0) {
-                if (c[C_COPY] == 0) return;
-                widen_only = true;
-            }
-        }
-    } else {
-        if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
-    }
-    XInvArgs a = a0;
-    if (a.batch) {
-        const ProbPtrs &q = a.batch[blockIdx.y];
-        a.S = q.S;
-        a.p = q.p;
-        a.p32 = q.p32;
-        if (ACC && a.sum_p) a.sum_p = q.scal + 4;
-    }
-    // accumulate mode also removes the mean of the previous iterate (the
-    // residual cannot see the constant mode, so the gauge is kept here)
-    const double pmean = (ACC && a.sum_p && !a.regular) ? (*a.sum_p) * a.inv_n : 0.0;
+// One workgroup's work (row block vb.x of problem vb.y) of the inverse pass;
+// LDS carved from `lds` (LDS_BYTES).
+template <int M, bool ACC, bool XW, bool P32> struct XIBody {
     using C = XCfg<M>;
-    constexpr int NB = C::NB, NT = C::NT, NX = 2 * M;
-    using Tile = LdsTile<R, M, NB, false, C::PAD>;
-    __shared__ Cx<R> s_tile[Tile::elems];
-    __shared__ Cx<R> s_tw[NX];
+    using Tile = LdsTile<R, M, C::NB, false, C::PAD>;
+    static constexpr size_t TILE_B = sizeof(Cx<R>) * Tile::elems;
+    static constexpr size_t LDS_BYTES = TILE_B + sizeof(Cx<R>) * 2 * M;
 
-    const int nrows = a.ny * a.nz;
-    const int row0 = block_order(blockIdx.x, gridDim.x, a.reverse) * NB;
-    PK_GLOBAL double *gp = gbl(a.p);
-    PK_GLOBAL float *gp32 = gbl(a.p32);
-    if (widen_only) {  // uniform over the workgroup
-        for (int e = threadIdx.x; e < NB * M; e += NT) {
-            const int row = row0 + e / M;
-            if (row >= nrows) break;
-            const size_t o = (size_t)row * NX + 2 * (e % M);
-            st_stream(gp + o, ld_stream(gp32 + o));
+    static __device__ __forceinline__ void run(const XInvArgs &a0, VBlock vb, char *lds)
+    {
+
+        // P32: the first iterate lives in FP32 (a.p32); the plain pass writes it
+        // there, the accumulating pass reads it there and writes p.  A problem
+        // of the device-side loop that stopped before any correction (C_COPY)
+        // gets p = p32 widened instead.
+        bool widen_only = false;
+        if constexpr (P32 && ACC) {
+            if (a0.batch && a0.gate) {
+                const int *c = a0.batch[vb.y].ctrl;
+                if (c[C_CORRECT] == 0) {
+                    if (c[C_COPY] == 0) return;
+                    widen_only = true;
+                }
+            }
+        } else {
+            if (gated_off(a0.batch, a0.gate, vb.y)) return;
         }
-        return;
-    }
-    load_table(s_tw, (const Cx<R> *)a.tw, NX);
-    __syncthreads();
+        XInvArgs a = a0;
+        if (a.batch) {
+            const ProbPtrs &q = a.batch[vb.y];
+            a.S = q.S;
+            a.p = q.p;
+            a.p32 = q.p32;
+            if (ACC && a.sum_p) a.sum_p = q.scal + 4;
+        }
+        // accumulate mode also removes the mean of the previous iterate (the
+        // residual cannot see the constant mode, so the gauge is kept here)
+        const double pmean = (ACC && a.sum_p && !a.regular) ? (*a.sum_p) * a.inv_n : 0.0;
+        constexpr int NB = C::NB, NT = C::NT, NX = 2 * M;
+        Cx<R> *s_tile = (Cx<R> *)lds;
+        Cx<R> *s_tw = (Cx<R> *)(lds + TILE_B);
 
-    const PK_GLOBAL Cx<R> *S = gbl((const Cx<R> *)a.S);
-    const bool sine = a.bc_x == 2;
-    const PK_GLOBAL Cx<R> *w4 = XW ? gbl((const Cx<R> *)a.tw4x) : nullptr;
-    auto gstore = [&](int b, int n, Cx<R> v) {
-        const int row = row0 + b;
-        if (row >= nrows) return;
-        double2 o = {double(v.re), -double(v.im)};
-        if constexpr (XW) {
-            // walls: v[j] goes back to x[r(j)] (negated at odd x for sines)
-            const int i0 = wall_index(2 * n, NX), i1 = wall_index(2 * n + 1, NX);
-            if (sine) {
-                o.x = (i0 & 1) ? -o.x : o.x;
-                o.y = (i1 & 1) ? -o.y : o.y;
-            }
-            PK_GLOBAL double *rp = gp + (size_t)row * NX;
-            PK_GLOBAL float *rp32 = gp32 + (size_t)row * NX;
-            if constexpr (ACC) {
-                o.x += (P32 ? (double)rp32[i0] : rp[i0]) - pmean;
-                o.y += (P32 ? (double)rp32[i1] : rp[i1]) - pmean;
-            }
-            if constexpr (P32 && !ACC) {
-                rp32[i0] = (float)o.x;
-                rp32[i1] = (float)o.y;
-            } else {
-                rp[i0] = o.x;
-                rp[i1] = o.y;
+        const int nrows = a.ny * a.nz;
+        const int row0 = block_order(vb.x, vb.gx, a.reverse) * NB;
+        PK_GLOBAL double *gp = gbl(a.p);
+        PK_GLOBAL float *gp32 = gbl(a.p32);
+        if (widen_only) {  // uniform over the workgroup
+            for (int e = threadIdx.x; e < NB * M; e += NT) {
+                const int row = row0 + e / M;
+                if (row >= nrows) break;
+                const size_t o = (size_t)row * NX + 2 * (e % M);
+                st_stream(gp + o, ld_stream(gp32 + o));
             }
             return;
         }
-        const size_t di = (size_t)row * NX + 2 * n;
-        if constexpr (ACC) {
-            const double2 old = P32 ? ld_stream(gp32 + di) : ld_stream(gp + di);
-            o.x += old.x - pmean;
-            o.y += old.y - pmean;
-        }
-        if constexpr (P32 && !ACC)
-            st_stream(gp32 + di, o);
-        else
-            st_stream(gp + di, o);
-    };
-    // spectrum value m of a row: the packed half spectrum, or for walls the
-    // inverse input formed from the cosine / sine coefficients
-    auto xval = [&](const PK_GLOBAL Cx<R> *sr, int m) -> Cx<R> {
-        if constexpr (XW)
-            return wall_load((const PK_GLOBAL R *)sr, NX, m, w4, sine);
-        else
-            return sr[m];
-    };
-    Tile tile{s_tile};
-    // walls: the tile holds conj(v) of each row in transform order; write
-    // x[2h] = v[h], x[2h+1] = v[nx-1-h] (negated for sines) with contiguous
-    // stores (or accumulate)
-    auto wall_rows_out = [&]() {
+        load_table(s_tw, (const Cx<R> *)a.tw, NX, NT);
         __syncthreads();
-        constexpr int PERW = (NB * M + NT - 1) / NT;
-        double2 old[PERW];
-        if constexpr (ACC) {
-            // all loads of the previous iterate in flight first
+
+        const PK_GLOBAL Cx<R> *S = gbl((const Cx<R> *)a.S);
+        const bool sine = a.bc_x == 2;
+        const PK_GLOBAL Cx<R> *w4 = XW ? gbl((const Cx<R> *)a.tw4x) : nullptr;
+        auto gstore = [&](int b, int n, Cx<R> v) {
+            const int row = row0 + b;
+            if (row >= nrows) return;
+            double2 o = {double(v.re), -double(v.im)};
+            if constexpr (XW) {
+                // walls: v[j] goes back to x[r(j)] (negated at odd x for sines)
+                const int i0 = wall_index(2 * n, NX), i1 = wall_index(2 * n + 1, NX);
+                if (sine) {
+                    o.x = (i0 & 1) ? -o.x : o.x;
+                    o.y = (i1 & 1) ? -o.y : o.y;
+                }
+                PK_GLOBAL double *rp = gp + (size_t)row * NX;
+                PK_GLOBAL float *rp32 = gp32 + (size_t)row * NX;
+                if constexpr (ACC) {
+                    o.x += (P32 ? (double)rp32[i0] : rp[i0]) - pmean;
+                    o.y += (P32 ? (double)rp32[i1] : rp[i1]) - pmean;
+                }
+                if constexpr (P32 && !ACC) {
+                    rp32[i0] = (float)o.x;
+                    rp32[i1] = (float)o.y;
+                } else {
+                    rp[i0] = o.x;
+                    rp[i1] = o.y;
+                }
+                return;
+            }
+            const size_t di = (size_t)row * NX + 2 * n;
+            if constexpr (ACC) {
+                const double2 old = P32 ? ld_stream(gp32 + di) : ld_stream(gp + di);
+                o.x += old.x - pmean;
+                o.y += old.y - pmean;
+            }
+            if constexpr (P32 && !ACC)
+                st_stream(gp32 + di, o);
+            else
+                st_stream(gp + di, o);
+        };
+        // spectrum value m of a row: the packed half spectrum, or for walls the
+        // inverse input formed from the cosine / sine coefficients
+        auto xval = [&](const PK_GLOBAL Cx<R> *sr, int m) -> Cx<R> {
+            if constexpr (XW)
+                return wall_load((const PK_GLOBAL R *)sr, NX, m, w4, sine);
+            else
+                return sr[m];
+        };
+        Tile tile{s_tile};
+        // walls: the tile holds conj(v) of each row in transform order; write
+        // x[2h] = v[h], x[2h+1] = v[nx-1-h] (negated for sines) with contiguous
+        // stores (or accumulate)
+        auto wall_rows_out = [&]() {
+            __syncthreads();
+            constexpr int PERW = (NB * M + NT - 1) / NT;
+            double2 old[PERW];
+            if constexpr (ACC) {
+                // all loads of the previous iterate in flight first
+#pragma unroll
+                for (int q = 0; q < PERW; ++q) {
+                    const int e = threadIdx.x + q * NT;
+                    const int row = row0 + e / M;
+                    old[q] = {0.0, 0.0};
+                    if (e < NB * M && row < nrows) {
+                        const size_t oi = (size_t)row * NX + 2 * (e % M);
+                        old[q] = P32 ? ld_stream(gp32 + oi) : ld_stream(gp + oi);
+                    }
+                }
+            }
 #pragma unroll
             for (int q = 0; q < PERW; ++q) {
                 const int e = threadIdx.x + q * NT;
-                const int row = row0 + e / M;
-                old[q] = {0.0, 0.0};
-                if (e < NB * M && row < nrows) {
-                    const size_t oi = (size_t)row * NX + 2 * (e % M);
-                    old[q] = P32 ? ld_stream(gp32 + oi) : ld_stream(gp + oi);
+                const int b = e / M, h = e % M;
+                const int row = row0 + b;
+                if (e >= NB * M || row >= nrows) continue;
+                const R *trow = (const R *)&tile.at(b, 0);
+                // the tile holds conj(z), z[j] = v[2j] + i v[2j+1]
+                const int j1 = NX - 1 - h;
+                const double v0 = (h & 1) ? -double(trow[h]) : double(trow[h]);
+                double v1 = (j1 & 1) ? -double(trow[j1]) : double(trow[j1]);
+                if (sine) v1 = -v1;
+                double2 o = {v0, v1};
+                if constexpr (ACC) {
+                    o.x += old[q].x - pmean;
+                    o.y += old[q].y - pmean;
                 }
+                if constexpr (P32 && !ACC)
+                    st_stream(gp32 + (size_t)row * NX + 2 * h, o);
+                else
+                    st_stream(gp + (size_t)row * NX + 2 * h, o);
             }
-        }
+        };
+        // reversed radix order: the small radix first gives more butterfly pairs
+        // per row for the fused first pass
+        constexpr RPlan pl = get_rplan(M, 1);
+        if constexpr (pl.count >= 2 && (M / pl.r[0]) % 2 == 0) {
+            // first pass with the merge fused (no twiddles in a first pass),
+            // outputs of butterfly j to the LDS tile at j RAD + r
+            constexpr int RAD = pl.r[0];
+            constexpr int NJ = M / RAD;
+            static_assert(NJ % 2 == 0, "pairing needs even NJ");
+            constexpr int U = NJ / 2, NU = NB * U;
+            constexpr int PER = (NU + NT - 1) / NT;
 #pragma unroll
-        for (int q = 0; q < PERW; ++q) {
-            const int e = threadIdx.x + q * NT;
-            const int b = e / M, h = e % M;
-            const int row = row0 + b;
-            if (e >= NB * M || row >= nrows) continue;
-            const R *trow = (const R *)&tile.at(b, 0);
-            // the tile holds conj(z), z[j] = v[2j] + i v[2j+1]
-            const int j1 = NX - 1 - h;
-            const double v0 = (h & 1) ? -double(trow[h]) : double(trow[h]);
-            double v1 = (j1 & 1) ? -double(trow[j1]) : double(trow[j1]);
-            if (sine) v1 = -v1;
-            double2 o = {v0, v1};
-            if constexpr (ACC) {
-                o.x += old[q].x - pmean;
-                o.y += old[q].y - pmean;
-            }
-            if constexpr (P32 && !ACC)
-                st_stream(gp32 + (size_t)row * NX + 2 * h, o);
-            else
-                st_stream(gp + (size_t)row * NX + 2 * h, o);
-        }
-    };
-    // reversed radix order: the small radix first gives more butterfly pairs
-    // per row for the fused first pass
-    constexpr RPlan pl = get_rplan(M, 1);
-    if constexpr (pl.count >= 2 && (M / pl.r[0]) % 2 == 0) {
-        // first pass with the merge fused (no twiddles in a first pass),
-        // outputs of butterfly j to the LDS tile at j RAD + r
-        constexpr int RAD = pl.r[0];
-        constexpr int NJ = M / RAD;
-        static_assert(NJ % 2 == 0, "pairing needs even NJ");
-        constexpr int U = NJ / 2, NU = NB * U;
-        constexpr int PER = (NU + NT - 1) / NT;
+            for (int q = 0; q < PER; ++q) {
+                const int u = threadIdx.x + q * NT;
+                if (NU % NT != 0 && u >= NU) break;
+                const int b = u / U, pp = u % U;
+                int j1, j2;
+                pair_of<NJ>(pp, j1, j2);
+                const int row = row0 + b;
+                Cx<R> v1[RAD], v2[RAD];
+                if (row < nrows) {
+                    const PK_GLOBAL Cx<R> *sr = S + (size_t)row * M;
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int u = threadIdx.x + q * NT;
-            if (NU % NT != 0 && u >= NU) break;
-            const int b = u / U, pp = u % U;
-            int j1, j2;
-            pair_of<NJ>(pp, j1, j2);
-            const int row = row0 + b;
-            Cx<R> v1[RAD], v2[RAD];
-            if (row < nrows) {
-                const PK_GLOBAL Cx<R> *sr = S + (size_t)row * M;
+                    for (int r = 0; r < RAD; ++r) {
+                        v1[r] = xval(sr, j1 + r * NJ);
+                        v2[r] = xval(sr, j2 + r * NJ);
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < RAD; ++r) v1[r] = v2[r] = {R(0), R(0)};
+                }
+                Cx<R> z1[RAD], z2[RAD];
+                if (pp == 0) {
+                    // m = 0 unpacks X(0) + i X(M); butterfly 0 pairs r <-> RAD-r
+                    z1[0] = {v1[0].re + v1[0].im, -(v1[0].re - v1[0].im)};
+#pragma unroll
+                    for (int r = 1; r < RAD; ++r)
+                        if (r <= RAD - r) merge_pair(v1[r], v1[RAD - r], s_tw[r * NJ], z1[r], z1[RAD - r]);
+#pragma unroll
+                    for (int r = 0; r < RAD; ++r)
+                        if (r <= RAD - 1 - r)
+                            merge_pair(v2[r], v2[RAD - 1 - r], s_tw[NJ / 2 + r * NJ], z2[r],
+                                       z2[RAD - 1 - r]);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < RAD; ++r)
+                        merge_pair(v1[r], v2[RAD - 1 - r], s_tw[j1 + r * NJ], z1[r], z2[RAD - 1 - r]);
+                }
+                Bfly<R, RAD>::run(z1);
+                Bfly<R, RAD>::run(z2);
 #pragma unroll
                 for (int r = 0; r < RAD; ++r) {
-                    v1[r] = xval(sr, j1 + r * NJ);
-                    v2[r] = xval(sr, j2 + r * NJ);
+                    tile.at(b, j1 * RAD + r) = z1[r];
+                    tile.at(b, j2 * RAD + r) = z2[r];
                 }
+            }
+            __syncthreads();
+            auto gnone = [&](int, int) -> Cx<R> { return {R(0), R(0)}; };
+            if constexpr (XW) {
+                // the last pass stores back into the tile (it synchronises between
+                // its reads and writes); rows are then written contiguously
+                auto tstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
+                fft_passes<R, M, NB, NT, false, C::PAD, false, 1, pl.count, 1>(s_tw, 2, gnone,
+                                                                               tstore, tile);
+                wall_rows_out();
             } else {
-#pragma unroll
-                for (int r = 0; r < RAD; ++r) v1[r] = v2[r] = {R(0), R(0)};
+                fft_passes<R, M, NB, NT, false, C::PAD, false, 1, pl.count, 1>(s_tw, 2, gnone,
+                                                                               gstore, tile);
             }
-            Cx<R> z1[RAD], z2[RAD];
-            if (pp == 0) {
-                // m = 0 unpacks X(0) + i X(M); butterfly 0 pairs r <-> RAD-r
-                z1[0] = {v1[0].re + v1[0].im, -(v1[0].re - v1[0].im)};
-#pragma unroll
-                for (int r = 1; r < RAD; ++r)
-                    if (r <= RAD - r) merge_pair(v1[r], v1[RAD - r], s_tw[r * NJ], z1[r], z1[RAD - r]);
-#pragma unroll
-                for (int r = 0; r < RAD; ++r)
-                    if (r <= RAD - 1 - r)
-                        merge_pair(v2[r], v2[RAD - 1 - r], s_tw[NJ / 2 + r * NJ], z2[r],
-                                   z2[RAD - 1 - r]);
+        } else {
+            auto gload = [&](int b, int n) -> Cx<R> {
+                const int row = row0 + b;
+                if (row >= nrows) return {R(0), R(0)};
+                const PK_GLOBAL Cx<R> *sr = S + (size_t)row * M;
+                if (n == 0) {
+                    const Cx<R> s0 = xval(sr, 0);
+                    return {s0.re + s0.im, -(s0.re - s0.im)};
+                }
+                Cx<R> zm, zc;
+                merge_pair(xval(sr, n), xval(sr, M - n), s_tw[n], zm, zc);
+                return zm;
+            };
+            if constexpr (XW) {
+                auto tstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
+                fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, tstore, tile);
+                wall_rows_out();
             } else {
-#pragma unroll
-                for (int r = 0; r < RAD; ++r)
-                    merge_pair(v1[r], v2[RAD - 1 - r], s_tw[j1 + r * NJ], z1[r], z2[RAD - 1 - r]);
+                fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, gstore, tile);
             }
-            Bfly<R, RAD>::run(z1);
-            Bfly<R, RAD>::run(z2);
-#pragma unroll
-            for (int r = 0; r < RAD; ++r) {
-                tile.at(b, j1 * RAD + r) = z1[r];
-                tile.at(b, j2 * RAD + r) = z2[r];
-            }
-        }
-        __syncthreads();
-        auto gnone = [&](int, int) -> Cx<R> { return {R(0), R(0)}; };
-        if constexpr (XW) {
-            // the last pass stores back into the tile (it synchronises between
-            // its reads and writes); rows are then written contiguously
-            auto tstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
-            fft_passes<R, M, NB, NT, false, C::PAD, false, 1, pl.count, 1>(s_tw, 2, gnone,
-                                                                           tstore, tile);
-            wall_rows_out();
-        } else {
-            fft_passes<R, M, NB, NT, false, C::PAD, false, 1, pl.count, 1>(s_tw, 2, gnone,
-                                                                           gstore, tile);
-        }
-    } else {
-        auto gload = [&](int b, int n) -> Cx<R> {
-            const int row = row0 + b;
-            if (row >= nrows) return {R(0), R(0)};
-            const PK_GLOBAL Cx<R> *sr = S + (size_t)row * M;
-            if (n == 0) {
-                const Cx<R> s0 = xval(sr, 0);
-                return {s0.re + s0.im, -(s0.re - s0.im)};
-            }
-            Cx<R> zm, zc;
-            merge_pair(xval(sr, n), xval(sr, M - n), s_tw[n], zm, zc);
-            return zm;
-        };
-        if constexpr (XW) {
-            auto tstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
-            fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, tstore, tile);
-            wall_rows_out();
-        } else {
-            fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, gstore, tile);
         }
     }
+};
+
+template <int M, bool ACC, bool XW, bool P32>
+__global__ __launch_bounds__(XCfg<M>::NT) void k_x_inv(XInvArgs a0)
+{
+    using B = XIBody<M, ACC, XW, P32>;
+    __shared__ __align__(16) char s_lds[B::LDS_BYTES];
+    B::run(a0, VBlock{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x}, s_lds);
 }
 
 // row blocks of the plain pass (an upper bound of its workgroup count), or
@@ -950,6 +983,9 @@ template <int M> static int run_x_inv(const XInvArgs &a, hipStream_t s)
 }  // namespace PK_NS
 using namespace PK_NS;
 
+// the host launchers are defined once, in this file's own object (the
+// work-list source includes this file for its kernel bodies)
+#ifndef PK_X_LIST_TU
 #define PK_CASE_FWD(N) case N: return run_x_fwd<N>(a, s, nblocks_out);
 #define PK_CASE_INV(N) case N: return run_x_inv<N>(a, s);
 #define PK_CASE_BLK(N) case N: return blocks_x<N>(ny, nz, residual, kr_max, kr_nb);
@@ -968,5 +1004,22 @@ int PK_SUFFIX(x_fwd_blocks)(int nx, int ny, int nz, int residual, int kr_max, in
 {
     switch (nx / 2) { PK_X_LENGTHS(PK_CASE_BLK) default: return -1; }
 }
+
+// workgroups (partial records) launch_x_fwd uses for this record
+template <int M> static int grid_of(const XFwdArgs &a)
+{
+    int nb = blocks_x<M>(a.ny, a.nz, a.residual, a.kr_max, a.kr_nb);
+    if (!a.residual)
+        nb = a.bc_x != 0 ? grid_x_fwd<M, true>(nb, a.batch ? a.nbatch : 1)
+                         : grid_x_fwd<M, false>(nb, a.batch ? a.nbatch : 1);
+    return nb;
+}
+#define PK_CASE_GRID(N) case N: return grid_of<N>(a);
+
+int PK_SUFFIX(x_fwd_grid)(const XFwdArgs &a)
+{
+    switch (a.nx / 2) { PK_X_LENGTHS(PK_CASE_GRID) default: return -1; }
+}
+#endif
 
 }  // namespace pk

@@ -35,39 +35,54 @@ template <int N, int V> struct YCfg {
     static constexpr int PV = (V & 2) ? 1 : 0;
 };
 
+// One workgroup's work: block vb.x (tile of NB x-wavenumbers of one plane)
+// of problem vb.y; LDS carved from `lds` (LDS_BYTES).  Called by the
+// per-group kernel and by the work-list kernel.
+template <int N, bool INV, int V> struct YBody {
+    using C = YCfg<N, V>;
+    static constexpr int NB = C::NB, NT = C::NT;
+    using Tile = LdsTile<R, N, NB, true, C::PAD>;
+    static constexpr size_t TILE_B = sizeof(Cx<R>) * Tile::elems;
+    static constexpr size_t LDS_BYTES = TILE_B + sizeof(Cx<R>) * N;
+
+    static __device__ __forceinline__ void run(const YArgs &a0, VBlock vb, char *lds)
+    {
+        if (gated_off(a0.batch, a0.gate, vb.y)) return;
+        YArgs a = a0;
+        if (a.batch) a.S = a.batch[vb.y].S;
+        Cx<R> *s_tile = (Cx<R> *)lds;
+        Cx<R> *s_tw = (Cx<R> *)(lds + TILE_B);
+
+        const int ntile = (a.M + NB - 1) / NB;
+        const int bid = block_order(vb.x, vb.gx, a.reverse);
+        const int tile_i = bid % ntile;
+        const int k = bid / ntile;
+        const int m0 = tile_i * NB;
+        load_table(s_tw, (const Cx<R> *)a.tw, N, NT);
+        __syncthreads();
+
+        Cx<R> *base = (Cx<R> *)a.S + (size_t)k * N * a.M + m0;
+        const int M = a.M;
+        auto gload = [&](int b, int n) -> Cx<R> {
+            if (m0 + b >= M) return {R(0), R(0)};
+            Cx<R> v = base[(size_t)n * M + b];
+            return INV ? cconj(v) : v;
+        };
+        auto gstore = [&](int b, int n, Cx<R> v) {
+            if (m0 + b >= M) return;
+            base[(size_t)n * M + b] = INV ? cconj(v) : v;
+        };
+        Tile tile{s_tile};
+        fft_tile<R, N, NB, NT, true, C::PAD, false, C::PV>(s_tw, 1, gload, gstore, tile);
+    }
+};
+
 template <int N, bool INV, int V>
 __global__ __launch_bounds__((YCfg<N, V>::NT)) void k_y(YArgs a0)
 {
-    if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
-    YArgs a = a0;
-    if (a.batch) a.S = a.batch[blockIdx.y].S;
-    using C = YCfg<N, V>;
-    constexpr int NB = C::NB, NT = C::NT;
-    using Tile = LdsTile<R, N, NB, true, C::PAD>;
-    __shared__ Cx<R> s_tile[Tile::elems];
-    __shared__ Cx<R> s_tw[N];
-
-    const int ntile = (a.M + NB - 1) / NB;
-    const int bid = block_order(blockIdx.x, gridDim.x, a.reverse);
-    const int tile_i = bid % ntile;
-    const int k = bid / ntile;
-    const int m0 = tile_i * NB;
-    load_table(s_tw, (const Cx<R> *)a.tw, N);
-    __syncthreads();
-
-    Cx<R> *base = (Cx<R> *)a.S + (size_t)k * N * a.M + m0;
-    const int M = a.M;
-    auto gload = [&](int b, int n) -> Cx<R> {
-        if (m0 + b >= M) return {R(0), R(0)};
-        Cx<R> v = base[(size_t)n * M + b];
-        return INV ? cconj(v) : v;
-    };
-    auto gstore = [&](int b, int n, Cx<R> v) {
-        if (m0 + b >= M) return;
-        base[(size_t)n * M + b] = INV ? cconj(v) : v;
-    };
-    Tile tile{s_tile};
-    fft_tile<R, N, NB, NT, true, C::PAD, false, C::PV>(s_tw, 1, gload, gstore, tile);
+    using B = YBody<N, INV, V>;
+    __shared__ __align__(16) char s_lds[B::LDS_BYTES];
+    B::run(a0, VBlock{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x}, s_lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -294,8 +309,101 @@ template <int N> static int run_y(const YArgs &a, hipStream_t s)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Work list: periodic y passes of problems of different shapes in one launch
+// (class = the transform length, tile variant 0, at most YL_NT threads).
+// ---------------------------------------------------------------------------
+constexpr int YL_NT = 256;
+#define PK_YL_LENGTHS(X) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+
+template <bool INV>
+__global__ __launch_bounds__(YL_NT) void k_y_list(ListArgs<YArgs>)
+{
+    extern __shared__ __align__(16) char s_dyn[];
+    const PK_KARG ListArgs<YArgs> *L = list_args<YArgs>();
+    int g;
+    VBlock vb;
+    if (!list_find(L, g, vb)) return;
+    const YArgs arg = L->a[g];
+    switch (L->cls[g]) {
+#define PK_YL_CASE(N)                                                                  \
+    case N:                                                                            \
+        if constexpr (YCfg<N, 0>::NT <= YL_NT) YBody<N, INV, 0>::run(arg, vb, s_dyn); \
+        break;
+        PK_YL_LENGTHS(PK_YL_CASE)
+#undef PK_YL_CASE
+    default: break;
+    }
+}
+
+// class info of a y record for the list kernel: false when it has none
+static bool y_list_class(const YArgs &a, int &nt, int &gx, size_t &lds)
+{
+    if (a.bc != 0) return false;
+    switch (a.ny) {
+#define PK_YL_INFO(N)                                                   \
+    case N: {                                                           \
+        using B = YBody<N, false, 0>;                                   \
+        if (B::NT > YL_NT) return false;                                \
+        nt = B::NT;                                                     \
+        gx = (a.M + B::NB - 1) / B::NB * a.nz;                          \
+        lds = B::LDS_BYTES;                                             \
+        return true;                                                    \
+    }
+        PK_YL_LENGTHS(PK_YL_INFO)
+#undef PK_YL_INFO
+    default: return false;
+    }
+}
+
 }  // namespace PK_NS
 using namespace PK_NS;
+
+int PK_SUFFIX(launch_y)(const YArgs &a, hipStream_t s);
+
+int PK_SUFFIX(launch_y_list)(const YArgs *a, int n, hipStream_t s)
+{
+    ListArgs<YArgs> L{};
+    size_t lds = 0;
+    int total = 0;
+    const bool inv = n > 0 && a[0].inverse;
+    auto flush = [&]() -> int {
+        if (L.nseg == 0) return 0;
+        L.start[L.nseg] = total;
+        if (inv)
+            hipLaunchKernelGGL(k_y_list<true>, dim3(total), dim3(YL_NT), lds, s, L);
+        else
+            hipLaunchKernelGGL(k_y_list<false>, dim3(total), dim3(YL_NT), lds, s, L);
+        L.nseg = 0;
+        total = 0;
+        lds = 0;
+        return (int)hipGetLastError();
+    };
+    for (int i = 0; i < n; ++i) {
+        if ((a[i].inverse != 0) != inv) return (int)hipErrorInvalidValue;
+        if (a[i].ny == 1) continue;  // the identity
+        int nt = 0, gx = 0;
+        size_t b = 0;
+        if (!y_list_class(a[i], nt, gx, b)) {
+            const int e = PK_SUFFIX(launch_y)(a[i], s);
+            if (e) return e;
+            continue;
+        }
+        const int g = L.nseg++;
+        L.start[g] = total;
+        L.gx[g] = gx;
+        L.cls[g] = a[i].ny;
+        L.nt[g] = nt;
+        L.a[g] = a[i];
+        total += gx * (a[i].batch ? a[i].nbatch : 1);
+        lds = lds > b ? lds : b;
+        if (L.nseg == LIST_MAX_SEG) {
+            const int e = flush();
+            if (e) return e;
+        }
+    }
+    return flush();
+}
 
 #define PK_CASE_Y(N) case N: return run_y<N>(a, s);
 

@@ -80,331 +80,347 @@ __device__ __forceinline__ double rcp_nr(double x)
     return fma(fma(-x, r, 1.0), r, r);
 }
 
-template <int L, int W, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
-{
-    if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
-    ZArgs a = a0;
-    if (a.batch) {
-        const ProbPtrs &pq = a.batch[blockIdx.y];
-        a.S = pq.S;
-        if (a.zero_mean_out) a.zero_mean_out = pq.scal;
-    }
-    extern __shared__ double smem_d[];
-    R *buf = (R *)smem_d;                                       // C*W slots of 4 reals
-    double *zbuf = smem_d + ((C * W * 4 * sizeof(R) + 7) / 8);  // 3*C doubles
+// One workgroup's work (block vb.x of problem vb.y): C chunks of L rows of W
+// columns; `smem_d` holds the dynamic LDS of zw_lds_bytes().
+template <int L, int W> struct ZWBody {
+    static __device__ __forceinline__ void run(const ZArgs &a0, VBlock vb, int C, int nspecial,
+                                               double *smem_d)
+    {
+        if (gated_off(a0.batch, a0.gate, vb.y)) return;
+        ZArgs a = a0;
+        if (a.batch) {
+            const ProbPtrs &pq = a.batch[vb.y];
+            a.S = pq.S;
+            if (a.zero_mean_out) a.zero_mean_out = pq.scal;
+        }
+        R *buf = (R *)smem_d;                                       // C*W slots of 4 reals
+        double *zbuf = smem_d + ((C * W * 4 * sizeof(R) + 7) / 8);  // 3*C doubles
 
-    const int t = threadIdx.x;
-    const int w = t % W, c = t / W;
-    const int nz = a.nz, M = a.M, ny = a.ny;
-    const size_t plane = (size_t)ny * M;
-    PK_GLOBAL Cx<R> *S = gbl((Cx<R> *)a.S);
-    const int s = c * L;
-    const int e = (s + L < nz) ? s + L : nz;  // chunk rows [s, e)
-    const bool special = (int)blockIdx.x < nspecial;
-    const double scale = a.dz2 * a.inv_nxny;
+        const int t = threadIdx.x;
+        const int w = t % W, c = t / W;
+        const int nz = a.nz, M = a.M, ny = a.ny;
+        const size_t plane = (size_t)ny * M;
+        PK_GLOBAL Cx<R> *S = gbl((Cx<R> *)a.S);
+        const int s = c * L;
+        const int e = (s + L < nz) ? s + L : nz;  // chunk rows [s, e)
+        const bool special = vb.x < nspecial;
+        const double scale = a.dz2 * a.inv_nxny;
 
-    Cx<R> d[L];
-    bool active;
-    bool zero_lane = false;
-    int q = 0, ky = 0, kyn = 0, part = 0, mm = 0;
-    double s_d;  // s = -(lam_x + lam_y) dz^2 >= 0
-    if (!special) {
-        q = block_order((int)blockIdx.x - nspecial, (int)gridDim.x - nspecial, a.reverse) * W + w;
-        const int m = q % M;
-        ky = q / M;
-        active = (q < ny * M) && (m != 0);
-        s_d = active ? -(a.lamx[m] + a.lamy[ky]) * a.dz2 : 1.0;
-        const PK_GLOBAL Cx<R> *col = S + (size_t)s * plane + (active ? q : 0);
+        Cx<R> d[L];
+        bool active;
+        bool zero_lane = false;
+        int q = 0, ky = 0, kyn = 0, part = 0, mm = 0;
+        double s_d;  // s = -(lam_x + lam_y) dz^2 >= 0
+        if (!special) {
+            q = block_order(vb.x - nspecial, vb.gx - nspecial, a.reverse) * W + w;
+            const int m = q % M;
+            ky = q / M;
+            active = (q < ny * M) && (m != 0);
+            s_d = active ? -(a.lamx[m] + a.lamy[ky]) * a.dz2 : 1.0;
+            const PK_GLOBAL Cx<R> *col = S + (size_t)s * plane + (active ? q : 0);
 #pragma unroll
-        for (int i = 0; i < L; ++i)
-            if (active && s + i < nz) {
-                const PK_GLOBAL Cx<R> &v = col[(size_t)i * plane];
-                d[i] = Cx<R>{v.re, v.im};
-            } else {
-                d[i] = Cx<R>{R(0), R(0)};
-            }
-    } else {
-        // two-mode columns: lanes [0, W/2) take part A, lanes [W/2, W) part B
-        // of the same (m, ky pair), so each half reads a contiguous run of m
-        // (walls along x) and the halves exchange values with a lane shuffle
-        constexpr int H = W / 2 > 0 ? W / 2 : 1;
-        part = w >= H ? 1 : 0;
-        const int mi = w - part * H;
-        const int sb = (int)blockIdx.x;
-        const int mblk = a.xwall ? (M + H - 1) / H : 1;
-        const int pair = a.xwall ? sb / mblk : sb * H + mi;
-        mm = a.xwall ? (sb % mblk) * H + mi : 0;
-        if (a.ywall) {
-            // walls along y: the coefficients along y are real-linear, so
-            // column (m, ky) holds the two real x-modes as A + iB with no
-            // partner column: part A solves Re, part B solves Im
-            active = pair < ny && mm < M;
-            ky = active ? pair : 0;
-            kyn = ky;
+            for (int i = 0; i < L; ++i)
+                if (active && s + i < nz) {
+                    const PK_GLOBAL Cx<R> &v = col[(size_t)i * plane];
+                    d[i] = Cx<R>{v.re, v.im};
+                } else {
+                    d[i] = Cx<R>{R(0), R(0)};
+                }
         } else {
-            active = pair <= ny / 2 && mm < M;
-            ky = active ? pair : 0;
-            kyn = (ny - ky) % ny;
-        }
-        zero_lane = active && mm == 0 && pair == 0 && part == 0 && !a.regular;
-        const double lx = a.xwall ? a.lamx[2 * (active ? mm : 0) + part]
-                                  : (part ? a.lamx[M] : a.lamx[0]);
-        s_d = (active && !zero_lane) ? -(lx + a.lamy[ky]) * a.dz2 : 1.0;
-        // part A reads column ky, part B column -ky (the same with walls along y)
-        const PK_GLOBAL Cx<R> *col =
-            S + (size_t)s * plane + (size_t)(part ? kyn : ky) * M + (active ? mm : 0);
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-            const int k = s + i;
-            Cx<R> own = {R(0), R(0)};
-            if (active && k < nz) {
-                const Cx<R> g = col[(size_t)i * plane];
-                own = {g.re, g.im};
-            }
-            Cx<R> v;
+            // two-mode columns: lanes [0, W/2) take part A, lanes [W/2, W) part B
+            // of the same (m, ky pair), so each half reads a contiguous run of m
+            // (walls along x) and the halves exchange values with a lane shuffle
+            constexpr int H = W / 2 > 0 ? W / 2 : 1;
+            part = w >= H ? 1 : 0;
+            const int mi = w - part * H;
+            const int sb = vb.x;
+            const int mblk = a.xwall ? (M + H - 1) / H : 1;
+            const int pair = a.xwall ? sb / mblk : sb * H + mi;
+            mm = a.xwall ? (sb % mblk) * H + mi : 0;
             if (a.ywall) {
-                v = part ? Cx<R>{own.im, R(0)} : Cx<R>{own.re, R(0)};
+                // walls along y: the coefficients along y are real-linear, so
+                // column (m, ky) holds the two real x-modes as A + iB with no
+                // partner column: part A solves Re, part B solves Im
+                active = pair < ny && mm < M;
+                ky = active ? pair : 0;
+                kyn = ky;
             } else {
-                const Cx<R> oth = {__shfl_xor(own.re, H, 64), __shfl_xor(own.im, H, 64)};
-                const Cx<R> z1 = part ? oth : own;           // Z(ky)
-                const Cx<R> z2 = cconj(part ? own : oth);    // conj Z(-ky)
-                v = part ? cscale(cmul_mi(csub(z1, z2)), R(0.5)) : cscale(cadd(z1, z2), R(0.5));
+                active = pair <= ny / 2 && mm < M;
+                ky = active ? pair : 0;
+                kyn = (ny - ky) % ny;
             }
-            d[i] = (active && k < nz) ? v : Cx<R>{R(0), R(0)};
-        }
-    }
+            zero_lane = active && mm == 0 && pair == 0 && part == 0 && !a.regular;
+            const double lx = a.xwall ? a.lamx[2 * (active ? mm : 0) + part]
+                                      : (part ? a.lamx[M] : a.lamx[0]);
+            s_d = (active && !zero_lane) ? -(lx + a.lamy[ky]) * a.dz2 : 1.0;
+            // part A reads column ky, part B column -ky (the same with walls along y)
+            const PK_GLOBAL Cx<R> *col =
+                S + (size_t)s * plane + (size_t)(part ? kyn : ky) * M + (active ? mm : 0);
 #pragma unroll
-    for (int i = 0; i < L; ++i) d[i] = cscale(d[i], R(scale));
-
-    // zero wavenumber: raw A(0,k) = Re S[k,0,0] is re-read (L1-resident)
-    // whenever needed, so the FP64 path keeps only scalars across barriers
-    auto zraw = [&](int k) -> double { return double(S[(size_t)k * plane].re); };
-
-    const R sv = R(s_d);
-    const R mw = rcp_nr(R(1) + sv);  // Moebius matrix [[1, s], [1, 1+s]] / (1+s)
-    const R mws = sv * mw;
-    // Dirichlet walls: 2 more on the first and last pivot; row 0 maps any
-    // entering v to (s + 2)/(s + 3) instead of s/(1 + s)
-    const R dir2 = a.dirichlet_z ? R(2) : R(0);
-    const R mws0 = a.dirichlet_z ? (sv + R(2)) * rcp_nr(sv + R(3)) : mws;
-
-    // ---- phase 1: Moebius product of the chunk (v recurrence) -----------
-    // Rows past nz (only in the last chunk) are padding: zero right-hand
-    // side; v = 1 (u = 0) on row nz-1 decouples them from the real rows in
-    // the back substitution, and nothing reads the last chunk's products.
-    R p00 = R(1), p01 = R(0), p10 = R(0), p11 = R(1);
-#pragma unroll
-    for (int i = 0; i < L; ++i) {
-        const int k = s + i;
-        const R a0 = (k == 0) ? R(0) : mw;  // row 0 ignores the entering v
-        const R b0 = (k == 0) ? mws0 : mws;
-        const R n00 = a0 * p00 + b0 * p10, n01 = a0 * p01 + b0 * p11;
-        const R n10 = a0 * p00 + p10, n11 = a0 * p01 + p11;
-        p00 = n00; p01 = n01; p10 = n10; p11 = n11;
-    }
-    R *slot = buf + (size_t)(c * W + w) * 4;
-    slot[0] = p00; slot[1] = p01; slot[2] = p10; slot[3] = p11;
-    if (zero_lane) {
-        double zsum = 0.0;
-        for (int k = s; k < e; ++k) zsum += zraw(k);
-        zbuf[c] = zsum;
-    }
-    __syncthreads();  // S1
-
-    // v entering the chunk: apply the preceding chunks' maps to v (all
-    // entries are >= 0 and the denominator is >= the numerator, so
-    // normalising by it each step is safe and keeps the scan bounded)
-    R vprev0 = R(0);
-    {
-        int cc = 0;
-        for (; cc + 4 <= c; cc += 4) {
-            R o[4][4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) o[u][e] = buf[(size_t)((cc + u) * W + w) * 4 + e];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                vprev0 = (o[u][0] * vprev0 + o[u][1]) * rcp_nr(o[u][2] * vprev0 + o[u][3]);
+            for (int i = 0; i < L; ++i) {
+                const int k = s + i;
+                Cx<R> own = {R(0), R(0)};
+                if (active && k < nz) {
+                    const Cx<R> g = col[(size_t)i * plane];
+                    own = {g.re, g.im};
+                }
+                Cx<R> v;
+                if (a.ywall) {
+                    v = part ? Cx<R>{own.im, R(0)} : Cx<R>{own.re, R(0)};
+                } else {
+                    const Cx<R> oth = {__shfl_xor(own.re, H, 64), __shfl_xor(own.im, H, 64)};
+                    const Cx<R> z1 = part ? oth : own;           // Z(ky)
+                    const Cx<R> z2 = cconj(part ? own : oth);    // conj Z(-ky)
+                    v = part ? cscale(cmul_mi(csub(z1, z2)), R(0.5)) : cscale(cadd(z1, z2), R(0.5));
+                }
+                d[i] = (active && k < nz) ? v : Cx<R>{R(0), R(0)};
+            }
         }
-        for (; cc < c; ++cc) {
-            const R *o = buf + (size_t)(cc * W + w) * 4;
-            vprev0 = (o[0] * vprev0 + o[1]) * rcp_nr(o[2] * vprev0 + o[3]);
-        }
-    }
+#pragma unroll
+        for (int i = 0; i < L; ++i) d[i] = cscale(d[i], R(scale));
 
-    // zero wavenumber, FP64: g = (raw - mean raw) * scale; face fluxes
-    // F_k = sum_{j<=k} g_j; positions p_k = sum_{j<k} F_j (p_0 = 0)
-    double zmu = 0.0, zF0 = 0.0, zsF = 0.0;
-    if (zero_lane) {
-        double tot = 0.0, pre = 0.0;
-        for (int cc = 0; cc < C; ++cc) {
-            if (cc == c) pre = tot;
-            tot += zbuf[cc];
-        }
-        zmu = tot / nz;
-        if (c == 0 && a.zero_mean_out) *a.zero_mean_out = tot * a.inv_ntot;
-        zF0 = (pre - s * zmu) * scale;  // flux entering the chunk, F_{s-1}
-        double run = zF0;
-        for (int k = s; k < e; ++k) {
-            run += (zraw(k) - zmu) * scale;
-            zsF += run;
-        }
-    }
-    __syncthreads();  // S2: Moebius slots consumed
+        // zero wavenumber: raw A(0,k) = Re S[k,0,0] is re-read (L1-resident)
+        // whenever needed, so the FP64 path keeps only scalars across barriers
+        auto zraw = [&](int k) -> double { return double(S[(size_t)k * plane].re); };
 
-    // ---- phase 2: local forward elimination ------------------------------
-    // Only v is kept per row: the products of u = 1 - v that carry the
-    // boundary values into the chunk (G_k = u_s..u_k forward, H_k = u_k..u_e
-    // backward) are rebuilt from it when needed.  Row nz-1 stores v = 1 (it
-    // does not couple to the row below) and its true u separately.
-    R vk[L];
-    R ulast = R(0);
-    {
-        Cx<R> Dp = {R(0), R(0)};
-        R Gp = R(1), vprev = vprev0;
+        const R sv = R(s_d);
+        const R mw = rcp_nr(R(1) + sv);  // Moebius matrix [[1, s], [1, 1+s]] / (1+s)
+        const R mws = sv * mw;
+        // Dirichlet walls: 2 more on the first and last pivot; row 0 maps any
+        // entering v to (s + 2)/(s + 3) instead of s/(1 + s)
+        const R dir2 = a.dirichlet_z ? R(2) : R(0);
+        const R mws0 = a.dirichlet_z ? (sv + R(2)) * rcp_nr(sv + R(3)) : mws;
+
+        // ---- phase 1: Moebius product of the chunk (v recurrence) -----------
+        // Rows past nz (only in the last chunk) are padding: zero right-hand
+        // side; v = 1 (u = 0) on row nz-1 decouples them from the real rows in
+        // the back substitution, and nothing reads the last chunk's products.
+        R p00 = R(1), p01 = R(0), p10 = R(0), p11 = R(1);
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             const int k = s + i;
-            // |pivot| = (excess over 1) + 1, except the last row (and nz = 1)
-            const R ex = (k == 0) ? sv + dir2 : sv + vprev;
-            const bool last = k >= nz - 1;
-            const R piv = (nz == 1) ? sv + dir2 + dir2 : (k == nz - 1 ? ex + dir2 : R(1) + ex);
-            const R u = rcp_nr(piv);
-            const R vnew = last ? R(1) : ex * u;
-            Dp = cscale(csub(Dp, d[i]), u);
-            Gp = u * Gp;
-            if (k == nz - 1) ulast = u;
-            vk[i] = vnew;
-            d[i] = Dp;
-            vprev = vnew;
+            const R a0 = (k == 0) ? R(0) : mw;  // row 0 ignores the entering v
+            const R b0 = (k == 0) ? mws0 : mws;
+            const R n00 = a0 * p00 + b0 * p10, n01 = a0 * p01 + b0 * p11;
+            const R n10 = a0 * p00 + p10, n11 = a0 * p01 + p11;
+            p00 = n00; p01 = n01; p10 = n10; p11 = n11;
         }
-        slot[0] = Dp.re; slot[1] = Dp.im; slot[2] = Gp;
-    }
-    if (zero_lane) zbuf[C + c] = zsF;
-    __syncthreads();  // S3
+        R *slot = buf + (size_t)(c * W + w) * 4;
+        slot[0] = p00; slot[1] = p01; slot[2] = p10; slot[3] = p11;
+        if (zero_lane) {
+            double zsum = 0.0;
+            for (int k = s; k < e; ++k) zsum += zraw(k);
+            zbuf[c] = zsum;
+        }
+        __syncthreads();  // S1
 
-    {
-        Cx<R> dprev = {R(0), R(0)};
-        int cc = 0;
-        for (; cc + 4 <= c; cc += 4) {
-            R o[4][3];
+        // v entering the chunk: apply the preceding chunks' maps to v (all
+        // entries are >= 0 and the denominator is >= the numerator, so
+        // normalising by it each step is safe and keeps the scan bounded)
+        R vprev0 = R(0);
+        {
+            int cc = 0;
+            for (; cc + 4 <= c; cc += 4) {
+                R o[4][4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int e = 0; e < 3; ++e) o[u][e] = buf[(size_t)((cc + u) * W + w) * 4 + e];
+                    for (int e = 0; e < 4; ++e) o[u][e] = buf[(size_t)((cc + u) * W + w) * 4 + e];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                dprev = {o[u][0] + o[u][2] * dprev.re, o[u][1] + o[u][2] * dprev.im};
+                for (int u = 0; u < 4; ++u)
+                    vprev0 = (o[u][0] * vprev0 + o[u][1]) * rcp_nr(o[u][2] * vprev0 + o[u][3]);
+            }
+            for (; cc < c; ++cc) {
+                const R *o = buf + (size_t)(cc * W + w) * 4;
+                vprev0 = (o[0] * vprev0 + o[1]) * rcp_nr(o[2] * vprev0 + o[3]);
+            }
         }
-        for (; cc < c; ++cc) {
-            const R *o = buf + (size_t)(cc * W + w) * 4;
-            dprev = {o[0] + o[2] * dprev.re, o[1] + o[2] * dprev.im};
-        }
-        R Gr = R(1);
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-            Gr *= (s + i == nz - 1) ? ulast : R(1) - vk[i];
-            d[i] = {d[i].re + Gr * dprev.re, d[i].im + Gr * dprev.im};
-        }
-    }
-    // ---- phase 3: local back substitution --------------------------------
-    Cx<R> Xn = {R(0), R(0)};
-    R Hn = R(1);
-#pragma unroll
-    for (int i = L - 1; i >= 0; --i) {
-        // p_k = d'_k + u_k p_{k+1} written as d'_k + (p_{k+1} - v_k p_{k+1})
-        const Cx<R> X = {d[i].re + (Xn.re - vk[i] * Xn.re), d[i].im + (Xn.im - vk[i] * Xn.im)};
-        d[i] = X;
-        Xn = X;
-        Hn *= R(1) - vk[i];
-    }
-    double zP0 = 0.0, zsx = 0.0;
-    if (zero_lane) {
-        for (int cc = 0; cc < c; ++cc) zP0 += zbuf[C + cc];  // p_s
-        double run = zF0, xk = zP0;
-        for (int k = s; k < e; ++k) {
-            zsx += xk;
-            run += (zraw(k) - zmu) * scale;
-            xk += run;
-        }
-    }
-    __syncthreads();  // S4: slots consumed
-    slot[0] = Xn.re; slot[1] = Xn.im; slot[2] = Hn;
-    if (zero_lane) zbuf[2 * C + c] = zsx;
-    __syncthreads();  // S5
 
-    {
-        Cx<R> y = {R(0), R(0)};
-        int cc = C - 1;
-        for (; cc - 4 >= c; cc -= 4) {
-            R o[4][3];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int e = 0; e < 3; ++e) o[u][e] = buf[(size_t)((cc - u) * W + w) * 4 + e];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) y = {o[u][0] + o[u][2] * y.re, o[u][1] + o[u][2] * y.im};
+        // zero wavenumber, FP64: g = (raw - mean raw) * scale; face fluxes
+        // F_k = sum_{j<=k} g_j; positions p_k = sum_{j<k} F_j (p_0 = 0)
+        double zmu = 0.0, zF0 = 0.0, zsF = 0.0;
+        if (zero_lane) {
+            double tot = 0.0, pre = 0.0;
+            for (int cc = 0; cc < C; ++cc) {
+                if (cc == c) pre = tot;
+                tot += zbuf[cc];
+            }
+            zmu = tot / nz;
+            if (c == 0 && a.zero_mean_out) *a.zero_mean_out = tot * a.inv_ntot;
+            zF0 = (pre - s * zmu) * scale;  // flux entering the chunk, F_{s-1}
+            double run = zF0;
+            for (int k = s; k < e; ++k) {
+                run += (zraw(k) - zmu) * scale;
+                zsF += run;
+            }
         }
-        for (; cc > c; --cc) {
-            const R *o = buf + (size_t)(cc * W + w) * 4;
-            y = {o[0] + o[2] * y.re, o[1] + o[2] * y.im};
+        __syncthreads();  // S2: Moebius slots consumed
+
+        // ---- phase 2: local forward elimination ------------------------------
+        // Only v is kept per row: the products of u = 1 - v that carry the
+        // boundary values into the chunk (G_k = u_s..u_k forward, H_k = u_k..u_e
+        // backward) are rebuilt from it when needed.  Row nz-1 stores v = 1 (it
+        // does not couple to the row below) and its true u separately.
+        R vk[L];
+        R ulast = R(0);
+        {
+            Cx<R> Dp = {R(0), R(0)};
+            R Gp = R(1), vprev = vprev0;
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                const int k = s + i;
+                // |pivot| = (excess over 1) + 1, except the last row (and nz = 1)
+                const R ex = (k == 0) ? sv + dir2 : sv + vprev;
+                const bool last = k >= nz - 1;
+                const R piv = (nz == 1) ? sv + dir2 + dir2 : (k == nz - 1 ? ex + dir2 : R(1) + ex);
+                const R u = rcp_nr(piv);
+                const R vnew = last ? R(1) : ex * u;
+                Dp = cscale(csub(Dp, d[i]), u);
+                Gp = u * Gp;
+                if (k == nz - 1) ulast = u;
+                vk[i] = vnew;
+                d[i] = Dp;
+                vprev = vnew;
+            }
+            slot[0] = Dp.re; slot[1] = Dp.im; slot[2] = Gp;
         }
-        R Hr = R(1);
+        if (zero_lane) zbuf[C + c] = zsF;
+        __syncthreads();  // S3
+
+        {
+            Cx<R> dprev = {R(0), R(0)};
+            int cc = 0;
+            for (; cc + 4 <= c; cc += 4) {
+                R o[4][3];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) o[u][e] = buf[(size_t)((cc + u) * W + w) * 4 + e];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    dprev = {o[u][0] + o[u][2] * dprev.re, o[u][1] + o[u][2] * dprev.im};
+            }
+            for (; cc < c; ++cc) {
+                const R *o = buf + (size_t)(cc * W + w) * 4;
+                dprev = {o[0] + o[2] * dprev.re, o[1] + o[2] * dprev.im};
+            }
+            R Gr = R(1);
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                Gr *= (s + i == nz - 1) ? ulast : R(1) - vk[i];
+                d[i] = {d[i].re + Gr * dprev.re, d[i].im + Gr * dprev.im};
+            }
+        }
+        // ---- phase 3: local back substitution --------------------------------
+        Cx<R> Xn = {R(0), R(0)};
+        R Hn = R(1);
 #pragma unroll
         for (int i = L - 1; i >= 0; --i) {
-            Hr *= R(1) - vk[i];
-            d[i] = {d[i].re + Hr * y.re, d[i].im + Hr * y.im};
+            // p_k = d'_k + u_k p_{k+1} written as d'_k + (p_{k+1} - v_k p_{k+1})
+            const Cx<R> X = {d[i].re + (Xn.re - vk[i] * Xn.re), d[i].im + (Xn.im - vk[i] * Xn.im)};
+            d[i] = X;
+            Xn = X;
+            Hn *= R(1) - vk[i];
         }
-    }
-    if (zero_lane) {
-        double tot = 0.0;
-        for (int cc = 0; cc < C; ++cc) tot += zbuf[2 * C + cc];
-        const double mean = tot / nz;
-        double run = zF0, xk = zP0;
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-            const int k = s + i;
-            if (k < nz) {
-                d[i] = {R(xk - mean), R(0)};
+        double zP0 = 0.0, zsx = 0.0;
+        if (zero_lane) {
+            for (int cc = 0; cc < c; ++cc) zP0 += zbuf[C + cc];  // p_s
+            double run = zF0, xk = zP0;
+            for (int k = s; k < e; ++k) {
+                zsx += xk;
                 run += (zraw(k) - zmu) * scale;
                 xk += run;
             }
         }
-    }
-    __syncthreads();  // S6: every zero-lane re-read of column (0,0) is done
+        __syncthreads();  // S4: slots consumed
+        slot[0] = Xn.re; slot[1] = Xn.im; slot[2] = Hn;
+        if (zero_lane) zbuf[2 * C + c] = zsx;
+        __syncthreads();  // S5
 
-    // ---- store ------------------------------------------------------------
-    if (!special) {
-        if (active) {
-            PK_GLOBAL Cx<R> *col = S + (size_t)s * plane + q;
+        {
+            Cx<R> y = {R(0), R(0)};
+            int cc = C - 1;
+            for (; cc - 4 >= c; cc -= 4) {
+                R o[4][3];
 #pragma unroll
-            for (int i = 0; i < L; ++i)
-                if (s + i < nz) col[(size_t)i * plane] = d[i];
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) o[u][e] = buf[(size_t)((cc - u) * W + w) * 4 + e];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) y = {o[u][0] + o[u][2] * y.re, o[u][1] + o[u][2] * y.im};
+            }
+            for (; cc > c; --cc) {
+                const R *o = buf + (size_t)(cc * W + w) * 4;
+                y = {o[0] + o[2] * y.re, o[1] + o[2] * y.im};
+            }
+            R Hr = R(1);
+#pragma unroll
+            for (int i = L - 1; i >= 0; --i) {
+                Hr *= R(1) - vk[i];
+                d[i] = {d[i].re + Hr * y.re, d[i].im + Hr * y.im};
+            }
         }
-    } else {
-        // the lanes of parts A and B of one (m, ky pair) are W/2 apart:
-        // exchange and recombine
-        constexpr int H = W / 2 > 0 ? W / 2 : 1;
-        PK_GLOBAL Cx<R> *col =
-            S + (size_t)s * plane + (size_t)(part == 0 ? ky : kyn) * M + (active ? mm : 0);
+        if (zero_lane) {
+            double tot = 0.0;
+            for (int cc = 0; cc < C; ++cc) tot += zbuf[2 * C + cc];
+            const double mean = tot / nz;
+            double run = zF0, xk = zP0;
 #pragma unroll
-        for (int i = 0; i < L; ++i) {
-            const R ore = __shfl_xor(d[i].re, H, 64);
-            const R oim = __shfl_xor(d[i].im, H, 64);
-            const int k = s + i;
-            if (active && k < nz) {
-                if (part == 0) {
-                    // column ky: A + iB
-                    col[(size_t)i * plane] = {d[i].re - oim, d[i].im + ore};
-                } else if (kyn != ky) {
-                    // column -ky: conj(A) + i conj(B)
-                    col[(size_t)i * plane] = {ore + d[i].im, -oim + d[i].re};
+            for (int i = 0; i < L; ++i) {
+                const int k = s + i;
+                if (k < nz) {
+                    d[i] = {R(xk - mean), R(0)};
+                    run += (zraw(k) - zmu) * scale;
+                    xk += run;
+                }
+            }
+        }
+        __syncthreads();  // S6: every zero-lane re-read of column (0,0) is done
+
+        // ---- store ------------------------------------------------------------
+        if (!special) {
+            if (active) {
+                PK_GLOBAL Cx<R> *col = S + (size_t)s * plane + q;
+#pragma unroll
+                for (int i = 0; i < L; ++i)
+                    if (s + i < nz) col[(size_t)i * plane] = d[i];
+            }
+        } else {
+            // the lanes of parts A and B of one (m, ky pair) are W/2 apart:
+            // exchange and recombine
+            constexpr int H = W / 2 > 0 ? W / 2 : 1;
+            PK_GLOBAL Cx<R> *col =
+                S + (size_t)s * plane + (size_t)(part == 0 ? ky : kyn) * M + (active ? mm : 0);
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                const R ore = __shfl_xor(d[i].re, H, 64);
+                const R oim = __shfl_xor(d[i].im, H, 64);
+                const int k = s + i;
+                if (active && k < nz) {
+                    if (part == 0) {
+                        // column ky: A + iB
+                        col[(size_t)i * plane] = {d[i].re - oim, d[i].im + ore};
+                    } else if (kyn != ky) {
+                        // column -ky: conj(A) + i conj(B)
+                        col[(size_t)i * plane] = {ore + d[i].im, -oim + d[i].re};
+                    }
                 }
             }
         }
     }
+};
+
+template <int W> constexpr size_t zw_lds_bytes(int C)
+{
+    return ((C * W * 4 * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double);
+}
+
+template <int L, int W, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
+{
+    extern __shared__ double smem_d[];
+    ZWBody<L, W>::run(a0, VBlock{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x}, C, nspecial,
+                      smem_d);
 }
 
 // Walls along x and y, one real system per lane.  Column (m, ky) of the
@@ -666,8 +682,151 @@ static int run_zw(const ZArgs &a, hipStream_t s)
     return (int)hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Work list: the z passes of problems of different shapes and z boundaries in
+// one launch.  Classes: 1 walls with nz <= 64 (8-row chunks, 32 columns per
+// workgroup), 2 walls with nz <= 256 (16-row chunks, 128-byte row runs), and
+// 1000 + N periodic columns of length N (the FFT body of k_zperiodic.hip).
+// Boxes with walls along both x and y keep their own launch.
+// ---------------------------------------------------------------------------
+#include "zper_body.hpp"
+
+constexpr int ZL_NT = 256;
+constexpr int ZL_W2 = 128 / (int)sizeof(Cx<R>);
+#define PK_ZL_LENGTHS(X) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+
+// SHORT: only columns of 64 rows or fewer (classes 1 and 1000 + N, N <= 64),
+// which need far fewer registers than the 16-row chunks of class 2
+template <bool SHORT>
+__global__ __launch_bounds__(ZL_NT) void k_z_list(ListArgs<ZArgs>)
+{
+    extern __shared__ double smem_d[];
+    const PK_KARG ListArgs<ZArgs> *L = list_args<ZArgs>();
+    int g;
+    VBlock vb;
+    if (!list_find(L, g, vb)) return;
+    const ZArgs arg = L->a[g];
+    switch (L->cls[g]) {
+    case 1: ZWBody<8, 32>::run(arg, vb, L->aux[g], L->aux2[g], smem_d); break;
+    case 2:
+        if constexpr (!SHORT) ZWBody<16, ZL_W2>::run(arg, vb, L->aux[g], L->aux2[g], smem_d);
+        break;
+#define PK_ZL_CASE(N)                                                                         \
+    case 1000 + N:                                                                            \
+        if constexpr (ZPCfg<N>::NT <= ZL_NT && (!SHORT || N <= 64))                           \
+            ZPBody<N>::run(arg, vb, L->aux2[g], (char *)smem_d);                              \
+        break;
+        PK_ZL_LENGTHS(PK_ZL_CASE)
+#undef PK_ZL_CASE
+    default: break;
+    }
+}
+
+// class, threads, blocks per problem, chunks, special blocks and LDS of a z
+// record in the list kernel; false when it has no class there
+static bool z_list_class(const ZArgs &a, int &cls, int &nt, int &gx, int &C, int &nspecial,
+                         size_t &lds)
+{
+    if (!a.periodic_z) {
+        if (a.xwall && a.ywall) return false;
+        int L, W;
+        if (a.nz <= 64) {
+            cls = 1; L = 8; W = 32;
+        } else if (a.nz <= 256) {
+            cls = 2; L = 16; W = ZL_W2;
+        } else {
+            return false;
+        }
+        C = (a.nz + L - 1) / L;
+        nt = W * C;
+        if (nt > ZL_NT) return false;
+        const int npairs = a.ywall ? a.ny : a.ny / 2 + 1;
+        const int H = W / 2 > 0 ? W / 2 : 1;
+        nspecial = a.xwall ? npairs * ((a.M + H - 1) / H) : (npairs + H - 1) / H;
+        const int nmain = a.xwall ? 0 : (a.ny * a.M + W - 1) / W;
+        gx = nspecial + nmain;
+        lds = cls == 1 ? zw_lds_bytes<32>(C) : zw_lds_bytes<ZL_W2>(C);
+        return true;
+    }
+    switch (a.nz) {
+#define PK_ZL_INFO(N)                                                                   \
+    case N: {                                                                           \
+        using Cf = ZPCfg<N>;                                                            \
+        if (Cf::NT > ZL_NT) return false;                                               \
+        constexpr int NB = Cf::NB, NP = Cf::NB / 2;                                     \
+        const int npairs = a.ny / 2 + 1;                                                \
+        int nmain = (a.ny * a.M + NB - 1) / NB;                                         \
+        if (a.xwall) {                                                                  \
+            nspecial = a.ywall ? a.ny * ((a.M + NB - 1) / NB) : npairs * ((a.M + NP - 1) / NP); \
+            nmain = 0;                                                                  \
+        } else {                                                                        \
+            nspecial = a.ywall ? (a.ny + NB - 1) / NB : (npairs + NP - 1) / NP;         \
+        }                                                                               \
+        cls = 1000 + N;                                                                 \
+        nt = Cf::NT;                                                                    \
+        gx = nspecial + nmain;                                                          \
+        C = 0;                                                                          \
+        lds = ZPBody<N>::LDS_BYTES;                                                     \
+        return true;                                                                    \
+    }
+        PK_ZL_LENGTHS(PK_ZL_INFO)
+#undef PK_ZL_INFO
+    default: return false;
+    }
+}
+
 }  // namespace PK_NS
 using namespace PK_NS;
+
+int PK_SUFFIX(launch_z_walls)(const ZArgs &a, hipStream_t s);
+int PK_SUFFIX(launch_z_periodic)(const ZArgs &a, hipStream_t s);
+
+int PK_SUFFIX(launch_z_list)(const ZArgs *a, int n, hipStream_t s)
+{
+    ListArgs<ZArgs> L{};
+    size_t lds = 0;
+    int total = 0;
+    bool shorts = true;  // every segment has columns of 64 rows or fewer
+    auto flush = [&]() -> int {
+        if (L.nseg == 0) return 0;
+        L.start[L.nseg] = total;
+        if (shorts)
+            hipLaunchKernelGGL(k_z_list<true>, dim3(total), dim3(ZL_NT), lds, s, L);
+        else
+            hipLaunchKernelGGL(k_z_list<false>, dim3(total), dim3(ZL_NT), lds, s, L);
+        L.nseg = 0;
+        total = 0;
+        lds = 0;
+        shorts = true;
+        return (int)hipGetLastError();
+    };
+    for (int i = 0; i < n; ++i) {
+        int cls = 0, nt = 0, gx = 0, C = 0, nsp = 0;
+        size_t b = 0;
+        if (!z_list_class(a[i], cls, nt, gx, C, nsp, b)) {
+            const int e = a[i].periodic_z ? PK_SUFFIX(launch_z_periodic)(a[i], s)
+                                          : PK_SUFFIX(launch_z_walls)(a[i], s);
+            if (e) return e;
+            continue;
+        }
+        const int g = L.nseg++;
+        L.start[g] = total;
+        L.gx[g] = gx;
+        L.cls[g] = cls;
+        L.nt[g] = nt;
+        L.aux[g] = C;
+        L.aux2[g] = nsp;
+        L.a[g] = a[i];
+        shorts = shorts && a[i].nz <= 64;
+        total += gx * (a[i].batch ? a[i].nbatch : 1);
+        lds = lds > b ? lds : b;
+        if (L.nseg == LIST_MAX_SEG) {
+            const int e = flush();
+            if (e) return e;
+        }
+    }
+    return flush();
+}
 
 int PK_SUFFIX(launch_z_walls)(const ZArgs &a, hipStream_t s)
 {

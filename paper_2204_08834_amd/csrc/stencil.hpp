@@ -428,7 +428,8 @@ struct CorrMarch : MarchIdx<M, TJ, NT> {
 
 // sum three doubles over the workgroup; thread 0 gets the totals (the
 // caller's `sh` holds 3 doubles per wavefront; the call syncs)
-__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *sh)
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *sh,
+                                           int nthreads = 0)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -444,7 +445,7 @@ __device__ __forceinline__ void block_sum3(double &a, double &b, double &c, doub
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int nw = (blockDim.x + 63) >> 6;
+        const int nw = ((nthreads > 0 ? nthreads : (int)blockDim.x) + 63) >> 6;
         a = 0.0;
         b = 0.0;
         c = 0.0;

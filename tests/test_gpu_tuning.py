@@ -103,7 +103,9 @@ def test_batch_autotune_and_describe():
     bp.autotune()
     d = bp.describe()
     print(d, flush=True)
-    assert d.count("\n") == 2 and "problems=2" in d and "problems=1" in d
+    assert d.count("\n") == 3 and "problems=2" in d and "problems=1" in d
+    # the autotuner also chose the batch schedule of each loop driver
+    assert d.startswith("schedule=") and "host loop:" in d and "device loops:" in d
     rc, stats = bp.solve(rhs, outs)
     assert rc == 0 and all(s["rel_residual"] <= 1e-10 for s in stats)
     bp.close()
