@@ -46,6 +46,8 @@ MUTATIONS = {
     "lap_dir_y": 15,
     "res_no_mean": 16,
     "res_mean_dir": 17,
+    "h_face": 18,
+    "h_mean": 19,
 }
 
 _lib = None
@@ -100,6 +102,15 @@ def _load():
     lib.oracle_correct_bc.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [
         ctypes.c_int] * 3 + [dp, ctypes.c_double, dp, dp, dp]
     lib.oracle_correct_bc.restype = ctypes.c_int
+    lib.oracle_solve_bc_h.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 2 + [dp] + [
+        ctypes.c_int] * 3 + [dp, dp, dp, dp, ctypes.c_int]
+    lib.oracle_solve_bc_h.restype = ctypes.c_int
+    lib.oracle_laplacian_bc_h.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 2 + [dp] + [
+        ctypes.c_int] * 3 + [dp, dp, ctypes.c_int]
+    lib.oracle_laplacian_bc_h.restype = ctypes.c_int
+    lib.oracle_residual_bc_h.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 2 + [dp] + [
+        ctypes.c_int] * 3 + [dp, dp, dp, dp, dp, ctypes.c_int]
+    lib.oracle_residual_bc_h.restype = ctypes.c_int
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     _lib = lib
@@ -117,10 +128,19 @@ def _check(f):
     return f
 
 
+def _cells(dz_cells, nz):
+    h = np.ascontiguousarray(dz_cells, dtype=np.float64)
+    if h.shape != (nz,):
+        raise ValueError(f"dz_cells must hold nz = {nz} cell thicknesses")
+    return h
+
+
 def solve(f, dx, dy, dz, bc_z, mutation: int | str = 0, return_info: bool = False,
-          bc_x: int = PERIODIC, bc_y: int = PERIODIC):
+          bc_x: int = PERIODIC, bc_y: int = PERIODIC, dz_cells=None):
     """p with L p = f - mean(f), zero-mean, when no axis is Dirichlet; else
-    L p = f.  Boundaries per axis: PERIODIC (0), NEUMANN (1), DIRICHLET (2)."""
+    L p = f.  Boundaries per axis: PERIODIC (0), NEUMANN (1), DIRICHLET (2).
+    dz_cells: nz cell thicknesses of a z-stretched grid (walls in z; dz is
+    then unused): the mean and the gauge are volume-weighted."""
     lib = _load()
     f = _check(f)
     nz, ny, nx = f.shape
@@ -128,9 +148,15 @@ def solve(f, dx, dy, dz, bc_z, mutation: int | str = 0, return_info: bool = Fals
     mean = ctypes.c_double(0.0)
     mim = ctypes.c_double(0.0)
     mutation = _mutation(mutation)
-    rc = lib.oracle_solve_bc(nx, ny, nz, dx, dy, dz, int(bc_x), int(bc_y), int(bc_z),
-                             _ptr(f), _ptr(p), ctypes.byref(mean), ctypes.byref(mim),
-                             int(mutation))
+    if dz_cells is not None:
+        h = _cells(dz_cells, nz)
+        rc = lib.oracle_solve_bc_h(nx, ny, nz, dx, dy, _ptr(h), int(bc_x), int(bc_y), int(bc_z),
+                                   _ptr(f), _ptr(p), ctypes.byref(mean), ctypes.byref(mim),
+                                   int(mutation))
+    else:
+        rc = lib.oracle_solve_bc(nx, ny, nz, dx, dy, dz, int(bc_x), int(bc_y), int(bc_z),
+                                 _ptr(f), _ptr(p), ctypes.byref(mean), ctypes.byref(mim),
+                                 int(mutation))
     if rc != 0:
         raise RuntimeError(f"oracle_solve failed ({rc})")
     if return_info:
@@ -143,23 +169,30 @@ def _mutation(m):
 
 
 def laplacian(p, dx, dy, dz, bc_z, bc_x: int = PERIODIC, bc_y: int = PERIODIC,
-              mutation: int | str = 0):
-    """L p, the 7-point operator with the ghost rule of each axis."""
+              mutation: int | str = 0, dz_cells=None):
+    """L p, the 7-point operator with the ghost rule of each axis (with
+    dz_cells: the conservative z part on cells of those thicknesses)."""
     lib = _load()
     p = _check(p)
     nz, ny, nx = p.shape
     out = np.empty_like(p)
-    rc = lib.oracle_laplacian_bc_mut(nx, ny, nz, dx, dy, dz, int(bc_x), int(bc_y), int(bc_z),
-                                     _ptr(p), _ptr(out), _mutation(mutation))
+    if dz_cells is not None:
+        h = _cells(dz_cells, nz)
+        rc = lib.oracle_laplacian_bc_h(nx, ny, nz, dx, dy, _ptr(h), int(bc_x), int(bc_y),
+                                       int(bc_z), _ptr(p), _ptr(out), _mutation(mutation))
+    else:
+        rc = lib.oracle_laplacian_bc_mut(nx, ny, nz, dx, dy, dz, int(bc_x), int(bc_y), int(bc_z),
+                                         _ptr(p), _ptr(out), _mutation(mutation))
     if rc != 0:
         raise RuntimeError("oracle_laplacian failed")
     return out
 
 
 def residual(f, p, dx, dy, dz, bc_z, return_field: bool = False, bc_x: int = PERIODIC,
-             bc_y: int = PERIODIC, mutation: int | str = 0):
+             bc_y: int = PERIODIC, mutation: int | str = 0, dz_cells=None):
     """Relative residual ||(f - mean f) - L p||_2 / ||f - mean f||_2 (and Linf);
-    the mean is removed only when no axis is Dirichlet."""
+    the mean is removed only when no axis is Dirichlet (volume-weighted with
+    dz_cells)."""
     lib = _load()
     f = _check(f)
     p = _check(p)
@@ -167,9 +200,16 @@ def residual(f, p, dx, dy, dz, bc_z, return_field: bool = False, bc_x: int = PER
     r = np.empty_like(f) if return_field else None
     l2 = ctypes.c_double()
     li = ctypes.c_double()
-    rc = lib.oracle_residual_bc_mut(nx, ny, nz, dx, dy, dz, int(bc_x), int(bc_y), int(bc_z),
-                                    _ptr(f), _ptr(p), _ptr(r) if r is not None else None,
-                                    ctypes.byref(l2), ctypes.byref(li), _mutation(mutation))
+    if dz_cells is not None:
+        h = _cells(dz_cells, nz)
+        rc = lib.oracle_residual_bc_h(nx, ny, nz, dx, dy, _ptr(h), int(bc_x), int(bc_y),
+                                      int(bc_z), _ptr(f), _ptr(p),
+                                      _ptr(r) if r is not None else None, ctypes.byref(l2),
+                                      ctypes.byref(li), _mutation(mutation))
+    else:
+        rc = lib.oracle_residual_bc_mut(nx, ny, nz, dx, dy, dz, int(bc_x), int(bc_y), int(bc_z),
+                                        _ptr(f), _ptr(p), _ptr(r) if r is not None else None,
+                                        ctypes.byref(l2), ctypes.byref(li), _mutation(mutation))
     if rc != 0:
         raise RuntimeError("oracle_residual failed")
     if return_field:

@@ -80,6 +80,9 @@
 #define MUT_LAP_DIR_Y 15      /* Dirichlet y wall takes the mirrored (Neumann) ghost in L */
 #define MUT_RES_NO_MEAN 16    /* residual keeps the mean of f on a singular problem */
 #define MUT_RES_MEAN_DIR 17   /* residual removes the mean of f despite a Dirichlet wall */
+/* planted mistakes of the stretched-z solve */
+#define MUT_H_FACE 18         /* distance between cell centres k, k+1 taken as h[k] */
+#define MUT_H_MEAN 19         /* plain (unweighted) mean of f removed and of p as the gauge */
 
 static const double ORC_PI = 3.14159265358979323846264338327950288;
 
@@ -657,6 +660,225 @@ int oracle_correct(int nx, int ny, int nz, double dx, double dy, double dz, int 
 {
     return oracle_correct_bc(nx, ny, nz, dx, dy, dz, ORC_PERIODIC, ORC_PERIODIC, bc_z, psi, beta,
                              u, v, w);
+}
+
+/*
+ * Stretched z: walls in z and cell thicknesses h[0..nz-1] (nonuniform spacing
+ * along z, uniform dx, dy).  Extends the z-direction elimination of Section
+ * 3.3.1 to cells of different thickness; the paper's solver is described on
+ * a uniform grid, so the operator here is the conservative (finite-volume)
+ * reading of the same second-order stencil on the marker-and-cell grid:
+ *
+ *   (L_z p)_k = [ (p[k+1] - p[k]) / d[k+1/2] - (p[k] - p[k-1]) / d[k-1/2] ] / h[k],
+ *   d[k+1/2] = (h[k] + h[k+1]) / 2   (distance between the cell centres),
+ *
+ * with no flux through a Neumann wall and, at a Dirichlet wall, the flux
+ * (0 - p[0]) / (h[0]/2) to the zero value on the face (likewise at the top).
+ * With equal thicknesses this is the uniform 7-point operator (the ghost
+ * rules of the uniform case give the same wall rows).
+ *
+ * L is symmetric in the inner product weighted by the cell volumes, so the
+ * singular (all-Neumann / periodic) problem is solvable for f with zero
+ * volume-weighted mean: the solve removes mean_w(f) = sum h[k] f / sum h[k]
+ * (over all cells) and returns the p with zero volume-weighted mean.
+ */
+static double mean_weighted(int nx, int ny, int nz, const double *h, const double *f,
+                            int mutation)
+{
+    double num = 0.0, den = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        const double w = (mutation == MUT_H_MEAN) ? 1.0 : h[k];
+        num += w * pairwise_sum(f + (long)k * nx * ny, (long)nx * ny);
+        den += w * (double)nx * ny;
+    }
+    return num / den;
+}
+
+static double centre_distance(const double *h, int k, int mutation)
+{
+    /* between the centres of cells k and k+1 */
+    return (mutation == MUT_H_FACE) ? h[k] : 0.5 * (h[k] + h[k + 1]);
+}
+
+/* One (mx,my) column: the rows of L_z + lam, multiplied by h[k] (symmetric
+ * form), Gauss elimination without pivoting (Thomas).  Singular column: p[0]
+ * pinned to 0, the first row dropped, the volume-weighted mean removed. */
+static void zsolve_walls_h(int nz, const double *h, double lam, int singular,
+                           double complex *g, double *lo, double *di, double *up, double *cp,
+                           int bc_z, int mutation)
+{
+    for (int k = 0; k < nz; ++k) {
+        lo[k] = (k > 0) ? 1.0 / centre_distance(h, k - 1, mutation) : 0.0;
+        up[k] = (k < nz - 1) ? 1.0 / centre_distance(h, k, mutation) : 0.0;
+        di[k] = lam * h[k] - lo[k] - up[k];
+        if (bc_z == ORC_DIRICHLET) {
+            if (k == 0) di[k] -= 2.0 / h[0];
+            if (k == nz - 1) di[k] -= 2.0 / h[nz - 1];
+        }
+        g[k] *= h[k];
+    }
+    if (!singular) {
+        thomas(nz, lo, di, up, g, cp);
+        return;
+    }
+    if (nz == 1) { g[0] = 0.0; return; }
+    thomas(nz - 1, lo + 1, di + 1, up + 1, g + 1, cp);
+    g[0] = 0.0;
+    double complex s = 0.0;
+    double w = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        const double wk = (mutation == MUT_H_MEAN) ? 1.0 : h[k];
+        s += wk * g[k];
+        w += wk;
+    }
+    s /= w;
+    for (int k = 0; k < nz; ++k) g[k] -= s;
+}
+
+/*
+ * oracle_solve_bc_h: the solve on a z-stretched grid (bc_z Neumann or
+ * Dirichlet walls; x and y as in oracle_solve_bc).  h: nz positive cell
+ * thicknesses.  Singular problems (no Dirichlet axis): f minus its
+ * volume-weighted mean (reported in rhs_mean), p with zero volume-weighted
+ * mean.
+ */
+int oracle_solve_bc_h(int nx, int ny, int nz, double dx, double dy, const double *h, int bc_x,
+                      int bc_y, int bc_z, const double *f, double *p, double *rhs_mean,
+                      double *max_imag, int mutation)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !(dx > 0) || !(dy > 0) || !h || !f || !p) return -1;
+    if (bc_x < 0 || bc_x > 2 || bc_y < 0 || bc_y > 2) return -1;
+    if (bc_z != ORC_NEUMANN && bc_z != ORC_DIRICHLET) return -1;
+    for (int k = 0; k < nz; ++k)
+        if (!(h[k] > 0)) return -1;
+    const int singular_problem =
+        bc_x != ORC_DIRICHLET && bc_y != ORC_DIRICHLET && bc_z != ORC_DIRICHLET;
+    long n = (long)nx * ny * nz, plane = (long)nx * ny;
+    double complex *a = malloc(sizeof(double complex) * n);
+    if (!a) return -1;
+
+    double mean = singular_problem ? mean_weighted(nx, ny, nz, h, f, mutation) : 0.0;
+    if (rhs_mean) *rhs_mean = mean;
+    for (long t = 0; t < n; ++t) a[t] = f[t] - mean;
+
+    if (bc_x == ORC_PERIODIC)
+        dft_axis(a, nx, ny, nz, 0, -1, 1.0, mutation);
+    else
+        wall_axis(a, nx, ny, nz, 0, bc_x, 0, mutation);
+    if (bc_y == ORC_PERIODIC)
+        dft_axis(a, nx, ny, nz, 1, -1, 1.0, mutation);
+    else
+        wall_axis(a, nx, ny, nz, 1, bc_y, 0, mutation);
+
+#pragma omp parallel
+    {
+        double complex *g = malloc(sizeof(double complex) * nz);
+        double *lo = malloc(sizeof(double) * nz), *di = malloc(sizeof(double) * nz);
+        double *up = malloc(sizeof(double) * nz), *cp = malloc(sizeof(double) * nz);
+#pragma omp for schedule(static)
+        for (long q = 0; q < plane; ++q) {
+            int mx = (int)(q % nx), my = (int)(q / nx);
+            double lam = eig_axis(bc_x, mx, nx, dx, mutation) + eig_axis(bc_y, my, ny, dy, mutation);
+            int singular = singular_problem && mx == 0 && my == 0;
+            for (int k = 0; k < nz; ++k) g[k] = a[(long)k * plane + q];
+            zsolve_walls_h(nz, h, lam, singular, g, lo, di, up, cp, bc_z, mutation);
+            for (int k = 0; k < nz; ++k) a[(long)k * plane + q] = g[k];
+        }
+        free(g); free(lo); free(di); free(up); free(cp);
+    }
+
+    if (bc_y == ORC_PERIODIC)
+        dft_axis(a, nx, ny, nz, 1, +1, 1.0 / ny, mutation);
+    else
+        wall_axis(a, nx, ny, nz, 1, bc_y, 1, mutation);
+    if (bc_x == ORC_PERIODIC)
+        dft_axis(a, nx, ny, nz, 0, +1, 1.0 / nx, mutation);
+    else
+        wall_axis(a, nx, ny, nz, 0, bc_x, 1, mutation);
+
+    double mre = 0.0, mim = 0.0;
+    for (long t = 0; t < n; ++t) {
+        p[t] = creal(a[t]);
+        double re = fabs(creal(a[t])), im = fabs(cimag(a[t]));
+        if (re > mre) mre = re;
+        if (im > mim) mim = im;
+    }
+    if (max_imag) *max_imag = (mre > 0) ? mim / mre : mim;
+    free(a);
+    if (singular_problem) {
+        double pm = mean_weighted(nx, ny, nz, h, p, mutation);
+        for (long t = 0; t < n; ++t) p[t] -= pm;
+    }
+    return 0;
+}
+
+/* out = L p on the z-stretched grid (x and y as in oracle_laplacian_bc) */
+int oracle_laplacian_bc_h(int nx, int ny, int nz, double dx, double dy, const double *h,
+                          int bc_x, int bc_y, int bc_z, const double *p, double *out,
+                          int mutation)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || !h || !p || !out) return -1;
+    if (bc_z != ORC_NEUMANN && bc_z != ORC_DIRICHLET) return -1;
+    double ax = 1.0 / (dx * dx), ay = 1.0 / (dy * dy);
+#pragma omp parallel for schedule(static)
+    for (long kk = 0; kk < (long)nz * ny; ++kk) {
+        int k = (int)(kk / ny), j = (int)(kk % ny);
+        double fjm, fjp;
+        int jm = nbr(j, -1, ny, bc_y, &fjm), jp = nbr(j, +1, ny, bc_y, &fjp);
+        for (int i = 0; i < nx; ++i) {
+            double fim, fip;
+            int im = nbr(i, -1, nx, bc_x, &fim), ip = nbr(i, +1, nx, bc_x, &fip);
+#define P(K, J, I) p[((long)(K) * ny + (J)) * nx + (I)]
+            double c = P(k, j, i);
+            double flux_up = 0.0, flux_dn = 0.0; /* through the top and bottom faces */
+            if (k < nz - 1)
+                flux_up = (P(k + 1, j, i) - c) / centre_distance(h, k, mutation);
+            else if (bc_z == ORC_DIRICHLET)
+                flux_up = (0.0 - c) / (0.5 * h[k]);
+            if (k > 0)
+                flux_dn = (c - P(k - 1, j, i)) / centre_distance(h, k - 1, mutation);
+            else if (bc_z == ORC_DIRICHLET)
+                flux_dn = (c - 0.0) / (0.5 * h[k]);
+            double v = ax * (fip * P(k, j, ip) - 2.0 * c + fim * P(k, j, im)) +
+                       ay * (fjp * P(k, jp, i) - 2.0 * c + fjm * P(k, jm, i)) +
+                       (flux_up - flux_dn) / h[k];
+#undef P
+            out[((long)k * ny + j) * nx + i] = v;
+        }
+    }
+    return 0;
+}
+
+/* r = (f - mean_w(f)) - L p on the z-stretched grid (the weighted mean
+ * removed only when no axis is Dirichlet), relative L2 and Linf norms */
+int oracle_residual_bc_h(int nx, int ny, int nz, double dx, double dy, const double *h,
+                         int bc_x, int bc_y, int bc_z, const double *f, const double *p,
+                         double *r, double *rel_l2, double *rel_linf, int mutation)
+{
+    long n = (long)nx * ny * nz;
+    double *lp = malloc(sizeof(double) * n);
+    if (!lp) return -1;
+    if (oracle_laplacian_bc_h(nx, ny, nz, dx, dy, h, bc_x, bc_y, bc_z, p, lp, mutation)) {
+        free(lp);
+        return -1;
+    }
+    int singular_problem =
+        bc_x != ORC_DIRICHLET && bc_y != ORC_DIRICHLET && bc_z != ORC_DIRICHLET;
+    double mean = singular_problem ? mean_weighted(nx, ny, nz, h, f, mutation) : 0.0;
+    double s2r = 0, s2f = 0, mr = 0, mf = 0;
+    for (long t = 0; t < n; ++t) {
+        double fb = f[t] - mean;
+        double rv = fb - lp[t];
+        if (r) r[t] = rv;
+        s2r += rv * rv;
+        s2f += fb * fb;
+        if (fabs(rv) > mr) mr = fabs(rv);
+        if (fabs(fb) > mf) mf = fabs(fb);
+    }
+    free(lp);
+    if (rel_l2) *rel_l2 = (s2f > 0) ? sqrt(s2r / s2f) : sqrt(s2r);
+    if (rel_linf) *rel_linf = (mf > 0) ? mr / mf : mr;
+    return 0;
 }
 
 int oracle_num_threads(void)
