@@ -75,6 +75,19 @@ typedef enum {
 } poisson_precision_t;
 
 /*
+ * Stretched z (dz_cells != NULL): walls in z (bc_z NEUMANN or DIRICHLET), cell
+ * k of thickness dz_cells[k] > 0 (dz is then unused, but must still be a
+ * valid spacing).  This extends the elimination along z of Section 3.3.1 to
+ * cells of different thickness: the z part of the operator is
+ *   [ (p[k+1] - p[k]) / d[k+1/2] - (p[k] - p[k-1]) / d[k-1/2] ] / dz_cells[k],
+ *   d[k+1/2] = (dz_cells[k] + dz_cells[k+1]) / 2,
+ * no flux through a Neumann wall, flux (0 - p[0]) / (dz_cells[0]/2) at a
+ * Dirichlet wall (likewise at the top); equal thicknesses give the uniform
+ * operator.  The singular problem removes the volume-weighted mean of f
+ * (reported as rhs_mean) and returns the p of zero volume-weighted mean.
+ * The plan copies the array; the caller may free it after plan creation.
+ * poisson_project does not take stretched plans (UNSUPPORTED).
+ *
  * Problem descriptor.
  *   nx      : even, nx/2 of the form 2^a or 3*2^a, 2 <= nx <= 2048.
  *   ny      : 2^a or 3*2^a, 1 <= ny <= 2048.
@@ -100,6 +113,7 @@ typedef struct {
     int precision;
     double rtol;
     int max_refine;
+    const double *dz_cells; /* NULL (uniform dz), or a host array of nz cell thicknesses */
 } poisson_desc_t;
 
 /*
@@ -119,7 +133,7 @@ typedef struct {
 typedef struct poisson_plan_s *poisson_plan;
 
 /* Fill a descriptor with defaults (periodic x,y,z, FP64, rtol 1e-10,
- * max_refine 8, unit spacing, sizes 0).  Host only. */
+ * max_refine 8, unit spacing, uniform z, sizes 0).  Host only. */
 int poisson_desc_init(poisson_desc_t *d);
 
 /* Check a descriptor without touching the GPU.  Host only. */

@@ -115,6 +115,39 @@ std::vector<double> quarter_table(int n)
     return tw;
 }
 
+// Rows of the z system of a stretched grid (cells of thickness h[k]), in the
+// form of the z solve (rows multiplied by h[k]), 8 doubles per row:
+// {a_k, c_k, h_k, D_k, d_k+1/2, sum_{j<k} h_j, 0, 0}: a_k and c_k the
+// conductances 1/d of the faces below and above (d the distance of the two
+// cell centres; 0 at a wall), D_k = 2/h_k at a Dirichlet wall (the value is
+// zero on the face, half a cell away), d_k+1/2 the centre distance above
+// (0 on the last row).  16 padding rows {0, 0, 0, 1, 0, sum h, 0, 0} follow
+// (the z solve's last chunk runs past nz).
+std::vector<double> zrow_table(const std::vector<double> &h, int bc_z)
+{
+    const int nz = (int)h.size();
+    std::vector<double> t(8 * (size_t)(nz + 16), 0.0);
+    double pre = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        double *r = &t[8 * (size_t)k];
+        r[0] = k > 0 ? 1.0 / (0.5 * (h[k - 1] + h[k])) : 0.0;
+        r[1] = k < nz - 1 ? 1.0 / (0.5 * (h[k] + h[k + 1])) : 0.0;
+        r[2] = h[k];
+        if (bc_z == POISSON_BC_DIRICHLET) {
+            if (k == 0) r[3] += 2.0 / h[0];
+            if (k == nz - 1) r[3] += 2.0 / h[nz - 1];
+        }
+        r[4] = k < nz - 1 ? 0.5 * (h[k] + h[k + 1]) : 0.0;
+        r[5] = pre;
+        pre += h[k];
+    }
+    for (int k = nz; k < nz + 16; ++k) {
+        t[8 * (size_t)k + 3] = 1.0;
+        t[8 * (size_t)k + 5] = pre;
+    }
+    return t;
+}
+
 // ---------------------------------------------------------------------------
 // device buffers
 // ---------------------------------------------------------------------------
@@ -345,11 +378,17 @@ struct Tables {
     std::shared_ptr<DevBuf> twy4[2];                 // walls along y: exp(-i pi k/(2 ny))
     std::shared_ptr<DevBuf> twx4[2];                 // walls along x: exp(-i pi k/(2 nx))
     std::shared_ptr<DevBuf> lamx, lamy, lamz;
+    std::shared_ptr<DevBuf> zrow;  // stretched z: the rows of the z system
+    std::shared_ptr<DevBuf> hz;    // stretched z: thickness of each plane
+    std::shared_ptr<DevBuf> zc;    // stretched z: residual coefficients of each plane
 };
 
 // problems with identical descriptors: one set of tables, one launch per pass
 struct Group {
-    poisson_desc_t d;
+    poisson_desc_t d;      // dz_cells is cleared: the thicknesses live in hz
+    std::vector<double> hz;  // stretched z: the cell thicknesses (empty: uniform)
+    double hsum = 0.0;
+    double mean_div = 0.0;   // sums of f and p over this give the (volume-weighted) means
     int M = 0;
     long long N = 0;
     Tables tab;
@@ -497,6 +536,13 @@ int validate(const poisson_desc_t *d)
     }
     const long long n = (long long)d->nx * d->ny * d->nz;
     if (n > (1LL << 31)) return POISSON_ERR_UNSUPPORTED;
+    if (d->dz_cells) {
+        // stretched z: walls in z only, positive finite thicknesses
+        if (d->bc_z == POISSON_BC_PERIODIC) return POISSON_ERR_UNSUPPORTED;
+        for (int k = 0; k < d->nz; ++k)
+            if (!(std::isfinite(d->dz_cells[k]) && d->dz_cells[k] > 0))
+                return POISSON_ERR_INVALID_ARG;
+    }
     return POISSON_OK;
 }
 
@@ -574,6 +620,27 @@ int build_group(Group &g, Alloc &A)
         (rc = upload_complex(A, t.twy4, quarter_table(d.ny), f32, f64)))
         return rc;
     auto lz = eig_table(d.nz, d.dz, d.nz);
+    g.mean_div = (double)g.N;
+    if (!g.hz.empty()) {
+        auto zt = zrow_table(g.hz, d.bc_z);
+        g.hsum = zt[8 * g.hz.size() + 5];
+        g.mean_div = (double)d.nx * d.ny * g.hsum;
+        if ((rc = A.put(t.zrow, zt.data(), zt.size() * 8))) return rc;
+        if ((rc = A.put(t.hz, g.hz.data(), g.hz.size() * 8))) return rc;
+        // residual: (a_k, c_k) / h_k per plane, 1/h_k^2 at a Dirichlet wall
+        // (the march's ghost plane is the negated wall plane), 0 at a
+        // Neumann wall (the ghost plane mirrors it)
+        std::vector<double> zc(2 * g.hz.size());
+        for (size_t k = 0; k < g.hz.size(); ++k) {
+            const double *r = &zt[8 * k];
+            const double hk = g.hz[k];
+            const bool wall_lo = k == 0, wall_hi = k + 1 == g.hz.size();
+            const bool dir = d.bc_z == POISSON_BC_DIRICHLET;
+            zc[2 * k] = wall_lo ? (dir ? 1.0 / (hk * hk) : 0.0) : r[0] / hk;
+            zc[2 * k + 1] = wall_hi ? (dir ? 1.0 / (hk * hk) : 0.0) : r[1] / hk;
+        }
+        if ((rc = A.put(t.zc, zc.data(), zc.size() * 8))) return rc;
+    }
     if ((rc = A.put(t.lamx, lx.data(), lx.size() * 8))) return rc;
     if ((rc = A.put(t.lamy, ly.data(), ly.size() * 8))) return rc;
     if ((rc = A.put(t.lamz, lz.data(), lz.size() * 8))) return rc;
@@ -698,7 +765,9 @@ int pass_x_fwd(LSet &L, bool residual, bool want_partials, bool sum = true)
     a.ay = 1.0 / (g.d.dy * g.d.dy);
     a.az = 1.0 / (g.d.dz * g.d.dz);
     a.sum_f = L.one.scal ? L.one.scal + 1 : nullptr;
-    a.inv_n = 1.0 / (double)g.N;
+    a.inv_n = 1.0 / g.mean_div;
+    a.hz = g.tab.hz ? (const double *)g.tab.hz->p : nullptr;
+    a.zc = g.tab.zc ? (const double *)g.tab.zc->p : nullptr;
     a.residual = residual ? 1 : 0;
     a.gate = L.gate;
     a.kr_max = g.tune.kr;
@@ -785,7 +854,9 @@ int pass_residual_check(LSet &L, bool sum = true)
     a.ay = 1.0 / (g.d.dy * g.d.dy);
     a.az = 1.0 / (g.d.dz * g.d.dz);
     a.sum_f = L.one.scal ? L.one.scal + 1 : nullptr;
-    a.inv_n = 1.0 / (double)g.N;
+    a.inv_n = 1.0 / g.mean_div;
+    a.hz = g.tab.hz ? (const double *)g.tab.hz->p : nullptr;
+    a.zc = g.tab.zc ? (const double *)g.tab.zc->p : nullptr;
     a.residual = 1;
     a.gate = L.gate;
     a.kr_max = g.tune.kr;
@@ -876,6 +947,8 @@ int pass_z(LSet &L)
     a.ywall = g.d.bc_y != POISSON_BC_PERIODIC ? 1 : 0;
     a.xwall = g.d.bc_x != POISSON_BC_PERIODIC ? 1 : 0;
     a.periodic_z = g.d.bc_z == POISSON_BC_PERIODIC ? 1 : 0;
+    a.zrow = g.tab.zrow ? (const double *)g.tab.zrow->p : nullptr;
+    a.hsum = g.hsum;
     const double bytes = (double)g.N * 2.0 * (L.prec == P_F32 ? 4.0 : 8.0) * L.n;
     char name[40];
     if (L.p->rec) {
@@ -902,7 +975,7 @@ int pass_x_inv(LSet &L, bool accumulate)
     // the inverse x pass follows the inverse y pass, which wrote the planes in order
     XInvArgs a{L.dev, L.n, L.one.S, L.one.p, g.tab.twx[L.prec == P_F32 ? 1 : 0]->p, g.d.nx,
                g.d.ny, g.d.nz, accumulate ? 1 : 0, g.tune.rev, nullptr,
-               1.0 / (double)g.N, L.gate, regular(g.d) ? 1 : 0, g.d.bc_x,
+               1.0 / g.mean_div, L.gate, regular(g.d) ? 1 : 0, g.d.bc_x,
                g.d.bc_x != POISSON_BC_PERIODIC ? g.tab.twx4[L.prec == P_F32 ? 1 : 0]->p
                                                : nullptr,
                0, L.one.p32};
@@ -1185,8 +1258,7 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
                     const double *s = hs + NSCAL * i;
                     const double rho = s[3] > 0 ? std::sqrt(s[2] / s[3]) : std::sqrt(s[2]);
                     out[i].rel_residual = rho;
-                    out[i].rhs_mean =
-                        regular(p->groups[gi].d) ? 0.0 : s[1] / (double)p->groups[gi].N;
+                    out[i].rhs_mean = regular(p->groups[gi].d) ? 0.0 : s[1] / p->groups[gi].mean_div;
                     out[i].iterations = corrections[i];
                     int status = -1;
                     if (!std::isfinite(rho))
@@ -1239,7 +1311,7 @@ int solve_all(poisson_plan p, const double *const *rhs, double *const *sol, pois
             for (int i : g.members)
                 out[i].rhs_mean =
                     regular(g.d) ? 0.0
-                                 : (prec == P_F64 ? hs[NSCAL * i] : hs[NSCAL * i + 1] / (double)g.N);
+                                 : (prec == P_F64 ? hs[NSCAL * i] : hs[NSCAL * i + 1] / g.mean_div);
     }
     if (p->batched && p->ptrs_done) (void)hipEventRecord(p->ptrs_done, p->ls);
 
@@ -1522,7 +1594,7 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
             if (!rc && (refine || st)) {
                 const double *sc = hs + NSCAL * i;
                 const int *c = hc + NCTRL * i;
-                o.rhs_mean = regular(g.d) ? 0.0 : (prec == P_F64 ? sc[0] : sc[1] / (double)g.N);
+                o.rhs_mean = regular(g.d) ? 0.0 : (prec == P_F64 ? sc[0] : sc[1] / g.mean_div);
                 if (refine) {
                     o.rel_residual = sc[5];
                     o.iterations = c[C_CORR];
@@ -1733,12 +1805,16 @@ int create_plan(const poisson_desc_t *descs, int count, void *stream, bool batch
         d.precision = p->precision;
         d.rtol = p->rtol;
         d.max_refine = p->max_refine;
+        std::vector<double> hz;
+        if (d.dz_cells) hz.assign(d.dz_cells, d.dz_cells + d.nz);
+        d.dz_cells = nullptr;
         int gi = -1;
         for (size_t k = 0; k < p->groups.size(); ++k)
-            if (same_problem(p->groups[k].d, d)) gi = (int)k;
+            if (same_problem(p->groups[k].d, d) && p->groups[k].hz == hz) gi = (int)k;
         if (gi < 0) {
             p->groups.emplace_back();
             p->groups.back().d = d;
+            p->groups.back().hz = hz;
             gi = (int)p->groups.size() - 1;
         }
         p->where[i] = {gi, (int)p->groups[gi].members.size()};
@@ -1855,6 +1931,7 @@ struct NoAllocDevice {
     poisson_desc_t desc{};
     std::vector<char> image;  // host image of the table region
     std::vector<double> host_state;
+    std::vector<double> hz;   // cell thicknesses of the cached plan (stretched z)
 };
 NoAllocDevice noalloc_dev[NOALLOC_MAX_DEVICES];
 
@@ -1884,6 +1961,8 @@ int noalloc_build(NoAllocDevice &D, const poisson_desc_t &d, int dev, hipStream_
     p->groups.emplace_back();
     Group &g = p->groups.back();
     g.d = d;
+    g.d.dz_cells = nullptr;
+    if (d.dz_cells) g.hz.assign(d.dz_cells, d.dz_cells + d.nz);
     g.members.assign(1, 0);
     D.image.clear();
     Alloc A;
@@ -1913,8 +1992,10 @@ int noalloc_build(NoAllocDevice &D, const poisson_desc_t &d, int dev, hipStream_
     p->hs = D.host_state.data();
     p->ctrl = (int *)((double *)p->scalars->p + NSCAL);
     p->host_ctrl = (int *)((double *)p->hs + NSCAL);
+    D.hz = p->groups[0].hz;
     D.plan = std::move(p);
     D.desc = d;
+    D.desc.dz_cells = nullptr;
     return POISSON_OK;
 }
 
@@ -1940,7 +2021,10 @@ int solve_noalloc(const poisson_desc_t *d, void *stream, const double *rhs, doub
         D.base = (char *)ptr;
     }
     const hipStream_t s = (hipStream_t)stream;
-    if (!D.plan || !same_desc(D.desc, *d)) {
+    bool same = D.plan && same_desc(D.desc, *d) && D.hz.size() == (size_t)(d->dz_cells ? d->nz : 0);
+    if (same && d->dz_cells)
+        same = std::equal(D.hz.begin(), D.hz.end(), d->dz_cells);
+    if (!same) {
         if ((rc = noalloc_build(D, *d, dev, s))) {
             D.plan.reset();
             return rc;
@@ -2035,7 +2119,7 @@ int poisson_project(poisson_plan plan, double *u, double *v, double *w, double *
     // the velocity conventions at the walls are those of the no-slip walls
     // (zero-gradient pressure); zero-value pressure walls are not projected
     const poisson_desc_t &d0 = plan->groups[0].d;
-    if (regular(d0)) return POISSON_ERR_UNSUPPORTED;
+    if (regular(d0) || !plan->groups[0].hz.empty()) return POISSON_ERR_UNSUPPORTED;
     const long long n = plan->groups[0].N;
     const double *arr[5] = {u, v, w, psi, p};
     for (int i = 0; i < 5; ++i)

@@ -179,6 +179,13 @@ struct XFwdArgs {
     const double *u, *v, *w;
     double cx, cy, cz;      // alpha/dx, alpha/dy, alpha/dz
     double *f_out;          // receives f in FP64 (nullable)
+    // stretched z (null: uniform): hz[k] the thickness of plane k, weighting
+    // the sums of f and p (volume-weighted means; inv_n is then
+    // 1/(nx ny sum h)); zc[2k], zc[2k+1] the z coefficients of plane k in
+    // the residual, (a_k, c_k)/h_k with a Dirichlet wall's 1/h_k^2 (its
+    // ghost plane is the negated wall plane)
+    const double *hz;
+    const double *zc;
 };
 
 // Inverse complex-to-real pass along x: p = result (store) or p += result.
@@ -242,6 +249,13 @@ struct ZArgs {
     int ywall;              // walls along y: the m = 0 column holds A + iB with real y-modes
     int xwall;              // walls along x: every column m holds the real x-modes 2m, 2m+1
     int periodic_z;         // 1: periodic z (transform), 0: walls (tridiagonal solve)
+    // stretched z (walls; cells of thickness h_k): 8 doubles per row k,
+    // {a_k, c_k, h_k, D_k, d_k+1/2, sum_{j<k} h_j, 0, 0} with a_k, c_k the
+    // conductances 1/d of the faces below and above (0 at a wall), D_k the
+    // Dirichlet wall term 2/h_k, d_k+1/2 the distance of the centres k, k+1;
+    // rows from nz on are padding {0, 0, 0, 1, 0, sum h, 0, 0}.  Null: uniform.
+    const double *zrow;
+    double hsum;            // sum of the thicknesses
 };
 
 // ---------------------------------------------------------------------------

@@ -249,19 +249,22 @@ template <int M> struct RCBody {
         m.ax = a.ax;
         m.ay = a.ay;
         m.az = a.az;
+        m.zc = a.zc;
         m.mu = (a.sum_f && !a.regular) ? (*a.sum_f) * a.inv_n : 0.0;
         m.tile = s_tile;
         m.setup(jb, a.ny, a.nz, a.bc_z, a.bc_y);
         m.bc_x = a.bc_x;
         m.start(k0);
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+        double wk = 1.0;  // stretched z: volume weight of p in plane k
         auto sink = [&](int, int, int, double r0, double r1, double f0, double f1, double2 c) {
             acc0 += r0 * r0 + r1 * r1;
             acc1 += f0 * f0 + f1 * f1;
-            acc2 += c.x + c.y;
+            acc2 += wk * (c.x + c.y);
         };
         for (int k = k0; k < k1; ++k) {
             if (k > k0) __syncthreads();
+            wk = a.hz ? a.hz[k] : 1.0;
             m.step(k, sink);
         }
         block_sum3(acc0, acc1, acc2, s_red, RC_NT);

@@ -48,7 +48,7 @@ template <int M> struct XFPlainBody {
             const int row = row0 + b;
             if (row >= nrows) return {R(0), R(0)};
             const double2 fv = ld_stream(gf + (size_t)row * NX + 2 * n);
-            acc0 += fv.x + fv.y;
+            acc0 += (a.hz ? a.hz[row / a.ny] : 1.0) * (fv.x + fv.y);
             return {R(fv.x), R(fv.y)};
         };
         auto out = [&](int b) -> PK_GLOBAL Cx<R> * {

@@ -288,7 +288,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
                 // walls: the reordered row v[j] = x[r(j)] (sines: signed)
                 const int i0 = wall_index(2 * n, NX), i1 = wall_index(2 * n + 1, NX);
                 double f0 = gf[(size_t)row * NX + i0], f1 = gf[(size_t)row * NX + i1];
-                acc0 += f0 + f1;
+                acc0 += (a.hz ? a.hz[row / a.ny] : 1.0) * (f0 + f1);
                 if (sine) {
                     f0 = (i0 & 1) ? -f0 : f0;
                     f1 = (i1 & 1) ? -f1 : f1;
@@ -298,7 +298,8 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
             // f is read once (streaming loads measured 16 % faster for the
             // FP64 pass; the residual marches, which also read f, lost 1-3 %)
                 const double2 fv = ld_stream(gf + (size_t)row * NX + 2 * n);
-                acc0 += fv.x + fv.y;
+                // stretched z: the sum of f weighted by the plane thickness
+                acc0 += (a.hz ? a.hz[row / a.ny] : 1.0) * (fv.x + fv.y);
                 return {R(fv.x), R(fv.y)};
             }
         };
@@ -326,7 +327,7 @@ __global__ __launch_bounds__(XCfg<M>::NT) void k_x_fwd(XFwdArgs a0)
                 const int e = threadIdx.x + q * NT;
                 if (e >= NB * M) continue;
                 const int b = e / M, h = e % M;
-                acc0 += fv[q].x + fv[q].y;
+                acc0 += (a.hz ? a.hz[(row0 + b) / a.ny] : 1.0) * (fv[q].x + fv[q].y);
                 R *trow = (R *)&tile.at(b, 0);
                 trow[h] = R(fv[q].x);
                 trow[NX - 1 - h] = R(sine ? -fv[q].y : fv[q].y);
@@ -452,6 +453,7 @@ template <int M, bool XW, bool P32> struct XRBody {
         m.ax = a.ax;
         m.ay = a.ay;
         m.az = a.az;
+        m.zc = a.zc;
         m.mu = (a.sum_f && !a.regular) ? (*a.sum_f) * a.inv_n : 0.0;
         m.tile = (double2(*)[M])s_buf;
         m.setup(jb, a.ny, a.nz, a.bc_z, a.bc_y);
@@ -469,10 +471,11 @@ template <int M, bool XW, bool P32> struct XRBody {
         for (int k = k0; k < k1; ++k) {
             __syncthreads();  // the previous plane's transform is done with the tile
             Cx<R> rr[Mar::PER];
+            const double wk = a.hz ? a.hz[k] : 1.0;  // stretched z: volume weight of p
             auto sink = [&](int q, int, int, double r0, double r1, double f0, double f1, double2 c) {
                 acc0 += r0 * r0 + r1 * r1;
                 acc1 += f0 * f0 + f1 * f1;
-                acc2 += c.x + c.y;
+                acc2 += wk * (c.x + c.y);
                 rr[q] = {R(r0), R(r1)};
             };
             m.step(k, sink);

@@ -82,7 +82,7 @@ __device__ __forceinline__ double rcp_nr(double x)
 
 // One workgroup's work (block vb.x of problem vb.y): C chunks of L rows of W
 // columns; `smem_d` holds the dynamic LDS of zw_lds_bytes().
-template <int L, int W> struct ZWBody {
+template <int L, int W, bool STR = false> struct ZWBody {
     static __device__ __forceinline__ void run(const ZArgs &a0, VBlock vb, int C, int nspecial,
                                                double *smem_d)
     {
@@ -105,6 +105,12 @@ template <int L, int W> struct ZWBody {
         const int e = (s + L < nz) ? s + L : nz;  // chunk rows [s, e)
         const bool special = vb.x < nspecial;
         const double scale = a.dz2 * a.inv_nxny;
+        // stretched z: the rows' coefficients from the table (ZArgs::zrow); s of
+        // the column is -(lam_x + lam_y) times dz^2 (uniform rows, divided by
+        // 1/dz^2) or, per row, times h_k (stretched rows, multiplied by h_k)
+        const double *zrow = a.zrow;
+        auto zr = [&](int k, int f) -> double { return zrow[8 * k + f]; };
+        const double sfac = STR ? 1.0 : a.dz2;
 
         Cx<R> d[L];
         bool active;
@@ -116,7 +122,7 @@ template <int L, int W> struct ZWBody {
             const int m = q % M;
             ky = q / M;
             active = (q < ny * M) && (m != 0);
-            s_d = active ? -(a.lamx[m] + a.lamy[ky]) * a.dz2 : 1.0;
+            s_d = active ? -(a.lamx[m] + a.lamy[ky]) * sfac : 1.0;
             const PK_GLOBAL Cx<R> *col = S + (size_t)s * plane + (active ? q : 0);
 #pragma unroll
             for (int i = 0; i < L; ++i)
@@ -152,7 +158,7 @@ template <int L, int W> struct ZWBody {
             zero_lane = active && mm == 0 && pair == 0 && part == 0 && !a.regular;
             const double lx = a.xwall ? a.lamx[2 * (active ? mm : 0) + part]
                                       : (part ? a.lamx[M] : a.lamx[0]);
-            s_d = (active && !zero_lane) ? -(lx + a.lamy[ky]) * a.dz2 : 1.0;
+            s_d = (active && !zero_lane) ? -(lx + a.lamy[ky]) * sfac : 1.0;
             // part A reads column ky, part B column -ky (the same with walls along y)
             const PK_GLOBAL Cx<R> *col =
                 S + (size_t)s * plane + (size_t)(part ? kyn : ky) * M + (active ? mm : 0);
@@ -177,7 +183,8 @@ template <int L, int W> struct ZWBody {
             }
         }
 #pragma unroll
-        for (int i = 0; i < L; ++i) d[i] = cscale(d[i], R(scale));
+        for (int i = 0; i < L; ++i)
+            d[i] = cscale(d[i], R(STR ? zr(s + i, 2) * a.inv_nxny : scale));
 
         // zero wavenumber: raw A(0,k) = Re S[k,0,0] is re-read (L1-resident)
         // whenever needed, so the FP64 path keeps only scalars across barriers
@@ -199,8 +206,19 @@ template <int L, int W> struct ZWBody {
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             const int k = s + i;
-            const R a0 = (k == 0) ? R(0) : mw;  // row 0 ignores the entering v
-            const R b0 = (k == 0) ? mws0 : mws;
+            R a0, b0;
+            if constexpr (STR) {
+                // [[a_k, s_k + D_k], [a_k, s_k + D_k + c_k]] / (s_k + D_k + c_k); a
+                // row without an upper neighbour (c_k = 0) maps anything to 1
+                const R ak = R(zr(k, 0)), ck = R(zr(k, 1));
+                const R sd = sv * R(zr(k, 2)) + R(zr(k, 3));
+                const R inv = rcp_nr(sd + ck);
+                a0 = ck > R(0) ? ak * inv : R(0);
+                b0 = ck > R(0) ? sd * inv : R(1);
+            } else {
+                a0 = (k == 0) ? R(0) : mw;  // row 0 ignores the entering v
+                b0 = (k == 0) ? mws0 : mws;
+            }
             const R n00 = a0 * p00 + b0 * p10, n01 = a0 * p01 + b0 * p11;
             const R n10 = a0 * p00 + p10, n11 = a0 * p01 + p11;
             p00 = n00; p01 = n01; p10 = n10; p11 = n11;
@@ -209,7 +227,7 @@ template <int L, int W> struct ZWBody {
         slot[0] = p00; slot[1] = p01; slot[2] = p10; slot[3] = p11;
         if (zero_lane) {
             double zsum = 0.0;
-            for (int k = s; k < e; ++k) zsum += zraw(k);
+            for (int k = s; k < e; ++k) zsum += (STR ? zr(k, 2) : 1.0) * zraw(k);
             zbuf[c] = zsum;
         }
         __syncthreads();  // S1
@@ -245,13 +263,17 @@ template <int L, int W> struct ZWBody {
                 if (cc == c) pre = tot;
                 tot += zbuf[cc];
             }
-            zmu = tot / nz;
-            if (c == 0 && a.zero_mean_out) *a.zero_mean_out = tot * a.inv_ntot;
-            zF0 = (pre - s * zmu) * scale;  // flux entering the chunk, F_{s-1}
+            // stretched: the volume-weighted mean, g_k = h_k (raw_k - mean) / (nx ny),
+            // and positions advance by the flux times the centre distance
+            zmu = STR ? tot / a.hsum : tot / nz;
+            if (c == 0 && a.zero_mean_out)
+                *a.zero_mean_out = STR ? zmu * a.inv_nxny : tot * a.inv_ntot;
+            zF0 = STR ? (pre - zr(s, 5) * zmu) * a.inv_nxny
+                      : (pre - s * zmu) * scale;  // flux entering the chunk, F_{s-1}
             double run = zF0;
             for (int k = s; k < e; ++k) {
-                run += (zraw(k) - zmu) * scale;
-                zsF += run;
+                run += STR ? zr(k, 2) * (zraw(k) - zmu) * a.inv_nxny : (zraw(k) - zmu) * scale;
+                zsF += STR ? run * zr(k, 4) : run;
             }
         }
         __syncthreads();  // S2: Moebius slots consumed
@@ -269,18 +291,33 @@ template <int L, int W> struct ZWBody {
 #pragma unroll
             for (int i = 0; i < L; ++i) {
                 const int k = s + i;
-                // |pivot| = (excess over 1) + 1, except the last row (and nz = 1)
-                const R ex = (k == 0) ? sv + dir2 : sv + vprev;
-                const bool last = k >= nz - 1;
-                const R piv = (nz == 1) ? sv + dir2 + dir2 : (k == nz - 1 ? ex + dir2 : R(1) + ex);
-                const R u = rcp_nr(piv);
-                const R vnew = last ? R(1) : ex * u;
-                Dp = cscale(csub(Dp, d[i]), u);
-                Gp = u * Gp;
-                if (k == nz - 1) ulast = u;
-                vk[i] = vnew;
-                d[i] = Dp;
-                vprev = vnew;
+                if constexpr (STR) {
+                    // |pivot| = c_k + e_k, e_k = s_k + D_k + a_k v_k-1; vk holds
+                    // 1/|pivot| (the multipliers are a_k / |pivot|, c_k / |pivot|)
+                    const R ak = R(zr(k, 0)), ck = R(zr(k, 1));
+                    const R ex = sv * R(zr(k, 2)) + R(zr(k, 3)) + ak * vprev;
+                    const R wv = rcp_nr(ck + ex);
+                    const R vnew = ck > R(0) ? ex * wv : R(1);
+                    Dp = cscale(csub(cscale(Dp, ak), d[i]), wv);
+                    Gp = ak * wv * Gp;
+                    vk[i] = wv;
+                    d[i] = Dp;
+                    vprev = vnew;
+                } else {
+                    // |pivot| = (excess over 1) + 1, except the last row (and nz = 1)
+                    const R ex = (k == 0) ? sv + dir2 : sv + vprev;
+                    const bool last = k >= nz - 1;
+                    const R piv =
+                        (nz == 1) ? sv + dir2 + dir2 : (k == nz - 1 ? ex + dir2 : R(1) + ex);
+                    const R u = rcp_nr(piv);
+                    const R vnew = last ? R(1) : ex * u;
+                    Dp = cscale(csub(Dp, d[i]), u);
+                    Gp = u * Gp;
+                    if (k == nz - 1) ulast = u;
+                    vk[i] = vnew;
+                    d[i] = Dp;
+                    vprev = vnew;
+                }
             }
             slot[0] = Dp.re; slot[1] = Dp.im; slot[2] = Gp;
         }
@@ -307,7 +344,7 @@ template <int L, int W> struct ZWBody {
             R Gr = R(1);
 #pragma unroll
             for (int i = 0; i < L; ++i) {
-                Gr *= (s + i == nz - 1) ? ulast : R(1) - vk[i];
+                Gr *= STR ? R(zr(s + i, 0)) * vk[i] : ((s + i == nz - 1) ? ulast : R(1) - vk[i]);
                 d[i] = {d[i].re + Gr * dprev.re, d[i].im + Gr * dprev.im};
             }
         }
@@ -317,19 +354,26 @@ template <int L, int W> struct ZWBody {
 #pragma unroll
         for (int i = L - 1; i >= 0; --i) {
             // p_k = d'_k + u_k p_{k+1} written as d'_k + (p_{k+1} - v_k p_{k+1})
-            const Cx<R> X = {d[i].re + (Xn.re - vk[i] * Xn.re), d[i].im + (Xn.im - vk[i] * Xn.im)};
+            Cx<R> X;
+            if constexpr (STR) {
+                const R uk = R(zr(s + i, 1)) * vk[i];  // c_k / |pivot_k|
+                X = {d[i].re + uk * Xn.re, d[i].im + uk * Xn.im};
+                Hn *= uk;
+            } else {
+                X = {d[i].re + (Xn.re - vk[i] * Xn.re), d[i].im + (Xn.im - vk[i] * Xn.im)};
+                Hn *= R(1) - vk[i];
+            }
             d[i] = X;
             Xn = X;
-            Hn *= R(1) - vk[i];
         }
         double zP0 = 0.0, zsx = 0.0;
         if (zero_lane) {
             for (int cc = 0; cc < c; ++cc) zP0 += zbuf[C + cc];  // p_s
             double run = zF0, xk = zP0;
             for (int k = s; k < e; ++k) {
-                zsx += xk;
-                run += (zraw(k) - zmu) * scale;
-                xk += run;
+                zsx += STR ? zr(k, 2) * xk : xk;
+                run += STR ? zr(k, 2) * (zraw(k) - zmu) * a.inv_nxny : (zraw(k) - zmu) * scale;
+                xk += STR ? run * zr(k, 4) : run;
             }
         }
         __syncthreads();  // S4: slots consumed
@@ -356,22 +400,22 @@ template <int L, int W> struct ZWBody {
             R Hr = R(1);
 #pragma unroll
             for (int i = L - 1; i >= 0; --i) {
-                Hr *= R(1) - vk[i];
+                Hr *= STR ? R(zr(s + i, 1)) * vk[i] : R(1) - vk[i];
                 d[i] = {d[i].re + Hr * y.re, d[i].im + Hr * y.im};
             }
         }
         if (zero_lane) {
             double tot = 0.0;
             for (int cc = 0; cc < C; ++cc) tot += zbuf[2 * C + cc];
-            const double mean = tot / nz;
+            const double mean = STR ? tot / a.hsum : tot / nz;
             double run = zF0, xk = zP0;
 #pragma unroll
             for (int i = 0; i < L; ++i) {
                 const int k = s + i;
                 if (k < nz) {
                     d[i] = {R(xk - mean), R(0)};
-                    run += (zraw(k) - zmu) * scale;
-                    xk += run;
+                    run += STR ? zr(k, 2) * (zraw(k) - zmu) * a.inv_nxny : (zraw(k) - zmu) * scale;
+                    xk += STR ? run * zr(k, 4) : run;
                 }
             }
         }
@@ -415,12 +459,12 @@ template <int W> constexpr size_t zw_lds_bytes(int C)
     return ((C * W * 4 * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double);
 }
 
-template <int L, int W, int MAXT>
+template <int L, int W, int MAXT, bool STR>
 __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
 {
     extern __shared__ double smem_d[];
-    ZWBody<L, W>::run(a0, VBlock{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x}, C, nspecial,
-                      smem_d);
+    ZWBody<L, W, STR>::run(a0, VBlock{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x}, C,
+                           nspecial, smem_d);
 }
 
 // Walls along x and y, one real system per lane.  Column (m, ky) of the
@@ -433,7 +477,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
 // recurrences of k_z_walls on real values: half the registers of a complex
 // lane whose imaginary half is zero.  Column (0, 0) is the zero mode (FP64,
 // as in k_z_walls).
-template <int L, int W, int MAXT>
+template <int L, int W, int MAXT, bool STR>
 __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
 {
     if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
@@ -455,19 +499,26 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
     const int s = c * L;
     const int e = (s + L < nz) ? s + L : nz;  // chunk rows [s, e)
     const double scale = a.dz2 * a.inv_nxny;
+    // stretched z: row coefficients from the table, s per row times h_k (as
+    // in ZWBody)
+    const double *zrow = a.zrow;
+    auto zr = [&](int k, int f) -> double { return zrow[8 * k + f]; };
+    const double sfac = STR ? 1.0 : a.dz2;
 
     const int q = block_order((int)blockIdx.x, (int)gridDim.x, a.reverse) * W + w;
     const int r = q % nx, ky = q / nx;
     const bool active = q < ny * nx;
     const bool zero_lane = active && q == 0 && !a.regular;
-    const double s_d = (active && !zero_lane) ? -(a.lamx[r] + a.lamy[ky]) * a.dz2 : 1.0;
+    const double s_d = (active && !zero_lane) ? -(a.lamx[r] + a.lamy[ky]) * sfac : 1.0;
 
     R d[L];
     {
         const PK_GLOBAL R *col = S + (size_t)s * plane + (active ? q : 0);
 #pragma unroll
         for (int i = 0; i < L; ++i)
-            d[i] = (active && s + i < nz) ? col[(size_t)i * plane] * R(scale) : R(0);
+            d[i] = (active && s + i < nz)
+                       ? col[(size_t)i * plane] * R(STR ? zr(s + i, 2) * a.inv_nxny : scale)
+                       : R(0);
     }
     // zero wavenumber: raw values re-read (L1-resident) whenever needed
     auto zraw = [&](int k) -> double { return double(S[(size_t)k * plane]); };
@@ -483,8 +534,17 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
 #pragma unroll
     for (int i = 0; i < L; ++i) {
         const int k = s + i;
-        const R x0 = (k == 0) ? R(0) : mw;
-        const R y0 = (k == 0) ? mws0 : mws;
+        R x0, y0;
+        if constexpr (STR) {
+            const R ak = R(zr(k, 0)), ck = R(zr(k, 1));
+            const R sd = sv * R(zr(k, 2)) + R(zr(k, 3));
+            const R inv = rcp_nr(sd + ck);
+            x0 = ck > R(0) ? ak * inv : R(0);
+            y0 = ck > R(0) ? sd * inv : R(1);
+        } else {
+            x0 = (k == 0) ? R(0) : mw;
+            y0 = (k == 0) ? mws0 : mws;
+        }
         const R n00 = x0 * p00 + y0 * p10, n01 = x0 * p01 + y0 * p11;
         const R n10 = x0 * p00 + p10, n11 = x0 * p01 + p11;
         p00 = n00; p01 = n01; p10 = n10; p11 = n11;
@@ -493,7 +553,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
     slot[0] = p00; slot[1] = p01; slot[2] = p10; slot[3] = p11;
     if (zero_lane) {
         double zsum = 0.0;
-        for (int k = s; k < e; ++k) zsum += zraw(k);
+        for (int k = s; k < e; ++k) zsum += (STR ? zr(k, 2) : 1.0) * zraw(k);
         zbuf[c] = zsum;
     }
     __syncthreads();  // S1
@@ -524,13 +584,14 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
             if (cc == c) pre = tot;
             tot += zbuf[cc];
         }
-        zmu = tot / nz;
-        if (c == 0 && a.zero_mean_out) *a.zero_mean_out = tot * a.inv_ntot;
-        zF0 = (pre - s * zmu) * scale;
+        zmu = STR ? tot / a.hsum : tot / nz;
+        if (c == 0 && a.zero_mean_out)
+            *a.zero_mean_out = STR ? zmu * a.inv_nxny : tot * a.inv_ntot;
+        zF0 = STR ? (pre - zr(s, 5) * zmu) * a.inv_nxny : (pre - s * zmu) * scale;
         double run = zF0;
         for (int k = s; k < e; ++k) {
-            run += (zraw(k) - zmu) * scale;
-            zsF += run;
+            run += STR ? zr(k, 2) * (zraw(k) - zmu) * a.inv_nxny : (zraw(k) - zmu) * scale;
+            zsF += STR ? run * zr(k, 4) : run;
         }
     }
     __syncthreads();  // S2
@@ -543,17 +604,31 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             const int k = s + i;
-            const R ex = (k == 0) ? sv + dir2 : sv + vprev;
-            const bool last = k >= nz - 1;
-            const R piv = (nz == 1) ? sv + dir2 + dir2 : (k == nz - 1 ? ex + dir2 : R(1) + ex);
-            const R u = rcp_nr(piv);
-            const R vnew = last ? R(1) : ex * u;
-            Dp = (Dp - d[i]) * u;
-            Gp = u * Gp;
-            if (k == nz - 1) ulast = u;
-            vk[i] = vnew;
-            d[i] = Dp;
-            vprev = vnew;
+            if constexpr (STR) {
+                // vk holds 1/|pivot| (as in ZWBody)
+                const R ak = R(zr(k, 0)), ck = R(zr(k, 1));
+                const R ex = sv * R(zr(k, 2)) + R(zr(k, 3)) + ak * vprev;
+                const R wv = rcp_nr(ck + ex);
+                const R vnew = ck > R(0) ? ex * wv : R(1);
+                Dp = (ak * Dp - d[i]) * wv;
+                Gp = ak * wv * Gp;
+                vk[i] = wv;
+                d[i] = Dp;
+                vprev = vnew;
+            } else {
+                const R ex = (k == 0) ? sv + dir2 : sv + vprev;
+                const bool last = k >= nz - 1;
+                const R piv =
+                    (nz == 1) ? sv + dir2 + dir2 : (k == nz - 1 ? ex + dir2 : R(1) + ex);
+                const R u = rcp_nr(piv);
+                const R vnew = last ? R(1) : ex * u;
+                Dp = (Dp - d[i]) * u;
+                Gp = u * Gp;
+                if (k == nz - 1) ulast = u;
+                vk[i] = vnew;
+                d[i] = Dp;
+                vprev = vnew;
+            }
         }
         slot[0] = Dp; slot[1] = Gp;
     }
@@ -579,7 +654,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
         R Gr = R(1);
 #pragma unroll
         for (int i = 0; i < L; ++i) {
-            Gr *= (s + i == nz - 1) ? ulast : R(1) - vk[i];
+            Gr *= STR ? R(zr(s + i, 0)) * vk[i] : ((s + i == nz - 1) ? ulast : R(1) - vk[i]);
             d[i] = d[i] + Gr * dprev;
         }
     }
@@ -587,19 +662,20 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
     R Xn = R(0), Hn = R(1);
 #pragma unroll
     for (int i = L - 1; i >= 0; --i) {
-        const R X = d[i] + (Xn - vk[i] * Xn);
+        const R uk = STR ? R(zr(s + i, 1)) * vk[i] : R(1) - vk[i];
+        const R X = STR ? d[i] + uk * Xn : d[i] + (Xn - vk[i] * Xn);
         d[i] = X;
         Xn = X;
-        Hn *= R(1) - vk[i];
+        Hn *= uk;
     }
     double zP0 = 0.0, zsx = 0.0;
     if (zero_lane) {
         for (int cc = 0; cc < c; ++cc) zP0 += zbuf[C + cc];
         double run = zF0, xk = zP0;
         for (int k = s; k < e; ++k) {
-            zsx += xk;
-            run += (zraw(k) - zmu) * scale;
-            xk += run;
+            zsx += STR ? zr(k, 2) * xk : xk;
+            run += STR ? zr(k, 2) * (zraw(k) - zmu) * a.inv_nxny : (zraw(k) - zmu) * scale;
+            xk += STR ? run * zr(k, 4) : run;
         }
     }
     __syncthreads();  // S4
@@ -626,22 +702,22 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
         R Hr = R(1);
 #pragma unroll
         for (int i = L - 1; i >= 0; --i) {
-            Hr *= R(1) - vk[i];
+            Hr *= STR ? R(zr(s + i, 1)) * vk[i] : R(1) - vk[i];
             d[i] = d[i] + Hr * y;
         }
     }
     if (zero_lane) {
         double tot = 0.0;
         for (int cc = 0; cc < C; ++cc) tot += zbuf[2 * C + cc];
-        const double mean = tot / nz;
+        const double mean = STR ? tot / a.hsum : tot / nz;
         double run = zF0, xk = zP0;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             const int k = s + i;
             if (k < nz) {
                 d[i] = R(xk - mean);
-                run += (zraw(k) - zmu) * scale;
-                xk += run;
+                run += STR ? zr(k, 2) * (zraw(k) - zmu) * a.inv_nxny : (zraw(k) - zmu) * scale;
+                xk += STR ? run * zr(k, 4) : run;
             }
         }
     }
@@ -655,19 +731,19 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
     }
 }
 
-template <int L, int W, int MAXT>
+template <int L, int W, int MAXT, bool STR>
 static int run_zwr(const ZArgs &a, hipStream_t s)
 {
     const int C = (a.nz + L - 1) / L;
     if (C * W > MAXT) return -1;
     const int nb = (a.ny * a.nx + W - 1) / W;
     const size_t shm = ((C * W * 4 * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double);
-    hipLaunchKernelGGL((k_z_walls_r<L, W, MAXT>), dim3(nb, a.batch ? a.nbatch : 1), dim3(W * C),
-                       shm, s, a, C);
+    hipLaunchKernelGGL((k_z_walls_r<L, W, MAXT, STR>), dim3(nb, a.batch ? a.nbatch : 1),
+                       dim3(W * C), shm, s, a, C);
     return (int)hipGetLastError();
 }
 
-template <int L, int W, int MAXT>
+template <int L, int W, int MAXT, bool STR>
 static int run_zw(const ZArgs &a, hipStream_t s)
 {
     const int C = (a.nz + L - 1) / L;
@@ -677,7 +753,7 @@ static int run_zw(const ZArgs &a, hipStream_t s)
     const int nspecial = a.xwall ? npairs * ((a.M + H - 1) / H) : (npairs + H - 1) / H;
     const int nmain = a.xwall ? 0 : (a.ny * a.M + W - 1) / W;
     const size_t shm = ((C * W * 4 * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double);
-    hipLaunchKernelGGL((k_z_walls<L, W, MAXT>), dim3(nspecial + nmain, a.batch ? a.nbatch : 1),
+    hipLaunchKernelGGL((k_z_walls<L, W, MAXT, STR>), dim3(nspecial + nmain, a.batch ? a.nbatch : 1),
                        dim3(W * C), shm, s, a, C, nspecial);
     return (int)hipGetLastError();
 }
@@ -728,7 +804,7 @@ static bool z_list_class(const ZArgs &a, int &cls, int &nt, int &gx, int &C, int
                          size_t &lds)
 {
     if (!a.periodic_z) {
-        if (a.xwall && a.ywall) return false;
+        if ((a.xwall && a.ywall) || a.zrow) return false;
         int L, W;
         if (a.nz <= 64) {
             cls = 1; L = 8; W = 32;
@@ -828,7 +904,9 @@ int PK_SUFFIX(launch_z_list)(const ZArgs *a, int n, hipStream_t s)
     return flush();
 }
 
-int PK_SUFFIX(launch_z_walls)(const ZArgs &a, hipStream_t s)
+namespace PK_NS {
+// tile choice of the wall-bounded z solve; STR: stretched rows (ZArgs::zrow)
+template <bool STR> static int dispatch_zw(const ZArgs &a, hipStream_t s)
 {
     // Chunk length L (registers per thread), W columns per workgroup,
     // W*ceil(nz/L) threads.  a.variant selects the tile (autotuned per shape):
@@ -844,43 +922,43 @@ int PK_SUFFIX(launch_z_walls)(const ZArgs &a, hipStream_t s)
         // 256-byte row runs.
         const int v = a.variant & 3;
         const bool c8 = v == 1 || v == 3, wide = v >= 2;
-        if (nz <= 64) return run_zwr<8, 32, 256>(a, s);
+        if (nz <= 64) return run_zwr<8, 32, 256, STR>(a, s);
         if constexpr (F32) {
             if (!c8 && !wide) {
-                if (nz <= 128) return run_zwr<16, 32, 256>(a, s);
-                if (nz <= 256) return run_zwr<16, 32, 512>(a, s);
-                if (nz <= 512) return run_zwr<16, 32, 1024>(a, s);
+                if (nz <= 128) return run_zwr<16, 32, 256, STR>(a, s);
+                if (nz <= 256) return run_zwr<16, 32, 512, STR>(a, s);
+                if (nz <= 512) return run_zwr<16, 32, 1024, STR>(a, s);
             } else if (!c8) {
-                if (nz <= 128) return run_zwr<16, 64, 512>(a, s);
-                if (nz <= 256) return run_zwr<16, 64, 1024>(a, s);
+                if (nz <= 128) return run_zwr<16, 64, 512, STR>(a, s);
+                if (nz <= 256) return run_zwr<16, 64, 1024, STR>(a, s);
             } else if (!wide) {
-                if (nz <= 128) return run_zwr<8, 32, 512>(a, s);
-                if (nz <= 256) return run_zwr<8, 32, 1024>(a, s);
+                if (nz <= 128) return run_zwr<8, 32, 512, STR>(a, s);
+                if (nz <= 256) return run_zwr<8, 32, 1024, STR>(a, s);
             } else {
-                if (nz <= 128) return run_zwr<8, 64, 1024>(a, s);
+                if (nz <= 128) return run_zwr<8, 64, 1024, STR>(a, s);
             }
         } else {
             if (!c8 && !wide) {
-                if (nz <= 256) return run_zwr<16, 16, 256>(a, s);
-                if (nz <= 512) return run_zwr<16, 16, 512>(a, s);
+                if (nz <= 256) return run_zwr<16, 16, 256, STR>(a, s);
+                if (nz <= 512) return run_zwr<16, 16, 512, STR>(a, s);
             } else if (!c8) {
-                if (nz <= 128) return run_zwr<16, 32, 256>(a, s);
-                if (nz <= 256) return run_zwr<16, 32, 512>(a, s);
+                if (nz <= 128) return run_zwr<16, 32, 256, STR>(a, s);
+                if (nz <= 256) return run_zwr<16, 32, 512, STR>(a, s);
             } else if (!wide) {
-                if (nz <= 128) return run_zwr<8, 16, 256>(a, s);
-                if (nz <= 256) return run_zwr<8, 16, 512>(a, s);
-                if (nz <= 512) return run_zwr<8, 16, 1024>(a, s);
+                if (nz <= 128) return run_zwr<8, 16, 256, STR>(a, s);
+                if (nz <= 256) return run_zwr<8, 16, 512, STR>(a, s);
+                if (nz <= 512) return run_zwr<8, 16, 1024, STR>(a, s);
             } else {
-                if (nz <= 128) return run_zwr<8, 32, 512>(a, s);
-                if (nz <= 256) return run_zwr<8, 32, 1024>(a, s);
+                if (nz <= 128) return run_zwr<8, 32, 512, STR>(a, s);
+                if (nz <= 256) return run_zwr<8, 32, 1024, STR>(a, s);
             }
-            if (nz <= 512) return run_zwr<16, 16, 512>(a, s);
+            if (nz <= 512) return run_zwr<16, 16, 512, STR>(a, s);
         }
         // beyond the variant's reach: narrower tiles of 8-row chunks (a
         // 1024-thread workgroup of 16-row chunks would spill registers)
-        if (nz <= 1024) return run_zwr<8, 8, 1024>(a, s);
-        if (nz <= 2048) return run_zwr<8, 4, 1024>(a, s);
-        if (nz <= 4096) return run_zwr<8, 2, 1024>(a, s);
+        if (nz <= 1024) return run_zwr<8, 8, 1024, STR>(a, s);
+        if (nz <= 2048) return run_zwr<8, 4, 1024, STR>(a, s);
+        if (nz <= 4096) return run_zwr<8, 2, 1024, STR>(a, s);
         return -1;
     }
     const bool c8 = a.variant == 1 || a.variant == 3;
@@ -888,40 +966,46 @@ int PK_SUFFIX(launch_z_walls)(const ZArgs &a, hipStream_t s)
     // read W/2 consecutive m each, so only the wide tiles give full
     // 128-byte runs (narrow ones split cache lines across dies)
     const bool wide = a.variant >= 2 || a.xwall;
-    if (nz <= 64) return run_zw<8, 32, 256>(a, s);
+    if (nz <= 64) return run_zw<8, 32, 256, STR>(a, s);
     if (!c8) {
         if constexpr (F32) {
             if (wide) {
-                if (nz <= 128) return run_zw<16, 32, 256>(a, s);
-                if (nz <= 256) return run_zw<16, 32, 512>(a, s);
-                if (nz <= 512) return run_zw<16, 32, 1024>(a, s);
+                if (nz <= 128) return run_zw<16, 32, 256, STR>(a, s);
+                if (nz <= 256) return run_zw<16, 32, 512, STR>(a, s);
+                if (nz <= 512) return run_zw<16, 32, 1024, STR>(a, s);
             } else {
-                if (nz <= 256) return run_zw<16, 16, 256>(a, s);
-                if (nz <= 512) return run_zw<16, 16, 512>(a, s);
-                if (nz <= 1024) return run_zw<16, 16, 1024>(a, s);
+                if (nz <= 256) return run_zw<16, 16, 256, STR>(a, s);
+                if (nz <= 512) return run_zw<16, 16, 512, STR>(a, s);
+                if (nz <= 1024) return run_zw<16, 16, 1024, STR>(a, s);
             }
-            if (nz <= 4096) return run_zw<16, 2, 1024>(a, s);
+            if (nz <= 4096) return run_zw<16, 2, 1024, STR>(a, s);
         } else {
             if (wide) {
-                if (nz <= 256) return run_zw<16, 16, 256>(a, s);
-                if (nz <= 512) return run_zw<16, 16, 512>(a, s);
+                if (nz <= 256) return run_zw<16, 16, 256, STR>(a, s);
+                if (nz <= 512) return run_zw<16, 16, 512, STR>(a, s);
             } else {
-                if (nz <= 512) return run_zw<16, 8, 256>(a, s);
-                if (nz <= 1024) return run_zw<16, 8, 512>(a, s);
+                if (nz <= 512) return run_zw<16, 8, 256, STR>(a, s);
+                if (nz <= 1024) return run_zw<16, 8, 512, STR>(a, s);
             }
         }
     }
     if (wide && !F32) {
-        if (nz <= 256) return run_zw<8, 16, 512>(a, s);
-        if (nz <= 512) return run_zw<8, 16, 1024>(a, s);
+        if (nz <= 256) return run_zw<8, 16, 512, STR>(a, s);
+        if (nz <= 512) return run_zw<8, 16, 1024, STR>(a, s);
     }
     if (wide && F32) {
-        if (nz <= 256) return run_zw<8, 32, 1024>(a, s);
+        if (nz <= 256) return run_zw<8, 32, 1024, STR>(a, s);
     }
-    if (nz <= 512) return run_zw<8, 8, 512>(a, s);
-    if (nz <= 1024) return run_zw<8, 8, 1024>(a, s);
-    if (nz <= 4096) return run_zw<8, 2, 1024>(a, s);
+    if (nz <= 512) return run_zw<8, 8, 512, STR>(a, s);
+    if (nz <= 1024) return run_zw<8, 8, 1024, STR>(a, s);
+    if (nz <= 4096) return run_zw<8, 2, 1024, STR>(a, s);
     return -1;
+}
+}  // namespace PK_NS
+
+int PK_SUFFIX(launch_z_walls)(const ZArgs &a, hipStream_t s)
+{
+    return a.zrow ? dispatch_zw<true>(a, s) : dispatch_zw<false>(a, s);
 }
 
 }  // namespace pk

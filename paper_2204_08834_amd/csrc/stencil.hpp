@@ -157,6 +157,7 @@ struct PlaneMarch : MarchIdx<M, TJ, NT> {
     const PK_GLOBAL double *f;  // set through gbl()
     const PK_GLOBAL PT *p;
     double ax, ay, az, mu;
+    const double *zc = nullptr;  // stretched z: per-plane coefficients (XFwdArgs::zc)
     double2 (*tile)[M];  // LDS, TJ + 2 rows
     double2 pd[PER], pc[PER];
 
@@ -198,6 +199,9 @@ struct PlaneMarch : MarchIdx<M, TJ, NT> {
             fv[q] = *(const PK_GLOBAL double2 *)(fk + o);
         }
         const double sm = this->sm, sn = this->sn;
+        // stretched z: the fluxes through the faces below and above
+        const bool zs = zc != nullptr;
+        const double czm = zs ? zc[2 * k] : 0.0, czp = zs ? zc[2 * k + 1] : 0.0;
         for (int h = threadIdx.x; h < M; h += NT) {
             const double2 a = ld_pair(pk_ + (size_t)jm * NX + 2 * h);
             const double2 b = ld_pair(pk_ + (size_t)jn * NX + 2 * h);
@@ -221,10 +225,12 @@ struct PlaneMarch : MarchIdx<M, TJ, NT> {
                                          : (bx == 0 ? tile[t + 1][M - 1].y : (bx == 1 ? c.x : -c.x));
                 const double pq = h != M - 1 ? tile[t + 1][h + 1].x
                                              : (bx == 0 ? tile[t + 1][0].x : (bx == 1 ? c.y : -c.y));
-                const double l0 = ax * (c.y - 2.0 * c.x + pl) + ay * (pn.x - 2.0 * c.x + ps.x) +
-                                  az * (u.x - 2.0 * c.x + d.x);
-                const double l1 = ax * (pq - 2.0 * c.y + c.x) + ay * (pn.y - 2.0 * c.y + ps.y) +
-                                  az * (u.y - 2.0 * c.y + d.y);
+                const double z0 = zs ? czp * (u.x - c.x) - czm * (c.x - d.x)
+                                     : az * (u.x - 2.0 * c.x + d.x);
+                const double z1 = zs ? czp * (u.y - c.y) - czm * (c.y - d.y)
+                                     : az * (u.y - 2.0 * c.y + d.y);
+                const double l0 = ax * (c.y - 2.0 * c.x + pl) + ay * (pn.x - 2.0 * c.x + ps.x) + z0;
+                const double l1 = ax * (pq - 2.0 * c.y + c.x) + ay * (pn.y - 2.0 * c.y + ps.y) + z1;
                 const double f0 = fv[q].x - mu, f1 = fv[q].y - mu;
                 sink(q, t, h, f0 - l0, f1 - l1, f0, f1, c);
             }

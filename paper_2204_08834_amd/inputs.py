@@ -308,6 +308,19 @@ def scaled(name: str, nx: int, ny: int, nz: int, seed: int | None = None) -> Pro
     return p
 
 
+def tanh_cells(nz, Lz=1.0, beta=2.0):
+    """Cell thicknesses of a wall-bounded axis clustered at both walls: the
+    faces sit at z_f(t) = Lz (1 + tanh(beta (2t - 1)) / tanh(beta)) / 2,
+    t = k / nz (the usual tanh stretching of channel and convection grids;
+    beta = 0 is the uniform grid)."""
+    t = np.arange(nz + 1) / nz
+    if beta == 0:
+        zf = Lz * t
+    else:
+        zf = Lz * (1.0 + np.tanh(beta * (2.0 * t - 1.0)) / math.tanh(beta)) / 2.0
+    return np.diff(zf)
+
+
 def random_rhs(nx, ny, nz, seed, zero_mean=True):
     """Plain U(-1,1) cell data (not a divergence), for tests of linear algebra."""
     rng = np.random.default_rng(seed)

@@ -38,7 +38,7 @@ class Desc(ctypes.Structure):
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
                 ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int), ("bc_z", ctypes.c_int),
                 ("precision", ctypes.c_int), ("rtol", ctypes.c_double),
-                ("max_refine", ctypes.c_int)]
+                ("max_refine", ctypes.c_int), ("dz_cells", ctypes.POINTER(ctypes.c_double))]
 
 
 class Stats(ctypes.Structure):
@@ -120,7 +120,10 @@ def error_string(code: int) -> str:
 
 
 def make_desc(nx, ny, nz, dx=1.0, dy=1.0, dz=1.0, bc_z=BC_NEUMANN, precision="fp64",
-              rtol=1e-10, max_refine=8, bc_x=BC_PERIODIC, bc_y=BC_PERIODIC) -> Desc:
+              rtol=1e-10, max_refine=8, bc_x=BC_PERIODIC, bc_y=BC_PERIODIC,
+              dz_cells=None) -> Desc:
+    """A descriptor; dz_cells: nz cell thicknesses of a z-stretched grid (the
+    array is kept alive with the descriptor, the library copies it)."""
     d = Desc()
     lib().poisson_desc_init(ctypes.byref(d))
     d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
@@ -129,6 +132,11 @@ def make_desc(nx, ny, nz, dx=1.0, dy=1.0, dz=1.0, bc_z=BC_NEUMANN, precision="fp
     d.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
     d.rtol = float(rtol)
     d.max_refine = int(max_refine)
+    if dz_cells is not None:
+        import numpy as np
+        h = np.ascontiguousarray(dz_cells, dtype=np.float64)
+        d._h = h  # keeps the buffer alive while the descriptor is used
+        d.dz_cells = h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return d
 
 
@@ -162,14 +170,15 @@ def _stream_handle(stream):
 
 def solve_noalloc(rhs, out, dx=1.0, dy=1.0, dz=1.0, bc_z=BC_NEUMANN, precision="fp64",
                   rtol=1e-10, max_refine=8, bc_x=BC_PERIODIC, bc_y=BC_PERIODIC, stream=None,
-                  check=True):
+                  check=True, dz_cells=None):
     """poisson_solve_noalloc: one solve without a plan and without device
     allocation (the library's fixed per-GPU scratch).  rhs, out: float64 GPU
     tensors of shape (nz, ny, nx).  Returns the stats dict."""
     nz, ny, nx = rhs.shape
     _check_field(rhs, (nz, ny, nx), "rhs")
     _check_field(out, (nz, ny, nx), "out")
-    d = make_desc(nx, ny, nz, dx, dy, dz, bc_z, precision, rtol, max_refine, bc_x, bc_y)
+    d = make_desc(nx, ny, nz, dx, dy, dz, bc_z, precision, rtol, max_refine, bc_x, bc_y,
+                  dz_cells)
     st = Stats()
     rc = lib().poisson_solve_noalloc(ctypes.byref(d), _stream_handle(stream),
                                      ctypes.c_void_p(rhs.data_ptr()),
@@ -185,9 +194,10 @@ class Plan:
     """One Poisson problem (grid, spacings, z boundary, precision) on one stream."""
 
     def __init__(self, nx, ny, nz, dx=1.0, dy=1.0, dz=1.0, bc_z=BC_NEUMANN, precision="fp64",
-                 rtol=1e-10, max_refine=8, stream=None, bc_x=BC_PERIODIC, bc_y=BC_PERIODIC):
+                 rtol=1e-10, max_refine=8, stream=None, bc_x=BC_PERIODIC, bc_y=BC_PERIODIC,
+                 dz_cells=None):
         self.desc = make_desc(nx, ny, nz, dx, dy, dz, bc_z, precision, rtol, max_refine,
-                              bc_x, bc_y)
+                              bc_x, bc_y, dz_cells)
         self.shape = (nz, ny, nx)
         self._stream = stream
         h = ctypes.c_void_p()
@@ -327,10 +337,14 @@ class BatchPlan:
         optionally bc_x, bc_y)."""
         n = len(problems)
         arr = (Desc * n)()
+        keep = []  # descriptors whose thickness arrays arr's copies point to
         for i, p in enumerate(problems):
-            arr[i] = make_desc(p["nx"], p["ny"], p["nz"], p["dx"], p["dy"], p["dz"],
-                               p["bc_z"], precision, rtol, max_refine,
-                               p.get("bc_x", BC_PERIODIC), p.get("bc_y", BC_PERIODIC))
+            d = make_desc(p["nx"], p["ny"], p["nz"], p["dx"], p["dy"], p["dz"],
+                          p["bc_z"], precision, rtol, max_refine,
+                          p.get("bc_x", BC_PERIODIC), p.get("bc_y", BC_PERIODIC),
+                          p.get("dz_cells"))
+            keep.append(d)
+            arr[i] = d
         self.shapes = [(p["nz"], p["ny"], p["nx"]) for p in problems]
         h = ctypes.c_void_p()
         rc = lib().poisson_batch_plan_create(arr, n, _stream_handle(stream), ctypes.byref(h))

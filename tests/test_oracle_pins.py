@@ -419,7 +419,10 @@ def _battery(orc, mutation):
     return failures
 
 
-@pytest.mark.parametrize("mutation", sorted(__import__("oracle").MUTATIONS))
+# the stretched-z mistakes (h_*) only change the stretched solve; they are
+# caught by the pins in test_oracle_stretched.py
+@pytest.mark.parametrize("mutation", sorted(m for m in __import__("oracle").MUTATIONS
+                                            if not m.startswith("h_")))
 def test_planted_mistakes_are_caught(orc, mutation):
     assert _battery(orc, 0) == []
     assert _battery(orc, mutation), f"planted mistake {mutation} not caught"
