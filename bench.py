@@ -13,7 +13,9 @@ fused into the first pass, the solve, the velocity correction and pressure
 update), under "projection", and wall-bounded boxes of the same grid (a
 cavity and a channel, cosine expansions along x and y), under "walls".  The
 256^3 triply periodic workload (spectral right-hand side) is timed the same
-way under "hit256".  The error of every returned field against the FP64
+way under "hit256", the 512x512x256 grid with tanh-stretched z cells under
+"stretched", and the largest single-GPU configuration (1024x1024x512 walls,
+spectral right-hand side synthesised on the GPU) under "rb1024".  The error of every returned field against the FP64
 oracle is reported under "err_vs_oracle" (the oracle's solve of the whole
 grid is also the CPU baseline).  The roofline
 entry is for the kernel with the largest share of the FP32+refinement step,
@@ -335,11 +337,78 @@ def bench_extra_workload(name, steps, warmup, tune, with_oracle):
         print(f"[bench] {name} {prec} {ms:.3f} ms/solve", file=sys.stderr, flush=True)
     res["fp32refine_over_fp64_speed"] = res["fp64"]["ms_per_step"] / res["fp32_refine"][
         "ms_per_step"]
-    if with_oracle:
-        import oracle
-        print(f"[bench] {name}: oracle solve for the error check", file=sys.stderr, flush=True)
-        ref = oracle.solve(prob.f, *sp, prob.bc_z)
-        res["err_vs_oracle"] = {k: error_vs_oracle(v, ref) for k, v in sols.items()}
+    # the error against the oracle is taken in the CPU-baseline leg
+    return res, (prob if with_oracle else None), sols
+
+
+def bench_stretched(steps, warmup, tune):
+    """The 512x512x256 walls grid (box 2x2x1) with tanh-stretched z cells
+    (beta = 2, clustered at both walls), U(-1,1) right-hand side (seed 3):
+    FP32 + refinement to 1e-10 and FP64."""
+    import torch
+    from paper_2204_08834_amd import inputs, poisson
+    nx, ny, nz = 512, 512, 256
+    h = inputs.tanh_cells(nz, 1.0, 2.0)
+    f = torch.from_numpy(inputs.random_rhs(nx, ny, nz, seed=3, zero_mean=False)).cuda()
+    out = torch.empty_like(f)
+    npts = nx * ny * nz
+    res = {"grid": [nx, ny, nz], "dz_cells": "tanh, beta 2 (min/max thickness "
+           f"{h.min():.2e}/{h.max():.2e})"}
+    for prec in ("fp32_refine", "fp64"):
+        plan = poisson.Plan(nx, ny, nz, 2.0 / nx, 2.0 / ny, 1.0 / nz, 1, prec, rtol=1e-10,
+                            dz_cells=h)
+        if tune:
+            plan.autotune()
+        for _ in range(warmup):
+            plan.solve(f, out)
+        ms, st = time_solves(plan, f, out, steps, sync_each=True)
+        plan.close()
+        res[prec] = {"ms_per_step": ms, "mpoints_s": npts / (ms * 1e-3) / 1e6,
+                     "rel_residual": st["rel_residual"], "iterations": st["iterations"]}
+        print(f"[bench] stretched {prec} {ms:.3f} ms/solve", file=sys.stderr, flush=True)
+    return res
+
+
+def bench_rb1024(steps, tune):
+    """The largest single-GPU configuration, 1024x1024x512 walls in z (box
+    2x2x1), right-hand side from the spectral recipe (shells 1..341, seed 5)
+    synthesised on the GPU (the host synthesis takes minutes): FP32 +
+    refinement to 1e-10 and FP64, with the refinement's relative residual
+    (the oracle's O(n^2) transforms are out of reach at this size)."""
+    import torch
+    from paper_2204_08834_amd import inputs, poisson
+    nx, ny, nz = 1024, 1024, 512
+    t0 = time.perf_counter()
+    rhs = inputs.spectral_velocity_rhs_torch(nx, ny, nz, 2.0, 2.0, 1.0, 1, 5, 341).contiguous()
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    torch.cuda.empty_cache()
+    out = torch.empty_like(rhs)
+    npts = nx * ny * nz
+    res = {"workload": f"rb1024: {DESCRIPTIONS['rb1024']}; synthesised on the GPU "
+                       f"(torch generator, {gen_s:.1f} s)", "grid": [nx, ny, nz]}
+    for prec in ("fp32_refine", "fp64"):
+        plan = poisson.Plan(nx, ny, nz, 2.0 / nx, 2.0 / ny, 1.0 / nz, 1, prec, rtol=1e-10)
+        if tune:
+            plan.autotune()
+        plan.solve(rhs, out)
+        ms, st = time_solves(plan, rhs, out, steps, sync_each=prec == "fp32_refine")
+        plan.set_timing(True)
+        plan.reset_timing()
+        plan.solve(rhs, out)
+        passes = plan.timing()
+        plan.close()
+        step_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in passes.values())
+        res[prec] = {"ms_per_step": ms, "mpoints_s": npts / (ms * 1e-3) / 1e6,
+                     "model_hbm_gbs": step_bytes / (ms * 1e-3) / 1e9,
+                     "model_bytes_per_point": step_bytes / npts}
+        if st is not None:
+            res[prec].update(rel_residual=st["rel_residual"], iterations=st["iterations"])
+        print(f"[bench] rb1024 {prec} {ms:.3f} ms/solve", file=sys.stderr, flush=True)
+    res["fp32refine_over_fp64_speed"] = res["fp64"]["ms_per_step"] / res["fp32_refine"][
+        "ms_per_step"]
+    del rhs, out
+    torch.cuda.empty_cache()
     return res
 
 
@@ -516,7 +585,8 @@ def main():
     ap.add_argument("--no-walls", action="store_true",
                     help="skip the wall-bounded boxes (walls along x and y)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the second workload (hit256: 256^3 triply periodic)")
+                    help="skip the other workloads (hit256: 256^3 triply periodic; the "
+                         "stretched-z 512x512x256 grid; rb1024: 1024x1024x512 walls)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the captured-graph loop timing (profiling runs: its gated-off "
                          "launches would mix into the per-kernel statistics)")
@@ -697,19 +767,38 @@ def main():
         print("[bench] batched mixed-64 workload", file=sys.stderr, flush=True)
         result["batch_mixed64"] = bench_batch(max(3, args.steps // 4), 2)
 
+    extra = None
     if not args.no_extra and prob.name != "hit256":
         print("[bench] hit256 workload", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
-        result["hit256"] = bench_extra_workload("hit256", args.steps, args.warmup,
-                                                not args.no_tune, not args.no_cpu)
+        result["hit256"], extra_prob, extra_sols = bench_extra_workload(
+            "hit256", args.steps, args.warmup, not args.no_tune, not args.no_cpu)
+        if extra_prob is not None:
+            extra = (extra_prob, extra_sols)
+
+    if not args.no_extra:
+        print("[bench] stretched z", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        result["stretched"] = bench_stretched(max(3, args.steps // 2), 2, not args.no_tune)
+        if prob.name != "rb1024":
+            print("[bench] rb1024 workload", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
+            result["rb1024"] = bench_rb1024(5, not args.no_tune)
 
     if not args.no_cpu:
+        import oracle
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         planes = prob.nz if args.cpu_planes <= 0 else min(args.cpu_planes, prob.nz)
         result["cpu_baseline"], ref = cpu_baseline(prob, planes)
         if ref is not None:
             # the error of each returned field against the FP64 oracle
             result["err_vs_oracle"] = {k: error_vs_oracle(v, ref) for k, v in solutions.items()}
+        if extra is not None:
+            xp, xs = extra
+            print(f"[bench] {xp.name}: oracle solve for the error check", file=sys.stderr,
+                  flush=True)
+            xref = oracle.solve(xp.f, *xp.spacings(), xp.bc_z)
+            result[xp.name]["err_vs_oracle"] = {k: error_vs_oracle(v, xref) for k, v in xs.items()}
     print(json.dumps(result), flush=True)
 
 

@@ -227,6 +227,94 @@ def spectral_velocity_rhs(nx, ny, nz, Lx, Ly, Lz, bc_z, seed, smax, slope=-5.0 /
     return _zero_mean(f)
 
 
+def spectral_velocity_rhs_torch(nx, ny, nz, Lx, Ly, Lz, bc_z, seed, smax, slope=-5.0 / 3.0,
+                                device="cuda", chunk=32):
+    """The recipe of spectral_velocity_rhs synthesised on a GPU with torch
+    (for grids whose synthesis on the host takes minutes): the same shells,
+    shell energies, solenoidal / potential split, face sampling, rms
+    normalisation, top-wall w = 0 and zero-mean divergence; random numbers
+    from one torch generator seeded with `seed`, drawn plane chunk by plane
+    chunk (a different realisation of the recipe than the host version's).
+    Returns the right-hand side as a float64 tensor on `device`."""
+    import torch
+
+    f64, c128 = torch.float64, torch.complex128
+    dev = torch.device(device)
+    nxh = nx // 2 + 1
+    k0 = 2.0 * math.pi / Lx
+    kx = 2.0 * math.pi * torch.fft.rfftfreq(nx, d=1.0 / nx, dtype=f64, device=dev) / Lx
+    kxf = 2.0 * math.pi * torch.fft.fftfreq(nx, d=1.0 / nx, dtype=f64, device=dev) / Lx
+    ky = 2.0 * math.pi * torch.fft.fftfreq(ny, d=1.0 / ny, dtype=f64, device=dev) / Ly
+    kz = 2.0 * math.pi * torch.fft.fftfreq(nz, d=1.0 / nz, dtype=f64, device=dev) / Lz
+    # modes per shell over the full two-sided spectrum
+    counts = torch.zeros(smax + 1, dtype=f64, device=dev)
+    kxy2 = kxf[None, :] ** 2 + ky[:, None] ** 2
+    for c in range(nz):
+        sh = torch.round(torch.sqrt(kxy2 + kz[c] ** 2) / k0).to(torch.int64)
+        sh = sh[(sh >= 1) & (sh <= smax)]
+        counts += torch.bincount(sh, minlength=smax + 1)[: smax + 1].to(f64)
+    shells = torch.arange(smax + 1, dtype=f64, device=dev)
+    e_mode = torch.where(counts > 0, shells.clamp(min=1.0) ** slope / counts.clamp(min=1.0),
+                         torch.zeros_like(counts))
+    e_mode[0] = 0.0
+    dx, dy, dz = Lx / nx, Ly / ny, Lz / nz
+    shifts = ((dx, 0.5 * dy, 0.5 * dz), (0.5 * dx, dy, 0.5 * dz), (0.5 * dx, 0.5 * dy, dz))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed))
+    spec = [torch.zeros((nz, ny, nxh), dtype=c128, device=dev) for _ in range(3)]
+    KX = kx[None, None, :].expand(1, ny, nxh)
+    KY = ky[None, :, None].expand(1, ny, nxh)
+    for c0 in range(0, nz, chunk):
+        c1 = min(nz, c0 + chunk)
+        m = c1 - c0
+        KZ = kz[c0:c1, None, None].expand(m, ny, nxh)
+        kk = torch.stack([KX.expand(m, ny, nxh), KY.expand(m, ny, nxh), KZ])
+        kmag = torch.sqrt((kk ** 2).sum(0))
+        sh = torch.round(kmag / k0).to(torch.int64)
+        ok = (sh >= 1) & (sh <= smax)
+        amp = torch.where(ok, torch.sqrt(e_mode[sh.clamp(0, smax)]), torch.zeros_like(kmag))
+        khat = kk / torch.where(kmag > 0, kmag, torch.ones_like(kmag))
+        a = torch.complex(torch.randn((3, m, ny, nxh), generator=gen, dtype=f64, device=dev),
+                          torch.randn((3, m, ny, nxh), generator=gen, dtype=f64, device=dev))
+        a = a - (a * khat).sum(0) * khat
+        an = torch.sqrt((a.abs() ** 2).sum(0))
+        a = a * torch.where(an > 0, 1.0 / torch.where(an > 0, an, torch.ones_like(an)),
+                            torch.zeros_like(an))
+        theta = torch.rand((m, ny, nxh), generator=gen, dtype=f64, device=dev) * (2.0 * math.pi)
+        pot = torch.exp(1j * theta) * khat
+        vec = (a + pot) * (amp * math.sqrt(0.5))
+        for comp in range(3):
+            sx, sy, sz = shifts[comp]
+            phase = torch.exp(1j * (kk[0] * sx + kk[1] * sy + kk[2] * sz))
+            spec[comp][c0:c1] = vec[comp] * phase
+        del kk, kmag, sh, ok, amp, khat, a, an, theta, pot, vec
+    norm = nx * ny * nz
+    vel = []
+    for comp in range(3):
+        vel.append(torch.fft.irfftn(spec[comp], s=(nz, ny, nx), dim=(0, 1, 2)) * norm)
+        spec[comp] = None
+    u, v, w = vel
+    rms = math.sqrt(float((u * u).mean() + (v * v).mean() + (w * w).mean()) / 3.0)
+    if rms > 0:
+        u /= rms
+        v /= rms
+        w /= rms
+    if bc_z == NEUMANN:
+        w[nz - 1] = 0.0
+    f = (u - torch.roll(u, 1, dims=2)) / dx
+    del u
+    f += (v - torch.roll(v, 1, dims=1)) / dy
+    del v
+    if bc_z == PERIODIC:
+        f += (w - torch.roll(w, 1, dims=0)) / dz
+    else:
+        wm = torch.empty_like(w)
+        wm[0] = 0.0
+        wm[1:] = w[:-1]
+        f += (w - wm) / dz
+    return f - f.mean(dtype=f64)
+
+
 # ----------------------------------------------------------------------------
 # named workloads
 # ----------------------------------------------------------------------------
