@@ -265,7 +265,8 @@ int upload_complex(Alloc &A, std::shared_ptr<DevBuf> out[2], const std::vector<d
 // read what the previous pass just wrote (block_order).
 struct Tune {
     int zv = 0, yv = 0, rev = 1;
-    int kr = 8;          // z-planes per workgroup of the residual passes (plane march)
+    int kr = 8;          // z-planes per workgroup of the residual pass with transform
+    int krc = 8;         // the same for the residual check (negative: exact depth)
     bool tuned = false;  // chosen by timing (else the defaults below)
 };
 
@@ -288,10 +289,15 @@ void apply_env_overrides(Tune &t)
     if (const char *e = getenv("POISSON_ZWALLS_VARIANT")) t.zv = atoi(e) & 3;
     if (const char *e = getenv("POISSON_Y_VARIANT")) t.yv = atoi(e) & 3;
     if (const char *e = getenv("POISSON_BLOCK_ORDER")) t.rev = strcmp(e, "forward") == 0 ? 0 : 1;
-    if (const char *e = getenv("POISSON_MARCH_PLANES")) {
+    // plane-range depths of the residual passes: 4, 8 or 16 (halved for
+    // small grids), other positive values exact
+    auto depth = [](const char *e, int &kr) {
         const int k = atoi(e);
-        if (k == 4 || k == 8 || k == 16) t.kr = k;
-    }
+        if (k == 4 || k == 8 || k == 16) kr = k;
+        else if (k > 0 && k <= 4096) kr = -k;
+    };
+    if (const char *e = getenv("POISSON_MARCH_PLANES")) depth(e, t.kr);
+    if (const char *e = getenv("POISSON_CHECK_PLANES")) depth(e, t.krc);
 }
 
 // process-wide cache of tuned variants: key "precision nx ny nz bc device"
@@ -332,12 +338,14 @@ void load_tune_file()
         std::string key(line);
         while (!key.empty() && key.back() == ' ') key.pop_back();
         Tune t;
-        const int got = sscanf(colon + 1, "%d %d %d %d", &t.zv, &t.yv, &t.rev, &t.kr);
+        const int got = sscanf(colon + 1, "%d %d %d %d %d", &t.zv, &t.yv, &t.rev, &t.kr, &t.krc);
         if (got >= 3) {
             t.zv &= 3;
             t.yv &= 3;
             t.rev = t.rev ? 1 : 0;
-            if (got < 4 || !(t.kr == 4 || t.kr == 8 || t.kr == 16)) t.kr = 8;
+            auto ok = [](int k) { return k == 4 || k == 8 || k == 16 || (k < 0 && k >= -4096); };
+            if (got < 4 || !ok(t.kr)) t.kr = 8;
+            if (got < 5 || !ok(t.krc)) t.krc = t.kr;
             t.tuned = true;
             tune_cache[key] = t;
         }
@@ -352,8 +360,8 @@ void save_tune_file()
     FILE *fp = fopen(path, "w");
     if (!fp) return;
     for (auto &kv : tune_cache)
-        fprintf(fp, "%s : %d %d %d %d\n", kv.first.c_str(), kv.second.zv, kv.second.yv,
-                kv.second.rev, kv.second.kr);
+        fprintf(fp, "%s : %d %d %d %d %d\n", kv.first.c_str(), kv.second.zv, kv.second.yv,
+                kv.second.rev, kv.second.kr, kv.second.krc);
     fclose(fp);
 }
 
@@ -859,7 +867,7 @@ int pass_residual_check(LSet &L, bool sum = true)
     a.zc = g.tab.zc ? (const double *)g.tab.zc->p : nullptr;
     a.residual = 1;
     a.gate = L.gate;
-    a.kr_max = g.tune.kr;
+    a.kr_max = g.tune.krc;
     a.kr_nb = kr_group(L);
     a.regular = regular(g.d) ? 1 : 0;
     int nc = 0;
@@ -1351,7 +1359,7 @@ int enqueue_residual_decision(poisson_plan p, LSet &L, bool with_check)
     }
     // partial records of whichever residual pass ran for each problem
     const int nr = x_fwd_blocks(P_F32, g.d.nx, g.d.ny, g.d.nz, 1, g.tune.kr, kr_group(L));
-    const int nc = residual_check_blocks(g.d.nx, g.d.ny, g.d.nz, g.tune.kr, kr_group(L));
+    const int nc = residual_check_blocks(g.d.nx, g.d.ny, g.d.nz, g.tune.krc, kr_group(L));
     if (p->rec) {
         Rec r;
         r.kind = RK_SUM;
@@ -1674,16 +1682,45 @@ int autotune_group(poisson_plan p, Group &g)
     if (g.d.ny >= 64 && g.d.bc_y == POISSON_BC_PERIODIC) pick(g.tune.yv, 4, whole);
     pick(g.tune.rev, 2, whole);
     if (p->precision == POISSON_FP32_REFINE) {
-        // plane-range depth of the residual passes: scored on the residual
-        // pass with transform followed by the residual check
-        static const int depths[3] = {4, 8, 16};
+        // plane-range depths of the residual pass with transform and of the
+        // residual check, each scored on its own pass: 4, 8 or 16 planes
+        // (halved for small grids), and the exact depths whose workgroups
+        // fill the device's resident slots in one or two whole rounds (a
+        // last partial round leaves most of the device idle: 1024 workgroups
+        // of 16 planes on 768 slots at 512x512x256 ran 6 % slower than 1536
+        // of 22)
+        const int nb = kr_group(L);
+        auto candidates = [&](int njb, int slots, int *c) {
+            int n = 0;
+            for (int k : {4, 8, 16}) c[n++] = k;
+            for (int rounds = 1; rounds <= 2 && slots > 0 && njb > 0; ++rounds) {
+                const long want = (long)slots * rounds / ((long)njb * nb);
+                if (want < 1) continue;
+                const int kr = (int)((g.d.nz + want - 1) / want);
+                bool dup = false;
+                for (int i = 0; i < n; ++i) dup = dup || c[i] == -kr;
+                if (!dup) c[n++] = -kr;
+            }
+            return n;
+        };
+        int cr[5], cc[5];
+        const int xw = g.d.bc_x != POISSON_BC_PERIODIC ? 1 : 0;
+        const int nr = candidates(x_fwd_blocks(P_F32, g.d.nx, g.d.ny, g.d.nz, 1, -g.d.nz, 1),
+                                  x_res_slots(g.d.nx, xw, L.cur32 ? 1 : 0), cr);
+        const int nc = candidates(residual_check_blocks(g.d.nx, g.d.ny, g.d.nz, -g.d.nz, 1),
+                                  residual_check_slots(g.d.nx), cc);
         int idx = 1;
-        pick(idx, 3, [&] {
-            g.tune.kr = depths[idx];
-            const int r = pass_x_fwd(L, true, true);
-            return r ? r : pass_residual_check(L);
+        pick(idx, nr, [&] {
+            g.tune.kr = cr[idx];
+            return pass_x_fwd(L, true, true);
         });
-        g.tune.kr = depths[idx];
+        g.tune.kr = cr[idx];
+        idx = 1;
+        pick(idx, nc, [&] {
+            g.tune.krc = cc[idx];
+            return pass_residual_check(L);
+        });
+        g.tune.krc = cc[idx];
     }
     g.tune.tuned = true;
     (void)hipStreamSynchronize(p->stream);
@@ -1882,7 +1919,7 @@ int project(poisson_plan p, double *u, double *v, double *w, double *pr, double 
     p->proj = poisson_plan_s::Proj{};
     if (rc) return rc;
     CorrArgs a{psi, u, v, w, pr, g.d.nx, g.d.ny, g.d.nz, g.d.bc_z,
-               beta / g.d.dx, beta / g.d.dy, beta / g.d.dz, g.tune.kr,
+               beta / g.d.dx, beta / g.d.dy, beta / g.d.dz, g.tune.kr > 0 ? g.tune.kr : 0,
                g.d.bc_x != POISSON_BC_PERIODIC ? 1 : 0, g.d.bc_y != POISSON_BC_PERIODIC ? 1 : 0};
     p->ls = p->stream;
     const double bytes = (double)g.N * (pr ? 72.0 : 56.0);
@@ -2154,7 +2191,7 @@ int poisson_plan_describe(poisson_plan plan, char *buf, int len)
         const Group &g = plan->groups[gi];
         snprintf(line, sizeof line,
                  "group %zu: %dx%dx%d %s %s problems=%zu z_tile=%d y_tile=%d reverse=%d "
-                 "march_planes=%d %s\n",
+                 "march_planes=%d check_planes=%d %s\n",
                  gi,
                  g.d.nx, g.d.ny, g.d.nz,
                  g.d.bc_z == POISSON_BC_NEUMANN
@@ -2163,8 +2200,8 @@ int poisson_plan_describe(poisson_plan plan, char *buf, int len)
                  plan->precision == POISSON_FP64 ? "fp64"
                                                  : (plan->precision == POISSON_FP32 ? "fp32"
                                                                                      : "fp32_refine"),
-                 g.members.size(), g.tune.zv, g.tune.yv, g.tune.rev, g.tune.kr,
-                 g.tune.tuned ? "tuned" : "default");
+                 g.members.size(), g.tune.zv, g.tune.yv, g.tune.rev, std::abs(g.tune.kr),
+                 std::abs(g.tune.krc), g.tune.tuned ? "tuned" : "default");
         out += line;
     }
     snprintf(buf, (size_t)len, "%s", out.c_str());

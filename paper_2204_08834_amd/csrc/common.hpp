@@ -345,6 +345,11 @@ int launch_sum_partials(const double *in, int n, double *out, const ProbPtrs *ba
 // (same layout as the forward x pass), for a convergence check.
 int launch_residual_check(const XFwdArgs &a, int *nblocks_out, hipStream_t s);
 int residual_check_blocks(int nx, int ny, int nz, int kr_max, int kr_nb = 1);
+// workgroups of the residual pass with transform (rows of nx points, walls
+// along x or not, p in FP32 or FP64) and of the residual check that the
+// current device holds at once (occupancy x compute units); -1 if unknown
+int x_res_slots(int nx, int xw, int p32);
+int residual_check_slots(int nx);
 // dst[i] = (double)src[i], i < n (device arrays)
 int launch_widen(const float *src, double *dst, size_t n, hipStream_t s);
 // clear `bytes` (a multiple of 4) at dst with a kernel

@@ -20,6 +20,7 @@ int launch_z_periodic_f32(const ZArgs &, hipStream_t);
 int launch_z_periodic_f64(const ZArgs &, hipStream_t);
 int x_fwd_blocks_f32(int, int, int, int, int, int);
 int x_fwd_blocks_f64(int, int, int, int, int, int);
+int x_res_slots_f32(int, int, int);
 int launch_y_list_f32(const YArgs *, int, hipStream_t);
 int launch_y_list_f64(const YArgs *, int, hipStream_t);
 int launch_z_list_f32(const ZArgs *, int, hipStream_t);
@@ -265,6 +266,7 @@ template <int M> struct RCBody {
         for (int k = k0; k < k1; ++k) {
             if (k > k0) __syncthreads();
             wk = a.hz ? a.hz[k] : 1.0;
+            m.fetch(k);
             m.step(k, sink);
         }
         block_sum3(acc0, acc1, acc2, s_red, RC_NT);
@@ -304,6 +306,34 @@ template <int M> static int run_rc(const XFwdArgs &a, hipStream_t s)
 int residual_check_blocks(int nx, int ny, int nz, int kr_max, int kr_nb)
 {
     switch (nx / 2) { PK_X_LENGTHS(PK_CASE_RCB) default: return -1; }
+}
+
+int x_res_slots(int nx, int xw, int p32) { return x_res_slots_f32(nx, xw, p32); }
+
+template <int M> static int rc_slots()
+{
+    static int cache[64] = {0};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int &r = cache[dev & 63];
+    if (r == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_residual_check<M>, RC_NT, 0) !=
+                hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            per_cu < 1 || cus < 1) {
+            (void)hipGetLastError();
+            return -1;
+        }
+        r = per_cu * cus;
+    }
+    return r;
+}
+#define PK_CASE_RCS(N) case N: return rc_slots<N>();
+
+int residual_check_slots(int nx)
+{
+    switch (nx / 2) { PK_X_LENGTHS(PK_CASE_RCS) default: return -1; }
 }
 
 int launch_residual_check(const XFwdArgs &a, int *nblocks_out, hipStream_t s)

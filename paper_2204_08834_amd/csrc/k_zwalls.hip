@@ -467,19 +467,27 @@ __global__ __launch_bounds__(MAXT) void k_z_walls(ZArgs a0, int C, int nspecial)
                            nspecial, smem_d);
 }
 
-// Walls along x and y, one real system per lane.  Column (m, ky) of the
-// spectrum holds the real coefficients of x-modes 2m and 2m+1 as its real
-// and imaginary parts, and the y-modes are real as well, so viewed as reals
-// the spectrum is an (nz, ny, nx) array whose entry r of row ky is the
-// coefficient of x-mode r: each (r, ky) is one real tridiagonal system with
-// s = -(lam_x(r) + lam_y(ky)) dz^2.  A lane takes one such column (a wavefront
-// reads a contiguous run of reals per plane, no lane exchange) and runs the
-// recurrences of k_z_walls on real values: half the registers of a complex
-// lane whose imaginary half is zero.  Column (0, 0) is the zero mode (FP64,
-// as in k_z_walls).
+// Walls along x and y: real systems.  Column (m, ky) of the spectrum holds
+// the real coefficients of x-modes 2m and 2m+1 as its real and imaginary
+// parts, and the y-modes are real as well, so viewed as reals the spectrum is
+// an (nz, ny, nx) array whose entry r of row ky is the coefficient of x-mode
+// r: each (r, ky) is one real tridiagonal system with
+// s = -(lam_x(r) + lam_y(ky)) dz^2.  A lane takes the ZR_V = 2 adjacent
+// systems r, r+1 of one row ky (nx is even): one 2-vector load per plane, a
+// wavefront reads contiguous runs of 2W reals, and the recurrences of
+// k_z_walls run on real values for both systems, interleaved.  The pivot
+// recurrences are serial chains of reciprocals; with one system per lane
+// the pass was bound by their latency (2.5 TB/s in FP64 at 512x512x256),
+// two independent chains per lane keep twice the bytes in flight per chain.
+// Column (0, 0) is the zero mode (FP64, as in k_z_walls): the first system
+// of the first lane.
+constexpr int ZR_V = 2;
+
 template <int L, int W, int MAXT, bool STR>
 __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
 {
+    constexpr int V = ZR_V;
+    using RV = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
     if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
     ZArgs a = a0;
     if (a.batch) {
@@ -488,8 +496,8 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
         if (a.zero_mean_out) a.zero_mean_out = pq.scal;
     }
     extern __shared__ double smem_d[];
-    R *buf = (R *)smem_d;                                       // C*W slots of 4 reals
-    double *zbuf = smem_d + ((C * W * 4 * sizeof(R) + 7) / 8);  // 3*C doubles
+    R *buf = (R *)smem_d;                                           // C*W slots of 4V reals
+    double *zbuf = smem_d + ((C * W * 4 * V * sizeof(R) + 7) / 8);  // 3*C doubles
 
     const int t = threadIdx.x;
     const int w = t % W, c = t / W;
@@ -505,52 +513,70 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
     auto zr = [&](int k, int f) -> double { return zrow[8 * k + f]; };
     const double sfac = STR ? 1.0 : a.dz2;
 
-    const int q = block_order((int)blockIdx.x, (int)gridDim.x, a.reverse) * W + w;
-    const int r = q % nx, ky = q / nx;
-    const bool active = q < ny * nx;
-    const bool zero_lane = active && q == 0 && !a.regular;
-    const double s_d = (active && !zero_lane) ? -(a.lamx[r] + a.lamy[ky]) * sfac : 1.0;
-
-    R d[L];
-    {
-        const PK_GLOBAL R *col = S + (size_t)s * plane + (active ? q : 0);
+    // systems q0 + v, v < V, of row ky
+    const int q0 = (block_order((int)blockIdx.x, (int)gridDim.x, a.reverse) * W + w) * V;
+    const int r0 = q0 % nx, ky = q0 / nx;
+    const bool active = q0 < ny * nx;
+    const bool zero_lane = active && q0 == 0 && !a.regular;
+    const R dir2 = a.dirichlet_z ? R(2) : R(0);
+    R sv[V], mw[V], mws[V], mws0[V];
 #pragma unroll
-        for (int i = 0; i < L; ++i)
-            d[i] = (active && s + i < nz)
-                       ? col[(size_t)i * plane] * R(STR ? zr(s + i, 2) * a.inv_nxny : scale)
-                       : R(0);
+    for (int v = 0; v < V; ++v) {
+        const bool zcol = zero_lane && v == 0;
+        const double s_d = (active && !zcol) ? -(a.lamx[r0 + v] + a.lamy[ky]) * sfac : 1.0;
+        sv[v] = R(s_d);
+        mw[v] = rcp_nr(R(1) + sv[v]);
+        mws[v] = sv[v] * mw[v];
+        mws0[v] = a.dirichlet_z ? (sv[v] + R(2)) * rcp_nr(sv[v] + R(3)) : mws[v];
+    }
+
+    R d[L][V];
+    {
+        const PK_GLOBAL R *col = S + (size_t)s * plane + (active ? q0 : 0);
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const R sc = R(STR ? zr(s + i, 2) * a.inv_nxny : scale);
+            RV x{R(0), R(0)};
+            if (active && s + i < nz) x = *(const PK_GLOBAL RV *)(col + (size_t)i * plane);
+            d[i][0] = x.x * sc;
+            d[i][1] = x.y * sc;
+        }
     }
     // zero wavenumber: raw values re-read (L1-resident) whenever needed
     auto zraw = [&](int k) -> double { return double(S[(size_t)k * plane]); };
 
-    const R sv = R(s_d);
-    const R mw = rcp_nr(R(1) + sv);
-    const R mws = sv * mw;
-    const R dir2 = a.dirichlet_z ? R(2) : R(0);
-    const R mws0 = a.dirichlet_z ? (sv + R(2)) * rcp_nr(sv + R(3)) : mws;
-
     // ---- phase 1: Moebius product of the chunk (v recurrence) -----------
-    R p00 = R(1), p01 = R(0), p10 = R(0), p11 = R(1);
+    R p00[V], p01[V], p10[V], p11[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        p00[v] = R(1); p01[v] = R(0); p10[v] = R(0); p11[v] = R(1);
+    }
 #pragma unroll
     for (int i = 0; i < L; ++i) {
         const int k = s + i;
-        R x0, y0;
-        if constexpr (STR) {
-            const R ak = R(zr(k, 0)), ck = R(zr(k, 1));
-            const R sd = sv * R(zr(k, 2)) + R(zr(k, 3));
-            const R inv = rcp_nr(sd + ck);
-            x0 = ck > R(0) ? ak * inv : R(0);
-            y0 = ck > R(0) ? sd * inv : R(1);
-        } else {
-            x0 = (k == 0) ? R(0) : mw;
-            y0 = (k == 0) ? mws0 : mws;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            R x0, y0;
+            if constexpr (STR) {
+                const R ak = R(zr(k, 0)), ck = R(zr(k, 1));
+                const R sd = sv[v] * R(zr(k, 2)) + R(zr(k, 3));
+                const R inv = rcp_nr(sd + ck);
+                x0 = ck > R(0) ? ak * inv : R(0);
+                y0 = ck > R(0) ? sd * inv : R(1);
+            } else {
+                x0 = (k == 0) ? R(0) : mw[v];
+                y0 = (k == 0) ? mws0[v] : mws[v];
+            }
+            const R n00 = x0 * p00[v] + y0 * p10[v], n01 = x0 * p01[v] + y0 * p11[v];
+            const R n10 = x0 * p00[v] + p10[v], n11 = x0 * p01[v] + p11[v];
+            p00[v] = n00; p01[v] = n01; p10[v] = n10; p11[v] = n11;
         }
-        const R n00 = x0 * p00 + y0 * p10, n01 = x0 * p01 + y0 * p11;
-        const R n10 = x0 * p00 + p10, n11 = x0 * p01 + p11;
-        p00 = n00; p01 = n01; p10 = n10; p11 = n11;
     }
-    R *slot = buf + (size_t)(c * W + w) * 4;
-    slot[0] = p00; slot[1] = p01; slot[2] = p10; slot[3] = p11;
+    R *slot = buf + (size_t)(c * W + w) * 4 * V;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        slot[4 * v] = p00[v]; slot[4 * v + 1] = p01[v]; slot[4 * v + 2] = p10[v]; slot[4 * v + 3] = p11[v];
+    }
     if (zero_lane) {
         double zsum = 0.0;
         for (int k = s; k < e; ++k) zsum += (STR ? zr(k, 2) : 1.0) * zraw(k);
@@ -558,22 +584,32 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
     }
     __syncthreads();  // S1
 
-    R vprev0 = R(0);
+    R vprev0[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) vprev0[v] = R(0);
     {
         int cc = 0;
-        for (; cc + 4 <= c; cc += 4) {
-            R o[4][4];
+        for (; cc + 2 <= c; cc += 2) {
+            R o[2][4 * V];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) o[u][j] = buf[(size_t)((cc + u) * W + w) * 4 + j];
+                for (int j = 0; j < 4 * V; ++j) o[u][j] = buf[(size_t)((cc + u) * W + w) * 4 * V + j];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                vprev0 = (o[u][0] * vprev0 + o[u][1]) * rcp_nr(o[u][2] * vprev0 + o[u][3]);
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const R *q = o[u] + 4 * v;
+                    vprev0[v] = (q[0] * vprev0[v] + q[1]) * rcp_nr(q[2] * vprev0[v] + q[3]);
+                }
         }
         for (; cc < c; ++cc) {
-            const R *o = buf + (size_t)(cc * W + w) * 4;
-            vprev0 = (o[0] * vprev0 + o[1]) * rcp_nr(o[2] * vprev0 + o[3]);
+            const R *o = buf + (size_t)(cc * W + w) * 4 * V;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const R *q = o + 4 * v;
+                vprev0[v] = (q[0] * vprev0[v] + q[1]) * rcp_nr(q[2] * vprev0[v] + q[3]);
+            }
         }
     }
 
@@ -597,77 +633,88 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
     __syncthreads();  // S2
 
     // ---- phase 2: local forward elimination ------------------------------
-    R vk[L];
-    R ulast = R(0);
-    {
-        R Dp = R(0), Gp = R(1), vprev = vprev0;
+    R vk[L][V];
+    R ulast[V], Dp[V], Gp[V], vprev[V];
 #pragma unroll
-        for (int i = 0; i < L; ++i) {
-            const int k = s + i;
+    for (int v = 0; v < V; ++v) {
+        ulast[v] = R(0); Dp[v] = R(0); Gp[v] = R(1); vprev[v] = vprev0[v];
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const int k = s + i;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
             if constexpr (STR) {
                 // vk holds 1/|pivot| (as in ZWBody)
                 const R ak = R(zr(k, 0)), ck = R(zr(k, 1));
-                const R ex = sv * R(zr(k, 2)) + R(zr(k, 3)) + ak * vprev;
+                const R ex = sv[v] * R(zr(k, 2)) + R(zr(k, 3)) + ak * vprev[v];
                 const R wv = rcp_nr(ck + ex);
                 const R vnew = ck > R(0) ? ex * wv : R(1);
-                Dp = (ak * Dp - d[i]) * wv;
-                Gp = ak * wv * Gp;
-                vk[i] = wv;
-                d[i] = Dp;
-                vprev = vnew;
+                Dp[v] = (ak * Dp[v] - d[i][v]) * wv;
+                Gp[v] = ak * wv * Gp[v];
+                vk[i][v] = wv;
+                d[i][v] = Dp[v];
+                vprev[v] = vnew;
             } else {
-                const R ex = (k == 0) ? sv + dir2 : sv + vprev;
+                const R ex = (k == 0) ? sv[v] + dir2 : sv[v] + vprev[v];
                 const bool last = k >= nz - 1;
-                const R piv =
-                    (nz == 1) ? sv + dir2 + dir2 : (k == nz - 1 ? ex + dir2 : R(1) + ex);
+                const R piv = (nz == 1) ? sv[v] + dir2 + dir2 : (k == nz - 1 ? ex + dir2 : R(1) + ex);
                 const R u = rcp_nr(piv);
                 const R vnew = last ? R(1) : ex * u;
-                Dp = (Dp - d[i]) * u;
-                Gp = u * Gp;
-                if (k == nz - 1) ulast = u;
-                vk[i] = vnew;
-                d[i] = Dp;
-                vprev = vnew;
+                Dp[v] = (Dp[v] - d[i][v]) * u;
+                Gp[v] = u * Gp[v];
+                if (k == nz - 1) ulast[v] = u;
+                vk[i][v] = vnew;
+                d[i][v] = Dp[v];
+                vprev[v] = vnew;
             }
         }
-        slot[0] = Dp; slot[1] = Gp;
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        slot[4 * v] = Dp[v];
+        slot[4 * v + 1] = Gp[v];
     }
     if (zero_lane) zbuf[C + c] = zsF;
     __syncthreads();  // S3
 
     {
-        R dprev = R(0);
-        int cc = 0;
-        for (; cc + 4 <= c; cc += 4) {
-            R o[4][2];
+        R dprev[V];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < V; ++v) dprev[v] = R(0);
+        for (int cc = 0; cc < c; ++cc) {
+            const R *o = buf + (size_t)(cc * W + w) * 4 * V;
 #pragma unroll
-                for (int j = 0; j < 2; ++j) o[u][j] = buf[(size_t)((cc + u) * W + w) * 4 + j];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) dprev = o[u][0] + o[u][1] * dprev;
+            for (int v = 0; v < V; ++v) dprev[v] = o[4 * v] + o[4 * v + 1] * dprev[v];
         }
-        for (; cc < c; ++cc) {
-            const R *o = buf + (size_t)(cc * W + w) * 4;
-            dprev = o[0] + o[1] * dprev;
-        }
-        R Gr = R(1);
+        R Gr[V];
 #pragma unroll
-        for (int i = 0; i < L; ++i) {
-            Gr *= STR ? R(zr(s + i, 0)) * vk[i] : ((s + i == nz - 1) ? ulast : R(1) - vk[i]);
-            d[i] = d[i] + Gr * dprev;
-        }
+        for (int v = 0; v < V; ++v) Gr[v] = R(1);
+#pragma unroll
+        for (int i = 0; i < L; ++i)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                Gr[v] *= STR ? R(zr(s + i, 0)) * vk[i][v]
+                             : ((s + i == nz - 1) ? ulast[v] : R(1) - vk[i][v]);
+                d[i][v] = d[i][v] + Gr[v] * dprev[v];
+            }
     }
     // ---- phase 3: local back substitution --------------------------------
-    R Xn = R(0), Hn = R(1);
+    R Xn[V], Hn[V];
 #pragma unroll
-    for (int i = L - 1; i >= 0; --i) {
-        const R uk = STR ? R(zr(s + i, 1)) * vk[i] : R(1) - vk[i];
-        const R X = STR ? d[i] + uk * Xn : d[i] + (Xn - vk[i] * Xn);
-        d[i] = X;
-        Xn = X;
-        Hn *= uk;
+    for (int v = 0; v < V; ++v) {
+        Xn[v] = R(0); Hn[v] = R(1);
     }
+#pragma unroll
+    for (int i = L - 1; i >= 0; --i)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const R uk = STR ? R(zr(s + i, 1)) * vk[i][v] : R(1) - vk[i][v];
+            const R X = STR ? d[i][v] + uk * Xn[v] : d[i][v] + (Xn[v] - vk[i][v] * Xn[v]);
+            d[i][v] = X;
+            Xn[v] = X;
+            Hn[v] *= uk;
+        }
     double zP0 = 0.0, zsx = 0.0;
     if (zero_lane) {
         for (int cc = 0; cc < c; ++cc) zP0 += zbuf[C + cc];
@@ -679,32 +726,33 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
         }
     }
     __syncthreads();  // S4
-    slot[0] = Xn; slot[1] = Hn;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        slot[4 * v] = Xn[v];
+        slot[4 * v + 1] = Hn[v];
+    }
     if (zero_lane) zbuf[2 * C + c] = zsx;
     __syncthreads();  // S5
 
     {
-        R y = R(0);
-        int cc = C - 1;
-        for (; cc - 4 >= c; cc -= 4) {
-            R o[4][2];
+        R y[V];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < V; ++v) y[v] = R(0);
+        for (int cc = C - 1; cc > c; --cc) {
+            const R *o = buf + (size_t)(cc * W + w) * 4 * V;
 #pragma unroll
-                for (int j = 0; j < 2; ++j) o[u][j] = buf[(size_t)((cc - u) * W + w) * 4 + j];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) y = o[u][0] + o[u][1] * y;
+            for (int v = 0; v < V; ++v) y[v] = o[4 * v] + o[4 * v + 1] * y[v];
         }
-        for (; cc > c; --cc) {
-            const R *o = buf + (size_t)(cc * W + w) * 4;
-            y = o[0] + o[1] * y;
-        }
-        R Hr = R(1);
+        R Hr[V];
 #pragma unroll
-        for (int i = L - 1; i >= 0; --i) {
-            Hr *= STR ? R(zr(s + i, 1)) * vk[i] : R(1) - vk[i];
-            d[i] = d[i] + Hr * y;
-        }
+        for (int v = 0; v < V; ++v) Hr[v] = R(1);
+#pragma unroll
+        for (int i = L - 1; i >= 0; --i)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                Hr[v] *= STR ? R(zr(s + i, 1)) * vk[i][v] : R(1) - vk[i][v];
+                d[i][v] = d[i][v] + Hr[v] * y[v];
+            }
     }
     if (zero_lane) {
         double tot = 0.0;
@@ -715,7 +763,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
         for (int i = 0; i < L; ++i) {
             const int k = s + i;
             if (k < nz) {
-                d[i] = R(xk - mean);
+                d[i][0] = R(xk - mean);
                 run += STR ? zr(k, 2) * (zraw(k) - zmu) * a.inv_nxny : (zraw(k) - zmu) * scale;
                 xk += STR ? run * zr(k, 4) : run;
             }
@@ -724,20 +772,26 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
     __syncthreads();  // S6: every zero-lane re-read of column (0,0) is done
 
     if (active) {
-        PK_GLOBAL R *col = S + (size_t)s * plane + q;
+        PK_GLOBAL R *col = S + (size_t)s * plane + q0;
 #pragma unroll
         for (int i = 0; i < L; ++i)
-            if (s + i < nz) col[(size_t)i * plane] = d[i];
+            if (s + i < nz) *(PK_GLOBAL RV *)(col + (size_t)i * plane) = RV{d[i][0], d[i][1]};
     }
 }
 
-template <int L, int W, int MAXT, bool STR>
+// W lanes (2W systems) per chunk row; workgroup size limits that leave the
+// registers the chunks hold (FP32: 16-row chunks at most 512 threads, 8-row
+// chunks 1024; FP64 half of that)
+template <int L> constexpr int zwr_maxt() { return (L == 16 ? 512 : 1024) / (sizeof(R) == 8 ? 2 : 1); }
+
+template <int L, int W, bool STR>
 static int run_zwr(const ZArgs &a, hipStream_t s)
 {
+    constexpr int MAXT = zwr_maxt<L>();
     const int C = (a.nz + L - 1) / L;
-    if (C * W > MAXT) return -1;
-    const int nb = (a.ny * a.nx + W - 1) / W;
-    const size_t shm = ((C * W * 4 * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double);
+    if (C * W > MAXT || a.nx % ZR_V != 0) return -1;
+    const int nb = (a.ny * a.nx / ZR_V + W - 1) / W;
+    const size_t shm = ((C * W * 4 * ZR_V * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double);
     hipLaunchKernelGGL((k_z_walls_r<L, W, MAXT, STR>), dim3(nb, a.batch ? a.nbatch : 1),
                        dim3(W * C), shm, s, a, C);
     return (int)hipGetLastError();
@@ -917,49 +971,36 @@ template <bool STR> static int dispatch_zw(const ZArgs &a, hipStream_t s)
     const int nz = a.nz;
     constexpr bool F32 = sizeof(R) == 4;
     if (a.xwall && a.ywall) {
-        // every column holds two real modes: one real system per lane
+        // every column holds two real modes: real systems, two per lane
         // (k_z_walls_r).  Tiles as below: 16- or 8-row chunks, 128- or
-        // 256-byte row runs.
+        // 256-byte row runs, narrowed to fit the workgroup size limit (deep
+        // grids take 8-row chunks)
         const int v = a.variant & 3;
-        const bool c8 = v == 1 || v == 3, wide = v >= 2;
-        if (nz <= 64) return run_zwr<8, 32, 256, STR>(a, s);
-        if constexpr (F32) {
-            if (!c8 && !wide) {
-                if (nz <= 128) return run_zwr<16, 32, 256, STR>(a, s);
-                if (nz <= 256) return run_zwr<16, 32, 512, STR>(a, s);
-                if (nz <= 512) return run_zwr<16, 32, 1024, STR>(a, s);
-            } else if (!c8) {
-                if (nz <= 128) return run_zwr<16, 64, 512, STR>(a, s);
-                if (nz <= 256) return run_zwr<16, 64, 1024, STR>(a, s);
-            } else if (!wide) {
-                if (nz <= 128) return run_zwr<8, 32, 512, STR>(a, s);
-                if (nz <= 256) return run_zwr<8, 32, 1024, STR>(a, s);
-            } else {
-                if (nz <= 128) return run_zwr<8, 64, 1024, STR>(a, s);
+        int L = (v == 1 || v == 3 || nz > 1024) ? 8 : 16;
+        int W = (F32 ? 16 : 8) * (v >= 2 ? 2 : 1);
+        const int maxt = L == 16 ? zwr_maxt<16>() : zwr_maxt<8>();
+        const int C = (nz + L - 1) / L;
+        while (W > 1 && C * W > maxt) W /= 2;
+        // shallow grids: wider workgroups
+        while (W < 32 && C * W < 256 && 2 * C * W <= maxt) W *= 2;
+        if (L == 16) {
+            switch (W) {
+            case 32: return run_zwr<16, 32, STR>(a, s);
+            case 16: return run_zwr<16, 16, STR>(a, s);
+            case 8: return run_zwr<16, 8, STR>(a, s);
+            case 4: return run_zwr<16, 4, STR>(a, s);
+            default: return -1;
             }
-        } else {
-            if (!c8 && !wide) {
-                if (nz <= 256) return run_zwr<16, 16, 256, STR>(a, s);
-                if (nz <= 512) return run_zwr<16, 16, 512, STR>(a, s);
-            } else if (!c8) {
-                if (nz <= 128) return run_zwr<16, 32, 256, STR>(a, s);
-                if (nz <= 256) return run_zwr<16, 32, 512, STR>(a, s);
-            } else if (!wide) {
-                if (nz <= 128) return run_zwr<8, 16, 256, STR>(a, s);
-                if (nz <= 256) return run_zwr<8, 16, 512, STR>(a, s);
-                if (nz <= 512) return run_zwr<8, 16, 1024, STR>(a, s);
-            } else {
-                if (nz <= 128) return run_zwr<8, 32, 512, STR>(a, s);
-                if (nz <= 256) return run_zwr<8, 32, 1024, STR>(a, s);
-            }
-            if (nz <= 512) return run_zwr<16, 16, 512, STR>(a, s);
         }
-        // beyond the variant's reach: narrower tiles of 8-row chunks (a
-        // 1024-thread workgroup of 16-row chunks would spill registers)
-        if (nz <= 1024) return run_zwr<8, 8, 1024, STR>(a, s);
-        if (nz <= 2048) return run_zwr<8, 4, 1024, STR>(a, s);
-        if (nz <= 4096) return run_zwr<8, 2, 1024, STR>(a, s);
-        return -1;
+        switch (W) {
+        case 32: return run_zwr<8, 32, STR>(a, s);
+        case 16: return run_zwr<8, 16, STR>(a, s);
+        case 8: return run_zwr<8, 8, STR>(a, s);
+        case 4: return run_zwr<8, 4, STR>(a, s);
+        case 2: return run_zwr<8, 2, STR>(a, s);
+        case 1: return run_zwr<8, 1, STR>(a, s);
+        default: return -1;
+        }
     }
     const bool c8 = a.variant == 1 || a.variant == 3;
     // walls along x: every column is a two-mode column whose lane halves

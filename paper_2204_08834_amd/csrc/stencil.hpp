@@ -37,9 +37,12 @@ __host__ __device__ constexpr int march_jblocks(int ny, int tj) { return (ny + t
 // fill the device.  nb is the size of the problem group, not the number of
 // problems a launch still serves, so that every launch of the group tiles
 // and sums the same way.  Each range re-reads two planes of p, so deeper
-// ranges read less.
+// ranges read less.  A negative kr_max is an exact depth (-kr_max planes,
+// no halving): the plan picks it so that the workgroups fill the resident
+// slots of the device in whole rounds.
 __host__ __device__ constexpr int march_planes(int ny, int nz, int tj, int kr_max, int nb = 1)
 {
+    if (kr_max < 0) return -kr_max < nz ? -kr_max : (nz > 0 ? nz : 1);
     int kr = kr_max > 0 ? kr_max : 8;
     const int b = nb > 1 ? nb : 1;
     while (kr > 1 && march_jblocks(ny, tj) * ((nz + kr - 1) / kr) * b < 1024) kr /= 2;
@@ -126,17 +129,13 @@ struct MarchIdx {
     }
 };
 
-// an element pair of p as FP64: p stored in FP64, or (the refinement's first
-// iterate) in FP32, widened exactly
-__device__ __forceinline__ double2 ld_pair(const PK_GLOBAL double *p)
-{
-    return *(const PK_GLOBAL double2 *)p;
-}
-__device__ __forceinline__ double2 ld_pair(const PK_GLOBAL float *p)
-{
-    const float2 v = *(const PK_GLOBAL float2 *)p;
-    return double2{(double)v.x, (double)v.y};
-}
+// a pair of p as stored (FP64, or FP32 for the first iterate) and its exact
+// FP64 value
+template <class T> struct Pair;
+template <> struct Pair<double> { using type = double2; };
+template <> struct Pair<float> { using type = float2; };
+__device__ __forceinline__ double2 widen(double2 v) { return v; }
+__device__ __forceinline__ double2 widen(float2 v) { return double2{(double)v.x, (double)v.y}; }
 
 template <int M, int TJ, int NT, class PT = double>
 struct PlaneMarch : MarchIdx<M, TJ, NT> {
@@ -159,7 +158,16 @@ struct PlaneMarch : MarchIdx<M, TJ, NT> {
     double ax, ay, az, mu;
     const double *zc = nullptr;  // stretched z: per-plane coefficients (XFwdArgs::zc)
     double2 (*tile)[M];  // LDS, TJ + 2 rows
-    double2 pd[PER], pc[PER];
+
+    // p is held as loaded (FP32 pairs for the refinement's first iterate,
+    // widened exactly where used): planes k-1 and k, and the inputs of step
+    // k that fetch(k) loads -- p at plane k+1, f at plane k and the two halo
+    // rows of plane k.
+    using P2 = typename Pair<PT>::type;
+    static constexpr int HPER = (M + NT - 1) / NT;  // halo pairs per thread
+    P2 pd[PER], pc[PER];
+    P2 pun[PER], hmn[HPER], hnn[HPER];
+    double2 fvn[PER];
 
     // p at planes k0-1 and k0 into registers.  Elements past the last row
     // of the grid load from the start of the plane (in bounds, never used):
@@ -169,55 +177,74 @@ struct PlaneMarch : MarchIdx<M, TJ, NT> {
         const PK_GLOBAL PT *pdn = p + (size_t)kdown(k0) * plane;
         const PK_GLOBAL PT *pcn = p + (size_t)k0 * plane;
         // below a Dirichlet bottom wall the ghost plane is -p(0)
-        const double gs = (k0 == 0 && this->bc_z == 2) ? -1.0 : 1.0;
+        const PT gs = (k0 == 0 && this->bc_z == 2) ? PT(-1) : PT(1);
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int o = roff(q);
-            const double2 x = ld_pair(pdn + o);
-            pd[q] = double2{gs * x.x, gs * x.y};
-            pc[q] = ld_pair(pcn + o);
+            const P2 x = *(const PK_GLOBAL P2 *)(pdn + o);
+            pd[q] = P2{gs * x.x, gs * x.y};
+            pc[q] = *(const PK_GLOBAL P2 *)(pcn + o);
         }
     }
 
-    // Residual at plane k: sink(q, t, h, r0, r1, f0, f1, pc) for every valid
-    // element (row j0 + t, pair h).  The caller syncs before the next step
-    // (the LDS tile is rewritten).
-    template <class Sink>
-    __device__ __forceinline__ void step(int k, Sink &sink)
+    // The loads of step k (the halo rows of plane k, p at plane k+1, f at
+    // plane k); halo lanes past the row load pair 0 (in bounds, never used).
+    // The halo rows go first: loads complete in issue order, so the wait for
+    // the halo rows (staged in LDS before the barrier of step k) leaves the
+    // other loads in flight across that barrier.  Issued last, the halo
+    // loads made the check 5 % slower on MI355X.
+    __device__ __forceinline__ void fetch(int k)
     {
         const PK_GLOBAL PT *pup = p + (size_t)kup(k) * plane;
         const PK_GLOBAL double *fk = f + (size_t)k * plane;
         const PK_GLOBAL PT *pk_ = p + (size_t)k * plane;
-        // above a Dirichlet top wall the ghost plane is -p(nz-1)
-        const double gs = (k == this->nz - 1 && this->bc_z == 2) ? -1.0 : 1.0;
-        double2 pu[PER], fv[PER];
+#pragma unroll
+        for (int i = 0; i < HPER; ++i) {
+            const int h = threadIdx.x + i * NT;
+            const int hc = (M % NT == 0 || h < M) ? h : 0;
+            hmn[i] = *(const PK_GLOBAL P2 *)(pk_ + (size_t)jm * NX + 2 * hc);
+            hnn[i] = *(const PK_GLOBAL P2 *)(pk_ + (size_t)jn * NX + 2 * hc);
+        }
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int o = roff(q);
-            const double2 x = ld_pair(pup + o);
-            pu[q] = double2{gs * x.x, gs * x.y};
-            fv[q] = *(const PK_GLOBAL double2 *)(fk + o);
+            pun[q] = *(const PK_GLOBAL P2 *)(pup + o);
+            fvn[q] = *(const PK_GLOBAL double2 *)(fk + o);
         }
+    }
+
+    // Residual at plane k from the inputs fetch(k) loaded: sink(q, t, h, r0,
+    // r1, f0, f1, pc) for every valid element (row j0 + t, pair h).  The
+    // caller syncs before the next step (the LDS tile is rewritten).
+    template <class Sink>
+    __device__ __forceinline__ void step(int k, Sink &sink)
+    {
+        // above a Dirichlet top wall the ghost plane is -p(nz-1)
+        const PT gs = (k == this->nz - 1 && this->bc_z == 2) ? PT(-1) : PT(1);
         const double sm = this->sm, sn = this->sn;
         // stretched z: the fluxes through the faces below and above
         const bool zs = zc != nullptr;
         const double czm = zs ? zc[2 * k] : 0.0, czp = zs ? zc[2 * k + 1] : 0.0;
-        for (int h = threadIdx.x; h < M; h += NT) {
-            const double2 a = ld_pair(pk_ + (size_t)jm * NX + 2 * h);
-            const double2 b = ld_pair(pk_ + (size_t)jn * NX + 2 * h);
-            tile[0][h] = double2{sm * a.x, sm * a.y};
-            tile[V + 1][h] = double2{sn * b.x, sn * b.y};
+#pragma unroll
+        for (int i = 0; i < HPER; ++i) {
+            const int h = threadIdx.x + i * NT;
+            if (M % NT == 0 || h < M) {
+                const double2 a = widen(hmn[i]), b = widen(hnn[i]);
+                tile[0][h] = double2{sm * a.x, sm * a.y};
+                tile[V + 1][h] = double2{sn * b.x, sn * b.y};
+            }
         }
 #pragma unroll
         for (int q = 0; q < PER; ++q)
-            if (valid(q)) tile[row_of(q) + 1][pair_of(q)] = pc[q];
+            if (valid(q)) tile[row_of(q) + 1][pair_of(q)] = widen(pc[q]);
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
+            pun[q] = P2{gs * pun[q].x, gs * pun[q].y};
             if (valid(q)) {
                 const int t = row_of(q), h = pair_of(q);
                 const double2 ps = tile[t][h], pn = tile[t + 2][h];
-                const double2 c = pc[q], d = pd[q], u = pu[q];
+                const double2 c = widen(pc[q]), d = widen(pd[q]), u = widen(pun[q]);
                 // x neighbours; at walls along x the ghost is the wall cell
                 // (Neumann) or its negation (Dirichlet)
                 const int bx = this->bc_x;
@@ -231,14 +258,14 @@ struct PlaneMarch : MarchIdx<M, TJ, NT> {
                                      : az * (u.y - 2.0 * c.y + d.y);
                 const double l0 = ax * (c.y - 2.0 * c.x + pl) + ay * (pn.x - 2.0 * c.x + ps.x) + z0;
                 const double l1 = ax * (pq - 2.0 * c.y + c.x) + ay * (pn.y - 2.0 * c.y + ps.y) + z1;
-                const double f0 = fv[q].x - mu, f1 = fv[q].y - mu;
+                const double f0 = fvn[q].x - mu, f1 = fvn[q].y - mu;
                 sink(q, t, h, f0 - l0, f1 - l1, f0, f1, c);
             }
         }
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             pd[q] = pc[q];
-            pc[q] = pu[q];
+            pc[q] = pun[q];
         }
     }
 };

@@ -111,13 +111,15 @@ def test_batch_autotune_and_describe():
     bp.close()
 
 
-@pytest.mark.parametrize("planes", [4, 8, 16])
-def test_march_depths(planes, monkeypatch):
-    """Every plane-range depth of the residual passes: converged solves, and
-    the device-side loop (whose sum counts the march grid) equal to the host
-    loop bitwise."""
+@pytest.mark.parametrize("planes,check", [(4, 4), (8, 8), (16, 16), (5, 3), (43, 22), (7, 40)])
+def test_march_depths(planes, check, monkeypatch):
+    """Every plane-range depth of the residual passes (4, 8, 16: halved for
+    small grids; others exact, uneven last range included): converged solves,
+    and the device-side loop (whose sum counts the march grid) equal to the
+    host loop bitwise."""
     P = _gpu()
     monkeypatch.setenv("POISSON_MARCH_PLANES", str(planes))
+    monkeypatch.setenv("POISSON_CHECK_PLANES", str(check))
     for name, shape in (("rb512", (128, 128, 96)), ("hit256", (64, 64, 64)), ("rb512", (96, 48, 36))):
         prob = inputs.scaled(name, *shape, seed=81)
         sp = prob.spacings()
@@ -127,7 +129,9 @@ def test_march_depths(planes, monkeypatch):
             with P.Plan(prob.nx, prob.ny, prob.nz, *sp, prob.bc_z, "fp32_refine") as plan:
                 plan.set_graph(mode)
                 out, st = plan.solve(rhs)
-                assert f"march_planes={planes}" in plan.describe()
+                # the plan's depth settings (an exact depth beyond the grid
+                # runs as one range of all planes)
+                assert f"march_planes={planes} check_planes={check} " in plan.describe()
                 torch.cuda.synchronize()
             res[mode] = (out.cpu().numpy(), st)
         assert res["host"][1]["status"] == 0 and res["host"][1]["rel_residual"] <= 1e-10
