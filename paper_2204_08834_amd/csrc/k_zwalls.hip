@@ -80,6 +80,22 @@ __device__ __forceinline__ double rcp_nr(double x)
     return fma(fma(-x, r, 1.0), r, r);
 }
 
+// Index of field f of the LDS slot of chunk cc, lane w (C chunks of W
+// lanes): the fields of a slot are grouped by P, and group g of every
+// (chunk, lane) is stored lane-contiguous, so that a wavefront reading or
+// writing one group of its lanes' slots touches consecutive words (no LDS
+// bank conflicts).  P = 1 stores every field lane-contiguous; P = 4 with
+// FP32 gives one 16-byte access per lane and group.  A slot of consecutive
+// reals per lane (the layout before) put the lanes of the FP64 and real
+// solves 32-64 bytes apart: bank conflicts took most of their cycles.
+// Measured at 512x512x256: P = 4 for complex FP32 columns (94 against 101
+// us), P = 1 for FP64 and for the real systems (FP32 113 against 139 us).
+template <int P>
+__device__ __forceinline__ size_t zw_slot(int f, int cc, int w, int C, int W)
+{
+    return (((size_t)(f / P) * C + cc) * W + w) * P + (f % P);
+}
+
 // One workgroup's work (block vb.x of problem vb.y): C chunks of L rows of W
 // columns; `smem_d` holds the dynamic LDS of zw_lds_bytes().
 template <int L, int W, bool STR = false> struct ZWBody {
@@ -93,11 +109,14 @@ template <int L, int W, bool STR = false> struct ZWBody {
             a.S = pq.S;
             if (a.zero_mean_out) a.zero_mean_out = pq.scal;
         }
-        R *buf = (R *)smem_d;                                       // C*W slots of 4 reals
+        // C*W slots of 4 reals in lane-contiguous groups (zw_slot)
+        R *buf = (R *)smem_d;
         double *zbuf = smem_d + ((C * W * 4 * sizeof(R) + 7) / 8);  // 3*C doubles
 
         const int t = threadIdx.x;
         const int w = t % W, c = t / W;
+        constexpr int P = sizeof(R) == 4 ? 4 : 1;
+        auto sl = [&](int f, int cc) -> R & { return buf[zw_slot<P>(f, cc, w, C, W)]; };
         const int nz = a.nz, M = a.M, ny = a.ny;
         const size_t plane = (size_t)ny * M;
         PK_GLOBAL Cx<R> *S = gbl((Cx<R> *)a.S);
@@ -223,8 +242,7 @@ template <int L, int W, bool STR = false> struct ZWBody {
             const R n10 = a0 * p00 + p10, n11 = a0 * p01 + p11;
             p00 = n00; p01 = n01; p10 = n10; p11 = n11;
         }
-        R *slot = buf + (size_t)(c * W + w) * 4;
-        slot[0] = p00; slot[1] = p01; slot[2] = p10; slot[3] = p11;
+        sl(0, c) = p00; sl(1, c) = p01; sl(2, c) = p10; sl(3, c) = p11;
         if (zero_lane) {
             double zsum = 0.0;
             for (int k = s; k < e; ++k) zsum += (STR ? zr(k, 2) : 1.0) * zraw(k);
@@ -243,15 +261,13 @@ template <int L, int W, bool STR = false> struct ZWBody {
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) o[u][e] = buf[(size_t)((cc + u) * W + w) * 4 + e];
+                    for (int e = 0; e < 4; ++e) o[u][e] = sl(e, cc + u);
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
                     vprev0 = (o[u][0] * vprev0 + o[u][1]) * rcp_nr(o[u][2] * vprev0 + o[u][3]);
             }
-            for (; cc < c; ++cc) {
-                const R *o = buf + (size_t)(cc * W + w) * 4;
-                vprev0 = (o[0] * vprev0 + o[1]) * rcp_nr(o[2] * vprev0 + o[3]);
-            }
+            for (; cc < c; ++cc)
+                vprev0 = (sl(0, cc) * vprev0 + sl(1, cc)) * rcp_nr(sl(2, cc) * vprev0 + sl(3, cc));
         }
 
         // zero wavenumber, FP64: g = (raw - mean raw) * scale; face fluxes
@@ -319,7 +335,7 @@ template <int L, int W, bool STR = false> struct ZWBody {
                     vprev = vnew;
                 }
             }
-            slot[0] = Dp.re; slot[1] = Dp.im; slot[2] = Gp;
+            sl(0, c) = Dp.re; sl(1, c) = Dp.im; sl(2, c) = Gp;
         }
         if (zero_lane) zbuf[C + c] = zsF;
         __syncthreads();  // S3
@@ -332,15 +348,13 @@ template <int L, int W, bool STR = false> struct ZWBody {
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
-                    for (int e = 0; e < 3; ++e) o[u][e] = buf[(size_t)((cc + u) * W + w) * 4 + e];
+                    for (int e = 0; e < 3; ++e) o[u][e] = sl(e, cc + u);
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
                     dprev = {o[u][0] + o[u][2] * dprev.re, o[u][1] + o[u][2] * dprev.im};
             }
-            for (; cc < c; ++cc) {
-                const R *o = buf + (size_t)(cc * W + w) * 4;
-                dprev = {o[0] + o[2] * dprev.re, o[1] + o[2] * dprev.im};
-            }
+            for (; cc < c; ++cc)
+                dprev = {sl(0, cc) + sl(2, cc) * dprev.re, sl(1, cc) + sl(2, cc) * dprev.im};
             R Gr = R(1);
 #pragma unroll
             for (int i = 0; i < L; ++i) {
@@ -377,7 +391,7 @@ template <int L, int W, bool STR = false> struct ZWBody {
             }
         }
         __syncthreads();  // S4: slots consumed
-        slot[0] = Xn.re; slot[1] = Xn.im; slot[2] = Hn;
+        sl(0, c) = Xn.re; sl(1, c) = Xn.im; sl(2, c) = Hn;
         if (zero_lane) zbuf[2 * C + c] = zsx;
         __syncthreads();  // S5
 
@@ -389,14 +403,11 @@ template <int L, int W, bool STR = false> struct ZWBody {
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
-                    for (int e = 0; e < 3; ++e) o[u][e] = buf[(size_t)((cc - u) * W + w) * 4 + e];
+                    for (int e = 0; e < 3; ++e) o[u][e] = sl(e, cc - u);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) y = {o[u][0] + o[u][2] * y.re, o[u][1] + o[u][2] * y.im};
             }
-            for (; cc > c; --cc) {
-                const R *o = buf + (size_t)(cc * W + w) * 4;
-                y = {o[0] + o[2] * y.re, o[1] + o[2] * y.im};
-            }
+            for (; cc > c; --cc) y = {sl(0, cc) + sl(2, cc) * y.re, sl(1, cc) + sl(2, cc) * y.im};
             R Hr = R(1);
 #pragma unroll
             for (int i = L - 1; i >= 0; --i) {
@@ -496,11 +507,13 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
         if (a.zero_mean_out) a.zero_mean_out = pq.scal;
     }
     extern __shared__ double smem_d[];
-    R *buf = (R *)smem_d;                                           // C*W slots of 4V reals
+    // C*W slots of 4V reals, every field lane-contiguous (zw_slot)
+    R *buf = (R *)smem_d;
     double *zbuf = smem_d + ((C * W * 4 * V * sizeof(R) + 7) / 8);  // 3*C doubles
 
     const int t = threadIdx.x;
     const int w = t % W, c = t / W;
+    auto sl = [&](int f, int cc) -> R & { return buf[zw_slot<1>(f, cc, w, C, W)]; };
     const int nz = a.nz, nx = a.nx, ny = a.ny;
     const size_t plane = (size_t)ny * nx;  // reals per z-plane
     PK_GLOBAL R *S = gbl((R *)a.S);
@@ -572,10 +585,9 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
             p00[v] = n00; p01[v] = n01; p10[v] = n10; p11[v] = n11;
         }
     }
-    R *slot = buf + (size_t)(c * W + w) * 4 * V;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        slot[4 * v] = p00[v]; slot[4 * v + 1] = p01[v]; slot[4 * v + 2] = p10[v]; slot[4 * v + 3] = p11[v];
+        sl(4 * v, c) = p00[v]; sl(4 * v + 1, c) = p01[v]; sl(4 * v + 2, c) = p10[v]; sl(4 * v + 3, c) = p11[v];
     }
     if (zero_lane) {
         double zsum = 0.0;
@@ -594,7 +606,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
 #pragma unroll
             for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int j = 0; j < 4 * V; ++j) o[u][j] = buf[(size_t)((cc + u) * W + w) * 4 * V + j];
+                for (int j = 0; j < 4 * V; ++j) o[u][j] = sl(j, cc + u);
 #pragma unroll
             for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -604,12 +616,10 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
                 }
         }
         for (; cc < c; ++cc) {
-            const R *o = buf + (size_t)(cc * W + w) * 4 * V;
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const R *q = o + 4 * v;
-                vprev0[v] = (q[0] * vprev0[v] + q[1]) * rcp_nr(q[2] * vprev0[v] + q[3]);
-            }
+            for (int v = 0; v < V; ++v)
+                vprev0[v] = (sl(4 * v, cc) * vprev0[v] + sl(4 * v + 1, cc)) *
+                            rcp_nr(sl(4 * v + 2, cc) * vprev0[v] + sl(4 * v + 3, cc));
         }
     }
 
@@ -672,8 +682,8 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
     }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        slot[4 * v] = Dp[v];
-        slot[4 * v + 1] = Gp[v];
+        sl(4 * v, c) = Dp[v];
+        sl(4 * v + 1, c) = Gp[v];
     }
     if (zero_lane) zbuf[C + c] = zsF;
     __syncthreads();  // S3
@@ -682,11 +692,9 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
         R dprev[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) dprev[v] = R(0);
-        for (int cc = 0; cc < c; ++cc) {
-            const R *o = buf + (size_t)(cc * W + w) * 4 * V;
+        for (int cc = 0; cc < c; ++cc)
 #pragma unroll
-            for (int v = 0; v < V; ++v) dprev[v] = o[4 * v] + o[4 * v + 1] * dprev[v];
-        }
+            for (int v = 0; v < V; ++v) dprev[v] = sl(4 * v, cc) + sl(4 * v + 1, cc) * dprev[v];
         R Gr[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) Gr[v] = R(1);
@@ -728,8 +736,8 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
     __syncthreads();  // S4
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        slot[4 * v] = Xn[v];
-        slot[4 * v + 1] = Hn[v];
+        sl(4 * v, c) = Xn[v];
+        sl(4 * v + 1, c) = Hn[v];
     }
     if (zero_lane) zbuf[2 * C + c] = zsx;
     __syncthreads();  // S5
@@ -738,11 +746,9 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
         R y[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) y[v] = R(0);
-        for (int cc = C - 1; cc > c; --cc) {
-            const R *o = buf + (size_t)(cc * W + w) * 4 * V;
+        for (int cc = C - 1; cc > c; --cc)
 #pragma unroll
-            for (int v = 0; v < V; ++v) y[v] = o[4 * v] + o[4 * v + 1] * y[v];
-        }
+            for (int v = 0; v < V; ++v) y[v] = sl(4 * v, cc) + sl(4 * v + 1, cc) * y[v];
         R Hr[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) Hr[v] = R(1);
