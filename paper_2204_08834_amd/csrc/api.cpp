@@ -1679,7 +1679,7 @@ int autotune_group(poisson_plan p, Group &g)
     // last-level cache
     auto whole = [&] { return solve_passes(L, false, false); };
     if (g.d.bc_z != POISSON_BC_PERIODIC) pick(g.tune.zv, 4, whole);
-    if (g.d.ny >= 64 && g.d.bc_y == POISSON_BC_PERIODIC) pick(g.tune.yv, 4, whole);
+    if (g.d.ny >= 64) pick(g.tune.yv, g.d.bc_y == POISSON_BC_PERIODIC ? 4 : 2, whole);
     pick(g.tune.rev, 2, whole);
     if (p->precision == POISSON_FP32_REFINE) {
         // plane-range depths of the residual pass with transform and of the

@@ -135,7 +135,12 @@ template <int N> struct YWCfg {
 
 __device__ __forceinline__ int wall_reorder(int j, int n) { return 2 * j < n ? 2 * j : 2 * n - 1 - 2 * j; }
 
-template <int N, bool INV>
+// WV (autotuned variant) of the forward pass: bit 0 takes the transform's
+// last pass into the LDS tile and combines the coefficient pairs from there
+// (as the lengths whose last pass has an odd number of butterflies do)
+// instead of the fused pair pass (FP64 at 512x512x256: 210 against 227 us;
+// FP32 alike)
+template <int N, bool INV, int WV>
 __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
 {
     if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
@@ -155,7 +160,12 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
     const int k = bid / ntile;
     const int m0 = tile_i * NB;
     load_table(s_tw, (const Cx<R> *)a.tw, N);
-    if constexpr (C::W4_LDS) load_table(s_w4l, (const Cx<R> *)a.tw4, N);
+    if constexpr (C::W4_LDS) {
+        // the forward pass keeps w_k / 2 (exact: a power-of-two scaling)
+        const Cx<R> *src = (const Cx<R> *)a.tw4;
+        for (int t = threadIdx.x; t < N; t += NT)
+            s_w4l[t] = INV ? src[t] : Cx<R>{src[t].re * R(0.5), src[t].im * R(0.5)};
+    }
     __syncthreads();
     auto w4 = [&]() {
         if constexpr (C::W4_LDS)
@@ -163,6 +173,12 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
         else
             return gbl((const Cx<R> *)a.tw4);
     }();
+    // w_k / 2 for the forward pass
+    auto whalf = [&](int kk) -> Cx<R> {
+        const Cx<R> w = w4[kk];
+        if constexpr (C::W4_LDS) return w;
+        return Cx<R>{w.re * R(0.5), w.im * R(0.5)};
+    };
 
     const int M = a.M;
     PK_GLOBAL Cx<R> *base = gbl((Cx<R> *)a.S) + (size_t)k * N * M + m0;
@@ -178,7 +194,7 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
         auto lstore = [&](int b, int n, Cx<R> v) { out.at(b, n) = v; };
         constexpr RPlan pl = make_rplan(N);
         constexpr int LR = pl.count >= 2 ? pl.r[pl.count - 1] : 1;
-        if constexpr (pl.count >= 2 && (N / LR) % 2 == 0) {
+        if constexpr (pl.count >= 2 && (N / LR) % 2 == 0 && (WV & 1) == 0) {
             // every pass but the last into LDS; the last pass with butterfly
             // pairs (p, NJ - p) (or (0, NJ/2)), so that V[k] and V[N-k] meet in
             // one thread and the coefficients are stored from registers:
@@ -189,13 +205,18 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
             constexpr int RAD = LR, NJ = N / LR, U = NJ / 2, NU = NB * U;
             constexpr int PER = (NU + NT - 1) / NT;
             auto emit = [&](int b, int kk, Cx<R> vk, Cx<R> vc) {
-                const Cx<R> w = w4[kk];
+                // with S = V[k] + V[N-k], D = V[k] - V[N-k] and h = w/2:
+                //   C[k]   = h_k S + i h_k^i D   = (h^r S^r - h^i D^i, h^r S^i + h^i D^r),
+                //   C[N-k] = h_{N-k} S - i h^i D (the same S and D)
+                const Cx<R> S = {vk.re + vc.re, vk.im + vc.im};
+                const Cx<R> D = {vk.re - vc.re, vk.im - vc.im};
+                const Cx<R> h = whalf(kk);
                 put(base + (size_t)(sine ? N - 1 - kk : kk) * M + b,
-                    cscale(cadd(cmul(w, vk), cmul(cconj(w), vc)), R(0.5)));
+                    Cx<R>{h.re * S.re - h.im * D.im, h.re * S.im + h.im * D.re});
                 if (kk != 0 && 2 * kk != N) {
-                    const Cx<R> w2 = w4[N - kk];
+                    const Cx<R> h2 = whalf(N - kk);
                     put(base + (size_t)(sine ? kk - 1 : N - kk) * M + b,
-                        cscale(cadd(cmul(w2, vc), cmul(cconj(w2), vk)), R(0.5)));
+                        Cx<R>{h2.re * S.re + h2.im * D.im, h2.re * S.im - h2.im * D.re});
                 }
             };
 #pragma unroll
@@ -239,16 +260,20 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
             for (int e = threadIdx.x; e < NB * N; e += NT) {
                 const int b = e % NB, kk = e / NB;
                 if (m0 + b >= M) continue;
-                const Cx<R> w = w4[kk];
+                const Cx<R> h = whalf(kk);
                 const Cx<R> v1 = out.at(b, kk), v2 = out.at(b, kk == 0 ? 0 : N - kk);
-                const Cx<R> c = cscale(cadd(cmul(w, v1), cmul(cconj(w), v2)), R(0.5));
-                put(base + (size_t)(sine ? N - 1 - kk : kk) * M + b, c);
+                const Cx<R> S = {v1.re + v2.re, v1.im + v2.im};
+                const Cx<R> D = {v1.re - v2.re, v1.im - v2.im};
+                put(base + (size_t)(sine ? N - 1 - kk : kk) * M + b,
+                    Cx<R>{h.re * S.re - h.im * D.im, h.re * S.im + h.im * D.re});
             }
         }
     } else {
         // W[k] = conj(w_k) (C[k] - i C[n-k]) formed in pass 0's loads from the
         // coefficient rows k and n-k (C[n] = 0; read reversed for sines); the
-        // inverse FFT as conj(FFT(conj))
+        // inverse FFT as conj(FFT(conj)).  (Staging the rows in the tile
+        // first, one read of each, measured slower on MI355X: the second
+        // read of a row hits the caches.)
         auto coef = [&](int b, int kk) -> Cx<R> {
             if (kk >= N) return {R(0), R(0)};
             const Cx<R> g = base[(size_t)(sine ? N - 1 - kk : kk) * M + b];
@@ -275,9 +300,11 @@ template <int N> static int run_yw(const YArgs &a, hipStream_t s)
     const int ntile = (a.M + C::NB - 1) / C::NB;
     const dim3 grid(ntile * a.nz, a.batch ? a.nbatch : 1);
     if (a.inverse)
-        hipLaunchKernelGGL((k_yw<N, true>), grid, dim3(C::NT), 0, s, a);
+        hipLaunchKernelGGL((k_yw<N, true, 0>), grid, dim3(C::NT), 0, s, a);
+    else if (a.variant & 1)
+        hipLaunchKernelGGL((k_yw<N, false, 1>), grid, dim3(C::NT), 0, s, a);
     else
-        hipLaunchKernelGGL((k_yw<N, false>), grid, dim3(C::NT), 0, s, a);
+        hipLaunchKernelGGL((k_yw<N, false, 0>), grid, dim3(C::NT), 0, s, a);
     return (int)hipGetLastError();
 }
 

@@ -255,6 +255,32 @@ def test_y_walls_match_oracle(orc, case, bc_y):
             assert err <= max(2e-5, 8 * k * 6e-8), (err, k)
 
 
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("bc_y", [NEU, DIR])
+def test_y_walls_forward_variants(orc, variant, bc_y, monkeypatch):
+    """Both forms of the wall-y forward pass (fused coefficient pairs in the
+    last transform pass, or the pairs combined from the LDS tile) against the
+    oracle, over lengths with one, two and three radix passes."""
+    P = _gpu()
+    monkeypatch.setenv("POISSON_Y_VARIANT", str(variant))
+    for (nx, ny, nz), bc_z in [((16, 12, 10), NEU), ((8, 3, 5), DIR), ((12, 96, 6), PER),
+                               ((4, 512, 3), NEU), ((2, 2048, 2), DIR), ((6, 768, 4), NEU)]:
+        sp = (BOX[0] / nx, BOX[1] / ny, BOX[2] / nz)
+        bcs = (PER, bc_y, bc_z)
+        f = inputs.random_rhs(nx, ny, nz, seed=3 * nx + ny + nz + bc_y, zero_mean=False) + 0.25
+        p_ref = orc.solve(f, *sp, bc_z, bc_y=bc_y)
+        k = kappa(nx, ny, nz, sp, bcs)
+        for prec in ("fp64", "fp32"):
+            print(f"[walls] y variant {variant} {nx}x{ny}x{nz} y{bc_y} z{bc_z} {prec}", flush=True)
+            p, st = gpu_solve(P, f, sp, bcs, prec)
+            assert st["status"] == 0, st
+            err = rel(p, p_ref)
+            if prec == "fp64":
+                assert err <= max(1e-12, 4 * k * 2.2e-16), (err, k)
+            else:
+                assert err <= max(2e-5, 8 * k * 6e-8), (err, k)
+
+
 @pytest.mark.parametrize("bcs", [(PER, NEU, NEU), (PER, DIR, NEU), (PER, NEU, PER),
                                  (PER, DIR, DIR)])
 def test_y_walls_eigenmode(bcs):
