@@ -362,9 +362,20 @@ def bench_stretched(steps, warmup, tune):
         for _ in range(warmup):
             plan.solve(f, out)
         ms, st = time_solves(plan, f, out, steps, sync_each=True)
+        plan.set_timing(True)
+        plan.reset_timing()
+        for _ in range(steps):
+            plan.solve(f, out)
+        passes = plan.timing()
+        schedule = plan.describe().strip()
         plan.close()
         res[prec] = {"ms_per_step": ms, "mpoints_s": npts / (ms * 1e-3) / 1e6,
-                     "rel_residual": st["rel_residual"], "iterations": st["iterations"]}
+                     "rel_residual": st["rel_residual"], "iterations": st["iterations"],
+                     "schedule": schedule,
+                     "passes": {k: {"avg_ms": v["total_ms"] / v["launches"],
+                                    "gbs": v["bytes_per_launch"] / (v["total_ms"] / v["launches"]
+                                                                    * 1e-3) / 1e9}
+                                for k, v in passes.items() if v["launches"]}}
         print(f"[bench] stretched {prec} {ms:.3f} ms/solve", file=sys.stderr, flush=True)
     return res
 

@@ -130,6 +130,20 @@ template <int L, int W, bool STR = false> struct ZWBody {
         const double *zrow = a.zrow;
         auto zr = [&](int k, int f) -> double { return zrow[8 * k + f]; };
         const double sfac = STR ? 1.0 : a.dz2;
+        // stretched rows in FP32: a, c, h and D of every row (padding rows
+        // included) staged in LDS, since the recurrences read them on their
+        // dependency chains (FP32 z pass at 512x512x256: 141 against 190 us;
+        // FP64 keeps the cached global reads: the staged form needs more
+        // registers than its 16-row chunks leave, 338 against 292 us)
+        constexpr bool ZSTAGE = STR && sizeof(R) == 4;
+        R *ztab = (R *)(zbuf + 3 * C);
+        if constexpr (ZSTAGE) {
+            for (int i = t; i < C * L; i += W * C)
+#pragma unroll
+                for (int f = 0; f < 4; ++f) ztab[4 * i + f] = R(zr(i, f));
+            __syncthreads();
+        }
+        auto zt = [&](int k, int f) -> R { return ZSTAGE ? ztab[4 * k + f] : R(zr(k, f)); };
 
         Cx<R> d[L];
         bool active;
@@ -229,8 +243,8 @@ template <int L, int W, bool STR = false> struct ZWBody {
             if constexpr (STR) {
                 // [[a_k, s_k + D_k], [a_k, s_k + D_k + c_k]] / (s_k + D_k + c_k); a
                 // row without an upper neighbour (c_k = 0) maps anything to 1
-                const R ak = R(zr(k, 0)), ck = R(zr(k, 1));
-                const R sd = sv * R(zr(k, 2)) + R(zr(k, 3));
+                const R ak = zt(k, 0), ck = zt(k, 1);
+                const R sd = sv * zt(k, 2) + zt(k, 3);
                 const R inv = rcp_nr(sd + ck);
                 a0 = ck > R(0) ? ak * inv : R(0);
                 b0 = ck > R(0) ? sd * inv : R(1);
@@ -310,8 +324,8 @@ template <int L, int W, bool STR = false> struct ZWBody {
                 if constexpr (STR) {
                     // |pivot| = c_k + e_k, e_k = s_k + D_k + a_k v_k-1; vk holds
                     // 1/|pivot| (the multipliers are a_k / |pivot|, c_k / |pivot|)
-                    const R ak = R(zr(k, 0)), ck = R(zr(k, 1));
-                    const R ex = sv * R(zr(k, 2)) + R(zr(k, 3)) + ak * vprev;
+                    const R ak = zt(k, 0), ck = zt(k, 1);
+                    const R ex = sv * zt(k, 2) + zt(k, 3) + ak * vprev;
                     const R wv = rcp_nr(ck + ex);
                     const R vnew = ck > R(0) ? ex * wv : R(1);
                     Dp = cscale(csub(cscale(Dp, ak), d[i]), wv);
@@ -358,7 +372,7 @@ template <int L, int W, bool STR = false> struct ZWBody {
             R Gr = R(1);
 #pragma unroll
             for (int i = 0; i < L; ++i) {
-                Gr *= STR ? R(zr(s + i, 0)) * vk[i] : ((s + i == nz - 1) ? ulast : R(1) - vk[i]);
+                Gr *= STR ? zt(s + i, 0) * vk[i] : ((s + i == nz - 1) ? ulast : R(1) - vk[i]);
                 d[i] = {d[i].re + Gr * dprev.re, d[i].im + Gr * dprev.im};
             }
         }
@@ -370,7 +384,7 @@ template <int L, int W, bool STR = false> struct ZWBody {
             // p_k = d'_k + u_k p_{k+1} written as d'_k + (p_{k+1} - v_k p_{k+1})
             Cx<R> X;
             if constexpr (STR) {
-                const R uk = R(zr(s + i, 1)) * vk[i];  // c_k / |pivot_k|
+                const R uk = zt(s + i, 1) * vk[i];  // c_k / |pivot_k|
                 X = {d[i].re + uk * Xn.re, d[i].im + uk * Xn.im};
                 Hn *= uk;
             } else {
@@ -411,7 +425,7 @@ template <int L, int W, bool STR = false> struct ZWBody {
             R Hr = R(1);
 #pragma unroll
             for (int i = L - 1; i >= 0; --i) {
-                Hr *= STR ? R(zr(s + i, 1)) * vk[i] : R(1) - vk[i];
+                Hr *= STR ? zt(s + i, 1) * vk[i] : R(1) - vk[i];
                 d[i] = {d[i].re + Hr * y.re, d[i].im + Hr * y.im};
             }
         }
@@ -525,6 +539,16 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
     const double *zrow = a.zrow;
     auto zr = [&](int k, int f) -> double { return zrow[8 * k + f]; };
     const double sfac = STR ? 1.0 : a.dz2;
+    // stretched rows staged in LDS in FP32 (as in ZWBody)
+    constexpr bool ZSTAGE = STR && sizeof(R) == 4;
+    R *ztab = (R *)(zbuf + 3 * C);
+    if constexpr (ZSTAGE) {
+        for (int i = t; i < C * L; i += W * C)
+#pragma unroll
+            for (int f = 0; f < 4; ++f) ztab[4 * i + f] = R(zr(i, f));
+        __syncthreads();
+    }
+    auto zt = [&](int k, int f) -> R { return ZSTAGE ? ztab[4 * k + f] : R(zr(k, f)); };
 
     // systems q0 + v, v < V, of row ky
     const int q0 = (block_order((int)blockIdx.x, (int)gridDim.x, a.reverse) * W + w) * V;
@@ -571,8 +595,8 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
         for (int v = 0; v < V; ++v) {
             R x0, y0;
             if constexpr (STR) {
-                const R ak = R(zr(k, 0)), ck = R(zr(k, 1));
-                const R sd = sv[v] * R(zr(k, 2)) + R(zr(k, 3));
+                const R ak = zt(k, 0), ck = zt(k, 1);
+                const R sd = sv[v] * zt(k, 2) + zt(k, 3);
                 const R inv = rcp_nr(sd + ck);
                 x0 = ck > R(0) ? ak * inv : R(0);
                 y0 = ck > R(0) ? sd * inv : R(1);
@@ -656,8 +680,8 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
         for (int v = 0; v < V; ++v) {
             if constexpr (STR) {
                 // vk holds 1/|pivot| (as in ZWBody)
-                const R ak = R(zr(k, 0)), ck = R(zr(k, 1));
-                const R ex = sv[v] * R(zr(k, 2)) + R(zr(k, 3)) + ak * vprev[v];
+                const R ak = zt(k, 0), ck = zt(k, 1);
+                const R ex = sv[v] * zt(k, 2) + zt(k, 3) + ak * vprev[v];
                 const R wv = rcp_nr(ck + ex);
                 const R vnew = ck > R(0) ? ex * wv : R(1);
                 Dp[v] = (ak * Dp[v] - d[i][v]) * wv;
@@ -702,7 +726,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
         for (int i = 0; i < L; ++i)
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                Gr[v] *= STR ? R(zr(s + i, 0)) * vk[i][v]
+                Gr[v] *= STR ? zt(s + i, 0) * vk[i][v]
                              : ((s + i == nz - 1) ? ulast[v] : R(1) - vk[i][v]);
                 d[i][v] = d[i][v] + Gr[v] * dprev[v];
             }
@@ -717,7 +741,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
     for (int i = L - 1; i >= 0; --i)
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            const R uk = STR ? R(zr(s + i, 1)) * vk[i][v] : R(1) - vk[i][v];
+            const R uk = STR ? zt(s + i, 1) * vk[i][v] : R(1) - vk[i][v];
             const R X = STR ? d[i][v] + uk * Xn[v] : d[i][v] + (Xn[v] - vk[i][v] * Xn[v]);
             d[i][v] = X;
             Xn[v] = X;
@@ -756,7 +780,7 @@ __global__ __launch_bounds__(MAXT) void k_z_walls_r(ZArgs a0, int C)
         for (int i = L - 1; i >= 0; --i)
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                Hr[v] *= STR ? R(zr(s + i, 1)) * vk[i][v] : R(1) - vk[i][v];
+                Hr[v] *= STR ? zt(s + i, 1) * vk[i][v] : R(1) - vk[i][v];
                 d[i][v] = d[i][v] + Hr[v] * y[v];
             }
     }
@@ -797,7 +821,8 @@ static int run_zwr(const ZArgs &a, hipStream_t s)
     const int C = (a.nz + L - 1) / L;
     if (C * W > MAXT || a.nx % ZR_V != 0) return -1;
     const int nb = (a.ny * a.nx / ZR_V + W - 1) / W;
-    const size_t shm = ((C * W * 4 * ZR_V * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double);
+    const size_t shm = ((C * W * 4 * ZR_V * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double) +
+                       (STR && sizeof(R) == 4 ? (size_t)C * L * 4 * sizeof(R) : 0);
     hipLaunchKernelGGL((k_z_walls_r<L, W, MAXT, STR>), dim3(nb, a.batch ? a.nbatch : 1),
                        dim3(W * C), shm, s, a, C);
     return (int)hipGetLastError();
@@ -812,7 +837,8 @@ static int run_zw(const ZArgs &a, hipStream_t s)
     constexpr int H = W / 2 > 0 ? W / 2 : 1;
     const int nspecial = a.xwall ? npairs * ((a.M + H - 1) / H) : (npairs + H - 1) / H;
     const int nmain = a.xwall ? 0 : (a.ny * a.M + W - 1) / W;
-    const size_t shm = ((C * W * 4 * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double);
+    const size_t shm = ((C * W * 4 * sizeof(R) + 7) / 8) * 8 + 3 * C * sizeof(double) +
+                       (STR && sizeof(R) == 4 ? (size_t)C * L * 4 * sizeof(R) : 0);
     hipLaunchKernelGGL((k_z_walls<L, W, MAXT, STR>), dim3(nspecial + nmain, a.batch ? a.nbatch : 1),
                        dim3(W * C), shm, s, a, C, nspecial);
     return (int)hipGetLastError();
