@@ -1689,12 +1689,16 @@ int autotune_group(poisson_plan p, Group &g)
         // last partial round leaves most of the device idle: 1024 workgroups
         // of 16 planes on 768 slots at 512x512x256 ran 6 % slower than 1536
         // of 22)
-        const int nb = kr_group(L);
+        // The candidates are timed on one problem of the group's shape, so
+        // the exact depths are offered to single-problem groups only (for a
+        // batched group they would be sized for one problem and run with all
+        // of them)
+        const bool single = g.members.size() <= 1;
         auto candidates = [&](int njb, int slots, int *c) {
             int n = 0;
             for (int k : {4, 8, 16}) c[n++] = k;
-            for (int rounds = 1; rounds <= 2 && slots > 0 && njb > 0; ++rounds) {
-                const long want = (long)slots * rounds / ((long)njb * nb);
+            for (int rounds = 1; single && rounds <= 2 && slots > 0 && njb > 0; ++rounds) {
+                const long want = (long)slots * rounds / (long)njb;
                 if (want < 1) continue;
                 const int kr = (int)((g.d.nz + want - 1) / want);
                 bool dup = false;
