@@ -776,6 +776,30 @@ template <int M, bool ACC, bool XW, bool P32> struct XIBody {
         // reversed radix order: the small radix first gives more butterfly pairs
         // per row for the fused first pass
         constexpr RPlan pl = get_rplan(M, 1);
+        // Accumulating onto the FP32 first iterate (periodic x): the iterate's
+        // values of this block are loaded before the transform, in the
+        // coalesced order of the final store loop, so that their reads are in
+        // flight during it; the last pass stores into the tile and the loop
+        // adds and writes p (loading them in the last pass's stores left
+        // their latency exposed)
+        // (first passes of radix 8 hold too many registers to keep four waves
+        // per SIMD with the prefetched values: radix 4 or less only)
+        constexpr bool PRE =
+            ACC && P32 && !XW && pl.count >= 2 && (M / pl.r[0]) % 2 == 0 && pl.r[0] <= 4;
+        constexpr int PERP = PRE ? (NB * M + NT - 1) / NT : 1;
+        pk_f2v pre[PERP];
+        if constexpr (PRE) {
+#pragma unroll
+            for (int q = 0; q < PERP; ++q) {
+                const int e = threadIdx.x + q * NT;
+                const int row = row0 + e / M;
+                pre[q] = pk_f2v{0.f, 0.f};
+                if ((NB * M) % NT == 0 || e < NB * M)
+                    if (row < nrows)
+                        pre[q] = __builtin_nontemporal_load(
+                            (const PK_GLOBAL pk_f2v *)(gp32 + (size_t)row * NX + 2 * (e % M)));
+            }
+        }
         if constexpr (pl.count >= 2 && (M / pl.r[0]) % 2 == 0) {
             // first pass with the merge fused (no twiddles in a first pass),
             // outputs of butterfly j to the LDS tile at j RAD + r
@@ -838,6 +862,22 @@ template <int M, bool ACC, bool XW, bool P32> struct XIBody {
                 fft_passes<R, M, NB, NT, false, C::PAD, false, 1, pl.count, 1>(s_tw, 2, gnone,
                                                                                tstore, tile);
                 wall_rows_out();
+            } else if constexpr (PRE) {
+                auto tstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
+                fft_passes<R, M, NB, NT, false, C::PAD, false, 1, pl.count, 1>(s_tw, 2, gnone,
+                                                                               tstore, tile);
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < PERP; ++q) {
+                    const int e = threadIdx.x + q * NT;
+                    const int b = e / M, h = e % M;
+                    const int row = row0 + b;
+                    if (((NB * M) % NT != 0 && e >= NB * M) || row >= nrows) continue;
+                    const Cx<R> v = tile.at(b, h);
+                    const double2 o = {double(v.re) + (double(pre[q].x) - pmean),
+                                       -double(v.im) + (double(pre[q].y) - pmean)};
+                    st_stream(gp + (size_t)row * NX + 2 * h, o);
+                }
             } else {
                 fft_passes<R, M, NB, NT, false, C::PAD, false, 1, pl.count, 1>(s_tw, 2, gnone,
                                                                                gstore, tile);
