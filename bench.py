@@ -412,7 +412,12 @@ def bench_rb1024(steps, tune):
         step_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in passes.values())
         res[prec] = {"ms_per_step": ms, "mpoints_s": npts / (ms * 1e-3) / 1e6,
                      "model_hbm_gbs": step_bytes / (ms * 1e-3) / 1e9,
-                     "model_bytes_per_point": step_bytes / npts}
+                     "model_bytes_per_point": step_bytes / npts,
+                     "passes": {k: {"avg_ms": v["total_ms"] / v["launches"],
+                                    "launches": v["launches"],
+                                    "gbs": v["bytes_per_launch"] / (v["total_ms"] / v["launches"]
+                                                                    * 1e-3) / 1e9}
+                                for k, v in passes.items() if v["launches"]}}
         if st is not None:
             res[prec].update(rel_residual=st["rel_residual"], iterations=st["iterations"])
         print(f"[bench] rb1024 {prec} {ms:.3f} ms/solve", file=sys.stderr, flush=True)

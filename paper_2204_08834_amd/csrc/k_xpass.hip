@@ -782,22 +782,24 @@ template <int M, bool ACC, bool XW, bool P32> struct XIBody {
         // flight during it; the last pass stores into the tile and the loop
         // adds and writes p (loading them in the last pass's stores left
         // their latency exposed)
-        // (first passes of radix 8 hold too many registers to keep four waves
-        // per SIMD with the prefetched values: radix 4 or less only)
-        constexpr bool PRE =
-            ACC && P32 && !XW && pl.count >= 2 && (M / pl.r[0]) % 2 == 0 && pl.r[0] <= 4;
+        constexpr bool PRE = ACC && !XW && pl.count >= 2 && (M / pl.r[0]) % 2 == 0;
         constexpr int PERP = PRE ? (NB * M + NT - 1) / NT : 1;
-        pk_f2v pre[PERP];
+        using PV2 = typename std::conditional<P32, pk_f2v, pk_d2v>::type;
+        PV2 pre[PERP];
         if constexpr (PRE) {
 #pragma unroll
             for (int q = 0; q < PERP; ++q) {
                 const int e = threadIdx.x + q * NT;
                 const int row = row0 + e / M;
-                pre[q] = pk_f2v{0.f, 0.f};
+                pre[q] = PV2{0, 0};
                 if ((NB * M) % NT == 0 || e < NB * M)
-                    if (row < nrows)
-                        pre[q] = __builtin_nontemporal_load(
-                            (const PK_GLOBAL pk_f2v *)(gp32 + (size_t)row * NX + 2 * (e % M)));
+                    if (row < nrows) {
+                        const size_t o = (size_t)row * NX + 2 * (e % M);
+                        if constexpr (P32)
+                            pre[q] = __builtin_nontemporal_load((const PK_GLOBAL pk_f2v *)(gp32 + o));
+                        else
+                            pre[q] = __builtin_nontemporal_load((const PK_GLOBAL pk_d2v *)(gp + o));
+                    }
             }
         }
         if constexpr (pl.count >= 2 && (M / pl.r[0]) % 2 == 0) {
