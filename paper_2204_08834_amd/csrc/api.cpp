@@ -305,7 +305,9 @@ std::mutex tune_mu;
 std::map<std::string, Tune> tune_cache;
 bool tune_file_loaded = false;
 
-std::string tune_key(const poisson_desc_t &d)
+// stretched: the group's z cells are not uniform (the plan keeps them apart
+// from the descriptor)
+std::string tune_key(const poisson_desc_t &d, bool stretched)
 {
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -313,15 +315,17 @@ std::string tune_key(const poisson_desc_t &d)
     std::string arch = "unknown";
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
     char buf[160];
-    snprintf(buf, sizeof buf, "%s %d %d %d %d%d%d %s", d.precision == POISSON_FP64 ? "f64" : "f32",
-             d.nx, d.ny, d.nz, d.bc_x, d.bc_y, d.bc_z, arch.c_str());
+    // stretched z grids run other z-solve kernels: their own entries
+    snprintf(buf, sizeof buf, "%s %d %d %d %d%d%d%s %s",
+             d.precision == POISSON_FP64 ? "f64" : "f32", d.nx, d.ny, d.nz, d.bc_x, d.bc_y,
+             d.bc_z, stretched ? "s" : "", arch.c_str());
     for (char *c = buf; *c; ++c)
         if (*c == ':') *c = '_';
     return buf;
 }
 
 // optional persistence: POISSON_TUNE_CACHE names a text file of lines
-// "<key> : zv yv rev kr"
+// "<key> : zv yv rev kr krc"
 void load_tune_file()
 {
     if (tune_file_loaded) return;
@@ -365,13 +369,13 @@ void save_tune_file()
     fclose(fp);
 }
 
-Tune initial_tune(const poisson_desc_t &d)
+Tune initial_tune(const poisson_desc_t &d, bool stretched)
 {
     Tune t = heuristic_tune(d);
     {
         std::lock_guard<std::mutex> lk(tune_mu);
         load_tune_file();
-        auto it = tune_cache.find(tune_key(d));
+        auto it = tune_cache.find(tune_key(d, stretched));
         if (it != tune_cache.end()) t = it->second;
     }
     apply_env_overrides(t);
@@ -661,7 +665,7 @@ int build_group(Group &g, Alloc &A)
     // 4 B/point, it is written and read back at half the bytes
     const bool refine = d.precision == POISSON_FP32_REFINE;
     if (refine && (rc = A.get(g.P32, (size_t)g.N * 4 * n))) return rc;
-    g.tune = initial_tune(g.d);
+    g.tune = initial_tune(g.d, !g.hz.empty());
     return POISSON_OK;
 }
 
@@ -1801,7 +1805,7 @@ int autotune_plan(poisson_plan p, int flags)
 {
     int rc = POISSON_OK;
     for (auto &g : p->groups) {
-        const std::string key = tune_key(g.d);
+        const std::string key = tune_key(g.d, !g.hz.empty());
         bool cached = false;
         if (!(flags & POISSON_TUNE_FORCE)) {
             std::lock_guard<std::mutex> lk(tune_mu);

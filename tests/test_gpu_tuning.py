@@ -92,6 +92,30 @@ def test_autotune_choices_solve_and_are_reused(orc, tmp_path, monkeypatch):
     assert "f64 96 96 48 001" in text and "f32 64 64 64 000" in text
 
 
+def test_stretched_grids_tune_apart(orc, tmp_path, monkeypatch):
+    """A stretched-z grid runs other z-solve kernels than the uniform grid of
+    the same shape: the tuner keeps a separate entry for it (and both solve
+    to the oracle)."""
+    P = _gpu()
+    monkeypatch.setenv("POISSON_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    for v in ("POISSON_ZWALLS_VARIANT", "POISSON_Y_VARIANT", "POISSON_BLOCK_ORDER"):
+        monkeypatch.delenv(v, raising=False)
+    nx, ny, nz = 48, 48, 40
+    sp = (2.0 / nx, 1.5 / ny)
+    f = inputs.random_rhs(nx, ny, nz, seed=91, zero_mean=False)
+    h = inputs.tanh_cells(nz, 1.0, 2.0)
+    for cells in (None, h):
+        ref = orc.solve(f, *sp, 1.0 / nz, NEU, dz_cells=cells)
+        with P.Plan(nx, ny, nz, *sp, 1.0 / nz, NEU, "fp64", dz_cells=cells) as plan:
+            plan.autotune()
+            out, st = plan.solve(torch.from_numpy(f).cuda())
+            assert "tuned" in plan.describe()
+        # (the stretched operator's conditioning is tested in test_gpu_stretched.py)
+        assert st["status"] == 0 and rel(out.cpu().numpy(), ref) <= (1e-12 if cells is None else 1e-10)
+    text = (tmp_path / "tune.txt").read_text()
+    assert "f64 48 48 40 001 " in text and "f64 48 48 40 001s " in text
+
+
 def test_batch_autotune_and_describe():
     P = _gpu()
     probs = [inputs.scaled("hit256", 32, 32, 32, seed=71), inputs.scaled("rb512", 64, 64, 32, seed=72),
