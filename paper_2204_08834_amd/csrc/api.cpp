@@ -468,6 +468,9 @@ struct poisson_plan_s {
     std::vector<ProbPtrs> dptrs_copy;        // what dptrs holds (device-side loop)
     bool dptrs_valid = false;
     hipStream_t gstream = nullptr;           // plan-owned stream of the device loop
+    // stream the device loop runs on: the caller's stream when its launches
+    // are issued eagerly, gstream when they are captured into a graph
+    hipStream_t ms = nullptr;
     std::vector<hipStream_t> side;           // one more stream per further group
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;
@@ -1433,7 +1436,7 @@ int enqueue_device_sequence(poisson_plan p, std::vector<LSet> &sets, bool head,
     if (p->list_mode) {
         // work-list schedule: every group's sequence recorded, then issued
         // on the loop stream, one launch per pass for all groups
-        p->ls = p->gstream;
+        p->ls = p->ms;
         std::vector<size_t> all(ng);
         for (size_t gi = 0; gi < ng; ++gi) all[gi] = gi;
         return over_groups(p, sets, all,
@@ -1445,11 +1448,11 @@ int enqueue_device_sequence(poisson_plan p, std::vector<LSet> &sets, bool head,
         const Group &ga = *sets[a].g, &gb = *sets[b].g;
         return (double)ga.N * ga.members.size() > (double)gb.N * gb.members.size();
     });
-    if (ng > 1 && hipEventRecord(p->ev_fork, p->gstream) != hipSuccess)
+    if (ng > 1 && hipEventRecord(p->ev_fork, p->ms) != hipSuccess)
         return hip_fail("stream fork", (int)hipGetLastError());
     for (size_t oi = 0; oi < ng && !rc; ++oi) {
         const size_t gi = order[oi];
-        p->ls = gi == 0 ? p->gstream : p->side[gi - 1];
+        p->ls = gi == 0 ? p->ms : p->side[gi - 1];
         if (gi > 0 && hipStreamWaitEvent(p->ls, p->ev_fork, 0) != hipSuccess) {
             rc = hip_fail("stream fork", (int)hipGetLastError());
             break;
@@ -1458,9 +1461,9 @@ int enqueue_device_sequence(poisson_plan p, std::vector<LSet> &sets, bool head,
         if (gi > 0 && hipEventRecord(p->ev_join[gi - 1], p->ls) != hipSuccess && !rc)
             rc = hip_fail("stream join", (int)hipGetLastError());
     }
-    p->ls = p->gstream;
+    p->ls = p->ms;
     for (size_t gi = 1; gi < ng; ++gi)
-        if (hipStreamWaitEvent(p->gstream, p->ev_join[gi - 1], 0) != hipSuccess && !rc)
+        if (hipStreamWaitEvent(p->ms, p->ev_join[gi - 1], 0) != hipSuccess && !rc)
             rc = hip_fail("stream join", (int)hipGetLastError());
     return rc;
 }
@@ -1494,6 +1497,7 @@ int build_graph(poisson_plan p, std::vector<LSet> &sets, int k)
 {
     hipError_t e = hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail("graph capture", (int)e);
+    p->ms = p->gstream;
     const int rc = enqueue_device_sequence(p, sets, k == 0);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(p->gstream, &g);
@@ -1528,9 +1532,13 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
     const bool refine = p->precision == POISSON_FP32_REFINE;
     const bool capture = p->graph_mode == 1 && !p->timing;
     const int count = p->count;
-    p->ls = p->gstream;
-    if (hipEventRecord(p->ev_in, p->stream) != hipSuccess ||
-        hipStreamWaitEvent(p->gstream, p->ev_in, 0) != hipSuccess)
+    // eager launches go straight to the caller's stream (the events that
+    // order the plan's stream after it cost about 40 us per solve between
+    // solves on MI355X); graphs are captured and launched on the plan's own
+    p->ms = capture ? p->gstream : p->stream;
+    p->ls = p->ms;
+    if (capture && (hipEventRecord(p->ev_in, p->stream) != hipSuccess ||
+                    hipStreamWaitEvent(p->gstream, p->ev_in, 0) != hipSuccess))
         return hip_fail("stream ordering", (int)hipGetLastError());
     if (p->ptrs_done && hipEventSynchronize(p->ptrs_done) != hipSuccess) return POISSON_ERR_HIP;
 
@@ -1552,7 +1560,7 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
     if (!p->dptrs_valid ||
         memcmp(p->dptrs_copy.data(), staging, sizeof(ProbPtrs) * count) != 0) {
         if (hipMemcpyAsync(p->dptrs->p, staging, sizeof(ProbPtrs) * count, hipMemcpyHostToDevice,
-                           p->gstream) != hipSuccess)
+                           p->ms) != hipSuccess)
             return hip_fail("pointer upload", (int)hipGetLastError());
         memcpy(p->dptrs_copy.data(), staging, sizeof(ProbPtrs) * count);
         p->dptrs_valid = true;
@@ -1574,6 +1582,7 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
         if (issued) {
         } else if (capture) {
             if (!p->gexec[k] && (rc = build_graph(p, sets, k))) break;
+            p->ms = p->gstream;
             const hipError_t e = hipGraphLaunch(p->gexec[k], p->gstream);
             if (e != hipSuccess) {
                 rc = hip_fail("graph launch", (int)e);
@@ -1585,8 +1594,8 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
         if (!refine && !st) break;
         // scalars and control records are one allocation: one read-back
         if (hipMemcpyAsync(p->hs, p->scalars->p, state_bytes(count),
-                           hipMemcpyDeviceToHost, p->gstream) != hipSuccess ||
-            hipStreamSynchronize(p->gstream) != hipSuccess) {
+                           hipMemcpyDeviceToHost, p->ms) != hipSuccess ||
+            hipStreamSynchronize(p->ms) != hipSuccess) {
             rc = hip_fail("scalar read-back", (int)hipGetLastError());
             break;
         }
@@ -1595,9 +1604,11 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
         for (int i = 0; i < count; ++i) running = running || hc[NCTRL * i + C_STATE] != 0;
         if (!running || round + 1 >= max_rounds) break;
     }
-    if (p->ptrs_done) (void)hipEventRecord(p->ptrs_done, p->gstream);
-    (void)hipEventRecord(p->ev_out, p->gstream);
-    (void)hipStreamWaitEvent(p->stream, p->ev_out, 0);
+    if (p->ptrs_done) (void)hipEventRecord(p->ptrs_done, p->ms);
+    if (p->ms != p->stream) {
+        (void)hipEventRecord(p->ev_out, p->ms);
+        (void)hipStreamWaitEvent(p->stream, p->ev_out, 0);
+    }
 
     int first = rc;
     for (auto &g : p->groups) {
