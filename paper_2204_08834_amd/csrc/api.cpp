@@ -468,11 +468,11 @@ struct poisson_plan_s {
     std::vector<ProbPtrs> dptrs_copy;        // what dptrs holds (device-side loop)
     bool dptrs_valid = false;
     hipStream_t gstream = nullptr;           // plan-owned stream of the device loop
-    // stream the device loop runs on: the caller's stream when its launches
-    // are issued eagerly, gstream when they are captured into a graph
+    // stream the device loop issues to: the caller's stream (eager launches
+    // and graph launches), gstream while a graph is being captured
     hipStream_t ms = nullptr;
     std::vector<hipStream_t> side;           // one more stream per further group
-    hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr;
+    hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;
     hipGraph_t graph[2] = {nullptr, nullptr};  // [0] solve + loop segments, [1] segments
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -507,8 +507,6 @@ struct poisson_plan_s {
         for (auto e : event_pool) (void)hipEventDestroy(e);
         if (ptrs_done) (void)hipEventDestroy(ptrs_done);
         drop_graphs();
-        if (ev_in) (void)hipEventDestroy(ev_in);
-        if (ev_out) (void)hipEventDestroy(ev_out);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         for (auto e : ev_join) (void)hipEventDestroy(e);
         for (auto st : side) (void)hipStreamDestroy(st);
@@ -1479,7 +1477,7 @@ int ensure_device_loop_objects(poisson_plan p)
     auto ev = [](hipEvent_t *e) {
         return hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
     };
-    if (!ev(&p->ev_in) || !ev(&p->ev_out) || !ev(&p->ev_fork)) return POISSON_ERR_HIP;
+    if (!ev(&p->ev_fork)) return POISSON_ERR_HIP;
     for (size_t gi = 1; gi < p->groups.size(); ++gi) {
         hipStream_t st = nullptr;
         hipEvent_t e = nullptr;
@@ -1497,10 +1495,12 @@ int build_graph(poisson_plan p, std::vector<LSet> &sets, int k)
 {
     hipError_t e = hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail("graph capture", (int)e);
+    hipStream_t ms = p->ms;
     p->ms = p->gstream;
     const int rc = enqueue_device_sequence(p, sets, k == 0);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(p->gstream, &g);
+    p->ms = ms;
     if (rc || e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
         (void)hipGetLastError();
@@ -1517,10 +1517,9 @@ int build_graph(poisson_plan p, std::vector<LSet> &sets, int k)
     return POISSON_OK;
 }
 
-// Solve with the device-side loop on the plan's own stream (ordered after
-// the caller's stream by events): per round one graph launch (or the same
-// launches issued eagerly) and one read-back of the scalars and control
-// records.
+// Solve with the device-side loop on the caller's stream: per round one
+// graph launch (or the same launches issued eagerly) and one read-back of
+// the scalars and control records.
 int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
                  poisson_stats_t *st)
 {
@@ -1532,14 +1531,12 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
     const bool refine = p->precision == POISSON_FP32_REFINE;
     const bool capture = p->graph_mode == 1 && !p->timing;
     const int count = p->count;
-    // eager launches go straight to the caller's stream (the events that
-    // order the plan's stream after it cost about 40 us per solve between
-    // solves on MI355X); graphs are captured and launched on the plan's own
-    p->ms = capture ? p->gstream : p->stream;
+    // launches (eager ones and graph launches) go straight to the caller's
+    // stream: ordering a stream of the plan's own after it with an event
+    // pair left the GPU idle for 60-85 us between solves on MI355X; graphs
+    // are captured on the plan's stream (the caller's may not be capturable)
+    p->ms = p->stream;
     p->ls = p->ms;
-    if (capture && (hipEventRecord(p->ev_in, p->stream) != hipSuccess ||
-                    hipStreamWaitEvent(p->gstream, p->ev_in, 0) != hipSuccess))
-        return hip_fail("stream ordering", (int)hipGetLastError());
     if (p->ptrs_done && hipEventSynchronize(p->ptrs_done) != hipSuccess) return POISSON_ERR_HIP;
 
     // pointers of every problem, uploaded in one copy when they changed
@@ -1582,8 +1579,7 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
         if (issued) {
         } else if (capture) {
             if (!p->gexec[k] && (rc = build_graph(p, sets, k))) break;
-            p->ms = p->gstream;
-            const hipError_t e = hipGraphLaunch(p->gexec[k], p->gstream);
+            const hipError_t e = hipGraphLaunch(p->gexec[k], p->ms);
             if (e != hipSuccess) {
                 rc = hip_fail("graph launch", (int)e);
                 break;
@@ -1605,10 +1601,6 @@ int solve_device(poisson_plan p, const double *const *rhs, double *const *sol,
         if (!running || round + 1 >= max_rounds) break;
     }
     if (p->ptrs_done) (void)hipEventRecord(p->ptrs_done, p->ms);
-    if (p->ms != p->stream) {
-        (void)hipEventRecord(p->ev_out, p->ms);
-        (void)hipStreamWaitEvent(p->stream, p->ev_out, 0);
-    }
 
     int first = rc;
     for (auto &g : p->groups) {
