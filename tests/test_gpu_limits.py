@@ -74,6 +74,8 @@ def test_longest_transforms_match_oracle(orc, case):
             err = rel(p, p_ref)
             print(f"[limits] kappa {k:.2e} error {err:.2e} residual gpu {res:.2e} "
                   f"oracle {ref_res:.2e}", flush=True)
+            print(f"[fp64-error] limits {nx}x{ny}x{nz} bc={bc}: {err:.2e} "
+                  f"(bound {max(1e-12, 4 * k * 2.2e-16):.2e})", flush=True)
             assert res <= 1e-13 and ref_res <= 1e-13
             assert err <= max(1e-12, 4 * k * 2.2e-16), err
         else:

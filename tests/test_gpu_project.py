@@ -95,6 +95,8 @@ def test_project_matches_oracle(orc, case, prec):
     err = np.linalg.norm(psi - psi_ref) / nref if np.linalg.norm(f) > 0 else np.abs(psi).max()
     if prec == "fp64":
         tol = max(1e-12, 4 * _kappa(nx, ny, nz, *sp, bc) * 2.2e-16)
+        print(f"[fp64-error] project {nx}x{ny}x{nz} bc={bc}: {err:.2e} (bound {tol:.2e})",
+              flush=True)
         assert err <= tol, err
     elif prec == "fp32_refine":
         res, _ = orc.residual(f, psi, *sp, bc)

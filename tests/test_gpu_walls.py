@@ -118,6 +118,8 @@ def test_dirichlet_z_matches_oracle(orc, case):
             res_ref, _ = orc.residual(f, p_ref, *sp, DIR)
             print(f"[walls] kappa {k:.1e} error {rel(p, p_ref):.2e} residual {res:.1e} "
                   f"oracle {res_ref:.1e}", flush=True)
+            print(f"[fp64-error] dirichlet-z {nx}x{ny}x{nz}: {rel(p, p_ref):.2e} "
+                  f"(bound {max(1e-12, 4 * k * 2.2e-16):.2e})", flush=True)
             assert res <= max(1e-13, 4 * res_ref), (res, res_ref)
             assert rel(p, p_ref) <= max(1e-12, 4 * k * 2.2e-16), (rel(p, p_ref), k)
         elif prec == "fp32_refine":
@@ -138,6 +140,8 @@ def test_dirichlet_z_tile_variants(orc, variant, monkeypatch):
         p_ref = orc.solve(f, *sp, DIR)
         p, _ = gpu_solve(P, f, sp, (PER, PER, DIR), "fp64")
         tol = max(1e-12, 4 * kappa(nx, ny, nz, sp, (PER, PER, DIR)) * 2.2e-16)
+        print(f"[fp64-error] dirichlet-z variant {variant} {nx}x{ny}x{nz}: {rel(p, p_ref):.2e} "
+              f"(bound {tol:.2e})", flush=True)
         assert rel(p, p_ref) <= tol, (variant, nx, ny, nz, rel(p, p_ref))
         q, st = gpu_solve(P, f, sp, (PER, PER, DIR), "fp32_refine")
         res, _ = orc.residual(f, q, *sp, DIR)
@@ -243,6 +247,8 @@ def test_y_walls_match_oracle(orc, case, bc_y):
         err = rel(p, p_ref)
         if prec == "fp64":
             res, _ = orc.residual(f, p, *sp, bc_z, bc_y=bc_y)
+            print(f"[fp64-error] y-walls {nx}x{ny}x{nz} y{bc_y} z{bc_z}: {err:.2e} "
+                  f"(bound {max(1e-12, 4 * k * 2.2e-16):.2e})", flush=True)
             print(f"[walls] kappa {k:.1e} error {err:.2e} residual {res:.1e} oracle "
                   f"{res_ref:.1e}", flush=True)
             assert res <= max(1e-13, 4 * res_ref), (res, res_ref)
@@ -355,6 +361,8 @@ def test_x_walls_match_oracle(orc, bcs):
                 assert abs(st["rhs_mean"] - f.mean()) <= 1e-12
             err = rel(p, p_ref)
             if prec == "fp64":
+                print(f"[fp64-error] x-walls {nx}x{ny}x{nz} {bcs}: {err:.2e} "
+                      f"(bound {max(1e-12, 4 * k * 2.2e-16):.2e})", flush=True)
                 assert err <= max(1e-12, 4 * k * 2.2e-16), (nx, ny, nz, err, k)
             elif prec == "fp32_refine":
                 res, _ = orc.residual(f, p, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
@@ -376,6 +384,8 @@ def test_x_walls_long_rows(orc, case):
     res_ref, _ = orc.residual(f, p_ref, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
     k = kappa(nx, ny, nz, sp, bcs)
     p, _ = gpu_solve(P, f, sp, bcs, "fp64")
+    print(f"[fp64-error] x-walls long rows {nx}x{ny}x{nz} {bcs}: {rel(p, p_ref):.2e} "
+          f"(bound {max(1e-12, 4 * k * 2.2e-16):.2e})", flush=True)
     assert rel(p, p_ref) <= max(1e-12, 4 * k * 2.2e-16), (rel(p, p_ref), k)
     rtol = max(1e-10, 10 * res_ref)
     q, st = gpu_solve(P, f, sp, bcs, "fp32_refine", rtol=rtol)
