@@ -239,3 +239,36 @@ def test_batch_with_a_zero_problem(mode):
     for a, b, sa, sb in zip(p_h, outs, st_h, st):
         assert np.array_equal(a, b)
         assert sa == sb
+
+
+@pytest.mark.parametrize("mode", ["device", "graph"])
+def test_loops_on_a_caller_stream(mode):
+    """The device-side loops issue to the plan's stream (eager launches and
+    graph launches alike; graphs are captured on a stream of the plan's
+    own): on a non-default caller stream, repeated solves with a right-hand
+    side rewritten on that stream in between equal the host loop's
+    bitwise."""
+    P = _gpu()
+    prob = inputs.scaled("rb512", 64, 48, 40, seed=141)
+    base = torch.from_numpy(prob.f).cuda()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    res = {}
+    for m in ("host", mode):
+        with torch.cuda.stream(s):
+            rhs = torch.empty_like(base)
+            out = torch.empty_like(base)
+            got = []
+            with P.Plan(prob.nx, prob.ny, prob.nz, *prob.spacings(), prob.bc_z, "fp32_refine",
+                        stream=s) as plan:
+                plan.set_graph(m)
+                for scale in (1.0, -2.0, 0.5):
+                    rhs.copy_(base).mul_(scale)  # queued on s before the solve
+                    _, st = plan.solve(rhs, out)
+                    got.append((out.clone(), st))
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        res[m] = [(o.cpu().numpy(), st) for o, st in got]
+    for (a, sa), (b, sb) in zip(res["host"], res[mode]):
+        assert sa["status"] == 0 and sa["rel_residual"] <= 1e-10
+        assert np.array_equal(a, b) and sa == sb
