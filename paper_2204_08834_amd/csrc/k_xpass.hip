@@ -729,15 +729,31 @@ template <int M, bool ACC, bool XW, bool P32> struct XIBody {
             else
                 return sr[m];
         };
+        // reversed radix order: the small radix first gives more butterfly pairs
+        // per row for the fused first pass
+        constexpr RPlan pl = get_rplan(M, 1);
+        // Accumulating, the previous iterate's values of the block are loaded
+        // before the transform (with the fused first pass), in the coalesced
+        // order of the final store loop, so that their reads are in flight
+        // during it; the last pass stores into the tile and the loop adds and
+        // writes p.  Loaded in the last pass's stores (periodic x) or after
+        // the transform (walls), their latency was exposed.
+        constexpr bool PRE = ACC && pl.count >= 2 && (M / pl.r[0]) % 2 == 0;
+        constexpr int PERP = PRE ? (NB * M + NT - 1) / NT : 1;
+        using PV2 = typename std::conditional<P32, pk_f2v, pk_d2v>::type;
         Tile tile{s_tile};
         // walls: the tile holds conj(v) of each row in transform order; write
         // x[2h] = v[h], x[2h+1] = v[nx-1-h] (negated for sines) with contiguous
         // stores (or accumulate)
-        auto wall_rows_out = [&]() {
+        auto wall_rows_out = [&](const auto &pre) {
             __syncthreads();
             constexpr int PERW = (NB * M + NT - 1) / NT;
             double2 old[PERW];
-            if constexpr (ACC) {
+            if constexpr (PRE) {  // loaded before the transform
+                static_assert(PERW == PERP, "same coalesced order");
+#pragma unroll
+                for (int q = 0; q < PERW; ++q) old[q] = {double(pre[q].x), double(pre[q].y)};
+            } else if constexpr (ACC) {
                 // all loads of the previous iterate in flight first
 #pragma unroll
                 for (int q = 0; q < PERW; ++q) {
@@ -773,18 +789,6 @@ template <int M, bool ACC, bool XW, bool P32> struct XIBody {
                     st_stream(gp + (size_t)row * NX + 2 * h, o);
             }
         };
-        // reversed radix order: the small radix first gives more butterfly pairs
-        // per row for the fused first pass
-        constexpr RPlan pl = get_rplan(M, 1);
-        // Accumulating onto the FP32 first iterate (periodic x): the iterate's
-        // values of this block are loaded before the transform, in the
-        // coalesced order of the final store loop, so that their reads are in
-        // flight during it; the last pass stores into the tile and the loop
-        // adds and writes p (loading them in the last pass's stores left
-        // their latency exposed)
-        constexpr bool PRE = ACC && !XW && pl.count >= 2 && (M / pl.r[0]) % 2 == 0;
-        constexpr int PERP = PRE ? (NB * M + NT - 1) / NT : 1;
-        using PV2 = typename std::conditional<P32, pk_f2v, pk_d2v>::type;
         PV2 pre[PERP];
         if constexpr (PRE) {
 #pragma unroll
@@ -863,7 +867,7 @@ template <int M, bool ACC, bool XW, bool P32> struct XIBody {
                 auto tstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
                 fft_passes<R, M, NB, NT, false, C::PAD, false, 1, pl.count, 1>(s_tw, 2, gnone,
                                                                                tstore, tile);
-                wall_rows_out();
+                wall_rows_out(pre);
             } else if constexpr (PRE) {
                 auto tstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
                 fft_passes<R, M, NB, NT, false, C::PAD, false, 1, pl.count, 1>(s_tw, 2, gnone,
@@ -900,7 +904,7 @@ template <int M, bool ACC, bool XW, bool P32> struct XIBody {
             if constexpr (XW) {
                 auto tstore = [&](int b, int n, Cx<R> v) { tile.at(b, n) = v; };
                 fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, tstore, tile);
-                wall_rows_out();
+                wall_rows_out(pre);
             } else {
                 fft_tile<R, M, NB, NT, false, C::PAD, false>(s_tw, 2, gload, gstore, tile);
             }

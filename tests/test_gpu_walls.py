@@ -394,6 +394,39 @@ def test_x_walls_long_rows(orc, case):
     assert rel(q, p_ref) <= err_bound(k, res, res_ref), (rel(q, p_ref), k, res)
 
 
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_real_column_tile_variants(orc, variant, monkeypatch):
+    """Walls along x and y: every z column is a set of real systems, two per
+    lane.  Each tile variant of that solve (16- or 8-row chunks, 128- or
+    256-byte row runs; nz = 1100 forces 8-row chunks, nz = 37 and 48 widen
+    the workgroup) against the oracle in FP64, FP32 + refinement and FP32."""
+    P = _gpu()
+    monkeypatch.setenv("POISSON_ZWALLS_VARIANT", str(variant))
+    for (nx, ny, nz), bcs in [((64, 32, 48), (NEU, NEU, NEU)), ((6, 8, 200), (DIR, NEU, DIR)),
+                              ((16, 8, 1100), (NEU, DIR, NEU)), ((24, 12, 37), (DIR, DIR, NEU))]:
+        sp = (BOX[0] / nx, BOX[1] / ny, BOX[2] / nz)
+        f = inputs.random_rhs(nx, ny, nz, seed=variant + nx + nz, zero_mean=False) + 0.2
+        p_ref = orc.solve(f, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+        res_ref, _ = orc.residual(f, p_ref, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+        k = kappa(nx, ny, nz, sp, bcs)
+        rtol = max(1e-10, 10 * res_ref)
+        for prec in ("fp64", "fp32_refine", "fp32"):
+            print(f"[walls] real columns variant {variant} {nx}x{ny}x{nz} {bcs} {prec}", flush=True)
+            p, st = gpu_solve(P, f, sp, bcs, prec, rtol=rtol)
+            assert st["status"] == 0, (variant, nx, ny, nz, prec, st)
+            err = rel(p, p_ref)
+            if prec == "fp64":
+                print(f"[fp64-error] real columns variant {variant} {nx}x{ny}x{nz} {bcs}: "
+                      f"{err:.2e} (bound {max(1e-12, 4 * k * 2.2e-16):.2e})", flush=True)
+                assert err <= max(1e-12, 4 * k * 2.2e-16), (variant, nx, ny, nz, err, k)
+            elif prec == "fp32_refine":
+                res, _ = orc.residual(f, p, *sp, bcs[2], bc_x=bcs[0], bc_y=bcs[1])
+                assert res <= rtol, (variant, nx, ny, nz, res, rtol, st)
+                assert err <= err_bound(k, res, res_ref), (variant, nx, ny, nz, err, k, res)
+            else:
+                assert err <= max(2e-5, 8 * k * 6e-8), (variant, nx, ny, nz, err, k)
+
 @pytest.mark.parametrize("bcs", [(NEU, NEU, NEU), (DIR, DIR, DIR), (NEU, PER, DIR), (DIR, NEU, PER)])
 def test_x_walls_eigenmode(bcs):
     """Closed-form modes at 256 x 96 x 64 (a cavity and mixed boxes)."""
