@@ -108,10 +108,9 @@ __device__ __forceinline__ void wall_emit(PK_GLOBAL T *row, int nx, int m, Cx<T>
 {
     const Cx<T> wa = w4[m];
     row[sine ? nx - 1 - m : m] = wa.re * X.re - wa.im * X.im;  // Re(w_m X)
-    if (2 * m != nx) {
-        const Cx<T> wb = w4[nx - m];
-        row[sine ? m - 1 : nx - m] = wb.re * X.re + wb.im * X.im;  // Re(w_{nx-m} conj X)
-    }
+    // w_{nx-m} = -i conj(w_m), so Re(w_{nx-m} conj X) = -Im(w_m X): one
+    // table entry serves both coefficients
+    if (2 * m != nx) row[sine ? m - 1 : nx - m] = -(wa.re * X.im + wa.im * X.re);
 }
 
 // coefficient k of a wall row (real view), reversed for sines; C[nx] = 0
@@ -159,60 +158,75 @@ __device__ __forceinline__ void x_forward(const Cx<R> *tw, GL &gload, LdsTile<R,
         static_assert(NJ == rplan_ns(pl, pl.count - 1) && NJ % 2 == 0, "pairing needs even NJ");
         constexpr int U = NJ / 2, NU = NB * U;
         constexpr int PER = (NU + NT - 1) / NT;
+        // walls: the basis (cosines or sines) is a compile-time constant of
+        // each copy of the last pass, so that every coefficient store has a
+        // fixed offset from its row pointer (a per-store select of the index
+        // took 40 more registers)
+        auto last_pass = [&](auto sine_c) {
+            constexpr bool sine = decltype(sine_c)::value;
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int u = threadIdx.x + q * NT;
-            if (NU % NT != 0 && u >= NU) break;
-            const int b = u / U, pp = u % U;
-            int j1, j2;
-            pair_of<NJ>(pp, j1, j2);
-            Cx<R> v1[RAD], v2[RAD];
+            for (int q = 0; q < PER; ++q) {
+                const int u = threadIdx.x + q * NT;
+                if (NU % NT != 0 && u >= NU) break;
+                const int b = u / U, pp = u % U;
+                int j1, j2;
+                pair_of<NJ>(pp, j1, j2);
+                Cx<R> v1[RAD], v2[RAD];
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) {
-                v1[r] = tile.at(b, j1 + r * NJ);
-                v2[r] = tile.at(b, j2 + r * NJ);
-            }
-#pragma unroll
-            for (int r = 1; r < RAD; ++r) {
-                v1[r] = cmul(v1[r], tw[2 * r * j1]);
-                v2[r] = cmul(v2[r], tw[2 * r * j2]);
-            }
-            Bfly<R, RAD>::run(v1);
-            Bfly<R, RAD>::run(v2);
-            PK_GLOBAL Cx<R> *Sr = out(b);
-            if (!Sr) continue;
-            PK_GLOBAL R *Sreal = (PK_GLOBAL R *)Sr;
-            auto emit = [&](int m, Cx<R> zm, Cx<R> zc) {
-                Cx<R> xm, xc;
-                split_pair(zm, zc, tw[m], xm, xc);
-                if constexpr (XW) {
-                    wall_emit(Sreal, 2 * M, m, xm, w4, sine);
-                    if (2 * m != M) wall_emit(Sreal, 2 * M, M - m, xc, w4, sine);
-                } else {
-                    put(Sr + m, xm);
-                    if (2 * m != M) put(Sr + (M - m), xc);
-                }
-            };
-            if (pp == 0) {
-                // butterfly 0: m = r NJ; m = 0 packs X(0) + i X(M)
-                const R X0 = v1[0].re + v1[0].im, XM = v1[0].re - v1[0].im;
-                if constexpr (XW) {
-                    Sreal[sine ? 2 * M - 1 : 0] = X0;
-                    Sreal[sine ? M - 1 : M] = XM * w4[M].re;
-                } else {
-                    put(Sr, Cx<R>{X0, XM});
+                for (int r = 0; r < RAD; ++r) {
+                    v1[r] = tile.at(b, j1 + r * NJ);
+                    v2[r] = tile.at(b, j2 + r * NJ);
                 }
 #pragma unroll
-                for (int r = 1; r < RAD; ++r)
-                    if (r <= RAD - r) emit(r * NJ, v1[r], v1[RAD - r]);
-                // butterfly NJ/2: m = NJ/2 + r NJ, partner r <-> RAD-1-r
+                for (int r = 1; r < RAD; ++r) {
+                    v1[r] = cmul(v1[r], tw[2 * r * j1]);
+                    v2[r] = cmul(v2[r], tw[2 * r * j2]);
+                }
+                Bfly<R, RAD>::run(v1);
+                Bfly<R, RAD>::run(v2);
+                PK_GLOBAL Cx<R> *Sr = out(b);
+                if (!Sr) continue;
+                PK_GLOBAL R *Sreal = (PK_GLOBAL R *)Sr;
+                auto emit = [&](int m, Cx<R> zm, Cx<R> zc) {
+                    Cx<R> xm, xc;
+                    split_pair(zm, zc, tw[m], xm, xc);
+                    if constexpr (XW) {
+                        wall_emit(Sreal, 2 * M, m, xm, w4, sine);
+                        if (2 * m != M) wall_emit(Sreal, 2 * M, M - m, xc, w4, sine);
+                    } else {
+                        put(Sr + m, xm);
+                        if (2 * m != M) put(Sr + (M - m), xc);
+                    }
+                };
+                if (pp == 0) {
+                    // butterfly 0: m = r NJ; m = 0 packs X(0) + i X(M)
+                    const R X0 = v1[0].re + v1[0].im, XM = v1[0].re - v1[0].im;
+                    if constexpr (XW) {
+                        Sreal[sine ? 2 * M - 1 : 0] = X0;
+                        Sreal[sine ? M - 1 : M] = XM * w4[M].re;
+                    } else {
+                        put(Sr, Cx<R>{X0, XM});
+                    }
 #pragma unroll
-                for (int r = 0; r < RAD; ++r)
-                    if (r <= RAD - 1 - r) emit(NJ / 2 + r * NJ, v2[r], v2[RAD - 1 - r]);
-            } else {
+                    for (int r = 1; r < RAD; ++r)
+                        if (r <= RAD - r) emit(r * NJ, v1[r], v1[RAD - r]);
+                    // butterfly NJ/2: m = NJ/2 + r NJ, partner r <-> RAD-1-r
 #pragma unroll
-                for (int r = 0; r < RAD; ++r) emit(j1 + r * NJ, v1[r], v2[RAD - 1 - r]);
+                    for (int r = 0; r < RAD; ++r)
+                        if (r <= RAD - 1 - r) emit(NJ / 2 + r * NJ, v2[r], v2[RAD - 1 - r]);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < RAD; ++r) emit(j1 + r * NJ, v1[r], v2[RAD - 1 - r]);
+                }
             }
+        };
+        if constexpr (XW) {
+            if (sine)
+                last_pass(std::true_type{});
+            else
+                last_pass(std::false_type{});
+        } else {
+            last_pass(std::false_type{});
         }
     } else {
         fft_tile<R, M, NB, NT, false, 0, GL_LDS>(tw, 2, gload, lstore, tile);
