@@ -139,8 +139,9 @@ __device__ __forceinline__ int wall_reorder(int j, int n) { return 2 * j < n ? 2
 // last pass into the LDS tile and combines the coefficient pairs from there
 // (as the lengths whose last pass has an odd number of butterflies do)
 // instead of the fused pair pass (FP64 at 512x512x256: 210 against 227 us;
-// FP32 alike)
-template <int N, bool INV, int WV>
+// FP32 alike).  SINE: Dirichlet walls (sine basis), a compile-time constant
+// so that every row address is a fixed function of the butterfly index.
+template <int N, bool INV, int WV, bool SINE>
 __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
 {
     if (gated_off(a0.batch, a0.gate, blockIdx.y)) return;
@@ -153,7 +154,7 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
     __shared__ Cx<R> s_tw[N];
     __shared__ Cx<R> s_w4l[C::W4_LDS ? N : 1];  // exp(-i pi k / (2n))
 
-    const bool sine = a.bc == 2;
+    constexpr bool sine = SINE;
     const int ntile = (a.M + NB - 1) / NB;
     const int bid = block_order(blockIdx.x, gridDim.x, a.reverse);
     const int tile_i = bid % ntile;
@@ -207,17 +208,16 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
             auto emit = [&](int b, int kk, Cx<R> vk, Cx<R> vc) {
                 // with S = V[k] + V[N-k], D = V[k] - V[N-k] and h = w/2:
                 //   C[k]   = h_k S + i h_k^i D   = (h^r S^r - h^i D^i, h^r S^i + h^i D^r),
-                //   C[N-k] = h_{N-k} S - i h^i D (the same S and D)
+                //   C[N-k] = h_{N-k} S - i h^i D (the same S and D), where
+                //   h_{N-k} = -i conj(h_k) = (-h^i, -h^r): one table entry
                 const Cx<R> S = {vk.re + vc.re, vk.im + vc.im};
                 const Cx<R> D = {vk.re - vc.re, vk.im - vc.im};
                 const Cx<R> h = whalf(kk);
                 put(base + (size_t)(sine ? N - 1 - kk : kk) * M + b,
                     Cx<R>{h.re * S.re - h.im * D.im, h.re * S.im + h.im * D.re});
-                if (kk != 0 && 2 * kk != N) {
-                    const Cx<R> h2 = whalf(N - kk);
+                if (kk != 0 && 2 * kk != N)
                     put(base + (size_t)(sine ? kk - 1 : N - kk) * M + b,
-                        Cx<R>{h2.re * S.re + h2.im * D.im, h2.re * S.im - h2.im * D.re});
-                }
+                        Cx<R>{-(h.im * S.re + h.re * D.im), h.re * D.re - h.im * S.im});
             };
 #pragma unroll
             for (int q = 0; q < PER; ++q) {
@@ -272,8 +272,9 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
         // W[k] = conj(w_k) (C[k] - i C[n-k]) formed in pass 0's loads from the
         // coefficient rows k and n-k (C[n] = 0; read reversed for sines); the
         // inverse FFT as conj(FFT(conj)).  (Staging the rows in the tile
-        // first, one read of each, measured slower on MI355X: the second
-        // read of a row hits the caches.)
+        // first, one read of each, measured slower on MI355X than reading
+        // each row twice; pass 0 with butterfly pairs below reads each once
+        // from registers.)
         auto coef = [&](int b, int kk) -> Cx<R> {
             if (kk >= N) return {R(0), R(0)};
             const Cx<R> g = base[(size_t)(sine ? N - 1 - kk : kk) * M + b];
@@ -290,7 +291,74 @@ __global__ __launch_bounds__((YWCfg<N>::NT)) void k_yw(YArgs a0)
             const R sg = (sine && (r & 1)) ? R(-1) : R(1);
             put(base + (size_t)r * M + b, Cx<R>{sg * v.re, -sg * v.im});
         };
-        fft_tile<R, N, NB, NT, true, C::PAD, false>(s_tw, 1, gload, gstore, tile);
+        constexpr RPlan pl = make_rplan(N);
+        constexpr int R0 = pl.count >= 2 ? pl.r[0] : 1;
+        if constexpr (pl.count >= 2 && (N / R0) % 2 == 0) {
+            // pass 0 with butterfly pairs (p, NJ - p) (or (0, NJ/2)): W[n] and
+            // W[N-n] need the same two coefficient rows, so one thread reads
+            // each pair once and forms both,
+            //   W[n] = conj(w_n) (A - i B),  W[N-n] = i w_n (B - i A),
+            //   A = C[n], B = C[N-n]  (w_{N-n} = -i conj(w_n)),
+            // returned conjugated (the inverse runs as conj(FFT(conj))).
+            constexpr int RAD = R0, NJ = N / RAD, U = NJ / 2, NU = NB * U;
+            constexpr int PER = (NU + NT - 1) / NT;
+            auto wpair = [&](int n, Cx<R> A, Cx<R> B, Cx<R> &wn, Cx<R> &wc) {
+                const Cx<R> w = w4[n];
+                wn = cconj(cmul(cconj(w), csub(A, cmul_pi(B))));
+                wc = cconj(cmul_pi(cmul(w, csub(B, cmul_pi(A)))));
+            };
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int u = threadIdx.x + q * NT;
+                if (NU % NT != 0 && u >= NU) break;
+                const int b = u % NB, pp = u / NB;
+                const int j1 = pp, j2 = pp == 0 ? NJ / 2 : NJ - pp;
+                const bool live = m0 + b < M;
+                auto cf = [&](int kk) -> Cx<R> { return live ? coef(b, kk) : Cx<R>{R(0), R(0)}; };
+                Cx<R> v1[RAD], v2[RAD];
+                if (pp == 0) {
+                    // butterfly 0: n = r NJ with partner (RAD - r) NJ (n = 0:
+                    // C[N] = 0); butterfly NJ/2: n = NJ/2 + r NJ, partner
+                    // r <-> RAD-1-r
+                    Cx<R> dummy;
+                    wpair(0, cf(0), Cx<R>{R(0), R(0)}, v1[0], dummy);
+                    // (an index that is its own partner, n = N/2, takes wn)
+#pragma unroll
+                    for (int r = 1; r < RAD; ++r)
+                        if (r <= RAD - r) {
+                            const Cx<R> A = cf(r * NJ), B = cf(N - r * NJ);
+                            wpair(r * NJ, A, B, v1[r], r == RAD - r ? dummy : v1[RAD - r]);
+                        }
+#pragma unroll
+                    for (int r = 0; r < RAD; ++r)
+                        if (r <= RAD - 1 - r) {
+                            const int n = NJ / 2 + r * NJ;
+                            const Cx<R> A = cf(n), B = cf(N - n);
+                            wpair(n, A, B, v2[r], r == RAD - 1 - r ? dummy : v2[RAD - 1 - r]);
+                        }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < RAD; ++r) {
+                        const int n = j1 + r * NJ;
+                        const Cx<R> A = cf(n), B = cf(N - n);
+                        wpair(n, A, B, v1[r], v2[RAD - 1 - r]);
+                    }
+                }
+                Bfly<R, RAD>::run(v1);
+                Bfly<R, RAD>::run(v2);
+#pragma unroll
+                for (int r = 0; r < RAD; ++r) {
+                    tile.at(b, j1 * RAD + r) = v1[r];
+                    tile.at(b, j2 * RAD + r) = v2[r];
+                }
+            }
+            __syncthreads();
+            auto gnone = [&](int, int) -> Cx<R> { return {R(0), R(0)}; };
+            fft_passes<R, N, NB, NT, true, C::PAD, false, 1, pl.count, 0>(s_tw, 1, gnone, gstore,
+                                                                          tile);
+        } else {
+            fft_tile<R, N, NB, NT, true, C::PAD, false>(s_tw, 1, gload, gstore, tile);
+        }
     }
 }
 
@@ -299,12 +367,23 @@ template <int N> static int run_yw(const YArgs &a, hipStream_t s)
     using C = YWCfg<N>;
     const int ntile = (a.M + C::NB - 1) / C::NB;
     const dim3 grid(ntile * a.nz, a.batch ? a.nbatch : 1);
-    if (a.inverse)
-        hipLaunchKernelGGL((k_yw<N, true, 0>), grid, dim3(C::NT), 0, s, a);
-    else if (a.variant & 1)
-        hipLaunchKernelGGL((k_yw<N, false, 1>), grid, dim3(C::NT), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_yw<N, false, 0>), grid, dim3(C::NT), 0, s, a);
+    const bool sn = a.bc == 2;
+    if (a.inverse) {
+        if (sn)
+            hipLaunchKernelGGL((k_yw<N, true, 0, true>), grid, dim3(C::NT), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_yw<N, true, 0, false>), grid, dim3(C::NT), 0, s, a);
+    } else if (a.variant & 1) {
+        if (sn)
+            hipLaunchKernelGGL((k_yw<N, false, 1, true>), grid, dim3(C::NT), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_yw<N, false, 1, false>), grid, dim3(C::NT), 0, s, a);
+    } else {
+        if (sn)
+            hipLaunchKernelGGL((k_yw<N, false, 0, true>), grid, dim3(C::NT), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_yw<N, false, 0, false>), grid, dim3(C::NT), 0, s, a);
+    }
     return (int)hipGetLastError();
 }
 
