@@ -73,7 +73,51 @@ template <int N, bool INV, int V> struct YBody {
             base[(size_t)n * M + b] = INV ? cconj(v) : v;
         };
         Tile tile{s_tile};
-        fft_tile<R, N, NB, NT, true, C::PAD, false, C::PV>(s_tw, 1, gload, gstore, tile);
+        constexpr RPlan pl = get_rplan(N, C::PV);
+        constexpr int R0 = pl.count >= 2 ? pl.r[0] : 1;
+        // FP32 inverse: pass 0 gives each thread the butterfly pair
+        // (p, NJ - p) (or (0, NJ/2)) instead of butterflies p and p + NJ/2
+        // (as the wall pass does, where the pair shares its inputs).
+        // Measured on MI355X at 512x512x256: inverse 105.6 -> 99.5 us; the
+        // forward pass and FP64 ran 1-3 % slower with it.
+        constexpr bool PAIR = INV && sizeof(R) == 4;
+        if constexpr (PAIR && pl.count >= 2 && (N / R0) % 2 == 0) {
+            constexpr int RAD = R0, NJ = N / RAD, U = NJ / 2, NU = NB * U;
+            constexpr int PER = (NU + NT - 1) / NT;
+            Cx<R> v1[PER][RAD], v2[PER][RAD];
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int u = threadIdx.x + q * NT;
+                if (NU % NT != 0 && u >= NU) break;
+                const int b = u % NB, pp = u / NB;
+                const int j1 = pp, j2 = pp == 0 ? NJ / 2 : NJ - pp;
+#pragma unroll
+                for (int r = 0; r < RAD; ++r) {
+                    v1[q][r] = gload(b, j1 + r * NJ);
+                    v2[q][r] = gload(b, j2 + r * NJ);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int u = threadIdx.x + q * NT;
+                if (NU % NT != 0 && u >= NU) break;
+                const int b = u % NB, pp = u / NB;
+                const int j1 = pp, j2 = pp == 0 ? NJ / 2 : NJ - pp;
+                Bfly<R, RAD>::run(v1[q]);
+                Bfly<R, RAD>::run(v2[q]);
+#pragma unroll
+                for (int r = 0; r < RAD; ++r) {
+                    tile.at(b, j1 * RAD + r) = v1[q][r];
+                    tile.at(b, j2 * RAD + r) = v2[q][r];
+                }
+            }
+            __syncthreads();
+            auto gnone = [&](int, int) -> Cx<R> { return {R(0), R(0)}; };
+            fft_passes<R, N, NB, NT, true, C::PAD, false, 1, pl.count, C::PV>(s_tw, 1, gnone,
+                                                                              gstore, tile);
+        } else {
+            fft_tile<R, N, NB, NT, true, C::PAD, false, C::PV>(s_tw, 1, gload, gstore, tile);
+        }
     }
 };
 
