@@ -232,13 +232,16 @@ def bench_walls(steps, warmup, tune):
             for _ in range(steps):
                 plan.solve(f, out)
             passes = plan.timing()
+            schedule = plan.describe().strip()
             plan.close()
             step_bytes = sum(v["bytes_per_launch"] * v["launches"] for v in passes.values()) / steps
             entry[prec] = {
                 "ms_per_step": ms, "mpoints_s": npts / (ms * 1e-3) / 1e6,
                 "rel_residual": st["rel_residual"], "iterations": st["iterations"],
                 "model_hbm_gbs": step_bytes / (ms * 1e-3) / 1e9,
+                "schedule": schedule,
                 "passes": {k: {"avg_ms": v["total_ms"] / v["launches"],
+                               "launches_per_step": v["launches"] / steps,
                                "gbs": v["bytes_per_launch"] / (v["total_ms"] / v["launches"]
                                                                * 1e-3) / 1e9}
                            for k, v in passes.items()}}
