@@ -76,8 +76,9 @@ template <int N, bool INV, int V> struct YBody {
         constexpr RPlan pl = get_rplan(N, C::PV);
         constexpr int R0 = pl.count >= 2 ? pl.r[0] : 1;
         // FP32 inverse: pass 0 gives each thread the butterfly pair
-        // (p, NJ - p) (or (0, NJ/2)) instead of butterflies p and p + NJ/2
-        // (as the wall pass does, where the pair shares its inputs).
+        // (p, NJ - p) (or (0, NJ/2)) instead of the plain mapping's
+        // butterflies NT/NB apart (as the wall pass does, where the pair
+        // shares its inputs).
         // Measured on MI355X at 512x512x256: inverse 105.6 -> 99.5 us; the
         // forward pass and FP64 ran 1-3 % slower with it.
         constexpr bool PAIR = INV && sizeof(R) == 4;
